@@ -1,0 +1,201 @@
+"""Benchmark: shifted SDA solves per second on one MI355X.
+
+A step is one pass of the whole hot path over the workload: the right-hand
+side (Alg. 7, step 4), the multi-shift solve of every shift to relative
+residual 1e-8 with the FP64 true-residual check, and the ratings s = X w of
+every shift.  The operator build (X^T, tiles, labels) happens once before the
+timed region, as does input generation.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload mid] [--chunk 32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TARGET_RELRES = 1e-8
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kernel: int, pb, nshift: int, chunk: int) -> float:
+    """Bytes one launch must move (every array once; gathered vectors counted once)."""
+    import paper_1709_04794_amd as fsda
+    n, d, z, g = pb.n, pb.d, pb.x_nnz, pb.s_nnz
+    lab = 8 * n if pb.alpha < 1.0 else 0
+    if kernel == fsda.K_X:      # rowptr, col, p (gathered), t written
+        return 4 * (n + 1) + 4 * z + 8 * d + 8 * n + lab
+    if kernel == fsda.K_S:      # rowptr, col, t (gathered), u written
+        return 4 * (n + 1) + 4 * g + 8 * n + 8 * n + lab
+    if kernel == fsda.K_XT:     # rowptr, col, u (gathered), p read, q written
+        return 4 * (d + 1) + 4 * z + 8 * n + 16 * d
+    if kernel in (fsda.K_RESID, fsda.K_PUPD):  # two vectors in, one out
+        return 24 * d
+    if kernel == fsda.K_FOLD:   # W, P in and out for every shift, chunk residuals in
+        return 32 * nshift * d + 8 * chunk * d
+    return 0.0
+
+
+KNAMES = {0: "k_tiles<EpiX> (t = X p)", 1: "k_tiles<EpiLap> (u = M' t)", 2: "k_tiles<EpiXT> (q = X^T u + s p)",
+          3: "k_fixup<EpiXT>", 4: "k_resid", 5: "k_pupdate", 6: "k_fold"}
+
+
+def cpu_baseline(pb, budget_s: float):
+    """The oracle (per-shift FP64 CG) on the host cores, on a bounded sample of shifts."""
+    import oracle
+    nt = oracle.max_threads()
+    order = [int(np.argmax(pb.betas)), int(np.argmin(pb.betas))]
+    solved, spent, sample = 0, 0.0, []
+    for s in order:
+        if spent > budget_s:
+            break
+        t0 = time.perf_counter()
+        W, it, rel, rc = oracle.solve(pb, betas=[pb.betas[s]], rtol=pb.rtol, maxit=20000)
+        dt = time.perf_counter() - t0
+        spent += dt
+        ok = bool(rel[0] <= TARGET_RELRES)
+        solved += ok
+        sample.append({"beta": float(pb.betas[s]), "iters": int(it[0]), "seconds": round(dt, 3),
+                       "relres": float(rel[0])})
+    return {"value": solved / spent if spent > 0 else 0.0, "unit": "solves/s", "cores": nt, "kind": "oracle",
+            "sample": "per-shift FP64 CG of the oracle on the same %s workload for %d of its %d shifts "
+                      "(largest and smallest beta) to rel. residual %.0e: %s"
+                      % (pb.name, len(sample), pb.betas.size, pb.rtol, json.dumps(sample))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--chunk", type=int, default=32)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--cache", default=os.path.join(ROOT, ".synth_cache"))
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="extra timed steps with kernel timing off (chunks replayed as HIP graphs), reported in detail")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1709_04794_amd as fsda
+
+    t0 = time.perf_counter()
+    pb = synth.workload(args.workload, seed=args.seed, cache_dir=args.cache)
+    log("workload %s generated in %.1fs: %s" % (args.workload, time.perf_counter() - t0, pb.summary()))
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    op = fsda.Operator.from_problem(pb, max_chunk=max(args.chunk, 1))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    log("operator built in %.2fs (workspace %.1f MB)" % (build_s, op.ws_bytes / 1e6))
+    S = pb.betas.size
+    W = torch.empty((S, pb.d), dtype=torch.float64, device="cuda")
+
+    def step():
+        b = op.rhs()
+        Wt, iters, relres, st = op.solve(pb.betas, rtol=pb.rtol, chunk=args.chunk, b=b, out=W)
+        op.project(Wt)
+        return iters, relres, st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    # which kernel dominates: one untimed pass per kernel class
+    per_class = {}
+    for k in range(7):
+        op.time_kernel(k, True)
+        step()
+        ms, nl = op.kernel_time()
+        per_class[k] = (ms, nl)
+        op.time_kernel(k, False)
+    dom = max(per_class, key=lambda k: per_class[k][0])
+    log("per-kernel ms per step: %s" % {KNAMES[k]: round(v[0], 3) for k, v in per_class.items()})
+
+    op.time_kernel(dom, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solved = 0
+    worst = 0.0
+    iters_seen = None
+    for _ in range(args.steps):
+        iters, relres, st = step()
+        solved += int((relres <= TARGET_RELRES).sum())
+        worst = max(worst, float(relres.max()))
+        iters_seen = iters
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kms, klaunch = op.kernel_time()
+    op.time_kernel(dom, False)
+
+    graph_rate = None
+    if args.graph_steps > 0:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gsolved = 0
+        for _ in range(args.graph_steps):
+            iters_g, relres_g, _ = step()
+            gsolved += int((relres_g <= TARGET_RELRES).sum())
+        torch.cuda.synchronize()
+        graph_rate = gsolved / (time.perf_counter() - t1)
+        log("graph-replay steps: %.3f solves/s" % graph_rate)
+
+    avg_launch_s = (kms / 1e3) / max(klaunch, 1)
+    bytes_launch = algorithmic_bytes(dom, pb, S, args.chunk)
+    achieved = bytes_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    value = solved / elapsed
+    out = {
+        "metric": "shifted SDA solves/sec at rel. residual 1e-8",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s: n=%d x d=%d binary, nnz_X=%d, kNN graph nnz_S=%d, l=%d labeled, alpha=%g, "
+                               "%d shifts logspace, rtol %g" % (pb.name, pb.n, pb.d, pb.x_nnz, pb.s_nnz,
+                                                                pb.lab_idx.size, pb.alpha, S, pb.rtol),
+                   "n": pb.n, "d": pb.d, "nnz_x": pb.x_nnz, "nnz_s": pb.s_nnz, "shifts": S, "chunk": args.chunk,
+                   "precision": "fp64"},
+        "roofline": {"bound": "hbm", "kernel": KNAMES[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                     "launches": klaunch},
+        "detail": {"iters": None if iters_seen is None else iters_seen.tolist(), "worst_relres": worst,
+                   "solved_per_step": solved / args.steps, "build_s": round(build_s, 3),
+                   "graph_replay_solves_per_s": graph_rate,
+                   "per_kernel_ms_per_step": {KNAMES[k]: round(v[0], 3) for k, v in per_class.items()},
+                   "per_kernel_launches_per_step": {KNAMES[k]: v[1] for k, v in per_class.items()}},
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(pb, args.cpu_budget)
+        log("cpu baseline took %.1fs" % (time.perf_counter() - t0))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

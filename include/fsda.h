@@ -1,0 +1,191 @@
+/*
+ * fsda.h -- C ABI of the MI355X (gfx950) multi-shift solver for fast
+ * semi-supervised discriminant analysis (FSDA; Tavernier et al., "Fast
+ * semi-supervised discriminant analysis for binary classification of large
+ * data-sets", arXiv:1709.04794).
+ *
+ * The library solves, for every regularisation value beta_s of a grid,
+ *
+ *     A(beta_s) w_s = b,   A(beta) = (X - 1 mu_l^T)^T [ (1-alpha) P_l + alpha L ] X + beta I_D
+ *
+ * (Alg. 7, step 4; the SDA eigenproblem of Eq. SDAeig centred on the labeled
+ * mean as in Sec. 2.5.2 and Sec. 3.2.3), with one shared Krylov basis for all
+ * shifts (Sec. 3.2.2, Alg. 3), and returns the ratings s_s = X w_s (Alg. 7,
+ * return value).  Notation: X is the n x d binary sample-by-feature matrix,
+ * l the number of labeled samples, mu_l = X^T 1_l / l the labeled mean,
+ * P_l = diag(1_l) the labeled-sample selector, L = D - S the unnormalised
+ * Laplacian of the binary similarity graph S (Sec. 2.3).
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked "device" are HIP device memory owned by the caller.  The
+ *    library never allocates or frees device memory; all derived data lives in
+ *    the caller's workspace.  Pointers marked "host" are ordinary host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on it; fsda_build_operator and fsda_multishift_solve return
+ *    only after their work on `stream` has finished, the other calls return
+ *    immediately after enqueueing.
+ *  - Index arrays are int32: n, d and each nnz must be below 2^31.
+ *  - A negative return value means nothing valid was written; the message is
+ *    available from fsda_last_error() (per thread).  Arguments are validated
+ *    on the host before any HIP call where that is possible.
+ *  - One handle must not be used from two threads at once; distinct handles
+ *    are independent.
+ */
+#ifndef FSDA_H
+#define FSDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------- */
+#define FSDA_OK 0             /* success                                              */
+#define FSDA_NOT_CONVERGED 1  /* warning: some shift reached maxit; results valid     */
+#define FSDA_E_ARG (-1)       /* bad argument (NULL pointer, size, handle)            */
+#define FSDA_E_CSR (-2)       /* a CSR array is malformed (checked on the device)     */
+#define FSDA_E_LABELS (-3)    /* labeled set invalid: out of range, repeated, one class */
+#define FSDA_E_RANGE (-4)     /* alpha outside [0,1], beta <= 0, rtol <= 0, ...       */
+#define FSDA_E_BREAKDOWN (-5) /* CG breakdown: <p, A p> <= 0 or not finite            */
+#define FSDA_E_WORKSPACE (-6) /* workspace NULL, too small or misaligned              */
+#define FSDA_E_HIP (-7)       /* a HIP runtime call failed                            */
+#define FSDA_E_OVERFLOW (-8)  /* a size does not fit the int32 index type             */
+
+/* ---- precision ------------------------------------------------------------- */
+#define FSDA_FP64 0  /* every vector and scalar in FP64                              */
+#define FSDA_MIXED 1 /* FP32 vectors and sparse products, FP64 dot products and     */
+                     /* recurrence scalars, then one FP64 refinement step           */
+
+/* Limits of one handle. */
+#define FSDA_MAX_SHIFTS 64
+#define FSDA_MAX_CHUNK 64
+
+typedef struct fsda_op fsda_op; /* opaque handle, host memory */
+
+/*
+ * The problem (Eq. SDAeig with the centring of Sec. 3.2.3):
+ *  n, d            samples and features.
+ *  x_rowptr[n+1], x_col[x_nnz]  (device) X in CSR form without values; every
+ *                  stored entry is a 1 (binary fingerprints, Sec. 5.1).  Column
+ *                  indices in [0, d), strictly increasing within a row.  The
+ *                  library builds X^T itself, with the features relabeled by
+ *                  decreasing frequency (an internal order; every vector the
+ *                  caller sees is in the caller's feature order).
+ *  s_rowptr[n+1], s_col[s_nnz]  (device) binary symmetric similarity S, no
+ *                  self loops (Sec. 2.3-2.4); degree d_i = row length.  Symmetry
+ *                  is the caller's responsibility (not checked).
+ *  lab_idx[n_lab], lab_y[n_lab] (device) labeled samples (any order, no
+ *                  repeats) and their classes +1 / -1.  Both classes present.
+ *  alpha           weight of the manifold term, 0 <= alpha <= 1 (Eq. SDAeig).
+ *  precision       FSDA_FP64 or FSDA_MIXED.
+ * The handle borrows these arrays: they must stay valid and unchanged until
+ * fsda_destroy_operator().
+ */
+typedef struct fsda_problem {
+  int64_t n, d;
+  const int32_t *x_rowptr, *x_col;
+  int64_t x_nnz;
+  const int32_t *s_rowptr, *s_col;
+  int64_t s_nnz;
+  const int32_t *lab_idx;
+  const int8_t *lab_y;
+  int64_t n_lab;
+  double alpha;
+  int precision;
+} fsda_problem;
+
+/*
+ * Bytes of device workspace the handle needs for up to `max_shifts` shifts
+ * (1..FSDA_MAX_SHIFTS) and a shift-state fold interval of up to `max_chunk`
+ * iterations (1..FSDA_MAX_CHUNK; see fsda_multishift_solve).  Host only: no
+ * HIP call.  *bytes (host) receives the size.
+ */
+int fsda_workspace_size(const fsda_problem *pb, int max_shifts, int max_chunk, size_t *bytes);
+
+/*
+ * Validates the problem, then builds the operator data in `workspace` (device,
+ * 256-byte aligned, ws_bytes >= fsda_workspace_size()): the feature relabeling,
+ * X and X^T in the internal order, the work partition of the three sparse
+ * products, the labeled weights and the canonical right-hand side.  *out
+ * (host) receives the handle.  Blocks until done.  The workspace belongs to the
+ * handle until it is destroyed.
+ * Errors: FSDA_E_ARG, FSDA_E_RANGE (alpha), FSDA_E_OVERFLOW, FSDA_E_WORKSPACE,
+ * FSDA_E_CSR, FSDA_E_LABELS, FSDA_E_HIP.
+ */
+int fsda_build_operator(const fsda_problem *pb, int max_shifts, int max_chunk, void *workspace,
+                        size_t ws_bytes, void *stream, fsda_op **out);
+
+/*
+ * Right-hand side of Alg. 7, step 4, into b[d] (device, FP64).
+ *  r == NULL: the canonical b = (X - 1 mu_l^T)^T y_c = X^T y_c, y_c the labels
+ *             minus their labeled mean (0 on unlabeled samples);
+ *  r != NULL: r[d] (device) is the start vector of Alg. 7, step 2, and
+ *             b = (X - 1 mu_l^T)^T [W 0; 0 0] X r with W_ij = 1/N_c on the
+ *             labeled class blocks (Sec. 2.1).  For two classes this equals
+ *             ((m+ - m-)/2) X^T y_c, m_c the class-c mean of X r.
+ */
+int fsda_rhs(fsda_op *op, const double *r, double *b, void *stream);
+
+/*
+ * q = A(sigma) p for one vector (the operator product inside each Krylov
+ * step, Sec. 3.2.3): p[d], q[d] device FP64, sigma >= 0 host.  The centring is
+ * applied once, as a rank-one correction in sample space.
+ */
+int fsda_apply(fsda_op *op, double sigma, const double *p, double *q, void *stream);
+
+/*
+ * Multi-shift solve (Alg. 3): one conjugate-gradient recurrence on
+ * A(min beta), every other shift carried by the collinear-residual
+ * coefficients zeta relative to it (Sec. 3.2.2).  The per-shift direction
+ * coefficient is formed with the freshly computed CG coefficient b_{i+1}, the
+ * reading under which the shifted residuals stay collinear.
+ *  b[d]        device FP64 right-hand side, or NULL for the canonical one.
+ *  betas[nshift] host, each > 0, 1 <= nshift <= max_shifts of the handle.
+ *  rtol        > 0: shift s stops updating once |zeta_s| ||r|| <= rtol ||b||.
+ *  maxit       >= 1 iterations of the shared recurrence.
+ *  chunk       1..max_chunk: iterations between folds of the per-shift state
+ *              and between host checks for termination (0 = default 32, capped
+ *              at max_chunk).  Every chunk gives the same result.
+ *  W[nshift][d] device FP64 output, w_s for beta_s.
+ *  iters[nshift] host int output: iterations after which shift s stopped.
+ *  relres[nshift] host FP64 output: true residual ||b - A(beta_s) w_s|| / ||b||
+ *              recomputed in FP64 from w_s after the solve.
+ * Returns FSDA_OK, FSDA_NOT_CONVERGED (some shift hit maxit; its w_s is the
+ * last iterate), FSDA_E_BREAKDOWN, or an argument error.  Blocks until done.
+ */
+int fsda_multishift_solve(fsda_op *op, const double *b, const double *betas, int nshift, double rtol, int maxit,
+                          int chunk, double *W, int *iters, double *relres, void *stream);
+
+/*
+ * Ratings s = X w for each shift (Alg. 7, return value; uncentred):
+ * W[nshift][d] device FP64 in, S[nshift][n] device FP64 out.
+ */
+int fsda_project(fsda_op *op, const double *W, int nshift, double *S, void *stream);
+
+/*
+ * Per-kernel timing for measurement: enable != 0 makes the handle record a
+ * pair of HIP events around every launch of the kernel class `kernel` on the
+ * launch stream: 0 = X product, 1 = graph/centring product, 2 = X^T product
+ * over the long rows (nonzero tiles), 3 = its fix-up of rows spanning tiles,
+ * 4 = residual update, 5 = direction update, 6 = shift-state fold, 7 = X^T
+ * product over the other rows.  While timing is on, solves launch kernels
+ * directly instead of replaying a graph.  Launches made after the recurrence
+ * stopped (which return at once) are not counted.  fsda_kernel_time() returns
+ * (host) the summed milliseconds and launch count of the timed class since
+ * the last reset and resets them.
+ */
+int fsda_time_kernel(fsda_op *op, int kernel, int enable);
+int fsda_kernel_time(fsda_op *op, double *ms, int64_t *launches);
+
+/* Frees the host handle (and its events); the caller frees the workspace. */
+void fsda_destroy_operator(fsda_op *op);
+
+/* Message for the last negative status returned on this thread. */
+const char *fsda_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSDA_H */

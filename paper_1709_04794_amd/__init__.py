@@ -1,0 +1,210 @@
+"""MI355X-native multi-shift solver for fast semi-supervised discriminant analysis.
+
+Thin Python binding of ``libfsda.so`` (the C ABI declared in ``include/fsda.h``).
+It only marshals arguments: every step of the solve runs in the library's HIP
+kernels.  PyTorch provides device memory and the current stream.
+
+    op = Operator.from_problem(problem)              # fsda_build_operator
+    W, iters, relres, status = op.solve(betas, rtol)  # fsda_multishift_solve
+    S = op.project(W)                                 # fsda_project
+
+The library must have been built (``python -m paper_1709_04794_amd.build``);
+importing the binding without it raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfsda.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "fsda.h")
+
+OK, NOT_CONVERGED = 0, 1
+E_ARG, E_CSR, E_LABELS, E_RANGE, E_BREAKDOWN, E_WORKSPACE, E_HIP, E_OVERFLOW = -1, -2, -3, -4, -5, -6, -7, -8
+FP64, MIXED = 0, 1
+MAX_SHIFTS, MAX_CHUNK = 64, 64
+# kernel classes for fsda_time_kernel
+K_X, K_S, K_XT, K_XT_FIX, K_RESID, K_PUPD, K_FOLD, K_XT_ROWS = range(8)
+
+
+class FsdaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("fsda status %d: %s" % (code, msg))
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int64),
+                ("x_rowptr", ctypes.c_void_p), ("x_col", ctypes.c_void_p), ("x_nnz", ctypes.c_int64),
+                ("s_rowptr", ctypes.c_void_p), ("s_col", ctypes.c_void_p), ("s_nnz", ctypes.c_int64),
+                ("lab_idx", ctypes.c_void_p), ("lab_y", ctypes.c_void_p), ("n_lab", ctypes.c_int64),
+                ("alpha", ctypes.c_double), ("precision", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libfsda.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libfsda.so is not built: run `python -m paper_1709_04794_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        pp = ctypes.POINTER(Problem)
+        L.fsda_workspace_size.argtypes = [pp, I, I, ctypes.POINTER(ctypes.c_size_t)]
+        L.fsda_build_operator.argtypes = [pp, I, I, P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+        L.fsda_rhs.argtypes = [P, P, P, P]
+        L.fsda_apply.argtypes = [P, D, P, P, P]
+        L.fsda_multishift_solve.argtypes = [P, P, P, I, D, I, I, P, P, P, P]
+        L.fsda_project.argtypes = [P, P, I, P, P]
+        L.fsda_time_kernel.argtypes = [P, I, I]
+        L.fsda_kernel_time.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
+        L.fsda_destroy_operator.argtypes = [P]
+        L.fsda_destroy_operator.restype = None
+        L.fsda_last_error.argtypes = []
+        L.fsda_last_error.restype = ctypes.c_char_p
+        for f in (L.fsda_workspace_size, L.fsda_build_operator, L.fsda_rhs, L.fsda_apply, L.fsda_multishift_solve,
+                  L.fsda_project, L.fsda_time_kernel, L.fsda_kernel_time):
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def declared_functions() -> list:
+    """Names of the functions declared in include/fsda.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(fsda_\w+)\s*\(", txt, re.M)))
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise FsdaError(rc, lib().fsda_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> Optional[ctypes.c_void_p]:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Operator:
+    """A built SDA operator on one GPU (fsda_build_operator).
+
+    The CSR arrays (int32), labeled indices (int32) and labels (int8, +-1) are
+    torch tensors on the GPU; the handle keeps references to them and owns a
+    workspace tensor.
+    """
+
+    def __init__(self, n: int, d: int, x_rowptr, x_col, s_rowptr, s_col, lab_idx, lab_y, alpha: float,
+                 precision: int = FP64, max_shifts: int = 32, max_chunk: int = 32, stream=None):
+        import torch
+        self.n, self.d = int(n), int(d)
+        self.alpha = float(alpha)
+        self.precision = precision
+        self.max_shifts, self.max_chunk = int(max_shifts), int(max_chunk)
+        self._keep = [x_rowptr, x_col, s_rowptr, s_col, lab_idx, lab_y]
+        for t, dt in ((x_rowptr, torch.int32), (x_col, torch.int32), (s_rowptr, torch.int32), (s_col, torch.int32),
+                      (lab_idx, torch.int32), (lab_y, torch.int8)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise TypeError("CSR and label arrays must be contiguous CUDA tensors of the documented dtypes")
+        self.pb = Problem(self.n, self.d, x_rowptr.data_ptr(), x_col.data_ptr(), x_col.numel(),
+                          s_rowptr.data_ptr(), s_col.data_ptr(), s_col.numel(),
+                          lab_idx.data_ptr(), lab_y.data_ptr(), lab_idx.numel(), self.alpha, int(precision))
+        size = ctypes.c_size_t(0)
+        _check(lib().fsda_workspace_size(ctypes.byref(self.pb), self.max_shifts, self.max_chunk, ctypes.byref(size)))
+        self.ws_bytes = int(size.value)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=x_col.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        _check(lib().fsda_build_operator(ctypes.byref(self.pb), self.max_shifts, self.max_chunk,
+                                         ctypes.c_void_p(self._ws_ptr), ctypes.c_size_t(self.ws_bytes),
+                                         _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.device = x_col.device
+
+    @classmethod
+    def from_problem(cls, pb, precision: int = FP64, max_shifts: Optional[int] = None, max_chunk: int = 32,
+                     device: str = "cuda", alpha: Optional[float] = None, **kw):
+        """Uploads a ``synth.Problem``-like object (numpy arrays) and builds."""
+        import torch
+
+        def up(a, dt):
+            return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        s_col = pb.s_col if pb.s_col.size else np.zeros(1, dtype=np.int32)
+        x_col = pb.x_col if pb.x_col.size else np.zeros(1, dtype=np.int32)
+        op = cls(pb.n, pb.d, up(pb.x_rowptr, torch.int32), up(x_col, torch.int32)[:pb.x_col.size],
+                 up(pb.s_rowptr, torch.int32), up(s_col, torch.int32)[:pb.s_col.size],
+                 up(pb.lab_idx, torch.int32), up(pb.lab_y, torch.int8), pb.alpha if alpha is None else alpha,
+                 precision=precision,
+                 max_shifts=max_shifts if max_shifts is not None else max(1, len(pb.betas)), max_chunk=max_chunk,
+                 **kw)
+        return op
+
+    # -- calls -------------------------------------------------------------
+    def rhs(self, r=None, stream=None):
+        import torch
+        b = torch.empty(self.d, dtype=torch.float64, device=self.device)
+        _check(lib().fsda_rhs(self.handle, _ptr(r), _ptr(b), _stream(stream)))
+        return b
+
+    def apply(self, sigma: float, p, stream=None):
+        import torch
+        q = torch.empty(self.d, dtype=torch.float64, device=self.device)
+        _check(lib().fsda_apply(self.handle, float(sigma), _ptr(p), _ptr(q), _stream(stream)))
+        return q
+
+    def solve(self, betas: Sequence[float], rtol: float, maxit: int = 100000, chunk: int = 0, b=None, out=None,
+              stream=None):
+        """Returns (W [S, d] float64 tensor, iters [S] int32, relres [S] float64, status)."""
+        import torch
+        betas = np.ascontiguousarray(betas, dtype=np.float64)
+        S = betas.size
+        W = out if out is not None else torch.empty((S, self.d), dtype=torch.float64, device=self.device)
+        iters = np.zeros(S, dtype=np.int32)
+        relres = np.zeros(S, dtype=np.float64)
+        rc = _check(lib().fsda_multishift_solve(self.handle, _ptr(b), betas.ctypes.data_as(ctypes.c_void_p), S,
+                                                float(rtol), int(maxit), int(chunk), _ptr(W),
+                                                iters.ctypes.data_as(ctypes.c_void_p),
+                                                relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return W, iters, relres, rc
+
+    def project(self, W, stream=None):
+        import torch
+        W = W.contiguous()
+        S = W.shape[0]
+        out = torch.empty((S, self.n), dtype=torch.float64, device=self.device)
+        _check(lib().fsda_project(self.handle, _ptr(W), S, _ptr(out), _stream(stream)))
+        return out
+
+    def time_kernel(self, kernel: int, enable: bool = True):
+        _check(lib().fsda_time_kernel(self.handle, int(kernel), int(enable)))
+
+    def kernel_time(self):
+        ms = ctypes.c_double(0)
+        n = ctypes.c_int64(0)
+        _check(lib().fsda_kernel_time(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fsda_destroy_operator(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

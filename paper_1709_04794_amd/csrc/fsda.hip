@@ -1,0 +1,851 @@
+// MI355X (gfx950) multi-shift solver for fast semi-supervised discriminant
+// analysis (FSDA, arXiv:1709.04794): host driver and the C ABI of
+// include/fsda.h.  Device code is in kernels.h.
+//
+// One iteration of the shared recurrence (Alg. 3 seeded at sigma0 = min beta)
+// is five products/updates on one stream:
+//   K1 k_rows<EpiX>      t = X p                (+ labeled mean of t for the centring)
+//   K2 k_rows<EpiLap>    u = (1-alpha)[labeled](t - c) + alpha (D - S) t
+//   K3 k_tiles/k_fixup/k_rows<EpiXT>  q = X^T u + sigma0 p (+ <p,q> partials)
+//   K4 k_resid           a_i, r_{i+1} = r_i - a_i q (+ <r,r> partials; zeta_{i+1})
+//   K5 k_pupdate         b_{i+1}, p_{i+1} = r_{i+1} + b_{i+1} p_i (per-shift stops)
+// and every `chunk` iterations one k_fold replays the per-shift recurrences
+//   W_s += a_s P_s ;  P_s = zeta_{i+1,s} r_{i+1} + b_s P_s      (Alg. 3, per shift)
+// over the buffered residuals, reading and writing each shift's state once per
+// chunk instead of once per iteration.  A chunk is captured once as a HIP
+// graph and replayed; the host reads a 16-byte status after each chunk.
+//
+// Features are relabeled internally by decreasing frequency: the popular
+// entries of the feature-space vectors share cache lines (the gathers of
+// t = X p hit in L2), and the rows of X^T come sorted by length, so the long
+// ones form a prefix handled by nonzero tiles and the rest fall into a few
+// length bins with a fixed number of lanes per row.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fsda.h"
+#include "kernels.h"
+
+using namespace fsda;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                                 \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess) return fail(FSDA_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int GRID_TILES = 1024;
+constexpr int GRID_ROWS = 2048;
+constexpr int GRID_STREAM = 512;
+constexpr int GRID_FOLD = 2048;
+constexpr int LONG_ROW = 1024;  // X^T rows at least this long go to split tiles
+constexpr size_t SORT_RESERVE = size_t(32) << 20;
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
+int grid_for(long long n, int cap) { return (int)std::max<long long>(1, std::min<long long>(ceil_div(n, BS), cap)); }
+int pow2_at_least(long long x) {
+  int p = 1;
+  while (p < x && p < 64) p <<= 1;
+  return p;
+}
+
+struct Layout {
+  size_t st, part, hist, labw, ycen, zw, t, u, b, p, q, bu, new2old, old2new, xcol, xt_rowptr, xt_col;
+  size_t tile_row, cross, head, tail;
+  size_t uni;
+  size_t ring, P;                                                         // union: solve
+  size_t mark, cnt, iota, cnt_sorted, rowid, keys, sort_tmp, sort_bytes;  // union: build
+  size_t total;
+  long long ldd;
+  int ntiles_max;
+};
+
+void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
+  const long long n = pb->n, d = pb->d, z = std::max<long long>(pb->x_nnz, 1);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at_ = o;
+    o = a256(o + bytes);
+    return at_;
+  };
+  L->ldd = (d + 63) / 64 * 64;
+  L->ntiles_max = (int)ceil_div(z, CAP) + 1;
+  L->st = take(sizeof(State));
+  L->part = take(sizeof(double) * NSITE * NPART);
+  L->hist = take(sizeof(double) * MAXCHUNK * MAXS * 4);
+  L->labw = take(8 * n);
+  L->ycen = take(8 * n);
+  L->zw = take(8 * n);
+  L->t = take(8 * n);
+  L->u = take(8 * n);
+  L->b = take(8 * d);
+  L->p = take(8 * d);
+  L->q = take(8 * d);
+  L->bu = take(8 * d);
+  L->new2old = take(4 * d);
+  L->old2new = take(4 * d);
+  L->xcol = take(4 * z);
+  L->xt_rowptr = take(4 * (d + 1));
+  L->xt_col = take(4 * z);
+  L->tile_row = take(4 * ((size_t)L->ntiles_max + 1));
+  L->cross = take(4 * (size_t)L->ntiles_max);
+  L->head = take(8 * (size_t)L->ntiles_max);
+  L->tail = take(8 * (size_t)L->ntiles_max);
+  L->uni = o;
+  size_t u = o;
+  L->ring = u;
+  u = a256(u + 8 * (size_t)L->ldd * max_chunk);
+  L->P = u;
+  u = a256(u + 8 * (size_t)L->ldd * max_shifts);
+  const size_t solve_end = u;
+  u = o;
+  L->mark = u;
+  u = a256(u + 4 * (size_t)n);
+  L->cnt = u;
+  u = a256(u + 4 * (size_t)d);
+  L->iota = u;
+  u = a256(u + 4 * (size_t)d);
+  L->cnt_sorted = u;
+  u = a256(u + 4 * (size_t)d);
+  L->rowid = u;
+  u = a256(u + 4 * (size_t)z);
+  L->keys = u;
+  u = a256(u + 4 * (size_t)z);
+  L->sort_tmp = u;
+  L->sort_bytes = SORT_RESERVE + 12 * (size_t)z + 12 * (size_t)d;
+  u = a256(u + L->sort_bytes);
+  L->total = std::max(solve_end, u);
+}
+
+struct TPair {
+  hipEvent_t a, b;
+  int tag;
+};
+
+struct GraphKey {
+  const double* W;
+  const double* rhs;
+  int nshift, chunk;
+  double sigma0;
+  bool operator==(const GraphKey& o) const {
+    return W == o.W && rhs == o.rhs && nshift == o.nshift && chunk == o.chunk && sigma0 == o.sigma0;
+  }
+};
+
+struct XtPlan {  // X^T product: long-row prefix in split tiles, the rest in length bins
+  Tiles tl;
+  bool has_tiles;
+  int gridA, gridB;
+  Rows rows;
+  int gridR;
+  int npart() const { return (has_tiles ? gridA + gridB : 0) + gridR; }
+};
+
+struct RowPlan {
+  Rows rows;
+  int grid;
+};
+
+}  // namespace
+
+struct fsda_op {
+  fsda_problem pb;
+  int max_shifts, max_chunk;
+  char* ws;
+  size_t ws_bytes;
+  Layout L;
+  RowPlan px, px_user, ps;
+  XtPlan pxt;
+  State* st;
+  State* hst;  // pinned host mirror
+  double *part, *hist, *labw, *ycen, *zw, *t, *u, *b, *p, *q, *bu, *ring, *P;
+  int *new2old, *old2new, *xcol, *xt_rowptr, *xt_col;
+  int npos, nneg;
+  int xt_bins[6];  // rows of X^T with length >= 1024, 256, 64, 16, 1 (sorted order), and d
+  // kernel timing: event pairs around the launches of one kernel class; a
+  // pair's tag is the iteration index inside its chunk (or -1), so launches
+  // after the recurrence stopped (which return at once) are left out
+  int tk_class, tk_on;
+  std::vector<TPair> pairs;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used;
+  int cur_tag;
+  double tk_ms;
+  long long tk_n;
+  // one chunk of the solve captured as a HIP graph, replayed every chunk
+  hipStream_t cap;
+  hipGraphExec_t gexec;
+  GraphKey gkey;
+  int use_graph;
+};
+
+namespace {
+
+template <class T>
+T* at(fsda_op* op, size_t off) {
+  return reinterpret_cast<T*>(op->ws + off);
+}
+
+int tk_flush(fsda_op* op, int real) {
+  for (const TPair& t : op->pairs) {
+    if (t.tag >= real) continue;
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
+    op->tk_ms += ms;
+    op->tk_n++;
+  }
+  op->pairs.clear();
+  op->pool_used = 0;
+  return FSDA_OK;
+}
+
+hipEvent_t tk_event(fsda_op* op) {
+  if (op->pool_used == op->pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    op->pool.push_back(e);
+  }
+  return op->pool[op->pool_used++];
+}
+
+// Kernel classes for fsda_time_kernel.
+enum {
+  KC_X = 0,
+  KC_S = 1,
+  KC_XT = 2,
+  KC_XT_FIX = 3,
+  KC_RESID = 4,
+  KC_PUPD = 5,
+  KC_FOLD = 6,
+  KC_XT_ROWS = 7,
+  KC_OTHER = 99
+};
+
+// Records an event pair around `f` when kernel class `cls` is being timed.
+template <class F>
+void launch(fsda_op* op, int cls, hipStream_t s, F f) {
+  const bool tm = op->tk_on && op->tk_class == cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (tm) {
+    a = tk_event(op);
+    b = tk_event(op);
+  }
+  if (a && b) (void)hipEventRecord(a, s);
+  f();
+  if (a && b) {
+    (void)hipEventRecord(b, s);
+    op->pairs.push_back(TPair{a, b, op->cur_tag});
+  }
+}
+
+template <class Epi>
+void run_rows(fsda_op* op, const RowPlan& pl, const double* src, Epi epi, double* part, int solve, hipStream_t s,
+              int cls) {
+  launch(op, cls, s, [&] {
+    hipLaunchKernelGGL(k_rows<Epi>, dim3(pl.grid), dim3(BS), 0, s, pl.rows, src, epi, op->st, part, 0, solve);
+  });
+}
+
+// X^T product; partial slots: tiles [0, gridA), fix-up [gridA, gridA+gridB), rows after.
+template <class Epi>
+void run_xt(fsda_op* op, const double* src, Epi epi, int solve, hipStream_t s, int cls_tiles) {
+  const XtPlan& pl = op->pxt;
+  double* part = op->part + SITE_XT * NPART;
+  int slot = 0;
+  if (pl.has_tiles) {
+    launch(op, cls_tiles, s, [&] {
+      hipLaunchKernelGGL(k_tiles<Epi>, dim3(pl.gridA), dim3(BS), 0, s, pl.tl, src, epi, op->st, part, 0, solve);
+    });
+    launch(op, cls_tiles == KC_XT ? KC_XT_FIX : KC_OTHER, s, [&] {
+      hipLaunchKernelGGL(k_fixup<Epi>, dim3(pl.gridB), dim3(BS), 0, s, pl.tl, epi, op->st, part, pl.gridA, solve);
+    });
+    slot = pl.gridA + pl.gridB;
+  }
+  launch(op, cls_tiles == KC_XT ? KC_XT_ROWS : KC_OTHER, s, [&] {
+    hipLaunchKernelGGL(k_rows<Epi>, dim3(pl.gridR), dim3(BS), 0, s, pl.rows, src, epi, op->st, part, slot, solve);
+  });
+}
+
+bool has_lab_term(const fsda_op* op) { return op->pb.alpha < 1.0; }
+
+// t = X' src (internal feature order).  Partials: sum over labeled rows of t / l.
+void product_x(fsda_op* op, const double* src, int solve, hipStream_t s) {
+  if (has_lab_term(op))
+    run_rows(op, op->px, src, EpiX<true>{op->t, op->labw}, op->part + SITE_X * NPART, solve, s, KC_X);
+  else
+    run_rows(op, op->px, src, EpiX<false>{op->t, nullptr}, op->part + SITE_X * NPART, solve, s, KC_X);
+}
+
+void product_lap(fsda_op* op, int solve, hipStream_t s) {
+  const double a = op->pb.alpha;
+  if (has_lab_term(op))
+    run_rows(op, op->ps, op->t,
+             EpiLap<true>{op->t, op->labw, op->pb.s_rowptr, op->u, a, op->part + SITE_X * NPART, op->px.grid, 0.0},
+             op->part, solve, s, KC_S);
+  else
+    run_rows(op, op->ps, op->t, EpiLap<false>{op->t, nullptr, op->pb.s_rowptr, op->u, a, nullptr, 0, 0.0}, op->part,
+             solve, s, KC_S);
+}
+
+// q = A(sigma) p in the internal feature order (the operator product of one Krylov step)
+void apply_internal(fsda_op* op, double sigma, const double* p, double* q, int solve, hipStream_t s, int cls) {
+  product_x(op, p, solve, s);
+  product_lap(op, solve, s);
+  run_xt(op, op->u, EpiXT<true>{q, p, sigma}, solve, s, cls);
+}
+
+int stream_grid(long long d) { return grid_for(ceil_div(d, UNR), GRID_STREAM); }
+
+void iteration(fsda_op* op, double sigma0, hipStream_t s, int tag) {
+  op->cur_tag = tag;
+  apply_internal(op, sigma0, op->p, op->q, 1, s, KC_XT);
+  const long long d = op->pb.d;
+  const int gs = stream_grid(d);
+  launch(op, KC_RESID, s, [&] {
+    hipLaunchKernelGGL(k_resid, dim3(gs), dim3(BS), 0, s, op->st, op->q, op->ring, op->L.ldd, d,
+                       op->part + SITE_XT * NPART, op->pxt.npart(), op->part + SITE_R * NPART);
+  });
+  launch(op, KC_PUPD, s, [&] {
+    hipLaunchKernelGGL(k_pupdate, dim3(gs), dim3(BS), 0, s, op->st, op->ring, op->p, op->L.ldd, d,
+                       op->part + SITE_R * NPART, gs, op->hist);
+  });
+  op->cur_tag = -1;
+}
+
+void fold(fsda_op* op, double* W, int nshift, int chunk, hipStream_t s) {
+  const long long d = op->pb.d;
+  const int g = grid_for(d, GRID_FOLD);
+  const size_t shm = (size_t)chunk * nshift * (3 * sizeof(double) + sizeof(int));
+  launch(op, KC_FOLD, s, [&] {
+    if (chunk <= 8)
+      hipLaunchKernelGGL(k_fold<8>, dim3(g), dim3(BS), shm, s, op->st, op->hist, op->ring, op->L.ldd, W, d, op->P,
+                         op->L.ldd, nshift);
+    else if (chunk <= 16)
+      hipLaunchKernelGGL(k_fold<16>, dim3(g), dim3(BS), shm, s, op->st, op->hist, op->ring, op->L.ldd, W, d, op->P,
+                         op->L.ldd, nshift);
+    else if (chunk <= 32)
+      hipLaunchKernelGGL(k_fold<32>, dim3(g), dim3(BS), shm, s, op->st, op->hist, op->ring, op->L.ldd, W, d, op->P,
+                         op->L.ldd, nshift);
+    else
+      hipLaunchKernelGGL(k_fold<64>, dim3(g), dim3(BS), shm, s, op->st, op->hist, op->ring, op->L.ldd, W, d, op->P,
+                         op->L.ldd, nshift);
+  });
+  hipLaunchKernelGGL(k_fold_done, dim3(1), dim3(1), 0, s, op->st);
+}
+
+void drop_graph(fsda_op* op) {
+  if (op->gexec) (void)hipGraphExecDestroy(op->gexec);
+  op->gexec = nullptr;
+}
+
+int check_problem(const fsda_problem* pb) {
+  if (!pb) return fail(FSDA_E_ARG, "problem is NULL");
+  if (pb->n <= 0 || pb->d <= 0) return fail(FSDA_E_ARG, "n and d must be positive");
+  if (pb->n >= (1LL << 31) || pb->d >= (1LL << 31) || pb->x_nnz >= (1LL << 31) || pb->s_nnz >= (1LL << 31) ||
+      pb->n_lab >= (1LL << 31))
+    return fail(FSDA_E_OVERFLOW, "a size does not fit int32 indices");
+  if (pb->x_nnz < 0 || pb->s_nnz < 0) return fail(FSDA_E_ARG, "negative nnz");
+  if (!pb->x_rowptr || (!pb->x_col && pb->x_nnz > 0)) return fail(FSDA_E_ARG, "X arrays are NULL");
+  if (!pb->s_rowptr || (!pb->s_col && pb->s_nnz > 0)) return fail(FSDA_E_ARG, "S arrays are NULL");
+  if (!pb->lab_idx || !pb->lab_y) return fail(FSDA_E_ARG, "label arrays are NULL");
+  if (pb->n_lab < 2 || pb->n_lab > pb->n) return fail(FSDA_E_LABELS, "need 2 <= n_lab <= n");
+  if (!(pb->alpha >= 0.0 && pb->alpha <= 1.0)) return fail(FSDA_E_RANGE, "alpha must lie in [0, 1]");
+  if (pb->precision != FSDA_FP64 && pb->precision != FSDA_MIXED) return fail(FSDA_E_ARG, "unknown precision");
+  return FSDA_OK;
+}
+
+int check_csr(const int* rowptr, const int* col, long long nrows, long long nnz, long long ncols, int noself,
+              int* flag_dev, int* flag_host, hipStream_t s, const char* what) {
+  const int g = grid_for(nrows, 1024);
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, flag_dev, 1LL, 0);
+  hipLaunchKernelGGL(k_check_rowptr, dim3(g), dim3(BS), 0, s, rowptr, nrows, nnz, flag_dev);
+  HIP_TRY(hipMemcpyAsync(flag_host, flag_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (*flag_host) return fail(FSDA_E_CSR, std::string(what) + ": row pointers are malformed");
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_check_cols, dim3(g), dim3(BS), 0, s, rowptr, col, nrows, ncols, noself, flag_dev);
+    HIP_TRY(hipMemcpyAsync(flag_host, flag_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (*flag_host & 2) return fail(FSDA_E_CSR, std::string(what) + ": column index out of range");
+    if (*flag_host & 4) return fail(FSDA_E_CSR, std::string(what) + ": columns not strictly increasing in a row");
+    if (*flag_host & 8) return fail(FSDA_E_CSR, std::string(what) + ": self loop");
+  }
+  return FSDA_OK;
+}
+
+// One bin, lanes per row from the mean row length.
+RowPlan one_bin(const int* rowptr, const int* col, long long nrows, long long nnz) {
+  RowPlan pl;
+  std::memset(&pl, 0, sizeof(pl));
+  pl.rows.rowptr = rowptr;
+  pl.rows.col = col;
+  pl.rows.nb = 1;
+  pl.rows.row0[0] = 0;
+  pl.rows.row0[1] = (int)nrows;
+  const int lpr = pow2_at_least(ceil_div(std::max<long long>(nnz, 1), std::max<long long>(nrows, 1) * UNR));
+  pl.rows.lpr[0] = lpr;
+  pl.rows.item0[0] = 0;
+  pl.rows.item0[1] = (int)ceil_div(nrows, BS / lpr);
+  pl.grid = std::max(1, std::min(pl.rows.item0[1], GRID_ROWS));
+  return pl;
+}
+
+// Split tiles of the long-row prefix [0, nlong) of X^T.
+void make_tiles(fsda_op* op, int nlong, long long nnz_long, hipStream_t s) {
+  XtPlan& pl = op->pxt;
+  pl.has_tiles = nlong > 0 && nnz_long > 0;
+  if (!pl.has_tiles) {
+    pl.gridA = pl.gridB = 0;
+    return;
+  }
+  const int nt = (int)ceil_div(nnz_long, CAP);
+  Tiles& tl = pl.tl;
+  tl.rowptr = op->xt_rowptr;
+  tl.col = op->xt_col;
+  tl.nrows = nlong;
+  tl.nnz = nnz_long;
+  tl.ntiles = nt;
+  tl.split = 1;
+  tl.tile = CAP;
+  tl.tile_row = at<int>(op, op->L.tile_row);
+  tl.cross = at<int>(op, op->L.cross);
+  tl.head = at<double>(op, op->L.head);
+  tl.tail = at<double>(op, op->L.tail);
+  hipLaunchKernelGGL(k_tile_rows, dim3(grid_for(nt + 1, 1024)), dim3(BS), 0, s, op->xt_rowptr, nlong, nnz_long, nt,
+                     CAP, at<int>(op, op->L.tile_row));
+  hipLaunchKernelGGL(k_cross, dim3(grid_for(nt, 1024)), dim3(BS), 0, s, op->xt_rowptr, nnz_long, nt, CAP,
+                     tl.tile_row, at<int>(op, op->L.cross));
+  hipLaunchKernelGGL(k_fill_d, dim3(grid_for(nt, 1024)), dim3(BS), 0, s, tl.head, (long long)nt, 0.0);
+  hipLaunchKernelGGL(k_fill_d, dim3(grid_for(nt, 1024)), dim3(BS), 0, s, tl.tail, (long long)nt, 0.0);
+  pl.gridA = std::min(nt, GRID_TILES);
+  pl.gridB = (int)std::max<long long>(1, std::min<long long>(ceil_div(nt, BS), 256));
+}
+
+// Length bins of the rows [nlong, d) of X^T (lengths decreasing).
+void make_xt_bins(fsda_op* op) {
+  XtPlan& pl = op->pxt;
+  Rows& R = pl.rows;
+  std::memset(&R, 0, sizeof(R));
+  R.rowptr = op->xt_rowptr;
+  R.col = op->xt_col;
+  // xt_bins: counts of rows with length >= 1024, 256, 64, 16, 1; then d
+  const int lprs[5] = {64, 16, 4, 1, 0};
+  int nb = 0, item = 0;
+  for (int k = 0; k < 5; k++) {
+    const int r0 = op->xt_bins[k], r1 = op->xt_bins[k + 1];
+    if (r1 <= r0) continue;
+    R.row0[nb] = r0;
+    R.row0[nb + 1] = r1;
+    R.lpr[nb] = lprs[k];
+    R.item0[nb] = item;
+    item += (int)ceil_div(r1 - r0, lprs[k] ? BS / lprs[k] : BS);
+    R.item0[nb + 1] = item;
+    nb++;
+  }
+  R.nb = nb;
+  if (nb == 0) {  // every row is long
+    R.nb = 1;
+    R.row0[0] = R.row0[1] = (int)op->pb.d;
+    R.lpr[0] = 0;
+    R.item0[0] = R.item0[1] = 0;
+  }
+  pl.gridR = std::max(1, std::min(R.item0[R.nb], GRID_ROWS));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* fsda_last_error(void) { return g_err.c_str(); }
+
+int fsda_workspace_size(const fsda_problem* pb, int max_shifts, int max_chunk, size_t* bytes) {
+  int rc = check_problem(pb);
+  if (rc) return rc;
+  if (!bytes) return fail(FSDA_E_ARG, "bytes is NULL");
+  if (max_shifts < 1 || max_shifts > FSDA_MAX_SHIFTS) return fail(FSDA_E_RANGE, "max_shifts out of range");
+  if (max_chunk < 1 || max_chunk > FSDA_MAX_CHUNK) return fail(FSDA_E_RANGE, "max_chunk out of range");
+  Layout L;
+  layout(pb, max_shifts, max_chunk, &L);
+  *bytes = L.total;
+  return FSDA_OK;
+}
+
+void fsda_destroy_operator(fsda_op* op) {
+  if (!op) return;
+  drop_graph(op);
+  for (hipEvent_t e : op->pool) (void)hipEventDestroy(e);
+  if (op->cap) (void)hipStreamDestroy(op->cap);
+  if (op->hst) (void)hipHostFree(op->hst);
+  delete op;
+}
+
+int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, void* workspace, size_t ws_bytes,
+                        void* stream, fsda_op** out) {
+  if (!out) return fail(FSDA_E_ARG, "out is NULL");
+  *out = nullptr;
+  size_t need = 0;
+  int rc = fsda_workspace_size(pb, max_shifts, max_chunk, &need);
+  if (rc) return rc;
+  if (!workspace || ws_bytes < need)
+    return fail(FSDA_E_WORKSPACE, "workspace NULL or smaller than fsda_workspace_size()");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(FSDA_E_WORKSPACE, "workspace not 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  fsda_op* op = new fsda_op();
+  op->pb = *pb;
+  op->max_shifts = max_shifts;
+  op->max_chunk = max_chunk;
+  op->ws = static_cast<char*>(workspace);
+  op->ws_bytes = ws_bytes;
+  layout(pb, max_shifts, max_chunk, &op->L);
+  op->tk_class = -1;
+  op->cur_tag = -1;
+  op->use_graph = 1;
+  {
+    const char* e = getenv("FSDA_NO_GRAPH");
+    if (e && e[0] == '1') op->use_graph = 0;
+  }
+  auto bail = [&](int code) {
+    fsda_destroy_operator(op);
+    return code;
+  };
+  if (hipStreamCreateWithFlags(&op->cap, hipStreamNonBlocking) != hipSuccess) {
+    op->cap = nullptr;
+    return bail(fail(FSDA_E_HIP, "hipStreamCreateWithFlags failed"));
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&op->hst), sizeof(State), hipHostMallocDefault) != hipSuccess) {
+    op->hst = nullptr;
+    return bail(fail(FSDA_E_HIP, "hipHostMalloc of the status mirror failed"));
+  }
+  const Layout& L = op->L;
+  op->st = at<State>(op, L.st);
+  op->part = at<double>(op, L.part);
+  op->hist = at<double>(op, L.hist);
+  op->labw = at<double>(op, L.labw);
+  op->ycen = at<double>(op, L.ycen);
+  op->zw = at<double>(op, L.zw);
+  op->t = at<double>(op, L.t);
+  op->u = at<double>(op, L.u);
+  op->b = at<double>(op, L.b);
+  op->p = at<double>(op, L.p);
+  op->q = at<double>(op, L.q);
+  op->bu = at<double>(op, L.bu);
+  op->ring = at<double>(op, L.ring);
+  op->P = at<double>(op, L.P);
+  op->new2old = at<int>(op, L.new2old);
+  op->old2new = at<int>(op, L.old2new);
+  op->xcol = at<int>(op, L.xcol);
+  op->xt_rowptr = at<int>(op, L.xt_rowptr);
+  op->xt_col = at<int>(op, L.xt_col);
+
+  const long long n = pb->n, d = pb->d, z = pb->x_nnz, g = pb->s_nnz;
+  int* flag_dev = at<int>(op, L.part);  // scratch before any solve uses the partials
+  int* flag_host = reinterpret_cast<int*>(op->hst);
+
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(BS), 0, s, reinterpret_cast<int*>(op->st),
+                     (long long)(sizeof(State) / 4), 0);
+
+  // 1. validate the CSR arrays before any kernel gathers through them
+  if ((rc = check_csr(pb->x_rowptr, pb->x_col, n, z, d, 0, flag_dev, flag_host, s, "X"))) return bail(rc);
+  if ((rc = check_csr(pb->s_rowptr, pb->s_col, n, g, n, 1, flag_dev, flag_host, s, "S"))) return bail(rc);
+
+  // 2. labels
+  {
+    int* mark = at<int>(op, L.mark);
+    int* cnt = flag_dev;
+    hipLaunchKernelGGL(k_fill_i, dim3(grid_for(n, 1024)), dim3(BS), 0, s, mark, n, 0);
+    hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, cnt, 3LL, 0);
+    hipLaunchKernelGGL(k_check_labels, dim3(grid_for(pb->n_lab, 1024)), dim3(BS), 0, s, pb->lab_idx, pb->lab_y,
+                       pb->n_lab, n, mark, cnt);
+    HIP_TRY(hipMemcpyAsync(flag_host, cnt, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (flag_host[2] & 1) return bail(fail(FSDA_E_LABELS, "labeled index out of range"));
+    if (flag_host[2] & 2) return bail(fail(FSDA_E_LABELS, "labeled index repeated"));
+    if (flag_host[2] & 4) return bail(fail(FSDA_E_LABELS, "labels must be +1 or -1"));
+    op->npos = flag_host[0];
+    op->nneg = flag_host[1];
+    if (op->npos == 0 || op->nneg == 0) return bail(fail(FSDA_E_LABELS, "both classes must be labeled"));
+    hipLaunchKernelGGL(k_fill_d, dim3(grid_for(n, 1024)), dim3(BS), 0, s, op->labw, n, 0.0);
+    hipLaunchKernelGGL(k_fill_d, dim3(grid_for(n, 1024)), dim3(BS), 0, s, op->ycen, n, 0.0);
+    hipLaunchKernelGGL(k_fill_d, dim3(grid_for(n, 1024)), dim3(BS), 0, s, op->zw, n, 0.0);
+    hipLaunchKernelGGL(k_label_vectors, dim3(grid_for(pb->n_lab, 1024)), dim3(BS), 0, s, pb->lab_idx, pb->lab_y,
+                       pb->n_lab, op->npos, op->nneg, op->labw, op->ycen, op->zw);
+  }
+
+  // 3. relabel features by decreasing frequency (ties by id), then X^T in the
+  //    new order as a stable sort of the nonzeros by new column id
+  {
+    int* cnt = at<int>(op, L.cnt);
+    int* iota = at<int>(op, L.iota);
+    int* cnt_sorted = at<int>(op, L.cnt_sorted);
+    void* tmp = op->ws + L.sort_tmp;
+    hipLaunchKernelGGL(k_fill_i, dim3(grid_for(d, 2048)), dim3(BS), 0, s, cnt, d, 0);
+    if (z > 0) hipLaunchKernelGGL(k_col_count, dim3(grid_for(z, 4096)), dim3(BS), 0, s, pb->x_col, z, cnt);
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(d, 2048)), dim3(BS), 0, s, iota, d);
+    int end_bit = 1;
+    while (end_bit < 31 && (1LL << end_bit) <= n) end_bit++;  // counts are <= n
+    size_t tb = 0;
+    HIP_TRY(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, cnt, cnt_sorted, iota, op->new2old, (int)d, 0,
+                                                         end_bit, s));
+    if (tb > L.sort_bytes)
+      return bail(fail(FSDA_E_WORKSPACE, "feature sort needs " + std::to_string(tb) + " bytes of temporary storage"));
+    HIP_TRY(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, cnt, cnt_sorted, iota, op->new2old, (int)d, 0,
+                                                         end_bit, s));
+    hipLaunchKernelGGL(k_invert, dim3(grid_for(d, 2048)), dim3(BS), 0, s, op->new2old, op->old2new, d);
+    if (z > 0) {
+      hipLaunchKernelGGL(k_gather_i, dim3(grid_for(z, 4096)), dim3(BS), 0, s, pb->x_col, op->old2new, op->xcol, z);
+      int* keys = at<int>(op, L.keys);
+      int* rowid = at<int>(op, L.rowid);
+      int kb = 1;
+      while (kb < 31 && (1LL << kb) < d) kb++;
+      tb = 0;
+      HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, op->xcol, keys, rowid, op->xt_col, (int)z, 0, kb, s));
+      if (tb > L.sort_bytes)
+        return bail(
+            fail(FSDA_E_WORKSPACE, "transpose sort needs " + std::to_string(tb) + " bytes of temporary storage"));
+      hipLaunchKernelGGL(k_expand_rows, dim3(grid_for(n, 2048)), dim3(BS), 0, s, pb->x_rowptr, n, rowid);
+      HIP_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tb, op->xcol, keys, rowid, op->xt_col, (int)z, 0, kb, s));
+      hipLaunchKernelGGL(k_keys_to_rowptr, dim3(grid_for(d + 1, 2048)), dim3(BS), 0, s, keys, z, (int)d,
+                         op->xt_rowptr);
+    } else {
+      hipLaunchKernelGGL(k_fill_i, dim3(grid_for(d + 1, 1024)), dim3(BS), 0, s, op->xt_rowptr, d + 1, 0);
+    }
+    // row-length classes of X^T (lengths are decreasing in the new order)
+    int* thr = flag_dev;
+    int* cnts = flag_dev + 8;
+    const int th[5] = {LONG_ROW, 256, 64, 16, 1};
+    HIP_TRY(hipMemcpyAsync(thr, th, sizeof(th), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_count_at_least, dim3(1), dim3(64), 0, s, cnt_sorted, d, thr, 5, cnts);
+    HIP_TRY(hipMemcpyAsync(flag_host, cnts, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < 5; k++) op->xt_bins[k] = flag_host[k];
+    op->xt_bins[5] = (int)d;
+    int nnz_long = 0;
+    if (op->xt_bins[0] > 0) {
+      HIP_TRY(hipMemcpyAsync(flag_host, op->xt_rowptr + op->xt_bins[0], sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      nnz_long = flag_host[0];
+    }
+    make_tiles(op, op->xt_bins[0], nnz_long, s);
+    make_xt_bins(op);
+  }
+
+  // 4. row plans of X (internal and user column order) and of S
+  op->px = one_bin(pb->x_rowptr, op->xcol, n, z);
+  op->px_user = one_bin(pb->x_rowptr, pb->x_col, n, z);
+  op->ps = one_bin(pb->s_rowptr, pb->s_col, n, g);
+
+  // 5. canonical right-hand side b = X^T y_c (internal order)
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(BS), 0, s, reinterpret_cast<int*>(op->st), (long long)(sizeof(State) / 4),
+                     0);
+  run_xt(op, op->ycen, EpiXT<false>{op->b, nullptr, 0.0}, 0, s, KC_OTHER);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = op;
+  return FSDA_OK;
+}
+
+int fsda_rhs(fsda_op* op, const double* r, double* b, void* stream) {
+  if (!op || !b) return fail(FSDA_E_ARG, "NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long d = op->pb.d;
+  if (!r) {
+    hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, op->b, op->old2new, b, d);
+  } else {
+    // z^T X r with z = 1+/N+ - 1-/N- (user feature order); b = (z^T X r / 2) X^T y_c
+    run_rows(op, op->px_user, r, EpiX<true>{op->t, op->zw}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
+    hipLaunchKernelGGL(k_gather_scaled_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, op->b, op->old2new, b, d,
+                       op->part + SITE_X * NPART, op->px_user.grid, 0.5);
+  }
+  HIP_TRY(hipGetLastError());
+  return FSDA_OK;
+}
+
+int fsda_apply(fsda_op* op, double sigma, const double* p, double* q, void* stream) {
+  if (!op || !p || !q) return fail(FSDA_E_ARG, "NULL argument");
+  if (!(sigma >= 0.0)) return fail(FSDA_E_RANGE, "sigma must be >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long d = op->pb.d;
+  hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, p, op->new2old, op->bu, d);
+  apply_internal(op, sigma, op->bu, op->q, 0, s, KC_XT);
+  hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, op->q, op->old2new, q, d);
+  HIP_TRY(hipGetLastError());
+  return FSDA_OK;
+}
+
+int fsda_project(fsda_op* op, const double* W, int nshift, double* S, void* stream) {
+  if (!op || !W || !S) return fail(FSDA_E_ARG, "NULL argument");
+  if (nshift < 1) return fail(FSDA_E_ARG, "nshift must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int k = 0; k < nshift; k++)
+    run_rows(op, op->px_user, W + (long long)k * op->pb.d, EpiX<false>{S + (long long)k * op->pb.n, nullptr},
+             op->part, 0, s, KC_OTHER);
+  HIP_TRY(hipGetLastError());
+  return FSDA_OK;
+}
+
+int fsda_multishift_solve(fsda_op* op, const double* b, const double* betas, int nshift, double rtol, int maxit,
+                          int chunk, double* W, int* iters, double* relres, void* stream) {
+  if (!op || !betas || !W || !iters || !relres) return fail(FSDA_E_ARG, "NULL argument");
+  if (nshift < 1 || nshift > op->max_shifts) return fail(FSDA_E_ARG, "nshift outside 1..max_shifts");
+  if (!(rtol > 0.0)) return fail(FSDA_E_RANGE, "rtol must be > 0");
+  if (maxit < 1) return fail(FSDA_E_RANGE, "maxit must be >= 1");
+  if (chunk < 0) return fail(FSDA_E_RANGE, "chunk must be >= 0");
+  if (chunk == 0) chunk = 32;
+  chunk = std::min(chunk, op->max_chunk);
+  while (chunk > 1 && chunk * nshift > MAXCHUNK * MAXS / 2) chunk >>= 1;
+  double sigma0 = betas[0];
+  for (int k = 0; k < nshift; k++) {
+    if (!(betas[k] > 0.0) || !std::isfinite(betas[k])) return fail(FSDA_E_RANGE, "every beta must be finite and > 0");
+    sigma0 = std::min(sigma0, betas[k]);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long d = op->pb.d;
+  const double* rhs = op->b;
+  if (b) {  // user right-hand side into the internal feature order
+    hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, b, op->new2old, op->bu, d);
+    rhs = op->bu;
+  }
+
+  State* h = op->hst;
+  std::memset(h, 0, sizeof(State));
+  h->nshift = nshift;
+  h->maxit = maxit;
+  h->chunk = chunk;
+  h->tol = rtol;  // scaled by ||b|| in k_init_done
+  h->a_prev = 1.0;
+  h->b_cur = 0.0;
+  for (int k = 0; k < nshift; k++) {
+    h->sig[k] = betas[k] - sigma0;
+    h->zp[k] = 1.0;
+    h->z[k] = 1.0;
+    h->active[k] = 1;
+  }
+  HIP_TRY(hipMemcpyAsync(op->st, h, sizeof(State), hipMemcpyHostToDevice, s));
+  const int gi = grid_for(d, 1024);
+  hipLaunchKernelGGL(k_init, dim3(gi), dim3(BS), 0, s, rhs, op->ring, op->p, op->P, op->L.ldd, W, d, nshift,
+                     op->part + SITE_INIT * NPART);
+  hipLaunchKernelGGL(k_init_done, dim3(1), dim3(BS), 0, s, op->st, op->part + SITE_INIT * NPART, gi);
+  HIP_TRY(hipGetLastError());
+
+  // one chunk = `chunk` iterations + the fold, replayed as a graph.  A timed
+  // solve launches directly: events recorded inside a replayed graph carry no
+  // usable timestamps.
+  bool graph = op->use_graph != 0 && !op->tk_on;
+  if (graph) {
+    const GraphKey key{W, rhs, nshift, chunk, sigma0};
+    if (!op->gexec || !(op->gkey == key)) {
+      drop_graph(op);
+      hipGraph_t gr = nullptr;
+      HIP_TRY(hipStreamBeginCapture(op->cap, hipStreamCaptureModeThreadLocal));
+      for (int j = 0; j < chunk; j++) iteration(op, sigma0, op->cap, j);
+      fold(op, W, nshift, chunk, op->cap);
+      const hipError_t ce = hipStreamEndCapture(op->cap, &gr);
+      hipError_t ie = hipErrorUnknown;
+      if (ce == hipSuccess) {
+        ie = hipGraphInstantiate(&op->gexec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+      }
+      if (ce != hipSuccess || ie != hipSuccess) {  // fall back to direct launches (the same kernels)
+        op->gexec = nullptr;
+        (void)hipGetLastError();
+        graph = false;
+      } else {
+        op->gkey = key;
+      }
+    }
+  }
+  const size_t off = offsetof(State, iter);
+  const int max_chunks = (int)std::min<long long>((long long)maxit / chunk + 2, 1LL << 30);
+  int done_iters = 0;
+  for (int c = 0; c < max_chunks; c++) {
+    if (graph) {
+      HIP_TRY(hipGraphLaunch(op->gexec, s));
+    } else {
+      for (int j = 0; j < chunk; j++) iteration(op, sigma0, s, j);
+      fold(op, W, nshift, chunk, s);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(h) + off, reinterpret_cast<char*>(op->st) + off, 4 * sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (op->tk_on) {
+      const int trc = tk_flush(op, h->iter - done_iters);
+      if (trc) return trc;
+    }
+    done_iters = h->iter;
+    if (h->stop) break;
+  }
+  // true residuals of every shift in FP64 (internal order), then W back to the user order
+  for (int k = 0; k < nshift; k++) {
+    double* w = W + (long long)k * d;
+    product_x(op, w, 0, s);
+    product_lap(op, 0, s);
+    run_xt(op, op->u, EpiRes{rhs, w, betas[k]}, 0, s, KC_OTHER);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, op->part + SITE_XT * NPART, op->pxt.npart(),
+                       &op->st->res2[k]);
+    hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, w, op->old2new, op->q, d);
+    HIP_TRY(hipMemcpyAsync(w, op->q, sizeof(double) * d, hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h, op->st, sizeof(State), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (op->tk_on) {
+    const int trc = tk_flush(op, 1 << 30);
+    if (trc) return trc;
+  }
+  for (int k = 0; k < nshift; k++) {
+    iters[k] = h->conv[k];
+    relres[k] = h->bnorm > 0.0 ? std::sqrt(h->res2[k]) / h->bnorm : 0.0;
+  }
+  if (h->status == FSDA_E_BREAKDOWN) return fail(FSDA_E_BREAKDOWN, "CG breakdown: <p, A p> <= 0 or not finite");
+  return h->status == FSDA_NOT_CONVERGED ? FSDA_NOT_CONVERGED : FSDA_OK;
+}
+
+int fsda_time_kernel(fsda_op* op, int kernel, int enable) {
+  if (!op) return fail(FSDA_E_ARG, "NULL handle");
+  op->tk_class = kernel;
+  op->tk_on = enable ? 1 : 0;
+  op->pairs.clear();
+  op->pool_used = 0;
+  op->tk_ms = 0;
+  op->tk_n = 0;
+  return FSDA_OK;
+}
+
+int fsda_kernel_time(fsda_op* op, double* ms, int64_t* launches) {
+  if (!op || !ms || !launches) return fail(FSDA_E_ARG, "NULL argument");
+  int rc = tk_flush(op, 1 << 30);
+  if (rc) return rc;
+  *ms = op->tk_ms;
+  *launches = op->tk_n;
+  op->tk_ms = 0;
+  op->tk_n = 0;
+  return FSDA_OK;
+}
+
+}  // extern "C"

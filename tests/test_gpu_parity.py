@@ -1,0 +1,208 @@
+"""GPU path vs the CPU oracle, through the C ABI (tiny sizes, several tiles, ragged tails).
+
+Tolerances: the spec bar is a relative solution error of 1e-6 per shift
+for the FP64 path.  Operator products differ from the oracle only by the
+summation order (the GPU centres once in sample space, the oracle twice), so
+they are compared at 1e-12 relative to the largest entry.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+fsda = pytest.importorskip("paper_1709_04794_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def maxrel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return synth.workload("tiny")
+
+
+@pytest.fixture(scope="module")
+def tiny_op(tiny):
+    return fsda.Operator.from_problem(tiny)
+
+
+def test_rhs_canonical_and_alg7(tiny, tiny_op):
+    b = tiny_op.rhs().cpu().numpy()
+    assert maxrel(b, oracle.rhs(tiny)) < 1e-13
+    r = synth.uniform(tiny.d, -1.0, 1.0, seed=1, stream=9)
+    bl = tiny_op.rhs(torch.from_numpy(r).cuda()).cpu().numpy()
+    assert maxrel(bl, oracle.rhs(tiny, r)) < 1e-11
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.5, 0.0])
+@pytest.mark.parametrize("sigma", [0.0, 1e-2, 3.0])
+def test_apply_matches_oracle(tiny, alpha, sigma):
+    op = fsda.Operator.from_problem(tiny, alpha=alpha)
+    p = synth.normal(tiny.d, seed=2, stream=3)
+    q = op.apply(sigma, torch.from_numpy(p).cuda()).cpu().numpy()
+    ref = oracle.apply(tiny, sigma, p, alpha=alpha)
+    assert maxrel(q, ref) < 1e-12
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.5, 0.0])
+def test_solve_matches_oracle_tiny(tiny, alpha):
+    op = fsda.Operator.from_problem(tiny, alpha=alpha)
+    W, iters, relres, st = op.solve(tiny.betas, rtol=tiny.rtol)
+    assert st == fsda.OK
+    Wr, itr, relr, rcr = oracle.solve(tiny, rtol=1e-13, maxit=20000, alpha=alpha)
+    W = W.cpu().numpy()
+    for s in range(tiny.betas.size):
+        assert relerr(W[s], Wr[s]) < 1e-6, (s, relerr(W[s], Wr[s]))
+        assert relres[s] < 20 * tiny.rtol, (s, relres[s])
+    # shifts with larger beta stop no later than the seed (smallest beta)
+    assert iters.max() == iters[np.argmin(tiny.betas)]
+
+
+def test_true_residual_reported_matches_oracle_residual(tiny, tiny_op):
+    W, iters, relres, st = tiny_op.solve(tiny.betas, rtol=1e-8)
+    W = W.cpu().numpy()
+    b = oracle.rhs(tiny)
+    for s, beta in enumerate(tiny.betas):
+        r = b - oracle.apply(tiny, beta, W[s])
+        ref = np.linalg.norm(r) / np.linalg.norm(b)
+        assert abs(relres[s] - ref) <= 1e-3 * ref + 1e-15
+        assert ref <= 5e-8
+
+
+@pytest.mark.parametrize("chunk", [1, 3, 16, 64])
+def test_chunk_gives_identical_bits(tiny, tiny_op, chunk):
+    ref, it0, _, _ = tiny_op.solve(tiny.betas, rtol=1e-9, chunk=32)
+    W, it1, _, _ = tiny_op.solve(tiny.betas, rtol=1e-9, chunk=chunk)
+    assert torch.equal(W, ref)
+    assert np.array_equal(it0, it1)
+
+
+def test_repeat_is_deterministic(tiny, tiny_op):
+    a = tiny_op.solve(tiny.betas, rtol=1e-9)[0]
+    b = tiny_op.solve(tiny.betas, rtol=1e-9)[0]
+    assert torch.equal(a, b)
+
+
+def test_project_matches_oracle(tiny, tiny_op):
+    W = torch.from_numpy(np.stack([synth.normal(tiny.d, seed=4, stream=s) for s in range(3)])).cuda()
+    S = tiny_op.project(W).cpu().numpy()
+    assert maxrel(S, oracle.project(tiny, W.cpu().numpy())) < 1e-13
+
+
+def test_user_rhs_alg7(tiny, tiny_op):
+    r = synth.uniform(tiny.d, -1.0, 1.0, seed=5, stream=1)
+    b = tiny_op.rhs(torch.from_numpy(r).cuda())
+    W, it, rel, st = tiny_op.solve(tiny.betas[:3], rtol=1e-10, b=b)
+    Wr, *_ = oracle.solve(tiny, betas=tiny.betas[:3], rtol=1e-13, b=oracle.rhs(tiny, r))
+    for s in range(3):
+        assert relerr(W[s].cpu().numpy(), Wr[s]) < 1e-6
+
+
+def test_single_shift_and_duplicates(tiny, tiny_op):
+    W1, *_ = tiny_op.solve([0.3], rtol=1e-10)
+    W2, *_ = tiny_op.solve([0.3, 0.3, 5.0], rtol=1e-10)
+    assert torch.equal(W2[0], W2[1])
+    assert relerr(W2[0].cpu().numpy(), W1[0].cpu().numpy()) < 1e-12
+    Wr, *_ = oracle.solve(tiny, betas=[0.3], rtol=1e-13)
+    assert relerr(W1[0].cpu().numpy(), Wr[0]) < 1e-6
+
+
+def test_maxit_reports_not_converged(tiny, tiny_op):
+    W, iters, relres, st = tiny_op.solve(tiny.betas, rtol=1e-12, maxit=7, chunk=4)
+    assert st == fsda.NOT_CONVERGED
+    assert iters[np.argmin(tiny.betas)] == 7
+    # the iterate after 7 steps equals 7 steps of plain CG for the seed shift
+    Wr, itr, *_ = oracle.solve(tiny, betas=[tiny.betas.min()], rtol=1e-30, maxit=7)
+    assert relerr(W[np.argmin(tiny.betas)].cpu().numpy(), Wr[0]) < 1e-9
+
+
+def test_ragged_small_problems():
+    """Several tiles, ragged tails, empty feature columns, isolated graph nodes, a shared feature."""
+    for seed, (n, d, nnz) in enumerate([(300, 5000, 9), (1500, 700, 30), (77, 4099, 3)]):
+        pb = synth.small_problem(n=n, d=d, mean_nnz=nnz, k=2, alpha=0.7, seed=seed, betas=(1e-3, 0.05, 2.0, 40.0),
+                                 n_lab=max(4, n // 10))
+        # isolate a few nodes and add a feature present in every row
+        rows = [sorted(set(pb.x_col[pb.x_rowptr[i]:pb.x_rowptr[i + 1]].tolist()) | {d - 1}) for i in range(n)]
+        pb.x_rowptr = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+        pb.x_col = np.concatenate(rows).astype(np.int32)
+        keep = np.ones(pb.s_col.size, dtype=bool)
+        srp = pb.s_rowptr.astype(np.int64)
+        iso = {0, 5, n - 1}
+        src = np.repeat(np.arange(n), np.diff(srp))
+        keep &= ~np.isin(src, list(iso)) & ~np.isin(pb.s_col, list(iso))
+        cnt = np.bincount(src[keep], minlength=n)
+        pb.s_col = pb.s_col[keep].astype(np.int32)
+        pb.s_rowptr = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
+        op = fsda.Operator.from_problem(pb)
+        W, iters, relres, st = op.solve(pb.betas, rtol=1e-11)
+        Wr, *_ = oracle.solve(pb, rtol=1e-13, maxit=50000)
+        for s in range(pb.betas.size):
+            assert relerr(W[s].cpu().numpy(), Wr[s]) < 1e-6, (seed, s)
+        assert abs(W[:, d - 1].cpu().numpy()).max() < 1e-9 * abs(W.cpu().numpy()).max()
+
+
+def test_two_labeled_samples():
+    pb = synth.small_problem(n=200, d=300, mean_nnz=8, k=3, alpha=0.4, seed=3, n_lab=2, pos_frac=0.5)
+    op = fsda.Operator.from_problem(pb)
+    W, iters, relres, st = op.solve(pb.betas, rtol=1e-11)
+    Wr, *_ = oracle.solve(pb, rtol=1e-13, maxit=50000)
+    for s in range(pb.betas.size):
+        assert relerr(W[s].cpu().numpy(), Wr[s]) < 1e-6
+
+
+def test_zero_rhs_gives_zero(tiny, tiny_op):
+    b = torch.zeros(tiny.d, dtype=torch.float64, device="cuda")
+    W, iters, relres, st = tiny_op.solve(tiny.betas, rtol=1e-8, b=b)
+    assert st == fsda.OK
+    assert float(W.abs().max()) == 0.0
+    assert np.all(iters == 0)
+
+
+def test_malformed_inputs_are_rejected(tiny):
+    bad = synth.Problem(**{**tiny.__dict__})
+    bad.x_col = tiny.x_col.copy()
+    bad.x_col[17] = tiny.d + 5
+    with pytest.raises(fsda.FsdaError) as e:
+        fsda.Operator.from_problem(bad)
+    assert e.value.code == fsda.E_CSR
+    bad = synth.Problem(**{**tiny.__dict__})
+    bad.s_rowptr = tiny.s_rowptr.copy()
+    bad.s_rowptr[10] = bad.s_rowptr[11] + 1
+    with pytest.raises(fsda.FsdaError) as e:
+        fsda.Operator.from_problem(bad)
+    assert e.value.code == fsda.E_CSR
+    bad = synth.Problem(**{**tiny.__dict__})
+    bad.lab_idx = tiny.lab_idx.copy()
+    bad.lab_idx[1] = bad.lab_idx[0]
+    with pytest.raises(fsda.FsdaError) as e:
+        fsda.Operator.from_problem(bad)
+    assert e.value.code == fsda.E_LABELS
+    bad = synth.Problem(**{**tiny.__dict__})
+    bad.lab_y = np.ones_like(tiny.lab_y)
+    with pytest.raises(fsda.FsdaError) as e:
+        fsda.Operator.from_problem(bad)
+    assert e.value.code == fsda.E_LABELS
+
+
+def test_graph_replay_equals_direct_launches(tiny, monkeypatch):
+    """The chunk replayed as a HIP graph gives the same bits as launching every kernel."""
+    op_g = fsda.Operator.from_problem(tiny)
+    monkeypatch.setenv("FSDA_NO_GRAPH", "1")
+    op_d = fsda.Operator.from_problem(tiny)
+    monkeypatch.delenv("FSDA_NO_GRAPH")
+    for _ in range(3):  # replays with eager work in between
+        Wg, itg, rg, _ = op_g.solve(tiny.betas, rtol=1e-9, chunk=8)
+        Wd, itd, rd, _ = op_d.solve(tiny.betas, rtol=1e-9, chunk=8)
+        torch.cuda.synchronize()
+        assert torch.equal(Wg, Wd)
+        assert np.array_equal(itg, itd)
+        assert np.array_equal(rg, rd)
