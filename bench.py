@@ -47,8 +47,31 @@ def algorithmic_bytes(kernel: int, pb, nshift: int, chunk: int) -> float:
     return 0.0
 
 
-KNAMES = {0: "k_tiles<EpiX> (t = X p)", 1: "k_tiles<EpiLap> (u = M' t)", 2: "k_tiles<EpiXT> (q = X^T u + s p)",
-          3: "k_fixup<EpiXT>", 4: "k_resid", 5: "k_pupdate", 6: "k_fold"}
+TRAFFIC_KEYS = {2: "k_xt", 0: "k_rows_x", 6: "k_fold"}
+
+
+def measured_traffic(kernel: int, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 byte counters, if they
+    were taken on the current kernel source; otherwise None."""
+    import glob
+    import hashlib
+    key = TRAFFIC_KEYS.get(kernel)
+    if key is None:
+        return None
+    src = os.path.join(ROOT, "paper_1709_04794_amd", "csrc", "kernels.h")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.txt")):
+        for line in open(f):
+            if not line.startswith("TRAFFIC "):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if kv.get("kernel") == key and kv.get("workload") == workload and kv.get("source") == sha:
+                return int(kv["bytes"])
+    return None
+
+
+KNAMES = {0: "k_rows<EpiX> (t = X p)", 1: "k_rows<EpiLap> (u = M' t)", 2: "k_xt<EpiXT> (q = X^T u + s p)",
+          4: "k_resid", 5: "k_pupdate", 6: "k_fold"}
 
 
 def cpu_baseline(pb, budget_s: float):
@@ -74,7 +97,44 @@ def cpu_baseline(pb, budget_s: float):
                       % (pb.name, len(sample), pb.betas.size, pb.rtol, json.dumps(sample))}
 
 
+def summarize_rocprof(d: str, kernel_substr: str, calib_mib: int) -> str:
+    """Condenses rocprofv3 CSV output in directory d into a few lines of text.
+
+    kernel_stats.csv: the --stats table (durations).  counter_collection.csv:
+    per-dispatch counters, averaged per kernel (first 90 chars of the name);
+    for the calibration copy the dispatches whose FETCH/WRITE is at least half
+    of the largest are averaged (the plain copy of calib_mib MiB).
+    """
+    import glob
+    import pandas as pd
+    lines = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+        df = pd.read_csv(f)
+        df["Name"] = df["Name"].str.slice(0, 90)
+        lines.append("kernel stats (%s):" % os.path.basename(f))
+        lines.append(df[["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"]].head(20).to_string())
+    for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        df = pd.read_csv(f)
+        df["Kernel_Name"] = df["Kernel_Name"].str.slice(0, 90)
+        for cname, g in df.groupby("Counter_Name"):
+            agg = g.groupby("Kernel_Name")["Counter_Value"].agg(["count", "mean"]).sort_values("mean",
+                                                                                           ascending=False)
+            lines.append("counter %s (mean per dispatch):" % cname)
+            sel = agg[[kernel_substr in k or "copy" in k.lower() for k in agg.index]]
+            lines.append(sel.head(12).to_string())
+            cp = g[g["Kernel_Name"].str.lower().str.contains("copy")]
+            if len(cp) and calib_mib > 0:
+                big = cp[cp["Counter_Value"] >= 0.5 * cp["Counter_Value"].max()]
+                lines.append("calibration copy of %d MiB: %s = %.1f KiB per dispatch over %d dispatches"
+                             % (calib_mib, cname, big["Counter_Value"].mean(), len(big)))
+    return "\n".join(lines)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-rocprof":
+        # python bench.py --summarize-rocprof DIR KERNEL_SUBSTR CALIB_MIB
+        print(summarize_rocprof(sys.argv[2], sys.argv[3], int(sys.argv[4])))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -85,6 +145,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--cache", default=os.path.join(ROOT, ".synth_cache"))
+    ap.add_argument("--kernel", type=int, default=-1,
+                    help="kernel class to time in the timed region (default: the one with the largest total time)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (profiler calibration of byte counters)")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="extra timed steps with kernel timing off (chunks replayed as HIP graphs), reported in detail")
     args = ap.parse_args()
@@ -95,6 +159,17 @@ def main():
     import torch
     import synth
     import paper_1709_04794_amd as fsda
+
+    if args.calib_copy_mb > 0:
+        nb = args.calib_copy_mb << 20
+        a = torch.empty(nb // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read + %d MiB written per launch, 3 launches" % (args.calib_copy_mb,
+                                                                                     args.calib_copy_mb))
+        del a, c
 
     t0 = time.perf_counter()
     pb = synth.workload(args.workload, seed=args.seed, cache_dir=args.cache)
@@ -119,16 +194,19 @@ def main():
     torch.cuda.synchronize()
     log("warmup done")
 
-    # which kernel dominates: one untimed pass per kernel class
+    # which kernel dominates: one pass per kernel class with that class timed
     per_class = {}
-    for k in range(7):
-        op.time_kernel(k, True)
-        step()
-        ms, nl = op.kernel_time()
-        per_class[k] = (ms, nl)
-        op.time_kernel(k, False)
-    dom = max(per_class, key=lambda k: per_class[k][0])
-    log("per-kernel ms per step: %s" % {KNAMES[k]: round(v[0], 3) for k, v in per_class.items()})
+    if args.kernel < 0:
+        for k in KNAMES:
+            op.time_kernel(k, True)
+            step()
+            ms, nl = op.kernel_time()
+            per_class[k] = (ms, nl)
+            op.time_kernel(k, False)
+        dom = max(per_class, key=lambda k: per_class[k][0])
+        log("per-kernel ms per step: %s" % {KNAMES[k]: round(v[0], 3) for k, v in per_class.items()})
+    else:
+        dom = args.kernel
 
     op.time_kernel(dom, True)
     torch.cuda.synchronize()
@@ -181,7 +259,8 @@ def main():
                    "n": pb.n, "d": pb.d, "nnz_x": pb.x_nnz, "nnz_s": pb.s_nnz, "shifts": S, "chunk": args.chunk,
                    "precision": "fp64"},
         "roofline": {"bound": "hbm", "kernel": KNAMES[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, args.workload),
                      "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "launches": klaunch},
         "detail": {"iters": None if iters_seen is None else iters_seen.tolist(), "worst_relres": worst,

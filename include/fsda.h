@@ -167,10 +167,9 @@ int fsda_project(fsda_op *op, const double *W, int nshift, double *S, void *stre
 /*
  * Per-kernel timing for measurement: enable != 0 makes the handle record a
  * pair of HIP events around every launch of the kernel class `kernel` on the
- * launch stream: 0 = X product, 1 = graph/centring product, 2 = X^T product
- * over the long rows (nonzero tiles), 3 = its fix-up of rows spanning tiles,
- * 4 = residual update, 5 = direction update, 6 = shift-state fold, 7 = X^T
- * product over the other rows.  While timing is on, solves launch kernels
+ * launch stream: 0 = X product, 1 = graph/centring product, 2 = X^T
+ * product, 4 = residual update, 5 = direction update, 6 = shift-state fold
+ * (3 is unused).  While timing is on, solves launch kernels
  * directly instead of replaying a graph.  Launches made after the recurrence
  * stopped (which return at once) are not counted.  fsda_kernel_time() returns
  * (host) the summed milliseconds and launch count of the timed class since

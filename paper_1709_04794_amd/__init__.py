@@ -29,7 +29,7 @@ E_ARG, E_CSR, E_LABELS, E_RANGE, E_BREAKDOWN, E_WORKSPACE, E_HIP, E_OVERFLOW = -
 FP64, MIXED = 0, 1
 MAX_SHIFTS, MAX_CHUNK = 64, 64
 # kernel classes for fsda_time_kernel
-K_X, K_S, K_XT, K_XT_FIX, K_RESID, K_PUPD, K_FOLD, K_XT_ROWS = range(8)
+K_X, K_S, K_XT, K_RESID, K_PUPD, K_FOLD = 0, 1, 2, 4, 5, 6
 
 
 class FsdaError(RuntimeError):

@@ -6,9 +6,10 @@
 // is five products/updates on one stream:
 //   K1 k_rows<EpiX>      t = X p                (+ labeled mean of t for the centring)
 //   K2 k_rows<EpiLap>    u = (1-alpha)[labeled](t - c) + alpha (D - S) t
-//   K3 k_tiles/k_fixup/k_rows<EpiXT>  q = X^T u + sigma0 p (+ <p,q> partials)
-//   K4 k_resid           a_i, r_{i+1} = r_i - a_i q (+ <r,r> partials; zeta_{i+1})
-//   K5 k_pupdate         b_{i+1}, p_{i+1} = r_{i+1} + b_{i+1} p_i (per-shift stops)
+//   K3 k_xt<EpiXT>       q = X^T u + sigma0 p (long rows left as chunk sums)
+//   K4 k_resid           a_i from <t,u> + sigma0 <p,p>, r_{i+1} = r_i - a_i q
+//                        (+ <r,r> partials; zeta_{i+1})
+//   K5 k_pupdate         b_{i+1}, p_{i+1} = r_{i+1} + b_{i+1} p_i (+ <p,p>; per-shift stops)
 // and every `chunk` iterations one k_fold replays the per-shift recurrences
 //   W_s += a_s P_s ;  P_s = zeta_{i+1,s} r_{i+1} + b_s P_s      (Alg. 3, per shift)
 // over the buffered residuals, reading and writing each shift's state once per
@@ -18,7 +19,7 @@
 // Features are relabeled internally by decreasing frequency: the popular
 // entries of the feature-space vectors share cache lines (the gathers of
 // t = X p hit in L2), and the rows of X^T come sorted by length, so the long
-// ones form a prefix handled by nonzero tiles and the rest fall into a few
+// ones form a prefix cut into single-row chunks and the rest fall into a few
 // length bins with a fixed number of lanes per row.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
@@ -52,11 +53,10 @@ int fail(int code, const std::string& msg) {
     if (e_ != hipSuccess) return fail(FSDA_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int GRID_TILES = 1024;
 constexpr int GRID_ROWS = 2048;
-constexpr int GRID_STREAM = 512;
+constexpr int GRID_STREAM = 2048;
 constexpr int GRID_FOLD = 2048;
-constexpr int LONG_ROW = 1024;  // X^T rows at least this long go to split tiles
+constexpr int LONG_ROW = 1024;  // X^T rows at least this long are cut into chunks
 constexpr size_t SORT_RESERVE = size_t(32) << 20;
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -70,13 +70,13 @@ int pow2_at_least(long long x) {
 
 struct Layout {
   size_t st, part, hist, labw, ycen, zw, t, u, b, p, q, bu, new2old, old2new, xcol, xt_rowptr, xt_col;
-  size_t tile_row, cross, head, tail;
+  size_t chunk_row, chunk_beg, lpart, row_chunk0;
   size_t uni;
   size_t ring, P;                                                         // union: solve
   size_t mark, cnt, iota, cnt_sorted, rowid, keys, sort_tmp, sort_bytes;  // union: build
   size_t total;
   long long ldd;
-  int ntiles_max;
+  long long nchunk_max, nlong_max;
 };
 
 void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
@@ -88,7 +88,8 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
     return at_;
   };
   L->ldd = (d + 63) / 64 * 64;
-  L->ntiles_max = (int)ceil_div(z, CAP) + 1;
+  L->nlong_max = z / LONG_ROW + 1;
+  L->nchunk_max = z / CH + L->nlong_max + 1;
   L->st = take(sizeof(State));
   L->part = take(sizeof(double) * NSITE * NPART);
   L->hist = take(sizeof(double) * MAXCHUNK * MAXS * 4);
@@ -106,10 +107,10 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->xcol = take(4 * z);
   L->xt_rowptr = take(4 * (d + 1));
   L->xt_col = take(4 * z);
-  L->tile_row = take(4 * ((size_t)L->ntiles_max + 1));
-  L->cross = take(4 * (size_t)L->ntiles_max);
-  L->head = take(8 * (size_t)L->ntiles_max);
-  L->tail = take(8 * (size_t)L->ntiles_max);
+  L->chunk_row = take(4 * (size_t)L->nchunk_max);
+  L->chunk_beg = take(4 * (size_t)L->nchunk_max);
+  L->lpart = take(8 * (size_t)L->nchunk_max);
+  L->row_chunk0 = take(4 * ((size_t)L->nlong_max + 1));
   L->uni = o;
   size_t u = o;
   L->ring = u;
@@ -151,13 +152,12 @@ struct GraphKey {
   }
 };
 
-struct XtPlan {  // X^T product: long-row prefix in split tiles, the rest in length bins
-  Tiles tl;
-  bool has_tiles;
-  int gridA, gridB;
-  Rows rows;
-  int gridR;
-  int npart() const { return (has_tiles ? gridA + gridB : 0) + gridR; }
+struct XtPlan {  // X^T product: long rows in single-row chunks, the rest in length bins
+  XtWork w;
+  int nlong;
+  const int* row_chunk0;
+  int grid;    // k_xt
+  int gridL;   // k_assemble
 };
 
 struct RowPlan {
@@ -180,7 +180,7 @@ struct fsda_op {
   double *part, *hist, *labw, *ycen, *zw, *t, *u, *b, *p, *q, *bu, *ring, *P;
   int *new2old, *old2new, *xcol, *xt_rowptr, *xt_col;
   int npos, nneg;
-  int xt_bins[6];  // rows of X^T with length >= 1024, 256, 64, 16, 1 (sorted order), and d
+  int xt_bins[8];  // rows of X^T with length >= 1024, 512, 256, 64, 16, 4, 1 (sorted order), and d
   // kernel timing: event pairs around the launches of one kernel class; a
   // pair's tag is the iteration index inside its chunk (or -1), so launches
   // after the recurrence stopped (which return at once) are left out
@@ -232,11 +232,9 @@ enum {
   KC_X = 0,
   KC_S = 1,
   KC_XT = 2,
-  KC_XT_FIX = 3,
   KC_RESID = 4,
   KC_PUPD = 5,
   KC_FOLD = 6,
-  KC_XT_ROWS = 7,
   KC_OTHER = 99
 };
 
@@ -265,25 +263,22 @@ void run_rows(fsda_op* op, const RowPlan& pl, const double* src, Epi epi, double
   });
 }
 
-// X^T product; partial slots: tiles [0, gridA), fix-up [gridA, gridA+gridB), rows after.
+// X^T product.  With `assemble`, the long rows are finished by k_assemble
+// (partial slots: k_xt [0, grid), k_assemble [grid, grid + gridL)); without,
+// their chunk sums stay in lpart for k_resid.
 template <class Epi>
-void run_xt(fsda_op* op, const double* src, Epi epi, int solve, hipStream_t s, int cls_tiles) {
+void run_xt(fsda_op* op, const double* src, Epi epi, int solve, bool assemble, hipStream_t s, int cls) {
   const XtPlan& pl = op->pxt;
   double* part = op->part + SITE_XT * NPART;
-  int slot = 0;
-  if (pl.has_tiles) {
-    launch(op, cls_tiles, s, [&] {
-      hipLaunchKernelGGL(k_tiles<Epi>, dim3(pl.gridA), dim3(BS), 0, s, pl.tl, src, epi, op->st, part, 0, solve);
-    });
-    launch(op, cls_tiles == KC_XT ? KC_XT_FIX : KC_OTHER, s, [&] {
-      hipLaunchKernelGGL(k_fixup<Epi>, dim3(pl.gridB), dim3(BS), 0, s, pl.tl, epi, op->st, part, pl.gridA, solve);
-    });
-    slot = pl.gridA + pl.gridB;
-  }
-  launch(op, cls_tiles == KC_XT ? KC_XT_ROWS : KC_OTHER, s, [&] {
-    hipLaunchKernelGGL(k_rows<Epi>, dim3(pl.gridR), dim3(BS), 0, s, pl.rows, src, epi, op->st, part, slot, solve);
+  launch(op, cls, s, [&] {
+    hipLaunchKernelGGL(k_xt<Epi>, dim3(pl.grid), dim3(BS), 0, s, pl.w, src, epi, op->st, part, solve);
   });
+  if (assemble && pl.nlong > 0)
+    hipLaunchKernelGGL(k_assemble<Epi>, dim3(pl.gridL), dim3(BS), 0, s, pl.nlong, pl.row_chunk0, pl.w.lpart, epi,
+                       op->st, part, pl.grid);
 }
+
+int xt_npart(const fsda_op* op) { return op->pxt.grid + (op->pxt.nlong > 0 ? op->pxt.gridL : 0); }
 
 bool has_lab_term(const fsda_op* op) { return op->pb.alpha < 1.0; }
 
@@ -300,33 +295,36 @@ void product_lap(fsda_op* op, int solve, hipStream_t s) {
   if (has_lab_term(op))
     run_rows(op, op->ps, op->t,
              EpiLap<true>{op->t, op->labw, op->pb.s_rowptr, op->u, a, op->part + SITE_X * NPART, op->px.grid, 0.0},
-             op->part, solve, s, KC_S);
+             op->part + SITE_TU * NPART, solve, s, KC_S);
   else
-    run_rows(op, op->ps, op->t, EpiLap<false>{op->t, nullptr, op->pb.s_rowptr, op->u, a, nullptr, 0, 0.0}, op->part,
-             solve, s, KC_S);
+    run_rows(op, op->ps, op->t, EpiLap<false>{op->t, nullptr, op->pb.s_rowptr, op->u, a, nullptr, 0, 0.0},
+             op->part + SITE_TU * NPART, solve, s, KC_S);
 }
 
 // q = A(sigma) p in the internal feature order (the operator product of one Krylov step)
-void apply_internal(fsda_op* op, double sigma, const double* p, double* q, int solve, hipStream_t s, int cls) {
-  product_x(op, p, solve, s);
-  product_lap(op, solve, s);
-  run_xt(op, op->u, EpiXT<true>{q, p, sigma}, solve, s, cls);
+void apply_internal(fsda_op* op, double sigma, const double* p, double* q, hipStream_t s) {
+  product_x(op, p, 0, s);
+  product_lap(op, 0, s);
+  run_xt(op, op->u, EpiXT<false>{q, p, sigma}, 0, true, s, KC_OTHER);
 }
 
 int stream_grid(long long d) { return grid_for(ceil_div(d, UNR), GRID_STREAM); }
 
 void iteration(fsda_op* op, double sigma0, hipStream_t s, int tag) {
   op->cur_tag = tag;
-  apply_internal(op, sigma0, op->p, op->q, 1, s, KC_XT);
+  product_x(op, op->p, 1, s);
+  product_lap(op, 1, s);
+  run_xt(op, op->u, EpiXT<false>{op->q, op->p, sigma0}, 1, false, s, KC_XT);
   const long long d = op->pb.d;
   const int gs = stream_grid(d);
   launch(op, KC_RESID, s, [&] {
-    hipLaunchKernelGGL(k_resid, dim3(gs), dim3(BS), 0, s, op->st, op->q, op->ring, op->L.ldd, d,
-                       op->part + SITE_XT * NPART, op->pxt.npart(), op->part + SITE_R * NPART);
+    hipLaunchKernelGGL(k_resid, dim3(gs), dim3(BS), 0, s, op->st, op->q, op->p, op->ring, op->L.ldd, d, sigma0,
+                       op->part + SITE_TU * NPART, op->ps.grid, op->part + SITE_PP * NPART, gs, op->pxt.nlong,
+                       op->pxt.row_chunk0, op->pxt.w.lpart, op->part + SITE_R * NPART);
   });
   launch(op, KC_PUPD, s, [&] {
     hipLaunchKernelGGL(k_pupdate, dim3(gs), dim3(BS), 0, s, op->st, op->ring, op->p, op->L.ldd, d,
-                       op->part + SITE_R * NPART, gs, op->hist);
+                       op->part + SITE_R * NPART, gs, op->hist, op->part + SITE_PP * NPART);
   });
   op->cur_tag = -1;
 }
@@ -334,7 +332,7 @@ void iteration(fsda_op* op, double sigma0, hipStream_t s, int tag) {
 void fold(fsda_op* op, double* W, int nshift, int chunk, hipStream_t s) {
   const long long d = op->pb.d;
   const int g = grid_for(d, GRID_FOLD);
-  const size_t shm = (size_t)chunk * nshift * (3 * sizeof(double) + sizeof(int));
+  const size_t shm = 0;
   launch(op, KC_FOLD, s, [&] {
     if (chunk <= 8)
       hipLaunchKernelGGL(k_fold<8>, dim3(g), dim3(BS), shm, s, op->st, op->hist, op->ring, op->L.ldd, W, d, op->P,
@@ -401,7 +399,7 @@ RowPlan one_bin(const int* rowptr, const int* col, long long nrows, long long nn
   pl.rows.nb = 1;
   pl.rows.row0[0] = 0;
   pl.rows.row0[1] = (int)nrows;
-  const int lpr = pow2_at_least(ceil_div(std::max<long long>(nnz, 1), std::max<long long>(nrows, 1) * UNR));
+  const int lpr = pow2_at_least(ceil_div(std::max<long long>(nnz, 1), std::max<long long>(nrows, 1) * RUNR));
   pl.rows.lpr[0] = lpr;
   pl.rows.item0[0] = 0;
   pl.rows.item0[1] = (int)ceil_div(nrows, BS / lpr);
@@ -409,48 +407,54 @@ RowPlan one_bin(const int* rowptr, const int* col, long long nrows, long long nn
   return pl;
 }
 
-// Split tiles of the long-row prefix [0, nlong) of X^T.
-void make_tiles(fsda_op* op, int nlong, long long nnz_long, hipStream_t s) {
+// Work of the X^T product: chunks of the long rows [0, nlong) (from their row
+// pointers, read back to the host once at build time), then length bins of the
+// other rows (lengths decreasing in the internal order).
+int make_xt(fsda_op* op, hipStream_t s) {
   XtPlan& pl = op->pxt;
-  pl.has_tiles = nlong > 0 && nnz_long > 0;
-  if (!pl.has_tiles) {
-    pl.gridA = pl.gridB = 0;
-    return;
+  XtWork& w = pl.w;
+  std::memset(&w, 0, sizeof(w));
+  w.rowptr = op->xt_rowptr;
+  w.col = op->xt_col;
+  w.chunk_row = at<int>(op, op->L.chunk_row);
+  w.chunk_beg = at<int>(op, op->L.chunk_beg);
+  w.lpart = at<double>(op, op->L.lpart);
+  const int nlong = op->xt_bins[0];
+  pl.nlong = nlong;
+  pl.row_chunk0 = at<int>(op, op->L.row_chunk0);
+  if (nlong > 0) {
+    std::vector<int> rp(nlong + 1);
+    HIP_TRY(hipMemcpyAsync(rp.data(), op->xt_rowptr, sizeof(int) * (nlong + 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int> crow, cbeg, c0(nlong + 1);
+    for (int j = 0; j < nlong; j++) {
+      c0[j] = (int)crow.size();
+      for (int k = rp[j]; k < rp[j + 1]; k += CH) {
+        crow.push_back(j);
+        cbeg.push_back(k);
+      }
+    }
+    c0[nlong] = (int)crow.size();
+    if ((long long)crow.size() > op->L.nchunk_max || nlong > op->L.nlong_max)
+      return fail(FSDA_E_WORKSPACE, "long-row chunk table larger than reserved");
+    w.nchunk = (int)crow.size();
+    HIP_TRY(hipMemcpyAsync(const_cast<int*>(w.chunk_row), crow.data(), sizeof(int) * crow.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(const_cast<int*>(w.chunk_beg), cbeg.data(), sizeof(int) * cbeg.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(const_cast<int*>(pl.row_chunk0), c0.data(), sizeof(int) * c0.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
   }
-  const int nt = (int)ceil_div(nnz_long, CAP);
-  Tiles& tl = pl.tl;
-  tl.rowptr = op->xt_rowptr;
-  tl.col = op->xt_col;
-  tl.nrows = nlong;
-  tl.nnz = nnz_long;
-  tl.ntiles = nt;
-  tl.split = 1;
-  tl.tile = CAP;
-  tl.tile_row = at<int>(op, op->L.tile_row);
-  tl.cross = at<int>(op, op->L.cross);
-  tl.head = at<double>(op, op->L.head);
-  tl.tail = at<double>(op, op->L.tail);
-  hipLaunchKernelGGL(k_tile_rows, dim3(grid_for(nt + 1, 1024)), dim3(BS), 0, s, op->xt_rowptr, nlong, nnz_long, nt,
-                     CAP, at<int>(op, op->L.tile_row));
-  hipLaunchKernelGGL(k_cross, dim3(grid_for(nt, 1024)), dim3(BS), 0, s, op->xt_rowptr, nnz_long, nt, CAP,
-                     tl.tile_row, at<int>(op, op->L.cross));
-  hipLaunchKernelGGL(k_fill_d, dim3(grid_for(nt, 1024)), dim3(BS), 0, s, tl.head, (long long)nt, 0.0);
-  hipLaunchKernelGGL(k_fill_d, dim3(grid_for(nt, 1024)), dim3(BS), 0, s, tl.tail, (long long)nt, 0.0);
-  pl.gridA = std::min(nt, GRID_TILES);
-  pl.gridB = (int)std::max<long long>(1, std::min<long long>(ceil_div(nt, BS), 256));
-}
-
-// Length bins of the rows [nlong, d) of X^T (lengths decreasing).
-void make_xt_bins(fsda_op* op) {
-  XtPlan& pl = op->pxt;
-  Rows& R = pl.rows;
-  std::memset(&R, 0, sizeof(R));
+  Rows& R = w.rows;
   R.rowptr = op->xt_rowptr;
   R.col = op->xt_col;
-  // xt_bins: counts of rows with length >= 1024, 256, 64, 16, 1; then d
-  const int lprs[5] = {64, 16, 4, 1, 0};
+  // xt_bins: counts of rows with length >= 1024, 512, 256, 64, 16, 4, 1; then d.
+  // lanes per row so that one pass of XUNR nonzeros per lane covers the bin
+  // (two passes for [512, 1024))
+  const int lprs[7] = {64, 64, 32, 8, 2, 1, 0};
   int nb = 0, item = 0;
-  for (int k = 0; k < 5; k++) {
+  for (int k = 0; k < 7; k++) {
     const int r0 = op->xt_bins[k], r1 = op->xt_bins[k + 1];
     if (r1 <= r0) continue;
     R.row0[nb] = r0;
@@ -468,7 +472,9 @@ void make_xt_bins(fsda_op* op) {
     R.lpr[0] = 0;
     R.item0[0] = R.item0[1] = 0;
   }
-  pl.gridR = std::max(1, std::min(R.item0[R.nb], GRID_ROWS));
+  pl.grid = std::max(1, std::min(w.nchunk + R.item0[R.nb], GRID_ROWS));
+  pl.gridL = grid_for(std::max(nlong, 1), 64);
+  return FSDA_OK;
 }
 
 }  // namespace
@@ -637,21 +643,14 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
     // row-length classes of X^T (lengths are decreasing in the new order)
     int* thr = flag_dev;
     int* cnts = flag_dev + 8;
-    const int th[5] = {LONG_ROW, 256, 64, 16, 1};
+    const int th[7] = {LONG_ROW, 512, 256, 64, 16, 4, 1};
     HIP_TRY(hipMemcpyAsync(thr, th, sizeof(th), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_count_at_least, dim3(1), dim3(64), 0, s, cnt_sorted, d, thr, 5, cnts);
-    HIP_TRY(hipMemcpyAsync(flag_host, cnts, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_count_at_least, dim3(1), dim3(64), 0, s, cnt_sorted, d, thr, 7, cnts);
+    HIP_TRY(hipMemcpyAsync(flag_host, cnts, 7 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    for (int k = 0; k < 5; k++) op->xt_bins[k] = flag_host[k];
-    op->xt_bins[5] = (int)d;
-    int nnz_long = 0;
-    if (op->xt_bins[0] > 0) {
-      HIP_TRY(hipMemcpyAsync(flag_host, op->xt_rowptr + op->xt_bins[0], sizeof(int), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      nnz_long = flag_host[0];
-    }
-    make_tiles(op, op->xt_bins[0], nnz_long, s);
-    make_xt_bins(op);
+    for (int k = 0; k < 7; k++) op->xt_bins[k] = flag_host[k];
+    op->xt_bins[7] = (int)d;
+    if ((rc = make_xt(op, s))) return bail(rc);
   }
 
   // 4. row plans of X (internal and user column order) and of S
@@ -662,7 +661,7 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
   // 5. canonical right-hand side b = X^T y_c (internal order)
   hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(BS), 0, s, reinterpret_cast<int*>(op->st), (long long)(sizeof(State) / 4),
                      0);
-  run_xt(op, op->ycen, EpiXT<false>{op->b, nullptr, 0.0}, 0, s, KC_OTHER);
+  run_xt(op, op->ycen, EpiXT<false>{op->b, nullptr, 0.0}, 0, true, s, KC_OTHER);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   *out = op;
@@ -691,7 +690,7 @@ int fsda_apply(fsda_op* op, double sigma, const double* p, double* q, void* stre
   hipStream_t s = static_cast<hipStream_t>(stream);
   const long long d = op->pb.d;
   hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, p, op->new2old, op->bu, d);
-  apply_internal(op, sigma, op->bu, op->q, 0, s, KC_XT);
+  apply_internal(op, sigma, op->bu, op->q, s);
   hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, op->q, op->old2new, q, d);
   HIP_TRY(hipGetLastError());
   return FSDA_OK;
@@ -746,10 +745,10 @@ int fsda_multishift_solve(fsda_op* op, const double* b, const double* betas, int
     h->active[k] = 1;
   }
   HIP_TRY(hipMemcpyAsync(op->st, h, sizeof(State), hipMemcpyHostToDevice, s));
-  const int gi = grid_for(d, 1024);
+  const int gi = stream_grid(d);
   hipLaunchKernelGGL(k_init, dim3(gi), dim3(BS), 0, s, rhs, op->ring, op->p, op->P, op->L.ldd, W, d, nshift,
-                     op->part + SITE_INIT * NPART);
-  hipLaunchKernelGGL(k_init_done, dim3(1), dim3(BS), 0, s, op->st, op->part + SITE_INIT * NPART, gi);
+                     op->part + SITE_PP * NPART);
+  hipLaunchKernelGGL(k_init_done, dim3(1), dim3(BS), 0, s, op->st, op->part + SITE_PP * NPART, gi);
   HIP_TRY(hipGetLastError());
 
   // one chunk = `chunk` iterations + the fold, replayed as a graph.  A timed
@@ -805,8 +804,8 @@ int fsda_multishift_solve(fsda_op* op, const double* b, const double* betas, int
     double* w = W + (long long)k * d;
     product_x(op, w, 0, s);
     product_lap(op, 0, s);
-    run_xt(op, op->u, EpiRes{rhs, w, betas[k]}, 0, s, KC_OTHER);
-    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, op->part + SITE_XT * NPART, op->pxt.npart(),
+    run_xt(op, op->u, EpiRes{rhs, w, betas[k]}, 0, true, s, KC_OTHER);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, op->part + SITE_XT * NPART, xt_npart(op),
                        &op->st->res2[k]);
     hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, w, op->old2new, op->q, d);
     HIP_TRY(hipMemcpyAsync(w, op->q, sizeof(double) * d, hipMemcpyDeviceToDevice, s));

@@ -22,17 +22,15 @@
 namespace fsda {
 
 constexpr int BS = 256;       // threads per block (4 waves of 64)
-constexpr int TILE = 2048;    // nonzeros per row-complete tile
-constexpr int CAP = 4096;     // values a tile stages (split tiles hold exactly CAP)
-constexpr int IPT = CAP / BS; // nonzeros per thread in a tile
-constexpr int ROWCAP = 2048;  // row pointers a tile stages
 constexpr int MAXS = 64;      // shifts per handle
 constexpr int MAXCHUNK = 64;  // iterations per shift-state fold
 constexpr int NPART = 4096;   // partials per reduction site
 constexpr int MAXBIN = 8;     // row-length bins of a row product
-constexpr int UNR = 4;        // independent loads per thread in streaming loops
+constexpr int UNR = 8;        // independent loads per thread in streaming loops
+constexpr int RUNR = 4;       // nonzeros per lane per pass in k_rows
+constexpr int XUNR = 8;       // nonzeros per lane per pass in the X^T row bins
 
-enum Site { SITE_X = 0, SITE_XT = 1, SITE_R = 2, SITE_INIT = 3, NSITE = 4 };
+enum Site { SITE_X = 0, SITE_XT = 1, SITE_R = 2, SITE_TU = 3, SITE_PP = 4, NSITE = 5 };
 
 // Solver state, resident in device memory.
 struct State {
@@ -156,7 +154,10 @@ __device__ void resid_scalars(State* st, double rrn, double b, double* hist) {
         still = 1;
         if (i + 1 >= st->maxit) st->conv[s] = i + 1;
       }
-    } else {
+    } else {  // identity step: w += 0 * P, P = 0 * r + 1 * P leave a frozen shift unchanged
+      h[0] = 0.0;
+      h[1] = 0.0;
+      h[2] = 1.0;
       h[3] = 0.0;
     }
   }
@@ -195,6 +196,8 @@ struct EpiX {
 // u = M' t = (1-alpha)[r labeled](t_r - c) + alpha (d_r t_r - (S t)_r): the
 // weight of Eq. SDAeig with the centring of Sec. 3.2.3 applied once, in sample
 // space.  c (the labeled mean of t) is the sum of the X product's partials.
+// Reduction <t, u> = p^T X^T M' X p, which with sigma <p, p> gives <p, A p>
+// without a reduction over the X^T product.
 template <bool LAB>
 struct EpiLap {
   const double* t;
@@ -205,7 +208,7 @@ struct EpiLap {
   const double* cpart;
   int ncpart;
   double c;
-  static constexpr bool kReduce = false;
+  static constexpr bool kReduce = true;  // <t, u> = <p, A p> - sigma <p, p>
   __device__ void prepare(const State*) { c = LAB ? sum_partials(cpart, ncpart) : 0.0; }
   __device__ double row(int r, double v) const {
     const double tr = t[r];
@@ -213,7 +216,7 @@ struct EpiLap {
     double x = alpha * (deg * tr - v);
     if (LAB && labw[r] != 0.0) x += (1.0 - alpha) * (tr - c);
     u[r] = x;
-    return 0.0;
+    return tr * x;
   }
 };
 
@@ -252,7 +255,7 @@ struct EpiRes {
 //
 // Rows are grouped in bins of similar length (for X^T the features are
 // relabeled by decreasing frequency, so the bins are contiguous row ranges).
-// In a bin, `lpr` lanes share a row and take UNR nonzeros each per pass: all
+// In a bin, `lpr` lanes share a row and take RUNR nonzeros each per pass: all
 // index loads, then all gathers, are in flight together; the lanes then add up
 // with shuffles.  lpr == 0 marks rows known to be empty.
 
@@ -288,18 +291,18 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const double* __restrict__ 
     double v = 0.0;
     if (live) {
       const int beg = R.rowptr[r], end = R.rowptr[r + 1];
-      for (int k0 = beg + lane; k0 < end; k0 += lpr * UNR) {
-        int idx[UNR];
-        double g[UNR];
+      for (int k0 = beg + lane; k0 < end; k0 += lpr * RUNR) {
+        int idx[RUNR];
+        double g[RUNR];
 #pragma unroll
-        for (int u = 0; u < UNR; u++) {
+        for (int u = 0; u < RUNR; u++) {
           const int k = k0 + u * lpr;
           idx[u] = k < end ? R.col[k] : -1;
         }
 #pragma unroll
-        for (int u = 0; u < UNR; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : 0.0;
+        for (int u = 0; u < RUNR; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : 0.0;
 #pragma unroll
-        for (int u = 0; u < UNR; u++) v += g[u];
+        for (int u = 0; u < RUNR; u++) v += g[u];
       }
     }
     for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -309,243 +312,122 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// sparse products over nonzero tiles (long rows)
+// X^T product: long rows in single-row chunks, the others in length bins
 // ---------------------------------------------------------------------------
 //
-// The nonzeros of rows [0, nrows) are cut into tiles of `tile` entries.  Tile
-// b owns the rows whose first nonzero lies in it.
-//  - row-complete mode: the block stages all of its own rows, even past the
-//    tile end (rows are at most CAP - TILE long), so each row finishes in one
-//    block;
-//  - split mode: the block stages exactly its tile; the partial sum of the row
-//    entering the tile goes to head[b], that of its last row leaving the tile
-//    to tail[b], and k_fixup finishes those rows from the heads of the tiles
-//    they cover.
-// In a tile, each thread takes IPT consecutive nonzeros, finds the row of the
-// first one by binary search over the tile's row pointers (staged in LDS) and
-// walks its values, splitting them at row ends; a block-wide segmented scan
-// hands every thread the partial sum of the row its values continue, and the
-// thread holding a row's last value finishes it.  Work per thread is the same
-// whatever the row lengths.
+// With features relabeled by decreasing frequency, the rows of X^T are sorted
+// by length.  Each long row (the prefix [0, nlong)) is cut into chunks of CH
+// nonzeros; a block sums one chunk (coalesced index loads, independent
+// gathers, block reduction) into lpart[chunk], and the consumer adds up a
+// row's chunk sums in order (k_resid inline, or k_assemble).  The remaining
+// rows go through the same lanes-per-row bins as k_rows, in the same launch.
 
-struct Tiles {
+constexpr int CH = 4096;        // nonzeros of a long-row chunk (16 per thread)
+
+struct XtWork {
   const int* rowptr;
   const int* col;
-  int nrows;
-  long long nnz;
-  const int* tile_row;  // [ntiles+1]
-  const int* cross;     // [ntiles] row leaving tile b, or -1 (split mode)
-  int ntiles;
-  int split;
-  int tile;
-  double* head;
-  double* tail;
+  int nchunk;              // chunks of the long rows, all processed before the bins
+  const int* chunk_row;    // [nchunk] row of each chunk
+  const int* chunk_beg;    // [nchunk] first nonzero of each chunk
+  double* lpart;           // [nchunk] chunk sums
+  Rows rows;               // bins of the other rows
 };
 
-__device__ __forceinline__ void seg_combine(int fa, double va, int& fb, double& vb) {
-  if (!fb) vb += va;
-  fb |= fa;
-}
-
-// Exclusive segmented scan of (flag, value) over the block in thread order.
-__device__ __forceinline__ double block_seg_exscan(int f, double v) {
-  __shared__ double wv[BS / 64];
-  __shared__ int wf[BS / 64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int fi = f;
-  double vi = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const double vo = __shfl_up(vi, o, 64);
-    const int fo = __shfl_up(fi, o, 64);
-    if (lane >= o) seg_combine(fo, vo, fi, vi);
-  }
-  double ve = __shfl_up(vi, 1, 64);
-  int fe = __shfl_up(fi, 1, 64);
-  if (lane == 0) {
-    ve = 0.0;
-    fe = 0;
-  }
-  __syncthreads();
-  if (lane == 63) {
-    wf[w] = fi;
-    wv[w] = vi;
-  }
-  __syncthreads();
-  int fp = 0;
-  double vp = 0.0;
-  for (int k = 0; k < w; k++) {
-    int fk = wf[k];
-    double vk = wv[k];
-    seg_combine(fp, vp, fk, vk);
-    fp = fk;
-    vp = vk;
-  }
-  seg_combine(fp, vp, fe, ve);
-  return ve;
-}
-
-__device__ __forceinline__ int padi(int j) { return j + (j >> 4); }
-
 template <class Epi>
-__global__ __launch_bounds__(BS) void k_tiles(Tiles tl, const double* __restrict__ src, Epi epi, State* st,
-                                              double* part, int slot0, int solve) {
+__global__ __launch_bounds__(BS) void k_xt(XtWork X, const double* __restrict__ src, Epi epi, State* st, double* part,
+                                           int solve) {
   if (solve && st->stop) return;
-  __shared__ double vals[CAP + CAP / 16];
-  __shared__ int rps[ROWCAP + 1];
   epi.prepare(st);
   const int tid = threadIdx.x;
   double acc = 0.0;
-  for (int b = blockIdx.x; b < tl.ntiles; b += gridDim.x) {
-    const long long lo = (long long)b * tl.tile;
-    const long long hi = min(lo + (long long)tl.tile, tl.nnz);
-    const int r0 = tl.tile_row[b], r1 = tl.tile_row[b + 1];
-    const long long rs0 = tl.rowptr[r0];
-    long long beg, end;
-    if (tl.split) {
-      beg = lo;
-      end = hi;
-    } else {
-      beg = rs0;
-      end = tl.rowptr[r1];
+  const int nitems = X.nchunk + X.rows.item0[X.rows.nb];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    if (it < X.nchunk) {
+      const int r = X.chunk_row[it];
+      const int beg = X.chunk_beg[it];
+      const int end = min(beg + CH, X.rowptr[r + 1]);
+      constexpr int U = CH / BS;
+      int idx[U];
+      double g[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int k = beg + u * BS + tid;
+        idx[u] = k < end ? X.col[k] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : 0.0;
+      double v = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; u++) v += g[u];
+      const double t = block_sum_all(v);
+      if (tid == 0) X.lpart[it] = t;
+      continue;
     }
-    const int cnt = (int)(end - beg);
-    const bool head = tl.split && (beg < rs0);
-    const int first = head ? r0 - 1 : r0;
-    const int nr = r1 - first;  // rows touching the tile, empty owned rows included
-    const bool fast = nr + 1 <= ROWCAP;
-    {
-      int idx[IPT];
-      double gv[IPT];
-#pragma unroll
-      for (int it = 0; it < IPT; it++) {
-        const int k = it * BS + tid;
-        idx[it] = (k < cnt) ? tl.col[beg + k] : -1;
-      }
-#pragma unroll
-      for (int it = 0; it < IPT; it++) gv[it] = (idx[it] >= 0) ? src[idx[it]] : 0.0;
-#pragma unroll
-      for (int it = 0; it < IPT; it++) {
-        const int k = it * BS + tid;
-        if (k < cnt) vals[padi(k)] = gv[it];
-      }
+    const Rows& R = X.rows;
+    const int ir = it - X.nchunk;
+    int b = 0;
+    while (ir >= R.item0[b + 1]) b++;
+    const int lpr = R.lpr[b];
+    if (lpr == 0) {
+      const int r = R.row0[b] + (ir - R.item0[b]) * BS + tid;
+      if (r < R.row0[b + 1]) acc += epi.row(r, 0.0);
+      continue;
     }
-    if (fast)
-      for (int i = tid; i <= nr; i += BS) rps[i] = tl.rowptr[first + i];
-    __syncthreads();
-    const int crossing = tl.split ? tl.cross[b] : -1;
-    if (fast) {
-      const int ia = tid * IPT;
-      const int ib = min(ia + IPT, cnt);
-      const bool has = ia < cnt;
-      const int ga = (int)beg + ia;
-      double x[IPT];
+    const int r = R.row0[b] + (ir - R.item0[b]) * (BS / lpr) + tid / lpr;
+    const int lane = tid & (lpr - 1);
+    const bool live = r < R.row0[b + 1];
+    double v = 0.0;
+    if (live) {
+      const int beg = R.rowptr[r], end = R.rowptr[r + 1];
+      for (int k0 = beg + lane; k0 < end; k0 += lpr * XUNR) {
+        int idx[XUNR];
+        double g[XUNR];
 #pragma unroll
-      for (int i = 0; i < IPT; i++) x[i] = (ia + i < cnt) ? vals[padi(ia + i)] : 0.0;
-      int s0 = 0;
-      if (has) {  // largest s with rps[s] <= ga
-        int l = 0, h = nr - 1;
-        while (l < h) {
-          const int m = (l + h + 1) >> 1;
-          if (rps[m] <= ga) l = m; else h = m - 1;
+        for (int u = 0; u < XUNR; u++) {
+          const int k = k0 + u * lpr;
+          idx[u] = k < end ? R.col[k] : -1;
         }
-        s0 = l;
-      }
-      const bool starts_here = has && rps[s0] == ga;
-      int flag = starts_here ? 1 : 0;
-      double run = 0.0;
-      {
-        int s = s0;
 #pragma unroll
-        for (int i = 0; i < IPT; i++) {
-          if (ia + i < ib) {
-            const int g = ga + i;
-            if (g >= rps[s + 1]) {
-              flag = 1;
-              do s++; while (rps[s + 1] <= g);
-              run = 0.0;
-            }
-            run += x[i];
-          }
-        }
-      }
-      const double carry = block_seg_exscan(has ? flag : 0, has ? run : 0.0);
-      if (has) {
-        int s = s0;
-        double v = starts_here ? 0.0 : carry;
-        auto finish = [&](int sr, double tot) {
-          const int r = first + sr;
-          if (head && sr == 0)
-            tl.head[b] = tot;
-          else if (r == crossing)
-            tl.tail[b] = tot;
-          else
-            acc += epi.row(r, tot);
-        };
+        for (int u = 0; u < XUNR; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : 0.0;
 #pragma unroll
-        for (int i = 0; i < IPT; i++) {
-          if (ia + i < ib) {
-            const int g = ga + i;
-            if (g >= rps[s + 1]) {
-              finish(s, v);
-              do s++; while (rps[s + 1] <= g);
-              v = 0.0;
-            }
-            v += x[i];
-          }
-        }
-        if (rps[s + 1] <= ga + (ib - ia) || ib == cnt) finish(s, v);
-      }
-      for (int i = (head ? 1 : 0) + tid; i < nr; i += BS)
-        if (rps[i] == rps[i + 1]) acc += epi.row(first + i, 0.0);
-    } else {
-      for (int i = tid; i < nr; i += BS) {
-        const int r = first + i;
-        const long long sb = max((long long)tl.rowptr[r], beg);
-        const long long se = min((long long)tl.rowptr[r + 1], end);
-        double v0 = 0.0, v1 = 0.0;
-        long long k = sb;
-        for (; k + 1 < se; k += 2) {
-          v0 += vals[padi((int)(k - beg))];
-          v1 += vals[padi((int)(k + 1 - beg))];
-        }
-        if (k < se) v0 += vals[padi((int)(k - beg))];
-        const double v = v0 + v1;
-        if (head && i == 0)
-          tl.head[b] = v;
-        else if (r == crossing)
-          tl.tail[b] = v;
-        else
-          acc += epi.row(r, v);
+        for (int u = 0; u < XUNR; u++) v += g[u];
       }
     }
-    if (tl.split && !head && tid == 0) tl.head[b] = 0.0;
-    __syncthreads();
+    for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (live && lane == 0) acc += epi.row(r, v);
   }
-  if (Epi::kReduce) write_partial(part, slot0 + blockIdx.x, acc);
+  if (Epi::kReduce) write_partial(part, blockIdx.x, acc);
 }
 
+// Long rows [0, nlong) of an X^T product: row j is the ordered sum of its chunk
+// sums lpart[row_chunk0[j] .. row_chunk0[j+1]).  Partial in slot `slot`.
 template <class Epi>
-__global__ __launch_bounds__(BS) void k_fixup(Tiles tl, Epi epi, State* st, double* part, int slot0, int solve) {
-  if (solve && st->stop) return;
+__global__ __launch_bounds__(BS) void k_assemble(int nlong, const int* row_chunk0, const double* lpart, Epi epi,
+                                                 State* st, double* part, int slot) {
   epi.prepare(st);
   double acc = 0.0;
-  for (int b = blockIdx.x * BS + threadIdx.x; b < tl.ntiles; b += gridDim.x * BS) {
-    const int r = tl.cross[b];
-    if (r < 0) continue;
-    const long long e = tl.rowptr[r + 1];
-    double v = tl.tail[b];
-    for (long long bb = b + 1; bb * tl.tile < e; bb++) v += tl.head[bb];
-    acc += epi.row(r, v);
+  for (int j = blockIdx.x * BS + threadIdx.x; j < nlong; j += gridDim.x * BS) {
+    const int c0 = row_chunk0[j], c1 = row_chunk0[j + 1];
+    double v = 0.0;
+    for (int k = c0; k < c1; k += 8) {
+      double x[8];
+#pragma unroll
+      for (int e = 0; e < 8; e++) x[e] = k + e < c1 ? lpart[k + e] : 0.0;
+#pragma unroll
+      for (int e = 0; e < 8; e++) v += x[e];
+    }
+    acc += epi.row(j, v);
   }
-  if (Epi::kReduce) write_partial(part, slot0 + blockIdx.x, acc);
+  if (Epi::kReduce) write_partial(part, slot + blockIdx.x, acc);
 }
 
 // ---------------------------------------------------------------------------
 // streaming kernels of the recurrence
 // ---------------------------------------------------------------------------
 
-// r_0 = b (ring slot 0), p_0 = b, P_s = b, W_s = 0; partials of <b, b>.
+// r_0 = b (ring slot 0), p_0 = b, P_s = b, W_s = 0; partials of <b, b> (also
+// the first <p, p>).  Launched with the grid of k_pupdate.
 __global__ __launch_bounds__(BS) void k_init(const double* __restrict__ b, double* ring, double* p, double* P,
                                              long long ldp, double* W, long long d, int nshift, double* part) {
   double acc = 0.0;
@@ -579,29 +461,52 @@ __global__ __launch_bounds__(BS) void k_init_done(State* st, const double* part,
   }
 }
 
-// K4: a_i = <r,r>/<p,q> from the X^T product's partials; r_{i+1} = r_i - a_i q
-// into the next ring slot; partials of <r_{i+1}, r_{i+1}>.  The last block
-// advances zeta (or flags a breakdown).
-__global__ __launch_bounds__(BS) void k_resid(State* st, const double* __restrict__ q, double* ring, long long ldd,
-                                              long long d, const double* pq_part, int npq, double* part) {
+// K4: <p, q> = <t, u> + sigma0 <p, p> from the partials of the graph product
+// and of the previous direction update; a_i = <r,r>/<p,q>; r_{i+1} = r_i - a_i q
+// into the next ring slot, where q_j of a long row j < nlong is the ordered sum
+// of its chunk sums plus sigma0 p_j; partials of <r_{i+1}, r_{i+1}>.  The last
+// block advances zeta (or flags a breakdown).  The first pass's vector loads
+// are issued before the partial sums, so both latencies overlap.
+__global__ __launch_bounds__(BS) void k_resid(State* st, const double* __restrict__ q, const double* __restrict__ p,
+                                              double* ring, long long ldd, long long d, double sigma0,
+                                              const double* tu_part, int ntu, const double* pp_part, int npp,
+                                              int nlong, const int* __restrict__ row_chunk0,
+                                              const double* __restrict__ lpart, double* part) {
   if (st->stop) return;
-  const double pq = sum_partials(pq_part, npq);
   const int i = st->iter, m = st->chunk;
+  const double* r = ring + (long long)(i % m) * ldd;
+  double* rn = ring + (long long)((i + 1) % m) * ldd;
+  const long long step = (long long)gridDim.x * BS * UNR;
+  long long j0 = (long long)blockIdx.x * BS * UNR + threadIdx.x;
+  double rv[UNR], qv[UNR];
+  auto load = [&]() {
+#pragma unroll
+    for (int u = 0; u < UNR; u++) {
+      const long long j = j0 + (long long)u * BS;
+      rv[u] = j < d ? r[j] : 0.0;
+      if (j < nlong) {  // sum the row's chunk sums in order, 8 loads in flight
+        const int c0 = row_chunk0[j], c1 = row_chunk0[j + 1];
+        double c = 0.0;
+        for (int k = c0; k < c1; k += 8) {
+          double x[8];
+#pragma unroll
+          for (int e = 0; e < 8; e++) x[e] = k + e < c1 ? lpart[k + e] : 0.0;
+#pragma unroll
+          for (int e = 0; e < 8; e++) c += x[e];
+        }
+        qv[u] = c + sigma0 * p[j];
+      } else {
+        qv[u] = j < d ? q[j] : 0.0;
+      }
+    }
+  };
+  load();
+  const double pq = sum_partials(tu_part, ntu) + sigma0 * sum_partials(pp_part, npp);
   const double a = st->rr / pq;
   const bool ok = (pq > 0.0) && isfinite(a);
   double acc = 0.0;
   if (ok) {
-    const double* r = ring + (long long)(i % m) * ldd;
-    double* rn = ring + (long long)((i + 1) % m) * ldd;
-    const long long step = (long long)gridDim.x * BS * UNR;
-    for (long long j0 = (long long)blockIdx.x * BS * UNR + threadIdx.x; j0 < d; j0 += step) {
-      double rv[UNR], qv[UNR];
-#pragma unroll
-      for (int u = 0; u < UNR; u++) {
-        const long long j = j0 + (long long)u * BS;
-        rv[u] = j < d ? r[j] : 0.0;
-        qv[u] = j < d ? q[j] : 0.0;
-      }
+    for (;;) {
 #pragma unroll
       for (int u = 0; u < UNR; u++) {
         const long long j = j0 + (long long)u * BS;
@@ -609,77 +514,83 @@ __global__ __launch_bounds__(BS) void k_resid(State* st, const double* __restric
         if (j < d) rn[j] = x;
         acc += x * x;
       }
+      j0 += step;
+      if (j0 >= d) break;
+      load();
     }
   }
   write_partial(part, blockIdx.x, acc);
-  if (last_block(&st->ticket[SITE_R])) {
+  if (last_block(&st->ticket[0])) {
     if (ok) {
       step_scalars(st, a);
     } else if (threadIdx.x == 0) {
       st->status = FSDA_E_BREAKDOWN;
       st->stop = 1;
     }
-    if (threadIdx.x == 0) st->ticket[SITE_R] = 0;
+    if (threadIdx.x == 0) st->ticket[0] = 0;
   }
 }
 
-// K5: b_{i+1} = <r_{i+1},r_{i+1}>/<r_i,r_i>; p_{i+1} = r_{i+1} + b_{i+1} p_i.  The
-// last block runs the per-shift scalar updates and the stop test.
+// K5: b_{i+1} = <r_{i+1},r_{i+1}>/<r_i,r_i>; p_{i+1} = r_{i+1} + b_{i+1} p_i, with
+// partials of <p_{i+1}, p_{i+1}>.  The last block runs the per-shift scalar
+// updates and the stop test.
 __global__ __launch_bounds__(BS) void k_pupdate(State* st, const double* ring, double* p, long long ldd, long long d,
-                                                const double* rr_part, int nrr, double* hist) {
+                                                const double* rr_part, int nrr, double* hist, double* pp_part) {
   if (st->stop) return;
-  const double rrn = sum_partials(rr_part, nrr);
   const int i = st->iter;
-  const double b = rrn / st->rr;
   const double* r = ring + (long long)((i + 1) % st->chunk) * ldd;
   const long long step = (long long)gridDim.x * BS * UNR;
-  for (long long j0 = (long long)blockIdx.x * BS * UNR + threadIdx.x; j0 < d; j0 += step) {
-    double rv[UNR], pv[UNR];
+  long long j0 = (long long)blockIdx.x * BS * UNR + threadIdx.x;
+  double rv[UNR], pv[UNR];
+#pragma unroll
+  for (int u = 0; u < UNR; u++) {
+    const long long j = j0 + (long long)u * BS;
+    rv[u] = j < d ? r[j] : 0.0;
+    pv[u] = j < d ? p[j] : 0.0;
+  }
+  const double rrn = sum_partials(rr_part, nrr);
+  const double b = rrn / st->rr;
+  double acc = 0.0;
+  for (;;) {
+#pragma unroll
+    for (int u = 0; u < UNR; u++) {
+      const long long j = j0 + (long long)u * BS;
+      const double x = rv[u] + b * pv[u];
+      if (j < d) p[j] = x;
+      acc += j < d ? x * x : 0.0;
+    }
+    j0 += step;
+    if (j0 >= d) break;
 #pragma unroll
     for (int u = 0; u < UNR; u++) {
       const long long j = j0 + (long long)u * BS;
       rv[u] = j < d ? r[j] : 0.0;
       pv[u] = j < d ? p[j] : 0.0;
     }
-#pragma unroll
-    for (int u = 0; u < UNR; u++) {
-      const long long j = j0 + (long long)u * BS;
-      if (j < d) p[j] = rv[u] + b * pv[u];
-    }
   }
-  if (last_block(&st->ticket[SITE_INIT])) {
+  write_partial(pp_part, blockIdx.x, acc);
+  if (last_block(&st->ticket[1])) {
     resid_scalars(st, rrn, b, hist);
-    if (threadIdx.x == 0) st->ticket[SITE_INIT] = 0;
+    if (threadIdx.x == 0) st->ticket[1] = 0;
   }
 }
 
 // Fold of iterations [fold_start, iter): per element, keep the buffered
 // residuals in registers and replay, shift by shift, the recurrences
 //   W_s += a_s P_s ;  P_s = zeta_{k+1,s} r_{k+1} + b_s P_s
-// exactly as a per-iteration pass would, in the same order.  Shifts go in
-// groups of SG so that their W and P loads are in flight together.
+// exactly as a per-iteration pass would, in the same order.  The coefficients
+// are the same for every lane (uniform loads through the scalar cache); a
+// frozen shift carries the identity step (0, 0, 1), and a shift frozen before
+// the chunk is skipped.  Shifts go in groups of SG so that their W and P loads
+// are in flight together.
 constexpr int SG = 4;
 template <int M>
 __global__ __launch_bounds__(BS) void k_fold(const State* st, const double* __restrict__ hist, const double* ring,
                                              long long ldd, double* W, long long d, double* P, long long ldp,
                                              int nshift) {
-  // (a_s, zeta, b_s) and the active flag of every (iteration, shift) of the
-  // chunk, in dynamic LDS sized by the host for chunk * nshift entries
-  extern __shared__ double dyn[];
   const int k0 = st->fold_start, k1 = st->iter, m = st->chunk;
   const int cnt = k1 - k0;
   if (cnt <= 0) return;
-  double* co = dyn;
-  int* act = reinterpret_cast<int*>(dyn + 3 * m * nshift);
-  for (int e = threadIdx.x; e < cnt * nshift; e += BS) {
-    const int k = e / nshift, s = e % nshift;
-    const double* h = hist + ((size_t)((k0 + k) % m) * MAXS + s) * 4;
-    co[e * 3 + 0] = h[0];
-    co[e * 3 + 1] = h[1];
-    co[e * 3 + 2] = h[2];
-    act[e] = h[3] != 0.0;
-  }
-  __syncthreads();
   for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
     double rv[M];
 #pragma unroll
@@ -687,31 +598,30 @@ __global__ __launch_bounds__(BS) void k_fold(const State* st, const double* __re
       if (k < cnt) rv[k] = ring[(long long)((k0 + k + 1) % m) * ldd + j];
     for (int s0 = 0; s0 < nshift; s0 += SG) {
       double w[SG], pp[SG];
+      bool on[SG];
 #pragma unroll
       for (int g = 0; g < SG; g++) {
         const int s = s0 + g;
-        const bool on = s < nshift && act[s];  // inactive at the chunk start -> stays inactive
-        w[g] = on ? W[s * d + j] : 0.0;
-        pp[g] = on ? P[s * ldp + j] : 0.0;
+        on[g] = s < nshift && hist[((size_t)(k0 % m) * MAXS + s) * 4 + 3] != 0.0;
+        w[g] = on[g] ? W[s * d + j] : 0.0;
+        pp[g] = on[g] ? P[s * ldp + j] : 0.0;
       }
 #pragma unroll
       for (int k = 0; k < M; k++) {
         if (k < cnt) {
+          const double* c = hist + (size_t)((k0 + k) % m) * MAXS * 4;
 #pragma unroll
           for (int g = 0; g < SG; g++) {
-            const int s = s0 + g;
-            if (s < nshift && act[k * nshift + s]) {
-              const double* c = co + (k * nshift + s) * 3;
-              w[g] += c[0] * pp[g];
-              pp[g] = c[1] * rv[k] + c[2] * pp[g];
-            }
+            const double* cs = c + (s0 + g) * 4;
+            w[g] += cs[0] * pp[g];
+            pp[g] = cs[1] * rv[k] + cs[2] * pp[g];
           }
         }
       }
 #pragma unroll
       for (int g = 0; g < SG; g++) {
         const int s = s0 + g;
-        if (s < nshift && act[s]) {
+        if (on[g]) {
           W[s * d + j] = w[g];
           P[s * ldp + j] = pp[g];
         }
@@ -825,29 +735,7 @@ __global__ void k_label_vectors(const int* idx, const int8_t* y, long long nl, i
   }
 }
 
-__global__ void k_tile_rows(const int* rowptr, int nrows, long long nnz, int ntiles, int tile, int* tile_row) {
-  FSDA_GRID_LOOP(b, (long long)ntiles + 1) {
-    if (b == ntiles) {
-      tile_row[b] = nrows;
-      continue;
-    }
-    const long long target = b * (long long)tile;
-    int lo = 0, hi = nrows;  // first r in [0, nrows] with rowptr[r] >= target
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if ((long long)rowptr[mid] >= target) hi = mid; else lo = mid + 1;
-    }
-    tile_row[b] = lo;
-  }
-}
 
-__global__ void k_cross(const int* rowptr, long long nnz, int ntiles, int tile, const int* tile_row, int* cross) {
-  FSDA_GRID_LOOP(b, ntiles) {
-    const int r0 = tile_row[b], r1 = tile_row[b + 1];
-    const long long hi = min((b + 1) * (long long)tile, nnz);
-    cross[b] = (r1 > r0 && (long long)rowptr[r1] > hi) ? r1 - 1 : -1;
-  }
-}
 
 __global__ void k_expand_rows(const int* rowptr, long long nrows, int* rowid) {
   FSDA_GRID_LOOP(r, nrows) for (int k = rowptr[r]; k < rowptr[r + 1]; k++) rowid[k] = (int)r;
