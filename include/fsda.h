@@ -56,7 +56,7 @@ extern "C" {
 /* ---- precision ------------------------------------------------------------- */
 #define FSDA_FP64 0  /* every vector and scalar in FP64                              */
 #define FSDA_MIXED 1 /* FP32 vectors and sparse products, FP64 dot products and     */
-                     /* recurrence scalars, then one FP64 refinement step           */
+                     /* recurrence scalars, then FP64 refinement (see the solve)   */
 
 /* Limits of one handle. */
 #define FSDA_MAX_SHIFTS 64
@@ -149,11 +149,21 @@ int fsda_apply(fsda_op *op, double sigma, const double *p, double *q, void *stre
  *              and between host checks for termination (0 = default 32, capped
  *              at max_chunk).  Every chunk gives the same result.
  *  W[nshift][d] device FP64 output, w_s for beta_s.
- *  iters[nshift] host int output: iterations after which shift s stopped.
+ *  iters[nshift] host int output: iterations after which shift s stopped
+ *              (FSDA_MIXED: plus the iterations of its correction solves).
  *  relres[nshift] host FP64 output: true residual ||b - A(beta_s) w_s|| / ||b||
  *              recomputed in FP64 from w_s after the solve.
  * Returns FSDA_OK, FSDA_NOT_CONVERGED (some shift hit maxit; its w_s is the
  * last iterate), FSDA_E_BREAKDOWN, or an argument error.  Blocks until done.
+ *
+ * FSDA_MIXED: the shared recurrence runs with FP32 vectors (FP64 dot products
+ * and scalars) to max(rtol, 1e-5), where FP32 rounding stalls it; then up to
+ * three refinement rounds, each forming R_s = b - A(beta_s) w_s in FP64,
+ * solving A(beta_s) delta_s = R_s for all unconverged shifts at once by
+ * batched FP32 CG (one column per shift; the residuals of different shifts are
+ * not collinear, so they cannot share one shifted basis) to 0.5 rtol ||b||,
+ * and adding delta_s in FP64.  The status is FSDA_OK when every reported
+ * relres[s] <= rtol, else FSDA_NOT_CONVERGED.
  */
 int fsda_multishift_solve(fsda_op *op, const double *b, const double *betas, int nshift, double rtol, int maxit,
                           int chunk, double *W, int *iters, double *relres, void *stream);
@@ -169,7 +179,9 @@ int fsda_project(fsda_op *op, const double *W, int nshift, double *S, void *stre
  * pair of HIP events around every launch of the kernel class `kernel` on the
  * launch stream: 0 = X product, 1 = graph/centring product, 2 = X^T
  * product, 4 = residual update, 5 = direction update, 6 = shift-state fold
- * (3 is unused).  While timing is on, solves launch kernels
+ * (3 is unused); the batched FP32 correction solves of FSDA_MIXED: 7 = X
+ * product, 8 = graph/centring product, 9 = X^T product, 10 = residual and
+ * correction update, 11 = direction update.  While timing is on, solves launch kernels
  * directly instead of replaying a graph.  Launches made after the recurrence
  * stopped (which return at once) are not counted.  fsda_kernel_time() returns
  * (host) the summed milliseconds and launch count of the timed class since

@@ -30,6 +30,8 @@ FP64, MIXED = 0, 1
 MAX_SHIFTS, MAX_CHUNK = 64, 64
 # kernel classes for fsda_time_kernel
 K_X, K_S, K_XT, K_RESID, K_PUPD, K_FOLD = 0, 1, 2, 4, 5, 6
+# ... and of the batched FP32 correction solves of the mixed path
+K_BX, K_BS, K_BXT, K_BRESID, K_BPUPD = 7, 8, 9, 10, 11
 
 
 class FsdaError(RuntimeError):

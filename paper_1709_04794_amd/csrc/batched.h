@@ -1,0 +1,443 @@
+// Batched conjugate gradients: T right-hand sides ("columns") against one SDA
+// operator, column c solving (X^T M' X + sigma_c I) x_c = b_c with its own
+// shift.  The three sparse products are applied to all T columns at once, so
+// every index is read once per iteration for the whole batch.
+//
+// Used for the correction solves of the mixed-precision path: the FP64
+// residuals R_s = b - A(beta_s) w_s of different shifts are not collinear, so
+// they cannot share one shifted Krylov basis and are solved as independent
+// systems (one column per shift), in FP32.
+//
+// Layout: vectors are column-interleaved, element (row j, column c) at
+// j * T + c.  A group of T lanes owns one row: the gather of one nonzero
+// fetches T contiguous FP32 values, and the group shares the index load.
+// Vectors and sparse sums are FP32; dot products and the per-column CG scalars
+// are FP64.  Reductions: every producing block writes one FP64 partial per
+// column; a one-block kernel sums them in a fixed order and updates the
+// per-column scalars, which the next kernels read.  No device-scope fence.
+#pragma once
+
+#include "kernels.h"
+
+namespace fsda {
+
+constexpr int BT_MAX = 64;  // columns of a batch
+constexpr int BU = 8;       // nonzeros in flight per lane
+
+struct BState {
+  int iter, stop, status, maxit;
+  int ncol, pad_[3];
+  double trel;                   // relative stop floor (of ||b_c||)
+  double rr[BT_MAX];             // <r_c, r_c>
+  double a[BT_MAX], b[BT_MAX];   // CG step and direction coefficients of the iteration
+  double tabs[BT_MAX];           // absolute stop target per column
+  double tol[BT_MAX];            // max(tabs, trel ||b_c||)
+  double bnorm[BT_MAX];
+  double sigma[BT_MAX];          // shift of column c
+  double cm[BT_MAX];             // labeled mean of t_c (centring)
+  int active[BT_MAX];
+  int conv[BT_MAX];              // iterations after which column c stopped
+};
+
+// Per-column block sum of acc (thread tid holds column tid % T) into
+// part[blockIdx.x * T + c], summed over the groups in a fixed order.
+template <int T>
+__device__ __forceinline__ void write_partials_cols(double* part, double acc) {
+  __shared__ double sh[BS];
+  constexpr int G = BS / T;
+  const int tid = threadIdx.x;
+  __syncthreads();
+  sh[tid] = acc;
+  __syncthreads();
+  if (tid < T) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < G; k++) t += sh[k * T + tid];
+    part[(size_t)blockIdx.x * T + tid] = t;
+  }
+}
+
+// out[c] (shared memory, c < T) = sum over blocks of part[blk * T + c], in a
+// fixed order.  All threads of the block must call it.
+template <int T>
+__device__ void col_sums(const double* part, int nblk, double* out) {
+  __shared__ double sh[BS];
+  constexpr int G = BS / T;
+  constexpr int U = 8;
+  const int c = threadIdx.x % T, g = threadIdx.x / T;
+  double v = 0.0;
+  for (int b0 = g; b0 < nblk; b0 += G * U) {
+    double x[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) x[u] = b0 + u * G < nblk ? part[(size_t)(b0 + u * G) * T + c] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; u++) v += x[u];
+  }
+  __syncthreads();
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x < T) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < G; k++) t += sh[k * T + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// products over T columns: one group of T lanes per row, lane c = column c
+// ---------------------------------------------------------------------------
+
+// t = X p; with W, partials of sum_r w_r t_rc (w = 1/l on labeled rows).
+template <int T, bool W>
+struct BEpiX {
+  float* t;
+  const double* w;
+  static constexpr bool kReduce = W;
+  __device__ void prepare(const BState*, int) {}
+  __device__ double row(int r, int c, float v) const {
+    t[(size_t)r * T + c] = v;
+    return W ? w[r] * (double)v : 0.0;
+  }
+};
+
+// u = M' t per column (the centring of each column with its own labeled mean
+// cm_c); partials of <t_c, u_c>.
+template <int T, bool LAB>
+struct BEpiLap {
+  const float* t;
+  const double* labw;
+  const int* srowptr;
+  float* u;
+  double alpha;
+  float cm;
+  static constexpr bool kReduce = true;
+  __device__ void prepare(const BState* st, int c) { cm = LAB ? (float)st->cm[c] : 0.f; }
+  __device__ double row(int r, int c, float v) const {
+    const float tr = t[(size_t)r * T + c];
+    const float deg = (float)(srowptr[r + 1] - srowptr[r]);
+    float x = (float)alpha * (deg * tr - v);
+    if (LAB && labw[r] != 0.0) x += (float)(1.0 - alpha) * (tr - cm);
+    u[(size_t)r * T + c] = x;
+    return (double)tr * (double)x;
+  }
+};
+
+// Index registers per lane of a group's cooperative index load: a pass over a
+// row reads T * BM(T) >= 64 consecutive indices with one coalesced load per
+// lane, then broadcasts them inside the group.
+template <int T>
+constexpr int BM() {
+  return T >= 32 ? 2 : 64 / T;
+}
+// Nonzeros of one X^T chunk: one cooperative pass of every group of a block.
+template <int T>
+constexpr int BCHUNK() {
+  return (BS / T) * T * BM<T>();
+}
+constexpr int BMED = 64;  // X^T rows at least this long are cut into chunks in the batched product
+
+// Sum over the nonzeros [beg, end) of a row of src[col[k] * T + c] for the
+// group's column c.  Lane c of the group loads the indices beg + m*T + c; each
+// index then comes from its lane by a shuffle inside the group (all lanes of a
+// group share the trip count, so every source lane is active), and the gathers
+// of a pass are independent of each other.
+template <int T>
+__device__ __forceinline__ float group_gather(const int* __restrict__ col, int beg, int end,
+                                              const float* __restrict__ src, int c) {
+  constexpr int M = BM<T>();
+  float v = 0.f;
+  for (int base = beg; base < end; base += T * M) {
+    int id[M];
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+      const int k = base + m * T + c;
+      id[m] = k < end ? col[k] : -1;
+    }
+#pragma unroll
+    for (int m = 0; m < M; m++) {
+      if (base + m * T >= end) break;  // uniform over the group
+#pragma unroll
+      for (int q = 0; q < T; q++) {
+        const int idx = __shfl(id[m], q, T);
+        v += idx >= 0 ? src[(size_t)idx * T + c] : 0.f;
+      }
+    }
+  }
+  return v;
+}
+
+template <int T, class Epi>
+__global__ __launch_bounds__(BS) void bk_rows(const int* __restrict__ rowptr, const int* __restrict__ col, int nrows,
+                                              const float* __restrict__ src, Epi epi, const BState* st,
+                                              double* part) {
+  if (st->stop) return;
+  constexpr int G = BS / T;
+  const int c = threadIdx.x % T, g = threadIdx.x / T;
+  epi.prepare(st, c);
+  double acc = 0.0;
+  for (int r0 = blockIdx.x * G; r0 < nrows; r0 += gridDim.x * G) {
+    const int r = r0 + g;
+    if (r >= nrows) continue;
+    const float v = group_gather<T>(col, rowptr[r], rowptr[r + 1], src, c);
+    acc += epi.row(r, c, v);
+  }
+  if (Epi::kReduce) write_partials_cols<T>(part, acc);
+}
+
+// X^T product, first level.  Block items: the chunks of BCHUNK<T>() nonzeros
+// of the rows [0, nmed) (each group sums its own slice of T * BM indices; the
+// groups are added in a fixed order into lpart[chunk * T + c]); then the rows
+// [nmed, d), one group per row: Q = X^T u + sigma_c P.
+template <int T>
+__global__ __launch_bounds__(BS) void bk_xt(const int* __restrict__ rowptr, const int* __restrict__ col, int d, int nmed,
+                                            int nchunk, const int* __restrict__ chunk_row,
+                                            const int* __restrict__ chunk_beg, float* lpart,
+                                            const float* __restrict__ u, const float* __restrict__ P, float* Q,
+                                            const BState* st) {
+  if (st->stop) return;
+  constexpr int G = BS / T;
+  constexpr int SL = T * BM<T>();  // nonzeros of a group's slice
+  __shared__ float sh[BS];
+  const int c = threadIdx.x % T, g = threadIdx.x / T;
+  const float sg = (float)st->sigma[c];
+  const int nitems = nchunk + (d - nmed + G - 1) / G;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    if (it < nchunk) {  // uniform over the block
+      const int r = chunk_row[it];
+      const int end = rowptr[r + 1];
+      const int beg = min(chunk_beg[it] + g * SL, end);
+      const float v = group_gather<T>(col, beg, min(beg + SL, end), u, c);
+      __syncthreads();
+      sh[threadIdx.x] = v;
+      __syncthreads();
+      if (threadIdx.x < T) {
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < G; k++) t += sh[k * T + threadIdx.x];
+        lpart[(size_t)it * T + threadIdx.x] = t;
+      }
+      continue;
+    }
+    const int r = nmed + (it - nchunk) * G + g;
+    if (r >= d) continue;
+    const float v = group_gather<T>(col, rowptr[r], rowptr[r + 1], u, c);
+    const size_t e = (size_t)r * T + c;
+    Q[e] = v + sg * P[e];
+  }
+}
+
+// X^T product, second level: row j < nmed is the fixed-order sum of its chunk
+// sums lpart[row_chunk0[j] .. row_chunk0[j+1]) (the groups of a block take
+// every G-th chunk, then add up in order), plus sigma_c P.
+template <int T>
+__global__ __launch_bounds__(BS) void bk_xt_rows(int nmed, const int* __restrict__ row_chunk0,
+                                                 const float* __restrict__ lpart, const float* __restrict__ P,
+                                                 float* Q, const BState* st) {
+  if (st->stop) return;
+  constexpr int G = BS / T;
+  __shared__ float sh[BS];
+  const int c = threadIdx.x % T, g = threadIdx.x / T;
+  const float sg = (float)st->sigma[c];
+  for (int j = blockIdx.x; j < nmed; j += gridDim.x) {
+    const int c0 = row_chunk0[j], c1 = row_chunk0[j + 1];
+    float v = 0.f;
+    for (int k0 = c0 + g; k0 < c1; k0 += G * BU) {
+      float x[BU];
+#pragma unroll
+      for (int e = 0; e < BU; e++) x[e] = k0 + e * G < c1 ? lpart[(size_t)(k0 + e * G) * T + c] : 0.f;
+#pragma unroll
+      for (int e = 0; e < BU; e++) v += x[e];
+    }
+    __syncthreads();
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x < T) {
+      float t = 0.f;
+#pragma unroll
+      for (int k = 0; k < G; k++) t += sh[k * T + threadIdx.x];
+      const size_t e = (size_t)j * T + threadIdx.x;
+      Q[e] = t + sg * P[e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// batched CG recurrences
+// ---------------------------------------------------------------------------
+
+// R = P = B_c (rounded to FP32; zero for c >= ncol), X = 0; partials of <r, r>.
+template <int T>
+__global__ __launch_bounds__(BS) void bk_init(const double* __restrict__ B, long long ldb, int ncol, float* R, float* P,
+                                              float* X, long long d, double* part) {
+  constexpr int G = BS / T;
+  const int c = threadIdx.x % T, g = threadIdx.x / T;
+  double acc = 0.0;
+  for (long long j = (long long)blockIdx.x * G + g; j < d; j += (long long)gridDim.x * G) {
+    const float x = c < ncol ? (float)B[(long long)c * ldb + j] : 0.f;
+    const size_t e = (size_t)j * T + c;
+    R[e] = x;
+    P[e] = x;
+    X[e] = 0.f;
+    acc += (double)x * (double)x;
+  }
+  write_partials_cols<T>(part, acc);
+}
+
+// rr_c, ||b_c||, tol_c; columns with a zero right-hand side, or one already
+// within its target, never start.  One block.
+template <int T>
+__global__ __launch_bounds__(BS) void bk_init_done(BState* st, const double* part, int np) {
+  __shared__ double rr[T];
+  __shared__ int any;
+  col_sums<T>(part, np, rr);
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < T) {
+    const double bn = sqrt(rr[c]);
+    const double tol = fmax(st->tabs[c], st->trel * bn);
+    st->rr[c] = rr[c];
+    st->bnorm[c] = bn;
+    st->tol[c] = tol;
+    st->conv[c] = 0;
+    const int on = c < st->ncol && rr[c] > 0.0 && bn > tol;
+    st->active[c] = on;
+    if (on) atomicOr(&any, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && !any) st->stop = 1;
+}
+
+// out[c] = sum of the partials (one block; the labeled means of the X product).
+template <int T>
+__global__ __launch_bounds__(BS) void bk_colsum(const BState* st, const double* part, int np, double* out) {
+  if (st->stop) return;
+  __shared__ double s[T];
+  col_sums<T>(part, np, s);
+  if (threadIdx.x < T) out[threadIdx.x] = s[threadIdx.x];
+}
+
+// a_c = <r,r>_c / (<t,u>_c + sigma_c <p,p>_c) for the active columns (0 for
+// the others); a breakdown of an active column stops the solve.  One block.
+template <int T>
+__global__ __launch_bounds__(BS) void bk_step_a(BState* st, const double* tu_part, int ntu, const double* pp_part,
+                                                int npp) {
+  if (st->stop) return;
+  __shared__ double tu[T], pp[T];
+  __shared__ int bad;
+  col_sums<T>(tu_part, ntu, tu);
+  col_sums<T>(pp_part, npp, pp);
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < T) {
+    double a = 0.0;
+    if (st->active[c]) {
+      const double pq = tu[c] + st->sigma[c] * pp[c];
+      a = st->rr[c] / pq;
+      if (!(pq > 0.0) || !isfinite(a)) {
+        atomicOr(&bad, 1);
+        a = 0.0;
+      }
+    }
+    st->a[c] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && bad) {
+    st->status = FSDA_E_BREAKDOWN;
+    st->stop = 1;
+  }
+}
+
+// R -= a_c Q, X += a_c P; partials of <r, r>.
+template <int T>
+__global__ __launch_bounds__(BS) void bk_resid(const BState* st, const float* __restrict__ Q, const float* __restrict__ P,
+                                               float* R, float* X, long long d, double* part) {
+  if (st->stop) return;
+  constexpr int G = BS / T;
+  const int c = threadIdx.x % T, g = threadIdx.x / T;
+  const double a = st->a[c];
+  double acc = 0.0;
+  for (long long j = (long long)blockIdx.x * G + g; j < d; j += (long long)gridDim.x * G) {
+    const size_t e = (size_t)j * T + c;
+    const float r = (float)((double)R[e] - a * (double)Q[e]);
+    R[e] = r;
+    X[e] = (float)((double)X[e] + a * (double)P[e]);
+    acc += (double)r * (double)r;
+  }
+  write_partials_cols<T>(part, acc);
+}
+
+// rr' = <r,r>; b_c = rr'/rr_c; per-column stop test ||r_c|| <= tol_c; iteration
+// count; stop when no column is active or at maxit.  One block.
+template <int T>
+__global__ __launch_bounds__(BS) void bk_step_b(BState* st, const double* rr_part, int nrr) {
+  if (st->stop) return;
+  __shared__ double rrn[T];
+  __shared__ int any;
+  col_sums<T>(rr_part, nrr, rrn);
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  const int i = st->iter;
+  const int c = threadIdx.x;
+  if (c < T) {
+    double b = 0.0;
+    if (st->active[c]) {
+      b = rrn[c] / st->rr[c];
+      st->rr[c] = rrn[c];
+      st->conv[c] = i + 1;
+      if (sqrt(rrn[c]) <= st->tol[c])
+        st->active[c] = 0;
+      else
+        atomicOr(&any, 1);
+    }
+    st->b[c] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->iter = i + 1;
+    if (!any) {
+      st->stop = 1;
+    } else if (i + 1 >= st->maxit) {
+      st->stop = 1;
+      st->status = FSDA_NOT_CONVERGED;
+    }
+  }
+}
+
+// P = R + b_c P for the columns still active (the others keep P); partials of <p, p>.
+template <int T>
+__global__ __launch_bounds__(BS) void bk_pupdate(const BState* st, const float* __restrict__ R, float* P, long long d,
+                                                 double* part) {
+  if (st->stop) return;
+  constexpr int G = BS / T;
+  const int c = threadIdx.x % T, g = threadIdx.x / T;
+  const double b = st->b[c];
+  const bool on = st->active[c] != 0;
+  double acc = 0.0;
+  for (long long j = (long long)blockIdx.x * G + g; j < d; j += (long long)gridDim.x * G) {
+    const size_t e = (size_t)j * T + c;
+    float p = P[e];
+    if (on) {
+      p = (float)((double)R[e] + b * (double)p);
+      P[e] = p;
+    }
+    acc += (double)p * (double)p;
+  }
+  write_partials_cols<T>(part, acc);
+}
+
+// W[c * ldw + j] += X[j * T + c] for c < ncol (FP64 accumulation of the FP32 correction).
+template <int T>
+__global__ __launch_bounds__(BS) void bk_add(const float* __restrict__ X, double* W, long long ldw, int ncol,
+                                             long long d) {
+  constexpr int G = BS / T;
+  const int c = threadIdx.x % T, g = threadIdx.x / T;
+  if (c >= ncol) return;
+  for (long long j = (long long)blockIdx.x * G + g; j < d; j += (long long)gridDim.x * G)
+    W[(long long)c * ldw + j] += (double)X[(size_t)j * T + c];
+}
+
+}  // namespace fsda

@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "fsda.h"
+#include "batched.h"
 #include "kernels.h"
 
 using namespace fsda;
@@ -58,6 +59,12 @@ constexpr int GRID_STREAM = 2048;
 constexpr int GRID_FOLD = 2048;
 constexpr int LONG_ROW = 1024;  // X^T rows at least this long are cut into chunks
 constexpr size_t SORT_RESERVE = size_t(32) << 20;
+constexpr int GRID_B = 2048;         // blocks of the batched kernels (partials per column and site)
+constexpr int B_CHUNK = 8;           // batched iterations per host check
+constexpr double MIXED_INNER = 1e-5; // FP32 main solve stops at max(rtol, this)
+constexpr double MIXED_FLOOR = 1e-6; // correction solves stop at most this far below ||R_s||
+constexpr int MIXED_ROUNDS = 3;      // refinement rounds at most
+enum BSite { BP_X = 0, BP_TU = 1, BP_RR = 2, BP_PP = 3, BP_N = 4 };
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
@@ -67,12 +74,17 @@ int pow2_at_least(long long x) {
   while (p < x && p < 64) p <<= 1;
   return p;
 }
+// columns of the batched kernels for ncol right-hand sides: 4, 8, 16, 32 or 64
+int batch_tile(int ncol) { return std::max(4, pow2_at_least(ncol)); }
 
 struct Layout {
   size_t st, part, hist, labw, ycen, zw, t, u, b, p, q, bu, new2old, old2new, xcol, xt_rowptr, xt_col;
   size_t chunk_row, chunk_beg, lpart, row_chunk0;
   size_t uni;
   size_t ring, P;                                                         // union: solve
+  size_t bst, bpart, b64, bR, bP, bQ, bX, bT, bU, blpart, bcrow, bcbeg, brc0;  // union: refinement (mixed)
+  long long bnchunk_max;
+  int btile;
   size_t mark, cnt, iota, cnt_sorted, rowid, keys, sort_tmp, sort_bytes;  // union: build
   size_t total;
   long long ldd;
@@ -111,13 +123,45 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->chunk_beg = take(4 * (size_t)L->nchunk_max);
   L->lpart = take(8 * (size_t)L->nchunk_max);
   L->row_chunk0 = take(4 * ((size_t)L->nlong_max + 1));
+  L->bnchunk_max = z / 512 + z / BMED + 2;
+  L->bcrow = L->bcbeg = L->brc0 = 0;
+  if (pb->precision == FSDA_MIXED) {  // chunk tables of the batched X^T product (kept across solves)
+    L->bcrow = take(4 * (size_t)L->bnchunk_max);
+    L->bcbeg = take(4 * (size_t)L->bnchunk_max);
+    L->brc0 = take(4 * (size_t)(z / BMED + 2));
+  }
   L->uni = o;
   size_t u = o;
   L->ring = u;
   u = a256(u + 8 * (size_t)L->ldd * max_chunk);
   L->P = u;
   u = a256(u + 8 * (size_t)L->ldd * max_shifts);
-  const size_t solve_end = u;
+  size_t solve_end = u;
+  // refinement of the mixed path: batched FP32 CG over one column per shift
+  // (used after the main solve, so it shares the ring and P space)
+  L->btile = batch_tile(max_shifts);
+  L->bst = L->bpart = L->b64 = L->bR = L->bP = L->bQ = L->bX = L->bT = L->bU = L->blpart = 0;
+
+  if (pb->precision == FSDA_MIXED) {
+    const size_t T = (size_t)L->btile;
+    u = o;
+    auto tk = [&](size_t bytes) {
+      const size_t a_ = u;
+      u = a256(u + bytes);
+      return a_;
+    };
+    L->bst = tk(sizeof(BState));
+    L->bpart = tk(sizeof(double) * BP_N * GRID_B * BT_MAX);
+    L->b64 = tk(8 * (size_t)L->ldd * max_shifts);
+    L->bR = tk(4 * (size_t)L->ldd * T);
+    L->bP = tk(4 * (size_t)L->ldd * T);
+    L->bQ = tk(4 * (size_t)L->ldd * T);
+    L->bX = tk(4 * (size_t)L->ldd * T);
+    L->bT = tk(4 * (size_t)n * T);
+    L->bU = tk(4 * (size_t)n * T);
+    L->blpart = tk(4 * (size_t)L->bnchunk_max * T);
+    solve_end = std::max(solve_end, u);
+  }
   u = o;
   L->mark = u;
   u = a256(u + 4 * (size_t)n);
@@ -145,10 +189,11 @@ struct TPair {
 struct GraphKey {
   const double* W;
   const double* rhs;
-  int nshift, chunk;
+  int nshift, chunk, vbytes;
   double sigma0;
   bool operator==(const GraphKey& o) const {
-    return W == o.W && rhs == o.rhs && nshift == o.nshift && chunk == o.chunk && sigma0 == o.sigma0;
+    return W == o.W && rhs == o.rhs && nshift == o.nshift && chunk == o.chunk && vbytes == o.vbytes &&
+           sigma0 == o.sigma0;
   }
 };
 
@@ -196,6 +241,15 @@ struct fsda_op {
   hipGraphExec_t gexec;
   GraphKey gkey;
   int use_graph;
+  // batched refinement solve: one chunk of iterations as a graph, per tile
+  hipGraphExec_t bgexec;
+  int bg_tile;
+  // X^T rows of >= BMED nonzeros: their row pointers (host copy) and the chunk
+  // table of the batched product for tile btab_tile
+  std::vector<int> xt_rp_med;
+  int nmed, btab_tile, bnchunk;
+  BState* bst;
+  BState* hbst;  // pinned host mirror
 };
 
 namespace {
@@ -235,6 +289,11 @@ enum {
   KC_RESID = 4,
   KC_PUPD = 5,
   KC_FOLD = 6,
+  KC_BX = 7,
+  KC_BS = 8,
+  KC_BXT = 9,
+  KC_BRESID = 10,
+  KC_BPUPD = 11,
   KC_OTHER = 99
 };
 
@@ -256,8 +315,8 @@ void launch(fsda_op* op, int cls, hipStream_t s, F f) {
 }
 
 template <class Epi>
-void run_rows(fsda_op* op, const RowPlan& pl, const double* src, Epi epi, double* part, int solve, hipStream_t s,
-              int cls) {
+void run_rows(fsda_op* op, const RowPlan& pl, const typename Epi::V* src, Epi epi, double* part, int solve,
+              hipStream_t s, int cls) {
   launch(op, cls, s, [&] {
     hipLaunchKernelGGL(k_rows<Epi>, dim3(pl.grid), dim3(BS), 0, s, pl.rows, src, epi, op->st, part, 0, solve);
   });
@@ -267,7 +326,7 @@ void run_rows(fsda_op* op, const RowPlan& pl, const double* src, Epi epi, double
 // (partial slots: k_xt [0, grid), k_assemble [grid, grid + gridL)); without,
 // their chunk sums stay in lpart for k_resid.
 template <class Epi>
-void run_xt(fsda_op* op, const double* src, Epi epi, int solve, bool assemble, hipStream_t s, int cls) {
+void run_xt(fsda_op* op, const typename Epi::V* src, Epi epi, int solve, bool assemble, hipStream_t s, int cls) {
   const XtPlan& pl = op->pxt;
   double* part = op->part + SITE_XT * NPART;
   launch(op, cls, s, [&] {
@@ -282,69 +341,86 @@ int xt_npart(const fsda_op* op) { return op->pxt.grid + (op->pxt.nlong > 0 ? op-
 
 bool has_lab_term(const fsda_op* op) { return op->pb.alpha < 1.0; }
 
-// t = X' src (internal feature order).  Partials: sum over labeled rows of t / l.
-void product_x(fsda_op* op, const double* src, int solve, hipStream_t s) {
-  if (has_lab_term(op))
-    run_rows(op, op->px, src, EpiX<true>{op->t, op->labw}, op->part + SITE_X * NPART, solve, s, KC_X);
-  else
-    run_rows(op, op->px, src, EpiX<false>{op->t, nullptr}, op->part + SITE_X * NPART, solve, s, KC_X);
+// The solve's work vectors as V (double, or float on the mixed path; the
+// buffers are sized for double either way).
+template <typename V>
+V* as(double* x) {
+  return reinterpret_cast<V*>(x);
 }
 
+// t = X' src (internal feature order).  Partials: sum over labeled rows of t / l.
+template <typename V>
+void product_x(fsda_op* op, const V* src, int solve, hipStream_t s) {
+  if (has_lab_term(op))
+    run_rows(op, op->px, src, EpiX<V, true>{as<V>(op->t), op->labw}, op->part + SITE_X * NPART, solve, s, KC_X);
+  else
+    run_rows(op, op->px, src, EpiX<V, false>{as<V>(op->t), nullptr}, op->part + SITE_X * NPART, solve, s, KC_X);
+}
+
+template <typename V>
 void product_lap(fsda_op* op, int solve, hipStream_t s) {
   const double a = op->pb.alpha;
+  V* t = as<V>(op->t);
+  V* u = as<V>(op->u);
   if (has_lab_term(op))
-    run_rows(op, op->ps, op->t,
-             EpiLap<true>{op->t, op->labw, op->pb.s_rowptr, op->u, a, op->part + SITE_X * NPART, op->px.grid, 0.0},
+    run_rows(op, op->ps, t,
+             EpiLap<V, true>{t, op->labw, op->pb.s_rowptr, u, a, op->part + SITE_X * NPART, op->px.grid, 0.0},
              op->part + SITE_TU * NPART, solve, s, KC_S);
   else
-    run_rows(op, op->ps, op->t, EpiLap<false>{op->t, nullptr, op->pb.s_rowptr, op->u, a, nullptr, 0, 0.0},
+    run_rows(op, op->ps, t, EpiLap<V, false>{t, nullptr, op->pb.s_rowptr, u, a, nullptr, 0, 0.0},
              op->part + SITE_TU * NPART, solve, s, KC_S);
 }
 
-// q = A(sigma) p in the internal feature order (the operator product of one Krylov step)
+// q = A(sigma) p in the internal feature order, FP64 (the operator product of one Krylov step)
 void apply_internal(fsda_op* op, double sigma, const double* p, double* q, hipStream_t s) {
-  product_x(op, p, 0, s);
-  product_lap(op, 0, s);
-  run_xt(op, op->u, EpiXT<false>{q, p, sigma}, 0, true, s, KC_OTHER);
+  product_x<double>(op, p, 0, s);
+  product_lap<double>(op, 0, s);
+  run_xt(op, op->u, EpiXT<double, false>{q, p, sigma}, 0, true, s, KC_OTHER);
 }
 
 int stream_grid(long long d) { return grid_for(ceil_div(d, UNR), GRID_STREAM); }
 
+template <typename V>
 void iteration(fsda_op* op, double sigma0, hipStream_t s, int tag) {
   op->cur_tag = tag;
-  product_x(op, op->p, 1, s);
-  product_lap(op, 1, s);
-  run_xt(op, op->u, EpiXT<false>{op->q, op->p, sigma0}, 1, false, s, KC_XT);
+  V* p = as<V>(op->p);
+  V* q = as<V>(op->q);
+  V* ring = as<V>(op->ring);
+  product_x<V>(op, p, 1, s);
+  product_lap<V>(op, 1, s);
+  run_xt(op, as<V>(op->u), EpiXT<V, false>{q, p, sigma0}, 1, false, s, KC_XT);
   const long long d = op->pb.d;
   const int gs = stream_grid(d);
   launch(op, KC_RESID, s, [&] {
-    hipLaunchKernelGGL(k_resid, dim3(gs), dim3(BS), 0, s, op->st, op->q, op->p, op->ring, op->L.ldd, d, sigma0,
+    hipLaunchKernelGGL(k_resid<V>, dim3(gs), dim3(BS), 0, s, op->st, q, p, ring, op->L.ldd, d, sigma0,
                        op->part + SITE_TU * NPART, op->ps.grid, op->part + SITE_PP * NPART, gs, op->pxt.nlong,
                        op->pxt.row_chunk0, op->pxt.w.lpart, op->part + SITE_R * NPART);
   });
   launch(op, KC_PUPD, s, [&] {
-    hipLaunchKernelGGL(k_pupdate, dim3(gs), dim3(BS), 0, s, op->st, op->ring, op->p, op->L.ldd, d,
+    hipLaunchKernelGGL(k_pupdate<V>, dim3(gs), dim3(BS), 0, s, op->st, ring, p, op->L.ldd, d,
                        op->part + SITE_R * NPART, gs, op->hist, op->part + SITE_PP * NPART);
   });
   op->cur_tag = -1;
 }
 
+template <typename V>
 void fold(fsda_op* op, double* W, int nshift, int chunk, hipStream_t s) {
   const long long d = op->pb.d;
   const int g = grid_for(d, GRID_FOLD);
-  const size_t shm = 0;
+  V* ring = as<V>(op->ring);
+  V* P = as<V>(op->P);
   launch(op, KC_FOLD, s, [&] {
     if (chunk <= 8)
-      hipLaunchKernelGGL(k_fold<8>, dim3(g), dim3(BS), shm, s, op->st, op->hist, op->ring, op->L.ldd, W, d, op->P,
+      hipLaunchKernelGGL((k_fold<8, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldd, W, d, P,
                          op->L.ldd, nshift);
     else if (chunk <= 16)
-      hipLaunchKernelGGL(k_fold<16>, dim3(g), dim3(BS), shm, s, op->st, op->hist, op->ring, op->L.ldd, W, d, op->P,
+      hipLaunchKernelGGL((k_fold<16, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldd, W, d, P,
                          op->L.ldd, nshift);
     else if (chunk <= 32)
-      hipLaunchKernelGGL(k_fold<32>, dim3(g), dim3(BS), shm, s, op->st, op->hist, op->ring, op->L.ldd, W, d, op->P,
+      hipLaunchKernelGGL((k_fold<32, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldd, W, d, P,
                          op->L.ldd, nshift);
     else
-      hipLaunchKernelGGL(k_fold<64>, dim3(g), dim3(BS), shm, s, op->st, op->hist, op->ring, op->L.ldd, W, d, op->P,
+      hipLaunchKernelGGL((k_fold<64, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldd, W, d, P,
                          op->L.ldd, nshift);
   });
   hipLaunchKernelGGL(k_fold_done, dim3(1), dim3(1), 0, s, op->st);
@@ -353,6 +429,8 @@ void fold(fsda_op* op, double* W, int nshift, int chunk, hipStream_t s) {
 void drop_graph(fsda_op* op) {
   if (op->gexec) (void)hipGraphExecDestroy(op->gexec);
   op->gexec = nullptr;
+  if (op->bgexec) (void)hipGraphExecDestroy(op->bgexec);
+  op->bgexec = nullptr;
 }
 
 int check_problem(const fsda_problem* pb) {
@@ -422,10 +500,15 @@ int make_xt(fsda_op* op, hipStream_t s) {
   const int nlong = op->xt_bins[0];
   pl.nlong = nlong;
   pl.row_chunk0 = at<int>(op, op->L.row_chunk0);
-  if (nlong > 0) {
-    std::vector<int> rp(nlong + 1);
-    HIP_TRY(hipMemcpyAsync(rp.data(), op->xt_rowptr, sizeof(int) * (nlong + 1), hipMemcpyDeviceToHost, s));
+  op->nmed = op->xt_bins[3];  // rows of >= 64 nonzeros
+  op->xt_rp_med.assign(op->nmed + 1, 0);
+  if (op->nmed > 0) {
+    HIP_TRY(hipMemcpyAsync(op->xt_rp_med.data(), op->xt_rowptr, sizeof(int) * (op->nmed + 1), hipMemcpyDeviceToHost,
+                           s));
     HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (nlong > 0) {
+    const std::vector<int>& rp = op->xt_rp_med;
     std::vector<int> crow, cbeg, c0(nlong + 1);
     for (int j = 0; j < nlong; j++) {
       c0[j] = (int)crow.size();
@@ -477,6 +560,310 @@ int make_xt(fsda_op* op, hipStream_t s) {
   return FSDA_OK;
 }
 
+// The multi-shift recurrence in vector type V: initial state, then chunks of
+// `chunk` iterations + one fold, replayed as a HIP graph (a timed solve
+// launches directly: events recorded inside a replayed graph carry no usable
+// timestamps), until every shift stopped.  W (FP64, internal order) receives
+// the iterates.
+template <typename V>
+int run_multishift(fsda_op* op, const double* rhs, const double* betas, double sigma0, int nshift, double rtol,
+                   int maxit, int chunk, double* W, hipStream_t s) {
+  const long long d = op->pb.d;
+  State* h = op->hst;
+  std::memset(h, 0, sizeof(State));
+  h->nshift = nshift;
+  h->maxit = maxit;
+  h->chunk = chunk;
+  h->tol = rtol;  // scaled by ||b|| in k_init_done
+  h->a_prev = 1.0;
+  h->b_cur = 0.0;
+  for (int k = 0; k < nshift; k++) {
+    h->sig[k] = betas[k] - sigma0;
+    h->zp[k] = 1.0;
+    h->z[k] = 1.0;
+    h->active[k] = 1;
+  }
+  HIP_TRY(hipMemcpyAsync(op->st, h, sizeof(State), hipMemcpyHostToDevice, s));
+  const int gi = stream_grid(d);
+  hipLaunchKernelGGL(k_init<V>, dim3(gi), dim3(BS), 0, s, rhs, as<V>(op->ring), as<V>(op->p), as<V>(op->P),
+                     op->L.ldd, W, d, nshift, op->part + SITE_PP * NPART);
+  hipLaunchKernelGGL(k_init_done, dim3(1), dim3(BS), 0, s, op->st, op->part + SITE_PP * NPART, gi);
+  HIP_TRY(hipGetLastError());
+
+  bool graph = op->use_graph != 0 && !op->tk_on;
+  if (graph) {
+    const GraphKey key{W, rhs, nshift, chunk, (int)sizeof(V), sigma0};
+    if (!op->gexec || !(op->gkey == key)) {
+      drop_graph(op);
+      hipGraph_t gr = nullptr;
+      HIP_TRY(hipStreamBeginCapture(op->cap, hipStreamCaptureModeThreadLocal));
+      for (int j = 0; j < chunk; j++) iteration<V>(op, sigma0, op->cap, j);
+      fold<V>(op, W, nshift, chunk, op->cap);
+      const hipError_t ce = hipStreamEndCapture(op->cap, &gr);
+      hipError_t ie = hipErrorUnknown;
+      if (ce == hipSuccess) {
+        ie = hipGraphInstantiate(&op->gexec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+      }
+      if (ce != hipSuccess || ie != hipSuccess) {  // fall back to direct launches (the same kernels)
+        op->gexec = nullptr;
+        (void)hipGetLastError();
+        graph = false;
+      } else {
+        op->gkey = key;
+      }
+    }
+  }
+  const size_t off = offsetof(State, iter);
+  const int max_chunks = (int)std::min<long long>((long long)maxit / chunk + 2, 1LL << 30);
+  int done_iters = 0;
+  for (int c = 0; c < max_chunks; c++) {
+    if (graph) {
+      HIP_TRY(hipGraphLaunch(op->gexec, s));
+    } else {
+      for (int j = 0; j < chunk; j++) iteration<V>(op, sigma0, s, j);
+      fold<V>(op, W, nshift, chunk, s);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(h) + off, reinterpret_cast<char*>(op->st) + off, 4 * sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (op->tk_on) {
+      const int trc = tk_flush(op, h->iter - done_iters);
+      if (trc) return trc;
+    }
+    done_iters = h->iter;
+    if (h->stop) break;
+  }
+  return FSDA_OK;
+}
+
+// FP64 true residuals R_k = b - A(beta_k) w_k of every shift (internal order):
+// ||R_k||^2 into st->res2[k], and R_k itself into out + k * ldo when out is not NULL.
+int residuals(fsda_op* op, const double* rhs, const double* betas, int nshift, const double* W, hipStream_t s,
+              double* out = nullptr, long long ldo = 0) {
+  const long long d = op->pb.d;
+  for (int k = 0; k < nshift; k++) {
+    const double* w = W + (long long)k * d;
+    product_x<double>(op, w, 0, s);
+    product_lap<double>(op, 0, s);
+    run_xt(op, op->u, EpiRes{rhs, w, betas[k], out ? out + (long long)k * ldo : nullptr}, 0, true, s, KC_OTHER);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, op->part + SITE_XT * NPART, xt_npart(op),
+                       &op->st->res2[k]);
+  }
+  HIP_TRY(hipGetLastError());
+  return FSDA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched FP32 CG (the correction solves of the mixed path)
+// ---------------------------------------------------------------------------
+
+int grid_b(long long items) { return (int)std::max<long long>(1, std::min<long long>(items, GRID_B)); }
+
+double* bpart(fsda_op* op, int site) { return at<double>(op, op->L.bpart) + (size_t)site * GRID_B * BT_MAX; }
+
+// One iteration over T columns: t = X P, u = M' t, a, Q = X^T u + sigma P,
+// R -= a Q and X += a P, b and the stop tests, P = R + b P.
+template <int T>
+void b_iteration(fsda_op* op, hipStream_t s, int tag) {
+  op->cur_tag = tag;
+  constexpr int G = BS / T;
+  const Layout& L = op->L;
+  const long long n = op->pb.n, d = op->pb.d;
+  float* t = at<float>(op, L.bT);
+  float* u = at<float>(op, L.bU);
+  float* R = at<float>(op, L.bR);
+  float* P = at<float>(op, L.bP);
+  float* Q = at<float>(op, L.bQ);
+  float* X = at<float>(op, L.bX);
+  float* lpart = at<float>(op, L.blpart);
+  BState* st = op->bst;
+  const int gx = grid_b(ceil_div(n, G));
+  const int gs = grid_b(ceil_div(d, G));
+  const bool lab = has_lab_term(op);
+  launch(op, KC_BX, s, [&] {
+    if (lab)
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, true>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol, (int)n, P,
+                         BEpiX<T, true>{t, op->labw}, st, bpart(op, BP_X));
+    else
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, false>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol, (int)n,
+                         P, BEpiX<T, false>{t, nullptr}, st, bpart(op, BP_X));
+  });
+  if (lab) hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, st, bpart(op, BP_X), gx, st->cm);
+  launch(op, KC_BS, s, [&] {
+    if (lab)
+      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, true>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr, op->pb.s_col,
+                         (int)n, t, BEpiLap<T, true>{t, op->labw, op->pb.s_rowptr, u, op->pb.alpha, 0.f}, st,
+                         bpart(op, BP_TU));
+    else
+      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, false>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr, op->pb.s_col,
+                         (int)n, t, BEpiLap<T, false>{t, nullptr, op->pb.s_rowptr, u, op->pb.alpha, 0.f}, st,
+                         bpart(op, BP_TU));
+  });
+  hipLaunchKernelGGL(bk_step_a<T>, dim3(1), dim3(BS), 0, s, st, bpart(op, BP_TU), gx, bpart(op, BP_PP), gs);
+  const int gxt = grid_b(op->bnchunk + ceil_div(d - op->nmed, G));
+  launch(op, KC_BXT, s, [&] {
+    hipLaunchKernelGGL(bk_xt<T>, dim3(gxt), dim3(BS), 0, s, op->xt_rowptr, op->xt_col, (int)d, op->nmed, op->bnchunk,
+                       at<int>(op, L.bcrow), at<int>(op, L.bcbeg), lpart, u, P, Q, st);
+    if (op->nmed > 0)
+      hipLaunchKernelGGL(bk_xt_rows<T>, dim3(grid_b(op->nmed)), dim3(BS), 0, s, op->nmed, at<int>(op, L.brc0), lpart,
+                         P, Q, st);
+  });
+  launch(op, KC_BRESID, s, [&] {
+    hipLaunchKernelGGL(bk_resid<T>, dim3(gs), dim3(BS), 0, s, st, Q, P, R, X, d, bpart(op, BP_RR));
+  });
+  hipLaunchKernelGGL(bk_step_b<T>, dim3(1), dim3(BS), 0, s, st, bpart(op, BP_RR), gs);
+  launch(op, KC_BPUPD, s, [&] {
+    hipLaunchKernelGGL(bk_pupdate<T>, dim3(gs), dim3(BS), 0, s, st, R, P, d, bpart(op, BP_PP));
+  });
+  op->cur_tag = -1;
+}
+
+// Batched CG over the columns B[c * ldb ..] (FP64, internal order), c < ncol,
+// with the per-column shift, targets and limits already in the host mirror
+// op->hbst.  The solution is left in the FP32 buffer bX ([row][T]); the host
+// mirror receives the final state.
+template <int T>
+int run_batched(fsda_op* op, const double* B, long long ldb, int ncol, hipStream_t s) {
+  constexpr int G = BS / T;
+  const long long d = op->pb.d;
+  if (op->btab_tile != T) {  // chunk table of the rows of >= BMED nonzeros for this tile
+    const int nmed = op->nmed;
+    const std::vector<int>& rp = op->xt_rp_med;
+    std::vector<int> crow, cbeg, c0(nmed + 1);
+    for (int j = 0; j < nmed; j++) {
+      c0[j] = (int)crow.size();
+      for (int k = rp[j]; k < rp[j + 1]; k += BCHUNK<T>()) {
+        crow.push_back(j);
+        cbeg.push_back(k);
+      }
+    }
+    c0[nmed] = (int)crow.size();
+    if ((long long)crow.size() > op->L.bnchunk_max)
+      return fail(FSDA_E_WORKSPACE, "batched chunk table larger than reserved");
+    if (!crow.empty()) {
+      HIP_TRY(hipMemcpyAsync(at<int>(op, op->L.bcrow), crow.data(), sizeof(int) * crow.size(), hipMemcpyHostToDevice,
+                             s));
+      HIP_TRY(hipMemcpyAsync(at<int>(op, op->L.bcbeg), cbeg.data(), sizeof(int) * cbeg.size(), hipMemcpyHostToDevice,
+                             s));
+    }
+    HIP_TRY(hipMemcpyAsync(at<int>(op, op->L.brc0), c0.data(), sizeof(int) * c0.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    op->bnchunk = (int)crow.size();
+    op->btab_tile = T;
+  }
+  BState* h = op->hbst;
+  h->ncol = ncol;
+  h->iter = h->stop = h->status = 0;
+  HIP_TRY(hipMemcpyAsync(op->bst, h, sizeof(BState), hipMemcpyHostToDevice, s));
+  const int gs = grid_b(ceil_div(d, G));
+  hipLaunchKernelGGL(bk_init<T>, dim3(gs), dim3(BS), 0, s, B, ldb, ncol, at<float>(op, op->L.bR),
+                     at<float>(op, op->L.bP), at<float>(op, op->L.bX), d, bpart(op, BP_PP));
+  hipLaunchKernelGGL(bk_init_done<T>, dim3(1), dim3(BS), 0, s, op->bst, bpart(op, BP_PP), gs);
+  HIP_TRY(hipGetLastError());
+  bool graph = op->use_graph != 0 && !op->tk_on;
+  if (graph && (!op->bgexec || op->bg_tile != T)) {
+    if (op->bgexec) (void)hipGraphExecDestroy(op->bgexec);
+    op->bgexec = nullptr;
+    hipGraph_t gr = nullptr;
+    HIP_TRY(hipStreamBeginCapture(op->cap, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < B_CHUNK; j++) b_iteration<T>(op, op->cap, j);
+    const hipError_t ce = hipStreamEndCapture(op->cap, &gr);
+    hipError_t ie = hipErrorUnknown;
+    if (ce == hipSuccess) {
+      ie = hipGraphInstantiate(&op->bgexec, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+    }
+    if (ce != hipSuccess || ie != hipSuccess) {  // direct launches of the same kernels
+      op->bgexec = nullptr;
+      (void)hipGetLastError();
+      graph = false;
+    } else {
+      op->bg_tile = T;
+    }
+  }
+  const size_t off = offsetof(BState, iter);
+  const int max_chunks = (int)std::min<long long>((long long)h->maxit / B_CHUNK + 2, 1LL << 30);
+  int done_iters = 0;
+  for (int c = 0; c < max_chunks; c++) {
+    if (graph) {
+      HIP_TRY(hipGraphLaunch(op->bgexec, s));
+    } else {
+      for (int j = 0; j < B_CHUNK; j++) b_iteration<T>(op, s, j);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(h) + off, reinterpret_cast<char*>(op->bst) + off,
+                           4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (op->tk_on) {
+      const int trc = tk_flush(op, h->iter - done_iters);
+      if (trc) return trc;
+    }
+    done_iters = h->iter;
+    if (h->stop) break;
+  }
+  HIP_TRY(hipMemcpyAsync(h, op->bst, sizeof(BState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return FSDA_OK;
+}
+
+// Refinement of the mixed path, W (internal order) in FP64: up to
+// MIXED_ROUNDS rounds of FP64 residuals R_s = b - A(beta_s) w_s, correction
+// solves A(beta_s) delta_s = R_s by batched FP32 CG (one column per shift,
+// to 0.5 rtol ||b||, never more than MIXED_FLOOR below ||R_s||), and
+// w_s += delta_s in FP64; stops as soon as every shift meets rtol.
+// extra[s] accumulates the correction iterations.
+template <int T>
+int refine(fsda_op* op, const double* rhs, const double* betas, int nshift, double rtol, int maxit, double* W,
+           int* extra, int* status, hipStream_t s) {
+  const long long d = op->pb.d;
+  double* R64 = at<double>(op, op->L.b64);
+  State* h = op->hst;
+  int rc;
+  for (int round = 0; round < MIXED_ROUNDS; round++) {
+    if ((rc = residuals(op, rhs, betas, nshift, W, s, R64, op->L.ldd))) return rc;
+    HIP_TRY(hipMemcpyAsync(h, op->st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double target = rtol * h->bnorm;
+    BState* hb = op->hbst;
+    std::memset(hb, 0, sizeof(BState));
+    bool all = true;
+    for (int k = 0; k < nshift; k++) {
+      const bool ok = std::sqrt(h->res2[k]) <= target;
+      all = all && ok;
+      hb->sigma[k] = betas[k];
+      hb->tabs[k] = ok ? HUGE_VAL : 0.5 * target;  // a shift within rtol does not start
+    }
+    if (all || !(h->bnorm > 0.0)) break;
+    hb->trel = MIXED_FLOOR;
+    hb->maxit = maxit;
+    if ((rc = run_batched<T>(op, R64, op->L.ldd, nshift, s))) return rc;
+    if (hb->status == FSDA_E_BREAKDOWN) {
+      *status = FSDA_E_BREAKDOWN;
+      return FSDA_OK;
+    }
+    if (hb->status == FSDA_NOT_CONVERGED) *status = FSDA_NOT_CONVERGED;
+    for (int k = 0; k < nshift; k++) extra[k] += hb->conv[k];
+    constexpr int G = BS / T;
+    hipLaunchKernelGGL(bk_add<T>, dim3(grid_b(ceil_div(d, G))), dim3(BS), 0, s, at<float>(op, op->L.bX), W, d, nshift,
+                       d);
+    HIP_TRY(hipGetLastError());
+  }
+  return FSDA_OK;
+}
+
+int refine_any(fsda_op* op, const double* rhs, const double* betas, int nshift, double rtol, int maxit, double* W,
+               int* extra, int* status, hipStream_t s) {
+  switch (std::min(batch_tile(nshift), op->L.btile)) {
+    case 4: return refine<4>(op, rhs, betas, nshift, rtol, maxit, W, extra, status, s);
+    case 8: return refine<8>(op, rhs, betas, nshift, rtol, maxit, W, extra, status, s);
+    case 16: return refine<16>(op, rhs, betas, nshift, rtol, maxit, W, extra, status, s);
+    case 32: return refine<32>(op, rhs, betas, nshift, rtol, maxit, W, extra, status, s);
+    default: return refine<64>(op, rhs, betas, nshift, rtol, maxit, W, extra, status, s);
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -505,6 +892,7 @@ void fsda_destroy_operator(fsda_op* op) {
   for (hipEvent_t e : op->pool) (void)hipEventDestroy(e);
   if (op->cap) (void)hipStreamDestroy(op->cap);
   if (op->hst) (void)hipHostFree(op->hst);
+  if (op->hbst) (void)hipHostFree(op->hbst);
   delete op;
 }
 
@@ -547,8 +935,13 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
     op->hst = nullptr;
     return bail(fail(FSDA_E_HIP, "hipHostMalloc of the status mirror failed"));
   }
+  if (hipHostMalloc(reinterpret_cast<void**>(&op->hbst), sizeof(BState), hipHostMallocDefault) != hipSuccess) {
+    op->hbst = nullptr;
+    return bail(fail(FSDA_E_HIP, "hipHostMalloc of the batched status mirror failed"));
+  }
   const Layout& L = op->L;
   op->st = at<State>(op, L.st);
+  op->bst = pb->precision == FSDA_MIXED ? at<BState>(op, L.bst) : nullptr;
   op->part = at<double>(op, L.part);
   op->hist = at<double>(op, L.hist);
   op->labw = at<double>(op, L.labw);
@@ -661,7 +1054,7 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
   // 5. canonical right-hand side b = X^T y_c (internal order)
   hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(BS), 0, s, reinterpret_cast<int*>(op->st), (long long)(sizeof(State) / 4),
                      0);
-  run_xt(op, op->ycen, EpiXT<false>{op->b, nullptr, 0.0}, 0, true, s, KC_OTHER);
+  run_xt(op, op->ycen, EpiXT<double, false>{op->b, nullptr, 0.0}, 0, true, s, KC_OTHER);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   *out = op;
@@ -676,7 +1069,7 @@ int fsda_rhs(fsda_op* op, const double* r, double* b, void* stream) {
     hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, op->b, op->old2new, b, d);
   } else {
     // z^T X r with z = 1+/N+ - 1-/N- (user feature order); b = (z^T X r / 2) X^T y_c
-    run_rows(op, op->px_user, r, EpiX<true>{op->t, op->zw}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
+    run_rows(op, op->px_user, r, EpiX<double, true>{op->t, op->zw}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
     hipLaunchKernelGGL(k_gather_scaled_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, op->b, op->old2new, b, d,
                        op->part + SITE_X * NPART, op->px_user.grid, 0.5);
   }
@@ -701,8 +1094,8 @@ int fsda_project(fsda_op* op, const double* W, int nshift, double* S, void* stre
   if (nshift < 1) return fail(FSDA_E_ARG, "nshift must be >= 1");
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (int k = 0; k < nshift; k++)
-    run_rows(op, op->px_user, W + (long long)k * op->pb.d, EpiX<false>{S + (long long)k * op->pb.n, nullptr},
-             op->part, 0, s, KC_OTHER);
+    run_rows(op, op->px_user, W + (long long)k * op->pb.d,
+             EpiX<double, false>{S + (long long)k * op->pb.n, nullptr}, op->part, 0, s, KC_OTHER);
   HIP_TRY(hipGetLastError());
   return FSDA_OK;
 }
@@ -729,87 +1122,28 @@ int fsda_multishift_solve(fsda_op* op, const double* b, const double* betas, int
     hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, b, op->new2old, op->bu, d);
     rhs = op->bu;
   }
-
-  State* h = op->hst;
-  std::memset(h, 0, sizeof(State));
-  h->nshift = nshift;
-  h->maxit = maxit;
-  h->chunk = chunk;
-  h->tol = rtol;  // scaled by ||b|| in k_init_done
-  h->a_prev = 1.0;
-  h->b_cur = 0.0;
-  for (int k = 0; k < nshift; k++) {
-    h->sig[k] = betas[k] - sigma0;
-    h->zp[k] = 1.0;
-    h->z[k] = 1.0;
-    h->active[k] = 1;
-  }
-  HIP_TRY(hipMemcpyAsync(op->st, h, sizeof(State), hipMemcpyHostToDevice, s));
-  const int gi = stream_grid(d);
-  hipLaunchKernelGGL(k_init, dim3(gi), dim3(BS), 0, s, rhs, op->ring, op->p, op->P, op->L.ldd, W, d, nshift,
-                     op->part + SITE_PP * NPART);
-  hipLaunchKernelGGL(k_init_done, dim3(1), dim3(BS), 0, s, op->st, op->part + SITE_PP * NPART, gi);
-  HIP_TRY(hipGetLastError());
-
-  // one chunk = `chunk` iterations + the fold, replayed as a graph.  A timed
-  // solve launches directly: events recorded inside a replayed graph carry no
-  // usable timestamps.
-  bool graph = op->use_graph != 0 && !op->tk_on;
-  if (graph) {
-    const GraphKey key{W, rhs, nshift, chunk, sigma0};
-    if (!op->gexec || !(op->gkey == key)) {
-      drop_graph(op);
-      hipGraph_t gr = nullptr;
-      HIP_TRY(hipStreamBeginCapture(op->cap, hipStreamCaptureModeThreadLocal));
-      for (int j = 0; j < chunk; j++) iteration(op, sigma0, op->cap, j);
-      fold(op, W, nshift, chunk, op->cap);
-      const hipError_t ce = hipStreamEndCapture(op->cap, &gr);
-      hipError_t ie = hipErrorUnknown;
-      if (ce == hipSuccess) {
-        ie = hipGraphInstantiate(&op->gexec, gr, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(gr);
-      }
-      if (ce != hipSuccess || ie != hipSuccess) {  // fall back to direct launches (the same kernels)
-        op->gexec = nullptr;
-        (void)hipGetLastError();
-        graph = false;
-      } else {
-        op->gkey = key;
-      }
-    }
-  }
-  const size_t off = offsetof(State, iter);
-  const int max_chunks = (int)std::min<long long>((long long)maxit / chunk + 2, 1LL << 30);
-  int done_iters = 0;
-  for (int c = 0; c < max_chunks; c++) {
-    if (graph) {
-      HIP_TRY(hipGraphLaunch(op->gexec, s));
-    } else {
-      for (int j = 0; j < chunk; j++) iteration(op, sigma0, s, j);
-      fold(op, W, nshift, chunk, s);
-    }
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(h) + off, reinterpret_cast<char*>(op->st) + off, 4 * sizeof(int),
-                           hipMemcpyDeviceToHost, s));
+  const bool mixed = op->pb.precision == FSDA_MIXED;
+  std::vector<int> extra(nshift, 0);
+  int rstatus = FSDA_OK;
+  int rc = mixed ? run_multishift<float>(op, rhs, betas, sigma0, nshift, std::max(rtol, MIXED_INNER), maxit, chunk,
+                                         W, s)
+                 : run_multishift<double>(op, rhs, betas, sigma0, nshift, rtol, maxit, chunk, W, s);
+  if (rc) return rc;
+  if (mixed) {
+    HIP_TRY(hipMemcpyAsync(op->hst, op->st, sizeof(State), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (op->tk_on) {
-      const int trc = tk_flush(op, h->iter - done_iters);
-      if (trc) return trc;
-    }
-    done_iters = h->iter;
-    if (h->stop) break;
+    if (op->hst->status != FSDA_E_BREAKDOWN &&
+        (rc = refine_any(op, rhs, betas, nshift, rtol, maxit, W, extra.data(), &rstatus, s)))
+      return rc;
   }
-  // true residuals of every shift in FP64 (internal order), then W back to the user order
+  if ((rc = residuals(op, rhs, betas, nshift, W, s))) return rc;
+  // W back to the caller's feature order
   for (int k = 0; k < nshift; k++) {
     double* w = W + (long long)k * d;
-    product_x(op, w, 0, s);
-    product_lap(op, 0, s);
-    run_xt(op, op->u, EpiRes{rhs, w, betas[k]}, 0, true, s, KC_OTHER);
-    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, op->part + SITE_XT * NPART, xt_npart(op),
-                       &op->st->res2[k]);
     hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, w, op->old2new, op->q, d);
     HIP_TRY(hipMemcpyAsync(w, op->q, sizeof(double) * d, hipMemcpyDeviceToDevice, s));
   }
+  State* h = op->hst;
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(h, op->st, sizeof(State), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -818,10 +1152,16 @@ int fsda_multishift_solve(fsda_op* op, const double* b, const double* betas, int
     if (trc) return trc;
   }
   for (int k = 0; k < nshift; k++) {
-    iters[k] = h->conv[k];
+    iters[k] = h->conv[k] + extra[k];
     relres[k] = h->bnorm > 0.0 ? std::sqrt(h->res2[k]) / h->bnorm : 0.0;
   }
-  if (h->status == FSDA_E_BREAKDOWN) return fail(FSDA_E_BREAKDOWN, "CG breakdown: <p, A p> <= 0 or not finite");
+  if (h->status == FSDA_E_BREAKDOWN || rstatus == FSDA_E_BREAKDOWN)
+    return fail(FSDA_E_BREAKDOWN, "CG breakdown: <p, A p> <= 0 or not finite");
+  if (mixed) {  // the refinement decides: converged when every shift meets rtol
+    bool ok = true;
+    for (int k = 0; k < nshift; k++) ok = ok && relres[k] <= rtol;
+    return ok ? FSDA_OK : FSDA_NOT_CONVERGED;
+  }
   return h->status == FSDA_NOT_CONVERGED ? FSDA_NOT_CONVERGED : FSDA_OK;
 }
 

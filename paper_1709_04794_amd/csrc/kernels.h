@@ -180,16 +180,20 @@ __device__ void resid_scalars(State* st, double rrn, double b, double* hist) {
 // row epilogues of the sparse products
 // ---------------------------------------------------------------------------
 
+// The epilogues are templated on the vector type V (double, or float on the
+// mixed-precision path): row sums and vectors are V, reductions are double.
+
 // t = X p; with W, reduction sum_r w_r t_r (w = 1/l on labeled rows gives their mean).
-template <bool W>
+template <typename T, bool W>
 struct EpiX {
-  double* t;
+  using V = T;
+  V* t;
   const double* w;
   static constexpr bool kReduce = W;
   __device__ void prepare(const State*) {}
-  __device__ double row(int r, double v) const {
+  __device__ double row(int r, V v) const {
     t[r] = v;
-    return W ? w[r] * v : 0.0;
+    return W ? w[r] * (double)v : 0.0;
   }
 };
 
@@ -198,53 +202,59 @@ struct EpiX {
 // space.  c (the labeled mean of t) is the sum of the X product's partials.
 // Reduction <t, u> = p^T X^T M' X p, which with sigma <p, p> gives <p, A p>
 // without a reduction over the X^T product.
-template <bool LAB>
+template <typename T, bool LAB>
 struct EpiLap {
-  const double* t;
+  using V = T;
+  const V* t;
   const double* labw;
   const int* srowptr;
-  double* u;
+  V* u;
   double alpha;
   const double* cpart;
   int ncpart;
   double c;
   static constexpr bool kReduce = true;  // <t, u> = <p, A p> - sigma <p, p>
   __device__ void prepare(const State*) { c = LAB ? sum_partials(cpart, ncpart) : 0.0; }
-  __device__ double row(int r, double v) const {
-    const double tr = t[r];
-    const double deg = (double)(srowptr[r + 1] - srowptr[r]);
-    double x = alpha * (deg * tr - v);
-    if (LAB && labw[r] != 0.0) x += (1.0 - alpha) * (tr - c);
+  __device__ double row(int r, V v) const {
+    const V tr = t[r];
+    const V deg = (V)(srowptr[r + 1] - srowptr[r]);
+    V x = (V)alpha * (deg * tr - v);
+    if (LAB && labw[r] != 0.0) x += (V)(1.0 - alpha) * (tr - (V)c);
     u[r] = x;
-    return tr * x;
+    return (double)tr * (double)x;
   }
 };
 
 // q = X^T u + sigma p; reduction <p, q>.
-template <bool RED>
+template <typename T, bool RED>
 struct EpiXT {
-  double* q;
-  const double* p;
+  using V = T;
+  V* q;
+  const V* p;
   double sigma;
   static constexpr bool kReduce = RED;
   __device__ void prepare(const State*) {}
-  __device__ double row(int r, double v) const {
-    const double pr = p ? p[r] : 0.0;
-    const double qq = v + sigma * pr;
+  __device__ double row(int r, V v) const {
+    const V pr = p ? p[r] : (V)0;
+    const V qq = v + (V)sigma * pr;
     q[r] = qq;
-    return pr * qq;
+    return (double)pr * (double)qq;
   }
 };
 
-// True residual of one shift: R = b - (X^T u + beta w); reduction ||R||^2.
+// True residual of one shift: R = b - (X^T u + beta w), stored when out is
+// not NULL; reduction ||R||^2.
 struct EpiRes {
+  using V = double;
   const double* b;
   const double* w;
   double beta;
+  double* out;
   static constexpr bool kReduce = true;
   __device__ void prepare(const State*) {}
   __device__ double row(int r, double v) const {
     const double R = b[r] - (v + beta * w[r]);
+    if (out) out[r] = R;
     return R * R;
   }
 };
@@ -269,8 +279,9 @@ struct Rows {
 };
 
 template <class Epi>
-__global__ __launch_bounds__(BS) void k_rows(Rows R, const double* __restrict__ src, Epi epi, State* st,
+__global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __restrict__ src, Epi epi, State* st,
                                              double* part, int slot0, int solve) {
+  using V = typename Epi::V;
   if (solve && st->stop) return;
   epi.prepare(st);
   const int tid = threadIdx.x;
@@ -282,25 +293,25 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const double* __restrict__ 
     const int lpr = R.lpr[b];
     if (lpr == 0) {
       const int r = R.row0[b] + (it - R.item0[b]) * BS + tid;
-      if (r < R.row0[b + 1]) acc += epi.row(r, 0.0);
+      if (r < R.row0[b + 1]) acc += epi.row(r, (V)0);
       continue;
     }
     const int r = R.row0[b] + (it - R.item0[b]) * (BS / lpr) + tid / lpr;
     const int lane = tid & (lpr - 1);
     const bool live = r < R.row0[b + 1];
-    double v = 0.0;
+    V v = (V)0;
     if (live) {
       const int beg = R.rowptr[r], end = R.rowptr[r + 1];
       for (int k0 = beg + lane; k0 < end; k0 += lpr * RUNR) {
         int idx[RUNR];
-        double g[RUNR];
+        V g[RUNR];
 #pragma unroll
         for (int u = 0; u < RUNR; u++) {
           const int k = k0 + u * lpr;
           idx[u] = k < end ? R.col[k] : -1;
         }
 #pragma unroll
-        for (int u = 0; u < RUNR; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : 0.0;
+        for (int u = 0; u < RUNR; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : (V)0;
 #pragma unroll
         for (int u = 0; u < RUNR; u++) v += g[u];
       }
@@ -335,8 +346,9 @@ struct XtWork {
 };
 
 template <class Epi>
-__global__ __launch_bounds__(BS) void k_xt(XtWork X, const double* __restrict__ src, Epi epi, State* st, double* part,
-                                           int solve) {
+__global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __restrict__ src, Epi epi, State* st,
+                                           double* part, int solve) {
+  using V = typename Epi::V;
   if (solve && st->stop) return;
   epi.prepare(st);
   const int tid = threadIdx.x;
@@ -349,18 +361,18 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const double* __restrict__ 
       const int end = min(beg + CH, X.rowptr[r + 1]);
       constexpr int U = CH / BS;
       int idx[U];
-      double g[U];
+      V g[U];
 #pragma unroll
       for (int u = 0; u < U; u++) {
         const int k = beg + u * BS + tid;
         idx[u] = k < end ? X.col[k] : -1;
       }
 #pragma unroll
-      for (int u = 0; u < U; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : 0.0;
-      double v = 0.0;
+      for (int u = 0; u < U; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : (V)0;
+      V v = (V)0;
 #pragma unroll
       for (int u = 0; u < U; u++) v += g[u];
-      const double t = block_sum_all(v);
+      const double t = block_sum_all((double)v);
       if (tid == 0) X.lpart[it] = t;
       continue;
     }
@@ -371,25 +383,25 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const double* __restrict__ 
     const int lpr = R.lpr[b];
     if (lpr == 0) {
       const int r = R.row0[b] + (ir - R.item0[b]) * BS + tid;
-      if (r < R.row0[b + 1]) acc += epi.row(r, 0.0);
+      if (r < R.row0[b + 1]) acc += epi.row(r, (V)0);
       continue;
     }
     const int r = R.row0[b] + (ir - R.item0[b]) * (BS / lpr) + tid / lpr;
     const int lane = tid & (lpr - 1);
     const bool live = r < R.row0[b + 1];
-    double v = 0.0;
+    V v = (V)0;
     if (live) {
       const int beg = R.rowptr[r], end = R.rowptr[r + 1];
       for (int k0 = beg + lane; k0 < end; k0 += lpr * XUNR) {
         int idx[XUNR];
-        double g[XUNR];
+        V g[XUNR];
 #pragma unroll
         for (int u = 0; u < XUNR; u++) {
           const int k = k0 + u * lpr;
           idx[u] = k < end ? R.col[k] : -1;
         }
 #pragma unroll
-        for (int u = 0; u < XUNR; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : 0.0;
+        for (int u = 0; u < XUNR; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : (V)0;
 #pragma unroll
         for (int u = 0; u < XUNR; u++) v += g[u];
       }
@@ -417,7 +429,7 @@ __global__ __launch_bounds__(BS) void k_assemble(int nlong, const int* row_chunk
 #pragma unroll
       for (int e = 0; e < 8; e++) v += x[e];
     }
-    acc += epi.row(j, v);
+    acc += epi.row(j, (typename Epi::V)v);
   }
   if (Epi::kReduce) write_partial(part, slot + blockIdx.x, acc);
 }
@@ -428,18 +440,19 @@ __global__ __launch_bounds__(BS) void k_assemble(int nlong, const int* row_chunk
 
 // r_0 = b (ring slot 0), p_0 = b, P_s = b, W_s = 0; partials of <b, b> (also
 // the first <p, p>).  Launched with the grid of k_pupdate.
-__global__ __launch_bounds__(BS) void k_init(const double* __restrict__ b, double* ring, double* p, double* P,
-                                             long long ldp, double* W, long long d, int nshift, double* part) {
+template <typename V>
+__global__ __launch_bounds__(BS) void k_init(const double* __restrict__ b, V* ring, V* p, V* P, long long ldp, double* W,
+                                             long long d, int nshift, double* part) {
   double acc = 0.0;
   for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
-    const double x = b[j];
+    const V x = (V)b[j];
     ring[j] = x;
     p[j] = x;
     for (int s = 0; s < nshift; s++) {
       P[s * ldp + j] = x;
       W[s * d + j] = 0.0;
     }
-    acc += x * x;
+    acc += (double)x * (double)x;
   }
   write_partial(part, blockIdx.x, acc);
 }
@@ -467,15 +480,16 @@ __global__ __launch_bounds__(BS) void k_init_done(State* st, const double* part,
 // of its chunk sums plus sigma0 p_j; partials of <r_{i+1}, r_{i+1}>.  The last
 // block advances zeta (or flags a breakdown).  The first pass's vector loads
 // are issued before the partial sums, so both latencies overlap.
-__global__ __launch_bounds__(BS) void k_resid(State* st, const double* __restrict__ q, const double* __restrict__ p,
-                                              double* ring, long long ldd, long long d, double sigma0,
+template <typename V>
+__global__ __launch_bounds__(BS) void k_resid(State* st, const V* __restrict__ q, const V* __restrict__ p,
+                                              V* ring, long long ldd, long long d, double sigma0,
                                               const double* tu_part, int ntu, const double* pp_part, int npp,
                                               int nlong, const int* __restrict__ row_chunk0,
                                               const double* __restrict__ lpart, double* part) {
   if (st->stop) return;
   const int i = st->iter, m = st->chunk;
-  const double* r = ring + (long long)(i % m) * ldd;
-  double* rn = ring + (long long)((i + 1) % m) * ldd;
+  const V* r = ring + (long long)(i % m) * ldd;
+  V* rn = ring + (long long)((i + 1) % m) * ldd;
   const long long step = (long long)gridDim.x * BS * UNR;
   long long j0 = (long long)blockIdx.x * BS * UNR + threadIdx.x;
   double rv[UNR], qv[UNR];
@@ -483,7 +497,7 @@ __global__ __launch_bounds__(BS) void k_resid(State* st, const double* __restric
 #pragma unroll
     for (int u = 0; u < UNR; u++) {
       const long long j = j0 + (long long)u * BS;
-      rv[u] = j < d ? r[j] : 0.0;
+      rv[u] = j < d ? (double)r[j] : 0.0;
       if (j < nlong) {  // sum the row's chunk sums in order, 8 loads in flight
         const int c0 = row_chunk0[j], c1 = row_chunk0[j + 1];
         double c = 0.0;
@@ -494,9 +508,9 @@ __global__ __launch_bounds__(BS) void k_resid(State* st, const double* __restric
 #pragma unroll
           for (int e = 0; e < 8; e++) c += x[e];
         }
-        qv[u] = c + sigma0 * p[j];
+        qv[u] = (double)(V)c + (double)((V)sigma0 * p[j]);
       } else {
-        qv[u] = j < d ? q[j] : 0.0;
+        qv[u] = j < d ? (double)q[j] : 0.0;
       }
     }
   };
@@ -510,9 +524,9 @@ __global__ __launch_bounds__(BS) void k_resid(State* st, const double* __restric
 #pragma unroll
       for (int u = 0; u < UNR; u++) {
         const long long j = j0 + (long long)u * BS;
-        const double x = rv[u] - a * qv[u];
+        const V x = (V)(rv[u] - a * qv[u]);
         if (j < d) rn[j] = x;
-        acc += x * x;
+        acc += (double)x * (double)x;
       }
       j0 += step;
       if (j0 >= d) break;
@@ -534,11 +548,12 @@ __global__ __launch_bounds__(BS) void k_resid(State* st, const double* __restric
 // K5: b_{i+1} = <r_{i+1},r_{i+1}>/<r_i,r_i>; p_{i+1} = r_{i+1} + b_{i+1} p_i, with
 // partials of <p_{i+1}, p_{i+1}>.  The last block runs the per-shift scalar
 // updates and the stop test.
-__global__ __launch_bounds__(BS) void k_pupdate(State* st, const double* ring, double* p, long long ldd, long long d,
+template <typename V>
+__global__ __launch_bounds__(BS) void k_pupdate(State* st, const V* ring, V* p, long long ldd, long long d,
                                                 const double* rr_part, int nrr, double* hist, double* pp_part) {
   if (st->stop) return;
   const int i = st->iter;
-  const double* r = ring + (long long)((i + 1) % st->chunk) * ldd;
+  const V* r = ring + (long long)((i + 1) % st->chunk) * ldd;
   const long long step = (long long)gridDim.x * BS * UNR;
   long long j0 = (long long)blockIdx.x * BS * UNR + threadIdx.x;
   double rv[UNR], pv[UNR];
@@ -555,17 +570,17 @@ __global__ __launch_bounds__(BS) void k_pupdate(State* st, const double* ring, d
 #pragma unroll
     for (int u = 0; u < UNR; u++) {
       const long long j = j0 + (long long)u * BS;
-      const double x = rv[u] + b * pv[u];
+      const V x = (V)(rv[u] + b * pv[u]);
       if (j < d) p[j] = x;
-      acc += j < d ? x * x : 0.0;
+      acc += j < d ? (double)x * (double)x : 0.0;
     }
     j0 += step;
     if (j0 >= d) break;
 #pragma unroll
     for (int u = 0; u < UNR; u++) {
       const long long j = j0 + (long long)u * BS;
-      rv[u] = j < d ? r[j] : 0.0;
-      pv[u] = j < d ? p[j] : 0.0;
+      rv[u] = j < d ? (double)r[j] : 0.0;
+      pv[u] = j < d ? (double)p[j] : 0.0;
     }
   }
   write_partial(pp_part, blockIdx.x, acc);
@@ -584,9 +599,9 @@ __global__ __launch_bounds__(BS) void k_pupdate(State* st, const double* ring, d
 // the chunk is skipped.  Shifts go in groups of SG so that their W and P loads
 // are in flight together.
 constexpr int SG = 4;
-template <int M>
-__global__ __launch_bounds__(BS) void k_fold(const State* st, const double* __restrict__ hist, const double* ring,
-                                             long long ldd, double* W, long long d, double* P, long long ldp,
+template <int M, typename V>
+__global__ __launch_bounds__(BS) void k_fold(const State* st, const double* __restrict__ hist, const V* ring,
+                                             long long ldd, double* W, long long d, V* P, long long ldp,
                                              int nshift) {
   const int k0 = st->fold_start, k1 = st->iter, m = st->chunk;
   const int cnt = k1 - k0;
@@ -595,7 +610,7 @@ __global__ __launch_bounds__(BS) void k_fold(const State* st, const double* __re
     double rv[M];
 #pragma unroll
     for (int k = 0; k < M; k++)
-      if (k < cnt) rv[k] = ring[(long long)((k0 + k + 1) % m) * ldd + j];
+      if (k < cnt) rv[k] = (double)ring[(long long)((k0 + k + 1) % m) * ldd + j];
     for (int s0 = 0; s0 < nshift; s0 += SG) {
       double w[SG], pp[SG];
       bool on[SG];
@@ -604,7 +619,7 @@ __global__ __launch_bounds__(BS) void k_fold(const State* st, const double* __re
         const int s = s0 + g;
         on[g] = s < nshift && hist[((size_t)(k0 % m) * MAXS + s) * 4 + 3] != 0.0;
         w[g] = on[g] ? W[s * d + j] : 0.0;
-        pp[g] = on[g] ? P[s * ldp + j] : 0.0;
+        pp[g] = on[g] ? (double)P[s * ldp + j] : 0.0;
       }
 #pragma unroll
       for (int k = 0; k < M; k++) {
@@ -614,7 +629,7 @@ __global__ __launch_bounds__(BS) void k_fold(const State* st, const double* __re
           for (int g = 0; g < SG; g++) {
             const double* cs = c + (s0 + g) * 4;
             w[g] += cs[0] * pp[g];
-            pp[g] = cs[1] * rv[k] + cs[2] * pp[g];
+            pp[g] = (double)(V)(cs[1] * rv[k] + cs[2] * pp[g]);  // P_s is stored in V
           }
         }
       }
@@ -623,7 +638,7 @@ __global__ __launch_bounds__(BS) void k_fold(const State* st, const double* __re
         const int s = s0 + g;
         if (on[g]) {
           W[s * d + j] = w[g];
-          P[s * ldp + j] = pp[g];
+          P[s * ldp + j] = (V)pp[g];
         }
       }
     }
