@@ -61,6 +61,7 @@ extern "C" {
 /* Limits of one handle. */
 #define FSDA_MAX_SHIFTS 64
 #define FSDA_MAX_CHUNK 64
+#define FSDA_MAX_TARGETS 64 /* targets of one fsda_multishift_solve_batch call */
 
 typedef struct fsda_op fsda_op; /* opaque handle, host memory */
 
@@ -169,6 +170,38 @@ int fsda_multishift_solve(fsda_op *op, const double *b, const double *betas, int
                           int chunk, double *W, int *iters, double *relres, void *stream);
 
 /*
+ * Many targets at once (the shared-basis solve of Sec. 3.2.2 applied to
+ * several binary labelings of the same samples, e.g. one per assay): target c
+ * has its own labeled set, hence its own centred operator
+ *     A_c(beta) = X^T [ (1-alpha)(P_lc - 1_lc 1_lc^T / l_c) + alpha L ] X + beta I
+ * and right-hand side b_c = X^T y_c (the canonical one of fsda_rhs for that
+ * labeled set), and is solved for every beta of one grid by its own shifted
+ * CG (Alg. 3, seeded at min beta), in FP64.  X, S and alpha are the
+ * handle's; its own labeled set is not used.  The sparse products of all
+ * targets of a call share one pass over the indices.
+ *  ntarget       1..FSDA_MAX_TARGETS.
+ *  lab_idx[], lab_y[] (device) the labeled sets of all targets, concatenated;
+ *                target c owns entries lab_off[c] .. lab_off[c+1]-1 (same
+ *                rules as the handle's labeled set: in range, no repeats,
+ *                labels +1/-1, both classes present).
+ *  lab_off[ntarget+1] host offsets, lab_off[0] = 0.
+ *  betas, nshift, rtol, maxit, chunk: as in fsda_multishift_solve (1 <= nshift
+ *                <= FSDA_MAX_SHIFTS; the handle's max_shifts does not apply).
+ *  workspace     device, 256-byte aligned, ws_bytes >= fsda_batch_workspace_size()
+ *                for the same ntarget, nshift and chunk; scratch for this call only.
+ *  W[ntarget][nshift][d] device FP64 output.
+ *  iters[ntarget * nshift], relres[ntarget * nshift] host outputs, per (target,
+ *                shift), relres the true FP64 residual relative to ||b_c||.
+ * Errors as fsda_multishift_solve; FSDA_E_LABELS names the offending target.
+ * Blocks until done.
+ */
+int fsda_batch_workspace_size(const fsda_op *op, int ntarget, int nshift, int chunk, size_t *bytes);
+int fsda_multishift_solve_batch(fsda_op *op, int ntarget, const int32_t *lab_idx, const int8_t *lab_y,
+                                const int64_t *lab_off, const double *betas, int nshift, double rtol, int maxit,
+                                int chunk, void *workspace, size_t ws_bytes, double *W, int *iters, double *relres,
+                                void *stream);
+
+/*
  * Ratings s = X w for each shift (Alg. 7, return value; uncentred):
  * W[nshift][d] device FP64 in, S[nshift][n] device FP64 out.
  */
@@ -181,7 +214,9 @@ int fsda_project(fsda_op *op, const double *W, int nshift, double *S, void *stre
  * product, 4 = residual update, 5 = direction update, 6 = shift-state fold
  * (3 is unused); the batched FP32 correction solves of FSDA_MIXED: 7 = X
  * product, 8 = graph/centring product, 9 = X^T product, 10 = residual and
- * correction update, 11 = direction update.  While timing is on, solves launch kernels
+ * correction update, 11 = direction update; fsda_multishift_solve_batch: 7-9
+ * its products, 10 = residual update, 11 = direction update, 12 = shift-state
+ * fold.  While timing is on, solves launch kernels
  * directly instead of replaying a graph.  Launches made after the recurrence
  * stopped (which return at once) are not counted.  fsda_kernel_time() returns
  * (host) the summed milliseconds and launch count of the timed class since

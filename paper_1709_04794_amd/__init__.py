@@ -27,11 +27,13 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "fsda.h")
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_CSR, E_LABELS, E_RANGE, E_BREAKDOWN, E_WORKSPACE, E_HIP, E_OVERFLOW = -1, -2, -3, -4, -5, -6, -7, -8
 FP64, MIXED = 0, 1
-MAX_SHIFTS, MAX_CHUNK = 64, 64
+MAX_SHIFTS, MAX_CHUNK, MAX_TARGETS = 64, 64, 64
 # kernel classes for fsda_time_kernel
 K_X, K_S, K_XT, K_RESID, K_PUPD, K_FOLD = 0, 1, 2, 4, 5, 6
 # ... and of the batched FP32 correction solves of the mixed path
 K_BX, K_BS, K_BXT, K_BRESID, K_BPUPD = 7, 8, 9, 10, 11
+# ... and the shift-state fold of fsda_multishift_solve_batch
+K_TFOLD = 12
 
 
 class FsdaError(RuntimeError):
@@ -68,12 +70,15 @@ def lib():
         L.fsda_project.argtypes = [P, P, I, P, P]
         L.fsda_time_kernel.argtypes = [P, I, I]
         L.fsda_kernel_time.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
+        L.fsda_batch_workspace_size.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_size_t)]
+        L.fsda_multishift_solve_batch.argtypes = [P, I, P, P, P, P, I, D, I, I, P, ctypes.c_size_t, P, P, P, P]
         L.fsda_destroy_operator.argtypes = [P]
         L.fsda_destroy_operator.restype = None
         L.fsda_last_error.argtypes = []
         L.fsda_last_error.restype = ctypes.c_char_p
         for f in (L.fsda_workspace_size, L.fsda_build_operator, L.fsda_rhs, L.fsda_apply, L.fsda_multishift_solve,
-                  L.fsda_project, L.fsda_time_kernel, L.fsda_kernel_time):
+                  L.fsda_project, L.fsda_time_kernel, L.fsda_kernel_time, L.fsda_batch_workspace_size,
+                  L.fsda_multishift_solve_batch):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -182,6 +187,43 @@ class Operator:
                                                 iters.ctypes.data_as(ctypes.c_void_p),
                                                 relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
         return W, iters, relres, rc
+
+    def solve_batch(self, labels, betas: Sequence[float], rtol: float, maxit: int = 100000, chunk: int = 0,
+                    stream=None):
+        """Several targets over this operator's X and S (fsda_multishift_solve_batch).
+
+        ``labels`` is a list of (lab_idx, lab_y) pairs (numpy arrays or tensors;
+        int32 indices, +-1 labels), one per target, at most MAX_TARGETS.
+        Returns (W [ntarget, S, d] float64 tensor, iters [ntarget, S] int32,
+        relres [ntarget, S] float64, status).
+        """
+        import torch
+        if not 1 <= len(labels) <= MAX_TARGETS:
+            raise ValueError("between 1 and %d targets per call" % MAX_TARGETS)
+        idx = [torch.as_tensor(np.asarray(i.cpu() if hasattr(i, "cpu") else i), dtype=torch.int32) for i, _ in labels]
+        ys = [torch.as_tensor(np.asarray(y.cpu() if hasattr(y, "cpu") else y), dtype=torch.int8) for _, y in labels]
+        off = np.zeros(len(labels) + 1, dtype=np.int64)
+        off[1:] = np.cumsum([i.numel() for i in idx])
+        lab_idx = torch.cat(idx).to(self.device)
+        lab_y = torch.cat(ys).to(self.device)
+        betas = np.ascontiguousarray(betas, dtype=np.float64)
+        S, K = betas.size, len(labels)
+        size = ctypes.c_size_t(0)
+        _check(lib().fsda_batch_workspace_size(self.handle, K, S, int(chunk), ctypes.byref(size)))
+        need = int(size.value) + 256
+        if getattr(self, "_bws", None) is None or self._bws.numel() < need:
+            self._bws = None
+            self._bws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        ws = (self._bws.data_ptr() + 255) // 256 * 256
+        W = torch.empty((K, S, self.d), dtype=torch.float64, device=self.device)
+        iters = np.zeros(K * S, dtype=np.int32)
+        relres = np.zeros(K * S, dtype=np.float64)
+        rc = _check(lib().fsda_multishift_solve_batch(
+            self.handle, K, _ptr(lab_idx), _ptr(lab_y), off.ctypes.data_as(ctypes.c_void_p),
+            betas.ctypes.data_as(ctypes.c_void_p), S, float(rtol), int(maxit), int(chunk), ctypes.c_void_p(ws),
+            ctypes.c_size_t(int(size.value)), _ptr(W), iters.ctypes.data_as(ctypes.c_void_p),
+            relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return W, iters.reshape(K, S), relres.reshape(K, S), rc
 
     def project(self, W, stream=None):
         import torch

@@ -89,47 +89,55 @@ __device__ void col_sums(const double* part, int nblk, double* out) {
 // products over T columns: one group of T lanes per row, lane c = column c
 // ---------------------------------------------------------------------------
 
-// t = X p; with W, partials of sum_r w_r t_rc (w = 1/l on labeled rows).
-template <int T, bool W>
+// The labeled weights of row r for column c are w[r * ws + c * cs]: one
+// labeled set for every column (ws = 1, cs = 0) or one per column (ws = T,
+// cs = 1, interleaved like the vectors).
+
+// t = X p; with W, partials of sum_r w_rc t_rc (w = 1/l on labeled rows).
+template <int T, typename V, bool W>
 struct BEpiX {
-  float* t;
+  using VT = V;
+  V* t;
   const double* w;
+  int ws, cs;
   static constexpr bool kReduce = W;
-  __device__ void prepare(const BState*, int) {}
-  __device__ double row(int r, int c, float v) const {
+  __device__ void prepare(const double*, int) {}
+  __device__ double row(int r, int c, V v) const {
     t[(size_t)r * T + c] = v;
-    return W ? w[r] * (double)v : 0.0;
+    return W ? w[(size_t)r * ws + c * cs] * (double)v : 0.0;
   }
 };
 
 // u = M' t per column (the centring of each column with its own labeled mean
 // cm_c); partials of <t_c, u_c>.
-template <int T, bool LAB>
+template <int T, typename V, bool LAB>
 struct BEpiLap {
-  const float* t;
+  using VT = V;
+  const V* t;
   const double* labw;
+  int ws, cs;
   const int* srowptr;
-  float* u;
+  V* u;
   double alpha;
-  float cm;
+  V cm;
   static constexpr bool kReduce = true;
-  __device__ void prepare(const BState* st, int c) { cm = LAB ? (float)st->cm[c] : 0.f; }
-  __device__ double row(int r, int c, float v) const {
-    const float tr = t[(size_t)r * T + c];
-    const float deg = (float)(srowptr[r + 1] - srowptr[r]);
-    float x = (float)alpha * (deg * tr - v);
-    if (LAB && labw[r] != 0.0) x += (float)(1.0 - alpha) * (tr - cm);
+  __device__ void prepare(const double* cmv, int c) { cm = LAB ? (V)cmv[c] : (V)0; }
+  __device__ double row(int r, int c, V v) const {
+    const V tr = t[(size_t)r * T + c];
+    const V deg = (V)(srowptr[r + 1] - srowptr[r]);
+    V x = (V)alpha * (deg * tr - v);
+    if (LAB && labw[(size_t)r * ws + c * cs] != 0.0) x += (V)(1.0 - alpha) * (tr - cm);
     u[(size_t)r * T + c] = x;
     return (double)tr * (double)x;
   }
 };
 
 // Index registers per lane of a group's cooperative index load: a pass over a
-// row reads T * BM(T) >= 64 consecutive indices with one coalesced load per
+// row reads T * BM(T) = 64 consecutive indices with one coalesced load per
 // lane, then broadcasts them inside the group.
 template <int T>
 constexpr int BM() {
-  return T >= 32 ? 2 : 64 / T;
+  return T >= 64 ? 1 : 64 / T;
 }
 // Nonzeros of one X^T chunk: one cooperative pass of every group of a block.
 template <int T>
@@ -143,11 +151,11 @@ constexpr int BMED = 64;  // X^T rows at least this long are cut into chunks in 
 // index then comes from its lane by a shuffle inside the group (all lanes of a
 // group share the trip count, so every source lane is active), and the gathers
 // of a pass are independent of each other.
-template <int T>
-__device__ __forceinline__ float group_gather(const int* __restrict__ col, int beg, int end,
-                                              const float* __restrict__ src, int c) {
+template <int T, typename V>
+__device__ __forceinline__ V group_gather(const int* __restrict__ col, int beg, int end, const V* __restrict__ src,
+                                          int c) {
   constexpr int M = BM<T>();
-  float v = 0.f;
+  V v = (V)0;
   for (int base = beg; base < end; base += T * M) {
     int id[M];
 #pragma unroll
@@ -161,26 +169,29 @@ __device__ __forceinline__ float group_gather(const int* __restrict__ col, int b
 #pragma unroll
       for (int q = 0; q < T; q++) {
         const int idx = __shfl(id[m], q, T);
-        v += idx >= 0 ? src[(size_t)idx * T + c] : 0.f;
+        v += idx >= 0 ? src[(size_t)idx * T + c] : (V)0;
       }
     }
   }
   return v;
 }
 
+// Rows of one CSR over T columns; `stop` (the solver's stop flag) ends the
+// launch at once when set, cm holds the per-column labeled means.
 template <int T, class Epi>
 __global__ __launch_bounds__(BS) void bk_rows(const int* __restrict__ rowptr, const int* __restrict__ col, int nrows,
-                                              const float* __restrict__ src, Epi epi, const BState* st,
-                                              double* part) {
-  if (st->stop) return;
+                                              const typename Epi::VT* __restrict__ src, Epi epi, const int* stop,
+                                              const double* cm, double* part) {
+  using V = typename Epi::VT;
+  if (*stop) return;
   constexpr int G = BS / T;
   const int c = threadIdx.x % T, g = threadIdx.x / T;
-  epi.prepare(st, c);
+  epi.prepare(cm, c);
   double acc = 0.0;
   for (int r0 = blockIdx.x * G; r0 < nrows; r0 += gridDim.x * G) {
     const int r = r0 + g;
     if (r >= nrows) continue;
-    const float v = group_gather<T>(col, rowptr[r], rowptr[r + 1], src, c);
+    const V v = group_gather<T, V>(col, rowptr[r], rowptr[r + 1], src, c);
     acc += epi.row(r, c, v);
   }
   if (Epi::kReduce) write_partials_cols<T>(part, acc);
@@ -189,31 +200,48 @@ __global__ __launch_bounds__(BS) void bk_rows(const int* __restrict__ rowptr, co
 // X^T product, first level.  Block items: the chunks of BCHUNK<T>() nonzeros
 // of the rows [0, nmed) (each group sums its own slice of T * BM indices; the
 // groups are added in a fixed order into lpart[chunk * T + c]); then the rows
-// [nmed, d), one group per row: Q = X^T u + sigma_c P.
-template <int T>
-__global__ __launch_bounds__(BS) void bk_xt(const int* __restrict__ rowptr, const int* __restrict__ col, int d, int nmed,
-                                            int nchunk, const int* __restrict__ chunk_row,
-                                            const int* __restrict__ chunk_beg, float* lpart,
-                                            const float* __restrict__ u, const float* __restrict__ P, float* Q,
-                                            const BState* st) {
-  if (st->stop) return;
+// [nmed, d), one group per row: Q = X^T u + sigma_c P (P interleaved, or NULL
+// for Q = X^T u).  Q is interleaved (ldq == 0: Q[r * T + c]) or column-major
+// (Q[c * ldq + r]).
+struct BXtArgs {
+  const int* rowptr;
+  const int* col;
+  int d, nmed, nchunk;
+  const int* chunk_row;
+  const int* chunk_beg;
+  const int* row_chunk0;
+};
+
+__device__ __forceinline__ size_t qidx(int T, long long ldq, long long r, int c) {
+  return ldq ? (size_t)c * ldq + r : (size_t)r * T + c;
+}
+
+template <int T, typename V>
+__global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __restrict__ u, const V* __restrict__ P,
+                                            V* Q, long long ldq, const double* sigma, const int* stop) {
+  if (*stop) return;
+  const int* __restrict__ rowptr = X.rowptr;
+  const int* __restrict__ col = X.col;
+  const int d = X.d, nmed = X.nmed, nchunk = X.nchunk;
+  const int* __restrict__ chunk_row = X.chunk_row;
+  const int* __restrict__ chunk_beg = X.chunk_beg;
   constexpr int G = BS / T;
   constexpr int SL = T * BM<T>();  // nonzeros of a group's slice
-  __shared__ float sh[BS];
+  __shared__ V sh[BS];
   const int c = threadIdx.x % T, g = threadIdx.x / T;
-  const float sg = (float)st->sigma[c];
+  const V sg = P ? (V)sigma[c] : (V)0;
   const int nitems = nchunk + (d - nmed + G - 1) / G;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     if (it < nchunk) {  // uniform over the block
       const int r = chunk_row[it];
       const int end = rowptr[r + 1];
       const int beg = min(chunk_beg[it] + g * SL, end);
-      const float v = group_gather<T>(col, beg, min(beg + SL, end), u, c);
+      const V v = group_gather<T, V>(col, beg, min(beg + SL, end), u, c);
       __syncthreads();
       sh[threadIdx.x] = v;
       __syncthreads();
       if (threadIdx.x < T) {
-        float t = 0.f;
+        V t = (V)0;
 #pragma unroll
         for (int k = 0; k < G; k++) t += sh[k * T + threadIdx.x];
         lpart[(size_t)it * T + threadIdx.x] = t;
@@ -222,31 +250,30 @@ __global__ __launch_bounds__(BS) void bk_xt(const int* __restrict__ rowptr, cons
     }
     const int r = nmed + (it - nchunk) * G + g;
     if (r >= d) continue;
-    const float v = group_gather<T>(col, rowptr[r], rowptr[r + 1], u, c);
-    const size_t e = (size_t)r * T + c;
-    Q[e] = v + sg * P[e];
+    const V v = group_gather<T, V>(col, rowptr[r], rowptr[r + 1], u, c);
+    Q[qidx(T, ldq, r, c)] = P ? v + sg * P[(size_t)r * T + c] : v;
   }
 }
 
 // X^T product, second level: row j < nmed is the fixed-order sum of its chunk
 // sums lpart[row_chunk0[j] .. row_chunk0[j+1]) (the groups of a block take
 // every G-th chunk, then add up in order), plus sigma_c P.
-template <int T>
-__global__ __launch_bounds__(BS) void bk_xt_rows(int nmed, const int* __restrict__ row_chunk0,
-                                                 const float* __restrict__ lpart, const float* __restrict__ P,
-                                                 float* Q, const BState* st) {
-  if (st->stop) return;
+template <int T, typename V>
+__global__ __launch_bounds__(BS) void bk_xt_rows(BXtArgs X, const V* __restrict__ lpart, const V* __restrict__ P, V* Q,
+                                                 long long ldq, const double* sigma, const int* stop) {
+  if (*stop) return;
+  const int nmed = X.nmed;
+  const int* __restrict__ row_chunk0 = X.row_chunk0;
   constexpr int G = BS / T;
-  __shared__ float sh[BS];
+  __shared__ V sh[BS];
   const int c = threadIdx.x % T, g = threadIdx.x / T;
-  const float sg = (float)st->sigma[c];
   for (int j = blockIdx.x; j < nmed; j += gridDim.x) {
     const int c0 = row_chunk0[j], c1 = row_chunk0[j + 1];
-    float v = 0.f;
+    V v = (V)0;
     for (int k0 = c0 + g; k0 < c1; k0 += G * BU) {
-      float x[BU];
+      V x[BU];
 #pragma unroll
-      for (int e = 0; e < BU; e++) x[e] = k0 + e * G < c1 ? lpart[(size_t)(k0 + e * G) * T + c] : 0.f;
+      for (int e = 0; e < BU; e++) x[e] = k0 + e * G < c1 ? lpart[(size_t)(k0 + e * G) * T + c] : (V)0;
 #pragma unroll
       for (int e = 0; e < BU; e++) v += x[e];
     }
@@ -254,11 +281,11 @@ __global__ __launch_bounds__(BS) void bk_xt_rows(int nmed, const int* __restrict
     sh[threadIdx.x] = v;
     __syncthreads();
     if (threadIdx.x < T) {
-      float t = 0.f;
+      const int cc = threadIdx.x;
+      V t = (V)0;
 #pragma unroll
-      for (int k = 0; k < G; k++) t += sh[k * T + threadIdx.x];
-      const size_t e = (size_t)j * T + threadIdx.x;
-      Q[e] = t + sg * P[e];
+      for (int k = 0; k < G; k++) t += sh[k * T + cc];
+      Q[qidx(T, ldq, j, cc)] = P ? t + (V)sigma[cc] * P[(size_t)j * T + cc] : t;
     }
   }
 }
@@ -312,8 +339,8 @@ __global__ __launch_bounds__(BS) void bk_init_done(BState* st, const double* par
 
 // out[c] = sum of the partials (one block; the labeled means of the X product).
 template <int T>
-__global__ __launch_bounds__(BS) void bk_colsum(const BState* st, const double* part, int np, double* out) {
-  if (st->stop) return;
+__global__ __launch_bounds__(BS) void bk_colsum(const int* stop, const double* part, int np, double* out) {
+  if (*stop) return;
   __shared__ double s[T];
   col_sums<T>(part, np, s);
   if (threadIdx.x < T) out[threadIdx.x] = s[threadIdx.x];

@@ -36,6 +36,7 @@
 #include "fsda.h"
 #include "batched.h"
 #include "kernels.h"
+#include "targets.h"
 
 using namespace fsda;
 
@@ -123,7 +124,7 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->chunk_beg = take(4 * (size_t)L->nchunk_max);
   L->lpart = take(8 * (size_t)L->nchunk_max);
   L->row_chunk0 = take(4 * ((size_t)L->nlong_max + 1));
-  L->bnchunk_max = z / 512 + z / BMED + 2;
+  L->bnchunk_max = z / 256 + z / BMED + 2;  // chunks of >= 256 nonzeros, plus one per row
   L->bcrow = L->bcbeg = L->brc0 = 0;
   if (pb->precision == FSDA_MIXED) {  // chunk tables of the batched X^T product (kept across solves)
     L->bcrow = take(4 * (size_t)L->bnchunk_max);
@@ -248,6 +249,12 @@ struct fsda_op {
   // table of the batched product for tile btab_tile
   std::vector<int> xt_rp_med;
   int nmed, btab_tile, bnchunk;
+  // batched targets: one chunk of iterations + fold as a graph, and its key
+  hipGraphExec_t tgexec;
+  const void* tkey_ws;
+  const double* tkey_W;
+  int tkey_T, tkey_ncol, tkey_nshift, tkey_chunk;
+  TState* htst;  // pinned host mirror
   BState* bst;
   BState* hbst;  // pinned host mirror
 };
@@ -294,6 +301,7 @@ enum {
   KC_BXT = 9,
   KC_BRESID = 10,
   KC_BPUPD = 11,
+  KC_TFOLD = 12,
   KC_OTHER = 99
 };
 
@@ -431,6 +439,8 @@ void drop_graph(fsda_op* op) {
   op->gexec = nullptr;
   if (op->bgexec) (void)hipGraphExecDestroy(op->bgexec);
   op->bgexec = nullptr;
+  if (op->tgexec) (void)hipGraphExecDestroy(op->tgexec);
+  op->tgexec = nullptr;
 }
 
 int check_problem(const fsda_problem* pb) {
@@ -682,33 +692,37 @@ void b_iteration(fsda_op* op, hipStream_t s, int tag) {
   const int gx = grid_b(ceil_div(n, G));
   const int gs = grid_b(ceil_div(d, G));
   const bool lab = has_lab_term(op);
+  const int* stop = &st->stop;
   launch(op, KC_BX, s, [&] {
     if (lab)
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, true>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol, (int)n, P,
-                         BEpiX<T, true>{t, op->labw}, st, bpart(op, BP_X));
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, float, true>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol,
+                         (int)n, P, BEpiX<T, float, true>{t, op->labw, 1, 0}, stop, st->cm, bpart(op, BP_X));
     else
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, false>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol, (int)n,
-                         P, BEpiX<T, false>{t, nullptr}, st, bpart(op, BP_X));
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, float, false>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol,
+                         (int)n, P, BEpiX<T, float, false>{t, nullptr, 1, 0}, stop, st->cm, bpart(op, BP_X));
   });
-  if (lab) hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, st, bpart(op, BP_X), gx, st->cm);
+  if (lab) hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, stop, bpart(op, BP_X), gx, st->cm);
   launch(op, KC_BS, s, [&] {
     if (lab)
-      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, true>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr, op->pb.s_col,
-                         (int)n, t, BEpiLap<T, true>{t, op->labw, op->pb.s_rowptr, u, op->pb.alpha, 0.f}, st,
-                         bpart(op, BP_TU));
+      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, float, true>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr,
+                         op->pb.s_col, (int)n, t,
+                         BEpiLap<T, float, true>{t, op->labw, 1, 0, op->pb.s_rowptr, u, op->pb.alpha, 0.f}, stop,
+                         st->cm, bpart(op, BP_TU));
     else
-      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, false>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr, op->pb.s_col,
-                         (int)n, t, BEpiLap<T, false>{t, nullptr, op->pb.s_rowptr, u, op->pb.alpha, 0.f}, st,
-                         bpart(op, BP_TU));
+      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, float, false>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr,
+                         op->pb.s_col, (int)n, t,
+                         BEpiLap<T, float, false>{t, nullptr, 1, 0, op->pb.s_rowptr, u, op->pb.alpha, 0.f}, stop,
+                         st->cm, bpart(op, BP_TU));
   });
   hipLaunchKernelGGL(bk_step_a<T>, dim3(1), dim3(BS), 0, s, st, bpart(op, BP_TU), gx, bpart(op, BP_PP), gs);
+  const BXtArgs xa{op->xt_rowptr, op->xt_col, (int)d, op->nmed, op->bnchunk, at<int>(op, L.bcrow),
+                   at<int>(op, L.bcbeg), at<int>(op, L.brc0)};
   const int gxt = grid_b(op->bnchunk + ceil_div(d - op->nmed, G));
   launch(op, KC_BXT, s, [&] {
-    hipLaunchKernelGGL(bk_xt<T>, dim3(gxt), dim3(BS), 0, s, op->xt_rowptr, op->xt_col, (int)d, op->nmed, op->bnchunk,
-                       at<int>(op, L.bcrow), at<int>(op, L.bcbeg), lpart, u, P, Q, st);
+    hipLaunchKernelGGL((bk_xt<T, float>), dim3(gxt), dim3(BS), 0, s, xa, lpart, u, P, Q, 0LL, st->sigma, stop);
     if (op->nmed > 0)
-      hipLaunchKernelGGL(bk_xt_rows<T>, dim3(grid_b(op->nmed)), dim3(BS), 0, s, op->nmed, at<int>(op, L.brc0), lpart,
-                         P, Q, st);
+      hipLaunchKernelGGL((bk_xt_rows<T, float>), dim3(grid_b(op->nmed)), dim3(BS), 0, s, xa, lpart, P, Q, 0LL,
+                         st->sigma, stop);
   });
   launch(op, KC_BRESID, s, [&] {
     hipLaunchKernelGGL(bk_resid<T>, dim3(gs), dim3(BS), 0, s, st, Q, P, R, X, d, bpart(op, BP_RR));
@@ -864,6 +878,356 @@ int refine_any(fsda_op* op, const double* rhs, const double* betas, int nshift, 
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// batched targets
+// ---------------------------------------------------------------------------
+
+struct TLayout {
+  size_t st, part, hist, flags, labw, B, P, Q, t, u, ring, Ps, lpart, crow, cbeg, rc0, total;
+  long long ld;
+};
+
+void tlayout(const fsda_op* op, int T, int nshift, int chunk, TLayout* L) {
+  const long long n = op->pb.n, z = std::max<long long>(op->pb.x_nnz, 1);
+  const size_t ld = (size_t)op->L.ldd;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t a_ = o;
+    o = a256(o + bytes);
+    return a_;
+  };
+  L->ld = op->L.ldd;
+  L->st = take(sizeof(TState));
+  L->part = take(sizeof(double) * BP_N * GRID_B * BT_MAX);
+  L->hist = take(sizeof(double) * 4 * (size_t)chunk * T * nshift);
+  L->flags = take(sizeof(int) * 4 * BT_MAX);
+  L->labw = take(8 * (size_t)n * T);
+  L->t = take(8 * (size_t)n * T);
+  L->u = take(8 * (size_t)n * T);
+  L->B = take(8 * ld * T);
+  L->P = take(8 * ld * T);
+  L->Q = take(8 * ld * T);
+  L->ring = take(8 * ld * T * chunk);
+  L->Ps = take(8 * ld * T * nshift);
+  L->lpart = take(8 * (size_t)op->L.bnchunk_max * T);
+  L->crow = take(4 * (size_t)op->L.bnchunk_max);
+  L->cbeg = take(4 * (size_t)op->L.bnchunk_max);
+  L->rc0 = take(4 * (size_t)(z / BMED + 2));
+  L->total = o;
+}
+
+struct TPtr {
+  TState* st;
+  double *part, *hist, *labw, *B, *P, *Q, *t, *u, *ring, *Ps, *lpart, *W;
+  int* flags;
+  BXtArgs xa;
+  long long ld;
+  int ncol, nshift, chunk;
+};
+
+double* tpart(const TPtr& p, int site) { return p.part + (size_t)site * GRID_B * BT_MAX; }
+
+// chunk table of the X^T rows of >= BMED nonzeros for tile T (batched product)
+template <int T>
+int t_chunk_table(fsda_op* op, int* crow_d, int* cbeg_d, int* rc0_d, int* nchunk, hipStream_t s) {
+  const int nmed = op->nmed;
+  const std::vector<int>& rp = op->xt_rp_med;
+  std::vector<int> crow, cbeg, c0(nmed + 1);
+  for (int j = 0; j < nmed; j++) {
+    c0[j] = (int)crow.size();
+    for (int k = rp[j]; k < rp[j + 1]; k += BCHUNK<T>()) {
+      crow.push_back(j);
+      cbeg.push_back(k);
+    }
+  }
+  c0[nmed] = (int)crow.size();
+  if ((long long)crow.size() > op->L.bnchunk_max) return fail(FSDA_E_WORKSPACE, "chunk table larger than reserved");
+  if (!crow.empty()) {
+    HIP_TRY(hipMemcpyAsync(crow_d, crow.data(), sizeof(int) * crow.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(cbeg_d, cbeg.data(), sizeof(int) * cbeg.size(), hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(hipMemcpyAsync(rc0_d, c0.data(), sizeof(int) * c0.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *nchunk = (int)crow.size();
+  return FSDA_OK;
+}
+
+// Q (column-major) = X^T M'_c X src for the T columns of src (interleaved), with
+// the products' partials; stop is the flag the launches test.
+template <int T>
+void t_products(fsda_op* op, const TPtr& p, const double* src, const int* stop, hipStream_t s, bool timed) {
+  constexpr int G = BS / T;
+  const long long n = op->pb.n;
+  const int gx = grid_b(ceil_div(n, G));
+  const bool lab = has_lab_term(op);
+  TState* st = p.st;
+  launch(op, timed ? KC_BX : KC_OTHER, s, [&] {
+    if (lab)
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, true>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol,
+                         (int)n, src, BEpiX<T, double, true>{p.t, p.labw, T, 1}, stop, st->cm, tpart(p, BP_X));
+    else
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, false>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol,
+                         (int)n, src, BEpiX<T, double, false>{p.t, nullptr, T, 1}, stop, st->cm, tpart(p, BP_X));
+  });
+  if (lab) hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, stop, tpart(p, BP_X), gx, st->cm);
+  launch(op, timed ? KC_BS : KC_OTHER, s, [&] {
+    if (lab)
+      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, double, true>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr,
+                         op->pb.s_col, (int)n, p.t,
+                         BEpiLap<T, double, true>{p.t, p.labw, T, 1, op->pb.s_rowptr, p.u, op->pb.alpha, 0.0}, stop,
+                         st->cm, tpart(p, BP_TU));
+    else
+      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, double, false>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr,
+                         op->pb.s_col, (int)n, p.t,
+                         BEpiLap<T, double, false>{p.t, nullptr, T, 1, op->pb.s_rowptr, p.u, op->pb.alpha, 0.0},
+                         stop, st->cm, tpart(p, BP_TU));
+  });
+}
+
+template <int T>
+void t_xt(fsda_op* op, const TPtr& p, const double* u, const double* P, double* Q, const int* stop, hipStream_t s,
+          bool timed) {
+  constexpr int G = BS / T;
+  const long long d = op->pb.d;
+  const int gxt = grid_b(p.xa.nchunk + ceil_div(d - p.xa.nmed, G));
+  launch(op, timed ? KC_BXT : KC_OTHER, s, [&] {
+    hipLaunchKernelGGL((bk_xt<T, double>), dim3(gxt), dim3(BS), 0, s, p.xa, p.lpart, u, P, Q, p.ld, p.st->sigma, stop);
+    if (p.xa.nmed > 0)
+      hipLaunchKernelGGL((bk_xt_rows<T, double>), dim3(grid_b(p.xa.nmed)), dim3(BS), 0, s, p.xa, p.lpart, P, Q, p.ld,
+                         p.st->sigma, stop);
+  });
+}
+
+int t_colgrid(long long d) { return grid_b(ceil_div(d, BS)); }
+
+template <int T>
+void t_iteration(fsda_op* op, const TPtr& p, hipStream_t s, int tag) {
+  op->cur_tag = tag;
+  constexpr int G = BS / T;
+  const long long n = op->pb.n, d = op->pb.d;
+  TState* st = p.st;
+  const int gx = grid_b(ceil_div(n, G));
+  const int gsb = grid_b(ceil_div(d, G));
+  const int gc = t_colgrid(d);
+  t_products<T>(op, p, p.P, &st->stop, s, true);
+  hipLaunchKernelGGL(ts_step_a<T>, dim3(1), dim3(BS), 0, s, st, tpart(p, BP_TU), gx, tpart(p, BP_PP), gsb);
+  t_xt<T>(op, p, p.u, p.P, p.Q, &st->stop, s, true);
+  launch(op, KC_BRESID, s, [&] {
+    hipLaunchKernelGGL(ts_resid<T>, dim3(gc, T), dim3(BS), 0, s, st, p.Q, p.ring, p.ld, d, tpart(p, BP_RR));
+  });
+  hipLaunchKernelGGL(ts_step_b<T>, dim3(1), dim3(BS), 0, s, st, tpart(p, BP_RR), gc, p.hist);
+  launch(op, KC_BPUPD, s, [&] {
+    hipLaunchKernelGGL(ts_pupdate<T>, dim3(gsb), dim3(BS), 0, s, st, p.ring, p.ld, p.P, d, tpart(p, BP_PP));
+  });
+  op->cur_tag = -1;
+}
+
+template <int T>
+void t_fold(fsda_op* op, const TPtr& p, hipStream_t s) {
+  const long long d = op->pb.d;
+  const dim3 g(t_colgrid(d), p.ncol);
+  launch(op, KC_TFOLD, s, [&] {
+    if (p.chunk <= 8)
+      hipLaunchKernelGGL(ts_fold<8>, g, dim3(BS), 0, s, p.st, p.hist, T, p.ring, p.ld, p.W, p.Ps, d, p.nshift);
+    else if (p.chunk <= 16)
+      hipLaunchKernelGGL(ts_fold<16>, g, dim3(BS), 0, s, p.st, p.hist, T, p.ring, p.ld, p.W, p.Ps, d, p.nshift);
+    else if (p.chunk <= 32)
+      hipLaunchKernelGGL(ts_fold<32>, g, dim3(BS), 0, s, p.st, p.hist, T, p.ring, p.ld, p.W, p.Ps, d, p.nshift);
+    else
+      hipLaunchKernelGGL(ts_fold<64>, g, dim3(BS), 0, s, p.st, p.hist, T, p.ring, p.ld, p.W, p.Ps, d, p.nshift);
+  });
+  hipLaunchKernelGGL(ts_fold_done, dim3(1), dim3(1), 0, s, p.st);
+}
+
+template <int T>
+int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* lab_idx, const int8_t* lab_y,
+                const int64_t* lab_off, const double* betas, int nshift, double rtol, int maxit, int chunk, double* W,
+                int* iters, double* relres, hipStream_t s) {
+  const long long n = op->pb.n, d = op->pb.d;
+  TPtr p;
+  p.st = reinterpret_cast<TState*>(ws + L.st);
+  p.part = reinterpret_cast<double*>(ws + L.part);
+  p.hist = reinterpret_cast<double*>(ws + L.hist);
+  p.flags = reinterpret_cast<int*>(ws + L.flags);
+  p.labw = reinterpret_cast<double*>(ws + L.labw);
+  p.t = reinterpret_cast<double*>(ws + L.t);
+  p.u = reinterpret_cast<double*>(ws + L.u);
+  p.B = reinterpret_cast<double*>(ws + L.B);
+  p.P = reinterpret_cast<double*>(ws + L.P);
+  p.Q = reinterpret_cast<double*>(ws + L.Q);
+  p.ring = reinterpret_cast<double*>(ws + L.ring);
+  p.Ps = reinterpret_cast<double*>(ws + L.Ps);
+  p.lpart = reinterpret_cast<double*>(ws + L.lpart);
+  p.W = W;
+  p.ld = L.ld;
+  p.ncol = ncol;
+  p.nshift = nshift;
+  p.chunk = chunk;
+  int* crow = reinterpret_cast<int*>(ws + L.crow);
+  int* cbeg = reinterpret_cast<int*>(ws + L.cbeg);
+  int* rc0 = reinterpret_cast<int*>(ws + L.rc0);
+  int nchunk = 0;
+  int rc = t_chunk_table<T>(op, crow, cbeg, rc0, &nchunk, s);
+  if (rc) return rc;
+  p.xa = BXtArgs{op->xt_rowptr, op->xt_col, (int)d, op->nmed, nchunk, crow, cbeg, rc0};
+
+  // solver state (uploaded first: the set-up launches test its `zero` flag)
+  double sigma0 = betas[0];
+  for (int k = 0; k < nshift; k++) sigma0 = std::min(sigma0, betas[k]);
+  TState* h = op->htst;
+  std::memset(h, 0, sizeof(TState));
+  h->maxit = maxit;
+  h->ncol = ncol;
+  h->nshift = nshift;
+  h->chunk = chunk;
+  for (int c = 0; c < T; c++) {
+    h->tol[c] = rtol;
+    h->sigma[c] = sigma0;
+  }
+  for (int k = 0; k < nshift; k++) h->rel[k] = betas[k] - sigma0;
+  HIP_TRY(hipMemcpyAsync(p.st, h, sizeof(TState), hipMemcpyHostToDevice, s));
+
+  // labels of every target: check, then labeled weights and centred labels
+  int* cnt = reinterpret_cast<int*>(p.t);  // n x T counters (t is free until the solve)
+  double* ycen = p.u;                      // u is free until the solve
+  hipLaunchKernelGGL(k_fill_i, dim3(grid_for(n * T, 4096)), dim3(BS), 0, s, cnt, n * T, 0);
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(BS), 0, s, p.flags, (long long)(4 * BT_MAX), 0);
+  hipLaunchKernelGGL(k_fill_d, dim3(grid_for(n * T, 4096)), dim3(BS), 0, s, p.labw, n * T, 0.0);
+  hipLaunchKernelGGL(k_fill_d, dim3(grid_for(n * T, 4096)), dim3(BS), 0, s, ycen, n * T, 0.0);
+  for (int c = 0; c < ncol; c++) {
+    const long long k0 = lab_off[c], k1 = lab_off[c + 1];
+    if (k1 > k0)
+      hipLaunchKernelGGL(tk_label_check<T>, dim3(grid_for(k1 - k0, 1024)), dim3(BS), 0, s, lab_idx, lab_y, k0, k1, c,
+                         n, cnt, p.flags);
+  }
+  std::vector<int> fl(4 * BT_MAX);
+  HIP_TRY(hipMemcpyAsync(fl.data(), p.flags, sizeof(int) * fl.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int c = 0; c < ncol; c++) {
+    const std::string tg = "target " + std::to_string(c) + ": ";
+    if (fl[c * 4 + 2] & 1) return fail(FSDA_E_LABELS, tg + "labeled index out of range");
+    if (fl[c * 4 + 2] & 2) return fail(FSDA_E_LABELS, tg + "labeled index repeated");
+    if (fl[c * 4 + 2] & 4) return fail(FSDA_E_LABELS, tg + "labels must be +1 or -1");
+    if (fl[c * 4 + 0] == 0 || fl[c * 4 + 1] == 0) return fail(FSDA_E_LABELS, tg + "both classes must be labeled");
+  }
+  for (int c = 0; c < ncol; c++) {
+    const long long k0 = lab_off[c], k1 = lab_off[c + 1];
+    const double l = (double)(k1 - k0);
+    const double ybar = (double)(fl[c * 4 + 0] - fl[c * 4 + 1]) / l;
+    hipLaunchKernelGGL(tk_label_vectors<T>, dim3(grid_for(k1 - k0, 1024)), dim3(BS), 0, s, lab_idx, lab_y, k0, k1, c,
+                       1.0 / l, ybar, p.labw, ycen);
+  }
+  // right-hand sides B_c = X^T y_c (column-major)
+  t_xt<T>(op, p, ycen, nullptr, p.B, &p.st->zero, s, false);
+
+  // initial state
+  const int gc = t_colgrid(d);
+  hipLaunchKernelGGL(ts_init<T>, dim3(gc, T), dim3(BS), 0, s, p.B, p.ld, p.ring, p.P, p.Ps, W, d, ncol, nshift,
+                     tpart(p, BP_PP));
+  hipLaunchKernelGGL(ts_init_done<T>, dim3(1), dim3(BS), 0, s, p.st, tpart(p, BP_PP), gc);
+  HIP_TRY(hipGetLastError());
+
+  // chunks of iterations + one fold, replayed as a graph
+  bool graph = op->use_graph != 0 && !op->tk_on;
+  if (graph && !(op->tgexec && op->tkey_ws == ws && op->tkey_W == W && op->tkey_T == T && op->tkey_ncol == ncol &&
+                 op->tkey_nshift == nshift && op->tkey_chunk == chunk)) {
+    if (op->tgexec) (void)hipGraphExecDestroy(op->tgexec);
+    op->tgexec = nullptr;
+    hipGraph_t gr = nullptr;
+    HIP_TRY(hipStreamBeginCapture(op->cap, hipStreamCaptureModeThreadLocal));
+    for (int j = 0; j < chunk; j++) t_iteration<T>(op, p, op->cap, j);
+    t_fold<T>(op, p, op->cap);
+    const hipError_t ce = hipStreamEndCapture(op->cap, &gr);
+    hipError_t ie = hipErrorUnknown;
+    if (ce == hipSuccess) {
+      ie = hipGraphInstantiate(&op->tgexec, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+    }
+    if (ce != hipSuccess || ie != hipSuccess) {
+      op->tgexec = nullptr;
+      (void)hipGetLastError();
+      graph = false;
+    } else {
+      op->tkey_ws = ws;
+      op->tkey_W = W;
+      op->tkey_T = T;
+      op->tkey_ncol = ncol;
+      op->tkey_nshift = nshift;
+      op->tkey_chunk = chunk;
+    }
+  }
+  const size_t off = offsetof(TState, iter);
+  const int max_chunks = (int)std::min<long long>((long long)maxit / chunk + 2, 1LL << 30);
+  int done_iters = 0;
+  for (int c = 0; c < max_chunks; c++) {
+    if (graph) {
+      HIP_TRY(hipGraphLaunch(op->tgexec, s));
+    } else {
+      for (int j = 0; j < chunk; j++) t_iteration<T>(op, p, s, j);
+      t_fold<T>(op, p, s);
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(h) + off, reinterpret_cast<char*>(p.st) + off, 4 * sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (op->tk_on) {
+      const int trc = tk_flush(op, h->iter - done_iters);
+      if (trc) return trc;
+    }
+    done_iters = h->iter;
+    if (h->stop) break;
+  }
+
+  // true FP64 residuals ||B_c - A_c(beta_s) w_cs|| of every (target, shift)
+  for (int k = 0; k < nshift; k++) {
+    constexpr int G = BS / T;
+    hipLaunchKernelGGL(ts_pack<T>, dim3(grid_b(ceil_div(d, G))), dim3(BS), 0, s, W, k, nshift, ncol, p.P, d);
+    t_products<T>(op, p, p.P, &p.st->zero, s, false);
+    t_xt<T>(op, p, p.u, nullptr, p.Q, &p.st->zero, s, false);
+    hipLaunchKernelGGL(ts_resnorm<T>, dim3(gc, ncol), dim3(BS), 0, s, p.B, p.Q, p.ld, W, k, nshift, betas[k], d,
+                       tpart(p, BP_RR));
+    hipLaunchKernelGGL(ts_res_done<T>, dim3(1), dim3(BS), 0, s, p.st, tpart(p, BP_RR), gc, k, ncol);
+  }
+  // W to the caller's feature order, through the ring (free now) in pieces
+  {
+    const long long rows = (long long)ncol * nshift;
+    const long long per = std::max<long long>(1, (long long)(chunk * T) * p.ld / d);
+    for (long long r0 = 0; r0 < rows; r0 += per) {
+      const long long r1 = std::min(rows, r0 + per);
+      hipLaunchKernelGGL(ts_unpermute, dim3(grid_for((r1 - r0) * d, 8192)), dim3(BS), 0, s, W, op->old2new, p.ring, r0,
+                         r1, d);
+      HIP_TRY(hipMemcpyAsync(W + r0 * d, p.ring, sizeof(double) * (r1 - r0) * d, hipMemcpyDeviceToDevice, s));
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h, p.st, sizeof(TState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (op->tk_on) {
+    const int trc = tk_flush(op, 1 << 30);
+    if (trc) return trc;
+  }
+  for (int c = 0; c < ncol; c++)
+    for (int k = 0; k < nshift; k++) {
+      const int e = c * TS_MAX + k;
+      iters[c * nshift + k] = h->conv[e];
+      relres[c * nshift + k] = h->bnorm[c] > 0.0 ? std::sqrt(h->res2[e]) / h->bnorm[c] : 0.0;
+    }
+  if (h->status == FSDA_E_BREAKDOWN) return fail(FSDA_E_BREAKDOWN, "CG breakdown: <p, A p> <= 0 or not finite");
+  return h->status == FSDA_NOT_CONVERGED ? FSDA_NOT_CONVERGED : FSDA_OK;
+}
+
+int targets_any(int T, fsda_op* op, char* ws, const TLayout& L, int ncol, const int* lab_idx, const int8_t* lab_y,
+                const int64_t* lab_off, const double* betas, int nshift, double rtol, int maxit, int chunk, double* W,
+                int* iters, double* relres, hipStream_t s) {
+  switch (T) {
+    case 4: return run_targets<4>(op, ws, L, ncol, lab_idx, lab_y, lab_off, betas, nshift, rtol, maxit, chunk, W, iters, relres, s);
+    case 8: return run_targets<8>(op, ws, L, ncol, lab_idx, lab_y, lab_off, betas, nshift, rtol, maxit, chunk, W, iters, relres, s);
+    case 16: return run_targets<16>(op, ws, L, ncol, lab_idx, lab_y, lab_off, betas, nshift, rtol, maxit, chunk, W, iters, relres, s);
+    case 32: return run_targets<32>(op, ws, L, ncol, lab_idx, lab_y, lab_off, betas, nshift, rtol, maxit, chunk, W, iters, relres, s);
+    default: return run_targets<64>(op, ws, L, ncol, lab_idx, lab_y, lab_off, betas, nshift, rtol, maxit, chunk, W, iters, relres, s);
+  }
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -893,6 +1257,7 @@ void fsda_destroy_operator(fsda_op* op) {
   if (op->cap) (void)hipStreamDestroy(op->cap);
   if (op->hst) (void)hipHostFree(op->hst);
   if (op->hbst) (void)hipHostFree(op->hbst);
+  if (op->htst) (void)hipHostFree(op->htst);
   delete op;
 }
 
@@ -938,6 +1303,10 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
   if (hipHostMalloc(reinterpret_cast<void**>(&op->hbst), sizeof(BState), hipHostMallocDefault) != hipSuccess) {
     op->hbst = nullptr;
     return bail(fail(FSDA_E_HIP, "hipHostMalloc of the batched status mirror failed"));
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&op->htst), sizeof(TState), hipHostMallocDefault) != hipSuccess) {
+    op->htst = nullptr;
+    return bail(fail(FSDA_E_HIP, "hipHostMalloc of the target-batch status mirror failed"));
   }
   const Layout& L = op->L;
   op->st = at<State>(op, L.st);
@@ -1163,6 +1532,47 @@ int fsda_multishift_solve(fsda_op* op, const double* b, const double* betas, int
     return ok ? FSDA_OK : FSDA_NOT_CONVERGED;
   }
   return h->status == FSDA_NOT_CONVERGED ? FSDA_NOT_CONVERGED : FSDA_OK;
+}
+
+int fsda_batch_workspace_size(const fsda_op* op, int ntarget, int nshift, int chunk, size_t* bytes) {
+  if (!op || !bytes) return fail(FSDA_E_ARG, "NULL argument");
+  if (ntarget < 1 || ntarget > FSDA_MAX_TARGETS) return fail(FSDA_E_ARG, "ntarget outside 1..FSDA_MAX_TARGETS");
+  if (nshift < 1 || nshift > FSDA_MAX_SHIFTS) return fail(FSDA_E_ARG, "nshift outside 1..FSDA_MAX_SHIFTS");
+  if (chunk < 0 || chunk > FSDA_MAX_CHUNK) return fail(FSDA_E_RANGE, "chunk outside 0..FSDA_MAX_CHUNK");
+  if (chunk == 0) chunk = 32;
+  TLayout L;
+  tlayout(op, batch_tile(ntarget), nshift, chunk, &L);
+  *bytes = L.total;
+  return FSDA_OK;
+}
+
+int fsda_multishift_solve_batch(fsda_op* op, int ntarget, const int32_t* lab_idx, const int8_t* lab_y,
+                                const int64_t* lab_off, const double* betas, int nshift, double rtol, int maxit,
+                                int chunk, void* workspace, size_t ws_bytes, double* W, int* iters, double* relres,
+                                void* stream) {
+  if (!op || !lab_idx || !lab_y || !lab_off || !betas || !W || !iters || !relres)
+    return fail(FSDA_E_ARG, "NULL argument");
+  size_t need = 0;
+  int rc = fsda_batch_workspace_size(op, ntarget, nshift, chunk, &need);
+  if (rc) return rc;
+  if (chunk == 0) chunk = 32;
+  if (!(rtol > 0.0)) return fail(FSDA_E_RANGE, "rtol must be > 0");
+  if (maxit < 1) return fail(FSDA_E_RANGE, "maxit must be >= 1");
+  for (int k = 0; k < nshift; k++)
+    if (!(betas[k] > 0.0) || !std::isfinite(betas[k])) return fail(FSDA_E_RANGE, "every beta must be finite and > 0");
+  if (lab_off[0] != 0) return fail(FSDA_E_ARG, "lab_off[0] must be 0");
+  for (int c = 0; c < ntarget; c++) {
+    if (lab_off[c + 1] - lab_off[c] < 2 || lab_off[c + 1] - lab_off[c] > op->pb.n)
+      return fail(FSDA_E_LABELS, "target " + std::to_string(c) + ": need 2 <= labeled count <= n");
+  }
+  if (!workspace || ws_bytes < need)
+    return fail(FSDA_E_WORKSPACE, "workspace NULL or smaller than fsda_batch_workspace_size()");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(FSDA_E_WORKSPACE, "workspace not 256-byte aligned");
+  const int T = batch_tile(ntarget);
+  TLayout L;
+  tlayout(op, T, nshift, chunk, &L);
+  return targets_any(T, op, static_cast<char*>(workspace), L, ntarget, lab_idx, lab_y, lab_off, betas, nshift, rtol,
+                     maxit, chunk, W, iters, relres, static_cast<hipStream_t>(stream));
 }
 
 int fsda_time_kernel(fsda_op* op, int kernel, int enable) {

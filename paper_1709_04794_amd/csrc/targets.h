@@ -1,0 +1,414 @@
+// Many binary targets over one sample set: T labelings of the same X and S
+// (each with its own labeled set, hence its own centring and right-hand side)
+// solved together over one shift grid.  Every target runs its own shifted CG
+// (Alg. 3, seeded at the smallest shift); the sparse products of all T targets
+// share one pass over the indices (the batched products of batched.h, in FP64).
+//
+// Layout: the vectors the products gather from (the direction P, and t, u in
+// sample space) are interleaved, element (row j, target c) at j * T + c.  The
+// vectors that are only streamed (the residual ring R, the product Q, the
+// right-hand sides B, and the per-shift state W_s, P_s) are column-major,
+// element (c, j) at c * ld + j (W and P_s at (c * S + s) * ld + j), so the
+// shift fold sees one target per block and reads its coefficients as
+// wave-uniform values.
+#pragma once
+
+#include "batched.h"
+
+namespace fsda {
+
+constexpr int TS_MAX = 64;  // shifts per target
+
+struct TState {
+  int iter, stop, status, maxit;
+  int ncol, nshift, chunk, fold_start;
+  int zero;                        // always 0: the stop flag of launches outside the recurrence
+  int pad_[3];
+  double rr[BT_MAX];               // <r_c, r_c>
+  double a_cur[BT_MAX], a_prev[BT_MAX], b_cur[BT_MAX];
+  double tol[BT_MAX];              // rtol ||b_c||
+  double bnorm[BT_MAX];
+  double sigma[BT_MAX];            // seed shift (the smallest beta), the same for every target
+  double cm[BT_MAX];               // labeled mean of t_c
+  int col_active[BT_MAX];
+  double rel[TS_MAX];              // beta_s - sigma0
+  // per (target, shift), index c * TS_MAX + s
+  double zp[BT_MAX * TS_MAX], z[BT_MAX * TS_MAX], zn[BT_MAX * TS_MAX], as[BT_MAX * TS_MAX];
+  double res2[BT_MAX * TS_MAX];    // ||b_c - A_c(beta_s) w_cs||^2 after the solve
+  int active[BT_MAX * TS_MAX];
+  int conv[BT_MAX * TS_MAX];
+};
+
+// Column-major streaming kernels run on a (gx, T) grid: block (x, c) covers
+// the rows j = x * BS + tid, x * BS + tid + gx * BS, ... of target c, and
+// writes one partial per block into part[x * T + c].
+template <int T>
+__device__ __forceinline__ void write_partial_col(double* part, double acc) {
+  const double t = block_sum_all(acc);
+  if (threadIdx.x == 0) part[(size_t)blockIdx.x * T + blockIdx.y] = t;
+}
+
+// ---------------------------------------------------------------------------
+// set-up
+// ---------------------------------------------------------------------------
+
+// Pass 1 over the labeled entries [k0, k1) of target c: range, repeats (cnt is
+// an n x T counter, zero on entry), label values, class counts into
+// flags[c * 4 + {0: positives, 1: negatives, 2: error bits}].
+template <int T>
+__global__ void tk_label_check(const int* idx, const int8_t* y, long long k0, long long k1, int c, long long n,
+                               int* cnt, int* flags) {
+  FSDA_GRID_LOOP(kk, k1 - k0) {
+    const long long k = k0 + kk;
+    const int i = idx[k];
+    if (i < 0 || i >= n) {
+      atomicOr(&flags[c * 4 + 2], 1);
+      continue;
+    }
+    if (atomicAdd(&cnt[(size_t)i * T + c], 1) != 0) atomicOr(&flags[c * 4 + 2], 2);
+    const int yy = y[k];
+    if (yy == 1)
+      atomicAdd(&flags[c * 4 + 0], 1);
+    else if (yy == -1)
+      atomicAdd(&flags[c * 4 + 1], 1);
+    else
+      atomicOr(&flags[c * 4 + 2], 4);
+  }
+}
+
+// Pass 2: labw[i * T + c] = 1/l_c, ycen[i * T + c] = y_i - mean_c(y) on the
+// labeled rows of target c (the arrays are zero elsewhere).
+template <int T>
+__global__ void tk_label_vectors(const int* idx, const int8_t* y, long long k0, long long k1, int c, double inv_l,
+                                 double ybar, double* labw, double* ycen) {
+  FSDA_GRID_LOOP(kk, k1 - k0) {
+    const long long k = k0 + kk;
+    const int i = idx[k];
+    labw[(size_t)i * T + c] = inv_l;
+    ycen[(size_t)i * T + c] = (y[k] > 0 ? 1.0 : -1.0) - ybar;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// recurrence
+// ---------------------------------------------------------------------------
+
+// ring slot 0 = B_c, P = B (interleaved), P_s = B_c, W_s = 0 (targets c < ncol
+// only; W is the caller's [ncol][nshift][d]); partials of <b_c, b_c>.
+template <int T>
+__global__ __launch_bounds__(BS) void ts_init(const double* __restrict__ B, long long ld, double* ring, double* P,
+                                              double* Ps, double* W, long long d, int ncol, int nshift,
+                                              double* part) {
+  const int c = blockIdx.y;
+  double acc = 0.0;
+  for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
+    const double x = B[(size_t)c * ld + j];
+    ring[(size_t)c * ld + j] = x;
+    P[(size_t)j * T + c] = x;
+    if (c < ncol)
+      for (int s = 0; s < nshift; s++) {
+        Ps[((size_t)c * nshift + s) * ld + j] = x;
+        W[((size_t)c * nshift + s) * d + j] = 0.0;
+      }
+    acc += x * x;
+  }
+  write_partial_col<T>(part, acc);
+}
+
+// rr_c, ||b_c||, tolerances, the zeta windows; a target with a zero right-hand
+// side (or a padding column) never starts.  One block.
+template <int T>
+__global__ __launch_bounds__(BS) void ts_init_done(TState* st, const double* part, int np) {
+  __shared__ double rr[T];
+  __shared__ int any;
+  col_sums<T>(part, np, rr);
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  const int S = st->nshift;
+  for (int e = threadIdx.x; e < T * S; e += BS) {
+    const int c = e / S, s = e % S, k = c * TS_MAX + s;
+    const int on = c < st->ncol && rr[c] > 0.0;
+    st->zp[k] = 1.0;
+    st->z[k] = 1.0;
+    st->active[k] = on;
+    st->conv[k] = 0;
+  }
+  if (threadIdx.x < T) {
+    const int c = threadIdx.x;
+    const int on = c < st->ncol && rr[c] > 0.0;
+    st->rr[c] = rr[c];
+    st->bnorm[c] = sqrt(rr[c]);
+    st->tol[c] = st->tol[c] * st->bnorm[c];  // held rtol
+    st->a_prev[c] = 1.0;
+    st->b_cur[c] = 0.0;
+    st->a_cur[c] = 0.0;
+    st->col_active[c] = on;
+    if (on) atomicOr(&any, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && !any) st->stop = 1;
+}
+
+// a_c = rr_c / (<t,u>_c + sigma0 <p,p>_c) (<p_0, p_0> = <b, b> = rr_c in the
+// first iteration); the zeta step of every active (target, shift):
+// zeta_{i+1} and a_s = a zeta_{i+1} / zeta_i.  One block.
+template <int T>
+__global__ __launch_bounds__(BS) void ts_step_a(TState* st, const double* tu_part, int ntu, const double* pp_part,
+                                                int npp) {
+  if (st->stop) return;
+  __shared__ double tu[T], pp[T], av[T];
+  __shared__ int bad;
+  col_sums<T>(tu_part, ntu, tu);
+  col_sums<T>(pp_part, npp, pp);
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  if (threadIdx.x < T) {
+    const int c = threadIdx.x;
+    double a = 0.0;
+    if (st->col_active[c]) {
+      const double ppc = st->iter == 0 ? st->rr[c] : pp[c];
+      const double pq = tu[c] + st->sigma[c] * ppc;
+      a = st->rr[c] / pq;
+      if (!(pq > 0.0) || !isfinite(a)) {
+        atomicOr(&bad, 1);
+        a = 0.0;
+      }
+    }
+    av[c] = a;
+  }
+  __syncthreads();
+  if (bad) {
+    if (threadIdx.x == 0) {
+      st->status = FSDA_E_BREAKDOWN;
+      st->stop = 1;
+    }
+    return;
+  }
+  const int S = st->nshift;
+  for (int e = threadIdx.x; e < T * S; e += BS) {
+    const int c = e / S, s = e % S, k = c * TS_MAX + s;
+    if (!st->active[k]) continue;
+    const double a = av[c], ap = st->a_prev[c], b = st->b_cur[c];
+    const double zp = st->zp[k], z = st->z[k];
+    const double den = a * b * (zp - z) + zp * ap * (1.0 + st->rel[s] * a);
+    const double zn = zp * z * ap / den;
+    st->zn[k] = zn;
+    st->as[k] = a * zn / z;
+  }
+  if (threadIdx.x < T) st->a_cur[threadIdx.x] = av[threadIdx.x];
+}
+
+// r_{i+1} = r_i - a_c q (ring slots i % m and (i + 1) % m, column-major);
+// partials of <r_{i+1}, r_{i+1}>.  Grid (gx, T).
+template <int T>
+__global__ __launch_bounds__(BS) void ts_resid(const TState* st, const double* __restrict__ Q, double* ring,
+                                               long long ld, long long d, double* part) {
+  if (st->stop) return;
+  const int c = blockIdx.y;
+  const int i = st->iter, m = st->chunk;
+  const double a = st->a_cur[c];
+  const double* r = ring + ((size_t)(i % m) * T + c) * ld;
+  double* rn = ring + ((size_t)((i + 1) % m) * T + c) * ld;
+  const double* q = Q + (size_t)c * ld;
+  double acc = 0.0;
+  for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
+    const double x = r[j] - a * q[j];
+    rn[j] = x;
+    acc += x * x;
+  }
+  write_partial_col<T>(part, acc);
+}
+
+// b_c = rr'/rr; per (target, shift): the fold coefficients (a_s, zeta_{i+1},
+// b_s = b (zeta_{i+1}/zeta_i)^2, 1), or the identity (0, 0, 1, 0) once frozen,
+// into hist[((i % m) * T + c) * S + s]; the stop test |zeta_{i+1}| ||r_{i+1}||
+// <= rtol ||b_c||; target and global stop; iteration count.  One block.
+template <int T>
+__global__ __launch_bounds__(BS) void ts_step_b(TState* st, const double* rr_part, int nrr, double* hist) {
+  if (st->stop) return;
+  __shared__ double rrn[T], bv[T];
+  __shared__ int still[T];
+  __shared__ int any;
+  col_sums<T>(rr_part, nrr, rrn);
+  if (threadIdx.x < T) {
+    const int c = threadIdx.x;
+    bv[c] = st->col_active[c] ? rrn[c] / st->rr[c] : 0.0;
+    still[c] = 0;
+  }
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  const int i = st->iter, S = st->nshift, slot = i % st->chunk;
+  for (int e = threadIdx.x; e < T * S; e += BS) {
+    const int c = e / S, s = e % S, k = c * TS_MAX + s;
+    double* h = hist + (((size_t)slot * T + c) * S + s) * 4;
+    if (st->active[k]) {
+      const double zn = st->zn[k], z = st->z[k];
+      const double ratio = zn / z;
+      h[0] = st->as[k];
+      h[1] = zn;
+      h[2] = bv[c] * ratio * ratio;
+      h[3] = 1.0;
+      st->zp[k] = z;
+      st->z[k] = zn;
+      st->conv[k] = i + 1;
+      if (fabs(zn) * sqrt(rrn[c]) <= st->tol[c])
+        st->active[k] = 0;
+      else
+        atomicOr(&still[c], 1);
+    } else {
+      h[0] = 0.0;
+      h[1] = 0.0;
+      h[2] = 1.0;
+      h[3] = 0.0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < T) {
+    const int c = threadIdx.x;
+    if (st->col_active[c]) {
+      st->a_prev[c] = st->a_cur[c];
+      st->b_cur[c] = bv[c];
+      st->rr[c] = rrn[c];
+      st->col_active[c] = still[c];
+      if (still[c]) atomicOr(&any, 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->iter = i + 1;
+    if (!any) {
+      st->stop = 1;
+    } else if (i + 1 >= st->maxit) {
+      st->stop = 1;
+      st->status = FSDA_NOT_CONVERGED;
+    }
+  }
+}
+
+// P = r_{i+1} + b_c P (interleaved; the ring is column-major) for the targets
+// still active; partials of <p, p> per target.
+template <int T>
+__global__ __launch_bounds__(BS) void ts_pupdate(const TState* st, const double* __restrict__ ring, long long ld,
+                                                 double* P, long long d, double* part) {
+  if (st->stop) return;
+  constexpr int G = BS / T;
+  const int c = threadIdx.x % T, g = threadIdx.x / T;
+  const double b = st->b_cur[c];
+  const bool on = st->col_active[c] != 0;
+  const double* r = ring + ((size_t)((st->iter) % st->chunk) * T + c) * ld;  // iter was advanced by ts_step_b
+  double acc = 0.0;
+  for (long long j = (long long)blockIdx.x * G + g; j < d; j += (long long)gridDim.x * G) {
+    const size_t e = (size_t)j * T + c;
+    double p = P[e];
+    if (on) {
+      p = r[j] + b * p;
+      P[e] = p;
+    }
+    acc += p * p;
+  }
+  write_partials_cols<T>(part, acc);
+}
+
+// Fold of iterations [fold_start, iter) of target c = blockIdx.y: per row, the
+// buffered residuals in registers, then shift by shift
+//   W_s += a_s P_s ;  P_s = zeta_{k+1,s} r_{k+1} + b_s P_s
+// in iteration order, with wave-uniform coefficients.  Shifts frozen before
+// the chunk are skipped.  Grid (gx, ncol).
+template <int M>
+__global__ __launch_bounds__(BS) void ts_fold(const TState* st, const double* __restrict__ hist, int T,
+                                              const double* ring, long long ld, double* W, double* Ps, long long d,
+                                              int nshift) {
+  const int k0 = st->fold_start, k1 = st->iter, m = st->chunk;
+  const int cnt = k1 - k0;
+  if (cnt <= 0) return;
+  const int c = blockIdx.y;
+  for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
+    double rv[M];
+#pragma unroll
+    for (int k = 0; k < M; k++)
+      if (k < cnt) rv[k] = ring[((size_t)((k0 + k + 1) % m) * T + c) * ld + j];
+    for (int s0 = 0; s0 < nshift; s0 += SG) {
+      double w[SG], pp[SG];
+      bool on[SG];
+#pragma unroll
+      for (int g = 0; g < SG; g++) {
+        const int s = s0 + g;
+        on[g] = s < nshift && hist[((((size_t)(k0 % m)) * T + c) * nshift + s) * 4 + 3] != 0.0;
+        w[g] = on[g] ? W[((size_t)c * nshift + s) * d + j] : 0.0;
+        pp[g] = on[g] ? Ps[((size_t)c * nshift + s) * ld + j] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < M; k++) {
+        if (k < cnt) {
+          const double* h = hist + (((size_t)((k0 + k) % m) * T + c) * nshift) * 4;
+#pragma unroll
+          for (int g = 0; g < SG; g++) {
+            if (s0 + g < nshift) {
+              const double* cs = h + (s0 + g) * 4;
+              w[g] += cs[0] * pp[g];
+              pp[g] = cs[1] * rv[k] + cs[2] * pp[g];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < SG; g++) {
+        const int s = s0 + g;
+        if (on[g]) {
+          W[((size_t)c * nshift + s) * d + j] = w[g];
+          Ps[((size_t)c * nshift + s) * ld + j] = pp[g];
+        }
+      }
+    }
+  }
+}
+
+__global__ void ts_fold_done(TState* st) { st->fold_start = st->iter; }
+
+// ---------------------------------------------------------------------------
+// after the solve
+// ---------------------------------------------------------------------------
+
+// P[j * T + c] = W[(c * nshift + s) * d + j] for c < ncol, 0 for the padding columns.
+template <int T>
+__global__ __launch_bounds__(BS) void ts_pack(const double* __restrict__ W, int s, int nshift, int ncol, double* P,
+                                              long long d) {
+  constexpr int G = BS / T;
+  const int c = threadIdx.x % T, g = threadIdx.x / T;
+  for (long long j = (long long)blockIdx.x * G + g; j < d; j += (long long)gridDim.x * G)
+    P[(size_t)j * T + c] = c < ncol ? W[((size_t)c * nshift + s) * d + j] : 0.0;
+}
+
+// partials of ||B_c - Q_c - beta w_cs||^2 (Q = X^T M' X w_cs, column-major).  Grid (gx, ncol).
+template <int T>
+__global__ __launch_bounds__(BS) void ts_resnorm(const double* __restrict__ B, const double* __restrict__ Q,
+                                                 long long ld, const double* __restrict__ W, int s, int nshift,
+                                                 double beta, long long d, double* part) {
+  const int c = blockIdx.y;
+  const double* w = W + ((size_t)c * nshift + s) * d;
+  double acc = 0.0;
+  for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
+    const double r = B[(size_t)c * ld + j] - (Q[(size_t)c * ld + j] + beta * w[j]);
+    acc += r * r;
+  }
+  write_partial_col<T>(part, acc);
+}
+
+// res2[c * TS_MAX + s] = sum of the partials of target c.  One block.
+template <int T>
+__global__ __launch_bounds__(BS) void ts_res_done(TState* st, const double* part, int np, int s, int ncol) {
+  __shared__ double v[T];
+  col_sums<T>(part, np, v);
+  if (threadIdx.x < ncol) st->res2[threadIdx.x * TS_MAX + s] = v[threadIdx.x];
+}
+
+// out[(row) * d + jj] = W[row * d + old2new[jj]] for rows [r0, r1) of W ([ncol * nshift][d]).
+__global__ void ts_unpermute(const double* __restrict__ W, const int* __restrict__ old2new, double* out, long long r0,
+                             long long r1, long long d) {
+  FSDA_GRID_LOOP(e, (r1 - r0) * d) {
+    const long long row = r0 + e / d, jj = e % d;
+    out[e] = W[row * d + old2new[jj]];
+  }
+}
+
+}  // namespace fsda

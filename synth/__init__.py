@@ -193,6 +193,26 @@ def labels(n: int, x_rowptr: np.ndarray, x_col: np.ndarray, d: int, n_lab: int, 
     return lab_idx, y
 
 
+def target_labels(pb, ntarget: int, seed: int, frac_median: float = 0.007, frac_sigma: float = 0.8,
+                  frac_lo: float = 0.001, frac_hi: float = 0.05, pos_lo: float = 0.02, pos_hi: float = 0.30,
+                  min_lab: int = 4):
+    """Labeled sets of ``ntarget`` binary targets over the samples of ``pb``.
+
+    Target c labels a fraction f_c of the samples, ln f_c ~ N(ln frac_median,
+    frac_sigma) clipped to [frac_lo, frac_hi] (at least ``min_lab`` rows), with
+    a positive rate ~ U(pos_lo, pos_hi); rows and signs come from ``labels``
+    with a target-specific hidden score.  Returns a list of (lab_idx, lab_y).
+    """
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 91]))
+    out = []
+    for c in range(ntarget):
+        f = float(np.clip(np.exp(rng.normal(np.log(frac_median), frac_sigma)), frac_lo, frac_hi))
+        pos = float(rng.uniform(pos_lo, pos_hi))
+        n_lab = min(pb.n, max(min_lab, int(round(f * pb.n))))
+        out.append(labels(pb.n, pb.x_rowptr, pb.x_col, pb.d, n_lab, pos, seed=seed * 1000 + c + 1))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # problems
 # ---------------------------------------------------------------------------

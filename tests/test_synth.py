@@ -78,3 +78,17 @@ def test_labels_planted():
     li, ly = synth.labels(1000, rp, col, 500, 100, 0.2, seed=3)
     assert li.size == 100 and np.all(np.diff(li) > 0)
     assert (ly > 0).sum() == 20 and (ly < 0).sum() == 80
+
+
+def test_target_labels_are_valid_and_reproducible():
+    pb = synth.workload("tiny")
+    a = synth.target_labels(pb, 7, seed=4, frac_median=0.02)
+    b = synth.target_labels(pb, 7, seed=4, frac_median=0.02)
+    assert len(a) == 7
+    for (i1, y1), (i2, y2) in zip(a, b):
+        assert np.array_equal(i1, i2) and np.array_equal(y1, y2)
+        assert i1.dtype == np.int32 and y1.dtype == np.int8
+        assert np.unique(i1).size == i1.size and i1.min() >= 0 and i1.max() < pb.n
+        assert set(np.unique(y1).tolist()) == {-1, 1}
+        assert i1.size >= 4
+    assert len({i.size for i, _ in a}) > 1  # the labeled fraction varies over targets
