@@ -9,6 +9,9 @@ Contents
     plain FP64 per-shift conjugate gradient (Alg. 2) on the centred,
     regularised SDA system of Alg. 7, with both centred products of Sec. 3.2.3
     written out.  OpenMP, fixed-order reductions.
+  * the same file's spectral-analysis variant (Alg. sasda; :func:`sa_solve`,
+    :func:`sa_apply`, :func:`sa_rhs`): per-shift CG in sample space on
+    Cl^T M + beta I_N, the ratings being the solution itself.
   * :mod:`oracle.dense`: dense NumPy/SciPy forms (Cholesky of the operator,
     sample-space push-through, labeled-only dual ridge) used to pin the above.
   * :mod:`oracle.shifted`: the paper's shifted CG (Alg. 3) in NumPy, for the
@@ -66,8 +69,11 @@ def _load():
         lib.orc_rhs.argtypes = [pp, P, P]
         lib.orc_solve.argtypes = [pp, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P, P, P]
         lib.orc_project.argtypes = [pp, P, ctypes.c_int, P]
+        lib.orc_sa_rhs.argtypes = [pp, P, P]
+        lib.orc_sa_apply.argtypes = [pp, ctypes.c_double, P, P]
+        lib.orc_sa_solve.argtypes = [pp, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P, P, P]
         for f in (lib.orc_mean_labeled, lib.orc_apply, lib.orc_m_apply, lib.orc_xct, lib.orc_rhs,
-                  lib.orc_solve, lib.orc_project):
+                  lib.orc_solve, lib.orc_project, lib.orc_sa_rhs, lib.orc_sa_apply, lib.orc_sa_solve):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -180,3 +186,35 @@ def project(pb, W: np.ndarray) -> np.ndarray:
     out = np.empty((W.shape[0], pb.n))
     _check(_load().orc_project(bnd.ref, _p(W), W.shape[0], _p(out)), "project")
     return out
+
+
+def sa_rhs(pb, r: np.ndarray = None, alpha=None) -> np.ndarray:
+    """Alg. sasda right-hand side: y_c (r is None) or [W 0; 0 0](r - 1 <1_l, r>/l)."""
+    bnd = _Bound(pb, alpha)
+    out = np.empty(pb.n)
+    rr = None if r is None else np.ascontiguousarray(r, dtype=np.float64)
+    _check(_load().orc_sa_rhs(bnd.ref, _p(rr), _p(out)), "sa_rhs")
+    return out
+
+
+def sa_apply(pb, beta: float, z: np.ndarray, alpha=None) -> np.ndarray:
+    """q = (Cl^T M + beta I_N) z (Alg. sasda, step 4)."""
+    bnd = _Bound(pb, alpha)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    q = np.empty(pb.n)
+    _check(_load().orc_sa_apply(bnd.ref, float(beta), _p(z), _p(q)), "sa_apply")
+    return q
+
+
+def sa_solve(pb, betas=None, rtol: float = 1e-12, maxit: int = 100000, g: np.ndarray = None, alpha=None):
+    """Alg. sasda per shift.  Returns (Z [S, n] = ratings, iters [S], relres [S] (true), status)."""
+    bnd = _Bound(pb, alpha)
+    betas = np.ascontiguousarray(pb.betas if betas is None else betas, dtype=np.float64)
+    S = betas.size
+    Z = np.zeros((S, pb.n))
+    iters = np.zeros(S, dtype=np.int32)
+    relres = np.zeros(S)
+    gg = None if g is None else np.ascontiguousarray(g, dtype=np.float64)
+    rc = _load().orc_sa_solve(bnd.ref, _p(gg), S, _p(betas), float(rtol), int(maxit), _p(Z), _p(iters), _p(relres))
+    _check(rc, "sa_solve")
+    return Z, iters, relres, rc

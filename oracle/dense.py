@@ -119,3 +119,24 @@ def solve_dual_ridge_alpha0(pb, beta: float) -> np.ndarray:
     yc = yl - yl.mean()
     G = Xlc @ Xlc.T + beta * np.eye(Xl.shape[0])
     return Xlc.T @ np.linalg.solve(G, yc)
+
+
+# ---- spectral analysis for SDA (Alg. sasda), sample space ------------------
+
+def sa_operator(pb, beta: float, alpha=None) -> np.ndarray:
+    """C^T M I_N + beta I_N, C = I_N - 1 1_l^T / l (Alg. sasda, step 4)."""
+    return centring(pb).T @ weight(pb, alpha) + beta * np.eye(pb.n)
+
+
+def sa_rhs(pb, r=None) -> np.ndarray:
+    """Canonical y_c, or W_full (r - 1 <1_l, r> / l) for a start vector r (Alg. sasda, steps 2-4)."""
+    if r is None:
+        return centred_labels(pb)
+    ones_l = np.zeros(pb.n)
+    ones_l[pb.lab_idx] = 1.0
+    rr = np.asarray(r, dtype=np.float64) - np.ones(pb.n) * (ones_l @ r) / len(pb.lab_idx)
+    return between_class_weight(pb) @ rr
+
+
+def sa_solve_dense(pb, beta: float, g=None, alpha=None) -> np.ndarray:
+    return np.linalg.solve(sa_operator(pb, beta, alpha), sa_rhs(pb) if g is None else g)

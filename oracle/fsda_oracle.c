@@ -286,11 +286,21 @@ int orc_rhs(const orc_problem *pb, const double *r, double *b) {
   return ORC_OK;
 }
 
-/* Conjugate gradient (Alg. 2) on (Xc^T M Xc + beta I) w = b, w0 = 0.
+/* q = (Cl^T M + beta I_N) z in sample space, Cl = I_N - 1 1_l^T / l, applied as
+ * printed in Alg. sasda (step 4): Cl^T v = v - 1_l <1, v> / l. */
+static void sa_apply_ctx(orc_ctx *c, double beta, const double *z, double *q) {
+  const orc_problem *pb = c->pb;
+  m_mul(c, z, c->t);
+  double s = total(pb->n, c->t) / (double)pb->n_lab;
+  for (int64_t i = 0; i < pb->n; i++) q[i] = c->t[i] - (c->lab[i] ? s : 0.0) + beta * z[i];
+}
+
+typedef void (*apply_fn)(orc_ctx *, double, const double *, double *);
+
+/* Conjugate gradient (Alg. 2) on A(beta) w = b, w0 = 0, A = apply, vectors of length d.
  * Alg. 2 writes gamma = -<r,r>/<p,q>, w <- w - gamma p, r <- r + gamma q. */
-static int cg_ctx(orc_ctx *c, double beta, const double *b, double rtol, int maxit, double *w, double *r,
-                  double *p, double *q, int *iters_out, double *relres_out) {
-  int64_t d = c->pb->d;
+static int cg_ctx(orc_ctx *c, apply_fn apply, int64_t d, double beta, const double *b, double rtol, int maxit,
+                  double *w, double *r, double *p, double *q, int *iters_out, double *relres_out) {
   double bnorm = sqrt(dot(d, b, b));
   for (int64_t j = 0; j < d; j++) { w[j] = 0.0; r[j] = b[j]; p[j] = b[j]; }
   double rr = dot(d, r, r);
@@ -298,7 +308,7 @@ static int cg_ctx(orc_ctx *c, double beta, const double *b, double rtol, int max
   int it = 0, status = ORC_NOT_CONVERGED;
   if (bnorm == 0.0) status = ORC_OK;
   while (status == ORC_NOT_CONVERGED && it < maxit) {
-    apply_ctx(c, beta, p, q);
+    apply(c, beta, p, q);
     double pq = dot(d, p, q);
     if (!(pq > 0.0) || !isfinite(pq)) { status = ORC_E_BREAKDOWN; break; }
     double gamma = -rr / pq;
@@ -316,7 +326,7 @@ static int cg_ctx(orc_ctx *c, double beta, const double *b, double rtol, int max
     rr = rr_new;
   }
   /* true residual b - A w */
-  apply_ctx(c, beta, w, q);
+  apply(c, beta, w, q);
   for (int64_t j = 0; j < d; j++) r[j] = b[j] - q[j];
   *relres_out = bnorm > 0.0 ? sqrt(dot(d, r, r)) / bnorm : 0.0;
   *iters_out = it;
@@ -340,7 +350,7 @@ int orc_solve(const orc_problem *pb, const double *b, int nshift, const double *
   int worst = ORC_OK;
   for (int s = 0; s < nshift; s++) {
     if (!(betas[s] > 0.0)) { worst = ORC_E_ARG; break; }
-    int st = cg_ctx(&c, betas[s], bb, rtol, maxit, W + (int64_t)s * d, r, p, q, iters + s, relres + s);
+    int st = cg_ctx(&c, apply_ctx, d, betas[s], bb, rtol, maxit, W + (int64_t)s * d, r, p, q, iters + s, relres + s);
     if (st < 0) { worst = st; break; }
     if (st > worst) worst = st;
   }
@@ -353,4 +363,74 @@ int orc_solve(const orc_problem *pb, const double *b, int nshift, const double *
 int orc_project(const orc_problem *pb, const double *W, int nshift, double *S) {
   for (int s = 0; s < nshift; s++) x_mul(pb, W + (int64_t)s * pb->d, S + (int64_t)s * pb->n);
   return ORC_OK;
+}
+
+/* ---- spectral analysis for SDA (Alg. sasda) -------------------------------- */
+
+/* Right-hand side of Alg. sasda in sample space.
+ * r == NULL : g = y_c (canonical; the printed right-hand side is a multiple of it);
+ * r != NULL : r' = r - 1 <1_l, r> / l (step 3), g = [W 0; 0 0] r' (step 4): on a
+ *             labeled row of class c the mean of r' over the labeled rows of class c. */
+int orc_sa_rhs(const orc_problem *pb, const double *r, double *g) {
+  orc_ctx c;
+  int rc = ctx_init(&c, pb);
+  if (rc) return rc;
+  int64_t n = pb->n;
+  if (r == NULL) {
+    memcpy(g, c.ycen, sizeof(double) * (size_t)n);
+  } else {
+    double sl = 0.0;
+    for (int64_t k = 0; k < pb->n_lab; k++) sl += r[pb->lab_idx[k]];
+    for (int64_t i = 0; i < n; i++) c.v[i] = r[i] - sl / (double)pb->n_lab;
+    double sp = 0.0, sn = 0.0;
+    int64_t np = 0, nn = 0;
+    for (int64_t k = 0; k < pb->n_lab; k++) {
+      int32_t i = pb->lab_idx[k];
+      if (pb->lab_y[k] > 0) { sp += c.v[i]; np++; } else { sn += c.v[i]; nn++; }
+    }
+    for (int64_t i = 0; i < n; i++) g[i] = 0.0;
+    for (int64_t k = 0; k < pb->n_lab; k++) {
+      int32_t i = pb->lab_idx[k];
+      g[i] = pb->lab_y[k] > 0 ? sp / (double)np : sn / (double)nn;
+    }
+  }
+  ctx_free(&c);
+  return ORC_OK;
+}
+
+/* q = (Cl^T M + beta I_N) z for one sample-space vector */
+int orc_sa_apply(const orc_problem *pb, double beta, const double *z, double *q) {
+  orc_ctx c;
+  int rc = ctx_init(&c, pb);
+  if (rc) return rc;
+  sa_apply_ctx(&c, beta, z, q);
+  ctx_free(&c);
+  return ORC_OK;
+}
+
+/* Alg. sasda: every shift solved by its own CG in sample space; the ratings are
+ * s = z.  g: [n] (NULL = canonical y_c).  Z: [nshift][n]. */
+int orc_sa_solve(const orc_problem *pb, const double *g, int nshift, const double *betas, double rtol, int maxit,
+                 double *Z, int *iters, double *relres) {
+  orc_ctx c;
+  int rc = ctx_init(&c, pb);
+  if (rc) return rc;
+  int64_t n = pb->n;
+  double *gg = (double *)malloc(sizeof(double) * (size_t)n);
+  if (g) memcpy(gg, g, sizeof(double) * (size_t)n);
+  else memcpy(gg, c.ycen, sizeof(double) * (size_t)n);
+  double *r = (double *)malloc(sizeof(double) * (size_t)n);
+  double *p = (double *)malloc(sizeof(double) * (size_t)n);
+  double *q = (double *)malloc(sizeof(double) * (size_t)n);
+  int worst = ORC_OK;
+  for (int s = 0; s < nshift; s++) {
+    if (!(betas[s] > 0.0)) { worst = ORC_E_ARG; break; }
+    int st = cg_ctx(&c, sa_apply_ctx, n, betas[s], gg, rtol, maxit, Z + (int64_t)s * n, r, p, q, iters + s,
+                    relres + s);
+    if (st < 0) { worst = st; break; }
+    if (st > worst) worst = st;
+  }
+  free(gg); free(r); free(p); free(q);
+  ctx_free(&c);
+  return worst;
 }
