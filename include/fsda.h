@@ -170,6 +170,30 @@ int fsda_multishift_solve(fsda_op *op, const double *b, const double *betas, int
                           int chunk, double *W, int *iters, double *relres, void *stream);
 
 /*
+ * Spectral analysis for SDA (Alg. sasda): the ratings of the samples present
+ * in X come straight from the sample-space system
+ *     (Cl^T M + beta I_N) z = g,   Cl = I_N - 1 1_l^T / l,
+ * M = (1-alpha) P_l + alpha L, solved for every beta by the same shared-basis
+ * recurrence (Alg. 3) over vectors of length n; the rating is s = z.  Cl^T M
+ * is the symmetric centred weight M' (the centring lands on the labeled rows
+ * only), so no X product is involved.  With alpha = 0 the unlabeled ratings
+ * are 0, so alpha > 0 is the useful range (alpha = 0 is not rejected).
+ * Always FP64, whatever the handle's precision.
+ *
+ * fsda_sa_rhs: g[n] (device) = y_c (r == NULL, canonical) or the printed
+ *   right-hand side [W 0; 0 0](r - 1 <1_l, r>/l) for the start vector r[n]
+ *   (device), which for two classes equals ((m+ - m-)/2) y_c, m_c the mean of
+ *   r over the labeled rows of class c.
+ * fsda_sa_solve: g[n] device (NULL = canonical y_c); betas, nshift, rtol,
+ *   maxit, chunk as in fsda_multishift_solve; Z[nshift][n] device FP64 output
+ *   (the ratings); iters, relres host as in fsda_multishift_solve (relres the
+ *   true FP64 residual ||g - (M' + beta_s I) z_s|| / ||g||).  Blocks until done.
+ */
+int fsda_sa_rhs(fsda_op *op, const double *r, double *g, void *stream);
+int fsda_sa_solve(fsda_op *op, const double *g, const double *betas, int nshift, double rtol, int maxit, int chunk,
+                  double *Z, int *iters, double *relres, void *stream);
+
+/*
  * Many targets at once (the shared-basis solve of Sec. 3.2.2 applied to
  * several binary labelings of the same samples, e.g. one per assay): target c
  * has its own labeled set, hence its own centred operator

@@ -70,6 +70,8 @@ def lib():
         L.fsda_project.argtypes = [P, P, I, P, P]
         L.fsda_time_kernel.argtypes = [P, I, I]
         L.fsda_kernel_time.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
+        L.fsda_sa_rhs.argtypes = [P, P, P, P]
+        L.fsda_sa_solve.argtypes = [P, P, P, I, D, I, I, P, P, P, P]
         L.fsda_batch_workspace_size.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_size_t)]
         L.fsda_multishift_solve_batch.argtypes = [P, I, P, P, P, P, I, D, I, I, P, ctypes.c_size_t, P, P, P, P]
         L.fsda_destroy_operator.argtypes = [P]
@@ -78,7 +80,7 @@ def lib():
         L.fsda_last_error.restype = ctypes.c_char_p
         for f in (L.fsda_workspace_size, L.fsda_build_operator, L.fsda_rhs, L.fsda_apply, L.fsda_multishift_solve,
                   L.fsda_project, L.fsda_time_kernel, L.fsda_kernel_time, L.fsda_batch_workspace_size,
-                  L.fsda_multishift_solve_batch):
+                  L.fsda_multishift_solve_batch, L.fsda_sa_rhs, L.fsda_sa_solve):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -187,6 +189,29 @@ class Operator:
                                                 iters.ctypes.data_as(ctypes.c_void_p),
                                                 relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
         return W, iters, relres, rc
+
+    def sa_rhs(self, r=None, stream=None):
+        """Right-hand side of the sample-space solve (Alg. sasda): y_c, or the printed one for start vector r."""
+        import torch
+        g = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(lib().fsda_sa_rhs(self.handle, _ptr(r), _ptr(g), _stream(stream)))
+        return g
+
+    def sa_solve(self, betas: Sequence[float], rtol: float, maxit: int = 100000, chunk: int = 0, g=None,
+                 stream=None):
+        """Ratings of the samples by the sample-space solve (Alg. sasda).
+
+        Returns (Z [S, n] float64 tensor, iters [S] int32, relres [S] float64, status)."""
+        import torch
+        betas = np.ascontiguousarray(betas, dtype=np.float64)
+        S = betas.size
+        Z = torch.empty((S, self.n), dtype=torch.float64, device=self.device)
+        iters = np.zeros(S, dtype=np.int32)
+        relres = np.zeros(S, dtype=np.float64)
+        rc = _check(lib().fsda_sa_solve(self.handle, _ptr(g), betas.ctypes.data_as(ctypes.c_void_p), S, float(rtol),
+                                        int(maxit), int(chunk), _ptr(Z), iters.ctypes.data_as(ctypes.c_void_p),
+                                        relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return Z, iters, relres, rc
 
     def solve_batch(self, labels, betas: Sequence[float], rtol: float, maxit: int = 100000, chunk: int = 0,
                     stream=None):

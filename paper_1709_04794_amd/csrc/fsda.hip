@@ -88,7 +88,8 @@ struct Layout {
   int btile;
   size_t mark, cnt, iota, cnt_sorted, rowid, keys, sort_tmp, sort_bytes;  // union: build
   size_t total;
-  long long ldd;
+  long long ldd;  // d padded: stride of the feature-space vectors of the refinement
+  long long ldv;  // max(d, n) padded: stride of the ring and per-shift directions
   long long nchunk_max, nlong_max;
 };
 
@@ -101,6 +102,8 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
     return at_;
   };
   L->ldd = (d + 63) / 64 * 64;
+  L->ldv = (std::max(d, n) + 63) / 64 * 64;
+  const long long m = std::max(d, n);  // vectors serve both feature-space and sample-space solves
   L->nlong_max = z / LONG_ROW + 1;
   L->nchunk_max = z / CH + L->nlong_max + 1;
   L->st = take(sizeof(State));
@@ -112,9 +115,9 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->t = take(8 * n);
   L->u = take(8 * n);
   L->b = take(8 * d);
-  L->p = take(8 * d);
-  L->q = take(8 * d);
-  L->bu = take(8 * d);
+  L->p = take(8 * m);
+  L->q = take(8 * m);
+  L->bu = take(8 * m);
   L->new2old = take(4 * d);
   L->old2new = take(4 * d);
   L->xcol = take(4 * z);
@@ -134,9 +137,9 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->uni = o;
   size_t u = o;
   L->ring = u;
-  u = a256(u + 8 * (size_t)L->ldd * max_chunk);
+  u = a256(u + 8 * (size_t)L->ldv * max_chunk);
   L->P = u;
-  u = a256(u + 8 * (size_t)L->ldd * max_shifts);
+  u = a256(u + 8 * (size_t)L->ldv * max_shifts);
   size_t solve_end = u;
   // refinement of the mixed path: batched FP32 CG over one column per shift
   // (used after the main solve, so it shares the ring and P space)
@@ -388,48 +391,60 @@ void apply_internal(fsda_op* op, double sigma, const double* p, double* q, hipSt
 
 int stream_grid(long long d) { return grid_for(ceil_div(d, UNR), GRID_STREAM); }
 
+// One iteration of the shared recurrence.  Feature space (FSDA): t = X p,
+// u = M' t, q = X^T u + sigma0 p.  Sample space (Alg. sasda, sa = true):
+// q = M' p + sigma0 p in one pass over S, the centring from the labeled-mean
+// partials of the previous direction update.  Then r and p as usual.
 template <typename V>
-void iteration(fsda_op* op, double sigma0, hipStream_t s, int tag) {
+void iteration(fsda_op* op, double sigma0, bool sa, hipStream_t s, int tag) {
   op->cur_tag = tag;
   V* p = as<V>(op->p);
   V* q = as<V>(op->q);
   V* ring = as<V>(op->ring);
-  product_x<V>(op, p, 1, s);
-  product_lap<V>(op, 1, s);
-  run_xt(op, as<V>(op->u), EpiXT<V, false>{q, p, sigma0}, 1, false, s, KC_XT);
-  const long long d = op->pb.d;
-  const int gs = stream_grid(d);
+  const long long m = sa ? op->pb.n : op->pb.d;
+  const int gs = stream_grid(m);
+  if (sa) {
+    run_rows(op, op->ps, op->p,
+             EpiLapSA{op->p, op->labw, op->pb.s_rowptr, op->q, op->pb.alpha, sigma0, op->part + SITE_X * NPART, gs,
+                      0.0},
+             op->part + SITE_TU * NPART, 1, s, KC_S);
+  } else {
+    product_x<V>(op, p, 1, s);
+    product_lap<V>(op, 1, s);
+    run_xt(op, as<V>(op->u), EpiXT<V, false>{q, p, sigma0}, 1, false, s, KC_XT);
+  }
   launch(op, KC_RESID, s, [&] {
-    hipLaunchKernelGGL(k_resid<V>, dim3(gs), dim3(BS), 0, s, op->st, q, p, ring, op->L.ldd, d, sigma0,
-                       op->part + SITE_TU * NPART, op->ps.grid, op->part + SITE_PP * NPART, gs, op->pxt.nlong,
-                       op->pxt.row_chunk0, op->pxt.w.lpart, op->part + SITE_R * NPART);
+    hipLaunchKernelGGL(k_resid<V>, dim3(gs), dim3(BS), 0, s, op->st, q, p, ring, op->L.ldv, m, sigma0,
+                       op->part + SITE_TU * NPART, op->ps.grid, op->part + SITE_PP * NPART, gs,
+                       sa ? 0 : op->pxt.nlong, op->pxt.row_chunk0, op->pxt.w.lpart, op->part + SITE_R * NPART);
   });
   launch(op, KC_PUPD, s, [&] {
-    hipLaunchKernelGGL(k_pupdate<V>, dim3(gs), dim3(BS), 0, s, op->st, ring, p, op->L.ldd, d,
-                       op->part + SITE_R * NPART, gs, op->hist, op->part + SITE_PP * NPART);
+    hipLaunchKernelGGL(k_pupdate<V>, dim3(gs), dim3(BS), 0, s, op->st, ring, p, op->L.ldv, m,
+                       op->part + SITE_R * NPART, gs, op->hist, op->part + SITE_PP * NPART,
+                       sa ? op->labw : nullptr, op->part + SITE_X * NPART);
   });
   op->cur_tag = -1;
 }
 
 template <typename V>
-void fold(fsda_op* op, double* W, int nshift, int chunk, hipStream_t s) {
-  const long long d = op->pb.d;
+void fold(fsda_op* op, double* W, int nshift, int chunk, bool sa, hipStream_t s) {
+  const long long d = sa ? op->pb.n : op->pb.d;
   const int g = grid_for(d, GRID_FOLD);
   V* ring = as<V>(op->ring);
   V* P = as<V>(op->P);
   launch(op, KC_FOLD, s, [&] {
     if (chunk <= 8)
-      hipLaunchKernelGGL((k_fold<8, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldd, W, d, P,
-                         op->L.ldd, nshift);
+      hipLaunchKernelGGL((k_fold<8, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldv, W, d, P,
+                         op->L.ldv, nshift);
     else if (chunk <= 16)
-      hipLaunchKernelGGL((k_fold<16, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldd, W, d, P,
-                         op->L.ldd, nshift);
+      hipLaunchKernelGGL((k_fold<16, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldv, W, d, P,
+                         op->L.ldv, nshift);
     else if (chunk <= 32)
-      hipLaunchKernelGGL((k_fold<32, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldd, W, d, P,
-                         op->L.ldd, nshift);
+      hipLaunchKernelGGL((k_fold<32, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldv, W, d, P,
+                         op->L.ldv, nshift);
     else
-      hipLaunchKernelGGL((k_fold<64, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldd, W, d, P,
-                         op->L.ldd, nshift);
+      hipLaunchKernelGGL((k_fold<64, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldv, W, d, P,
+                         op->L.ldv, nshift);
   });
   hipLaunchKernelGGL(k_fold_done, dim3(1), dim3(1), 0, s, op->st);
 }
@@ -577,8 +592,8 @@ int make_xt(fsda_op* op, hipStream_t s) {
 // the iterates.
 template <typename V>
 int run_multishift(fsda_op* op, const double* rhs, const double* betas, double sigma0, int nshift, double rtol,
-                   int maxit, int chunk, double* W, hipStream_t s) {
-  const long long d = op->pb.d;
+                   int maxit, int chunk, double* W, hipStream_t s, bool sa = false) {
+  const long long d = sa ? op->pb.n : op->pb.d;
   State* h = op->hst;
   std::memset(h, 0, sizeof(State));
   h->nshift = nshift;
@@ -596,19 +611,20 @@ int run_multishift(fsda_op* op, const double* rhs, const double* betas, double s
   HIP_TRY(hipMemcpyAsync(op->st, h, sizeof(State), hipMemcpyHostToDevice, s));
   const int gi = stream_grid(d);
   hipLaunchKernelGGL(k_init<V>, dim3(gi), dim3(BS), 0, s, rhs, as<V>(op->ring), as<V>(op->p), as<V>(op->P),
-                     op->L.ldd, W, d, nshift, op->part + SITE_PP * NPART);
+                     op->L.ldv, W, d, nshift, op->part + SITE_PP * NPART, sa ? op->labw : nullptr,
+                     op->part + SITE_X * NPART);
   hipLaunchKernelGGL(k_init_done, dim3(1), dim3(BS), 0, s, op->st, op->part + SITE_PP * NPART, gi);
   HIP_TRY(hipGetLastError());
 
   bool graph = op->use_graph != 0 && !op->tk_on;
   if (graph) {
-    const GraphKey key{W, rhs, nshift, chunk, (int)sizeof(V), sigma0};
+    const GraphKey key{W, rhs, nshift, chunk, (int)sizeof(V) + (sa ? 100 : 0), sigma0};
     if (!op->gexec || !(op->gkey == key)) {
       drop_graph(op);
       hipGraph_t gr = nullptr;
       HIP_TRY(hipStreamBeginCapture(op->cap, hipStreamCaptureModeThreadLocal));
-      for (int j = 0; j < chunk; j++) iteration<V>(op, sigma0, op->cap, j);
-      fold<V>(op, W, nshift, chunk, op->cap);
+      for (int j = 0; j < chunk; j++) iteration<V>(op, sigma0, sa, op->cap, j);
+      fold<V>(op, W, nshift, chunk, sa, op->cap);
       const hipError_t ce = hipStreamEndCapture(op->cap, &gr);
       hipError_t ie = hipErrorUnknown;
       if (ce == hipSuccess) {
@@ -631,8 +647,8 @@ int run_multishift(fsda_op* op, const double* rhs, const double* betas, double s
     if (graph) {
       HIP_TRY(hipGraphLaunch(op->gexec, s));
     } else {
-      for (int j = 0; j < chunk; j++) iteration<V>(op, sigma0, s, j);
-      fold<V>(op, W, nshift, chunk, s);
+      for (int j = 0; j < chunk; j++) iteration<V>(op, sigma0, sa, s, j);
+      fold<V>(op, W, nshift, chunk, sa, s);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(h) + off, reinterpret_cast<char*>(op->st) + off, 4 * sizeof(int),
@@ -660,6 +676,22 @@ int residuals(fsda_op* op, const double* rhs, const double* betas, int nshift, c
     run_xt(op, op->u, EpiRes{rhs, w, betas[k], out ? out + (long long)k * ldo : nullptr}, 0, true, s, KC_OTHER);
     hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, op->part + SITE_XT * NPART, xt_npart(op),
                        &op->st->res2[k]);
+  }
+  HIP_TRY(hipGetLastError());
+  return FSDA_OK;
+}
+
+// True residuals ||g - (M' + beta_k) z_k||^2 of the sample-space solve into st->res2[k].
+int residuals_sa(fsda_op* op, const double* g, const double* betas, int nshift, const double* Z, hipStream_t s) {
+  const long long n = op->pb.n;
+  const int gw = stream_grid(n);
+  for (int k = 0; k < nshift; k++) {
+    const double* z = Z + (long long)k * n;
+    hipLaunchKernelGGL(k_wsum, dim3(gw), dim3(BS), 0, s, op->labw, z, n, op->part + SITE_X * NPART);
+    run_rows(op, op->ps, z,
+             EpiResSA{g, z, op->labw, op->pb.s_rowptr, op->pb.alpha, betas[k], op->part + SITE_X * NPART, gw, 0.0},
+             op->part + SITE_XT * NPART, 0, s, KC_OTHER);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, op->part + SITE_XT * NPART, op->ps.grid, &op->st->res2[k]);
   }
   HIP_TRY(hipGetLastError());
   return FSDA_OK;
@@ -1531,6 +1563,57 @@ int fsda_multishift_solve(fsda_op* op, const double* b, const double* betas, int
     for (int k = 0; k < nshift; k++) ok = ok && relres[k] <= rtol;
     return ok ? FSDA_OK : FSDA_NOT_CONVERGED;
   }
+  return h->status == FSDA_NOT_CONVERGED ? FSDA_NOT_CONVERGED : FSDA_OK;
+}
+
+int fsda_sa_rhs(fsda_op* op, const double* r, double* g, void* stream) {
+  if (!op || !g) return fail(FSDA_E_ARG, "NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long n = op->pb.n;
+  if (!r) {
+    HIP_TRY(hipMemcpyAsync(g, op->ycen, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  } else {  // ((m+ - m-)/2) y_c with m+ - m- = sum_i z_i r_i, z = 1+/N+ - 1-/N-
+    const int gw = stream_grid(n);
+    hipLaunchKernelGGL(k_wsum, dim3(gw), dim3(BS), 0, s, op->zw, r, n, op->part + SITE_X * NPART);
+    hipLaunchKernelGGL(k_scaled_d, dim3(grid_for(n, 2048)), dim3(BS), 0, s, op->ycen, g, n,
+                       op->part + SITE_X * NPART, gw, 0.5);
+  }
+  HIP_TRY(hipGetLastError());
+  return FSDA_OK;
+}
+
+int fsda_sa_solve(fsda_op* op, const double* g, const double* betas, int nshift, double rtol, int maxit, int chunk,
+                  double* Z, int* iters, double* relres, void* stream) {
+  if (!op || !betas || !Z || !iters || !relres) return fail(FSDA_E_ARG, "NULL argument");
+  if (nshift < 1 || nshift > op->max_shifts) return fail(FSDA_E_ARG, "nshift outside 1..max_shifts");
+  if (!(rtol > 0.0)) return fail(FSDA_E_RANGE, "rtol must be > 0");
+  if (maxit < 1) return fail(FSDA_E_RANGE, "maxit must be >= 1");
+  if (chunk < 0) return fail(FSDA_E_RANGE, "chunk must be >= 0");
+  if (chunk == 0) chunk = 32;
+  chunk = std::min(chunk, op->max_chunk);
+  while (chunk > 1 && chunk * nshift > MAXCHUNK * MAXS / 2) chunk >>= 1;
+  double sigma0 = betas[0];
+  for (int k = 0; k < nshift; k++) {
+    if (!(betas[k] > 0.0) || !std::isfinite(betas[k])) return fail(FSDA_E_RANGE, "every beta must be finite and > 0");
+    sigma0 = std::min(sigma0, betas[k]);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const double* rhs = g ? g : op->ycen;
+  int rc = run_multishift<double>(op, rhs, betas, sigma0, nshift, rtol, maxit, chunk, Z, s, true);
+  if (rc) return rc;
+  if ((rc = residuals_sa(op, rhs, betas, nshift, Z, s))) return rc;
+  State* h = op->hst;
+  HIP_TRY(hipMemcpyAsync(h, op->st, sizeof(State), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (op->tk_on) {
+    const int trc = tk_flush(op, 1 << 30);
+    if (trc) return trc;
+  }
+  for (int k = 0; k < nshift; k++) {
+    iters[k] = h->conv[k];
+    relres[k] = h->bnorm > 0.0 ? std::sqrt(h->res2[k]) / h->bnorm : 0.0;
+  }
+  if (h->status == FSDA_E_BREAKDOWN) return fail(FSDA_E_BREAKDOWN, "CG breakdown: <p, A p> <= 0 or not finite");
   return h->status == FSDA_NOT_CONVERGED ? FSDA_NOT_CONVERGED : FSDA_OK;
 }
 

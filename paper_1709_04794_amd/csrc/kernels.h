@@ -259,6 +259,63 @@ struct EpiRes {
   }
 };
 
+// Spectral analysis (Alg. sasda) works in sample space with the identity in
+// place of X: q = M' p + sigma p, where the centring uses the labeled mean of p
+// (the sum of the partials the previous direction update wrote).  Reduction
+// <p, M' p>, which with sigma <p, p> gives <p, q>.
+struct EpiLapSA {
+  using V = double;
+  const double* p;
+  const double* labw;
+  const int* srowptr;
+  double* q;
+  double alpha, sigma;
+  const double* cpart;
+  int ncpart;
+  double c;
+  static constexpr bool kReduce = true;
+  __device__ void prepare(const State*) { c = sum_partials(cpart, ncpart); }
+  __device__ double row(int r, double v) const {
+    const double pr = p[r];
+    double x = alpha * ((double)(srowptr[r + 1] - srowptr[r]) * pr - v);
+    if (labw[r] != 0.0) x += (1.0 - alpha) * (pr - c);
+    q[r] = x + sigma * pr;
+    return pr * x;
+  }
+};
+
+// True residual of one shift of the spectral-analysis system:
+// R = g - (M' z + beta z); reduction ||R||^2.
+struct EpiResSA {
+  using V = double;
+  const double* g;
+  const double* z;
+  const double* labw;
+  const int* srowptr;
+  double alpha, beta;
+  const double* cpart;
+  int ncpart;
+  double c;
+  static constexpr bool kReduce = true;
+  __device__ void prepare(const State*) { c = sum_partials(cpart, ncpart); }
+  __device__ double row(int r, double v) const {
+    const double zr = z[r];
+    double x = alpha * ((double)(srowptr[r + 1] - srowptr[r]) * zr - v);
+    if (labw[r] != 0.0) x += (1.0 - alpha) * (zr - c);
+    const double R = g[r] - (x + beta * zr);
+    return R * R;
+  }
+};
+
+// partials of sum_j w_j v_j (the labeled mean when w = 1/l on labeled rows)
+__global__ __launch_bounds__(BS) void k_wsum(const double* __restrict__ w, const double* __restrict__ v, long long n,
+                                             double* part) {
+  double acc = 0.0;
+  for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < n; j += (long long)gridDim.x * BS)
+    acc += w[j] * v[j];
+  write_partial(part, blockIdx.x, acc);
+}
+
 // ---------------------------------------------------------------------------
 // sparse products, lanes per row
 // ---------------------------------------------------------------------------
@@ -440,10 +497,12 @@ __global__ __launch_bounds__(BS) void k_assemble(int nlong, const int* row_chunk
 
 // r_0 = b (ring slot 0), p_0 = b, P_s = b, W_s = 0; partials of <b, b> (also
 // the first <p, p>).  Launched with the grid of k_pupdate.
+// With labw (sample-space solves), also partials of sum_j labw_j p_j into lpart.
 template <typename V>
 __global__ __launch_bounds__(BS) void k_init(const double* __restrict__ b, V* ring, V* p, V* P, long long ldp, double* W,
-                                             long long d, int nshift, double* part) {
-  double acc = 0.0;
+                                             long long d, int nshift, double* part, const double* labw,
+                                             double* lpart) {
+  double acc = 0.0, lac = 0.0;
   for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
     const V x = (V)b[j];
     ring[j] = x;
@@ -453,8 +512,10 @@ __global__ __launch_bounds__(BS) void k_init(const double* __restrict__ b, V* ri
       W[s * d + j] = 0.0;
     }
     acc += (double)x * (double)x;
+    if (labw) lac += labw[j] * (double)x;
   }
   write_partial(part, blockIdx.x, acc);
+  if (labw) write_partial(lpart, blockIdx.x, lac);
 }
 
 // rr = <b,b>, tol = rtol ||b||; a zero right-hand side stops at once.  One block.
@@ -546,11 +607,13 @@ __global__ __launch_bounds__(BS) void k_resid(State* st, const V* __restrict__ q
 }
 
 // K5: b_{i+1} = <r_{i+1},r_{i+1}>/<r_i,r_i>; p_{i+1} = r_{i+1} + b_{i+1} p_i, with
-// partials of <p_{i+1}, p_{i+1}>.  The last block runs the per-shift scalar
+// partials of <p_{i+1}, p_{i+1}> (and, with labw, of sum_j labw_j p_j for the
+// next sample-space centring).  The last block runs the per-shift scalar
 // updates and the stop test.
 template <typename V>
 __global__ __launch_bounds__(BS) void k_pupdate(State* st, const V* ring, V* p, long long ldd, long long d,
-                                                const double* rr_part, int nrr, double* hist, double* pp_part) {
+                                                const double* rr_part, int nrr, double* hist, double* pp_part,
+                                                const double* labw, double* lpart) {
   if (st->stop) return;
   const int i = st->iter;
   const V* r = ring + (long long)((i + 1) % st->chunk) * ldd;
@@ -565,7 +628,7 @@ __global__ __launch_bounds__(BS) void k_pupdate(State* st, const V* ring, V* p, 
   }
   const double rrn = sum_partials(rr_part, nrr);
   const double b = rrn / st->rr;
-  double acc = 0.0;
+  double acc = 0.0, lac = 0.0;
   for (;;) {
 #pragma unroll
     for (int u = 0; u < UNR; u++) {
@@ -573,6 +636,7 @@ __global__ __launch_bounds__(BS) void k_pupdate(State* st, const V* ring, V* p, 
       const V x = (V)(rv[u] + b * pv[u]);
       if (j < d) p[j] = x;
       acc += j < d ? (double)x * (double)x : 0.0;
+      if (labw && j < d) lac += labw[j] * (double)x;
     }
     j0 += step;
     if (j0 >= d) break;
@@ -584,6 +648,7 @@ __global__ __launch_bounds__(BS) void k_pupdate(State* st, const V* ring, V* p, 
     }
   }
   write_partial(pp_part, blockIdx.x, acc);
+  if (labw) write_partial(lpart, blockIdx.x, lac);
   if (last_block(&st->ticket[1])) {
     resid_scalars(st, rrn, b, hist);
     if (threadIdx.x == 0) st->ticket[1] = 0;
@@ -673,6 +738,12 @@ __global__ __launch_bounds__(BS) void k_gather_scaled_d(const double* __restrict
                                                         double f) {
   const double c = f * sum_partials(part, np);
   FSDA_GRID_LOOP(j, n) dst[j] = c * src[map[j]];
+}
+// dst[j] = f * sum(partials) * src[j]
+__global__ __launch_bounds__(BS) void k_scaled_d(const double* __restrict__ src, double* dst, long long n,
+                                                 const double* part, int np, double f) {
+  const double c = f * sum_partials(part, np);
+  FSDA_GRID_LOOP(j, n) dst[j] = c * src[j];
 }
 __global__ void k_gather_i(const int* __restrict__ src, const int* __restrict__ map, int* dst, long long n) {
   FSDA_GRID_LOOP(j, n) dst[j] = map[src[j]];

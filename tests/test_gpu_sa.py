@@ -1,0 +1,97 @@
+"""Sample-space solve (Alg. sasda, fsda_sa_solve) vs the CPU oracle's per-shift CG."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+fsda = pytest.importorskip("paper_1709_04794_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return synth.workload("tiny")
+
+
+def test_sa_rhs(tiny):
+    op = fsda.Operator.from_problem(tiny, alpha=0.5)
+    g = op.sa_rhs().cpu().numpy()
+    assert np.array_equal(g, oracle.sa_rhs(tiny))
+    r = synth.uniform(tiny.n, -1.0, 1.0, seed=4, stream=2)
+    gl = op.sa_rhs(torch.from_numpy(r).cuda()).cpu().numpy()
+    ref = oracle.sa_rhs(tiny, r)
+    assert np.abs(gl - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.5, 0.25])
+def test_sa_solve_matches_oracle(tiny, alpha):
+    op = fsda.Operator.from_problem(tiny, alpha=alpha)
+    Z, iters, relres, st = op.sa_solve(tiny.betas, rtol=1e-10)
+    assert st == fsda.OK
+    Zr, *_ = oracle.sa_solve(tiny, rtol=1e-13, maxit=50000, alpha=alpha)
+    Z = Z.cpu().numpy()
+    g = oracle.sa_rhs(tiny)
+    for s, beta in enumerate(tiny.betas):
+        assert relerr(Z[s], Zr[s]) < 1e-6, (s, relerr(Z[s], Zr[s]))
+        assert relres[s] < 20 * 1e-10
+        ref = np.linalg.norm(g - oracle.sa_apply(tiny, beta, Z[s], alpha=alpha)) / np.linalg.norm(g)
+        assert abs(relres[s] - ref) <= 1e-3 * ref + 1e-15
+        assert abs(Z[s].sum()) < 1e-8 * np.abs(Z[s]).sum()  # the all-ones direction stays out
+    assert iters.max() == iters[np.argmin(tiny.betas)]
+
+
+def test_sa_alpha0_unlabeled_ratings_are_zero(tiny):
+    op = fsda.Operator.from_problem(tiny, alpha=0.0)
+    Z, iters, relres, st = op.sa_solve(tiny.betas, rtol=1e-12)
+    Z = Z.cpu().numpy()
+    unl = np.setdiff1d(np.arange(tiny.n), tiny.lab_idx)
+    assert np.all(Z[:, unl] == 0.0)
+    g = oracle.sa_rhs(tiny)
+    for s, beta in enumerate(tiny.betas):
+        assert np.allclose(Z[s, tiny.lab_idx], g[tiny.lab_idx] / (1.0 + beta), rtol=1e-10, atol=0)
+
+
+def test_sa_equals_feature_space_path_with_identity_data():
+    pb = synth.small_problem(n=900, d=500, mean_nnz=6, k=4, alpha=0.6, seed=3, n_lab=120)
+    ident = dataclasses.replace(pb, d=pb.n, x_rowptr=np.arange(pb.n + 1, dtype=np.int32),
+                                x_col=np.arange(pb.n, dtype=np.int32))
+    Z, *_ = fsda.Operator.from_problem(pb).sa_solve(pb.betas, rtol=1e-12)
+    W, *_ = fsda.Operator.from_problem(ident).solve(pb.betas, rtol=1e-12)
+    for s in range(pb.betas.size):
+        assert relerr(Z[s].cpu().numpy(), W[s].cpu().numpy()) < 1e-9
+
+
+@pytest.mark.parametrize("chunk", [1, 5, 32])
+def test_sa_chunk_bits_and_graph(tiny, chunk, monkeypatch):
+    op = fsda.Operator.from_problem(tiny, alpha=0.5)
+    ref, it0, _, _ = op.sa_solve(tiny.betas, rtol=1e-9, chunk=16)
+    Z, it1, _, _ = op.sa_solve(tiny.betas, rtol=1e-9, chunk=chunk)
+    assert torch.equal(Z, ref) and np.array_equal(it0, it1)
+    monkeypatch.setenv("FSDA_NO_GRAPH", "1")
+    opd = fsda.Operator.from_problem(tiny, alpha=0.5)
+    monkeypatch.delenv("FSDA_NO_GRAPH")
+    Zd, itd, _, _ = opd.sa_solve(tiny.betas, rtol=1e-9, chunk=chunk)
+    assert torch.equal(Zd, ref)
+
+
+def test_sa_ragged_and_user_rhs():
+    for seed, (n, d, nnz) in enumerate([(300, 50, 9), (77, 40, 3), (1500, 70, 5)]):
+        pb = synth.small_problem(n=n, d=d, mean_nnz=nnz, k=2, alpha=0.7, seed=seed, betas=(1e-3, 0.05, 2.0, 40.0),
+                                 n_lab=max(4, n // 10))
+        op = fsda.Operator.from_problem(pb)
+        r = synth.uniform(pb.n, -1.0, 1.0, seed=seed, stream=3)
+        g = op.sa_rhs(torch.from_numpy(r).cuda())
+        Z, iters, relres, st = op.sa_solve(pb.betas, rtol=1e-11, g=g)
+        assert st == fsda.OK
+        Zr, *_ = oracle.sa_solve(pb, rtol=1e-13, maxit=50000, g=oracle.sa_rhs(pb, r))
+        for s in range(pb.betas.size):
+            assert relerr(Z[s].cpu().numpy(), Zr[s]) < 1e-6, (seed, s)
