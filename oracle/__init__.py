@@ -12,6 +12,8 @@ Contents
   * the same file's spectral-analysis variant (Alg. sasda; :func:`sa_solve`,
     :func:`sa_apply`, :func:`sa_rhs`): per-shift CG in sample space on
     Cl^T M + beta I_N, the ratings being the solution itself.
+  * the regression phase of the spectral-regression variants (:func:`reg_solve`):
+    per-shift CG on (X^T X + beta I) w = X^T z.
   * :mod:`oracle.dense`: dense NumPy/SciPy forms (Cholesky of the operator,
     sample-space push-through, labeled-only dual ridge) used to pin the above.
   * :mod:`oracle.shifted`: the paper's shifted CG (Alg. 3) in NumPy, for the
@@ -72,8 +74,9 @@ def _load():
         lib.orc_sa_rhs.argtypes = [pp, P, P]
         lib.orc_sa_apply.argtypes = [pp, ctypes.c_double, P, P]
         lib.orc_sa_solve.argtypes = [pp, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P, P, P]
+        lib.orc_reg_solve.argtypes = [pp, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P, P, P]
         for f in (lib.orc_mean_labeled, lib.orc_apply, lib.orc_m_apply, lib.orc_xct, lib.orc_rhs,
-                  lib.orc_solve, lib.orc_project, lib.orc_sa_rhs, lib.orc_sa_apply, lib.orc_sa_solve):
+                  lib.orc_solve, lib.orc_project, lib.orc_sa_rhs, lib.orc_sa_apply, lib.orc_sa_solve, lib.orc_reg_solve):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -218,3 +221,17 @@ def sa_solve(pb, betas=None, rtol: float = 1e-12, maxit: int = 100000, g: np.nda
     rc = _load().orc_sa_solve(bnd.ref, _p(gg), S, _p(betas), float(rtol), int(maxit), _p(Z), _p(iters), _p(relres))
     _check(rc, "sa_solve")
     return Z, iters, relres, rc
+
+
+def reg_solve(pb, z: np.ndarray, betas, rtol: float = 1e-12, maxit: int = 100000):
+    """Regression phase: (X^T X + beta I) w = X^T z per shift.  Returns (W [S, d], iters, relres, status)."""
+    bnd = _Bound(pb)
+    betas = np.ascontiguousarray(betas, dtype=np.float64)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    S = betas.size
+    W = np.zeros((S, pb.d))
+    iters = np.zeros(S, dtype=np.int32)
+    relres = np.zeros(S)
+    rc = _load().orc_reg_solve(bnd.ref, _p(z), S, _p(betas), float(rtol), int(maxit), _p(W), _p(iters), _p(relres))
+    _check(rc, "reg_solve")
+    return W, iters, relres, rc

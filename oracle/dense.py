@@ -140,3 +140,17 @@ def sa_rhs(pb, r=None) -> np.ndarray:
 
 def sa_solve_dense(pb, beta: float, g=None, alpha=None) -> np.ndarray:
     return np.linalg.solve(sa_operator(pb, beta, alpha), sa_rhs(pb) if g is None else g)
+
+
+# ---- regression phase (Alg. optimizedSR, step 5) ---------------------------
+
+def reg_solve_dense(pb, beta: float, z) -> np.ndarray:
+    """LU of X^T X + beta I against X^T z."""
+    X = dense_x(pb)
+    return np.linalg.solve(X.T @ X + beta * np.eye(pb.d), X.T @ z)
+
+
+def reg_solve_svd(pb, beta: float, z) -> np.ndarray:
+    """Through the thin SVD X = U diag(s) V^T: w = V diag(s / (s^2 + beta)) U^T z."""
+    U, sv, Vt = np.linalg.svd(dense_x(pb), full_matrices=False)
+    return Vt.T @ ((sv / (sv * sv + beta)) * (U.T @ z))

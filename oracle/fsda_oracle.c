@@ -434,3 +434,39 @@ int orc_sa_solve(const orc_problem *pb, const double *g, int nshift, const doubl
   ctx_free(&c);
   return worst;
 }
+
+/* ---- regression phase of the spectral-regression variants ----------------- */
+
+/* q = (X^T X + beta I_D) p: the regularised least-squares operator of the
+ * regression step (Alg. optimizedSR, step 5), no graph and no centring. */
+static void reg_apply_ctx(orc_ctx *c, double beta, const double *p, double *q) {
+  x_mul(c->pb, p, c->v);
+  xt_mul(c, c->v, q);
+  for (int64_t j = 0; j < c->pb->d; j++) q[j] += beta * p[j];
+}
+
+/* (X^T X + beta I) w = X^T z for every beta, one CG per shift.  z: [n] sample
+ * space; W: [nshift][d]. */
+int orc_reg_solve(const orc_problem *pb, const double *z, int nshift, const double *betas, double rtol, int maxit,
+                  double *W, int *iters, double *relres) {
+  orc_ctx c;
+  int rc = ctx_init(&c, pb);
+  if (rc) return rc;
+  int64_t d = pb->d;
+  double *b = (double *)malloc(sizeof(double) * (size_t)d);
+  xt_mul(&c, z, b);
+  double *r = (double *)malloc(sizeof(double) * (size_t)d);
+  double *p = (double *)malloc(sizeof(double) * (size_t)d);
+  double *q = (double *)malloc(sizeof(double) * (size_t)d);
+  int worst = ORC_OK;
+  for (int s = 0; s < nshift; s++) {
+    if (!(betas[s] > 0.0)) { worst = ORC_E_ARG; break; }
+    int st = cg_ctx(&c, reg_apply_ctx, d, betas[s], b, rtol, maxit, W + (int64_t)s * d, r, p, q, iters + s,
+                    relres + s);
+    if (st < 0) { worst = st; break; }
+    if (st > worst) worst = st;
+  }
+  free(b); free(r); free(p); free(q);
+  ctx_free(&c);
+  return worst;
+}
