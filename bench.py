@@ -7,6 +7,13 @@ every shift.  The operator build (X^T, tiles, labels) happens once before the
 timed region, as does input generation.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload mid] [--chunk 32]
+
+The default run also times, once each and outside the headline, the other
+entry points on the same workload (detail.paths): the mixed-precision solve,
+a batch of 16 targets, and the sample-space solve.  A separate mode replays
+the paper's CG versus shifted CG table on a matrix of the ChEMBL shape:
+
+    python bench.py --experiment shifted-table
 """
 from __future__ import annotations
 
@@ -97,6 +104,84 @@ def cpu_baseline(pb, budget_s: float):
                       % (pb.name, len(sample), pb.betas.size, pb.rtol, json.dumps(sample))}
 
 
+def time_paths(pb, fsda, torch, chunk: int):
+    """One warm and one timed call of each further entry point on the workload."""
+    import synth
+    out = {}
+    S = pb.betas.size
+
+    def timed(fn, reps=1):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, r
+
+    op_m = fsda.Operator.from_problem(pb, precision=fsda.MIXED, max_chunk=chunk)
+    dt, (W, it, rel, st) = timed(lambda: op_m.solve(pb.betas, rtol=pb.rtol, chunk=chunk))
+    out["mixed"] = {"seconds": round(dt, 4), "solves_per_s": round(int((rel <= TARGET_RELRES).sum()) / dt, 3),
+                    "worst_relres": float(rel.max()), "iters": it.tolist(), "status": st,
+                    "what": "FP32 shared recurrence to 1e-5, then FP64 residuals and batched FP32 correction "
+                            "solves, every shift to rel. residual %.0e" % pb.rtol}
+    op_m.close()
+    del op_m
+    op = fsda.Operator.from_problem(pb, max_chunk=chunk)
+    labs = synth.target_labels(pb, 16, seed=1)
+    dt, (W, it, rel, st) = timed(lambda: op.solve_batch(labs, pb.betas, rtol=pb.rtol, chunk=chunk))
+    out["batched_targets"] = {"targets": len(labs), "seconds": round(dt, 4),
+                              "shifted_solves_per_s": round(int((rel <= TARGET_RELRES).sum()) / dt, 3),
+                              "worst_relres": float(rel.max()), "max_iters": int(it.max()), "status": st,
+                              "what": "16 labelings (labeled fraction lognormal around 0.7%%, positive rate "
+                                      "U(0.02, 0.3)) x %d shifts, FP64, to rel. residual %.0e" % (S, pb.rtol)}
+    del W
+    dt, (Z, it, rel, st) = timed(lambda: op.sa_solve(pb.betas, rtol=pb.rtol, chunk=chunk), reps=3)
+    out["sample_space"] = {"seconds": round(dt, 5), "solves_per_s": round(int((rel <= TARGET_RELRES).sum()) / dt, 3),
+                           "worst_relres": float(rel.max()), "max_iters": int(it.max()), "status": st,
+                           "what": "Alg. sasda ratings for every shift, FP64, to rel. residual %.0e" % pb.rtol}
+    op.close()
+    return out
+
+
+SHIFTED_TABLE = [  # (betas, CG seconds, shifted CG seconds, speed-up) as printed in Table tab:shifted
+    (tuple(10.0 ** np.arange(-9, 3)), 43.11, 6.02, 7.16),
+    (tuple(np.round(np.arange(1.0, 2.15, 0.1), 1) * 1e-6), 50.98, 5.68, 8.98),
+]
+
+
+def shifted_table(args, fsda, torch):
+    """CG per shift versus the shared-basis recurrence on (X^T X + beta I) w = X^T z, tolerance 1e-3."""
+    import synth
+    t0 = time.perf_counter()
+    pb = synth.workload("chembl", seed=args.seed, cache_dir=args.cache)
+    log("chembl-shaped matrix in %.1fs: %s" % (time.perf_counter() - t0, pb.summary()))
+    op = fsda.Operator.from_problem(pb, max_shifts=12, max_chunk=args.chunk)
+    z = op.sa_rhs()  # the centred labels y_c as the regressed sample-space vector
+    rows = []
+    for betas, p_cg, p_sh, p_sp in SHIFTED_TABLE:
+        res = {}
+        for shared in (True, False):
+            op.regression_solve(z, betas, rtol=pb.rtol, chunk=args.chunk, shared_basis=shared)  # warm
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            W, it, rel, st = op.regression_solve(z, betas, rtol=pb.rtol, chunk=args.chunk, shared_basis=shared)
+            torch.cuda.synchronize()
+            res[shared] = (time.perf_counter() - t1, it, rel, st)
+        cg_s, sh_s = res[False][0], res[True][0]
+        rows.append({"betas": list(betas), "cg_s": round(cg_s, 4), "shifted_s": round(sh_s, 4),
+                     "speedup": round(cg_s / sh_s, 3), "iters_cg": res[False][1].tolist(),
+                     "iters_shifted": res[True][1].tolist(),
+                     "worst_relres": max(float(res[False][2].max()), float(res[True][2].max())),
+                     "paper": {"cg_s": p_cg, "shifted_s": p_sh, "speedup": p_sp}})
+        log("table row: CG %.3fs shifted %.3fs speed-up %.2f (paper %.2f)" % (cg_s, sh_s, cg_s / sh_s, p_sp))
+    print(json.dumps({"experiment": "shifted-table", "unit": "s", "tolerance": pb.rtol,
+                      "workload": "chembl-shaped: n=%d x d=%d binary, nnz_X=%d, Zipf %.1f feature popularity; "
+                                  "regressed vector y_c of %d labeled rows"
+                                  % (pb.n, pb.d, pb.x_nnz, 1.1, pb.lab_idx.size),
+                      "rows": rows}), flush=True)
+
+
 def summarize_rocprof(d: str, kernel_substr: str, calib_mib: int) -> str:
     """Condenses rocprofv3 CSV output in directory d into a few lines of text.
 
@@ -151,6 +236,8 @@ def main():
                     help="first run a plain device copy of this many MiB (profiler calibration of byte counters)")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="extra timed steps with kernel timing off (chunks replayed as HIP graphs), reported in detail")
+    ap.add_argument("--no-paths", action="store_true", help="skip timing the further entry points (detail.paths)")
+    ap.add_argument("--experiment", default="", help="'shifted-table': the CG versus shifted CG table instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -159,6 +246,13 @@ def main():
     import torch
     import synth
     import paper_1709_04794_amd as fsda
+
+    if args.experiment == "shifted-table":
+        shifted_table(args, fsda, torch)
+        return
+    if args.experiment:
+        print("unknown experiment %r" % args.experiment, file=sys.stderr)
+        sys.exit(2)
 
     if args.calib_copy_mb > 0:
         nb = args.calib_copy_mb << 20
@@ -269,6 +363,12 @@ def main():
                    "per_kernel_ms_per_step": {KNAMES[k]: round(v[0], 3) for k, v in per_class.items()},
                    "per_kernel_launches_per_step": {KNAMES[k]: v[1] for k, v in per_class.items()}},
     }
+    if not args.no_paths:
+        t0 = time.perf_counter()
+        op.close()
+        del op
+        out["detail"]["paths"] = time_paths(pb, fsda, torch, args.chunk)
+        log("further entry points timed in %.1fs" % (time.perf_counter() - t0))
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(pb, args.cpu_budget)

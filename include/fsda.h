@@ -194,6 +194,20 @@ int fsda_sa_solve(fsda_op *op, const double *g, const double *betas, int nshift,
                   double *Z, int *iters, double *relres, void *stream);
 
 /*
+ * Regression phase of the spectral-regression variants (Alg. optimizedSR,
+ * step 5; Alg. SR, step 6): (X^T X + beta I_D) w = X^T z for every beta, z[n]
+ * a sample-space vector (device, e.g. the ratings of fsda_sa_solve).  No
+ * graph, no centring, no labels (the handle's are not used).  shared_basis
+ * != 0: one recurrence for all shifts (Alg. 3); 0: an independent CG per
+ * shift (the baseline of Table tab:shifted), each stopping at its own rtol.
+ * betas, nshift, rtol, maxit, chunk, W[nshift][d], iters, relres as in
+ * fsda_multishift_solve (relres relative to ||X^T z||).  Always FP64.
+ * Blocks until done.
+ */
+int fsda_regression_solve(fsda_op *op, const double *z, const double *betas, int nshift, double rtol, int maxit,
+                          int chunk, int shared_basis, double *W, int *iters, double *relres, void *stream);
+
+/*
  * Many targets at once (the shared-basis solve of Sec. 3.2.2 applied to
  * several binary labelings of the same samples, e.g. one per assay): target c
  * has its own labeled set, hence its own centred operator

@@ -72,6 +72,7 @@ def lib():
         L.fsda_kernel_time.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
         L.fsda_sa_rhs.argtypes = [P, P, P, P]
         L.fsda_sa_solve.argtypes = [P, P, P, I, D, I, I, P, P, P, P]
+        L.fsda_regression_solve.argtypes = [P, P, P, I, D, I, I, I, P, P, P, P]
         L.fsda_batch_workspace_size.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_size_t)]
         L.fsda_multishift_solve_batch.argtypes = [P, I, P, P, P, P, I, D, I, I, P, ctypes.c_size_t, P, P, P, P]
         L.fsda_destroy_operator.argtypes = [P]
@@ -80,7 +81,7 @@ def lib():
         L.fsda_last_error.restype = ctypes.c_char_p
         for f in (L.fsda_workspace_size, L.fsda_build_operator, L.fsda_rhs, L.fsda_apply, L.fsda_multishift_solve,
                   L.fsda_project, L.fsda_time_kernel, L.fsda_kernel_time, L.fsda_batch_workspace_size,
-                  L.fsda_multishift_solve_batch, L.fsda_sa_rhs, L.fsda_sa_solve):
+                  L.fsda_multishift_solve_batch, L.fsda_sa_rhs, L.fsda_sa_solve, L.fsda_regression_solve):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -212,6 +213,23 @@ class Operator:
                                         int(maxit), int(chunk), _ptr(Z), iters.ctypes.data_as(ctypes.c_void_p),
                                         relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
         return Z, iters, relres, rc
+
+    def regression_solve(self, z, betas: Sequence[float], rtol: float, maxit: int = 100000, chunk: int = 0,
+                         shared_basis: bool = True, stream=None):
+        """(X^T X + beta I) w = X^T z for every beta (fsda_regression_solve).
+
+        Returns (W [S, d] float64 tensor, iters [S] int32, relres [S] float64, status)."""
+        import torch
+        betas = np.ascontiguousarray(betas, dtype=np.float64)
+        S = betas.size
+        W = torch.empty((S, self.d), dtype=torch.float64, device=self.device)
+        iters = np.zeros(S, dtype=np.int32)
+        relres = np.zeros(S, dtype=np.float64)
+        rc = _check(lib().fsda_regression_solve(self.handle, _ptr(z), betas.ctypes.data_as(ctypes.c_void_p), S,
+                                                float(rtol), int(maxit), int(chunk), int(bool(shared_basis)), _ptr(W),
+                                                iters.ctypes.data_as(ctypes.c_void_p),
+                                                relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return W, iters, relres, rc
 
     def solve_batch(self, labels, betas: Sequence[float], rtol: float, maxit: int = 100000, chunk: int = 0,
                     stream=None):

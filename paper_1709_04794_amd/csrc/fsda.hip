@@ -193,12 +193,18 @@ struct TPair {
 struct GraphKey {
   const double* W;
   const double* rhs;
-  int nshift, chunk, vbytes;
-  double sigma0;
+  int nshift, chunk, vbytes, mode;
   bool operator==(const GraphKey& o) const {
     return W == o.W && rhs == o.rhs && nshift == o.nshift && chunk == o.chunk && vbytes == o.vbytes &&
-           sigma0 == o.sigma0;
+           mode == o.mode;
   }
+};
+
+// operator of the shared recurrence
+enum Mode {
+  MODE_FSDA = 0,  // X^T M' X + sigma I (feature space)
+  MODE_SA = 1,    // M' + sigma I_N (sample space, Alg. sasda)
+  MODE_REG = 2    // X^T X + sigma I (the regression phase of the spectral-regression variants)
 };
 
 struct XtPlan {  // X^T product: long rows in single-row chunks, the rest in length bins
@@ -386,37 +392,46 @@ void product_lap(fsda_op* op, int solve, hipStream_t s) {
 void apply_internal(fsda_op* op, double sigma, const double* p, double* q, hipStream_t s) {
   product_x<double>(op, p, 0, s);
   product_lap<double>(op, 0, s);
-  run_xt(op, op->u, EpiXT<double, false>{q, p, sigma}, 0, true, s, KC_OTHER);
+  run_xt(op, op->u, EpiXT<double, false>{q, p, sigma, nullptr}, 0, true, s, KC_OTHER);
 }
 
 int stream_grid(long long d) { return grid_for(ceil_div(d, UNR), GRID_STREAM); }
 
-// One iteration of the shared recurrence.  Feature space (FSDA): t = X p,
-// u = M' t, q = X^T u + sigma0 p.  Sample space (Alg. sasda, sa = true):
+// One iteration of the shared recurrence.  Feature space (MODE_FSDA): t = X p,
+// u = M' t, q = X^T u + sigma0 p.  Sample space (MODE_SA, Alg. sasda):
 // q = M' p + sigma0 p in one pass over S, the centring from the labeled-mean
-// partials of the previous direction update.  Then r and p as usual.
+// partials of the previous direction update.  Regression (MODE_REG):
+// t = X p, q = X^T t + sigma0 p.  Then r and p as usual.  sigma0 is read from
+// the solver state, so one captured chunk serves any seed shift.
 template <typename V>
-void iteration(fsda_op* op, double sigma0, bool sa, hipStream_t s, int tag) {
+void iteration(fsda_op* op, int mode, hipStream_t s, int tag) {
   op->cur_tag = tag;
   V* p = as<V>(op->p);
   V* q = as<V>(op->q);
   V* ring = as<V>(op->ring);
+  const bool sa = mode == MODE_SA;
   const long long m = sa ? op->pb.n : op->pb.d;
   const int gs = stream_grid(m);
+  const double* sig = &op->st->sigma0;
+  int ntu = op->ps.grid;
   if (sa) {
     run_rows(op, op->ps, op->p,
-             EpiLapSA{op->p, op->labw, op->pb.s_rowptr, op->q, op->pb.alpha, sigma0, op->part + SITE_X * NPART, gs,
+             EpiLapSA{op->p, op->labw, op->pb.s_rowptr, op->q, op->pb.alpha, 0.0, op->part + SITE_X * NPART, gs,
                       0.0},
              op->part + SITE_TU * NPART, 1, s, KC_S);
+  } else if (mode == MODE_REG) {
+    run_rows(op, op->px, p, EpiXReg<V>{as<V>(op->t)}, op->part + SITE_TU * NPART, 1, s, KC_X);
+    run_xt(op, as<V>(op->t), EpiXT<V, false>{q, p, 0.0, sig}, 1, false, s, KC_XT);
+    ntu = op->px.grid;
   } else {
     product_x<V>(op, p, 1, s);
     product_lap<V>(op, 1, s);
-    run_xt(op, as<V>(op->u), EpiXT<V, false>{q, p, sigma0}, 1, false, s, KC_XT);
+    run_xt(op, as<V>(op->u), EpiXT<V, false>{q, p, 0.0, sig}, 1, false, s, KC_XT);
   }
   launch(op, KC_RESID, s, [&] {
-    hipLaunchKernelGGL(k_resid<V>, dim3(gs), dim3(BS), 0, s, op->st, q, p, ring, op->L.ldv, m, sigma0,
-                       op->part + SITE_TU * NPART, op->ps.grid, op->part + SITE_PP * NPART, gs,
-                       sa ? 0 : op->pxt.nlong, op->pxt.row_chunk0, op->pxt.w.lpart, op->part + SITE_R * NPART);
+    hipLaunchKernelGGL(k_resid<V>, dim3(gs), dim3(BS), 0, s, op->st, q, p, ring, op->L.ldv, m,
+                       op->part + SITE_TU * NPART, ntu, op->part + SITE_PP * NPART, gs, sa ? 0 : op->pxt.nlong,
+                       op->pxt.row_chunk0, op->pxt.w.lpart, op->part + SITE_R * NPART);
   });
   launch(op, KC_PUPD, s, [&] {
     hipLaunchKernelGGL(k_pupdate<V>, dim3(gs), dim3(BS), 0, s, op->st, ring, p, op->L.ldv, m,
@@ -427,8 +442,8 @@ void iteration(fsda_op* op, double sigma0, bool sa, hipStream_t s, int tag) {
 }
 
 template <typename V>
-void fold(fsda_op* op, double* W, int nshift, int chunk, bool sa, hipStream_t s) {
-  const long long d = sa ? op->pb.n : op->pb.d;
+void fold(fsda_op* op, double* W, int nshift, int chunk, int mode, hipStream_t s) {
+  const long long d = mode == MODE_SA ? op->pb.n : op->pb.d;
   const int g = grid_for(d, GRID_FOLD);
   V* ring = as<V>(op->ring);
   V* P = as<V>(op->P);
@@ -592,7 +607,8 @@ int make_xt(fsda_op* op, hipStream_t s) {
 // the iterates.
 template <typename V>
 int run_multishift(fsda_op* op, const double* rhs, const double* betas, double sigma0, int nshift, double rtol,
-                   int maxit, int chunk, double* W, hipStream_t s, bool sa = false) {
+                   int maxit, int chunk, double* W, hipStream_t s, int mode = MODE_FSDA) {
+  const bool sa = mode == MODE_SA;
   const long long d = sa ? op->pb.n : op->pb.d;
   State* h = op->hst;
   std::memset(h, 0, sizeof(State));
@@ -600,6 +616,7 @@ int run_multishift(fsda_op* op, const double* rhs, const double* betas, double s
   h->maxit = maxit;
   h->chunk = chunk;
   h->tol = rtol;  // scaled by ||b|| in k_init_done
+  h->sigma0 = sigma0;
   h->a_prev = 1.0;
   h->b_cur = 0.0;
   for (int k = 0; k < nshift; k++) {
@@ -618,13 +635,13 @@ int run_multishift(fsda_op* op, const double* rhs, const double* betas, double s
 
   bool graph = op->use_graph != 0 && !op->tk_on;
   if (graph) {
-    const GraphKey key{W, rhs, nshift, chunk, (int)sizeof(V) + (sa ? 100 : 0), sigma0};
+    const GraphKey key{W, rhs, nshift, chunk, (int)sizeof(V), mode};
     if (!op->gexec || !(op->gkey == key)) {
       drop_graph(op);
       hipGraph_t gr = nullptr;
       HIP_TRY(hipStreamBeginCapture(op->cap, hipStreamCaptureModeThreadLocal));
-      for (int j = 0; j < chunk; j++) iteration<V>(op, sigma0, sa, op->cap, j);
-      fold<V>(op, W, nshift, chunk, sa, op->cap);
+      for (int j = 0; j < chunk; j++) iteration<V>(op, mode, op->cap, j);
+      fold<V>(op, W, nshift, chunk, mode, op->cap);
       const hipError_t ce = hipStreamEndCapture(op->cap, &gr);
       hipError_t ie = hipErrorUnknown;
       if (ce == hipSuccess) {
@@ -647,8 +664,8 @@ int run_multishift(fsda_op* op, const double* rhs, const double* betas, double s
     if (graph) {
       HIP_TRY(hipGraphLaunch(op->gexec, s));
     } else {
-      for (int j = 0; j < chunk; j++) iteration<V>(op, sigma0, sa, s, j);
-      fold<V>(op, W, nshift, chunk, sa, s);
+      for (int j = 0; j < chunk; j++) iteration<V>(op, mode, s, j);
+      fold<V>(op, W, nshift, chunk, mode, s);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(h) + off, reinterpret_cast<char*>(op->st) + off, 4 * sizeof(int),
@@ -674,6 +691,20 @@ int residuals(fsda_op* op, const double* rhs, const double* betas, int nshift, c
     product_x<double>(op, w, 0, s);
     product_lap<double>(op, 0, s);
     run_xt(op, op->u, EpiRes{rhs, w, betas[k], out ? out + (long long)k * ldo : nullptr}, 0, true, s, KC_OTHER);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, op->part + SITE_XT * NPART, xt_npart(op),
+                       &op->st->res2[k]);
+  }
+  HIP_TRY(hipGetLastError());
+  return FSDA_OK;
+}
+
+// True residuals ||b - (X^T X + beta_k) w_k||^2 of the regression solve into st->res2[k].
+int residuals_reg(fsda_op* op, const double* rhs, const double* betas, int nshift, const double* W, hipStream_t s) {
+  const long long d = op->pb.d;
+  for (int k = 0; k < nshift; k++) {
+    const double* w = W + (long long)k * d;
+    run_rows(op, op->px, w, EpiX<double, false>{op->t, nullptr}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
+    run_xt(op, op->t, EpiRes{rhs, w, betas[k], nullptr}, 0, true, s, KC_OTHER);
     hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, op->part + SITE_XT * NPART, xt_npart(op),
                        &op->st->res2[k]);
   }
@@ -1455,7 +1486,7 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
   // 5. canonical right-hand side b = X^T y_c (internal order)
   hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(BS), 0, s, reinterpret_cast<int*>(op->st), (long long)(sizeof(State) / 4),
                      0);
-  run_xt(op, op->ycen, EpiXT<double, false>{op->b, nullptr, 0.0}, 0, true, s, KC_OTHER);
+  run_xt(op, op->ycen, EpiXT<double, false>{op->b, nullptr, 0.0, nullptr}, 0, true, s, KC_OTHER);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(s));
   *out = op;
@@ -1599,7 +1630,7 @@ int fsda_sa_solve(fsda_op* op, const double* g, const double* betas, int nshift,
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const double* rhs = g ? g : op->ycen;
-  int rc = run_multishift<double>(op, rhs, betas, sigma0, nshift, rtol, maxit, chunk, Z, s, true);
+  int rc = run_multishift<double>(op, rhs, betas, sigma0, nshift, rtol, maxit, chunk, Z, s, MODE_SA);
   if (rc) return rc;
   if ((rc = residuals_sa(op, rhs, betas, nshift, Z, s))) return rc;
   State* h = op->hst;
@@ -1615,6 +1646,71 @@ int fsda_sa_solve(fsda_op* op, const double* g, const double* betas, int nshift,
   }
   if (h->status == FSDA_E_BREAKDOWN) return fail(FSDA_E_BREAKDOWN, "CG breakdown: <p, A p> <= 0 or not finite");
   return h->status == FSDA_NOT_CONVERGED ? FSDA_NOT_CONVERGED : FSDA_OK;
+}
+
+int fsda_regression_solve(fsda_op* op, const double* z, const double* betas, int nshift, double rtol, int maxit,
+                          int chunk, int shared_basis, double* W, int* iters, double* relres, void* stream) {
+  if (!op || !z || !betas || !W || !iters || !relres) return fail(FSDA_E_ARG, "NULL argument");
+  if (nshift < 1 || nshift > op->max_shifts) return fail(FSDA_E_ARG, "nshift outside 1..max_shifts");
+  if (!(rtol > 0.0)) return fail(FSDA_E_RANGE, "rtol must be > 0");
+  if (maxit < 1) return fail(FSDA_E_RANGE, "maxit must be >= 1");
+  if (chunk < 0) return fail(FSDA_E_RANGE, "chunk must be >= 0");
+  if (chunk == 0) chunk = 32;
+  chunk = std::min(chunk, op->max_chunk);
+  while (chunk > 1 && chunk * nshift > MAXCHUNK * MAXS / 2) chunk >>= 1;
+  double sigma0 = betas[0];
+  for (int k = 0; k < nshift; k++) {
+    if (!(betas[k] > 0.0) || !std::isfinite(betas[k])) return fail(FSDA_E_RANGE, "every beta must be finite and > 0");
+    sigma0 = std::min(sigma0, betas[k]);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long d = op->pb.d;
+  // b = X^T z in the internal feature order
+  run_xt(op, z, EpiXT<double, false>{op->bu, nullptr, 0.0, nullptr}, 0, true, s, KC_OTHER);
+  HIP_TRY(hipGetLastError());
+  State* h = op->hst;
+  std::vector<int> conv(nshift, 0);
+  int status = FSDA_OK;
+  int rc;
+  if (shared_basis) {
+    if ((rc = run_multishift<double>(op, op->bu, betas, sigma0, nshift, rtol, maxit, chunk, W, s, MODE_REG)))
+      return rc;
+    HIP_TRY(hipMemcpyAsync(h, op->st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < nshift; k++) conv[k] = h->conv[k];
+    status = h->status;
+  } else {
+    // one CG per shift, each into row 0 of W (so every solve replays the same
+    // captured chunk), moved to its own row afterwards; the last one is row 0's
+    for (int k = nshift - 1; k >= 0; k--) {
+      if ((rc = run_multishift<double>(op, op->bu, betas + k, betas[k], 1, rtol, maxit, chunk, W, s, MODE_REG)))
+        return rc;
+      if (k > 0) HIP_TRY(hipMemcpyAsync(W + (long long)k * d, W, sizeof(double) * d, hipMemcpyDeviceToDevice, s));
+      HIP_TRY(hipMemcpyAsync(h, op->st, sizeof(State), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      conv[k] = h->conv[0];
+      if (h->status == FSDA_E_BREAKDOWN || (h->status == FSDA_NOT_CONVERGED && status == FSDA_OK)) status = h->status;
+    }
+  }
+  if ((rc = residuals_reg(op, op->bu, betas, nshift, W, s))) return rc;
+  for (int k = 0; k < nshift; k++) {
+    double* w = W + (long long)k * d;
+    hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, w, op->old2new, op->q, d);
+    HIP_TRY(hipMemcpyAsync(w, op->q, sizeof(double) * d, hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h, op->st, sizeof(State), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (op->tk_on) {
+    const int trc = tk_flush(op, 1 << 30);
+    if (trc) return trc;
+  }
+  for (int k = 0; k < nshift; k++) {
+    iters[k] = conv[k];
+    relres[k] = h->bnorm > 0.0 ? std::sqrt(h->res2[k]) / h->bnorm : 0.0;
+  }
+  if (status == FSDA_E_BREAKDOWN) return fail(FSDA_E_BREAKDOWN, "CG breakdown: <p, A p> <= 0 or not finite");
+  return status == FSDA_NOT_CONVERGED ? FSDA_NOT_CONVERGED : FSDA_OK;
 }
 
 int fsda_batch_workspace_size(const fsda_op* op, int ntarget, int nshift, int chunk, size_t* bytes) {

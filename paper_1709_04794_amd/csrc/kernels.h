@@ -45,6 +45,7 @@ struct State {
   double bnorm;
   double a_cur, a_prev;    // CG step lengths a_i, a_{i-1} (a_i = -gamma_i of Alg. 3)
   double b_cur;            // CG direction coefficient b_i (alpha_i of Alg. 3)
+  double sigma0;           // seed shift of the shared recurrence
   double sig[MAXS];        // beta_s - sigma0
   double zp[MAXS], z[MAXS], zn[MAXS];  // zeta_{i-1}, zeta_i, zeta_{i+1}
   double as[MAXS], bs[MAXS];           // per-shift step and direction coefficients
@@ -183,6 +184,20 @@ __device__ void resid_scalars(State* st, double rrn, double b, double* hist) {
 // The epilogues are templated on the vector type V (double, or float on the
 // mixed-precision path): row sums and vectors are V, reductions are double.
 
+// t = X p; reduction <t, t> (the regression operator X^T X + sigma I, whose
+// <p, A p> is <t, t> + sigma <p, p>).
+template <typename T>
+struct EpiXReg {
+  using V = T;
+  V* t;
+  static constexpr bool kReduce = true;
+  __device__ void prepare(const State*) {}
+  __device__ double row(int r, V v) const {
+    t[r] = v;
+    return (double)v * (double)v;
+  }
+};
+
 // t = X p; with W, reduction sum_r w_r t_r (w = 1/l on labeled rows gives their mean).
 template <typename T, bool W>
 struct EpiX {
@@ -225,15 +240,18 @@ struct EpiLap {
   }
 };
 
-// q = X^T u + sigma p; reduction <p, q>.
+// q = X^T u + sigma p (sigma read from *sigp when sigp is not NULL); reduction <p, q>.
 template <typename T, bool RED>
 struct EpiXT {
   using V = T;
   V* q;
   const V* p;
   double sigma;
+  const double* sigp;
   static constexpr bool kReduce = RED;
-  __device__ void prepare(const State*) {}
+  __device__ void prepare(const State*) {
+    if (sigp) sigma = *sigp;
+  }
   __device__ double row(int r, V v) const {
     const V pr = p ? p[r] : (V)0;
     const V qq = v + (V)sigma * pr;
@@ -274,7 +292,10 @@ struct EpiLapSA {
   int ncpart;
   double c;
   static constexpr bool kReduce = true;
-  __device__ void prepare(const State*) { c = sum_partials(cpart, ncpart); }
+  __device__ void prepare(const State* st) {
+    c = sum_partials(cpart, ncpart);
+    sigma = st->sigma0;
+  }
   __device__ double row(int r, double v) const {
     const double pr = p[r];
     double x = alpha * ((double)(srowptr[r + 1] - srowptr[r]) * pr - v);
@@ -543,11 +564,12 @@ __global__ __launch_bounds__(BS) void k_init_done(State* st, const double* part,
 // are issued before the partial sums, so both latencies overlap.
 template <typename V>
 __global__ __launch_bounds__(BS) void k_resid(State* st, const V* __restrict__ q, const V* __restrict__ p,
-                                              V* ring, long long ldd, long long d, double sigma0,
-                                              const double* tu_part, int ntu, const double* pp_part, int npp,
-                                              int nlong, const int* __restrict__ row_chunk0,
-                                              const double* __restrict__ lpart, double* part) {
+                                              V* ring, long long ldd, long long d, const double* tu_part, int ntu,
+                                              const double* pp_part, int npp, int nlong,
+                                              const int* __restrict__ row_chunk0, const double* __restrict__ lpart,
+                                              double* part) {
   if (st->stop) return;
+  const double sigma0 = st->sigma0;
   const int i = st->iter, m = st->chunk;
   const V* r = ring + (long long)(i % m) * ldd;
   V* rn = ring + (long long)((i + 1) % m) * ldd;

@@ -134,6 +134,8 @@ def knn_graph(n: int, x_rowptr: np.ndarray, x_col: np.ndarray, k: int, ties: boo
     (MinHash candidates + exact re-rank, for large n) or "auto".
     Returns (rowptr int32[n+1], col int32[nnz]), sorted columns.
     """
+    if k <= 0:  # no graph
+        return np.zeros(n + 1, dtype=np.int32), np.zeros(0, dtype=np.int32)
     lib = _load()
     rp = np.ascontiguousarray(x_rowptr, dtype=np.int64)
     col = np.ascontiguousarray(x_col, dtype=np.int32)
@@ -272,6 +274,10 @@ RECIPES = {
                   alpha=1.0, betas=tuple(np.logspace(-3, 2, 16)), rtol=1e-8),
     "large": Recipe(n=1_500_000, d=4_000_000, mean_nnz=70, zipf_s=1.2, lab_frac=0.01, pos_frac=0.05, k=10,
                     alpha=1.0, betas=tuple(np.logspace(-4, 2, 32)), rtol=1e-8),
+    # the shape of the ChEMBL matrix of the shifted-CG timing table (regression
+    # phase only, so no graph): 167,668 x 291,714 with about 12.2 million nonzeros
+    "chembl": Recipe(n=167_668, d=291_714, mean_nnz=72.8, zipf_s=1.1, lab_frac=0.01, pos_frac=0.2, k=0,
+                     alpha=1.0, betas=tuple(10.0 ** np.arange(-9, 3)), rtol=1e-3),
 }
 
 

@@ -96,4 +96,16 @@ def test_null_handle_calls_fail_cleanly():
     assert L.fsda_project(None, ctypes.c_void_p(8), 1, ctypes.c_void_p(8), None) == fsda.E_ARG
     assert L.fsda_apply(None, 0.0, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == fsda.E_ARG
     assert L.fsda_rhs(None, None, ctypes.c_void_p(8), None) == fsda.E_ARG
+    assert L.fsda_sa_rhs(None, None, ctypes.c_void_p(8), None) == fsda.E_ARG
+    assert L.fsda_sa_solve(None, None, betas.ctypes.data, 1, 1e-8, 10, 0, ctypes.c_void_p(8), it.ctypes.data,
+                           rr.ctypes.data, None) == fsda.E_ARG
+    assert L.fsda_regression_solve(None, ctypes.c_void_p(8), betas.ctypes.data, 1, 1e-3, 10, 0, 1,
+                                   ctypes.c_void_p(8), it.ctypes.data, rr.ctypes.data, None) == fsda.E_ARG
+    size = ctypes.c_size_t(0)
+    assert L.fsda_batch_workspace_size(None, 4, 4, 0, ctypes.byref(size)) == fsda.E_ARG
+    off = np.array([0, 5], dtype=np.int64)
+    assert L.fsda_multishift_solve_batch(None, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), off.ctypes.data,
+                                         betas.ctypes.data, 1, 1e-8, 10, 0, ctypes.c_void_p(256), 1 << 20,
+                                         ctypes.c_void_p(8), it.ctypes.data, rr.ctypes.data, None) == fsda.E_ARG
+    assert b"NULL" in L.fsda_last_error()
     L.fsda_destroy_operator(None)

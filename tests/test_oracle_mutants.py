@@ -19,12 +19,16 @@ from oracle import dense
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "fsda_oracle.c")
 
-# Changes that must NOT matter: Sec. 3.2.3 shows one centred product suffices,
-# so dropping the centring of X v leaves the operator unchanged; and
-# Xc^T 1_l = 0, so the right-hand side Xc^T y does not need centred labels.
+FSDA_PINS = ["dense", "rhs", "annihilation"]
+
+# Changes that must NOT matter for the pins listed with them: Sec. 3.2.3 shows
+# one centred product suffices, so dropping the centring of X v leaves the
+# operator unchanged; and Xc^T 1_l = 0, so the feature-space right-hand side
+# Xc^T y does not need centred labels (the sample-space one, y_c itself, does:
+# that change must fail the sample-space pin).
 EQUIVALENT = {
-    "drop_centring_in_xc": ("out[i] -= m;", "(void)m;"),
-    "labels_not_centred": ("- ybar;", "- 0.0;"),
+    "drop_centring_in_xc": ("out[i] -= m;", "(void)m;", None),
+    "labels_not_centred": ("- ybar;", "- 0.0;", FSDA_PINS),
 }
 
 MUTANTS = {
@@ -33,10 +37,18 @@ MUTANTS = {
     "drop_one_minus_alpha": ("out[i] = (1.0 - a) * (c->lab[i] ? t[i] : 0.0) + a * lt;",
                              "out[i] = (c->lab[i] ? t[i] : 0.0) + a * lt;"),
     "cg_update_sign": ("w[j] -= gamma * p[j];", "w[j] += gamma * p[j];"),
-    "shift_not_added": ("q[j] += beta * p[j];", "q[j] += 0.5 * beta * p[j];"),
+    "shift_not_added": ("  xct_mul(c, c->t, q);\n  for (int64_t j = 0; j < c->pb->d; j++) q[j] += beta * p[j];",
+                        "  xct_mul(c, c->t, q);\n  for (int64_t j = 0; j < c->pb->d; j++) q[j] += 0.5 * beta * p[j];"),
     "direction_uses_old_residual": ("double a = rr_new / rr;", "double a = rr / rr_new;"),
     "mu_not_divided": ("c->mu[j] /= (double)pb->n_lab;", "c->mu[j] /= 1.0;"),
+    # sample-space solve (Alg. sasda) and regression phase
+    "sa_drop_centring": ("q[i] = c->t[i] - (c->lab[i] ? s : 0.0) + beta * z[i];", "q[i] = c->t[i] + beta * z[i];"),
+    "sa_rhs_not_orthogonalised": ("c.v[i] = r[i] - sl / (double)pb->n_lab;", "c.v[i] = r[i];"),
+    "reg_shift_doubled": ("  xt_mul(c, c->v, q);\n  for (int64_t j = 0; j < c->pb->d; j++) q[j] += beta * p[j];",
+                          "  xt_mul(c, c->v, q);\n  for (int64_t j = 0; j < c->pb->d; j++) q[j] += 2.0 * beta * p[j];"),
 }
+
+ALL = ["dense", "rhs", "annihilation", "sa_dense", "sa_rhs", "reg_svd"]
 
 
 def _checks():
@@ -66,11 +78,32 @@ def _checks():
             ok.append("annihilation")
     except RuntimeError:
         pass
+    try:
+        Z, *_ = oracle.sa_solve(pb, rtol=1e-13, maxit=3000)
+        if all(np.linalg.norm(Z[s] - dense.sa_solve_dense(pb, bt)) < 1e-8 * np.linalg.norm(Z[s])
+               for s, bt in enumerate(pb.betas)):
+            ok.append("sa_dense")
+    except RuntimeError:
+        pass
+    try:
+        r = synth.uniform(pb.n, -1.0, 1.0, seed=3, stream=1)
+        if np.allclose(oracle.sa_rhs(pb, r), dense.sa_rhs(pb, r), rtol=0, atol=1e-13):
+            ok.append("sa_rhs")
+    except RuntimeError:
+        pass
+    try:
+        z = synth.normal(pb.n, seed=5, stream=2)
+        Wr, *_ = oracle.reg_solve(pb, z, [0.01, 1.0], rtol=1e-13, maxit=3000)
+        if all(np.linalg.norm(Wr[s] - dense.reg_solve_svd(pb, bt, z)) < 1e-8 * np.linalg.norm(Wr[s])
+               for s, bt in enumerate([0.01, 1.0])):
+            ok.append("reg_svd")
+    except RuntimeError:
+        pass
     return ok
 
 
 def test_unmutated_oracle_passes_quick_pins():
-    assert _checks() == ["dense", "rhs", "annihilation"]
+    assert _checks() == ALL
 
 
 def _held_with(old, new, monkeypatch):
@@ -91,9 +124,14 @@ def _held_with(old, new, monkeypatch):
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_mutant_is_caught(name, monkeypatch):
     held = _held_with(*MUTANTS[name], monkeypatch)
-    assert held != ["dense", "rhs", "annihilation"], "mutant %s passed every pin" % name
+    assert held != ALL, "mutant %s passed every pin" % name
 
 
 @pytest.mark.parametrize("name", sorted(EQUIVALENT))
 def test_equivalent_change_passes(name, monkeypatch):
-    assert _held_with(*EQUIVALENT[name], monkeypatch) == ["dense", "rhs", "annihilation"]
+    old, new, pins = EQUIVALENT[name]
+    held = _held_with(old, new, monkeypatch)
+    if pins is None:
+        assert held == ALL
+    else:
+        assert [p for p in held if p in pins] == pins and held != ALL
