@@ -14,6 +14,8 @@ Contents
     Cl^T M + beta I_N, the ratings being the solution itself.
   * the regression phase of the spectral-regression variants (:func:`reg_solve`):
     per-shift CG on (X^T X + beta I) w = X^T z.
+  * :mod:`oracle.hyper`: the hold-out loss of the ratings and its gradient in
+    log beta and alpha by one adjoint solve per shift.
   * :mod:`oracle.dense`: dense NumPy/SciPy forms (Cholesky of the operator,
     sample-space push-through, labeled-only dual ridge) used to pin the above.
   * :mod:`oracle.shifted`: the paper's shifted CG (Alg. 3) in NumPy, for the
