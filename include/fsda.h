@@ -240,6 +240,50 @@ int fsda_multishift_solve_batch(fsda_op *op, int ntarget, const int32_t *lab_idx
                                 void *stream);
 
 /*
+ * Independent systems with different right-hand sides, solved together:
+ *     A(sigma_c) x_c = b_c,  c < ncol,  A(sigma) = X^T M' X + sigma I
+ * (the handle's operator; e.g. the adjoint systems of the hypergradient, whose
+ * right-hand sides differ per shift, so one shifted basis cannot serve them).
+ * Batched CG in FP64, one column per system, the sparse products of all
+ * columns sharing one pass over the indices.
+ *  B[ncol][d]   device, right-hand sides in the caller's feature order.
+ *  sigmas[ncol] host, each > 0.   ncol 1..FSDA_MAX_TARGETS.
+ *  rtol, maxit  column c stops when ||r_c|| <= rtol ||b_c||; at most maxit iterations.
+ *  workspace    device, 256-byte aligned, >= fsda_columns_workspace_size(); scratch.
+ *  X[ncol][d]   device FP64 output.   iters, relres[ncol] host (true FP64 residual).
+ * Blocks until done.
+ */
+int fsda_columns_workspace_size(const fsda_op *op, int ncol, size_t *bytes);
+int fsda_solve_columns(fsda_op *op, const double *B, const double *sigmas, int ncol, double rtol, int maxit,
+                       void *workspace, size_t ws_bytes, double *X, int *iters, double *relres, void *stream);
+
+/*
+ * Hold-out loss of the ratings (Alg. 7, return value) for selecting beta and
+ * alpha:  H_s = 1/2 ||X_ho w_s - y_ho||^2 / n_ho for every row w_s of W.
+ *  W[nshift][d]  device, caller's feature order (e.g. from fsda_multishift_solve).
+ *  ho_idx[n_ho]  device int32 held-out rows (distinct, in range); ho_y[n_ho] device FP64 targets.
+ *  loss[nshift]  host output.
+ *  G[nshift][d]  device output or NULL: the gradient of H_s in w_s,
+ *                X_ho^T (X_ho w_s - y_ho) / n_ho, the right-hand side of the
+ *                adjoint system A(beta_s) lambda_s = G_s (fsda_solve_columns).
+ * FSDA_E_ARG for a held-out index out of range or repeated.  Blocks until done.
+ */
+int fsda_holdout(fsda_op *op, const double *W, int nshift, const int32_t *ho_idx, const double *ho_y, int64_t n_ho,
+                 double *loss, double *G, void *stream);
+
+/*
+ * Hypergradient of the hold-out loss from the solutions W and the adjoint
+ * solutions Lambda (A symmetric: A(beta_s) lambda_s = G_s):
+ *     dH_s/d log beta_s = -beta_s <lambda_s, w_s>
+ *     dH_s/d alpha      = -<X lambda_s, [L - (P_l - 1_l 1_l^T / l)] X w_s>
+ * (A is affine in alpha with that slope; b does not depend on either).
+ *  W, Lambda[nshift][d] device, caller's order; betas[nshift] host.
+ *  dlogbeta[nshift], dalpha[nshift] host outputs.  Blocks until done.
+ */
+int fsda_hypergradient(fsda_op *op, const double *W, const double *Lambda, const double *betas, int nshift,
+                       double *dlogbeta, double *dalpha, void *stream);
+
+/*
  * Ratings s = X w for each shift (Alg. 7, return value; uncentred):
  * W[nshift][d] device FP64 in, S[nshift][n] device FP64 out.
  */

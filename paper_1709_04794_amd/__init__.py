@@ -73,6 +73,10 @@ def lib():
         L.fsda_sa_rhs.argtypes = [P, P, P, P]
         L.fsda_sa_solve.argtypes = [P, P, P, I, D, I, I, P, P, P, P]
         L.fsda_regression_solve.argtypes = [P, P, P, I, D, I, I, I, P, P, P, P]
+        L.fsda_columns_workspace_size.argtypes = [P, I, ctypes.POINTER(ctypes.c_size_t)]
+        L.fsda_solve_columns.argtypes = [P, P, P, I, D, I, P, ctypes.c_size_t, P, P, P, P]
+        L.fsda_holdout.argtypes = [P, P, I, P, P, ctypes.c_int64, P, P, P]
+        L.fsda_hypergradient.argtypes = [P, P, P, P, I, P, P, P]
         L.fsda_batch_workspace_size.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_size_t)]
         L.fsda_multishift_solve_batch.argtypes = [P, I, P, P, P, P, I, D, I, I, P, ctypes.c_size_t, P, P, P, P]
         L.fsda_destroy_operator.argtypes = [P]
@@ -81,7 +85,8 @@ def lib():
         L.fsda_last_error.restype = ctypes.c_char_p
         for f in (L.fsda_workspace_size, L.fsda_build_operator, L.fsda_rhs, L.fsda_apply, L.fsda_multishift_solve,
                   L.fsda_project, L.fsda_time_kernel, L.fsda_kernel_time, L.fsda_batch_workspace_size,
-                  L.fsda_multishift_solve_batch, L.fsda_sa_rhs, L.fsda_sa_solve, L.fsda_regression_solve):
+                  L.fsda_multishift_solve_batch, L.fsda_sa_rhs, L.fsda_sa_solve, L.fsda_regression_solve,
+                  L.fsda_columns_workspace_size, L.fsda_solve_columns, L.fsda_holdout, L.fsda_hypergradient):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -230,6 +235,52 @@ class Operator:
                                                 iters.ctypes.data_as(ctypes.c_void_p),
                                                 relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
         return W, iters, relres, rc
+
+    def solve_columns(self, B, sigmas: Sequence[float], rtol: float, maxit: int = 100000, stream=None):
+        """A(sigma_c) x_c = b_c for the rows b_c of B [ncol, d] (fsda_solve_columns).
+
+        Returns (X [ncol, d] float64 tensor, iters [ncol] int32, relres [ncol] float64, status)."""
+        import torch
+        B = B.contiguous()
+        sig = np.ascontiguousarray(sigmas, dtype=np.float64)
+        K = sig.size
+        size = ctypes.c_size_t(0)
+        _check(lib().fsda_columns_workspace_size(self.handle, K, ctypes.byref(size)))
+        need = int(size.value) + 256
+        if getattr(self, "_cws", None) is None or self._cws.numel() < need:
+            self._cws = None
+            self._cws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        ws = (self._cws.data_ptr() + 255) // 256 * 256
+        X = torch.empty((K, self.d), dtype=torch.float64, device=self.device)
+        iters = np.zeros(K, dtype=np.int32)
+        relres = np.zeros(K, dtype=np.float64)
+        rc = _check(lib().fsda_solve_columns(self.handle, _ptr(B), sig.ctypes.data_as(ctypes.c_void_p), K, float(rtol),
+                                             int(maxit), ctypes.c_void_p(ws), ctypes.c_size_t(int(size.value)),
+                                             _ptr(X), iters.ctypes.data_as(ctypes.c_void_p),
+                                             relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return X, iters, relres, rc
+
+    def holdout(self, W, ho_idx, ho_y, gradient: bool = True, stream=None):
+        """Hold-out loss per row of W and (optionally) its gradient in w (fsda_holdout)."""
+        import torch
+        W = W.contiguous()
+        S = W.shape[0]
+        loss = np.zeros(S, dtype=np.float64)
+        G = torch.empty((S, self.d), dtype=torch.float64, device=self.device) if gradient else None
+        _check(lib().fsda_holdout(self.handle, _ptr(W), S, _ptr(ho_idx), _ptr(ho_y), int(ho_idx.numel()),
+                                  loss.ctypes.data_as(ctypes.c_void_p), _ptr(G), _stream(stream)))
+        return loss, G
+
+    def hypergradient(self, W, Lam, betas: Sequence[float], stream=None):
+        """(dH/dlog beta [S], dH/dalpha [S]) from solutions and adjoint solutions (fsda_hypergradient)."""
+        betas = np.ascontiguousarray(betas, dtype=np.float64)
+        S = betas.size
+        dlb = np.zeros(S, dtype=np.float64)
+        da = np.zeros(S, dtype=np.float64)
+        _check(lib().fsda_hypergradient(self.handle, _ptr(W.contiguous()), _ptr(Lam.contiguous()),
+                                        betas.ctypes.data_as(ctypes.c_void_p), S, dlb.ctypes.data_as(ctypes.c_void_p),
+                                        da.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return dlb, da
 
     def solve_batch(self, labels, betas: Sequence[float], rtol: float, maxit: int = 100000, chunk: int = 0,
                     stream=None):

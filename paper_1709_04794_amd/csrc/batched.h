@@ -26,7 +26,7 @@ constexpr int BU = 8;       // nonzeros in flight per lane
 
 struct BState {
   int iter, stop, status, maxit;
-  int ncol, pad_[3];
+  int ncol, zero, pad_[2];       // zero: always 0, the stop flag of launches outside the recurrence
   double trel;                   // relative stop floor (of ||b_c||)
   double rr[BT_MAX];             // <r_c, r_c>
   double a[BT_MAX], b[BT_MAX];   // CG step and direction coefficients of the iteration
@@ -37,6 +37,7 @@ struct BState {
   double cm[BT_MAX];             // labeled mean of t_c (centring)
   int active[BT_MAX];
   int conv[BT_MAX];              // iterations after which column c stopped
+  double res2[BT_MAX];           // true residual ||b_c - A(sigma_c) x_c||^2 after a solve
 };
 
 // Per-column block sum of acc (thread tid holds column tid % T) into
@@ -294,19 +295,19 @@ __global__ __launch_bounds__(BS) void bk_xt_rows(BXtArgs X, const V* __restrict_
 // batched CG recurrences
 // ---------------------------------------------------------------------------
 
-// R = P = B_c (rounded to FP32; zero for c >= ncol), X = 0; partials of <r, r>.
-template <int T>
-__global__ __launch_bounds__(BS) void bk_init(const double* __restrict__ B, long long ldb, int ncol, float* R, float* P,
-                                              float* X, long long d, double* part) {
+// R = P = B_c (rounded to V; zero for c >= ncol), X = 0; partials of <r, r>.
+template <int T, typename V>
+__global__ __launch_bounds__(BS) void bk_init(const double* __restrict__ B, long long ldb, int ncol, V* R, V* P, V* X,
+                                              long long d, double* part) {
   constexpr int G = BS / T;
   const int c = threadIdx.x % T, g = threadIdx.x / T;
   double acc = 0.0;
   for (long long j = (long long)blockIdx.x * G + g; j < d; j += (long long)gridDim.x * G) {
-    const float x = c < ncol ? (float)B[(long long)c * ldb + j] : 0.f;
+    const V x = c < ncol ? (V)B[(long long)c * ldb + j] : (V)0;
     const size_t e = (size_t)j * T + c;
     R[e] = x;
     P[e] = x;
-    X[e] = 0.f;
+    X[e] = (V)0;
     acc += (double)x * (double)x;
   }
   write_partials_cols<T>(part, acc);
@@ -379,9 +380,9 @@ __global__ __launch_bounds__(BS) void bk_step_a(BState* st, const double* tu_par
 }
 
 // R -= a_c Q, X += a_c P; partials of <r, r>.
-template <int T>
-__global__ __launch_bounds__(BS) void bk_resid(const BState* st, const float* __restrict__ Q, const float* __restrict__ P,
-                                               float* R, float* X, long long d, double* part) {
+template <int T, typename V>
+__global__ __launch_bounds__(BS) void bk_resid(const BState* st, const V* __restrict__ Q, const V* __restrict__ P, V* R,
+                                               V* X, long long d, double* part) {
   if (st->stop) return;
   constexpr int G = BS / T;
   const int c = threadIdx.x % T, g = threadIdx.x / T;
@@ -389,9 +390,9 @@ __global__ __launch_bounds__(BS) void bk_resid(const BState* st, const float* __
   double acc = 0.0;
   for (long long j = (long long)blockIdx.x * G + g; j < d; j += (long long)gridDim.x * G) {
     const size_t e = (size_t)j * T + c;
-    const float r = (float)((double)R[e] - a * (double)Q[e]);
+    const V r = (V)((double)R[e] - a * (double)Q[e]);
     R[e] = r;
-    X[e] = (float)((double)X[e] + a * (double)P[e]);
+    X[e] = (V)((double)X[e] + a * (double)P[e]);
     acc += (double)r * (double)r;
   }
   write_partials_cols<T>(part, acc);
@@ -435,8 +436,8 @@ __global__ __launch_bounds__(BS) void bk_step_b(BState* st, const double* rr_par
 }
 
 // P = R + b_c P for the columns still active (the others keep P); partials of <p, p>.
-template <int T>
-__global__ __launch_bounds__(BS) void bk_pupdate(const BState* st, const float* __restrict__ R, float* P, long long d,
+template <int T, typename V>
+__global__ __launch_bounds__(BS) void bk_pupdate(const BState* st, const V* __restrict__ R, V* P, long long d,
                                                  double* part) {
   if (st->stop) return;
   constexpr int G = BS / T;
@@ -446,9 +447,9 @@ __global__ __launch_bounds__(BS) void bk_pupdate(const BState* st, const float* 
   double acc = 0.0;
   for (long long j = (long long)blockIdx.x * G + g; j < d; j += (long long)gridDim.x * G) {
     const size_t e = (size_t)j * T + c;
-    float p = P[e];
+    V p = P[e];
     if (on) {
-      p = (float)((double)R[e] + b * (double)p);
+      p = (V)((double)R[e] + b * (double)p);
       P[e] = p;
     }
     acc += (double)p * (double)p;
@@ -456,15 +457,43 @@ __global__ __launch_bounds__(BS) void bk_pupdate(const BState* st, const float* 
   write_partials_cols<T>(part, acc);
 }
 
-// W[c * ldw + j] += X[j * T + c] for c < ncol (FP64 accumulation of the FP32 correction).
-template <int T>
-__global__ __launch_bounds__(BS) void bk_add(const float* __restrict__ X, double* W, long long ldw, int ncol,
-                                             long long d) {
+// W[c * ldw + j] += X[j * T + c] for c < ncol (FP64 accumulation of the correction).
+template <int T, typename V>
+__global__ __launch_bounds__(BS) void bk_add(const V* __restrict__ X, double* W, long long ldw, int ncol, long long d) {
   constexpr int G = BS / T;
   const int c = threadIdx.x % T, g = threadIdx.x / T;
   if (c >= ncol) return;
   for (long long j = (long long)blockIdx.x * G + g; j < d; j += (long long)gridDim.x * G)
     W[(long long)c * ldw + j] += (double)X[(size_t)j * T + c];
+}
+
+// partials of ||B_c - (Q + sigma_c X)_c||^2 (B column-major [c][ldb], Q and X
+// interleaved): the true residual of A(sigma_c) x_c = b_c once Q = X^T M' X x.
+template <int T, typename V>
+__global__ __launch_bounds__(BS) void bk_resnorm(const BState* st, const double* __restrict__ B, long long ldb, int ncol,
+                                                 const V* __restrict__ Q, const V* __restrict__ X, long long d,
+                                                 double* part) {
+  constexpr int G = BS / T;
+  const int c = threadIdx.x % T, g = threadIdx.x / T;
+  const double sg = st->sigma[c];
+  double acc = 0.0;
+  if (c < ncol)
+    for (long long j = (long long)blockIdx.x * G + g; j < d; j += (long long)gridDim.x * G) {
+      const size_t e = (size_t)j * T + c;
+      const double r = B[(size_t)c * ldb + j] - ((double)Q[e] + sg * (double)X[e]);
+      acc += r * r;
+    }
+  write_partials_cols<T>(part, acc);
+}
+
+// out[c * d + jj] = X[old2new[jj] * T + c] for c < ncol (interleaved, internal
+// feature order -> one row per column in the caller's order).
+template <int T, typename V>
+__global__ void bk_unpack(const V* __restrict__ X, const int* __restrict__ old2new, double* out, int ncol, long long d) {
+  FSDA_GRID_LOOP(e, (long long)ncol * d) {
+    const long long c = e / d, jj = e % d;
+    out[e] = (double)X[(size_t)old2new[jj] * T + c];
+  }
 }
 
 }  // namespace fsda

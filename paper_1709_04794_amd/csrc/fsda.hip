@@ -253,7 +253,11 @@ struct fsda_op {
   int use_graph;
   // batched refinement solve: one chunk of iterations as a graph, per tile
   hipGraphExec_t bgexec;
+  const void* bg_key;
   int bg_tile;
+  hipGraphExec_t cgexec;  // fsda_solve_columns
+  const void* cg_key;
+  int cg_tile;
   // X^T rows of >= BMED nonzeros: their row pointers (host copy) and the chunk
   // table of the batched product for tile btab_tile
   std::vector<int> xt_rp_med;
@@ -471,6 +475,8 @@ void drop_graph(fsda_op* op) {
   op->bgexec = nullptr;
   if (op->tgexec) (void)hipGraphExecDestroy(op->tgexec);
   op->tgexec = nullptr;
+  if (op->cgexec) (void)hipGraphExecDestroy(op->cgexec);
+  op->cgexec = nullptr;
 }
 
 int check_problem(const fsda_problem* pb) {
@@ -729,135 +735,147 @@ int residuals_sa(fsda_op* op, const double* g, const double* betas, int nshift, 
 }
 
 // ---------------------------------------------------------------------------
-// batched FP32 CG (the correction solves of the mixed path)
+// batched CG over independent columns (the correction solves of the mixed
+// path in FP32; fsda_solve_columns in FP64)
 // ---------------------------------------------------------------------------
 
 int grid_b(long long items) { return (int)std::max<long long>(1, std::min<long long>(items, GRID_B)); }
 
-double* bpart(fsda_op* op, int site) { return at<double>(op, op->L.bpart) + (size_t)site * GRID_B * BT_MAX; }
-
-// One iteration over T columns: t = X P, u = M' t, a, Q = X^T u + sigma P,
-// R -= a Q and X += a P, b and the stop tests, P = R + b P.
+// chunk table of the X^T rows of >= BMED nonzeros for tile T (batched products)
 template <int T>
-void b_iteration(fsda_op* op, hipStream_t s, int tag) {
-  op->cur_tag = tag;
+int chunk_table(fsda_op* op, int* crow_d, int* cbeg_d, int* rc0_d, int* nchunk, hipStream_t s) {
+  const int nmed = op->nmed;
+  const std::vector<int>& rp = op->xt_rp_med;
+  std::vector<int> crow, cbeg, c0(nmed + 1);
+  for (int j = 0; j < nmed; j++) {
+    c0[j] = (int)crow.size();
+    for (int k = rp[j]; k < rp[j + 1]; k += BCHUNK<T>()) {
+      crow.push_back(j);
+      cbeg.push_back(k);
+    }
+  }
+  c0[nmed] = (int)crow.size();
+  if ((long long)crow.size() > op->L.bnchunk_max) return fail(FSDA_E_WORKSPACE, "chunk table larger than reserved");
+  if (!crow.empty()) {
+    HIP_TRY(hipMemcpyAsync(crow_d, crow.data(), sizeof(int) * crow.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(cbeg_d, cbeg.data(), sizeof(int) * cbeg.size(), hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(hipMemcpyAsync(rc0_d, c0.data(), sizeof(int) * c0.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *nchunk = (int)crow.size();
+  return FSDA_OK;
+}
+
+// The buffers of one batched solve over T columns (interleaved, [row][T]).
+template <typename V>
+struct BBuf {
+  BState* st;
+  BState* hst;   // pinned host mirror
+  double* part;  // BP_N sites of GRID_B x BT_MAX partials
+  V *R, *P, *Q, *X, *t, *u, *lpart;
+  BXtArgs xa;
+  double* site(int k) const { return part + (size_t)k * GRID_B * BT_MAX; }
+};
+
+// t = X src, u = M' t (with the labeled-mean and <t, u> partials), and
+// Q = X^T u + sigma_c P (P NULL: Q = X^T u), all over T columns.
+template <int T, typename V>
+void b_products(fsda_op* op, const BBuf<V>& b, const V* src, const V* P, const int* stop, hipStream_t s, bool timed) {
   constexpr int G = BS / T;
-  const Layout& L = op->L;
   const long long n = op->pb.n, d = op->pb.d;
-  float* t = at<float>(op, L.bT);
-  float* u = at<float>(op, L.bU);
-  float* R = at<float>(op, L.bR);
-  float* P = at<float>(op, L.bP);
-  float* Q = at<float>(op, L.bQ);
-  float* X = at<float>(op, L.bX);
-  float* lpart = at<float>(op, L.blpart);
-  BState* st = op->bst;
+  BState* st = b.st;
   const int gx = grid_b(ceil_div(n, G));
-  const int gs = grid_b(ceil_div(d, G));
   const bool lab = has_lab_term(op);
-  const int* stop = &st->stop;
-  launch(op, KC_BX, s, [&] {
+  launch(op, timed ? KC_BX : KC_OTHER, s, [&] {
     if (lab)
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, float, true>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol,
-                         (int)n, P, BEpiX<T, float, true>{t, op->labw, 1, 0}, stop, st->cm, bpart(op, BP_X));
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, V, true>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol, (int)n,
+                         src, BEpiX<T, V, true>{b.t, op->labw, 1, 0}, stop, st->cm, b.site(BP_X));
     else
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, float, false>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol,
-                         (int)n, P, BEpiX<T, float, false>{t, nullptr, 1, 0}, stop, st->cm, bpart(op, BP_X));
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, V, false>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol,
+                         (int)n, src, BEpiX<T, V, false>{b.t, nullptr, 1, 0}, stop, st->cm, b.site(BP_X));
   });
-  if (lab) hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, stop, bpart(op, BP_X), gx, st->cm);
-  launch(op, KC_BS, s, [&] {
+  if (lab) hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, stop, b.site(BP_X), gx, st->cm);
+  launch(op, timed ? KC_BS : KC_OTHER, s, [&] {
     if (lab)
-      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, float, true>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr,
-                         op->pb.s_col, (int)n, t,
-                         BEpiLap<T, float, true>{t, op->labw, 1, 0, op->pb.s_rowptr, u, op->pb.alpha, 0.f}, stop,
-                         st->cm, bpart(op, BP_TU));
+      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, V, true>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr, op->pb.s_col,
+                         (int)n, b.t, BEpiLap<T, V, true>{b.t, op->labw, 1, 0, op->pb.s_rowptr, b.u, op->pb.alpha, (V)0},
+                         stop, st->cm, b.site(BP_TU));
     else
-      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, float, false>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr,
-                         op->pb.s_col, (int)n, t,
-                         BEpiLap<T, float, false>{t, nullptr, 1, 0, op->pb.s_rowptr, u, op->pb.alpha, 0.f}, stop,
-                         st->cm, bpart(op, BP_TU));
+      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, V, false>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr,
+                         op->pb.s_col, (int)n, b.t,
+                         BEpiLap<T, V, false>{b.t, nullptr, 1, 0, op->pb.s_rowptr, b.u, op->pb.alpha, (V)0}, stop,
+                         st->cm, b.site(BP_TU));
   });
-  hipLaunchKernelGGL(bk_step_a<T>, dim3(1), dim3(BS), 0, s, st, bpart(op, BP_TU), gx, bpart(op, BP_PP), gs);
-  const BXtArgs xa{op->xt_rowptr, op->xt_col, (int)d, op->nmed, op->bnchunk, at<int>(op, L.bcrow),
-                   at<int>(op, L.bcbeg), at<int>(op, L.brc0)};
-  const int gxt = grid_b(op->bnchunk + ceil_div(d - op->nmed, G));
-  launch(op, KC_BXT, s, [&] {
-    hipLaunchKernelGGL((bk_xt<T, float>), dim3(gxt), dim3(BS), 0, s, xa, lpart, u, P, Q, 0LL, st->sigma, stop);
-    if (op->nmed > 0)
-      hipLaunchKernelGGL((bk_xt_rows<T, float>), dim3(grid_b(op->nmed)), dim3(BS), 0, s, xa, lpart, P, Q, 0LL,
+  const int gxt = grid_b(b.xa.nchunk + ceil_div(d - b.xa.nmed, G));
+  launch(op, timed ? KC_BXT : KC_OTHER, s, [&] {
+    hipLaunchKernelGGL((bk_xt<T, V>), dim3(gxt), dim3(BS), 0, s, b.xa, b.lpart, b.u, P, b.Q, 0LL, st->sigma, stop);
+    if (b.xa.nmed > 0)
+      hipLaunchKernelGGL((bk_xt_rows<T, V>), dim3(grid_b(b.xa.nmed)), dim3(BS), 0, s, b.xa, b.lpart, P, b.Q, 0LL,
                          st->sigma, stop);
   });
+}
+
+// One iteration over T columns: the products, a, R -= a Q and X += a P, b and
+// the stop tests, P = R + b P.
+template <int T, typename V>
+void b_iteration(fsda_op* op, const BBuf<V>& b, hipStream_t s, int tag) {
+  op->cur_tag = tag;
+  constexpr int G = BS / T;
+  const long long n = op->pb.n, d = op->pb.d;
+  BState* st = b.st;
+  const int gx = grid_b(ceil_div(n, G));
+  const int gs = grid_b(ceil_div(d, G));
+  b_products<T, V>(op, b, b.P, b.P, &st->stop, s, true);
+  // (the products' TU partials and the previous direction update's PP partials)
+  hipLaunchKernelGGL(bk_step_a<T>, dim3(1), dim3(BS), 0, s, st, b.site(BP_TU), gx, b.site(BP_PP), gs);
   launch(op, KC_BRESID, s, [&] {
-    hipLaunchKernelGGL(bk_resid<T>, dim3(gs), dim3(BS), 0, s, st, Q, P, R, X, d, bpart(op, BP_RR));
+    hipLaunchKernelGGL((bk_resid<T, V>), dim3(gs), dim3(BS), 0, s, st, b.Q, b.P, b.R, b.X, d, b.site(BP_RR));
   });
-  hipLaunchKernelGGL(bk_step_b<T>, dim3(1), dim3(BS), 0, s, st, bpart(op, BP_RR), gs);
+  hipLaunchKernelGGL(bk_step_b<T>, dim3(1), dim3(BS), 0, s, st, b.site(BP_RR), gs);
   launch(op, KC_BPUPD, s, [&] {
-    hipLaunchKernelGGL(bk_pupdate<T>, dim3(gs), dim3(BS), 0, s, st, R, P, d, bpart(op, BP_PP));
+    hipLaunchKernelGGL((bk_pupdate<T, V>), dim3(gs), dim3(BS), 0, s, st, b.R, b.P, d, b.site(BP_PP));
   });
   op->cur_tag = -1;
 }
 
 // Batched CG over the columns B[c * ldb ..] (FP64, internal order), c < ncol,
 // with the per-column shift, targets and limits already in the host mirror
-// op->hbst.  The solution is left in the FP32 buffer bX ([row][T]); the host
-// mirror receives the final state.
-template <int T>
-int run_batched(fsda_op* op, const double* B, long long ldb, int ncol, hipStream_t s) {
+// b.hst.  The solution is left in b.X; the host mirror receives the final
+// state.  Chunks of B_CHUNK iterations are captured once per (tile, key) into
+// *gexec and replayed.
+template <int T, typename V>
+int run_batched(fsda_op* op, const BBuf<V>& b, const double* B, long long ldb, int ncol, hipGraphExec_t* gexec,
+                const void** gkey, int* gtile, const void* key, hipStream_t s) {
   constexpr int G = BS / T;
   const long long d = op->pb.d;
-  if (op->btab_tile != T) {  // chunk table of the rows of >= BMED nonzeros for this tile
-    const int nmed = op->nmed;
-    const std::vector<int>& rp = op->xt_rp_med;
-    std::vector<int> crow, cbeg, c0(nmed + 1);
-    for (int j = 0; j < nmed; j++) {
-      c0[j] = (int)crow.size();
-      for (int k = rp[j]; k < rp[j + 1]; k += BCHUNK<T>()) {
-        crow.push_back(j);
-        cbeg.push_back(k);
-      }
-    }
-    c0[nmed] = (int)crow.size();
-    if ((long long)crow.size() > op->L.bnchunk_max)
-      return fail(FSDA_E_WORKSPACE, "batched chunk table larger than reserved");
-    if (!crow.empty()) {
-      HIP_TRY(hipMemcpyAsync(at<int>(op, op->L.bcrow), crow.data(), sizeof(int) * crow.size(), hipMemcpyHostToDevice,
-                             s));
-      HIP_TRY(hipMemcpyAsync(at<int>(op, op->L.bcbeg), cbeg.data(), sizeof(int) * cbeg.size(), hipMemcpyHostToDevice,
-                             s));
-    }
-    HIP_TRY(hipMemcpyAsync(at<int>(op, op->L.brc0), c0.data(), sizeof(int) * c0.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    op->bnchunk = (int)crow.size();
-    op->btab_tile = T;
-  }
-  BState* h = op->hbst;
+  BState* h = b.hst;
   h->ncol = ncol;
-  h->iter = h->stop = h->status = 0;
-  HIP_TRY(hipMemcpyAsync(op->bst, h, sizeof(BState), hipMemcpyHostToDevice, s));
+  h->iter = h->stop = h->status = h->zero = 0;
+  HIP_TRY(hipMemcpyAsync(b.st, h, sizeof(BState), hipMemcpyHostToDevice, s));
   const int gs = grid_b(ceil_div(d, G));
-  hipLaunchKernelGGL(bk_init<T>, dim3(gs), dim3(BS), 0, s, B, ldb, ncol, at<float>(op, op->L.bR),
-                     at<float>(op, op->L.bP), at<float>(op, op->L.bX), d, bpart(op, BP_PP));
-  hipLaunchKernelGGL(bk_init_done<T>, dim3(1), dim3(BS), 0, s, op->bst, bpart(op, BP_PP), gs);
+  hipLaunchKernelGGL((bk_init<T, V>), dim3(gs), dim3(BS), 0, s, B, ldb, ncol, b.R, b.P, b.X, d, b.site(BP_PP));
+  hipLaunchKernelGGL(bk_init_done<T>, dim3(1), dim3(BS), 0, s, b.st, b.site(BP_PP), gs);
   HIP_TRY(hipGetLastError());
   bool graph = op->use_graph != 0 && !op->tk_on;
-  if (graph && (!op->bgexec || op->bg_tile != T)) {
-    if (op->bgexec) (void)hipGraphExecDestroy(op->bgexec);
-    op->bgexec = nullptr;
+  if (graph && (!*gexec || *gtile != T || *gkey != key)) {
+    if (*gexec) (void)hipGraphExecDestroy(*gexec);
+    *gexec = nullptr;
     hipGraph_t gr = nullptr;
     HIP_TRY(hipStreamBeginCapture(op->cap, hipStreamCaptureModeThreadLocal));
-    for (int j = 0; j < B_CHUNK; j++) b_iteration<T>(op, op->cap, j);
+    for (int j = 0; j < B_CHUNK; j++) b_iteration<T, V>(op, b, op->cap, j);
     const hipError_t ce = hipStreamEndCapture(op->cap, &gr);
     hipError_t ie = hipErrorUnknown;
     if (ce == hipSuccess) {
-      ie = hipGraphInstantiate(&op->bgexec, gr, nullptr, nullptr, 0);
+      ie = hipGraphInstantiate(gexec, gr, nullptr, nullptr, 0);
       (void)hipGraphDestroy(gr);
     }
     if (ce != hipSuccess || ie != hipSuccess) {  // direct launches of the same kernels
-      op->bgexec = nullptr;
+      *gexec = nullptr;
       (void)hipGetLastError();
       graph = false;
     } else {
-      op->bg_tile = T;
+      *gtile = T;
+      *gkey = key;
     }
   }
   const size_t off = offsetof(BState, iter);
@@ -865,13 +883,13 @@ int run_batched(fsda_op* op, const double* B, long long ldb, int ncol, hipStream
   int done_iters = 0;
   for (int c = 0; c < max_chunks; c++) {
     if (graph) {
-      HIP_TRY(hipGraphLaunch(op->bgexec, s));
+      HIP_TRY(hipGraphLaunch(*gexec, s));
     } else {
-      for (int j = 0; j < B_CHUNK; j++) b_iteration<T>(op, s, j);
+      for (int j = 0; j < B_CHUNK; j++) b_iteration<T, V>(op, b, s, j);
     }
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(h) + off, reinterpret_cast<char*>(op->bst) + off,
-                           4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(h) + off, reinterpret_cast<char*>(b.st) + off, 4 * sizeof(int),
+                           hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (op->tk_on) {
       const int trc = tk_flush(op, h->iter - done_iters);
@@ -880,8 +898,33 @@ int run_batched(fsda_op* op, const double* B, long long ldb, int ncol, hipStream
     done_iters = h->iter;
     if (h->stop) break;
   }
-  HIP_TRY(hipMemcpyAsync(h, op->bst, sizeof(BState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h, b.st, sizeof(BState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  return FSDA_OK;
+}
+
+// The FP32 buffers of the mixed path's refinement (in the handle's workspace,
+// with the chunk table for tile T built on first use).
+template <int T>
+int refine_buffers(fsda_op* op, BBuf<float>* b, hipStream_t s) {
+  const Layout& L = op->L;
+  if (op->btab_tile != T) {
+    int rc = chunk_table<T>(op, at<int>(op, L.bcrow), at<int>(op, L.bcbeg), at<int>(op, L.brc0), &op->bnchunk, s);
+    if (rc) return rc;
+    op->btab_tile = T;
+  }
+  b->st = op->bst;
+  b->hst = op->hbst;
+  b->part = at<double>(op, L.bpart);
+  b->R = at<float>(op, L.bR);
+  b->P = at<float>(op, L.bP);
+  b->Q = at<float>(op, L.bQ);
+  b->X = at<float>(op, L.bX);
+  b->t = at<float>(op, L.bT);
+  b->u = at<float>(op, L.bU);
+  b->lpart = at<float>(op, L.blpart);
+  b->xa = BXtArgs{op->xt_rowptr, op->xt_col, (int)op->pb.d, op->nmed, op->bnchunk, at<int>(op, L.bcrow),
+                  at<int>(op, L.bcbeg), at<int>(op, L.brc0)};
   return FSDA_OK;
 }
 
@@ -897,7 +940,9 @@ int refine(fsda_op* op, const double* rhs, const double* betas, int nshift, doub
   const long long d = op->pb.d;
   double* R64 = at<double>(op, op->L.b64);
   State* h = op->hst;
-  int rc;
+  BBuf<float> b;
+  int rc = refine_buffers<T>(op, &b, s);
+  if (rc) return rc;
   for (int round = 0; round < MIXED_ROUNDS; round++) {
     if ((rc = residuals(op, rhs, betas, nshift, W, s, R64, op->L.ldd))) return rc;
     HIP_TRY(hipMemcpyAsync(h, op->st, sizeof(State), hipMemcpyDeviceToHost, s));
@@ -915,7 +960,9 @@ int refine(fsda_op* op, const double* rhs, const double* betas, int nshift, doub
     if (all || !(h->bnorm > 0.0)) break;
     hb->trel = MIXED_FLOOR;
     hb->maxit = maxit;
-    if ((rc = run_batched<T>(op, R64, op->L.ldd, nshift, s))) return rc;
+    if ((rc = run_batched<T, float>(op, b, R64, op->L.ldd, nshift, &op->bgexec, &op->bg_key, &op->bg_tile, nullptr,
+                                    s)))
+      return rc;
     if (hb->status == FSDA_E_BREAKDOWN) {
       *status = FSDA_E_BREAKDOWN;
       return FSDA_OK;
@@ -923,11 +970,113 @@ int refine(fsda_op* op, const double* rhs, const double* betas, int nshift, doub
     if (hb->status == FSDA_NOT_CONVERGED) *status = FSDA_NOT_CONVERGED;
     for (int k = 0; k < nshift; k++) extra[k] += hb->conv[k];
     constexpr int G = BS / T;
-    hipLaunchKernelGGL(bk_add<T>, dim3(grid_b(ceil_div(d, G))), dim3(BS), 0, s, at<float>(op, op->L.bX), W, d, nshift,
-                       d);
+    hipLaunchKernelGGL((bk_add<T, float>), dim3(grid_b(ceil_div(d, G))), dim3(BS), 0, s, b.X, W, d, nshift, d);
     HIP_TRY(hipGetLastError());
   }
   return FSDA_OK;
+}
+
+// ---- independent columns in FP64 (fsda_solve_columns) ----------------------
+
+struct CLayout {
+  size_t st, part, b64, R, P, Q, X, t, u, lpart, crow, cbeg, rc0, total;
+  long long ld;
+};
+
+void clayout(const fsda_op* op, int T, int ncol, CLayout* L) {
+  const long long n = op->pb.n, z = std::max<long long>(op->pb.x_nnz, 1);
+  const size_t ld = (size_t)op->L.ldd;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t a_ = o;
+    o = a256(o + bytes);
+    return a_;
+  };
+  L->ld = op->L.ldd;
+  L->st = take(sizeof(BState));
+  L->part = take(sizeof(double) * BP_N * GRID_B * BT_MAX);
+  L->b64 = take(8 * ld * ncol);
+  L->R = take(8 * ld * T);
+  L->P = take(8 * ld * T);
+  L->Q = take(8 * ld * T);
+  L->X = take(8 * ld * T);
+  L->t = take(8 * (size_t)n * T);
+  L->u = take(8 * (size_t)n * T);
+  L->lpart = take(8 * (size_t)op->L.bnchunk_max * T);
+  L->crow = take(4 * (size_t)op->L.bnchunk_max);
+  L->cbeg = take(4 * (size_t)op->L.bnchunk_max);
+  L->rc0 = take(4 * (size_t)(z / BMED + 2));
+  L->total = o;
+}
+
+template <int T>
+int run_columns(fsda_op* op, char* ws, const CLayout& L, const double* B, const double* sigmas, int ncol, double rtol,
+                int maxit, double* Xout, int* iters, double* relres, hipStream_t s) {
+  const long long d = op->pb.d;
+  BBuf<double> b;
+  b.st = reinterpret_cast<BState*>(ws + L.st);
+  b.hst = op->hbst;
+  b.part = reinterpret_cast<double*>(ws + L.part);
+  b.R = reinterpret_cast<double*>(ws + L.R);
+  b.P = reinterpret_cast<double*>(ws + L.P);
+  b.Q = reinterpret_cast<double*>(ws + L.Q);
+  b.X = reinterpret_cast<double*>(ws + L.X);
+  b.t = reinterpret_cast<double*>(ws + L.t);
+  b.u = reinterpret_cast<double*>(ws + L.u);
+  b.lpart = reinterpret_cast<double*>(ws + L.lpart);
+  int* crow = reinterpret_cast<int*>(ws + L.crow);
+  int* cbeg = reinterpret_cast<int*>(ws + L.cbeg);
+  int* rc0 = reinterpret_cast<int*>(ws + L.rc0);
+  int nchunk = 0;
+  int rc = chunk_table<T>(op, crow, cbeg, rc0, &nchunk, s);
+  if (rc) return rc;
+  b.xa = BXtArgs{op->xt_rowptr, op->xt_col, (int)d, op->nmed, nchunk, crow, cbeg, rc0};
+  // right-hand sides in the internal feature order
+  double* B64 = reinterpret_cast<double*>(ws + L.b64);
+  for (int c = 0; c < ncol; c++)
+    hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, B + (long long)c * d, op->new2old,
+                       B64 + (long long)c * L.ld, d);
+  BState* h = b.hst;
+  std::memset(h, 0, sizeof(BState));
+  for (int c = 0; c < ncol; c++) h->sigma[c] = sigmas[c];
+  h->trel = rtol;
+  h->maxit = maxit;
+  if ((rc = run_batched<T, double>(op, b, B64, L.ld, ncol, &op->cgexec, &op->cg_key, &op->cg_tile, ws, s))) return rc;
+  const int status = h->status;
+  // true FP64 residuals ||b_c - A(sigma_c) x_c||
+  constexpr int G = BS / T;
+  const int gs = grid_b(ceil_div(d, G));
+  const int* zero = &b.st->zero;
+  b_products<T, double>(op, b, b.X, nullptr, zero, s, false);
+  hipLaunchKernelGGL((bk_resnorm<T, double>), dim3(gs), dim3(BS), 0, s, b.st, B64, L.ld, ncol, b.Q, b.X, d,
+                     b.site(BP_RR));
+  hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, zero, b.site(BP_RR), gs, b.st->res2);
+  hipLaunchKernelGGL((bk_unpack<T, double>), dim3(grid_for((long long)ncol * d, 8192)), dim3(BS), 0, s, b.X,
+                     op->old2new, Xout, ncol, d);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h, b.st, sizeof(BState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (op->tk_on) {
+    const int trc = tk_flush(op, 1 << 30);
+    if (trc) return trc;
+  }
+  for (int c = 0; c < ncol; c++) {
+    iters[c] = h->conv[c];
+    relres[c] = h->bnorm[c] > 0.0 ? std::sqrt(h->res2[c]) / h->bnorm[c] : 0.0;
+  }
+  if (status == FSDA_E_BREAKDOWN) return fail(FSDA_E_BREAKDOWN, "CG breakdown: <p, A p> <= 0 or not finite");
+  return status == FSDA_NOT_CONVERGED ? FSDA_NOT_CONVERGED : FSDA_OK;
+}
+
+int columns_any(int T, fsda_op* op, char* ws, const CLayout& L, const double* B, const double* sigmas, int ncol,
+                double rtol, int maxit, double* X, int* iters, double* relres, hipStream_t s) {
+  switch (T) {
+    case 4: return run_columns<4>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s);
+    case 8: return run_columns<8>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s);
+    case 16: return run_columns<16>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s);
+    case 32: return run_columns<32>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s);
+    default: return run_columns<64>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s);
+  }
 }
 
 int refine_any(fsda_op* op, const double* rhs, const double* betas, int nshift, double rtol, int maxit, double* W,
@@ -990,31 +1139,6 @@ struct TPtr {
 };
 
 double* tpart(const TPtr& p, int site) { return p.part + (size_t)site * GRID_B * BT_MAX; }
-
-// chunk table of the X^T rows of >= BMED nonzeros for tile T (batched product)
-template <int T>
-int t_chunk_table(fsda_op* op, int* crow_d, int* cbeg_d, int* rc0_d, int* nchunk, hipStream_t s) {
-  const int nmed = op->nmed;
-  const std::vector<int>& rp = op->xt_rp_med;
-  std::vector<int> crow, cbeg, c0(nmed + 1);
-  for (int j = 0; j < nmed; j++) {
-    c0[j] = (int)crow.size();
-    for (int k = rp[j]; k < rp[j + 1]; k += BCHUNK<T>()) {
-      crow.push_back(j);
-      cbeg.push_back(k);
-    }
-  }
-  c0[nmed] = (int)crow.size();
-  if ((long long)crow.size() > op->L.bnchunk_max) return fail(FSDA_E_WORKSPACE, "chunk table larger than reserved");
-  if (!crow.empty()) {
-    HIP_TRY(hipMemcpyAsync(crow_d, crow.data(), sizeof(int) * crow.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(cbeg_d, cbeg.data(), sizeof(int) * cbeg.size(), hipMemcpyHostToDevice, s));
-  }
-  HIP_TRY(hipMemcpyAsync(rc0_d, c0.data(), sizeof(int) * c0.size(), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  *nchunk = (int)crow.size();
-  return FSDA_OK;
-}
 
 // Q (column-major) = X^T M'_c X src for the T columns of src (interleaved), with
 // the products' partials; stop is the flag the launches test.
@@ -1131,7 +1255,7 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
   int* cbeg = reinterpret_cast<int*>(ws + L.cbeg);
   int* rc0 = reinterpret_cast<int*>(ws + L.rc0);
   int nchunk = 0;
-  int rc = t_chunk_table<T>(op, crow, cbeg, rc0, &nchunk, s);
+  int rc = chunk_table<T>(op, crow, cbeg, rc0, &nchunk, s);
   if (rc) return rc;
   p.xa = BXtArgs{op->xt_rowptr, op->xt_col, (int)d, op->nmed, nchunk, crow, cbeg, rc0};
 
@@ -1711,6 +1835,118 @@ int fsda_regression_solve(fsda_op* op, const double* z, const double* betas, int
   }
   if (status == FSDA_E_BREAKDOWN) return fail(FSDA_E_BREAKDOWN, "CG breakdown: <p, A p> <= 0 or not finite");
   return status == FSDA_NOT_CONVERGED ? FSDA_NOT_CONVERGED : FSDA_OK;
+}
+
+int fsda_columns_workspace_size(const fsda_op* op, int ncol, size_t* bytes) {
+  if (!op || !bytes) return fail(FSDA_E_ARG, "NULL argument");
+  if (ncol < 1 || ncol > FSDA_MAX_TARGETS) return fail(FSDA_E_ARG, "ncol outside 1..FSDA_MAX_TARGETS");
+  CLayout L;
+  clayout(op, batch_tile(ncol), ncol, &L);
+  *bytes = L.total;
+  return FSDA_OK;
+}
+
+int fsda_solve_columns(fsda_op* op, const double* B, const double* sigmas, int ncol, double rtol, int maxit,
+                       void* workspace, size_t ws_bytes, double* X, int* iters, double* relres, void* stream) {
+  if (!op || !B || !sigmas || !X || !iters || !relres) return fail(FSDA_E_ARG, "NULL argument");
+  size_t need = 0;
+  int rc = fsda_columns_workspace_size(op, ncol, &need);
+  if (rc) return rc;
+  if (!(rtol > 0.0)) return fail(FSDA_E_RANGE, "rtol must be > 0");
+  if (maxit < 1) return fail(FSDA_E_RANGE, "maxit must be >= 1");
+  for (int c = 0; c < ncol; c++)
+    if (!(sigmas[c] > 0.0) || !std::isfinite(sigmas[c])) return fail(FSDA_E_RANGE, "every shift must be finite and > 0");
+  if (!workspace || ws_bytes < need)
+    return fail(FSDA_E_WORKSPACE, "workspace NULL or smaller than fsda_columns_workspace_size()");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(FSDA_E_WORKSPACE, "workspace not 256-byte aligned");
+  const int T = batch_tile(ncol);
+  CLayout L;
+  clayout(op, T, ncol, &L);
+  return columns_any(T, op, static_cast<char*>(workspace), L, B, sigmas, ncol, rtol, maxit, X, iters, relres,
+                     static_cast<hipStream_t>(stream));
+}
+
+int fsda_holdout(fsda_op* op, const double* W, int nshift, const int32_t* ho_idx, const double* ho_y, int64_t n_ho,
+                 double* loss, double* G, void* stream) {
+  if (!op || !W || !ho_idx || !ho_y || !loss) return fail(FSDA_E_ARG, "NULL argument");
+  if (nshift < 1 || nshift > FSDA_MAX_SHIFTS) return fail(FSDA_E_ARG, "nshift outside 1..FSDA_MAX_SHIFTS");
+  if (n_ho < 1 || n_ho > op->pb.n) return fail(FSDA_E_ARG, "need 1 <= n_ho <= n");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long n = op->pb.n, d = op->pb.d;
+  int* flag = reinterpret_cast<int*>(op->hist);
+  int* mark = reinterpret_cast<int*>(op->bu);  // n counters (bu holds max(n, d) doubles)
+  hipLaunchKernelGGL(k_fill_i, dim3(grid_for(n, 2048)), dim3(BS), 0, s, mark, n, 0);
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, flag, 1LL, 0);
+  hipLaunchKernelGGL(k_ho_check, dim3(grid_for(n_ho, 1024)), dim3(BS), 0, s, ho_idx, (long long)n_ho, n, mark, flag);
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hflag & 1) return fail(FSDA_E_ARG, "held-out index out of range");
+  if (hflag & 2) return fail(FSDA_E_ARG, "held-out index repeated");
+  double* v = op->u;                     // sample-space adjoint load
+  double* sums = op->hist + 64;          // per shift: sum of squared errors
+  const int gh = grid_for(n_ho, GRID_STREAM);
+  for (int k = 0; k < nshift; k++) {
+    const double* w = W + (long long)k * d;
+    run_rows(op, op->px_user, w, EpiX<double, false>{op->t, nullptr}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
+    hipLaunchKernelGGL(k_fill_d, dim3(grid_for(n, 2048)), dim3(BS), 0, s, v, n, 0.0);
+    hipLaunchKernelGGL(k_ho_resid, dim3(gh), dim3(BS), 0, s, op->t, ho_idx, ho_y, (long long)n_ho, v,
+                       op->part + SITE_R * NPART);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, op->part + SITE_R * NPART, gh, sums + k);
+    if (G) {  // G_k = X^T v (internal order) -> caller's order
+      run_xt(op, v, EpiXT<double, false>{op->q, nullptr, 0.0, nullptr}, 0, true, s, KC_OTHER);
+      hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, op->q, op->old2new, G + (long long)k * d,
+                         d);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  std::vector<double> hs(nshift);
+  HIP_TRY(hipMemcpyAsync(hs.data(), sums, sizeof(double) * nshift, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int k = 0; k < nshift; k++) loss[k] = 0.5 * hs[k] / (double)n_ho;
+  return FSDA_OK;
+}
+
+int fsda_hypergradient(fsda_op* op, const double* W, const double* Lambda, const double* betas, int nshift,
+                       double* dlogbeta, double* dalpha, void* stream) {
+  if (!op || !W || !Lambda || !betas || !dlogbeta || !dalpha) return fail(FSDA_E_ARG, "NULL argument");
+  if (nshift < 1 || nshift > FSDA_MAX_SHIFTS) return fail(FSDA_E_ARG, "nshift outside 1..FSDA_MAX_SHIFTS");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long n = op->pb.n, d = op->pb.d;
+  double* sums = op->hist + 64;  // per shift: <l, w>, <X l, L X w>, sum w (X l)(X w), sum w X l, sum w X w
+  const int gd = grid_for(d, GRID_STREAM), gn = grid_for(n, GRID_STREAM);
+  double* pA = op->part + SITE_R * NPART;
+  double* pB = op->part + SITE_PP * NPART;
+  double* pC = op->part + SITE_TU * NPART;
+  double* pL = op->part + SITE_XT * NPART;
+  for (int k = 0; k < nshift; k++) {
+    const double* w = W + (long long)k * d;
+    const double* l = Lambda + (long long)k * d;
+    double* out = sums + 5 * k;
+    hipLaunchKernelGGL(k_dot, dim3(gd), dim3(BS), 0, s, l, w, d, pA);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pA, gd, out + 0);
+    run_rows(op, op->px_user, w, EpiX<double, false>{op->t, nullptr}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
+    run_rows(op, op->px_user, l, EpiX<double, false>{op->u, nullptr}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
+    run_rows(op, op->ps, op->t, EpiLapDot{op->t, op->u, op->pb.s_rowptr}, pL, 0, s, KC_OTHER);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pL, op->ps.grid, out + 1);
+    hipLaunchKernelGGL(k_labdots, dim3(gn), dim3(BS), 0, s, op->labw, op->u, op->t, n, pA, pB, pC);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pA, gn, out + 2);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pB, gn, out + 3);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pC, gn, out + 4);
+  }
+  HIP_TRY(hipGetLastError());
+  std::vector<double> hs(5 * nshift);
+  HIP_TRY(hipMemcpyAsync(hs.data(), sums, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double l = (double)op->pb.n_lab;
+  for (int k = 0; k < nshift; k++) {
+    const double* o = hs.data() + 5 * k;
+    dlogbeta[k] = -betas[k] * o[0];
+    // <X l, (P_l - 1_l 1_l^T / l) X w> = l (sum w a b - (sum w a)(sum w b)) with w = 1/l on labeled rows
+    const double lab = l * (o[2] - o[3] * o[4]);
+    dalpha[k] = -(o[1] - lab);
+  }
+  return FSDA_OK;
 }
 
 int fsda_batch_workspace_size(const fsda_op* op, int ntarget, int nshift, int chunk, size_t* bytes) {

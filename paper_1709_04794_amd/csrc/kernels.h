@@ -338,6 +338,72 @@ __global__ __launch_bounds__(BS) void k_wsum(const double* __restrict__ w, const
 }
 
 // ---------------------------------------------------------------------------
+// hold-out loss and hypergradient terms
+// ---------------------------------------------------------------------------
+
+// flag bits: 1 held-out index out of range, 2 repeated (mark: n zeroed counters)
+__global__ void k_ho_check(const int* idx, long long nho, long long n, int* mark, int* flag) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < nho; k += (long long)gridDim.x * blockDim.x) {
+    const int i = idx[k];
+    if (i < 0 || i >= n) {
+      atomicOr(flag, 1);
+      continue;
+    }
+    if (atomicAdd(&mark[i], 1) != 0) atomicOr(flag, 2);
+  }
+}
+
+// e_k = t[idx_k] - y_k: v[idx_k] = e_k / n_ho (v zero elsewhere); partials of sum e_k^2.
+__global__ __launch_bounds__(BS) void k_ho_resid(const double* __restrict__ t, const int* __restrict__ idx,
+                                                 const double* __restrict__ y, long long nho, double* v,
+                                                 double* part) {
+  double acc = 0.0;
+  for (long long k = (long long)blockIdx.x * BS + threadIdx.x; k < nho; k += (long long)gridDim.x * BS) {
+    const double e = t[idx[k]] - y[k];
+    v[idx[k]] = e / (double)nho;
+    acc += e * e;
+  }
+  write_partial(part, blockIdx.x, acc);
+}
+
+// partials of <a, b>
+__global__ __launch_bounds__(BS) void k_dot(const double* __restrict__ a, const double* __restrict__ b, long long n,
+                                            double* part) {
+  double acc = 0.0;
+  for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < n; j += (long long)gridDim.x * BS) acc += a[j] * b[j];
+  write_partial(part, blockIdx.x, acc);
+}
+
+// partials of sum w a b, sum w a, sum w b (w = 1/l on labeled rows)
+__global__ __launch_bounds__(BS) void k_labdots(const double* __restrict__ w, const double* __restrict__ a,
+                                                const double* __restrict__ b, long long n, double* p0, double* p1,
+                                                double* p2) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < n; j += (long long)gridDim.x * BS) {
+    const double wj = w[j];
+    s0 += wj * a[j] * b[j];
+    s1 += wj * a[j];
+    s2 += wj * b[j];
+  }
+  write_partial(p0, blockIdx.x, s0);
+  write_partial(p1, blockIdx.x, s1);
+  write_partial(p2, blockIdx.x, s2);
+}
+
+// Rows of S over src = t_w: reduction <t_l, L t_w>, (L t_w)_r = d_r t_w,r - (S t_w)_r.
+struct EpiLapDot {
+  using V = double;
+  const double* tw;
+  const double* tl;
+  const int* srowptr;
+  static constexpr bool kReduce = true;
+  __device__ void prepare(const State*) {}
+  __device__ double row(int r, double v) const {
+    return tl[r] * ((double)(srowptr[r + 1] - srowptr[r]) * tw[r] - v);
+  }
+};
+
+// ---------------------------------------------------------------------------
 // sparse products, lanes per row
 // ---------------------------------------------------------------------------
 //

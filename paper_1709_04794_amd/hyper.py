@@ -1,0 +1,73 @@
+"""Hold-out loss of the FSDA ratings as a differentiable function of (log beta, alpha).
+
+``HoldoutLoss.apply(log_beta, alpha, objective)`` returns the loss per shift
+H_s = 1/2 ||X_ho w_s - y_ho||^2 / n_ho, w_s the solution for beta_s =
+exp(log_beta_s) on the operator with weight alpha.  Its backward pass is the
+adjoint method: one batched solve A(beta_s) lambda_s = dH_s/dw_s for all
+shifts (fsda_solve_columns), then dH_s/dlog beta_s = -beta_s <lambda_s, w_s> and
+dH_s/dalpha = -<X lambda_s, [L - (P_l - 1_l 1_l^T/l)] X w_s>
+(fsda_hypergradient).  Every step runs in the library's kernels; this module
+only moves arguments.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import Operator, OK, NOT_CONVERGED
+
+
+class Objective:
+    """The fixed parts of the objective: the problem (X, S, labeled set), the
+    held-out rows and their targets, and the solve tolerance.  Operators are
+    built per alpha and cached."""
+
+    def __init__(self, pb, ho_idx, ho_y, rtol: float = 1e-10, maxit: int = 100000, device: str = "cuda"):
+        import torch
+        self.pb = pb
+        self.rtol, self.maxit = float(rtol), int(maxit)
+        self.ho_idx = torch.as_tensor(np.ascontiguousarray(ho_idx, dtype=np.int32)).to(device)
+        self.ho_y = torch.as_tensor(np.ascontiguousarray(ho_y, dtype=np.float64)).to(device)
+        self._ops = {}
+
+    def operator(self, alpha: float) -> Operator:
+        a = float(alpha)
+        if a not in self._ops:
+            self._ops[a] = Operator.from_problem(self.pb, alpha=a, max_shifts=64)
+        return self._ops[a]
+
+
+def _torch_function():
+    import torch
+
+    class HoldoutLoss(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, log_beta, alpha, objective):
+            betas = torch.exp(log_beta.detach()).cpu().numpy().astype(np.float64)
+            op = objective.operator(float(alpha))
+            W, iters, relres, st = op.solve(betas, rtol=objective.rtol, maxit=objective.maxit)
+            if st not in (OK, NOT_CONVERGED):
+                raise RuntimeError("solve failed with status %d" % st)
+            loss, G = op.holdout(W, objective.ho_idx, objective.ho_y, gradient=True)
+            ctx.objective, ctx.alpha, ctx.betas = objective, float(alpha), betas
+            ctx.W, ctx.G = W, G
+            return torch.as_tensor(loss, dtype=log_beta.dtype, device=log_beta.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            op = ctx.objective.operator(ctx.alpha)
+            Lam, iters, relres, st = op.solve_columns(ctx.G, ctx.betas, rtol=ctx.objective.rtol,
+                                                      maxit=ctx.objective.maxit)
+            dlb, da = op.hypergradient(ctx.W, Lam, ctx.betas)
+            g = grad_out.detach().cpu().numpy()
+            grad_lb = torch.as_tensor(g * dlb, dtype=grad_out.dtype, device=grad_out.device)
+            grad_a = torch.as_tensor(float((g * da).sum()), dtype=grad_out.dtype, device=grad_out.device)
+            return grad_lb, grad_a, None
+
+    return HoldoutLoss
+
+
+HoldoutLoss = None
+try:  # torch is a dependency of the binding; keep the import lazy-tolerant for docs tools
+    HoldoutLoss = _torch_function()
+except ImportError:  # pragma: no cover
+    pass
