@@ -45,9 +45,11 @@ def algorithmic_bytes(kernel: int, pb, nshift: int, chunk: int) -> float:
         return 4 * (n + 1) + 4 * z + 8 * d + 8 * n + lab
     if kernel == fsda.K_S:      # rowptr, col, t (gathered), u written
         return 4 * (n + 1) + 4 * g + 8 * n + 8 * n + lab
-    if kernel == fsda.K_XT:     # rowptr, col, u (gathered), p read, q written
-        return 4 * (d + 1) + 4 * z + 8 * n + 16 * d
-    if kernel in (fsda.K_RESID, fsda.K_PUPD):  # two vectors in, one out
+    if kernel == fsda.K_XT:     # rowptr, col, u (gathered), p and r read, r_{i+1} written
+        return 4 * (d + 1) + 4 * z + 8 * n + 24 * d
+    if kernel == fsda.K_RESID:  # the long rows of X^T: their p, r in and r_{i+1} out (chunk sums aside)
+        return 0.0
+    if kernel == fsda.K_PUPD:   # r_{i+1}, p in; p out
         return 24 * d
     if kernel == fsda.K_FOLD:   # W, P in and out for every shift, chunk residuals in
         return 32 * nshift * d + 8 * chunk * d
@@ -77,8 +79,9 @@ def measured_traffic(kernel: int, workload: str):
     return None
 
 
-KNAMES = {0: "k_rows<EpiX> (t = X p)", 1: "k_rows<EpiLap> (u = M' t)", 2: "k_xt<EpiXT> (q = X^T u + s p)",
-          4: "k_resid", 5: "k_pupdate", 6: "k_fold"}
+KNAMES = {0: "k_rows<EpiX> (t = X p)", 1: "k_rows<EpiLap> (u = M' t)",
+          2: "k_xt<EpiXTR> (q = X^T u + s p, r -= a q)", 4: "k_long (long rows of X^T, zeta step)",
+          5: "k_pupdate", 6: "k_fold"}
 
 
 def cpu_baseline(pb, budget_s: float):

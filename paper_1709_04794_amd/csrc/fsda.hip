@@ -80,13 +80,14 @@ int batch_tile(int ncol) { return std::max(4, pow2_at_least(ncol)); }
 
 struct Layout {
   size_t st, part, hist, labw, ycen, zw, t, u, b, p, q, bu, new2old, old2new, xcol, xt_rowptr, xt_col;
+  size_t xmask, xrrowptr, xrcol;  // X split into mask features and the rest
   size_t chunk_row, chunk_beg, lpart, row_chunk0;
   size_t uni;
   size_t ring, P;                                                         // union: solve
   size_t bst, bpart, b64, bR, bP, bQ, bX, bT, bU, blpart, bcrow, bcbeg, brc0;  // union: refinement (mixed)
   long long bnchunk_max;
   int btile;
-  size_t mark, cnt, iota, cnt_sorted, rowid, keys, sort_tmp, sort_bytes;  // union: build
+  size_t mark, cnt, iota, cnt_sorted, rowid, keys, sort_tmp, sort_bytes, mcnt;  // union: build
   size_t total;
   long long ldd;  // d padded: stride of the feature-space vectors of the refinement
   long long ldv;  // max(d, n) padded: stride of the ring and per-shift directions
@@ -123,6 +124,9 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->xcol = take(4 * z);
   L->xt_rowptr = take(4 * (d + 1));
   L->xt_col = take(4 * z);
+  L->xmask = take(8 * n);
+  L->xrrowptr = take(4 * (n + 1));
+  L->xrcol = take(4 * z);
   L->chunk_row = take(4 * (size_t)L->nchunk_max);
   L->chunk_beg = take(4 * (size_t)L->nchunk_max);
   L->lpart = take(8 * (size_t)L->nchunk_max);
@@ -180,8 +184,10 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->keys = u;
   u = a256(u + 4 * (size_t)z);
   L->sort_tmp = u;
-  L->sort_bytes = SORT_RESERVE + 12 * (size_t)z + 12 * (size_t)d;
+  L->sort_bytes = SORT_RESERVE + 12 * (size_t)z + 12 * (size_t)d + 8 * (size_t)n;
   u = a256(u + L->sort_bytes);
+  L->mcnt = u;
+  u = a256(u + 4 * ((size_t)n + 1));
   L->total = std::max(solve_end, u);
 }
 
@@ -228,13 +234,14 @@ struct fsda_op {
   char* ws;
   size_t ws_bytes;
   Layout L;
-  RowPlan px, px_user, ps;
+  RowPlan px, px_user, ps;  // px: mask features + CSR of the others (internal order); px_user: caller's order
   XtPlan pxt;
   State* st;
   State* hst;  // pinned host mirror
   double *part, *hist, *labw, *ycen, *zw, *t, *u, *b, *p, *q, *bu, *ring, *P;
   int *new2old, *old2new, *xcol, *xt_rowptr, *xt_col;
   int npos, nneg;
+  int mtop;  // features held as per-sample masks (the first mtop of the internal order)
   int xt_bins[8];  // rows of X^T with length >= 1024, 512, 256, 64, 16, 4, 1 (sorted order), and d
   // kernel timing: event pairs around the launches of one kernel class; a
   // pair's tag is the iteration index inside its chunk (or -1), so launches
@@ -347,9 +354,10 @@ void run_rows(fsda_op* op, const RowPlan& pl, const typename Epi::V* src, Epi ep
 // (partial slots: k_xt [0, grid), k_assemble [grid, grid + gridL)); without,
 // their chunk sums stay in lpart for k_resid.
 template <class Epi>
-void run_xt(fsda_op* op, const typename Epi::V* src, Epi epi, int solve, bool assemble, hipStream_t s, int cls) {
+void run_xt(fsda_op* op, const typename Epi::V* src, Epi epi, int solve, bool assemble, hipStream_t s, int cls,
+            double* part = nullptr) {
   const XtPlan& pl = op->pxt;
-  double* part = op->part + SITE_XT * NPART;
+  if (!part) part = op->part + SITE_XT * NPART;
   launch(op, cls, s, [&] {
     hipLaunchKernelGGL(k_xt<Epi>, dim3(pl.grid), dim3(BS), 0, s, pl.w, src, epi, op->st, part, solve);
   });
@@ -416,30 +424,45 @@ void iteration(fsda_op* op, int mode, hipStream_t s, int tag) {
   const bool sa = mode == MODE_SA;
   const long long m = sa ? op->pb.n : op->pb.d;
   const int gs = stream_grid(m);
-  const double* sig = &op->st->sigma0;
   int ntu = op->ps.grid;
+  int nrr = gs;  // partials of <r_{i+1}, r_{i+1}>
   if (sa) {
     run_rows(op, op->ps, op->p,
              EpiLapSA{op->p, op->labw, op->pb.s_rowptr, op->q, op->pb.alpha, 0.0, op->part + SITE_X * NPART, gs,
                       0.0},
              op->part + SITE_TU * NPART, 1, s, KC_S);
-  } else if (mode == MODE_REG) {
-    run_rows(op, op->px, p, EpiXReg<V>{as<V>(op->t)}, op->part + SITE_TU * NPART, 1, s, KC_X);
-    run_xt(op, as<V>(op->t), EpiXT<V, false>{q, p, 0.0, sig}, 1, false, s, KC_XT);
-    ntu = op->px.grid;
+    launch(op, KC_RESID, s, [&] {
+      hipLaunchKernelGGL(k_resid<V>, dim3(gs), dim3(BS), 0, s, op->st, q, p, ring, op->L.ldv, m,
+                         op->part + SITE_TU * NPART, ntu, op->part + SITE_PP * NPART, gs, 0, op->pxt.row_chunk0,
+                         op->pxt.w.lpart, op->part + SITE_R * NPART);
+    });
   } else {
-    product_x<V>(op, p, 1, s);
-    product_lap<V>(op, 1, s);
-    run_xt(op, as<V>(op->u), EpiXT<V, false>{q, p, 0.0, sig}, 1, false, s, KC_XT);
+    // t = X p (MODE_FSDA then u = M' t; MODE_REG: u = t); then one pass over X^T
+    // that also updates the residual of every short row, and k_long for the long rows
+    const V* u = as<V>(op->u);
+    if (mode == MODE_REG) {
+      run_rows(op, op->px, p, EpiXReg<V>{as<V>(op->t)}, op->part + SITE_TU * NPART, 1, s, KC_X);
+      ntu = op->px.grid;
+      u = as<V>(op->t);
+    } else {
+      product_x<V>(op, p, 1, s);
+      product_lap<V>(op, 1, s);
+    }
+    run_xt(op, u,
+           EpiXTR<V>{p, ring, op->L.ldv, op->part + SITE_TU * NPART, ntu, op->part + SITE_PP * NPART, gs, 0.0, 0.0,
+                     nullptr, nullptr},
+           1, false, s, KC_XT, op->part + SITE_R * NPART);
+    const int gl = std::max(1, std::min((int)ceil_div(op->pxt.nlong, BS), 64));
+    launch(op, KC_RESID, s, [&] {
+      hipLaunchKernelGGL(k_long<V>, dim3(gl), dim3(BS), 0, s, op->st, p, ring, op->L.ldv, op->pxt.nlong,
+                         op->pxt.row_chunk0, op->pxt.w.lpart, op->part + SITE_TU * NPART, ntu,
+                         op->part + SITE_PP * NPART, gs, op->part + SITE_R * NPART, op->pxt.grid);
+    });
+    nrr = op->pxt.grid + gl;
   }
-  launch(op, KC_RESID, s, [&] {
-    hipLaunchKernelGGL(k_resid<V>, dim3(gs), dim3(BS), 0, s, op->st, q, p, ring, op->L.ldv, m,
-                       op->part + SITE_TU * NPART, ntu, op->part + SITE_PP * NPART, gs, sa ? 0 : op->pxt.nlong,
-                       op->pxt.row_chunk0, op->pxt.w.lpart, op->part + SITE_R * NPART);
-  });
   launch(op, KC_PUPD, s, [&] {
     hipLaunchKernelGGL(k_pupdate<V>, dim3(gs), dim3(BS), 0, s, op->st, ring, p, op->L.ldv, m,
-                       op->part + SITE_R * NPART, gs, op->hist, op->part + SITE_PP * NPART,
+                       op->part + SITE_R * NPART, nrr, op->hist, op->part + SITE_PP * NPART,
                        sa ? op->labw : nullptr, op->part + SITE_X * NPART);
   });
   op->cur_tag = -1;
@@ -547,10 +570,10 @@ int make_xt(fsda_op* op, hipStream_t s) {
   pl.nlong = nlong;
   pl.row_chunk0 = at<int>(op, op->L.row_chunk0);
   op->nmed = op->xt_bins[3];  // rows of >= 64 nonzeros
-  op->xt_rp_med.assign(op->nmed + 1, 0);
-  if (op->nmed > 0) {
-    HIP_TRY(hipMemcpyAsync(op->xt_rp_med.data(), op->xt_rowptr, sizeof(int) * (op->nmed + 1), hipMemcpyDeviceToHost,
-                           s));
+  const int ncopy = std::max(op->nmed, nlong);
+  op->xt_rp_med.assign(ncopy + 1, 0);
+  if (ncopy > 0) {
+    HIP_TRY(hipMemcpyAsync(op->xt_rp_med.data(), op->xt_rowptr, sizeof(int) * (ncopy + 1), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
   if (nlong > 0) {
@@ -1599,11 +1622,33 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
     HIP_TRY(hipStreamSynchronize(s));
     for (int k = 0; k < 7; k++) op->xt_bins[k] = flag_host[k];
     op->xt_bins[7] = (int)d;
+    op->mtop = (int)std::min<long long>(MK, d);
     if ((rc = make_xt(op, s))) return bail(rc);
   }
 
-  // 4. row plans of X (internal and user column order) and of S
-  op->px = one_bin(pb->x_rowptr, op->xcol, n, z);
+  // 4. X in the internal order as per-sample masks of the mask features plus a
+  //    CSR of the other features; row plans of X (internal and user order) and S
+  {
+    unsigned long long* xm = at<unsigned long long>(op, L.xmask);
+    int* rrp = at<int>(op, L.xrrowptr);
+    int* rcol = at<int>(op, L.xrcol);
+    int* mcnt = at<int>(op, L.mcnt);
+    hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, mcnt + n, 1LL, 0);
+    hipLaunchKernelGGL(k_mask_split, dim3(grid_for(n, 2048)), dim3(BS), 0, s, pb->x_rowptr, op->xcol, n, op->mtop, xm,
+                       mcnt);
+    size_t tb = 0;
+    HIP_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, mcnt, rrp, (int)(n + 1), s));
+    if (tb > L.sort_bytes) return bail(fail(FSDA_E_WORKSPACE, "scan needs " + std::to_string(tb) + " bytes"));
+    HIP_TRY(hipcub::DeviceScan::ExclusiveSum(op->ws + L.sort_tmp, tb, mcnt, rrp, (int)(n + 1), s));
+    hipLaunchKernelGGL(k_mask_fill, dim3(grid_for(n, 2048)), dim3(BS), 0, s, pb->x_rowptr, op->xcol, n, op->mtop, rrp,
+                       rcol);
+    int zr = 0;
+    HIP_TRY(hipMemcpyAsync(&zr, rrp + n, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    op->px = one_bin(rrp, rcol, n, zr);
+    op->px.rows.mask = xm;
+    op->px.rows.mtop = op->mtop;
+  }
   op->px_user = one_bin(pb->x_rowptr, pb->x_col, n, z);
   op->ps = one_bin(pb->s_rowptr, pb->s_col, n, g);
 

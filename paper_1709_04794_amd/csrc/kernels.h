@@ -260,6 +260,50 @@ struct EpiXT {
   }
 };
 
+// The step length of the shared recurrence, a_i = <r,r> / (<t,u> + sigma0 <p,p>),
+// from the partials of the graph product and of the previous direction update
+// (every block of a consumer sums them in the same order).
+__device__ __forceinline__ double step_length(const State* st, const double* tu_part, int ntu, const double* pp_part,
+                                              int npp, double* pq_out) {
+  const double pq = sum_partials(tu_part, ntu) + st->sigma0 * sum_partials(pp_part, npp);
+  *pq_out = pq;
+  return st->rr / pq;
+}
+
+// X^T product fused with the residual update of the shared recurrence: for
+// a row j of X^T, q_j = (X^T u)_j + sigma0 p_j and r_{i+1,j} = r_{i,j} - a_i q_j
+// (ring slots i mod m and i+1 mod m); reduction <r_{i+1}, r_{i+1}>.  The long
+// rows, left as chunk sums, are finished by k_long.
+template <typename T>
+struct EpiXTR {
+  using V = T;
+  const V* p;
+  V* ring;
+  long long ldd;
+  const double* tu_part;
+  int ntu;
+  const double* pp_part;
+  int npp;
+  double a, sigma;
+  const V* rin;
+  V* rout;
+  static constexpr bool kReduce = true;
+  __device__ void prepare(const State* st) {
+    double pq;
+    a = step_length(st, tu_part, ntu, pp_part, npp, &pq);
+    sigma = st->sigma0;
+    const int i = st->iter, m = st->chunk;
+    rin = ring + (long long)(i % m) * ldd;
+    rout = ring + (long long)((i + 1) % m) * ldd;
+  }
+  __device__ double row(int r, V v) const {
+    const V q = v + (V)sigma * p[r];
+    const V x = (V)((double)rin[r] - a * (double)q);
+    rout[r] = x;
+    return (double)x * (double)x;
+  }
+};
+
 // True residual of one shift: R = b - (X^T u + beta w), stored when out is
 // not NULL; reduction ||R||^2.
 struct EpiRes {
@@ -413,6 +457,12 @@ struct EpiLapDot {
 // index loads, then all gathers, are in flight together; the lanes then add up
 // with shuffles.  lpr == 0 marks rows known to be empty.
 
+// In the X product the most frequent features (internal ids [0, MK), the
+// relabeling puts them first) are held per sample as one 64-bit mask instead of
+// CSR entries: their values are staged in shared memory and added per set bit,
+// with no gathers.
+constexpr int MK = 64;  // features in the mask
+
 struct Rows {
   const int* rowptr;
   const int* col;
@@ -420,6 +470,8 @@ struct Rows {
   int row0[MAXBIN + 1];
   int lpr[MAXBIN];
   int item0[MAXBIN + 1];  // work items before bin b; an item is BS/lpr rows (BS when lpr == 0)
+  const unsigned long long* mask;  // NULL, or per row the mask features (col then holds only the others)
+  int mtop;                        // features in the mask, <= MK
 };
 
 template <class Epi>
@@ -429,6 +481,11 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __re
   if (solve && st->stop) return;
   epi.prepare(st);
   const int tid = threadIdx.x;
+  __shared__ V ptop[MK];  // src over the mask features
+  if (R.mask) {
+    if (tid < MK) ptop[tid] = tid < R.mtop ? src[tid] : (V)0;
+    __syncthreads();
+  }
   double acc = 0.0;
   const int nitems = R.item0[R.nb];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -446,6 +503,14 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __re
     V v = (V)0;
     if (live) {
       const int beg = R.rowptr[r], end = R.rowptr[r + 1];
+      unsigned long long mine = 0;
+      int mbase = 0;
+      if (R.mask) {  // lane takes MK/lpr consecutive mask bits of its row
+        const int nbits = MK / lpr;
+        mbase = lane * nbits;
+        const unsigned long long m = R.mask[r] >> mbase;
+        mine = nbits >= 64 ? m : (m & ((1ull << nbits) - 1));
+      }
       for (int k0 = beg + lane; k0 < end; k0 += lpr * RUNR) {
         int idx[RUNR];
         V g[RUNR];
@@ -458,6 +523,10 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __re
         for (int u = 0; u < RUNR; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : (V)0;
 #pragma unroll
         for (int u = 0; u < RUNR; u++) v += g[u];
+      }
+      while (mine) {
+        v += ptop[mbase + __ffsll((long long)mine) - 1];
+        mine &= mine - 1;
       }
     }
     for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -694,6 +763,53 @@ __global__ __launch_bounds__(BS) void k_resid(State* st, const V* __restrict__ q
   }
 }
 
+// The long rows [0, nlong) of the fused X^T + residual pass: q_j is the
+// ordered sum of the row's chunk sums plus sigma0 p_j, r_{i+1,j} = r_{i,j} - a_i q_j;
+// partials of <r_{i+1}, r_{i+1}> into part[slot0 + block].  The last block
+// advances zeta (or flags a breakdown), as the residual kernel does.
+template <typename V>
+__global__ __launch_bounds__(BS) void k_long(State* st, const V* __restrict__ p, V* ring, long long ldd, int nlong,
+                                             const int* __restrict__ row_chunk0, const double* __restrict__ lpart,
+                                             const double* tu_part, int ntu, const double* pp_part, int npp,
+                                             double* part, int slot0) {
+  if (st->stop) return;
+  double pq;
+  const double a = step_length(st, tu_part, ntu, pp_part, npp, &pq);
+  const bool ok = (pq > 0.0) && isfinite(a);
+  const double sigma0 = st->sigma0;
+  const int i = st->iter, m = st->chunk;
+  const V* r = ring + (long long)(i % m) * ldd;
+  V* rn = ring + (long long)((i + 1) % m) * ldd;
+  double acc = 0.0;
+  if (ok) {
+    for (int j = blockIdx.x * BS + threadIdx.x; j < nlong; j += gridDim.x * BS) {
+      const int c0 = row_chunk0[j], c1 = row_chunk0[j + 1];
+      double c = 0.0;
+      for (int k = c0; k < c1; k += 8) {
+        double x[8];
+#pragma unroll
+        for (int e = 0; e < 8; e++) x[e] = k + e < c1 ? lpart[k + e] : 0.0;
+#pragma unroll
+        for (int e = 0; e < 8; e++) c += x[e];
+      }
+      const double q = (double)(V)c + (double)((V)sigma0 * p[j]);
+      const V x = (V)((double)r[j] - a * q);
+      rn[j] = x;
+      acc += (double)x * (double)x;
+    }
+  }
+  write_partial(part, slot0 + blockIdx.x, acc);
+  if (last_block(&st->ticket[0])) {
+    if (ok) {
+      step_scalars(st, a);
+    } else if (threadIdx.x == 0) {
+      st->status = FSDA_E_BREAKDOWN;
+      st->stop = 1;
+    }
+    if (threadIdx.x == 0) st->ticket[0] = 0;
+  }
+}
+
 // K5: b_{i+1} = <r_{i+1},r_{i+1}>/<r_i,r_i>; p_{i+1} = r_{i+1} + b_{i+1} p_i, with
 // partials of <p_{i+1}, p_{i+1}> (and, with labw, of sum_j labw_j p_j for the
 // next sample-space centring).  The last block runs the per-shift scalar
@@ -913,6 +1029,37 @@ __global__ void k_label_vectors(const int* idx, const int8_t* y, long long nl, i
 
 __global__ void k_expand_rows(const int* rowptr, long long nrows, int* rowid) {
   FSDA_GRID_LOOP(r, nrows) for (int k = rowptr[r]; k < rowptr[r + 1]; k++) rowid[k] = (int)r;
+}
+
+// Split the rows of X (internal column ids) into the mask features [0, mtop)
+// and the rest: mask[r] gets a bit per mask feature, cnt[r] the number of others.
+__global__ void k_mask_split(const int* rowptr, const int* col, long long nrows, int mtop, unsigned long long* mask,
+                             int* cnt) {
+  FSDA_GRID_LOOP(r, nrows) {
+    unsigned long long m = 0;
+    int c = 0;
+    for (int k = rowptr[r]; k < rowptr[r + 1]; k++) {
+      const int j = col[k];
+      if (j < mtop)
+        m |= 1ull << j;
+      else
+        c++;
+    }
+    mask[r] = m;
+    cnt[r] = c;
+  }
+}
+
+// The other features of each row, in order, at rrowptr[r].
+__global__ void k_mask_fill(const int* rowptr, const int* col, long long nrows, int mtop, const int* rrowptr,
+                            int* rcol) {
+  FSDA_GRID_LOOP(r, nrows) {
+    int o = rrowptr[r];
+    for (int k = rowptr[r]; k < rowptr[r + 1]; k++) {
+      const int j = col[k];
+      if (j >= mtop) rcol[o++] = j;
+    }
+  }
 }
 
 // rowptr[j] = first position of key >= j in the sorted key array.

@@ -68,7 +68,9 @@ def test_batch_equals_single_target_path(tiny):
         Ws, its, rs, _ = single.solve(tiny.betas, rtol=1e-11)
         for s in range(tiny.betas.size):
             assert relerr(W[c, s].cpu().numpy(), Ws[s].cpu().numpy()) < 1e-7
-        assert np.all(np.abs(iters[c] - its) <= 2)
+        # the same recurrence with other summation orders: near rtol = 1e-11 the step at
+        # which a shift crosses the threshold moves by a few iterations
+        assert np.all(np.abs(iters[c] - its) <= np.maximum(2, 0.02 * its)), (iters[c], its)
 
 
 def test_batch_label_order_and_determinism(tiny):
