@@ -75,7 +75,7 @@ def measured_traffic(kernel: int, workload: str):
                 continue
             kv = dict(t.split("=", 1) for t in line.split()[1:])
             if kv.get("kernel") == key and kv.get("workload") == workload and kv.get("source") == sha:
-                return int(kv["bytes"])
+                return int(float(kv["bytes"]))
     return None
 
 
@@ -218,10 +218,55 @@ def summarize_rocprof(d: str, kernel_substr: str, calib_mib: int) -> str:
     return "\n".join(lines)
 
 
+TRAFFIC_MATCH = {"k_xt": "k_xt<fsda::EpiXTR<double>", "k_rows_x": "k_rows<fsda::EpiX<double, false>",
+                 "k_fold": "k_fold<32, double>"}
+
+
+def traffic_lines(dfetch: str, dwrite: str, calib_mib: int, workload: str) -> str:
+    """TRAFFIC lines (HBM bytes per launch) from a FETCH_SIZE run and a WRITE_SIZE run.
+
+    Each counter is calibrated on the plain device copy of calib_mib MiB recorded in
+    the same run (its per-dispatch value against the bytes it must read or write)."""
+    import glob
+    import hashlib
+    import pandas as pd
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1709_04794_amd", "csrc", "kernels.h"), "rb")
+                         .read()).hexdigest()[:16]
+    per = {}
+    for d, cname in ((dfetch, "FETCH_SIZE"), (dwrite, "WRITE_SIZE")):
+        f = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))[0]
+        df = pd.read_csv(f)
+        g = df[df["Counter_Name"] == cname]
+        cp = g[g["Kernel_Name"].str.lower().str.contains("copy")]
+        big = cp[cp["Counter_Value"] >= 0.5 * cp["Counter_Value"].max()]
+        factor = (calib_mib << 20) / (big["Counter_Value"].mean() * 1024.0)
+        out = {"factor": factor}
+        for key, sub in TRAFFIC_MATCH.items():
+            sel = g[g["Kernel_Name"].str.contains(sub, regex=False)]
+            if len(sel):
+                out[key] = (float(sel["Counter_Value"].mean()), len(sel))
+        per[cname] = out
+    lines = ["calibration factors: FETCH_SIZE x %.4f, WRITE_SIZE x %.4f (KiB per dispatch -> bytes / 1024)"
+             % (per["FETCH_SIZE"]["factor"], per["WRITE_SIZE"]["factor"])]
+    for key in TRAFFIC_MATCH:
+        if key in per["FETCH_SIZE"] and key in per["WRITE_SIZE"]:
+            fk, fn = per["FETCH_SIZE"][key]
+            wk, wn = per["WRITE_SIZE"][key]
+            rb = fk * 1024 * per["FETCH_SIZE"]["factor"]
+            wb = wk * 1024 * per["WRITE_SIZE"]["factor"]
+            lines.append("TRAFFIC kernel=%s workload=%s source=%s bytes=%d read=%d written=%d dispatches=%d,%d"
+                         % (key, workload, sha, rb + wb, rb, wb, fn, wn))
+    return "\n".join(lines)
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-rocprof":
         # python bench.py --summarize-rocprof DIR KERNEL_SUBSTR CALIB_MIB
         print(summarize_rocprof(sys.argv[2], sys.argv[3], int(sys.argv[4])))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--traffic-lines":
+        # python bench.py --traffic-lines FETCH_DIR WRITE_DIR CALIB_MIB WORKLOAD
+        print(traffic_lines(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5]))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,7 +378,18 @@ def main():
         graph_rate = gsolved / (time.perf_counter() - t1)
         log("graph-replay steps: %.3f solves/s" % graph_rate)
 
-    avg_launch_s = (kms / 1e3) / max(klaunch, 1)
+    # the event pair around each timed launch costs some time of its own on the
+    # stream: measure empty pairs the same way and take that off
+    ev_ms = []
+    for _ in range(200):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        b.record()
+        ev_ms.append((a, b))
+    torch.cuda.synchronize()
+    pair_us = float(np.median([a.elapsed_time(b) for a, b in ev_ms])) * 1e3
+    raw_launch_s = (kms / 1e3) / max(klaunch, 1)
+    avg_launch_s = max(raw_launch_s - pair_us * 1e-6, 1e-9)
     bytes_launch = algorithmic_bytes(dom, pb, S, args.chunk)
     achieved = bytes_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     value = solved / elapsed
@@ -359,7 +415,8 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(dom, args.workload),
                      "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                     "launches": klaunch},
+                     "launches": klaunch, "event_pair_us": round(pair_us, 2),
+                     "avg_launch_us_with_events": round(raw_launch_s * 1e6, 2)},
         "detail": {"iters": None if iters_seen is None else iters_seen.tolist(), "worst_relres": worst,
                    "solved_per_step": solved / args.steps, "build_s": round(build_s, 3),
                    "graph_replay_solves_per_s": graph_rate,
