@@ -59,16 +59,25 @@ def algorithmic_bytes(kernel: int, pb, nshift: int, chunk: int) -> float:
 TRAFFIC_KEYS = {2: "k_xt", 0: "k_rows_x", 6: "k_fold"}
 
 
+def kernel_source_key() -> str:
+    """sha256 prefix of the device code (kernels.h without comments or blank lines): the
+    byte counters in profiles/ hold for the kernels they were taken on."""
+    import hashlib
+    import re
+    src = open(os.path.join(ROOT, "paper_1709_04794_amd", "csrc", "kernels.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in src.splitlines()]
+    return hashlib.sha256("\n".join(ln for ln in lines if ln.strip()).encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel: int, workload: str):
     """HBM bytes per launch from the committed rocprofv3 byte counters, if they
     were taken on the current kernel source; otherwise None."""
     import glob
-    import hashlib
     key = TRAFFIC_KEYS.get(kernel)
     if key is None:
         return None
-    src = os.path.join(ROOT, "paper_1709_04794_amd", "csrc", "kernels.h")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = kernel_source_key()
     for f in glob.glob(os.path.join(ROOT, "profiles", "*traffic*.txt")):
         for line in open(f):
             if not line.startswith("TRAFFIC "):
@@ -228,10 +237,8 @@ def traffic_lines(dfetch: str, dwrite: str, calib_mib: int, workload: str) -> st
     Each counter is calibrated on the plain device copy of calib_mib MiB recorded in
     the same run (its per-dispatch value against the bytes it must read or write)."""
     import glob
-    import hashlib
     import pandas as pd
-    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1709_04794_amd", "csrc", "kernels.h"), "rb")
-                         .read()).hexdigest()[:16]
+    sha = kernel_source_key()
     per = {}
     for d, cname in ((dfetch, "FETCH_SIZE"), (dwrite, "WRITE_SIZE")):
         f = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))[0]

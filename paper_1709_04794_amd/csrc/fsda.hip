@@ -1,20 +1,23 @@
 // MI355X (gfx950) multi-shift solver for fast semi-supervised discriminant
 // analysis (FSDA, arXiv:1709.04794): host driver and the C ABI of
-// include/fsda.h.  Device code is in kernels.h.
+// include/fsda.h.  Device code is in kernels.h (the shared recurrence),
+// batched.h (batched CG over independent columns) and targets.h (many targets).
 //
 // One iteration of the shared recurrence (Alg. 3 seeded at sigma0 = min beta)
-// is five products/updates on one stream:
-//   K1 k_rows<EpiX>      t = X p                (+ labeled mean of t for the centring)
-//   K2 k_rows<EpiLap>    u = (1-alpha)[labeled](t - c) + alpha (D - S) t
-//   K3 k_xt<EpiXT>       q = X^T u + sigma0 p (long rows left as chunk sums)
-//   K4 k_resid           a_i from <t,u> + sigma0 <p,p>, r_{i+1} = r_i - a_i q
-//                        (+ <r,r> partials; zeta_{i+1})
-//   K5 k_pupdate         b_{i+1}, p_{i+1} = r_{i+1} + b_{i+1} p_i (+ <p,p>; per-shift stops)
+// in feature space is four passes on one stream:
+//   K1 k_rows<EpiX>      t = X p (mask features + CSR of the others; + labeled mean of t)
+//   K2 k_rows<EpiLap>    u = (1-alpha)[labeled](t - c) + alpha (D - S) t  (+ <t,u> partials)
+//   K3 k_xt<EpiXTR>      a_i = <r,r> / (<t,u> + sigma0 <p,p>); q = X^T u + sigma0 p and
+//                        r_{i+1} = r_i - a_i q for the short rows (long rows as chunk sums)
+//   K3' k_long           the long rows' q and r_{i+1}; zeta_{i+1} of every shift
+//   K4 k_pupdate         b_{i+1}, p_{i+1} = r_{i+1} + b_{i+1} p_i (+ <p,p>; per-shift stops)
 // and every `chunk` iterations one k_fold replays the per-shift recurrences
 //   W_s += a_s P_s ;  P_s = zeta_{i+1,s} r_{i+1} + b_s P_s      (Alg. 3, per shift)
 // over the buffered residuals, reading and writing each shift's state once per
 // chunk instead of once per iteration.  A chunk is captured once as a HIP
-// graph and replayed; the host reads a 16-byte status after each chunk.
+// graph and replayed; the host reads a 16-byte status after each chunk.  The
+// sample-space solve (Alg. sasda) replaces K1-K3' by one pass over S and k_resid;
+// the regression phase replaces K1-K2 by t = X p.
 //
 // Features are relabeled internally by decreasing frequency: the popular
 // entries of the feature-space vectors share cache lines (the gathers of

@@ -543,7 +543,7 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __re
 // by length.  Each long row (the prefix [0, nlong)) is cut into chunks of CH
 // nonzeros; a block sums one chunk (coalesced index loads, independent
 // gathers, block reduction) into lpart[chunk], and the consumer adds up a
-// row's chunk sums in order (k_resid inline, or k_assemble).  The remaining
+// row's chunk sums in order (k_long or k_resid, or k_assemble).  The remaining
 // rows go through the same lanes-per-row bins as k_rows, in the same launch.
 
 constexpr int CH = 4096;        // nonzeros of a long-row chunk (16 per thread)
@@ -691,7 +691,8 @@ __global__ __launch_bounds__(BS) void k_init_done(State* st, const double* part,
   }
 }
 
-// K4: <p, q> = <t, u> + sigma0 <p, p> from the partials of the graph product
+// Residual update as a pass of its own (the sample-space solve): <p, q> =
+// <t, u> + sigma0 <p, p> from the partials of the graph product
 // and of the previous direction update; a_i = <r,r>/<p,q>; r_{i+1} = r_i - a_i q
 // into the next ring slot, where q_j of a long row j < nlong is the ordered sum
 // of its chunk sums plus sigma0 p_j; partials of <r_{i+1}, r_{i+1}>.  The last
@@ -810,7 +811,7 @@ __global__ __launch_bounds__(BS) void k_long(State* st, const V* __restrict__ p,
   }
 }
 
-// K5: b_{i+1} = <r_{i+1},r_{i+1}>/<r_i,r_i>; p_{i+1} = r_{i+1} + b_{i+1} p_i, with
+// Direction update: b_{i+1} = <r_{i+1},r_{i+1}>/<r_i,r_i>; p_{i+1} = r_{i+1} + b_{i+1} p_i, with
 // partials of <p_{i+1}, p_{i+1}> (and, with labw, of sum_j labw_j p_j for the
 // next sample-space centring).  The last block runs the per-shift scalar
 // updates and the stop test.
