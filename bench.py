@@ -397,6 +397,22 @@ def main():
     pair_us = float(np.median([a.elapsed_time(b) for a, b in ev_ms])) * 1e3
     raw_launch_s = (kms / 1e3) / max(klaunch, 1)
     avg_launch_s = max(raw_launch_s - pair_us * 1e-6, 1e-9)
+    # the operator apply of one iteration (X, graph and X^T passes, with the
+    # long rows of X^T) against its algorithmic bytes 8Z + 4G + 40N + 28D
+    # (index arrays once, vectors once); the fused residual update rides along
+    # uncounted, so the figure is a lower bound
+    op_apply = None
+    if per_class:
+        us = 0.0
+        for k in (fsda.K_X, fsda.K_S, fsda.K_XT, fsda.K_RESID):
+            ms, nl = per_class.get(k, (0.0, 0))
+            if nl:
+                us += max(1e3 * ms / nl - pair_us, 0.0)
+        b_op = 8 * pb.x_nnz + 4 * pb.s_nnz + 40 * pb.n + 28 * pb.d
+        op_apply = {"bytes": b_op, "us": round(us, 2), "GBps": round(b_op / (us * 1e-6) / 1e9, 1),
+                    "frac": round(b_op / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                    "note": "X, graph and X^T passes of one iteration including the long rows of X^T "
+                            "(which also update r, bytes not counted); HIP-event times minus the event-pair overhead"}
     bytes_launch = algorithmic_bytes(dom, pb, S, args.chunk)
     achieved = bytes_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     value = solved / elapsed
@@ -424,6 +440,7 @@ def main():
                      "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "launches": klaunch, "event_pair_us": round(pair_us, 2),
                      "avg_launch_us_with_events": round(raw_launch_s * 1e6, 2)},
+        "operator_apply": op_apply,
         "detail": {"iters": None if iters_seen is None else iters_seen.tolist(), "worst_relres": worst,
                    "solved_per_step": solved / args.steps, "build_s": round(build_s, 3),
                    "graph_replay_solves_per_s": graph_rate,
