@@ -47,9 +47,9 @@ def algorithmic_bytes(kernel: int, pb, nshift: int, chunk: int) -> float:
         return 4 * (n + 1) + 4 * g + 8 * n + 8 * n + lab
     if kernel == fsda.K_XT:     # rowptr, col, u (gathered), p and r read, r_{i+1} written
         return 4 * (d + 1) + 4 * z + 8 * n + 24 * d
-    if kernel == fsda.K_RESID:  # the long rows of X^T: their p, r in and r_{i+1} out (chunk sums aside)
+    if kernel == fsda.K_RESID:  # not launched by the feature-space solve
         return 0.0
-    if kernel == fsda.K_PUPD:   # r_{i+1}, p in; p out
+    if kernel == fsda.K_PUPD:   # r_{i+1}, p in; p out (the long rows' chunk sums aside)
         return 24 * d
     if kernel == fsda.K_FOLD:   # W, P in and out for every shift, chunk residuals in
         return 32 * nshift * d + 8 * chunk * d
@@ -89,8 +89,8 @@ def measured_traffic(kernel: int, workload: str):
 
 
 KNAMES = {0: "k_rows<EpiX> (t = X p)", 1: "k_rows<EpiLap> (u = M' t)",
-          2: "k_xt<EpiXTR> (q = X^T u + s p, r -= a q)", 4: "k_long (long rows of X^T, zeta step)",
-          5: "k_pupdate", 6: "k_fold"}
+          2: "k_xt<EpiXTR> (q = X^T u + s p, r -= a q)", 4: "k_resid (sample space)",
+          5: "k_pupdate (long rows of X^T, p update, shift scalars)", 6: "k_fold"}
 
 
 def cpu_baseline(pb, budget_s: float):
@@ -397,10 +397,10 @@ def main():
     pair_us = float(np.median([a.elapsed_time(b) for a, b in ev_ms])) * 1e3
     raw_launch_s = (kms / 1e3) / max(klaunch, 1)
     avg_launch_s = max(raw_launch_s - pair_us * 1e-6, 1e-9)
-    # the operator apply of one iteration (X, graph and X^T passes, with the
-    # long rows of X^T) against its algorithmic bytes 8Z + 4G + 40N + 28D
-    # (index arrays once, vectors once); the fused residual update rides along
-    # uncounted, so the figure is a lower bound
+    # the operator apply of one iteration (X, graph and X^T passes) against its
+    # algorithmic bytes 8Z + 4G + 40N + 28D (index arrays once, vectors once);
+    # the residual update fused into the X^T pass rides along uncounted, and the
+    # long rows of X^T are finished in the direction update, outside this time
     op_apply = None
     if per_class:
         us = 0.0
@@ -411,8 +411,9 @@ def main():
         b_op = 8 * pb.x_nnz + 4 * pb.s_nnz + 40 * pb.n + 28 * pb.d
         op_apply = {"bytes": b_op, "us": round(us, 2), "GBps": round(b_op / (us * 1e-6) / 1e9, 1),
                     "frac": round(b_op / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-                    "note": "X, graph and X^T passes of one iteration including the long rows of X^T "
-                            "(which also update r, bytes not counted); HIP-event times minus the event-pair overhead"}
+                    "note": "X, graph and X^T passes of one iteration (the X^T pass also updates r, bytes not "
+                            "counted; its long rows are finished in the direction update); HIP-event times "
+                            "minus the event-pair overhead"}
     bytes_launch = algorithmic_bytes(dom, pb, S, args.chunk)
     achieved = bytes_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     value = solved / elapsed

@@ -294,8 +294,9 @@ int fsda_project(fsda_op *op, const double *W, int nshift, double *S, void *stre
  * pair of HIP events around every launch of the kernel class `kernel` on the
  * launch stream: 0 = X product, 1 = graph/centring product, 2 = X^T
  * product (fused with the residual update of every short row of X^T in the
- * feature-space solves), 4 = residual update (feature space: the long rows of
- * X^T only), 5 = direction update, 6 = shift-state fold (3 is unused); the batched FP32 correction solves of FSDA_MIXED: 7 = X
+ * feature-space solves), 4 = residual update (sample-space solves), 5 =
+ * direction update (feature space: also the residual update of the long rows
+ * of X^T), 6 = shift-state fold (3 is unused); the batched FP32 correction solves of FSDA_MIXED: 7 = X
  * product, 8 = graph/centring product, 9 = X^T product, 10 = residual and
  * correction update, 11 = direction update; fsda_multishift_solve_batch: 7-9
  * its products, 10 = residual update, 11 = direction update, 12 = shift-state

@@ -9,14 +9,14 @@
 //   K2 k_rows<EpiLap>    u = (1-alpha)[labeled](t - c) + alpha (D - S) t  (+ <t,u> partials)
 //   K3 k_xt<EpiXTR>      a_i = <r,r> / (<t,u> + sigma0 <p,p>); q = X^T u + sigma0 p and
 //                        r_{i+1} = r_i - a_i q for the short rows (long rows as chunk sums)
-//   K3' k_long           the long rows' q and r_{i+1}; zeta_{i+1} of every shift
-//   K4 k_pupdate         b_{i+1}, p_{i+1} = r_{i+1} + b_{i+1} p_i (+ <p,p>; per-shift stops)
+//   K4 k_pupdate         the long rows' q and r_{i+1}; b_{i+1}, p_{i+1} = r_{i+1} + b_{i+1} p_i
+//                        (+ <p,p>); zeta_{i+1} and the per-shift stops
 // and every `chunk` iterations one k_fold replays the per-shift recurrences
 //   W_s += a_s P_s ;  P_s = zeta_{i+1,s} r_{i+1} + b_s P_s      (Alg. 3, per shift)
 // over the buffered residuals, reading and writing each shift's state once per
 // chunk instead of once per iteration.  A chunk is captured once as a HIP
 // graph and replayed; the host reads a 16-byte status after each chunk.  The
-// sample-space solve (Alg. sasda) replaces K1-K3' by one pass over S and k_resid;
+// sample-space solve (Alg. sasda) replaces K1-K3 by one pass over S and k_resid;
 // the regression phase replaces K1-K2 by t = X p.
 //
 // Features are relabeled internally by decreasing frequency: the popular
@@ -441,7 +441,8 @@ void iteration(fsda_op* op, int mode, hipStream_t s, int tag) {
     });
   } else {
     // t = X p (MODE_FSDA then u = M' t; MODE_REG: u = t); then one pass over X^T
-    // that also updates the residual of every short row, and k_long for the long rows
+    // that also updates the residual of every short row (the long rows are
+    // finished by the direction update)
     const V* u = as<V>(op->u);
     if (mode == MODE_REG) {
       run_rows(op, op->px, p, EpiXReg<V>{as<V>(op->t)}, op->part + SITE_TU * NPART, 1, s, KC_X);
@@ -452,21 +453,17 @@ void iteration(fsda_op* op, int mode, hipStream_t s, int tag) {
       product_lap<V>(op, 1, s);
     }
     run_xt(op, u,
-           EpiXTR<V>{p, ring, op->L.ldv, op->part + SITE_TU * NPART, ntu, op->part + SITE_PP * NPART, gs, 0.0, 0.0,
+           EpiXTR<V>{p, ring, op->L.ldv, op->part + SITE_TU * NPART, ntu, op->part + SITE_PP * NPART, gs, 0.0, 0.0, 0.0,
                      nullptr, nullptr},
            1, false, s, KC_XT, op->part + SITE_R * NPART);
-    const int gl = std::max(1, std::min((int)ceil_div(op->pxt.nlong, BS), 64));
-    launch(op, KC_RESID, s, [&] {
-      hipLaunchKernelGGL(k_long<V>, dim3(gl), dim3(BS), 0, s, op->st, p, ring, op->L.ldv, op->pxt.nlong,
-                         op->pxt.row_chunk0, op->pxt.w.lpart, op->part + SITE_TU * NPART, ntu,
-                         op->part + SITE_PP * NPART, gs, op->part + SITE_R * NPART, op->pxt.grid);
-    });
-    nrr = op->pxt.grid + gl;
+    nrr = op->pxt.grid;
   }
+  const int nlong = sa ? 0 : op->pxt.nlong;
   launch(op, KC_PUPD, s, [&] {
     hipLaunchKernelGGL(k_pupdate<V>, dim3(gs), dim3(BS), 0, s, op->st, ring, p, op->L.ldv, m,
                        op->part + SITE_R * NPART, nrr, op->hist, op->part + SITE_PP * NPART,
-                       sa ? op->labw : nullptr, op->part + SITE_X * NPART);
+                       sa ? op->labw : nullptr, op->part + SITE_X * NPART, sa ? 0 : 1, nlong, op->pxt.row_chunk0,
+                       op->pxt.w.lpart);
   });
   op->cur_tag = -1;
 }

@@ -32,9 +32,15 @@ constexpr int XUNR = 8;       // nonzeros per lane per pass in the X^T row bins
 
 enum Site { SITE_X = 0, SITE_XT = 1, SITE_R = 2, SITE_TU = 3, SITE_PP = 4, NSITE = 5 };
 
+// Last-block detection counts blocks in TG groups (block b in group b mod TG,
+// each counter on its own 128-byte line) and then groups in one more counter:
+// increments of a single address serialise at about 10 ns each, so one
+// counter for 500 blocks would cost 5 us, the two levels about 0.5 us.
+constexpr int TG = 16;
+enum TicketSite { TK_STEP = 0, TK_DIR = 1, NTK = 2 };
+
 // Solver state, resident in device memory.
 struct State {
-  unsigned int ticket[8];  // last-block counters
   int iter;                // iterations of the shared recurrence completed
   int stop;                // every shift stopped, maxit, or breakdown
   int status;              // 0 ok, 1 maxit reached, -5 breakdown
@@ -52,6 +58,8 @@ struct State {
   double res2[MAXS];       // ||b - A(beta_s) w_s||^2 after the solve
   int active[MAXS];
   int conv[MAXS];          // iteration at which shift s stopped
+  double a_new, pq_new;    // a_i and <p_i, A p_i>, published by the X^T pass for the direction update
+  alignas(128) unsigned int tk[NTK][TG + 1][32];  // last-block counters (one 128-byte line each)
 };
 
 // ---------------------------------------------------------------------------
@@ -98,11 +106,25 @@ __device__ __forceinline__ void write_partial(double* part, int slot, double acc
   if (threadIdx.x == 0) part[slot] = t;
 }
 
-// True in every thread of the last block to reach it.
-__device__ __forceinline__ bool last_block(unsigned int* ticket) {
+// True in every thread of the last block to reach it.  Relaxed: the last
+// block reads nothing the other blocks wrote in this kernel.  It also resets
+// the counters, which no block touches any more, for the next launch.
+__device__ __forceinline__ bool last_block(State* st, int site) {
   __shared__ int amlast;
   __syncthreads();
-  if (threadIdx.x == 0) amlast = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  if (threadIdx.x == 0) {
+    unsigned int(*c)[32] = st->tk[site];
+    const int ng = min(TG, (int)gridDim.x);
+    const int g = blockIdx.x % ng;
+    const unsigned int cnt = gridDim.x / ng + (g < (int)(gridDim.x % ng) ? 1u : 0u);
+    int last = 0;
+    if (atomicAdd(&c[g][0], 1u) == cnt - 1) last = atomicAdd(&c[TG][0], 1u) == (unsigned int)ng - 1;
+    if (last) {
+      for (int k = 0; k < ng; k++) c[k][0] = 0;
+      c[TG][0] = 0;
+    }
+    amlast = last;
+  }
   __syncthreads();
   return amlast != 0;
 }
@@ -249,9 +271,11 @@ struct EpiXT {
   double sigma;
   const double* sigp;
   static constexpr bool kReduce = RED;
+  static constexpr bool kPublish = false;
   __device__ void prepare(const State*) {
     if (sigp) sigma = *sigp;
   }
+  __device__ void publish(State*) const {}
   __device__ double row(int r, V v) const {
     const V pr = p ? p[r] : (V)0;
     const V qq = v + (V)sigma * pr;
@@ -273,7 +297,7 @@ __device__ __forceinline__ double step_length(const State* st, const double* tu_
 // X^T product fused with the residual update of the shared recurrence: for
 // a row j of X^T, q_j = (X^T u)_j + sigma0 p_j and r_{i+1,j} = r_{i,j} - a_i q_j
 // (ring slots i mod m and i+1 mod m); reduction <r_{i+1}, r_{i+1}>.  The long
-// rows, left as chunk sums, are finished by k_long.
+// rows, left as chunk sums, are finished by the direction update (k_pupdate).
 template <typename T>
 struct EpiXTR {
   using V = T;
@@ -284,12 +308,16 @@ struct EpiXTR {
   int ntu;
   const double* pp_part;
   int npp;
-  double a, sigma;
+  double a, sigma, pq;
   const V* rin;
   V* rout;
   static constexpr bool kReduce = true;
+  static constexpr bool kPublish = true;  // a_i and <p, A p> for the direction update
+  __device__ void publish(State* st) const {
+    st->a_new = a;
+    st->pq_new = pq;
+  }
   __device__ void prepare(const State* st) {
-    double pq;
     a = step_length(st, tu_part, ntu, pp_part, npp, &pq);
     sigma = st->sigma0;
     const int i = st->iter, m = st->chunk;
@@ -313,7 +341,9 @@ struct EpiRes {
   double beta;
   double* out;
   static constexpr bool kReduce = true;
+  static constexpr bool kPublish = false;
   __device__ void prepare(const State*) {}
+  __device__ void publish(State*) const {}
   __device__ double row(int r, double v) const {
     const double R = b[r] - (v + beta * w[r]);
     if (out) out[r] = R;
@@ -543,7 +573,7 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __re
 // by length.  Each long row (the prefix [0, nlong)) is cut into chunks of CH
 // nonzeros; a block sums one chunk (coalesced index loads, independent
 // gathers, block reduction) into lpart[chunk], and the consumer adds up a
-// row's chunk sums in order (k_long or k_resid, or k_assemble).  The remaining
+// row's chunk sums in order (k_pupdate or k_resid, or k_assemble).  The remaining
 // rows go through the same lanes-per-row bins as k_rows, in the same launch.
 
 constexpr int CH = 4096;        // nonzeros of a long-row chunk (16 per thread)
@@ -564,6 +594,7 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __re
   using V = typename Epi::V;
   if (solve && st->stop) return;
   epi.prepare(st);
+  if (Epi::kPublish && blockIdx.x == 0 && threadIdx.x == 0) epi.publish(st);
   const int tid = threadIdx.x;
   double acc = 0.0;
   const int nitems = X.nchunk + X.rows.item0[X.rows.nb];
@@ -753,110 +784,156 @@ __global__ __launch_bounds__(BS) void k_resid(State* st, const V* __restrict__ q
     }
   }
   write_partial(part, blockIdx.x, acc);
-  if (last_block(&st->ticket[0])) {
+  if (last_block(st, TK_STEP)) {
     if (ok) {
       step_scalars(st, a);
     } else if (threadIdx.x == 0) {
       st->status = FSDA_E_BREAKDOWN;
       st->stop = 1;
     }
-    if (threadIdx.x == 0) st->ticket[0] = 0;
   }
 }
 
-// The long rows [0, nlong) of the fused X^T + residual pass: q_j is the
-// ordered sum of the row's chunk sums plus sigma0 p_j, r_{i+1,j} = r_{i,j} - a_i q_j;
-// partials of <r_{i+1}, r_{i+1}> into part[slot0 + block].  The last block
-// advances zeta (or flags a breakdown), as the residual kernel does.
+// r_{i+1,j} of a long row j < nlong of X^T (the fused X^T pass leaves these
+// rows as chunk sums): q_j is the ordered sum of the row's chunk sums plus
+// sigma0 p_j, and r_{i+1,j} = r_{i,j} - a_i q_j.  Returns r_{i+1,j} and p_j.
+struct LongRow {
+  double r, p;
+};
 template <typename V>
-__global__ __launch_bounds__(BS) void k_long(State* st, const V* __restrict__ p, V* ring, long long ldd, int nlong,
-                                             const int* __restrict__ row_chunk0, const double* __restrict__ lpart,
-                                             const double* tu_part, int ntu, const double* pp_part, int npp,
-                                             double* part, int slot0) {
-  if (st->stop) return;
-  double pq;
-  const double a = step_length(st, tu_part, ntu, pp_part, npp, &pq);
-  const bool ok = (pq > 0.0) && isfinite(a);
-  const double sigma0 = st->sigma0;
-  const int i = st->iter, m = st->chunk;
-  const V* r = ring + (long long)(i % m) * ldd;
-  V* rn = ring + (long long)((i + 1) % m) * ldd;
-  double acc = 0.0;
-  if (ok) {
-    for (int j = blockIdx.x * BS + threadIdx.x; j < nlong; j += gridDim.x * BS) {
-      const int c0 = row_chunk0[j], c1 = row_chunk0[j + 1];
-      double c = 0.0;
-      for (int k = c0; k < c1; k += 8) {
-        double x[8];
+__device__ __forceinline__ LongRow long_row_residual(int j, const int* __restrict__ row_chunk0,
+                                                     const double* __restrict__ lpart, const V* p, const V* r,
+                                                     double a, double sigma0) {
+  const int c0 = row_chunk0[j], c1 = row_chunk0[j + 1];
+  const V pv = p[j];
+  const V rv = r[j];
+  double c = 0.0;
+  for (int k = c0; k < c1; k += 8) {
+    double x[8];
 #pragma unroll
-        for (int e = 0; e < 8; e++) x[e] = k + e < c1 ? lpart[k + e] : 0.0;
+    for (int e = 0; e < 8; e++) x[e] = k + e < c1 ? lpart[k + e] : 0.0;
 #pragma unroll
-        for (int e = 0; e < 8; e++) c += x[e];
-      }
-      const double q = (double)(V)c + (double)((V)sigma0 * p[j]);
-      const V x = (V)((double)r[j] - a * q);
-      rn[j] = x;
-      acc += (double)x * (double)x;
-    }
+    for (int e = 0; e < 8; e++) c += x[e];
   }
-  write_partial(part, slot0 + blockIdx.x, acc);
-  if (last_block(&st->ticket[0])) {
-    if (ok) {
-      step_scalars(st, a);
-    } else if (threadIdx.x == 0) {
-      st->status = FSDA_E_BREAKDOWN;
-      st->stop = 1;
-    }
-    if (threadIdx.x == 0) st->ticket[0] = 0;
-  }
+  const double q = (double)(V)c + (double)((V)sigma0 * pv);
+  return LongRow{(double)(V)((double)rv - a * q), (double)pv};
 }
 
 // Direction update: b_{i+1} = <r_{i+1},r_{i+1}>/<r_i,r_i>; p_{i+1} = r_{i+1} + b_{i+1} p_i, with
 // partials of <p_{i+1}, p_{i+1}> (and, with labw, of sum_j labw_j p_j for the
 // next sample-space centring).  The last block runs the per-shift scalar
 // updates and the stop test.
+//
+// After the fused X^T pass (step != 0) this kernel also finishes the long rows
+// [0, nlong).  Every block computes their r_{i+1} (same values, same order),
+// for <r_{i+1}, r_{i+1}> = (partials of the X^T pass) + (long rows).  Their
+// r_{i+1} and p_{i+1} are stored by the last block only, since every block
+// reads r_i and p_i there (with a fold interval of 1, r_i and r_{i+1} share a
+// ring slot); and the last block first advances zeta with the step a_i that
+// the X^T pass published.
+constexpr int LCACHE = 4;  // long rows per thread kept in registers for the last block's stores
 template <typename V>
-__global__ __launch_bounds__(BS) void k_pupdate(State* st, const V* ring, V* p, long long ldd, long long d,
+__global__ __launch_bounds__(BS) void k_pupdate(State* st, V* ring, V* p, long long ldd, long long d,
                                                 const double* rr_part, int nrr, double* hist, double* pp_part,
-                                                const double* labw, double* lpart) {
+                                                const double* labw, double* lpart, int step, int nlong,
+                                                const int* __restrict__ row_chunk0,
+                                                const double* __restrict__ chunk_sum) {
   if (st->stop) return;
-  const int i = st->iter;
-  const V* r = ring + (long long)((i + 1) % st->chunk) * ldd;
-  const long long step = (long long)gridDim.x * BS * UNR;
+  const int i = st->iter, m = st->chunk;
+  V* r = ring + (long long)((i + 1) % m) * ldd;
+  const V* rprev = ring + (long long)(i % m) * ldd;
+  const double a = step ? st->a_new : 0.0;
+  const bool ok = !step || (st->pq_new > 0.0 && isfinite(a));
+  const double sigma0 = st->sigma0;
+  const long long gstep = (long long)gridDim.x * BS * UNR;
   long long j0 = (long long)blockIdx.x * BS * UNR + threadIdx.x;
   double rv[UNR], pv[UNR];
-#pragma unroll
-  for (int u = 0; u < UNR; u++) {
-    const long long j = j0 + (long long)u * BS;
-    rv[u] = j < d ? r[j] : 0.0;
-    pv[u] = j < d ? p[j] : 0.0;
-  }
-  const double rrn = sum_partials(rr_part, nrr);
-  const double b = rrn / st->rr;
-  double acc = 0.0, lac = 0.0;
-  for (;;) {
+  double acc = 0.0, lac = 0.0, rrn = 0.0, b = 0.0;
+  double lx[LCACHE], lp[LCACHE];
+  if (ok) {
+    // first elements of this block, in flight during the sums below
 #pragma unroll
     for (int u = 0; u < UNR; u++) {
       const long long j = j0 + (long long)u * BS;
-      const V x = (V)(rv[u] + b * pv[u]);
-      if (j < d) p[j] = x;
-      acc += j < d ? (double)x * (double)x : 0.0;
-      if (labw && j < d) lac += labw[j] * (double)x;
+      if (j < nlong) {
+        const LongRow lr = long_row_residual<V>((int)j, row_chunk0, chunk_sum, p, rprev, a, sigma0);
+        rv[u] = lr.r;
+        pv[u] = lr.p;
+      } else {
+        rv[u] = j < d ? (double)r[j] : 0.0;
+        pv[u] = j < d ? (double)p[j] : 0.0;
+      }
     }
-    j0 += step;
-    if (j0 >= d) break;
+    double rl = 0.0;  // the long rows' part of <r_{i+1}, r_{i+1}>
 #pragma unroll
-    for (int u = 0; u < UNR; u++) {
-      const long long j = j0 + (long long)u * BS;
-      rv[u] = j < d ? (double)r[j] : 0.0;
-      pv[u] = j < d ? (double)p[j] : 0.0;
+    for (int k = 0; k < LCACHE; k++) {
+      const int j = threadIdx.x + k * BS;
+      lx[k] = lp[k] = 0.0;
+      if (j < nlong) {
+        const LongRow lr = long_row_residual<V>(j, row_chunk0, chunk_sum, p, rprev, a, sigma0);
+        lx[k] = lr.r;
+        lp[k] = lr.p;
+        rl += lr.r * lr.r;
+      }
+    }
+    for (int j = threadIdx.x + LCACHE * BS; j < nlong; j += BS) {
+      const LongRow lr = long_row_residual<V>(j, row_chunk0, chunk_sum, p, rprev, a, sigma0);
+      rl += lr.r * lr.r;
+    }
+    rrn = sum_partials(rr_part, nrr) + (nlong > 0 ? block_sum_all(rl) : 0.0);
+    b = rrn / st->rr;
+    for (;;) {
+#pragma unroll
+      for (int u = 0; u < UNR; u++) {
+        const long long j = j0 + (long long)u * BS;
+        const V x = (V)(rv[u] + b * pv[u]);
+        if (j < d && j >= nlong) p[j] = x;
+        acc += j < d ? (double)x * (double)x : 0.0;
+        if (labw && j < d) lac += labw[j] * (double)x;
+      }
+      j0 += gstep;
+      if (j0 >= d) break;
+#pragma unroll
+      for (int u = 0; u < UNR; u++) {
+        const long long j = j0 + (long long)u * BS;
+        if (j < nlong) {
+          const LongRow lr = long_row_residual<V>((int)j, row_chunk0, chunk_sum, p, rprev, a, sigma0);
+          rv[u] = lr.r;
+          pv[u] = lr.p;
+        } else {
+          rv[u] = j < d ? (double)r[j] : 0.0;
+          pv[u] = j < d ? (double)p[j] : 0.0;
+        }
+      }
     }
   }
   write_partial(pp_part, blockIdx.x, acc);
   if (labw) write_partial(lpart, blockIdx.x, lac);
-  if (last_block(&st->ticket[1])) {
-    resid_scalars(st, rrn, b, hist);
-    if (threadIdx.x == 0) st->ticket[1] = 0;
+  if (last_block(st, TK_DIR)) {
+    if (!ok) {
+      if (threadIdx.x == 0) {
+        st->status = FSDA_E_BREAKDOWN;
+        st->stop = 1;
+      }
+    } else {
+      // r_{i+1}, p_{i+1} of the long rows: every other block has finished reading r_i, p_i
+#pragma unroll
+      for (int k = 0; k < LCACHE; k++) {
+        const int j = threadIdx.x + k * BS;
+        if (j < nlong) {
+          r[j] = (V)lx[k];
+          p[j] = (V)(lx[k] + b * lp[k]);
+        }
+      }
+      for (int j = threadIdx.x + LCACHE * BS; j < nlong; j += BS) {
+        const LongRow lr = long_row_residual<V>(j, row_chunk0, chunk_sum, p, rprev, a, sigma0);
+        r[j] = (V)lr.r;
+        p[j] = (V)(lr.r + b * lr.p);
+      }
+      if (step) step_scalars(st, a);
+      __syncthreads();
+      resid_scalars(st, rrn, b, hist);
+    }
   }
 }
 
