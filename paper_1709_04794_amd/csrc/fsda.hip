@@ -349,7 +349,8 @@ template <class Epi>
 void run_rows(fsda_op* op, const RowPlan& pl, const typename Epi::V* src, Epi epi, double* part, int solve,
               hipStream_t s, int cls) {
   launch(op, cls, s, [&] {
-    hipLaunchKernelGGL(k_rows<Epi>, dim3(pl.grid), dim3(BS), 0, s, pl.rows, src, epi, op->st, part, 0, solve);
+    const size_t smem = pl.rows.mask ? sizeof(typename Epi::V) * pl.rows.nhot : 0;
+    hipLaunchKernelGGL(k_rows<Epi>, dim3(pl.grid), dim3(BS), smem, s, pl.rows, src, epi, op->st, part, 0, solve);
   });
 }
 
@@ -1648,6 +1649,7 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
     op->px = one_bin(rrp, rcol, n, zr);
     op->px.rows.mask = xm;
     op->px.rows.mtop = op->mtop;
+    op->px.rows.nhot = (int)std::min<long long>(HOT, d);
   }
   op->px_user = one_bin(pb->x_rowptr, pb->x_col, n, z);
   op->ps = one_bin(pb->s_rowptr, pb->s_col, n, g);

@@ -490,8 +490,11 @@ struct EpiLapDot {
 // In the X product the most frequent features (internal ids [0, MK), the
 // relabeling puts them first) are held per sample as one 64-bit mask instead of
 // CSR entries: their values are staged in shared memory and added per set bit,
-// with no gathers.
-constexpr int MK = 64;  // features in the mask
+// with no gathers.  The next most frequent ones, up to HOT, stay CSR entries
+// but are read from the same shared copy: random 8-byte gathers are limited by
+// the rate of distinct cache-line lookups, which shared memory does not pay.
+constexpr int MK = 64;     // features in the mask
+constexpr int HOT = 2048;  // features staged in shared memory by the X product (16 KiB of FP64)
 
 struct Rows {
   const int* rowptr;
@@ -502,6 +505,7 @@ struct Rows {
   int item0[MAXBIN + 1];  // work items before bin b; an item is BS/lpr rows (BS when lpr == 0)
   const unsigned long long* mask;  // NULL, or per row the mask features (col then holds only the others)
   int mtop;                        // features in the mask, <= MK
+  int nhot;                        // with mask: features [0, nhot) staged in shared memory, mtop <= nhot <= HOT
 };
 
 template <class Epi>
@@ -511,9 +515,11 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __re
   if (solve && st->stop) return;
   epi.prepare(st);
   const int tid = threadIdx.x;
-  __shared__ V ptop[MK];  // src over the mask features
+  extern __shared__ double rows_smem[];  // with mask: src over the features [0, nhot), launched with that size
+  V* ptop = reinterpret_cast<V*>(rows_smem);
+  const int nhot = R.mask ? R.nhot : 0;
   if (R.mask) {
-    if (tid < MK) ptop[tid] = tid < R.mtop ? src[tid] : (V)0;
+    for (int k = tid; k < nhot; k += BS) ptop[k] = src[k];
     __syncthreads();
   }
   double acc = 0.0;
@@ -550,7 +556,7 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __re
           idx[u] = k < end ? R.col[k] : -1;
         }
 #pragma unroll
-        for (int u = 0; u < RUNR; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : (V)0;
+        for (int u = 0; u < RUNR; u++) g[u] = idx[u] >= 0 ? (idx[u] < nhot ? ptop[idx[u]] : src[idx[u]]) : (V)0;
 #pragma unroll
         for (int u = 0; u < RUNR; u++) v += g[u];
       }
