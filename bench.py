@@ -289,7 +289,11 @@ def main():
                     help="kernel class to time in the timed region (default: the one with the largest total time)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (profiler calibration of byte counters)")
-    ap.add_argument("--graph-steps", type=int, default=0,
+    ap.add_argument("--event-every", type=int, default=7,
+                    help="in the timed region, HIP events around every N-th launch of the timed kernel class "
+                         "(each pair costs a few microseconds of stream time; N prime to the fold interval, so "
+                         "the samples visit every position in a chunk)")
+    ap.add_argument("--graph-steps", type=int, default=2,
                     help="extra timed steps with kernel timing off (chunks replayed as HIP graphs), reported in detail")
     ap.add_argument("--no-paths", action="store_true", help="skip timing the further entry points (detail.paths)")
     ap.add_argument("--experiment", default="", help="'shifted-table': the CG versus shifted CG table instead")
@@ -357,7 +361,7 @@ def main():
     else:
         dom = args.kernel
 
-    op.time_kernel(dom, True)
+    op.time_kernel(dom, True, every=args.event_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     solved = 0
@@ -439,7 +443,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(dom, args.workload),
                      "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                     "launches": klaunch, "event_pair_us": round(pair_us, 2),
+                     "launches": klaunch, "timed_every": args.event_every, "event_pair_us": round(pair_us, 2),
                      "avg_launch_us_with_events": round(raw_launch_s * 1e6, 2)},
         "operator_apply": op_apply,
         "detail": {"iters": None if iters_seen is None else iters_seen.tolist(), "worst_relres": worst,

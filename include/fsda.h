@@ -290,9 +290,11 @@ int fsda_hypergradient(fsda_op *op, const double *W, const double *Lambda, const
 int fsda_project(fsda_op *op, const double *W, int nshift, double *S, void *stream);
 
 /*
- * Per-kernel timing for measurement: enable != 0 makes the handle record a
- * pair of HIP events around every launch of the kernel class `kernel` on the
- * launch stream: 0 = X product, 1 = graph/centring product, 2 = X^T
+ * Per-kernel timing for measurement: enable >= 1 makes the handle record a
+ * pair of HIP events around every enable-th launch (the first, then every
+ * enable-th after it; 1 = every launch) of the kernel class `kernel` on the
+ * launch stream; enable = 0 switches timing off, a negative value is
+ * FSDA_E_RANGE.  Classes: 0 = X product, 1 = graph/centring product, 2 = X^T
  * product (fused with the residual update of every short row of X^T in the
  * feature-space solves), 4 = residual update (sample-space solves), 5 =
  * direction update (feature space: also the residual update of the long rows
@@ -303,8 +305,8 @@ int fsda_project(fsda_op *op, const double *W, int nshift, double *S, void *stre
  * fold.  While timing is on, solves launch kernels
  * directly instead of replaying a graph.  Launches made after the recurrence
  * stopped (which return at once) are not counted.  fsda_kernel_time() returns
- * (host) the summed milliseconds and launch count of the timed class since
- * the last reset and resets them.
+ * (host) the summed milliseconds and count of the timed launches since the
+ * last reset and resets them.
  */
 int fsda_time_kernel(fsda_op *op, int kernel, int enable);
 int fsda_kernel_time(fsda_op *op, double *ms, int64_t *launches);

@@ -327,8 +327,9 @@ class Operator:
         _check(lib().fsda_project(self.handle, _ptr(W), S, _ptr(out), _stream(stream)))
         return out
 
-    def time_kernel(self, kernel: int, enable: bool = True):
-        _check(lib().fsda_time_kernel(self.handle, int(kernel), int(enable)))
+    def time_kernel(self, kernel: int, enable: bool = True, every: int = 1):
+        """Events around every `every`-th launch of kernel class `kernel` (off when not enable)."""
+        _check(lib().fsda_time_kernel(self.handle, int(kernel), int(every) if enable else 0))
 
     def kernel_time(self):
         ms = ctypes.c_double(0)

@@ -250,6 +250,8 @@ struct fsda_op {
   // pair's tag is the iteration index inside its chunk (or -1), so launches
   // after the recurrence stopped (which return at once) are left out
   int tk_class, tk_on;
+  int tk_every;       // time every tk_every-th launch of the class
+  long long tk_seen;  // launches of the class since timing was switched on
   std::vector<TPair> pairs;
   std::vector<hipEvent_t> pool;
   size_t pool_used;
@@ -331,7 +333,8 @@ enum {
 // Records an event pair around `f` when kernel class `cls` is being timed.
 template <class F>
 void launch(fsda_op* op, int cls, hipStream_t s, F f) {
-  const bool tm = op->tk_on && op->tk_class == cls;
+  bool tm = false;
+  if (op->tk_on && op->tk_class == cls) tm = op->tk_seen++ % op->tk_every == 0;
   hipEvent_t a = nullptr, b = nullptr;
   if (tm) {
     a = tk_event(op);
@@ -2039,8 +2042,11 @@ int fsda_multishift_solve_batch(fsda_op* op, int ntarget, const int32_t* lab_idx
 
 int fsda_time_kernel(fsda_op* op, int kernel, int enable) {
   if (!op) return fail(FSDA_E_ARG, "NULL handle");
+  if (enable < 0) return fail(FSDA_E_RANGE, "enable must be >= 0");
   op->tk_class = kernel;
   op->tk_on = enable ? 1 : 0;
+  op->tk_every = enable ? enable : 1;
+  op->tk_seen = 0;
   op->pairs.clear();
   op->pool_used = 0;
   op->tk_ms = 0;
