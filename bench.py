@@ -162,6 +162,80 @@ SHIFTED_TABLE = [  # (betas, CG seconds, shifted CG seconds, speed-up) as printe
 ]
 
 
+def gather_ceiling(args, fsda, torch):
+    """The resource the sparse products are bound by: random 8-byte gathers.
+
+    Times fsda_gather_sum (a bare gather-and-add kernel) on index streams of the
+    workload's sizes: uniform indices, and the index patterns of the products
+    themselves (X^T: the samples of every feature row; X: the features of every
+    sample beyond the ones staged in shared memory; S: the neighbours of every
+    sample).  Also counts the distinct 128-byte lines each row of a product
+    touches (16 FP64 values per line), the number of cache-line lookups a
+    product cannot avoid.  Features are ordered by decreasing frequency, as the
+    operator orders them internally.
+    """
+    import synth
+    pb = synth.workload(args.workload, seed=args.seed, cache_dir=args.cache)
+    n, d = pb.n, pb.d
+    hot = 2048  # features the X product reads from shared memory
+    cnt = np.bincount(pb.x_col, minlength=d)
+    new = np.empty(d, np.int64)
+    new[np.argsort(-cnt, kind="stable")] = np.arange(d)
+    xrow = np.repeat(np.arange(n), np.diff(pb.x_rowptr))
+    xcol = new[pb.x_col]
+    o = np.lexsort((xrow, xcol))
+    xt_row, xt_col = xcol[o], xrow[o]          # rows of X^T (features), entries: samples
+    srow = np.repeat(np.arange(n), np.diff(pb.s_rowptr))
+
+    def lines(rows, cols):
+        return int(np.unique(rows.astype(np.int64) * (1 << 32) + cols // 16).size)
+
+    cold = xcol >= hot
+    stats = {"xt_entries": int(xt_col.size), "xt_lines": lines(xt_row, xt_col),
+             "x_cold_entries": int(cold.sum()), "x_cold_lines": lines(xrow[cold], xcol[cold]),
+             "s_entries": int(pb.s_col.size), "s_lines": lines(srow, pb.s_col)}
+    log("distinct lines per row, summed: %s" % stats)
+
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(args.seed)
+    pattern = {
+        "uniform over n (u, t)": (n, rng.integers(0, n, xt_col.size)),
+        "X^T pattern over n (u)": (n, xt_col),
+        "uniform over d (p)": (d, rng.integers(0, d, xt_col.size)),
+        "X cold pattern over d (p)": (d, xcol[cold]),
+        "S pattern over n (t)": (n, pb.s_col),
+        "uniform over 4096 (L1-resident)": (4096, rng.integers(0, 4096, xt_col.size)),
+    }
+    ev = []
+    for _ in range(50):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        b.record()
+        ev.append((a, b))
+    torch.cuda.synchronize()
+    pair_us = float(np.median([a.elapsed_time(b) for a, b in ev])) * 1e3
+    out = {}
+    for name, (size, idx) in pattern.items():
+        src = torch.rand(size, dtype=torch.float64, device=dev)
+        it = torch.from_numpy(np.ascontiguousarray(idx, dtype=np.int32)).to(dev)
+        part = fsda.gather_sum(src, it)  # checks the indices once
+        want = float(src[it.long()].sum())
+        got = float(part.sum())
+        assert abs(got - want) <= 1e-9 * max(1.0, abs(want)), (name, got, want)
+        best = 1e9
+        for _ in range(10):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fsda.gather_sum(src, it, part=part, checked=True)  # the kernel alone between the events
+            b.record()
+            b.synchronize()
+            best = min(best, a.elapsed_time(b) * 1e3 - pair_us)
+        out[name] = {"gathers": int(idx.size), "us": round(best, 2), "Ggathers_per_s": round(idx.size / best / 1e3, 1)}
+        log("%-34s %9d gathers  %8.2f us  %6.1f G/s" % (name, idx.size, best, idx.size / best / 1e3))
+    print(json.dumps({"experiment": "gather-ceiling", "workload": pb.name, "event_pair_us": round(pair_us, 2),
+                      "lines": stats, "rates": out}))
+
+
 def shifted_table(args, fsda, torch):
     """CG per shift versus the shared-basis recurrence on (X^T X + beta I) w = X^T z, tolerance 1e-3."""
     import synth
@@ -296,7 +370,9 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=2,
                     help="extra timed steps with kernel timing off (chunks replayed as HIP graphs), reported in detail")
     ap.add_argument("--no-paths", action="store_true", help="skip timing the further entry points (detail.paths)")
-    ap.add_argument("--experiment", default="", help="'shifted-table': the CG versus shifted CG table instead")
+    ap.add_argument("--experiment", default="",
+                    help="'shifted-table': the CG versus shifted CG table instead; 'gather-ceiling': the rate of "
+                         "random gathers the sparse products are bound by")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -308,6 +384,9 @@ def main():
 
     if args.experiment == "shifted-table":
         shifted_table(args, fsda, torch)
+        return
+    if args.experiment == "gather-ceiling":
+        gather_ceiling(args, fsda, torch)
         return
     if args.experiment:
         print("unknown experiment %r" % args.experiment, file=sys.stderr)

@@ -311,6 +311,18 @@ int fsda_project(fsda_op *op, const double *W, int nshift, double *S, void *stre
 int fsda_time_kernel(fsda_op *op, int kernel, int enable);
 int fsda_kernel_time(fsda_op *op, double *ms, int64_t *launches);
 
+/*
+ * Measurement aid (no part of the method): partials[b] = the sum of src[idx[k]]
+ * over the k that block b of `grid` blocks takes (grid-stride, 256 threads per
+ * block, 8 independent gathers in flight per thread), enqueued on `stream`.
+ * It measures the rate of random 8-byte gathers, the resource the sparse
+ * products of the solve are bound by.  src (device FP64), idx[nidx] (device
+ * int32, every entry in [0, length of src): not checked), partials[grid]
+ * (device FP64, written).  nidx >= 0, 1 <= grid <= 65536, else FSDA_E_RANGE;
+ * NULL partials (or NULL src/idx with nidx > 0) is FSDA_E_ARG.
+ */
+int fsda_gather_sum(const double *src, const int *idx, int64_t nidx, double *partials, int grid, void *stream);
+
 /* Frees the host handle (and its events); the caller frees the workspace. */
 void fsda_destroy_operator(fsda_op *op);
 

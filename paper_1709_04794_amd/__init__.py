@@ -79,6 +79,7 @@ def lib():
         L.fsda_hypergradient.argtypes = [P, P, P, P, I, P, P, P]
         L.fsda_batch_workspace_size.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_size_t)]
         L.fsda_multishift_solve_batch.argtypes = [P, I, P, P, P, P, I, D, I, I, P, ctypes.c_size_t, P, P, P, P]
+        L.fsda_gather_sum.argtypes = [P, P, ctypes.c_int64, P, I, P]
         L.fsda_destroy_operator.argtypes = [P]
         L.fsda_destroy_operator.restype = None
         L.fsda_last_error.argtypes = []
@@ -86,7 +87,8 @@ def lib():
         for f in (L.fsda_workspace_size, L.fsda_build_operator, L.fsda_rhs, L.fsda_apply, L.fsda_multishift_solve,
                   L.fsda_project, L.fsda_time_kernel, L.fsda_kernel_time, L.fsda_batch_workspace_size,
                   L.fsda_multishift_solve_batch, L.fsda_sa_rhs, L.fsda_sa_solve, L.fsda_regression_solve,
-                  L.fsda_columns_workspace_size, L.fsda_solve_columns, L.fsda_holdout, L.fsda_hypergradient):
+                  L.fsda_columns_workspace_size, L.fsda_solve_columns, L.fsda_holdout, L.fsda_hypergradient,
+                  L.fsda_gather_sum):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -112,6 +114,28 @@ def _stream(stream=None):
 
 def _ptr(t) -> Optional[ctypes.c_void_p]:
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def gather_sum(src, idx, grid: int = 2048, stream=None, part=None, checked: bool = False):
+    """Per-block sums of src[idx] (fsda_gather_sum): a measurement aid for the
+    rate of random 8-byte gathers.  src: contiguous CUDA float64, idx:
+    contiguous CUDA int32 with every entry in [0, len(src)), checked here before
+    the kernel reads them unless the caller has checked them (checked=True, so
+    that a timed call enqueues the kernel alone).  part: optional CUDA float64
+    output of `grid` entries."""
+    import torch
+    if src.dtype != torch.float64 or idx.dtype != torch.int32 or not (src.is_cuda and idx.is_cuda):
+        raise TypeError("src must be CUDA float64 and idx CUDA int32")
+    if not (src.is_contiguous() and idx.is_contiguous()):
+        raise ValueError("src and idx must be contiguous")
+    if not checked and idx.numel() and (int(idx.min()) < 0 or int(idx.max()) >= src.numel()):
+        raise ValueError("idx entries outside [0, len(src))")
+    if part is None:
+        part = torch.empty(grid, dtype=torch.float64, device=src.device)
+    elif part.dtype != torch.float64 or not part.is_cuda or part.numel() < grid:
+        raise ValueError("part must be CUDA float64 with at least grid entries")
+    _check(lib().fsda_gather_sum(_ptr(src), _ptr(idx), idx.numel(), _ptr(part), int(grid), _stream(stream)))
+    return part
 
 
 class Operator:

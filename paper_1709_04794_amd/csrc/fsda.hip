@@ -2054,6 +2054,16 @@ int fsda_time_kernel(fsda_op* op, int kernel, int enable) {
   return FSDA_OK;
 }
 
+int fsda_gather_sum(const double* src, const int* idx, int64_t nidx, double* partials, int grid, void* stream) {
+  if (nidx < 0) return fail(FSDA_E_RANGE, "nidx must be >= 0");
+  if (grid < 1 || grid > 65536) return fail(FSDA_E_RANGE, "grid outside 1..65536");
+  if (!partials || (nidx > 0 && (!src || !idx))) return fail(FSDA_E_ARG, "NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_gather_sum, dim3(grid), dim3(BS), 0, s, src, idx, (long long)nidx, partials);
+  HIP_TRY(hipGetLastError());
+  return FSDA_OK;
+}
+
 int fsda_kernel_time(fsda_op* op, double* ms, int64_t* launches) {
   if (!op || !ms || !launches) return fail(FSDA_E_ARG, "NULL argument");
   int rc = tk_flush(op, 1 << 30);

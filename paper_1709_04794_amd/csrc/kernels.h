@@ -1000,6 +1000,29 @@ __global__ __launch_bounds__(BS) void k_fold(const State* st, const double* __re
 
 __global__ void k_fold_done(State* st) { st->fold_start = st->iter; }
 
+// Measurement aid: per block, the sum of src[idx[k]] over a grid-stride share
+// of k (UNR independent gathers in flight per thread), one partial per block.
+// It isolates the rate of random 8-byte gathers, which bounds the products.
+__global__ __launch_bounds__(BS) void k_gather_sum(const double* __restrict__ src, const int* __restrict__ idx,
+                                                   long long nidx, double* part) {
+  double acc = 0.0;
+  const long long stride = (long long)gridDim.x * BS;
+  for (long long k0 = (long long)blockIdx.x * BS + threadIdx.x; k0 < nidx; k0 += stride * UNR) {
+    int ii[UNR];
+    double g[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; u++) {
+      const long long k = k0 + (long long)u * stride;
+      ii[u] = k < nidx ? idx[k] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; u++) g[u] = ii[u] >= 0 ? src[ii[u]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < UNR; u++) acc += g[u];
+  }
+  write_partial(part, blockIdx.x, acc);
+}
+
 // out = sum of np partials (one block).
 __global__ __launch_bounds__(BS) void k_sum_to(const double* part, int np, double* out) {
   const double all = sum_partials(part, np);
