@@ -162,6 +162,56 @@ SHIFTED_TABLE = [  # (betas, CG seconds, shifted CG seconds, speed-up) as printe
 ]
 
 
+HOT_FEATURES = 2048  # features the X product reads from shared memory
+
+
+def gather_patterns(pb):
+    """Index streams of the three products (features in decreasing frequency, as
+    the operator orders them): X^T gathers u at the samples of every feature
+    row; X gathers p at the features of every sample beyond the ones staged in
+    shared memory; S gathers t at the neighbours of every sample."""
+    n, d = pb.n, pb.d
+    cnt = np.bincount(pb.x_col, minlength=d)
+    new = np.empty(d, np.int64)
+    new[np.argsort(-cnt, kind="stable")] = np.arange(d)
+    xrow = np.repeat(np.arange(n), np.diff(pb.x_rowptr))
+    xcol = new[pb.x_col]
+    o = np.lexsort((xrow, xcol))
+    cold = xcol >= HOT_FEATURES
+    return {"xt": (xcol[o], xrow[o], n), "x_cold": (xrow[cold], xcol[cold], d),
+            "s": (np.repeat(np.arange(n), np.diff(pb.s_rowptr)), pb.s_col, n)}
+
+
+def time_gathers(fsda, torch, size, idx, reps=10, pair_us=0.0):
+    """Best time (us) of the bare gather kernel over idx into a vector of `size`."""
+    src = torch.rand(size, dtype=torch.float64, device="cuda")
+    it = torch.from_numpy(np.ascontiguousarray(idx, dtype=np.int32)).cuda()
+    part = fsda.gather_sum(src, it)  # checks the indices once
+    want = float(src[it.long()].sum())
+    got = float(part.sum())
+    assert abs(got - want) <= 1e-9 * max(1.0, abs(want)), (got, want)
+    best = 1e9
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fsda.gather_sum(src, it, part=part, checked=True)  # the kernel alone between the events
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) * 1e3 - pair_us)
+    return best
+
+
+def event_pair_us(torch, count=200):
+    ev = []
+    for _ in range(count):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        b.record()
+        ev.append((a, b))
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev])) * 1e3
+
+
 def gather_ceiling(args, fsda, torch):
     """The resource the sparse products are bound by: random 8-byte gathers.
 
@@ -177,59 +227,29 @@ def gather_ceiling(args, fsda, torch):
     import synth
     pb = synth.workload(args.workload, seed=args.seed, cache_dir=args.cache)
     n, d = pb.n, pb.d
-    hot = 2048  # features the X product reads from shared memory
-    cnt = np.bincount(pb.x_col, minlength=d)
-    new = np.empty(d, np.int64)
-    new[np.argsort(-cnt, kind="stable")] = np.arange(d)
-    xrow = np.repeat(np.arange(n), np.diff(pb.x_rowptr))
-    xcol = new[pb.x_col]
-    o = np.lexsort((xrow, xcol))
-    xt_row, xt_col = xcol[o], xrow[o]          # rows of X^T (features), entries: samples
-    srow = np.repeat(np.arange(n), np.diff(pb.s_rowptr))
+    pat = gather_patterns(pb)
 
     def lines(rows, cols):
         return int(np.unique(rows.astype(np.int64) * (1 << 32) + cols // 16).size)
 
-    cold = xcol >= hot
-    stats = {"xt_entries": int(xt_col.size), "xt_lines": lines(xt_row, xt_col),
-             "x_cold_entries": int(cold.sum()), "x_cold_lines": lines(xrow[cold], xcol[cold]),
-             "s_entries": int(pb.s_col.size), "s_lines": lines(srow, pb.s_col)}
+    stats = {"xt_entries": int(pat["xt"][1].size), "xt_lines": lines(*pat["xt"][:2]),
+             "x_cold_entries": int(pat["x_cold"][1].size), "x_cold_lines": lines(*pat["x_cold"][:2]),
+             "s_entries": int(pat["s"][1].size), "s_lines": lines(*pat["s"][:2])}
     log("distinct lines per row, summed: %s" % stats)
-
-    dev = torch.device("cuda")
     rng = np.random.default_rng(args.seed)
-    pattern = {
-        "uniform over n (u, t)": (n, rng.integers(0, n, xt_col.size)),
-        "X^T pattern over n (u)": (n, xt_col),
-        "uniform over d (p)": (d, rng.integers(0, d, xt_col.size)),
-        "X cold pattern over d (p)": (d, xcol[cold]),
-        "S pattern over n (t)": (n, pb.s_col),
-        "uniform over 4096 (L1-resident)": (4096, rng.integers(0, 4096, xt_col.size)),
+    z = pat["xt"][1].size
+    streams = {
+        "uniform over n (u, t)": (n, rng.integers(0, n, z)),
+        "X^T pattern over n (u)": (n, pat["xt"][1]),
+        "uniform over d (p)": (d, rng.integers(0, d, z)),
+        "X cold pattern over d (p)": (d, pat["x_cold"][1]),
+        "S pattern over n (t)": (n, pat["s"][1]),
+        "uniform over 4096 (L1-resident)": (4096, rng.integers(0, 4096, z)),
     }
-    ev = []
-    for _ in range(50):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        b.record()
-        ev.append((a, b))
-    torch.cuda.synchronize()
-    pair_us = float(np.median([a.elapsed_time(b) for a, b in ev])) * 1e3
+    pair_us = event_pair_us(torch, 50)
     out = {}
-    for name, (size, idx) in pattern.items():
-        src = torch.rand(size, dtype=torch.float64, device=dev)
-        it = torch.from_numpy(np.ascontiguousarray(idx, dtype=np.int32)).to(dev)
-        part = fsda.gather_sum(src, it)  # checks the indices once
-        want = float(src[it.long()].sum())
-        got = float(part.sum())
-        assert abs(got - want) <= 1e-9 * max(1.0, abs(want)), (name, got, want)
-        best = 1e9
-        for _ in range(10):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-            fsda.gather_sum(src, it, part=part, checked=True)  # the kernel alone between the events
-            b.record()
-            b.synchronize()
-            best = min(best, a.elapsed_time(b) * 1e3 - pair_us)
+    for name, (size, idx) in streams.items():
+        best = time_gathers(fsda, torch, size, idx, pair_us=pair_us)
         out[name] = {"gathers": int(idx.size), "us": round(best, 2), "Ggathers_per_s": round(idx.size / best / 1e3, 1)}
         log("%-34s %9d gathers  %8.2f us  %6.1f G/s" % (name, idx.size, best, idx.size / best / 1e3))
     print(json.dumps({"experiment": "gather-ceiling", "workload": pb.name, "event_pair_us": round(pair_us, 2),
@@ -370,6 +390,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=2,
                     help="extra timed steps with kernel timing off (chunks replayed as HIP graphs), reported in detail")
     ap.add_argument("--no-paths", action="store_true", help="skip timing the further entry points (detail.paths)")
+    ap.add_argument("--no-gather-ceiling", action="store_true",
+                    help="skip timing the bare gathers of the dominant product's index stream")
     ap.add_argument("--experiment", default="",
                     help="'shifted-table': the CG versus shifted CG table instead; 'gather-ceiling': the rate of "
                          "random gathers the sparse products are bound by")
@@ -470,14 +492,7 @@ def main():
 
     # the event pair around each timed launch costs some time of its own on the
     # stream: measure empty pairs the same way and take that off
-    ev_ms = []
-    for _ in range(200):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        b.record()
-        ev_ms.append((a, b))
-    torch.cuda.synchronize()
-    pair_us = float(np.median([a.elapsed_time(b) for a, b in ev_ms])) * 1e3
+    pair_us = event_pair_us(torch)
     raw_launch_s = (kms / 1e3) / max(klaunch, 1)
     avg_launch_s = max(raw_launch_s - pair_us * 1e-6, 1e-9)
     # the operator apply of one iteration (X, graph and X^T passes) against its
@@ -499,6 +514,17 @@ def main():
                             "minus the event-pair overhead"}
     bytes_launch = algorithmic_bytes(dom, pb, S, args.chunk)
     achieved = bytes_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    # the products are bound by random 8-byte gathers: time a bare gather kernel
+    # on the dominant product's own index stream
+    gather = None
+    pname = {fsda.K_XT: "xt", fsda.K_X: "x_cold", fsda.K_S: "s"}.get(dom)
+    if pname is not None and not args.no_gather_ceiling:
+        _, idx, size = gather_patterns(pb)[pname]
+        g_us = time_gathers(fsda, torch, size, idx, pair_us=pair_us)
+        gather = {"pattern": pname, "gathers": int(idx.size), "bare_gather_us": round(g_us, 2),
+                  "kernel_us": round(avg_launch_s * 1e6, 2), "frac": round(g_us / (avg_launch_s * 1e6), 4),
+                  "note": "time of a bare gather-and-add kernel over the same index stream / the kernel's "
+                          "time (python bench.py --experiment gather-ceiling covers all three products)"}
     value = solved / elapsed
     out = {
         "metric": "shifted SDA solves/sec at rel. residual 1e-8",
@@ -523,7 +549,7 @@ def main():
                      "traffic": measured_traffic(dom, args.workload),
                      "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "launches": klaunch, "timed_every": args.event_every, "event_pair_us": round(pair_us, 2),
-                     "avg_launch_us_with_events": round(raw_launch_s * 1e6, 2)},
+                     "avg_launch_us_with_events": round(raw_launch_s * 1e6, 2), "gather_ceiling": gather},
         "operator_apply": op_apply,
         "detail": {"iters": None if iters_seen is None else iters_seen.tolist(), "worst_relres": worst,
                    "solved_per_step": solved / args.steps, "build_s": round(build_s, 3),
