@@ -60,8 +60,9 @@ extern "C" {
 
 /* Limits of one handle. */
 #define FSDA_MAX_SHIFTS 64
-#define FSDA_MAX_CHUNK 64
-#define FSDA_MAX_TARGETS 64 /* targets of one fsda_multishift_solve_batch call */
+#define FSDA_MAX_CHUNK 256
+#define FSDA_MAX_TARGETS 64     /* targets of one fsda_multishift_solve_batch call */
+#define FSDA_MAX_BATCH_CHUNK 64 /* fold interval of fsda_multishift_solve_batch */
 
 typedef struct fsda_op fsda_op; /* opaque handle, host memory */
 
@@ -147,8 +148,11 @@ int fsda_apply(fsda_op *op, double sigma, const double *p, double *q, void *stre
  *  rtol        > 0: shift s stops updating once |zeta_s| ||r|| <= rtol ||b||.
  *  maxit       >= 1 iterations of the shared recurrence.
  *  chunk       1..max_chunk: iterations between folds of the per-shift state
- *              and between host checks for termination (0 = default 32, capped
- *              at max_chunk).  Every chunk gives the same result.
+ *              and between host checks for termination (0 = default 128,
+ *              capped at max_chunk).  The recurrence, the iteration counts and
+ *              the stopping points do not depend on chunk; W does only through
+ *              the order of its rounding (a chunk's per-shift updates are
+ *              applied as one linear combination of its residuals).
  *  W[nshift][d] device FP64 output, w_s for beta_s.
  *  iters[nshift] host int output: iterations after which shift s stopped
  *              (FSDA_MIXED: plus the iterations of its correction solves).
@@ -224,7 +228,9 @@ int fsda_regression_solve(fsda_op *op, const double *z, const double *betas, int
  *                labels +1/-1, both classes present).
  *  lab_off[ntarget+1] host offsets, lab_off[0] = 0.
  *  betas, nshift, rtol, maxit, chunk: as in fsda_multishift_solve (1 <= nshift
- *                <= FSDA_MAX_SHIFTS; the handle's max_shifts does not apply).
+ *                <= FSDA_MAX_SHIFTS; the handle's max_shifts does not apply;
+ *                0 <= chunk <= FSDA_MAX_BATCH_CHUNK, 0 = default 32; here every
+ *                chunk gives the same bits).
  *  workspace     device, 256-byte aligned, ws_bytes >= fsda_batch_workspace_size()
  *                for the same ntarget, nshift and chunk; scratch for this call only.
  *  W[ntarget][nshift][d] device FP64 output.

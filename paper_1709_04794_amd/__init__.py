@@ -27,7 +27,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "fsda.h")
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_CSR, E_LABELS, E_RANGE, E_BREAKDOWN, E_WORKSPACE, E_HIP, E_OVERFLOW = -1, -2, -3, -4, -5, -6, -7, -8
 FP64, MIXED = 0, 1
-MAX_SHIFTS, MAX_CHUNK, MAX_TARGETS = 64, 64, 64
+MAX_SHIFTS, MAX_CHUNK, MAX_TARGETS, MAX_BATCH_CHUNK = 64, 256, 64, 64
 # kernel classes for fsda_time_kernel
 K_X, K_S, K_XT, K_RESID, K_PUPD, K_FOLD = 0, 1, 2, 4, 5, 6
 # ... and of the batched FP32 correction solves of the mixed path
@@ -147,7 +147,7 @@ class Operator:
     """
 
     def __init__(self, n: int, d: int, x_rowptr, x_col, s_rowptr, s_col, lab_idx, lab_y, alpha: float,
-                 precision: int = FP64, max_shifts: int = 32, max_chunk: int = 32, stream=None):
+                 precision: int = FP64, max_shifts: int = 32, max_chunk: int = 128, stream=None):
         import torch
         self.n, self.d = int(n), int(d)
         self.alpha = float(alpha)
@@ -175,7 +175,7 @@ class Operator:
         self.device = x_col.device
 
     @classmethod
-    def from_problem(cls, pb, precision: int = FP64, max_shifts: Optional[int] = None, max_chunk: int = 32,
+    def from_problem(cls, pb, precision: int = FP64, max_shifts: Optional[int] = None, max_chunk: int = 128,
                      device: str = "cuda", alpha: Optional[float] = None, **kw):
         """Uploads a ``synth.Problem``-like object (numpy arrays) and builds."""
         import torch

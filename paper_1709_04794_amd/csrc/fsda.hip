@@ -82,7 +82,7 @@ int pow2_at_least(long long x) {
 int batch_tile(int ncol) { return std::max(4, pow2_at_least(ncol)); }
 
 struct Layout {
-  size_t st, part, hist, labw, ycen, zw, t, u, b, p, q, bu, new2old, old2new, xcol, xt_rowptr, xt_col;
+  size_t st, part, hist, fcoef, labw, ycen, zw, t, u, b, p, q, bu, new2old, old2new, xcol, xt_rowptr, xt_col;
   size_t xmask, xrrowptr, xrcol;  // X split into mask features and the rest
   size_t chunk_row, chunk_beg, lpart, row_chunk0;
   size_t uni;
@@ -113,6 +113,7 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->st = take(sizeof(State));
   L->part = take(sizeof(double) * NSITE * NPART);
   L->hist = take(sizeof(double) * MAXCHUNK * MAXS * 4);
+  L->fcoef = take(sizeof(FoldCoef));
   L->labw = take(8 * n);
   L->ycen = take(8 * n);
   L->zw = take(8 * n);
@@ -474,23 +475,14 @@ void iteration(fsda_op* op, int mode, hipStream_t s, int tag) {
 
 template <typename V>
 void fold(fsda_op* op, double* W, int nshift, int chunk, int mode, hipStream_t s) {
+  (void)chunk;
   const long long d = mode == MODE_SA ? op->pb.n : op->pb.d;
   const int g = grid_for(d, GRID_FOLD);
-  V* ring = as<V>(op->ring);
-  V* P = as<V>(op->P);
+  FoldCoef* cf = at<FoldCoef>(op, op->L.fcoef);
+  hipLaunchKernelGGL(k_fold_coef, dim3(1), dim3(BS), 0, s, op->st, op->hist, cf, nshift);
   launch(op, KC_FOLD, s, [&] {
-    if (chunk <= 8)
-      hipLaunchKernelGGL((k_fold<8, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldv, W, d, P,
-                         op->L.ldv, nshift);
-    else if (chunk <= 16)
-      hipLaunchKernelGGL((k_fold<16, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldv, W, d, P,
-                         op->L.ldv, nshift);
-    else if (chunk <= 32)
-      hipLaunchKernelGGL((k_fold<32, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldv, W, d, P,
-                         op->L.ldv, nshift);
-    else
-      hipLaunchKernelGGL((k_fold<64, V>), dim3(g), dim3(BS), 0, s, op->st, op->hist, ring, op->L.ldv, W, d, P,
-                         op->L.ldv, nshift);
+    hipLaunchKernelGGL(k_fold_apply<V>, dim3(g), dim3(BS), 0, s, op->st, cf, as<V>(op->ring), op->L.ldv, W, d,
+                       as<V>(op->P), op->L.ldv, nshift);
   });
   hipLaunchKernelGGL(k_fold_done, dim3(1), dim3(1), 0, s, op->st);
 }
@@ -1713,7 +1705,7 @@ int fsda_multishift_solve(fsda_op* op, const double* b, const double* betas, int
   if (!(rtol > 0.0)) return fail(FSDA_E_RANGE, "rtol must be > 0");
   if (maxit < 1) return fail(FSDA_E_RANGE, "maxit must be >= 1");
   if (chunk < 0) return fail(FSDA_E_RANGE, "chunk must be >= 0");
-  if (chunk == 0) chunk = 32;
+  if (chunk == 0) chunk = 128;
   chunk = std::min(chunk, op->max_chunk);
   while (chunk > 1 && chunk * nshift > MAXCHUNK * MAXS / 2) chunk >>= 1;
   double sigma0 = betas[0];
@@ -1794,7 +1786,7 @@ int fsda_sa_solve(fsda_op* op, const double* g, const double* betas, int nshift,
   if (!(rtol > 0.0)) return fail(FSDA_E_RANGE, "rtol must be > 0");
   if (maxit < 1) return fail(FSDA_E_RANGE, "maxit must be >= 1");
   if (chunk < 0) return fail(FSDA_E_RANGE, "chunk must be >= 0");
-  if (chunk == 0) chunk = 32;
+  if (chunk == 0) chunk = 128;
   chunk = std::min(chunk, op->max_chunk);
   while (chunk > 1 && chunk * nshift > MAXCHUNK * MAXS / 2) chunk >>= 1;
   double sigma0 = betas[0];
@@ -1829,7 +1821,7 @@ int fsda_regression_solve(fsda_op* op, const double* z, const double* betas, int
   if (!(rtol > 0.0)) return fail(FSDA_E_RANGE, "rtol must be > 0");
   if (maxit < 1) return fail(FSDA_E_RANGE, "maxit must be >= 1");
   if (chunk < 0) return fail(FSDA_E_RANGE, "chunk must be >= 0");
-  if (chunk == 0) chunk = 32;
+  if (chunk == 0) chunk = 128;
   chunk = std::min(chunk, op->max_chunk);
   while (chunk > 1 && chunk * nshift > MAXCHUNK * MAXS / 2) chunk >>= 1;
   double sigma0 = betas[0];
@@ -2003,7 +1995,7 @@ int fsda_batch_workspace_size(const fsda_op* op, int ntarget, int nshift, int ch
   if (!op || !bytes) return fail(FSDA_E_ARG, "NULL argument");
   if (ntarget < 1 || ntarget > FSDA_MAX_TARGETS) return fail(FSDA_E_ARG, "ntarget outside 1..FSDA_MAX_TARGETS");
   if (nshift < 1 || nshift > FSDA_MAX_SHIFTS) return fail(FSDA_E_ARG, "nshift outside 1..FSDA_MAX_SHIFTS");
-  if (chunk < 0 || chunk > FSDA_MAX_CHUNK) return fail(FSDA_E_RANGE, "chunk outside 0..FSDA_MAX_CHUNK");
+  if (chunk < 0 || chunk > FSDA_MAX_BATCH_CHUNK) return fail(FSDA_E_RANGE, "chunk outside 0..FSDA_MAX_BATCH_CHUNK");
   if (chunk == 0) chunk = 32;
   TLayout L;
   tlayout(op, batch_tile(ntarget), nshift, chunk, &L);

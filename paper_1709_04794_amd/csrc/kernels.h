@@ -23,7 +23,7 @@ namespace fsda {
 
 constexpr int BS = 256;       // threads per block (4 waves of 64)
 constexpr int MAXS = 64;      // shifts per handle
-constexpr int MAXCHUNK = 64;  // iterations per shift-state fold
+constexpr int MAXCHUNK = 256;  // iterations per shift-state fold
 constexpr int NPART = 4096;   // partials per reduction site
 constexpr int MAXBIN = 8;     // row-length bins of a row product
 constexpr int UNR = 8;        // independent loads per thread in streaming loops
@@ -943,55 +943,82 @@ __global__ __launch_bounds__(BS) void k_pupdate(State* st, V* ring, V* p, long l
   }
 }
 
-// Fold of iterations [fold_start, iter): per element, keep the buffered
-// residuals in registers and replay, shift by shift, the recurrences
-//   W_s += a_s P_s ;  P_s = zeta_{k+1,s} r_{k+1} + b_s P_s
-// exactly as a per-iteration pass would, in the same order.  The coefficients
-// are the same for every lane (uniform loads through the scalar cache); a
-// frozen shift carries the identity step (0, 0, 1), and a shift frozen before
-// the chunk is skipped.  Shifts go in groups of SG so that their W and P loads
-// are in flight together.
-constexpr int SG = 4;
-template <int M, typename V>
-__global__ __launch_bounds__(BS) void k_fold(const State* st, const double* __restrict__ hist, const V* ring,
-                                             long long ldd, double* W, long long d, V* P, long long ldp,
-                                             int nshift) {
-  const int k0 = st->fold_start, k1 = st->iter, m = st->chunk;
-  const int cnt = k1 - k0;
+// Fold of iterations [fold_start, iter) into the per-shift state.  Per shift s
+// the iterations k = 0 .. cnt-1 of the chunk apply
+//   W_s += a_k P_s ;  P_s = zeta_k r_k + b_k P_s       (Alg. 3; r_k the residual of iteration fold_start + k + 1)
+// (a frozen shift carries the identity step a = zeta = 0, b = 1).  Unrolled,
+//   W_s <- W_s + A_s P_s + sum_k H_k,s r_k ,   P_s <- B_s P_s + sum_k G_k,s r_k
+// with, backwards from G'_{cnt-1} = 0 and E_{cnt-1} = 1,
+//   H_k = zeta_k G'_k, G_k = zeta_k E_k,  G'_{k-1} = a_k + b_k G'_k,  E_{k-1} = b_k E_k,
+//   A_s = G'_{-1}, B_s = E_{-1}.
+// k_fold_coef (one block, one thread per shift) computes the coefficients;
+// k_fold_apply streams the buffered residuals once per group of FG shifts and
+// reads and writes W_s and P_s once per chunk: a (2 FG x cnt) by (cnt x d)
+// contraction plus the two scalings, per chunk instead of per iteration.
+constexpr int FG = 16;  // shifts per pass over the buffered residuals
+struct FoldCoef {
+  double h[MAXCHUNK][MAXS];  // H_k,s
+  double g[MAXCHUNK][MAXS];  // G_k,s
+  double a[MAXS], b[MAXS];   // A_s, B_s
+  int on[MAXS];              // shift active at the first iteration of the chunk
+};
+
+__global__ __launch_bounds__(BS) void k_fold_coef(const State* st, const double* __restrict__ hist, FoldCoef* cf,
+                                                  int nshift) {
+  const int k0 = st->fold_start, cnt = st->iter - k0, m = st->chunk;
+  const int s = threadIdx.x;
+  if (cnt <= 0 || s >= nshift) return;
+  double gp = 0.0, e = 1.0;
+  for (int k = cnt - 1; k >= 0; k--) {
+    const double* h = hist + ((size_t)((k0 + k) % m) * MAXS + s) * 4;
+    const double a = h[0], z = h[1], b = h[2];
+    cf->h[k][s] = z * gp;
+    cf->g[k][s] = z * e;
+    gp = a + b * gp;
+    e = b * e;
+  }
+  cf->a[s] = gp;
+  cf->b[s] = e;
+  cf->on[s] = hist[((size_t)(k0 % m) * MAXS + s) * 4 + 3] != 0.0;
+}
+
+template <typename V>
+__global__ __launch_bounds__(BS) void k_fold_apply(const State* st, const FoldCoef* __restrict__ cf, const V* ring,
+                                                   long long ldd, double* W, long long d, V* P, long long ldp,
+                                                   int nshift) {
+  const int k0 = st->fold_start, cnt = st->iter - k0, m = st->chunk;
   if (cnt <= 0) return;
+  constexpr int KU = 4;  // buffered residuals in flight
   for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
-    double rv[M];
+    for (int s0 = 0; s0 < nshift; s0 += FG) {
+      double ah[FG], ag[FG];
 #pragma unroll
-    for (int k = 0; k < M; k++)
-      if (k < cnt) rv[k] = (double)ring[(long long)((k0 + k + 1) % m) * ldd + j];
-    for (int s0 = 0; s0 < nshift; s0 += SG) {
-      double w[SG], pp[SG];
-      bool on[SG];
+      for (int g = 0; g < FG; g++) ah[g] = ag[g] = 0.0;
+      for (int k = 0; k < cnt; k += KU) {
+        double rv[KU];
 #pragma unroll
-      for (int g = 0; g < SG; g++) {
-        const int s = s0 + g;
-        on[g] = s < nshift && hist[((size_t)(k0 % m) * MAXS + s) * 4 + 3] != 0.0;
-        w[g] = on[g] ? W[s * d + j] : 0.0;
-        pp[g] = on[g] ? (double)P[s * ldp + j] : 0.0;
-      }
+        for (int u = 0; u < KU; u++)
+          rv[u] = k + u < cnt ? (double)ring[(long long)((k0 + k + u + 1) % m) * ldd + j] : 0.0;
 #pragma unroll
-      for (int k = 0; k < M; k++) {
-        if (k < cnt) {
-          const double* c = hist + (size_t)((k0 + k) % m) * MAXS * 4;
+        for (int u = 0; u < KU; u++) {
+          if (k + u < cnt) {
+            const double* hk = cf->h[k + u] + s0;
+            const double* gk = cf->g[k + u] + s0;
 #pragma unroll
-          for (int g = 0; g < SG; g++) {
-            const double* cs = c + (s0 + g) * 4;
-            w[g] += cs[0] * pp[g];
-            pp[g] = (double)(V)(cs[1] * rv[k] + cs[2] * pp[g]);  // P_s is stored in V
+            for (int g = 0; g < FG; g++) {
+              ah[g] += hk[g] * rv[u];
+              ag[g] += gk[g] * rv[u];
+            }
           }
         }
       }
 #pragma unroll
-      for (int g = 0; g < SG; g++) {
+      for (int g = 0; g < FG; g++) {
         const int s = s0 + g;
-        if (on[g]) {
-          W[s * d + j] = w[g];
-          P[s * ldp + j] = (V)pp[g];
+        if (s < nshift && cf->on[s]) {
+          const double p = (double)P[s * ldp + j];
+          W[s * d + j] += cf->a[s] * p + ah[g];
+          P[s * ldp + j] = (V)(cf->b[s] * p + ag[g]);  // P_s is stored in V
         }
       }
     }

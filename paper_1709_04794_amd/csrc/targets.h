@@ -18,6 +18,7 @@
 namespace fsda {
 
 constexpr int TS_MAX = 64;  // shifts per target
+constexpr int TSG = 4;      // shifts per group in ts_fold (their W and P loads in flight together)
 
 struct TState {
   int iter, stop, status, maxit;
@@ -327,11 +328,11 @@ __global__ __launch_bounds__(BS) void ts_fold(const TState* st, const double* __
 #pragma unroll
     for (int k = 0; k < M; k++)
       if (k < cnt) rv[k] = ring[((size_t)((k0 + k + 1) % m) * T + c) * ld + j];
-    for (int s0 = 0; s0 < nshift; s0 += SG) {
-      double w[SG], pp[SG];
-      bool on[SG];
+    for (int s0 = 0; s0 < nshift; s0 += TSG) {
+      double w[TSG], pp[TSG];
+      bool on[TSG];
 #pragma unroll
-      for (int g = 0; g < SG; g++) {
+      for (int g = 0; g < TSG; g++) {
         const int s = s0 + g;
         on[g] = s < nshift && hist[((((size_t)(k0 % m)) * T + c) * nshift + s) * 4 + 3] != 0.0;
         w[g] = on[g] ? W[((size_t)c * nshift + s) * d + j] : 0.0;
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(BS) void ts_fold(const TState* st, const double* __
         if (k < cnt) {
           const double* h = hist + (((size_t)((k0 + k) % m) * T + c) * nshift) * 4;
 #pragma unroll
-          for (int g = 0; g < SG; g++) {
+          for (int g = 0; g < TSG; g++) {
             if (s0 + g < nshift) {
               const double* cs = h + (s0 + g) * 4;
               w[g] += cs[0] * pp[g];
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(BS) void ts_fold(const TState* st, const double* __
         }
       }
 #pragma unroll
-      for (int g = 0; g < SG; g++) {
+      for (int g = 0; g < TSG; g++) {
         const int s = s0 + g;
         if (on[g]) {
           W[((size_t)c * nshift + s) * d + j] = w[g];

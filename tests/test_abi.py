@@ -65,7 +65,7 @@ def test_workspace_size_rejects(kw, code):
     assert len(fsda.lib().fsda_last_error()) > 0
 
 
-@pytest.mark.parametrize("ms,mc", [(0, 32), (65, 32), (8, 0), (8, 65)])
+@pytest.mark.parametrize("ms,mc", [(0, 32), (65, 32), (8, 0), (8, fsda.MAX_CHUNK + 1)])
 def test_workspace_size_rejects_limits(ms, mc):
     rc, _ = _ws(_pb(), ms, mc)
     assert rc == fsda.E_RANGE

@@ -66,7 +66,10 @@ def test_regression_ragged_chunks_and_repeat():
     zt = torch.from_numpy(z).cuda()
     ref, it0, _, _ = op.regression_solve(zt, betas, rtol=1e-11, chunk=32)
     W, it1, _, _ = op.regression_solve(zt, betas, rtol=1e-11, chunk=7)
-    assert torch.equal(W, ref) and np.array_equal(it0, it1)
+    assert np.array_equal(it0, it1)  # the fold interval changes W only through its rounding
+    assert relerr(W.cpu().numpy(), ref.cpu().numpy()) < 1e-12
+    W2, _, _, _ = op.regression_solve(zt, betas, rtol=1e-11, chunk=7)
+    assert torch.equal(W2, W)
     Wr, *_ = oracle.reg_solve(pb, z, betas, rtol=1e-13, maxit=50000)
     for s in range(betas.size):
         assert relerr(W[s].cpu().numpy(), Wr[s]) < 1e-6

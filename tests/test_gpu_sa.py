@@ -75,12 +75,14 @@ def test_sa_chunk_bits_and_graph(tiny, chunk, monkeypatch):
     op = fsda.Operator.from_problem(tiny, alpha=0.5)
     ref, it0, _, _ = op.sa_solve(tiny.betas, rtol=1e-9, chunk=16)
     Z, it1, _, _ = op.sa_solve(tiny.betas, rtol=1e-9, chunk=chunk)
-    assert torch.equal(Z, ref) and np.array_equal(it0, it1)
+    assert np.array_equal(it0, it1)
+    # the fold interval changes Z only through the order of its rounding
+    assert relerr(Z.cpu().numpy(), ref.cpu().numpy()) < 1e-12
     monkeypatch.setenv("FSDA_NO_GRAPH", "1")
     opd = fsda.Operator.from_problem(tiny, alpha=0.5)
     monkeypatch.delenv("FSDA_NO_GRAPH")
     Zd, itd, _, _ = opd.sa_solve(tiny.betas, rtol=1e-9, chunk=chunk)
-    assert torch.equal(Zd, ref)
+    assert torch.equal(Zd, Z)  # graph replay and direct launches: the same bits
 
 
 def test_sa_ragged_and_user_rhs():
