@@ -141,7 +141,7 @@ def time_paths(pb, fsda, torch, chunk: int):
     del op_m
     op = fsda.Operator.from_problem(pb, max_chunk=chunk)
     labs = synth.target_labels(pb, 16, seed=1)
-    dt, (W, it, rel, st) = timed(lambda: op.solve_batch(labs, pb.betas, rtol=pb.rtol, chunk=chunk))
+    dt, (W, it, rel, st) = timed(lambda: op.solve_batch(labs, pb.betas, rtol=pb.rtol))  # its default fold interval
     out["batched_targets"] = {"targets": len(labs), "seconds": round(dt, 4),
                               "shifted_solves_per_s": round(int((rel <= TARGET_RELRES).sum()) / dt, 3),
                               "worst_relres": float(rel.max()), "max_iters": int(it.max()), "status": st,
@@ -153,6 +153,32 @@ def time_paths(pb, fsda, torch, chunk: int):
                            "worst_relres": float(rel.max()), "max_iters": int(it.max()), "status": st,
                            "what": "Alg. sasda ratings for every shift, FP64, to rel. residual %.0e" % pb.rtol}
     op.close()
+    del op
+    # hold-out loss of every shift and its gradient in (log beta, alpha) by the
+    # adjoint method: forward solve, hold-out loss, batched adjoint solves, gradient
+    from paper_1709_04794_amd import hyper
+    rng = np.random.default_rng(3)
+    pool = np.setdiff1d(np.arange(pb.n), pb.lab_idx)
+    ho = np.sort(rng.choice(pool, size=min(2000, pool.size), replace=False))
+    ho_y = np.where(synth.normal(ho.size, seed=3, stream=7) > 0, 1.0, -1.0)
+    obj = hyper.Objective(pb, ho, ho_y, rtol=pb.rtol)
+    lb = torch.tensor(np.log(pb.betas), dtype=torch.float64, requires_grad=True)
+    al = torch.tensor(float(pb.alpha), dtype=torch.float64, requires_grad=True)
+
+    def hypergrad():
+        lb.grad = al.grad = None
+        loss = hyper.HoldoutLoss.apply(lb, al, obj)
+        loss.sum().backward()
+        return loss
+
+    dt, loss = timed(hypergrad)
+    out["hypergradient"] = {"seconds": round(dt, 4), "shifts": S, "holdout_rows": int(ho.size),
+                            "finite": bool(torch.isfinite(lb.grad).all() and torch.isfinite(al.grad)),
+                            "what": "hold-out loss of %d shifts and its gradient in (log beta, alpha): forward solve, "
+                                    "hold-out loss, %d adjoint solves (batched), gradient; FP64, rtol %.0e"
+                                    % (S, S, pb.rtol)}
+    for o in obj._ops.values():
+        o.close()
     return out
 
 
