@@ -199,6 +199,86 @@ __device__ void resid_scalars(State* st, double rrn, double b, double* hist) {
   }
 }
 
+// The shift state of thread s (shift s), loaded at the start of a kernel so
+// that its last block can run step_scalars and resid_scalars on registers.
+struct ShiftRegs {
+  double zp, z, sig, a_prev, b_cur, tol;
+  int active, nshift, maxit;
+};
+__device__ __forceinline__ ShiftRegs load_shift_regs(const State* st) {
+  ShiftRegs q;
+  q.nshift = st->nshift;
+  q.maxit = st->maxit;
+  q.a_prev = st->a_prev;
+  q.b_cur = st->b_cur;
+  q.tol = st->tol;
+  const int s = threadIdx.x;
+  q.active = 0;
+  q.zp = q.z = q.sig = 0.0;
+  if (s < q.nshift) {
+    q.active = st->active[s];
+    q.zp = st->zp[s];
+    q.z = st->z[s];
+    q.sig = st->sig[s];
+  }
+  return q;
+}
+
+// step_scalars(st, a) followed by resid_scalars(st, rrn, b, hist), the same
+// arithmetic in the same order, from the registers q of the same kernel.
+__device__ void step_resid_scalars(State* st, const ShiftRegs& q, int i, double a, double rrn, double b,
+                                   double* hist) {
+  const double rn = sqrt(rrn);
+  const int slot = i % st->chunk;
+  const int s = threadIdx.x;
+  int still = 0;
+  if (s < q.nshift) {
+    double* h = hist + ((size_t)slot * MAXS + s) * 4;
+    if (q.active) {
+      const double den = a * q.b_cur * (q.zp - q.z) + q.zp * q.a_prev * (1.0 + q.sig * a);
+      const double zn = q.zp * q.z * q.a_prev / den;
+      const double as = a * zn / q.z;
+      const double ratio = zn / q.z;
+      const double bs = b * ratio * ratio;
+      st->zn[s] = zn;
+      st->as[s] = as;
+      st->bs[s] = bs;
+      h[0] = as;
+      h[1] = zn;
+      h[2] = bs;
+      h[3] = 1.0;
+      st->zp[s] = q.z;
+      st->z[s] = zn;
+      if (fabs(zn) * rn <= q.tol) {
+        st->active[s] = 0;
+        st->conv[s] = i + 1;
+      } else {
+        still = 1;
+        if (i + 1 >= q.maxit) st->conv[s] = i + 1;
+      }
+    } else {  // identity step
+      h[0] = 0.0;
+      h[1] = 0.0;
+      h[2] = 1.0;
+      h[3] = 0.0;
+    }
+  }
+  const int any = __syncthreads_or(still);
+  if (threadIdx.x == 0) {
+    st->a_cur = a;
+    st->a_prev = a;
+    st->b_cur = b;
+    st->rr = rrn;
+    st->iter = i + 1;
+    if (!any) {
+      st->stop = 1;
+    } else if (i + 1 >= q.maxit) {
+      st->stop = 1;
+      st->status = FSDA_NOT_CONVERGED;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // row epilogues of the sparse products
 // ---------------------------------------------------------------------------
@@ -851,6 +931,8 @@ __global__ __launch_bounds__(BS) void k_pupdate(State* st, V* ring, V* p, long l
   const double a = step ? st->a_new : 0.0;
   const bool ok = !step || (st->pq_new > 0.0 && isfinite(a));
   const double sigma0 = st->sigma0;
+  ShiftRegs q{};
+  if (step) q = load_shift_regs(st);
   const long long gstep = (long long)gridDim.x * BS * UNR;
   long long j0 = (long long)blockIdx.x * BS * UNR + threadIdx.x;
   double rv[UNR], pv[UNR];
@@ -936,9 +1018,10 @@ __global__ __launch_bounds__(BS) void k_pupdate(State* st, V* ring, V* p, long l
         r[j] = (V)lr.r;
         p[j] = (V)(lr.r + b * lr.p);
       }
-      if (step) step_scalars(st, a);
-      __syncthreads();
-      resid_scalars(st, rrn, b, hist);
+      if (step)
+        step_resid_scalars(st, q, i, a, rrn, b, hist);
+      else
+        resid_scalars(st, rrn, b, hist);
     }
   }
 }
