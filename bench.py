@@ -348,7 +348,7 @@ def summarize_rocprof(d: str, kernel_substr: str, calib_mib: int) -> str:
 
 
 TRAFFIC_MATCH = {"k_xt": "k_xt<fsda::EpiXTR<double>", "k_rows_x": "k_rows<fsda::EpiX<double, false>",
-                 "k_fold": "k_fold<32, double>"}
+                 "k_fold": "k_fold_apply<double>"}
 
 
 def traffic_lines(dfetch: str, dwrite: str, calib_mib: int, workload: str) -> str:

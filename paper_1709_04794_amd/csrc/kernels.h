@@ -1046,19 +1046,33 @@ struct FoldCoef {
   int on[MAXS];              // shift active at the first iteration of the chunk
 };
 
-__global__ __launch_bounds__(BS) void k_fold_coef(const State* st, const double* __restrict__ hist, FoldCoef* cf,
-                                                  int nshift) {
+__global__ __launch_bounds__(BS) void k_fold_coef(const State* st, const double* __restrict__ hist,
+                                                  FoldCoef* __restrict__ cf, int nshift) {
   const int k0 = st->fold_start, cnt = st->iter - k0, m = st->chunk;
   const int s = threadIdx.x;
   if (cnt <= 0 || s >= nshift) return;
+  constexpr int KB = 16;  // steps whose coefficients are loaded together
   double gp = 0.0, e = 1.0;
-  for (int k = cnt - 1; k >= 0; k--) {
-    const double* h = hist + ((size_t)((k0 + k) % m) * MAXS + s) * 4;
-    const double a = h[0], z = h[1], b = h[2];
-    cf->h[k][s] = z * gp;
-    cf->g[k][s] = z * e;
-    gp = a + b * gp;
-    e = b * e;
+  for (int kb = cnt - 1; kb >= 0; kb -= KB) {
+    double a[KB], z[KB], b[KB];
+#pragma unroll
+    for (int u = 0; u < KB; u++) {
+      const int k = kb - u;
+      const double* h = hist + ((size_t)((k0 + (k >= 0 ? k : 0)) % m) * MAXS + s) * 4;
+      a[u] = h[0];
+      z[u] = h[1];
+      b[u] = h[2];
+    }
+#pragma unroll
+    for (int u = 0; u < KB; u++) {
+      const int k = kb - u;
+      if (k >= 0) {
+        cf->h[k][s] = z[u] * gp;
+        cf->g[k][s] = z[u] * e;
+        gp = a[u] + b[u] * gp;
+        e = b[u] * e;
+      }
+    }
   }
   cf->a[s] = gp;
   cf->b[s] = e;
@@ -1071,7 +1085,7 @@ __global__ __launch_bounds__(BS) void k_fold_apply(const State* st, const FoldCo
                                                    int nshift) {
   const int k0 = st->fold_start, cnt = st->iter - k0, m = st->chunk;
   if (cnt <= 0) return;
-  constexpr int KU = 4;  // buffered residuals in flight
+  constexpr int KU = 8;  // buffered residuals in flight
   for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
     for (int s0 = 0; s0 < nshift; s0 += FG) {
       double ah[FG], ag[FG];
