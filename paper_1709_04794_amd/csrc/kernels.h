@@ -1085,6 +1085,7 @@ __global__ __launch_bounds__(BS) void k_fold_apply(const State* st, const FoldCo
                                                    int nshift) {
   const int k0 = st->fold_start, cnt = st->iter - k0, m = st->chunk;
   if (cnt <= 0) return;
+  const int first = (k0 + 1) % m;
   constexpr int KU = 8;  // buffered residuals in flight
   for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
     for (int s0 = 0; s0 < nshift; s0 += FG) {
@@ -1094,8 +1095,10 @@ __global__ __launch_bounds__(BS) void k_fold_apply(const State* st, const FoldCo
       for (int k = 0; k < cnt; k += KU) {
         double rv[KU];
 #pragma unroll
-        for (int u = 0; u < KU; u++)
-          rv[u] = k + u < cnt ? (double)ring[(long long)((k0 + k + u + 1) % m) * ldd + j] : 0.0;
+        for (int u = 0; u < KU; u++) {  // slot (k0 + k + u + 1) mod m: the chunk wraps the ring at most once
+          const int sl = first + k + u;
+          rv[u] = k + u < cnt ? (double)ring[(long long)(sl < m ? sl : sl - m) * ldd + j] : 0.0;
+        }
 #pragma unroll
         for (int u = 0; u < KU; u++) {
           if (k + u < cnt) {
