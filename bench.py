@@ -6,7 +6,7 @@ residual 1e-8 with the FP64 true-residual check, and the ratings s = X w of
 every shift.  The operator build (X^T, tiles, labels) happens once before the
 timed region, as does input generation.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload mid] [--chunk 32]
+    python bench.py [--steps K] [--warmup W] [--workload mid] [--chunk 128]
 
 The default run also times, once each and outside the headline, the other
 entry points on the same workload (detail.paths): the mixed-precision solve,

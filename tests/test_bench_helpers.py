@@ -1,0 +1,39 @@
+"""Host-side helpers of bench.py that build index streams and byte models: the
+gather patterns are the products' own index sets, and the byte model adds up.
+CPU only."""
+import numpy as np
+
+import bench
+import synth
+
+
+def test_gather_patterns_are_the_products_index_sets():
+    pb = synth.small_problem(n=120, d=3000, mean_nnz=20, k=3, seed=5)
+    pat = bench.gather_patterns(pb)
+    xt_rows, xt_cols, xt_size = pat["xt"]
+    assert xt_size == pb.n and xt_cols.size == pb.x_col.size
+    # the X^T stream lists, feature by feature (decreasing frequency), the samples of that feature
+    cnt = np.bincount(pb.x_col, minlength=pb.d)
+    assert np.all(np.diff(cnt[np.argsort(-cnt, kind="stable")][xt_rows]) <= 0)
+    xrow = np.repeat(np.arange(pb.n), np.diff(pb.x_rowptr))
+    assert sorted(zip(xt_cols.tolist(), xt_rows.tolist())) == sorted(
+        zip(xrow.tolist(), np.argsort(np.argsort(-cnt, kind="stable"), kind="stable")[pb.x_col].tolist()))
+    # the X stream beyond the features staged in shared memory
+    xr, xc, xsize = pat["x_cold"]
+    assert xsize == pb.d and np.all(xc >= bench.HOT_FEATURES)
+    new = np.argsort(np.argsort(-cnt, kind="stable"), kind="stable")[pb.x_col]
+    assert xc.size == int((new >= bench.HOT_FEATURES).sum())
+    # the graph stream is S itself
+    sr, sc, ssize = pat["s"]
+    assert ssize == pb.n and np.array_equal(sc, pb.s_col)
+    assert np.array_equal(sr, np.repeat(np.arange(pb.n), np.diff(pb.s_rowptr)))
+
+
+def test_operator_apply_bytes_are_the_sum_of_the_products():
+    pb = synth.small_problem(n=200, d=500, mean_nnz=7, k=3, seed=2)
+    import paper_1709_04794_amd as fsda
+    total = sum(bench.algorithmic_bytes(k, pb, 4, 32) for k in (fsda.K_X, fsda.K_S, fsda.K_XT))
+    n, d, z, g = pb.n, pb.d, pb.x_nnz, pb.s_nnz
+    lab = 16 * n if pb.alpha < 1.0 else 0
+    # products as launched (the X^T pass also reads and writes r: 8d + 8d beyond the bare apply)
+    assert total == 8 * z + 4 * g + 40 * n + 36 * d + 12 + lab

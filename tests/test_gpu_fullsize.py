@@ -1,5 +1,5 @@
 """The benchmark workload at full size (mid: 2e5 x 1e6, 1.2e7 nonzeros, 16 shifts), in the
-launch configuration bench.py times (FP64, chunk 32, graph replay).
+launch configuration bench.py times (FP64, fold interval 128, graph replay).
 
 The oracle cannot solve every shift in seconds at this size, so the checks are: the
 operator product against the oracle's (full vector), the two extreme shifts against oracle
@@ -31,8 +31,8 @@ def mid():
 
 @pytest.fixture(scope="module")
 def mid_solved(mid):
-    op = fsda.Operator.from_problem(mid, max_chunk=32)
-    W, iters, relres, st = op.solve(mid.betas, rtol=mid.rtol, chunk=32)
+    op = fsda.Operator.from_problem(mid, max_chunk=128)
+    W, iters, relres, st = op.solve(mid.betas, rtol=mid.rtol, chunk=128)
     return op, W.cpu().numpy(), iters, relres, st
 
 
@@ -65,7 +65,7 @@ def test_fullsize_extreme_shifts_match_oracle_solve(mid, mid_solved, which):
     launch configuration, tighter tolerance)."""
     op = mid_solved[0]
     s = int(np.argmax(mid.betas)) if which == "largest" else int(np.argmin(mid.betas))
-    W, iters, relres, st = op.solve([mid.betas[s]], rtol=1e-11, chunk=32)
+    W, iters, relres, st = op.solve([mid.betas[s]], rtol=1e-11, chunk=128)
     Wr, itr, rr, rc = oracle.solve(mid, betas=[mid.betas[s]], rtol=1e-11, maxit=20000)
     assert relerr(W[0].cpu().numpy(), Wr[0]) < 1e-6, (s, relerr(W[0].cpu().numpy(), Wr[0]))
 
