@@ -282,6 +282,33 @@ def gather_ceiling(args, fsda, torch):
                       "lines": stats, "rates": out}))
 
 
+def batched_targets(args, fsda, torch):
+    """Many targets over one X and S (fsda_multishift_solve_batch): shifted solves per
+    second at rel. residual 1e-8 for batches of 16, 32 and 64 labelings of the
+    workload (labeled fraction lognormal around 0.7 %, positive rate U(0.02, 0.3))."""
+    import synth
+    pb = synth.workload(args.workload, seed=args.seed, cache_dir=args.cache)
+    op = fsda.Operator.from_problem(pb)
+    rows = []
+    for k in (16, 32, 64):
+        labs = synth.target_labels(pb, k, seed=1)
+        op.solve_batch(labs[:4], pb.betas, rtol=pb.rtol)  # warm the kernels
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        W, it, rel, st = op.solve_batch(labs, pb.betas, rtol=pb.rtol)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        solved = int((rel <= TARGET_RELRES).sum())
+        rows.append({"targets": k, "shifts": int(pb.betas.size), "seconds": round(dt, 3),
+                     "shifted_solves_per_s": round(solved / dt, 2), "solved": solved,
+                     "max_iters": int(it.max()), "worst_relres": float(rel.max()), "status": st})
+        log("%d targets x %d shifts: %.3f s, %.1f shifted solves/s, worst relres %.2e"
+            % (k, pb.betas.size, dt, solved / dt, rel.max()))
+        del W
+    op.close()
+    print(json.dumps({"experiment": "batched-targets", "workload": pb.name, "rtol": pb.rtol, "rows": rows}))
+
+
 def shifted_table(args, fsda, torch):
     """CG per shift versus the shared-basis recurrence on (X^T X + beta I) w = X^T z, tolerance 1e-3."""
     import synth
@@ -420,7 +447,7 @@ def main():
                     help="skip timing the bare gathers of the dominant product's index stream")
     ap.add_argument("--experiment", default="",
                     help="'shifted-table': the CG versus shifted CG table instead; 'gather-ceiling': the rate of "
-                         "random gathers the sparse products are bound by")
+                         "random gathers the sparse products are bound by; 'batched-targets': 16, 32 and 64 targets")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -435,6 +462,9 @@ def main():
         return
     if args.experiment == "gather-ceiling":
         gather_ceiling(args, fsda, torch)
+        return
+    if args.experiment == "batched-targets":
+        batched_targets(args, fsda, torch)
         return
     if args.experiment:
         print("unknown experiment %r" % args.experiment, file=sys.stderr)

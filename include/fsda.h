@@ -219,8 +219,9 @@ int fsda_regression_solve(fsda_op *op, const double *z, const double *betas, int
  * and right-hand side b_c = X^T y_c (the canonical one of fsda_rhs for that
  * labeled set), and is solved for every beta of one grid by its own shifted
  * CG (Alg. 3, seeded at min beta), in FP64.  X, S and alpha are the
- * handle's; its own labeled set is not used.  The sparse products of all
- * targets of a call share one pass over the indices.
+ * handle's; its own labeled set is not used.  Targets go in tiles of up to
+ * 16, one tile after the other; the sparse products of the targets of a tile
+ * share one pass over the indices.
  *  ntarget       1..FSDA_MAX_TARGETS.
  *  lab_idx[], lab_y[] (device) the labeled sets of all targets, concatenated;
  *                target c owns entries lab_off[c] .. lab_off[c+1]-1 (same

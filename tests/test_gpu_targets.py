@@ -47,9 +47,10 @@ def test_batch_targets_match_oracle(tiny, alpha):
     assert np.all(iters.max(axis=1) == iters[:, np.argmin(tiny.betas)])
 
 
-@pytest.mark.parametrize("ntarget", [1, 6, 9, 20])
+@pytest.mark.parametrize("ntarget", [1, 6, 9, 20, 37])
 def test_batch_every_tile(tiny, ntarget):
-    """1, 6, 9 and 20 targets run with 4, 8, 16 and 32 columns (padding included)."""
+    """1, 6 and 9 targets run with 4, 8 and 16 columns (padding included); 20 and 37
+    in tiles of 16 (16 + 4; 16 + 16 + 5), one after the other."""
     labs = synth.target_labels(tiny, ntarget, seed=ntarget, frac_median=0.03, frac_hi=0.1)
     betas = np.array([3e-2, 0.4, 7.0])
     op = fsda.Operator.from_problem(tiny, alpha=0.5)
@@ -128,3 +129,14 @@ def test_batch_maxit_and_bad_labels(tiny):
     with pytest.raises(fsda.FsdaError) as e:
         op.solve_batch(bad, tiny.betas, rtol=1e-8)
     assert e.value.code == fsda.E_LABELS
+
+
+def test_batch_error_names_target_in_a_later_tile(tiny):
+    """Targets past the first tile of 16 are named by their index in the call."""
+    labs = synth.target_labels(tiny, 20, seed=13, frac_median=0.03, frac_hi=0.1)
+    idx, y = labs[17]
+    labs[17] = (idx, np.ones_like(y))
+    op = fsda.Operator.from_problem(tiny)
+    with pytest.raises(fsda.FsdaError) as e:
+        op.solve_batch(labs, tiny.betas, rtol=1e-8)
+    assert e.value.code == fsda.E_LABELS and "target 17" in str(e.value)
