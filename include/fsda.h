@@ -62,7 +62,7 @@ extern "C" {
 #define FSDA_MAX_SHIFTS 64
 #define FSDA_MAX_CHUNK 256
 #define FSDA_MAX_TARGETS 64     /* targets of one fsda_multishift_solve_batch call */
-#define FSDA_MAX_BATCH_CHUNK 64 /* fold interval of fsda_multishift_solve_batch */
+#define FSDA_MAX_BATCH_CHUNK 128 /* fold interval of fsda_multishift_solve_batch */
 
 typedef struct fsda_op fsda_op; /* opaque handle, host memory */
 
@@ -230,8 +230,8 @@ int fsda_regression_solve(fsda_op *op, const double *z, const double *betas, int
  *  lab_off[ntarget+1] host offsets, lab_off[0] = 0.
  *  betas, nshift, rtol, maxit, chunk: as in fsda_multishift_solve (1 <= nshift
  *                <= FSDA_MAX_SHIFTS; the handle's max_shifts does not apply;
- *                0 <= chunk <= FSDA_MAX_BATCH_CHUNK, 0 = default 32; here every
- *                chunk gives the same bits).
+ *                0 <= chunk <= FSDA_MAX_BATCH_CHUNK, 0 = default 64; as there,
+ *                chunk changes W only through the order of its rounding).
  *  workspace     device, 256-byte aligned, ws_bytes >= fsda_batch_workspace_size()
  *                for the same ntarget, nshift and chunk; scratch for this call only.
  *  W[ntarget][nshift][d] device FP64 output.

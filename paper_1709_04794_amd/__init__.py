@@ -27,7 +27,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "fsda.h")
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_CSR, E_LABELS, E_RANGE, E_BREAKDOWN, E_WORKSPACE, E_HIP, E_OVERFLOW = -1, -2, -3, -4, -5, -6, -7, -8
 FP64, MIXED = 0, 1
-MAX_SHIFTS, MAX_CHUNK, MAX_TARGETS, MAX_BATCH_CHUNK = 64, 256, 64, 64
+MAX_SHIFTS, MAX_CHUNK, MAX_TARGETS, MAX_BATCH_CHUNK = 64, 256, 64, 128
 # kernel classes for fsda_time_kernel
 K_X, K_S, K_XT, K_RESID, K_PUPD, K_FOLD = 0, 1, 2, 4, 5, 6
 # ... and of the batched FP32 correction solves of the mixed path

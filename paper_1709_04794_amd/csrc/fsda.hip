@@ -1119,7 +1119,7 @@ int refine_any(fsda_op* op, const double* rhs, const double* betas, int nshift, 
 // ---------------------------------------------------------------------------
 
 struct TLayout {
-  size_t st, part, hist, flags, labw, B, P, Q, t, u, ring, Ps, lpart, crow, cbeg, rc0, total;
+  size_t st, part, hist, coef, flags, labw, B, P, Q, t, u, ring, Ps, lpart, crow, cbeg, rc0, total;
   long long ld;
 };
 
@@ -1136,6 +1136,7 @@ void tlayout(const fsda_op* op, int T, int nshift, int chunk, TLayout* L) {
   L->st = take(sizeof(TState));
   L->part = take(sizeof(double) * BP_N * GRID_B * BT_MAX);
   L->hist = take(sizeof(double) * 4 * (size_t)chunk * T * nshift);
+  L->coef = take(sizeof(double) * ts_coef_stride(chunk, nshift) * T);
   L->flags = take(sizeof(int) * 4 * BT_MAX);
   L->labw = take(8 * (size_t)n * T);
   L->t = take(8 * (size_t)n * T);
@@ -1154,7 +1155,7 @@ void tlayout(const fsda_op* op, int T, int nshift, int chunk, TLayout* L) {
 
 struct TPtr {
   TState* st;
-  double *part, *hist, *labw, *B, *P, *Q, *t, *u, *ring, *Ps, *lpart, *W;
+  double *part, *hist, *coef, *labw, *B, *P, *Q, *t, *u, *ring, *Ps, *lpart, *W;
   int* flags;
   BXtArgs xa;
   long long ld;
@@ -1237,15 +1238,9 @@ template <int T>
 void t_fold(fsda_op* op, const TPtr& p, hipStream_t s) {
   const long long d = op->pb.d;
   const dim3 g(t_colgrid(d), p.ncol);
+  hipLaunchKernelGGL(ts_fold_coef, dim3(1, p.ncol), dim3(BS), 0, s, p.st, p.hist, T, p.coef, p.nshift);
   launch(op, KC_TFOLD, s, [&] {
-    if (p.chunk <= 8)
-      hipLaunchKernelGGL(ts_fold<8>, g, dim3(BS), 0, s, p.st, p.hist, T, p.ring, p.ld, p.W, p.Ps, d, p.nshift);
-    else if (p.chunk <= 16)
-      hipLaunchKernelGGL(ts_fold<16>, g, dim3(BS), 0, s, p.st, p.hist, T, p.ring, p.ld, p.W, p.Ps, d, p.nshift);
-    else if (p.chunk <= 32)
-      hipLaunchKernelGGL(ts_fold<32>, g, dim3(BS), 0, s, p.st, p.hist, T, p.ring, p.ld, p.W, p.Ps, d, p.nshift);
-    else
-      hipLaunchKernelGGL(ts_fold<64>, g, dim3(BS), 0, s, p.st, p.hist, T, p.ring, p.ld, p.W, p.Ps, d, p.nshift);
+    hipLaunchKernelGGL(ts_fold_apply, g, dim3(BS), 0, s, p.st, p.coef, T, p.ring, p.ld, p.W, p.Ps, d, p.nshift);
   });
   hipLaunchKernelGGL(ts_fold_done, dim3(1), dim3(1), 0, s, p.st);
 }
@@ -1259,6 +1254,7 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
   p.st = reinterpret_cast<TState*>(ws + L.st);
   p.part = reinterpret_cast<double*>(ws + L.part);
   p.hist = reinterpret_cast<double*>(ws + L.hist);
+  p.coef = reinterpret_cast<double*>(ws + L.coef);
   p.flags = reinterpret_cast<int*>(ws + L.flags);
   p.labw = reinterpret_cast<double*>(ws + L.labw);
   p.t = reinterpret_cast<double*>(ws + L.t);
@@ -1998,7 +1994,7 @@ int fsda_batch_workspace_size(const fsda_op* op, int ntarget, int nshift, int ch
   if (ntarget < 1 || ntarget > FSDA_MAX_TARGETS) return fail(FSDA_E_ARG, "ntarget outside 1..FSDA_MAX_TARGETS");
   if (nshift < 1 || nshift > FSDA_MAX_SHIFTS) return fail(FSDA_E_ARG, "nshift outside 1..FSDA_MAX_SHIFTS");
   if (chunk < 0 || chunk > FSDA_MAX_BATCH_CHUNK) return fail(FSDA_E_RANGE, "chunk outside 0..FSDA_MAX_BATCH_CHUNK");
-  if (chunk == 0) chunk = 32;
+  if (chunk == 0) chunk = 64;
   TLayout L;
   tlayout(op, batch_tile(std::min(ntarget, TARGET_TILE)), nshift, chunk, &L);
   *bytes = L.total;
@@ -2014,7 +2010,7 @@ int fsda_multishift_solve_batch(fsda_op* op, int ntarget, const int32_t* lab_idx
   size_t need = 0;
   int rc = fsda_batch_workspace_size(op, ntarget, nshift, chunk, &need);
   if (rc) return rc;
-  if (chunk == 0) chunk = 32;
+  if (chunk == 0) chunk = 64;
   if (!(rtol > 0.0)) return fail(FSDA_E_RANGE, "rtol must be > 0");
   if (maxit < 1) return fail(FSDA_E_RANGE, "maxit must be >= 1");
   for (int k = 0; k < nshift; k++)

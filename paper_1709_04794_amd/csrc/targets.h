@@ -18,7 +18,6 @@
 namespace fsda {
 
 constexpr int TS_MAX = 64;  // shifts per target
-constexpr int TSG = 4;      // shifts per group in ts_fold (their W and P loads in flight together)
 
 struct TState {
   int iter, stop, status, maxit;
@@ -310,54 +309,101 @@ __global__ __launch_bounds__(BS) void ts_pupdate(const TState* st, const double*
   write_partials_cols<T>(part, acc);
 }
 
-// Fold of iterations [fold_start, iter) of target c = blockIdx.y: per row, the
-// buffered residuals in registers, then shift by shift
-//   W_s += a_s P_s ;  P_s = zeta_{k+1,s} r_{k+1} + b_s P_s
-// in iteration order, with wave-uniform coefficients.  Shifts frozen before
-// the chunk are skipped.  Grid (gx, ncol).
-template <int M>
-__global__ __launch_bounds__(BS) void ts_fold(const TState* st, const double* __restrict__ hist, int T,
-                                              const double* ring, long long ld, double* W, double* Ps, long long d,
-                                              int nshift) {
-  const int k0 = st->fold_start, k1 = st->iter, m = st->chunk;
-  const int cnt = k1 - k0;
+// Fold of iterations [fold_start, iter) into the state of every (target,
+// shift), as in the single-target solve: the chunk's steps
+//   W_s += a_k P_s ;  P_s = zeta_k r_k + b_k P_s
+// unrolled into W_s <- W_s + A_s P_s + sum_k H_k,s r_k, P_s <- B_s P_s + sum_k G_k,s r_k.
+// ts_fold_coef: one block per target (blockIdx.y), one thread per shift, the
+// coefficients backwards over the chunk into coef[c] = {H [cnt][S], G [cnt][S],
+// A [S], B [S], on [S]}; ts_fold_apply: grid (gx, ncol), the target's buffered
+// residuals streamed once per group of TFG shifts.
+constexpr int TFG = 16;  // shifts per pass over a target's buffered residuals
+__host__ __device__ inline size_t ts_coef_stride(int chunk, int nshift) {
+  return (size_t)(2 * chunk + 3) * nshift;  // doubles per target
+}
+
+__global__ __launch_bounds__(BS) void ts_fold_coef(const TState* st, const double* __restrict__ hist, int T,
+                                                   double* __restrict__ coef, int nshift) {
+  const int k0 = st->fold_start, cnt = st->iter - k0, m = st->chunk;
+  const int c = blockIdx.y, s = threadIdx.x;
+  if (cnt <= 0 || s >= nshift) return;
+  double* H = coef + (size_t)c * ts_coef_stride(m, nshift);
+  double* G = H + (size_t)m * nshift;
+  double* AB = G + (size_t)m * nshift;  // A [S], B [S], on [S]
+  constexpr int KB = 16;
+  double gp = 0.0, e = 1.0;
+  for (int kb = cnt - 1; kb >= 0; kb -= KB) {
+    double a[KB], z[KB], b[KB];
+#pragma unroll
+    for (int u = 0; u < KB; u++) {
+      const int k = kb - u >= 0 ? kb - u : 0;
+      const double* h = hist + ((((size_t)((k0 + k) % m)) * T + c) * nshift + s) * 4;
+      a[u] = h[0];
+      z[u] = h[1];
+      b[u] = h[2];
+    }
+#pragma unroll
+    for (int u = 0; u < KB; u++) {
+      const int k = kb - u;
+      if (k >= 0) {
+        H[(size_t)k * nshift + s] = z[u] * gp;
+        G[(size_t)k * nshift + s] = z[u] * e;
+        gp = a[u] + b[u] * gp;
+        e = b[u] * e;
+      }
+    }
+  }
+  AB[s] = gp;
+  AB[nshift + s] = e;
+  AB[2 * nshift + s] = hist[((((size_t)(k0 % m)) * T + c) * nshift + s) * 4 + 3] != 0.0 ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(BS) void ts_fold_apply(const TState* st, const double* __restrict__ coef, int T,
+                                                    const double* ring, long long ld, double* W, double* Ps,
+                                                    long long d, int nshift) {
+  const int k0 = st->fold_start, cnt = st->iter - k0, m = st->chunk;
   if (cnt <= 0) return;
   const int c = blockIdx.y;
+  const double* H = coef + (size_t)c * ts_coef_stride(m, nshift);
+  const double* G = H + (size_t)m * nshift;
+  const double* AB = G + (size_t)m * nshift;
+  const int first = (k0 + 1) % m;
+  constexpr int KU = 8;  // buffered residuals in flight
   for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
-    double rv[M];
+    for (int s0 = 0; s0 < nshift; s0 += TFG) {
+      double ah[TFG], ag[TFG];
 #pragma unroll
-    for (int k = 0; k < M; k++)
-      if (k < cnt) rv[k] = ring[((size_t)((k0 + k + 1) % m) * T + c) * ld + j];
-    for (int s0 = 0; s0 < nshift; s0 += TSG) {
-      double w[TSG], pp[TSG];
-      bool on[TSG];
+      for (int g = 0; g < TFG; g++) ah[g] = ag[g] = 0.0;
+      for (int k = 0; k < cnt; k += KU) {
+        double rv[KU];
 #pragma unroll
-      for (int g = 0; g < TSG; g++) {
-        const int s = s0 + g;
-        on[g] = s < nshift && hist[((((size_t)(k0 % m)) * T + c) * nshift + s) * 4 + 3] != 0.0;
-        w[g] = on[g] ? W[((size_t)c * nshift + s) * d + j] : 0.0;
-        pp[g] = on[g] ? Ps[((size_t)c * nshift + s) * ld + j] : 0.0;
-      }
+        for (int u = 0; u < KU; u++) {  // slot (k0 + k + u + 1) mod m: the chunk wraps the ring at most once
+          const int sl = first + k + u;
+          rv[u] = k + u < cnt ? ring[((size_t)(sl < m ? sl : sl - m) * T + c) * ld + j] : 0.0;
+        }
 #pragma unroll
-      for (int k = 0; k < M; k++) {
-        if (k < cnt) {
-          const double* h = hist + (((size_t)((k0 + k) % m) * T + c) * nshift) * 4;
+        for (int u = 0; u < KU; u++) {
+          if (k + u < cnt) {
+            const double* hk = H + (size_t)(k + u) * nshift + s0;
+            const double* gk = G + (size_t)(k + u) * nshift + s0;
 #pragma unroll
-          for (int g = 0; g < TSG; g++) {
-            if (s0 + g < nshift) {
-              const double* cs = h + (s0 + g) * 4;
-              w[g] += cs[0] * pp[g];
-              pp[g] = cs[1] * rv[k] + cs[2] * pp[g];
+            for (int g = 0; g < TFG; g++) {
+              if (s0 + g < nshift) {
+                ah[g] += hk[g] * rv[u];
+                ag[g] += gk[g] * rv[u];
+              }
             }
           }
         }
       }
 #pragma unroll
-      for (int g = 0; g < TSG; g++) {
+      for (int g = 0; g < TFG; g++) {
         const int s = s0 + g;
-        if (on[g]) {
-          W[((size_t)c * nshift + s) * d + j] = w[g];
-          Ps[((size_t)c * nshift + s) * ld + j] = pp[g];
+        if (s < nshift && AB[2 * nshift + s] != 0.0) {
+          const size_t e = (size_t)c * nshift + s;
+          const double pv = Ps[e * ld + j];
+          W[e * d + j] += AB[s] * pv + ah[g];
+          Ps[e * ld + j] = AB[nshift + s] * pv + ag[g];
         }
       }
     }
