@@ -177,22 +177,45 @@ __device__ __forceinline__ V group_gather(const int* __restrict__ col, int beg, 
   return v;
 }
 
+// The X product over T columns reads its most frequent features, the mask
+// features [0, nmask) (one 64-bit mask per row; the CSR then holds only the
+// others), from a per-block shared copy of their T columns.
+struct BMask {
+  const unsigned long long* mask;
+  int nmask;
+};
+
 // Rows of one CSR over T columns; `stop` (the solver's stop flag) ends the
-// launch at once when set, cm holds the per-column labeled means.
-template <int T, class Epi>
+// launch at once when set, cm holds the per-column labeled means.  With MASK,
+// bm gives the masks and the launch has nmask * T values of V of dynamic
+// shared memory.
+template <int T, class Epi, bool MASK = false>
 __global__ __launch_bounds__(BS) void bk_rows(const int* __restrict__ rowptr, const int* __restrict__ col, int nrows,
                                               const typename Epi::VT* __restrict__ src, Epi epi, const int* stop,
-                                              const double* cm, double* part) {
+                                              const double* cm, double* part, BMask bm) {
   using V = typename Epi::VT;
   if (*stop) return;
   constexpr int G = BS / T;
   const int c = threadIdx.x % T, g = threadIdx.x / T;
+  extern __shared__ double bk_smem[];
+  V* hot = reinterpret_cast<V*>(bk_smem);
+  if (MASK) {
+    for (int e = threadIdx.x; e < bm.nmask * T; e += BS) hot[e] = src[e];
+    __syncthreads();
+  }
   epi.prepare(cm, c);
   double acc = 0.0;
   for (int r0 = blockIdx.x * G; r0 < nrows; r0 += gridDim.x * G) {
     const int r = r0 + g;
     if (r >= nrows) continue;
-    const V v = group_gather<T, V>(col, rowptr[r], rowptr[r + 1], src, c);
+    V v = group_gather<T, V>(col, rowptr[r], rowptr[r + 1], src, c);
+    if (MASK) {
+      unsigned long long mb = bm.mask[r];
+      while (mb) {
+        v += hot[(__ffsll((long long)mb) - 1) * T + c];
+        mb &= mb - 1;
+      }
+    }
     acc += epi.row(r, c, v);
   }
   if (Epi::kReduce) write_partials_cols<T>(part, acc);

@@ -802,6 +802,15 @@ struct BBuf {
 
 // t = X src, u = M' t (with the labeled-mean and <t, u> partials), and
 // Q = X^T u + sigma_c P (P NULL: Q = X^T u), all over T columns.
+// The batched X product reads the mask features from a shared copy per block
+// (64 x T values; a copy of more features, up to 32 KiB, lowered the resident
+// waves and made the product slower).
+template <int T, typename V>
+BMask b_mask(const fsda_op* op, size_t* smem) {
+  *smem = sizeof(V) * (size_t)op->mtop * T;
+  return BMask{op->px.rows.mask, op->mtop};
+}
+
 template <int T, typename V>
 void b_products(fsda_op* op, const BBuf<V>& b, const V* src, const V* P, const int* stop, hipStream_t s, bool timed) {
   constexpr int G = BS / T;
@@ -809,25 +818,29 @@ void b_products(fsda_op* op, const BBuf<V>& b, const V* src, const V* P, const i
   BState* st = b.st;
   const int gx = grid_b(ceil_div(n, G));
   const bool lab = has_lab_term(op);
+  size_t sm = 0;
+  const BMask bm = b_mask<T, V>(op, &sm);
+  const int* xrp = op->px.rows.rowptr;
+  const int* xrc = op->px.rows.col;
   launch(op, timed ? KC_BX : KC_OTHER, s, [&] {
     if (lab)
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, V, true>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol, (int)n,
-                         src, BEpiX<T, V, true>{b.t, op->labw, 1, 0}, stop, st->cm, b.site(BP_X));
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, V, true>, true>), dim3(gx), dim3(BS), sm, s, xrp, xrc, (int)n, src,
+                         BEpiX<T, V, true>{b.t, op->labw, 1, 0}, stop, st->cm, b.site(BP_X), bm);
     else
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, V, false>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol,
-                         (int)n, src, BEpiX<T, V, false>{b.t, nullptr, 1, 0}, stop, st->cm, b.site(BP_X));
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, V, false>, true>), dim3(gx), dim3(BS), sm, s, xrp, xrc, (int)n, src,
+                         BEpiX<T, V, false>{b.t, nullptr, 1, 0}, stop, st->cm, b.site(BP_X), bm);
   });
   if (lab) hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, stop, b.site(BP_X), gx, st->cm);
   launch(op, timed ? KC_BS : KC_OTHER, s, [&] {
     if (lab)
       hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, V, true>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr, op->pb.s_col,
                          (int)n, b.t, BEpiLap<T, V, true>{b.t, op->labw, 1, 0, op->pb.s_rowptr, b.u, op->pb.alpha, (V)0},
-                         stop, st->cm, b.site(BP_TU));
+                         stop, st->cm, b.site(BP_TU), BMask{nullptr, 0});
     else
       hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, V, false>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr,
                          op->pb.s_col, (int)n, b.t,
                          BEpiLap<T, V, false>{b.t, nullptr, 1, 0, op->pb.s_rowptr, b.u, op->pb.alpha, (V)0}, stop,
-                         st->cm, b.site(BP_TU));
+                         st->cm, b.site(BP_TU), BMask{nullptr, 0});
   });
   const int gxt = grid_b(b.xa.nchunk + ceil_div(d - b.xa.nmed, G));
   launch(op, timed ? KC_BXT : KC_OTHER, s, [&] {
@@ -1173,13 +1186,17 @@ void t_products(fsda_op* op, const TPtr& p, const double* src, const int* stop, 
   const int gx = grid_b(ceil_div(n, G));
   const bool lab = has_lab_term(op);
   TState* st = p.st;
+  size_t sm = 0;
+  const BMask bm = b_mask<T, double>(op, &sm);
+  const int* xrp = op->px.rows.rowptr;
+  const int* xrc = op->px.rows.col;
   launch(op, timed ? KC_BX : KC_OTHER, s, [&] {
     if (lab)
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, true>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol,
-                         (int)n, src, BEpiX<T, double, true>{p.t, p.labw, T, 1}, stop, st->cm, tpart(p, BP_X));
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, true>, true>), dim3(gx), dim3(BS), sm, s, xrp, xrc, (int)n, src,
+                         BEpiX<T, double, true>{p.t, p.labw, T, 1}, stop, st->cm, tpart(p, BP_X), bm);
     else
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, false>>), dim3(gx), dim3(BS), 0, s, op->pb.x_rowptr, op->xcol,
-                         (int)n, src, BEpiX<T, double, false>{p.t, nullptr, T, 1}, stop, st->cm, tpart(p, BP_X));
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, false>, true>), dim3(gx), dim3(BS), sm, s, xrp, xrc, (int)n, src,
+                         BEpiX<T, double, false>{p.t, nullptr, T, 1}, stop, st->cm, tpart(p, BP_X), bm);
   });
   if (lab) hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, stop, tpart(p, BP_X), gx, st->cm);
   launch(op, timed ? KC_BS : KC_OTHER, s, [&] {
@@ -1187,12 +1204,12 @@ void t_products(fsda_op* op, const TPtr& p, const double* src, const int* stop, 
       hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, double, true>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr,
                          op->pb.s_col, (int)n, p.t,
                          BEpiLap<T, double, true>{p.t, p.labw, T, 1, op->pb.s_rowptr, p.u, op->pb.alpha, 0.0}, stop,
-                         st->cm, tpart(p, BP_TU));
+                         st->cm, tpart(p, BP_TU), BMask{nullptr, 0});
     else
       hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, double, false>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr,
                          op->pb.s_col, (int)n, p.t,
                          BEpiLap<T, double, false>{p.t, nullptr, T, 1, op->pb.s_rowptr, p.u, op->pb.alpha, 0.0},
-                         stop, st->cm, tpart(p, BP_TU));
+                         stop, st->cm, tpart(p, BP_TU), BMask{nullptr, 0});
   });
 }
 
