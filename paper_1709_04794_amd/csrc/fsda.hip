@@ -590,6 +590,11 @@ int make_xt(fsda_op* op, hipStream_t s) {
     if ((long long)crow.size() > op->L.nchunk_max || nlong > op->L.nlong_max)
       return fail(FSDA_E_WORKSPACE, "long-row chunk table larger than reserved");
     w.nchunk = (int)crow.size();
+    // rows of more than one chunk: a prefix (lengths decrease), their chunks first
+    int nmulti = 0;
+    while (nmulti < nlong && rp[nmulti + 1] - rp[nmulti] > CH) nmulti++;
+    w.nchunk_multi = c0[nmulti];
+    pl.nlong = nmulti;
     HIP_TRY(hipMemcpyAsync(const_cast<int*>(w.chunk_row), crow.data(), sizeof(int) * crow.size(),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(const_cast<int*>(w.chunk_beg), cbeg.data(), sizeof(int) * cbeg.size(),

@@ -656,10 +656,11 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __re
 // ---------------------------------------------------------------------------
 //
 // With features relabeled by decreasing frequency, the rows of X^T are sorted
-// by length.  Each long row (the prefix [0, nlong)) is cut into chunks of CH
-// nonzeros; a block sums one chunk (coalesced index loads, independent
-// gathers, block reduction) into lpart[chunk], and the consumer adds up a
-// row's chunk sums in order (k_pupdate or k_resid, or k_assemble).  The remaining
+// by length.  Each long row is cut into chunks of CH nonzeros; a block sums
+// one chunk (coalesced index loads, independent gathers, block reduction).  A
+// row of one chunk is finished there; the rows of several chunks (the prefix
+// [0, nlong)) leave their chunk sums in lpart[chunk], and the consumer adds up
+// a row's chunk sums in order (k_pupdate, or k_assemble).  The remaining
 // rows go through the same lanes-per-row bins as k_rows, in the same launch.
 
 constexpr int CH = 4096;        // nonzeros of a long-row chunk (16 per thread)
@@ -668,6 +669,8 @@ struct XtWork {
   const int* rowptr;
   const int* col;
   int nchunk;              // chunks of the long rows, all processed before the bins
+  int nchunk_multi;        // the first ones, of the rows of more than one chunk; a row of one
+                           // chunk is finished where it is summed
   const int* chunk_row;    // [nchunk] row of each chunk
   const int* chunk_beg;    // [nchunk] first nonzero of each chunk
   double* lpart;           // [nchunk] chunk sums
@@ -703,7 +706,12 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __re
 #pragma unroll
       for (int u = 0; u < U; u++) v += g[u];
       const double t = block_sum_all((double)v);
-      if (tid == 0) X.lpart[it] = t;
+      if (tid == 0) {
+        if (it < X.nchunk_multi)
+          X.lpart[it] = t;
+        else
+          acc += epi.row(r, (V)t);  // the whole row
+      }
       continue;
     }
     const Rows& R = X.rows;
