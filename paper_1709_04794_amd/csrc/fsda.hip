@@ -581,7 +581,7 @@ int make_xt(fsda_op* op, hipStream_t s) {
     std::vector<int> crow, cbeg, c0(nlong + 1);
     for (int j = 0; j < nlong; j++) {
       c0[j] = (int)crow.size();
-      for (int k = rp[j]; k < rp[j + 1]; k += CH) {
+      for (int k = rp[j]; k < rp[j + 1]; k += CHUNK) {
         crow.push_back(j);
         cbeg.push_back(k);
       }
@@ -592,7 +592,7 @@ int make_xt(fsda_op* op, hipStream_t s) {
     w.nchunk = (int)crow.size();
     // rows of more than one chunk: a prefix (lengths decrease), their chunks first
     int nmulti = 0;
-    while (nmulti < nlong && rp[nmulti + 1] - rp[nmulti] > CH) nmulti++;
+    while (nmulti < nlong && rp[nmulti + 1] - rp[nmulti] > CHUNK) nmulti++;
     w.nchunk_multi = c0[nmulti];
     pl.nlong = nmulti;
     HIP_TRY(hipMemcpyAsync(const_cast<int*>(w.chunk_row), crow.data(), sizeof(int) * crow.size(),

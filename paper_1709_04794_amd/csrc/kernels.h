@@ -656,14 +656,16 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __re
 // ---------------------------------------------------------------------------
 //
 // With features relabeled by decreasing frequency, the rows of X^T are sorted
-// by length.  Each long row is cut into chunks of CH nonzeros; a block sums
+// by length.  Each long row is cut into chunks of CHUNK nonzeros; a block sums
 // one chunk (coalesced index loads, independent gathers, block reduction).  A
 // row of one chunk is finished there; the rows of several chunks (the prefix
 // [0, nlong)) leave their chunk sums in lpart[chunk], and the consumer adds up
 // a row's chunk sums in order (k_pupdate, or k_assemble).  The remaining
 // rows go through the same lanes-per-row bins as k_rows, in the same launch.
 
-constexpr int CH = 4096;        // nonzeros of a long-row chunk (16 per thread)
+constexpr int CH = 4096;        // nonzeros per pass over a long-row chunk (16 per thread)
+constexpr int NCP = 2;          // passes per chunk
+constexpr int CHUNK = NCP * CH; // nonzeros of a long-row chunk
 
 struct XtWork {
   const int* rowptr;
@@ -690,21 +692,23 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __re
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     if (it < X.nchunk) {
       const int r = X.chunk_row[it];
-      const int beg = X.chunk_beg[it];
-      const int end = min(beg + CH, X.rowptr[r + 1]);
+      const int beg0 = X.chunk_beg[it];
+      const int end = min(beg0 + CHUNK, X.rowptr[r + 1]);
       constexpr int U = CH / BS;
-      int idx[U];
-      V g[U];
-#pragma unroll
-      for (int u = 0; u < U; u++) {
-        const int k = beg + u * BS + tid;
-        idx[u] = k < end ? X.col[k] : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < U; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : (V)0;
       V v = (V)0;
+      for (int beg = beg0; beg < end; beg += CH) {
+        int idx[U];
+        V g[U];
 #pragma unroll
-      for (int u = 0; u < U; u++) v += g[u];
+        for (int u = 0; u < U; u++) {
+          const int k = beg + u * BS + tid;
+          idx[u] = k < end ? X.col[k] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : (V)0;
+#pragma unroll
+        for (int u = 0; u < U; u++) v += g[u];
+      }
       const double t = block_sum_all((double)v);
       if (tid == 0) {
         if (it < X.nchunk_multi)
