@@ -25,6 +25,7 @@ import ctypes
 import dataclasses
 import os
 import subprocess
+import time
 from typing import Optional
 
 import numpy as np
@@ -281,18 +282,29 @@ RECIPES = {
 }
 
 
-def make_problem(recipe: Recipe, seed: int = 0, name: str = "custom", **override) -> Problem:
+def make_problem(recipe: Recipe, seed: int = 0, name: str = "custom", log=None, **override) -> Problem:
+    """Generate a problem from a recipe; ``log`` (a callable taking one string), when given,
+    is told when each of the three generation steps has finished."""
     r = dataclasses.replace(recipe, **override) if override else recipe
+    t0 = time.perf_counter()
+
+    def step(what):
+        if log is not None:
+            log("%s: %s done after %.1f s" % (name, what, time.perf_counter() - t0))
+
     xr, xc = fingerprints(r.n, r.d, r.mean_nnz, r.zipf_s, seed)
+    step("fingerprints")
     sr, sc = knn_graph(r.n, xr, xc, r.k, ties=r.ties, method=r.knn, seed=seed)
+    step("kNN graph")
     n_lab = max(2, int(round(r.lab_frac * r.n)))
     li, ly = labels(r.n, xr, xc, r.d, n_lab, r.pos_frac, seed)
+    step("labels")
     return Problem(name=name, n=r.n, d=r.d, x_rowptr=xr, x_col=xc, s_rowptr=sr, s_col=sc, lab_idx=li,
                    lab_y=ly, alpha=float(r.alpha), betas=np.asarray(r.betas, dtype=np.float64), rtol=r.rtol,
                    seed=seed)
 
 
-def workload(name: str, seed: int = 0, cache_dir: Optional[str] = None, **override) -> Problem:
+def workload(name: str, seed: int = 0, cache_dir: Optional[str] = None, log=None, **override) -> Problem:
     """Named workload; cached as .npz under ``cache_dir`` when given."""
     recipe = RECIPES[name]
     path = None
@@ -304,7 +316,7 @@ def workload(name: str, seed: int = 0, cache_dir: Optional[str] = None, **overri
             return Problem(name=name, n=int(z["n"]), d=int(z["d"]), x_rowptr=z["x_rowptr"], x_col=z["x_col"],
                            s_rowptr=z["s_rowptr"], s_col=z["s_col"], lab_idx=z["lab_idx"], lab_y=z["lab_y"],
                            alpha=float(z["alpha"]), betas=z["betas"], rtol=float(z["rtol"]), seed=seed)
-    pb = make_problem(recipe, seed=seed, name=name, **override)
+    pb = make_problem(recipe, seed=seed, name=name, log=log, **override)
     if path is not None:
         np.savez(path, n=pb.n, d=pb.d, x_rowptr=pb.x_rowptr, x_col=pb.x_col, s_rowptr=pb.s_rowptr,
                  s_col=pb.s_col, lab_idx=pb.lab_idx, lab_y=pb.lab_y, alpha=pb.alpha, betas=pb.betas,
