@@ -208,6 +208,26 @@ def gather_patterns(pb):
             "s": (np.repeat(np.arange(n), np.diff(pb.s_rowptr)), pb.s_col, n)}
 
 
+def xcd_sliced_stream(idx, n, aligned=True, piece=256, nslice=8):
+    """The X^T index stream (sample indices < n) reordered for fsda_gather_sum's
+    grid-stride loop, where entry k is handled by block (k // piece) % grid and
+    blocks go to the XCDs round robin: piece p holds only indices of sample slice
+    p % nslice ([x n / nslice, (x+1) n / nslice)), so each XCD gathers from one
+    slice.  aligned=False rotates the slice of each round of nslice pieces, so that
+    every slice is spread over all XCDs (same pieces, same order within a slice).
+    The leftover of the unequal slices follows at the end, unsliced."""
+    idx = np.asarray(idx)
+    sl = (idx.astype(np.int64) * nslice) // n
+    o = np.argsort(sl, kind="stable")
+    parts = np.split(idx[o], np.searchsorted(sl[o], np.arange(1, nslice)))
+    m = min(len(q) for q in parts) // piece * piece
+    A = np.stack([q[:m].reshape(-1, piece) for q in parts], axis=1)  # [round, slice, piece]
+    if not aligned:
+        R = A.shape[0]
+        A = A[np.arange(R)[:, None], (np.arange(nslice)[None, :] + np.arange(R)[:, None]) % nslice]
+    return np.concatenate([A.reshape(-1)] + [q[m:] for q in parts])
+
+
 def time_gathers(fsda, torch, size, idx, reps=10, pair_us=0.0):
     """Best time (us) of the bare gather kernel over idx into a vector of `size`."""
     src = torch.rand(size, dtype=torch.float64, device="cuda")
@@ -245,7 +265,8 @@ def gather_ceiling(args, fsda, torch):
     workload's sizes: uniform indices, and the index patterns of the products
     themselves (X^T: the samples of every feature row; X: the features of every
     sample beyond the ones staged in shared memory; S: the neighbours of every
-    sample).  Also counts the distinct 128-byte lines each row of a product
+    sample), and the X^T pattern cut into XCD slices (xcd_sliced_stream) with and
+    without the alignment of slices to XCDs.  Also counts the distinct 128-byte lines each row of a product
     touches (16 FP64 values per line), the number of cache-line lookups a
     product cannot avoid.  Features are ordered by decreasing frequency, as the
     operator orders them internally.
@@ -271,6 +292,8 @@ def gather_ceiling(args, fsda, torch):
         "X cold pattern over d (p)": (d, pat["x_cold"][1]),
         "S pattern over n (t)": (n, pat["s"][1]),
         "uniform over 4096 (L1-resident)": (4096, rng.integers(0, 4096, z)),
+        "X^T pattern, XCD slices": (n, xcd_sliced_stream(pat["xt"][1], n)),
+        "X^T pattern, slices not XCD-aligned": (n, xcd_sliced_stream(pat["xt"][1], n, aligned=False)),
     }
     pair_us = event_pair_us(torch, 50)
     out = {}
@@ -513,6 +536,7 @@ def main():
             ms, nl = op.kernel_time()
             per_class[k] = (ms, nl)
             op.time_kernel(k, False)
+            log("class %s timed: %.3f ms per step" % (KNAMES[k], ms))
         dom = max(per_class, key=lambda k: per_class[k][0])
         log("per-kernel ms per step: %s" % {KNAMES[k]: round(v[0], 3) for k, v in per_class.items()})
     else:

@@ -113,6 +113,14 @@ int fsda_workspace_size(const fsda_problem *pb, int max_shifts, int max_chunk, s
  * products, the labeled weights and the canonical right-hand side.  *out
  * (host) receives the handle.  Blocks until done.  The workspace belongs to the
  * handle until it is destroyed.
+ * XCD slices: when the FP64 sample-space vector is larger than 2 MiB
+ * (n > 262,144), the X^T product is planned so that each of the eight XCDs
+ * gathers from one eighth of the sample range (its rows of >= 64 nonzeros are
+ * cut at the sample boundaries x n / 8 and their parts added in a fixed order).
+ * Results differ from the unsliced plan only in the summation order of those
+ * rows.  The environment variable FSDA_XT_SLICES set to 1 (never) or 8
+ * (always) overrides the choice; it is read by fsda_workspace_size and by this
+ * call, which must see the same value (else FSDA_E_WORKSPACE may result).
  * Errors: FSDA_E_ARG, FSDA_E_RANGE (alpha), FSDA_E_OVERFLOW, FSDA_E_WORKSPACE,
  * FSDA_E_CSR, FSDA_E_LABELS, FSDA_E_HIP.
  */

@@ -88,7 +88,7 @@ constexpr int TARGET_TILE = 16;
 struct Layout {
   size_t st, part, hist, fcoef, labw, ycen, zw, t, u, b, p, q, bu, new2old, old2new, xcol, xt_rowptr, xt_col;
   size_t xmask, xrrowptr, xrcol;  // X split into mask features and the rest
-  size_t chunk_row, chunk_beg, lpart, row_chunk0;
+  size_t chunk_row, chunk_beg, chunk_end, lpart, row_chunk0, segp;
   size_t uni;
   size_t ring, P;                                                         // union: solve
   size_t bst, bpart, b64, bR, bP, bQ, bX, bT, bU, blpart, bcrow, bcbeg, brc0;  // union: refinement (mixed)
@@ -98,8 +98,21 @@ struct Layout {
   size_t total;
   long long ldd;  // d padded: stride of the feature-space vectors of the refinement
   long long ldv;  // max(d, n) padded: stride of the ring and per-shift directions
-  long long nchunk_max, nlong_max;
+  long long nchunk_max, nlong_max, npart_max, nsplit_max;
+  int nslice;  // X^T slices: 1, or NSLICE (one per XCD)
 };
+
+// X^T is split into XCD slices when the FP64 sample-space vector it gathers from
+// is larger than this (an XCD's L2 is 4 MiB; at 1.6 MB the gathers already run
+// at the rate of L2-resident data).  The environment variable FSDA_XT_SLICES set
+// to 1 or 8 overrides the choice.
+constexpr long long SLICE_BYTES = 2LL << 20;
+int xt_slices(const fsda_problem* pb) {
+  const char* e = std::getenv("FSDA_XT_SLICES");
+  if (e && std::strcmp(e, "1") == 0) return 1;
+  if (e && std::strcmp(e, "8") == 0) return NSLICE;
+  return 8 * pb->n > SLICE_BYTES ? NSLICE : 1;
+}
 
 void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   const long long n = pb->n, d = pb->d, z = std::max<long long>(pb->x_nnz, 1);
@@ -112,8 +125,20 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->ldd = (d + 63) / 64 * 64;
   L->ldv = (std::max(d, n) + 63) / 64 * 64;
   const long long m = std::max(d, n);  // vectors serve both feature-space and sample-space solves
+  L->nslice = xt_slices(pb);
   L->nlong_max = z / LONG_ROW + 1;
   L->nchunk_max = z / CH + L->nlong_max + 1;
+  L->npart_max = L->nchunk_max;
+  L->nsplit_max = 0;
+  if (L->nslice > 1) {
+    // split rows (>= SPLIT_ROW nonzeros); chunk items of the rows of >= SLICE_LONG:
+    // per row NSLICE x ceil(longest slice / CHUNK) <= NSLICE (len / CHUNK + 1);
+    // parts: those chunks plus NSLICE per binned split row
+    L->nsplit_max = z / SPLIT_ROW + 1;
+    L->nchunk_max = (long long)NSLICE * (z / CHUNK + z / SLICE_LONG + 1);
+    L->npart_max = L->nchunk_max + (long long)NSLICE * L->nsplit_max;
+    L->nlong_max = L->nsplit_max;
+  }
   L->st = take(sizeof(State));
   L->part = take(sizeof(double) * NSITE * NPART);
   L->hist = take(sizeof(double) * MAXCHUNK * MAXS * 4);
@@ -137,8 +162,10 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->xrcol = take(4 * z);
   L->chunk_row = take(4 * (size_t)L->nchunk_max);
   L->chunk_beg = take(4 * (size_t)L->nchunk_max);
-  L->lpart = take(8 * (size_t)L->nchunk_max);
+  L->chunk_end = take(4 * (size_t)L->nchunk_max);
+  L->lpart = take(8 * (size_t)L->npart_max);
   L->row_chunk0 = take(4 * ((size_t)L->nlong_max + 1));
+  L->segp = take(4 * (size_t)(NSLICE + 1) * (size_t)L->nsplit_max);
   L->bnchunk_max = z / 256 + z / BMED + 2;  // chunks of >= 256 nonzeros, plus one per row
   L->bcrow = L->bcbeg = L->brc0 = 0;
   if (pb->precision == FSDA_MIXED) {  // chunk tables of the batched X^T product (kept across solves)
@@ -375,7 +402,7 @@ void run_xt(fsda_op* op, const typename Epi::V* src, Epi epi, int solve, bool as
   });
   if (assemble && pl.nlong > 0)
     hipLaunchKernelGGL(k_assemble<Epi>, dim3(pl.gridL), dim3(BS), 0, s, pl.nlong, pl.row_chunk0, pl.w.lpart, epi,
-                       op->st, part, pl.grid);
+                       op->st, part, pl.grid, solve);
 }
 
 int xt_npart(const fsda_op* op) { return op->pxt.grid + (op->pxt.nlong > 0 ? op->pxt.gridL : 0); }
@@ -461,13 +488,17 @@ void iteration(fsda_op* op, int mode, hipStream_t s, int tag) {
       product_x<V>(op, p, 1, s);
       product_lap<V>(op, 1, s);
     }
+    // with XCD slices the split rows (tens of thousands) are finished by
+    // k_assemble after the X^T pass (not part of the timed X^T class); otherwise
+    // the few multi-chunk rows are finished by the direction update
+    const bool sliced = op->L.nslice > 1;
     run_xt(op, u,
            EpiXTR<V>{p, ring, op->L.ldv, op->part + SITE_TU * NPART, ntu, op->part + SITE_PP * NPART, gs, 0.0, 0.0, 0.0,
                      nullptr, nullptr},
-           1, false, s, KC_XT, op->part + SITE_R * NPART);
-    nrr = op->pxt.grid;
+           1, sliced, s, KC_XT, op->part + SITE_R * NPART);
+    nrr = sliced ? xt_npart(op) : op->pxt.grid;
   }
-  const int nlong = sa ? 0 : op->pxt.nlong;
+  const int nlong = sa || op->L.nslice > 1 ? 0 : op->pxt.nlong;
   launch(op, KC_PUPD, s, [&] {
     hipLaunchKernelGGL(k_pupdate<V>, dim3(gs), dim3(BS), 0, s, op->st, ring, p, op->L.ldv, m,
                        op->part + SITE_R * NPART, nrr, op->hist, op->part + SITE_PP * NPART,
@@ -554,6 +585,85 @@ RowPlan one_bin(const int* rowptr, const int* col, long long nrows, long long nn
   return pl;
 }
 
+// XCD-sliced work of the X^T product (see XtSlices): the rows of >= SPLIT_ROW
+// nonzeros [0, nsplit) are cut at the slice boundaries (found on the device, read
+// back once).  Rows of >= SLICE_LONG: per row ncut = ceil(longest slice / CHUNK)
+// rounds of NSLICE chunk items, item (round c, slice x) taking nonzeros
+// [c CHUNK, (c+1) CHUNK) of slice x (possibly empty), so that a row's parts are
+// contiguous and item k runs slice k % 8.  The other split rows go to bins of
+// NSLICE items each, by length: [1024, 8192) 64 lanes, [512, 1024) 16,
+// [256, 512) 8, [64, 256) 4 (about XUNR nonzeros of a slice per lane).
+int make_xt_slices(fsda_op* op, hipStream_t s) {
+  XtPlan& pl = op->pxt;
+  XtWork& w = pl.w;
+  XtSlices& S = w.sl;
+  const int nsplit = op->xt_bins[3];
+  const std::vector<int>& rp = op->xt_rp_med;
+  if (nsplit > op->L.nsplit_max) return fail(FSDA_E_WORKSPACE, "split-row table larger than reserved");
+  S.nsplit = nsplit;
+  S.segp = at<int>(op, op->L.segp);
+  pl.nlong = nsplit;
+  if (nsplit == 0) return FSDA_OK;
+  const long long nseg = (long long)(NSLICE + 1) * nsplit;
+  hipLaunchKernelGGL(k_slice_bounds, dim3((unsigned)ceil_div(nseg, BS)), dim3(BS), 0, s, op->xt_rowptr, op->xt_col,
+                     nsplit, (long long)op->pb.n, const_cast<int*>(S.segp));
+  HIP_TRY(hipGetLastError());
+  std::vector<int> sp(nseg);
+  HIP_TRY(hipMemcpyAsync(sp.data(), S.segp, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  auto len = [&](int j) { return rp[j + 1] - rp[j]; };
+  int nlc = 0;
+  while (nlc < nsplit && len(nlc) >= SLICE_LONG) nlc++;
+  std::vector<int> crow, cbeg, cend, c0(nsplit + 1);
+  for (int j = 0; j < nlc; j++) {
+    int longest = 0;
+    for (int x = 0; x < NSLICE; x++) longest = std::max(longest, sp[(x + 1) * nsplit + j] - sp[x * nsplit + j]);
+    const int ncut = std::max(1, (int)ceil_div(longest, CHUNK));
+    c0[j] = (int)crow.size();
+    for (int c = 0; c < ncut; c++)
+      for (int x = 0; x < NSLICE; x++) {
+        const int s0 = sp[x * nsplit + j], s1 = sp[(x + 1) * nsplit + j];
+        crow.push_back(j);
+        cbeg.push_back((int)std::min<long long>(s0 + (long long)c * CHUNK, s1));
+        cend.push_back((int)std::min<long long>(s0 + (long long)(c + 1) * CHUNK, s1));
+      }
+  }
+  const int nchunk = (int)crow.size();
+  for (int j = nlc; j <= nsplit; j++) c0[j] = nchunk + NSLICE * (j - nlc);
+  if ((long long)nchunk > op->L.nchunk_max || (long long)c0[nsplit] > op->L.npart_max)
+    return fail(FSDA_E_WORKSPACE, "sliced chunk table larger than reserved");
+  w.nchunk = nchunk;
+  w.nchunk_multi = nchunk;  // every chunk is a part of a split row
+  S.nlc = nlc;
+  S.part0 = nchunk;
+  // bins of the split rows [nlc, nsplit); lengths decrease with the row index
+  const int lo[4] = {1024, 512, 256, SPLIT_ROW};
+  const int lprs[4] = {64, 16, 8, 4};
+  int nb = 0, item = 0, j = nlc;
+  for (int k = 0; k < 4; k++) {
+    const int r0 = j;
+    while (j < nsplit && len(j) >= lo[k]) j++;
+    if (j == r0) continue;
+    S.row0[nb] = r0;
+    S.row0[nb + 1] = j;
+    S.lpr[nb] = lprs[k];
+    S.item0[nb] = item;
+    item += (int)ceil_div(j - r0, BS / lprs[k]);
+    S.item0[nb + 1] = item;
+    nb++;
+  }
+  if (j != nsplit) return fail(FSDA_E_CSR, "X^T rows not ordered by length");
+  S.nb = nb;
+  if (nchunk > 0) {
+    HIP_TRY(hipMemcpyAsync(const_cast<int*>(w.chunk_row), crow.data(), sizeof(int) * nchunk, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(const_cast<int*>(w.chunk_beg), cbeg.data(), sizeof(int) * nchunk, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(const_cast<int*>(w.chunk_end), cend.data(), sizeof(int) * nchunk, hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(hipMemcpyAsync(const_cast<int*>(pl.row_chunk0), c0.data(), sizeof(int) * c0.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return FSDA_OK;
+}
+
 // Work of the X^T product: chunks of the long rows [0, nlong) (from their row
 // pointers, read back to the host once at build time), then length bins of the
 // other rows (lengths decreasing in the internal order).
@@ -565,6 +675,7 @@ int make_xt(fsda_op* op, hipStream_t s) {
   w.col = op->xt_col;
   w.chunk_row = at<int>(op, op->L.chunk_row);
   w.chunk_beg = at<int>(op, op->L.chunk_beg);
+  w.chunk_end = at<int>(op, op->L.chunk_end);
   w.lpart = at<double>(op, op->L.lpart);
   const int nlong = op->xt_bins[0];
   pl.nlong = nlong;
@@ -576,14 +687,19 @@ int make_xt(fsda_op* op, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(op->xt_rp_med.data(), op->xt_rowptr, sizeof(int) * (ncopy + 1), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
-  if (nlong > 0) {
+  const bool sliced = op->L.nslice > 1;
+  if (sliced) {
+    const int rc = make_xt_slices(op, s);
+    if (rc) return rc;
+  } else if (nlong > 0) {
     const std::vector<int>& rp = op->xt_rp_med;
-    std::vector<int> crow, cbeg, c0(nlong + 1);
+    std::vector<int> crow, cbeg, cend, c0(nlong + 1);
     for (int j = 0; j < nlong; j++) {
       c0[j] = (int)crow.size();
       for (int k = rp[j]; k < rp[j + 1]; k += CHUNK) {
         crow.push_back(j);
         cbeg.push_back(k);
+        cend.push_back(std::min(k + CHUNK, rp[j + 1]));
       }
     }
     c0[nlong] = (int)crow.size();
@@ -599,6 +715,8 @@ int make_xt(fsda_op* op, hipStream_t s) {
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(const_cast<int*>(w.chunk_beg), cbeg.data(), sizeof(int) * cbeg.size(),
                            hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(const_cast<int*>(w.chunk_end), cend.data(), sizeof(int) * cend.size(),
+                           hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(const_cast<int*>(pl.row_chunk0), c0.data(), sizeof(int) * c0.size(),
                            hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -609,9 +727,10 @@ int make_xt(fsda_op* op, hipStream_t s) {
   // xt_bins: counts of rows with length >= 1024, 512, 256, 64, 16, 4, 1; then d.
   // lanes per row so that one pass of XUNR nonzeros per lane covers the bin
   // (two passes for [512, 1024))
+  // (with XCD slices the rows of >= 64 nonzeros are the split rows, done above)
   const int lprs[7] = {64, 64, 32, 8, 2, 1, 0};
   int nb = 0, item = 0;
-  for (int k = 0; k < 7; k++) {
+  for (int k = sliced ? 3 : 0; k < 7; k++) {
     const int r0 = op->xt_bins[k], r1 = op->xt_bins[k + 1];
     if (r1 <= r0) continue;
     R.row0[nb] = r0;
@@ -629,8 +748,8 @@ int make_xt(fsda_op* op, hipStream_t s) {
     R.lpr[0] = 0;
     R.item0[0] = R.item0[1] = 0;
   }
-  pl.grid = std::max(1, std::min(w.nchunk + R.item0[R.nb], GRID_ROWS));
-  pl.gridL = grid_for(std::max(nlong, 1), 64);
+  pl.grid = std::max(1, std::min(w.nchunk + NSLICE * w.sl.item0[w.sl.nb] + R.item0[R.nb], GRID_ROWS));
+  pl.gridL = sliced ? grid_for(std::max(pl.nlong, 1), 256) : grid_for(std::max(nlong, 1), 64);
   return FSDA_OK;
 }
 

@@ -662,22 +662,68 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __re
 // [0, nlong)) leave their chunk sums in lpart[chunk], and the consumer adds up
 // a row's chunk sums in order (k_pupdate, or k_assemble).  The remaining
 // rows go through the same lanes-per-row bins as k_rows, in the same launch.
+// With XCD slices (below) the long rows are cut at sample boundaries too.
 
 constexpr int CH = 4096;        // nonzeros per pass over a long-row chunk (16 per thread)
 constexpr int NCP = 8;          // passes per chunk (2: 65.0, 4: 65.6, 8: 65.7 solves/s at mid)
 constexpr int CHUNK = NCP * CH; // nonzeros of a long-row chunk
 
+// XCD slices.  Work-groups are dispatched to the eight XCDs round robin, so with a
+// grid that is a multiple of eight (or one item per block) item `it` runs on XCD
+// it % 8.  When the sample-space vector is larger than an XCD's L2, the rows of at
+// least SPLIT_ROW nonzeros are cut at the sample boundaries x n / 8 and segment x of
+// every such row is given to items with it % 8 == x: each XCD then gathers from one
+// eighth of the vector, which stays in its L2.  A split row's sum is the ordered sum
+// of its parts (k_assemble).
+constexpr int NSLICE = 8;        // XCDs of the chip
+constexpr int SPLIT_ROW = 64;    // rows at least this long are split into slices
+constexpr int SLICE_LONG = 8192; // split rows at least this long are summed in block chunks
+
+struct XtSlices {
+  int nb;                   // bins of split rows processed lanes-per-row (0: no such bins)
+  int row0[MAXBIN + 1];
+  int lpr[MAXBIN];
+  int item0[MAXBIN + 1];    // items of one slice before bin b (each item runs for all slices)
+  int nsplit;               // split rows [0, nsplit)
+  int nlc;                  // [0, nlc) are summed in the chunk items, [nlc, nsplit) in the bins
+  const int* segp;          // [(NSLICE + 1) * nsplit]: slice x of row j is [segp[x*nsplit+j], segp[(x+1)*nsplit+j])
+  int part0;                // lpart index of part 0 of row nlc; row j >= nlc has parts part0 + NSLICE (j - nlc) + x
+};
+
 struct XtWork {
   const int* rowptr;
   const int* col;
   int nchunk;              // chunks of the long rows, all processed before the bins
-  int nchunk_multi;        // the first ones, of the rows of more than one chunk; a row of one
+  int nchunk_multi;        // the first ones, of the rows of more than one part; a row of one
                            // chunk is finished where it is summed
   const int* chunk_row;    // [nchunk] row of each chunk
   const int* chunk_beg;    // [nchunk] first nonzero of each chunk
-  double* lpart;           // [nchunk] chunk sums
+  const int* chunk_end;    // [nchunk] one past its last nonzero
+  double* lpart;           // [parts] chunk and slice sums
+  XtSlices sl;             // bins of the split rows (sliced mode)
   Rows rows;               // bins of the other rows
 };
+
+// Sum of src over the nonzeros [beg, end) of a row shared by lpr lanes (this lane's share).
+template <typename V>
+__device__ __forceinline__ V lane_row_sum(const int* __restrict__ col, const V* __restrict__ src, int beg, int end,
+                                          int lane, int lpr) {
+  V v = (V)0;
+  for (int k0 = beg + lane; k0 < end; k0 += lpr * XUNR) {
+    int idx[XUNR];
+    V g[XUNR];
+#pragma unroll
+    for (int u = 0; u < XUNR; u++) {
+      const int k = k0 + u * lpr;
+      idx[u] = k < end ? col[k] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < XUNR; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : (V)0;
+#pragma unroll
+    for (int u = 0; u < XUNR; u++) v += g[u];
+  }
+  return v;
+}
 
 template <class Epi>
 __global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __restrict__ src, Epi epi, State* st,
@@ -688,12 +734,12 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __re
   if (Epi::kPublish && blockIdx.x == 0 && threadIdx.x == 0) epi.publish(st);
   const int tid = threadIdx.x;
   double acc = 0.0;
-  const int nitems = X.nchunk + X.rows.item0[X.rows.nb];
+  const int nitems = X.nchunk + NSLICE * X.sl.item0[X.sl.nb] + X.rows.item0[X.rows.nb];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     if (it < X.nchunk) {
       const int r = X.chunk_row[it];
       const int beg0 = X.chunk_beg[it];
-      const int end = min(beg0 + CHUNK, X.rowptr[r + 1]);
+      const int end = X.chunk_end[it];
       constexpr int U = CH / BS;
       V v = (V)0;
       for (int beg = beg0; beg < end; beg += CH) {
@@ -718,8 +764,24 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __re
       }
       continue;
     }
+    int ir = it - X.nchunk;
+    const XtSlices& S = X.sl;
+    if (ir < NSLICE * S.item0[S.nb]) {  // a bin item of the split rows, for slice x = it % 8
+      const int k = ir / NSLICE, x = ir % NSLICE;
+      int b = 0;
+      while (k >= S.item0[b + 1]) b++;
+      const int lpr = S.lpr[b];
+      const int j = S.row0[b] + (k - S.item0[b]) * (BS / lpr) + tid / lpr;
+      const int lane = tid & (lpr - 1);
+      const bool live = j < S.row0[b + 1];
+      V v = (V)0;
+      if (live) v = lane_row_sum<V>(X.col, src, S.segp[x * S.nsplit + j], S.segp[(x + 1) * S.nsplit + j], lane, lpr);
+      for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (live && lane == 0) X.lpart[S.part0 + NSLICE * (j - S.nlc) + x] = (double)v;
+      continue;
+    }
+    ir -= NSLICE * S.item0[S.nb];
     const Rows& R = X.rows;
-    const int ir = it - X.nchunk;
     int b = 0;
     while (ir >= R.item0[b + 1]) b++;
     const int lpr = R.lpr[b];
@@ -732,33 +794,41 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __re
     const int lane = tid & (lpr - 1);
     const bool live = r < R.row0[b + 1];
     V v = (V)0;
-    if (live) {
-      const int beg = R.rowptr[r], end = R.rowptr[r + 1];
-      for (int k0 = beg + lane; k0 < end; k0 += lpr * XUNR) {
-        int idx[XUNR];
-        V g[XUNR];
-#pragma unroll
-        for (int u = 0; u < XUNR; u++) {
-          const int k = k0 + u * lpr;
-          idx[u] = k < end ? R.col[k] : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < XUNR; u++) g[u] = idx[u] >= 0 ? src[idx[u]] : (V)0;
-#pragma unroll
-        for (int u = 0; u < XUNR; u++) v += g[u];
-      }
-    }
+    if (live) v = lane_row_sum<V>(R.col, src, R.rowptr[r], R.rowptr[r + 1], lane, lpr);
     for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if (live && lane == 0) acc += epi.row(r, v);
   }
   if (Epi::kReduce) write_partial(part, blockIdx.x, acc);
 }
 
-// Long rows [0, nlong) of an X^T product: row j is the ordered sum of its chunk
-// sums lpart[row_chunk0[j] .. row_chunk0[j+1]).  Partial in slot `slot`.
+// Slice boundaries of the split rows of X^T: segp[x * nsplit + j] is the first
+// nonzero k of row j with col[k] >= x n / NSLICE (the row's end if none), for
+// x = 0..NSLICE.  Sample indices increase along a row of X^T.
+__global__ __launch_bounds__(BS) void k_slice_bounds(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                     int nsplit, long long n, int* segp) {
+  const long long t = (long long)blockIdx.x * BS + threadIdx.x;
+  if (t >= (long long)(NSLICE + 1) * nsplit) return;
+  const int x = (int)(t / nsplit), j = (int)(t % nsplit);
+  const int key = (int)((long long)x * n / NSLICE);
+  int lo = rowptr[j], hi = rowptr[j + 1];
+  while (lo < hi) {
+    const int mid = lo + (hi - lo) / 2;
+    if (col[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  segp[t] = lo;
+}
+
+// Multi-part rows [0, nlong) of an X^T product (the rows of several chunks, or
+// with XCD slices every split row): row j is the ordered sum of its parts
+// lpart[row_chunk0[j] .. row_chunk0[j+1]).  Partial in slot `slot`.  In a solve
+// (solve != 0) nothing runs once every shift has stopped.
 template <class Epi>
 __global__ __launch_bounds__(BS) void k_assemble(int nlong, const int* row_chunk0, const double* lpart, Epi epi,
-                                                 State* st, double* part, int slot) {
+                                                 State* st, double* part, int slot, int solve) {
+  if (solve && st->stop) return;
   epi.prepare(st);
   double acc = 0.0;
   for (int j = blockIdx.x * BS + threadIdx.x; j < nlong; j += gridDim.x * BS) {

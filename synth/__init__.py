@@ -324,6 +324,42 @@ def workload(name: str, seed: int = 0, cache_dir: Optional[str] = None, log=None
     return pb
 
 
+def planted_problem(n: int, counts, n_lab: int, pos_frac: float = 0.3, alpha: float = 0.5,
+                    betas=(0.1, 1.0, 10.0), seed: int = 0, rtol: float = 1e-10) -> Problem:
+    """X with planted feature counts: feature f occurs in counts[f] distinct samples drawn
+    uniformly (counts[f] == n makes a dense column), so the rows of X^T have exactly these
+    lengths.  The graph is the path i -- i+1 (symmetric, degrees 1 and 2).  n_lab labeled
+    samples drawn uniformly, round(pos_frac n_lab) of them positive (at least one of each)."""
+    rng = np.random.default_rng(seed)
+    rs, cs = [], []
+    for f, c in enumerate(counts):
+        if c > 0:
+            rs.append(np.arange(n) if c >= n else rng.choice(n, size=int(c), replace=False))
+            cs.append(np.full(min(int(c), n), f))
+    r = np.concatenate(rs) if rs else np.zeros(0, np.int64)
+    c = np.concatenate(cs) if cs else np.zeros(0, np.int64)
+    o = np.lexsort((c, r))
+    x_rowptr = np.zeros(n + 1, np.int32)
+    np.cumsum(np.bincount(r, minlength=n), out=x_rowptr[1:])
+    x_col = c[o].astype(np.int32)
+    left = np.arange(1, n)  # sample i > 0 links to i - 1, sample i < n - 1 to i + 1
+    deg = np.full(n, 2, np.int64)
+    deg[0] = deg[-1] = 1
+    s_rowptr = np.zeros(n + 1, np.int32)
+    np.cumsum(deg, out=s_rowptr[1:])
+    s_col = np.empty(int(deg.sum()), np.int32)
+    s_col[s_rowptr[left]] = left - 1
+    right = np.arange(0, n - 1)
+    s_col[s_rowptr[right + 1] - 1] = right + 1
+    lab_idx = np.sort(rng.choice(n, size=n_lab, replace=False)).astype(np.int32)
+    npos = min(max(1, int(round(pos_frac * n_lab))), n_lab - 1)
+    lab_y = -np.ones(n_lab, np.int8)
+    lab_y[rng.choice(n_lab, size=npos, replace=False)] = 1
+    return Problem(name="planted", n=n, d=len(counts), x_rowptr=x_rowptr, x_col=x_col, s_rowptr=s_rowptr,
+                   s_col=s_col, lab_idx=lab_idx, lab_y=lab_y, alpha=float(alpha),
+                   betas=np.asarray(betas, dtype=np.float64), rtol=rtol, seed=seed)
+
+
 def small_problem(n: int, d: int, mean_nnz: float = 6, k: int = 3, n_lab: Optional[int] = None,
                   pos_frac: float = 0.3, alpha: float = 0.5, betas=(1e-2, 1e-1, 1.0, 10.0), seed: int = 0,
                   zipf_s: float = 1.1, ties: bool = True, rtol: float = 1e-12) -> Problem:

@@ -37,3 +37,24 @@ def test_operator_apply_bytes_are_the_sum_of_the_products():
     lab = 16 * n if pb.alpha < 1.0 else 0
     # products as launched (the X^T pass also reads and writes r: 8d + 8d beyond the bare apply)
     assert total == 8 * z + 4 * g + 40 * n + 36 * d + 12 + lab
+
+
+def test_xcd_sliced_stream_is_a_slice_aligned_permutation():
+    """Same indices; piece p (256 entries, block p % grid, XCD p % 8) holds only slice
+    p % 8; the non-aligned control spreads every slice over all eight positions."""
+    pb = synth.workload("tiny")
+    idx = bench.gather_patterns(pb)["xt"][1]
+    n = pb.n
+    for aligned in (True, False):
+        s = bench.xcd_sliced_stream(idx, n, aligned=aligned)
+        assert np.array_equal(np.sort(s), np.sort(idx))
+        m = min(np.bincount((idx.astype(np.int64) * 8) // n, minlength=8)) // 256 * 256
+        pieces = s[: 8 * m].reshape(-1, 256)
+        sl = (pieces.astype(np.int64) * 8) // n
+        assert (sl == sl[:, :1]).all()  # one slice per piece
+        p = np.arange(len(pieces))
+        if aligned:
+            assert (sl[:, 0] == p % 8).all()
+        else:
+            assert (sl[:, 0] == (p % 8 + p // 8) % 8).all()
+            assert len(np.unique(sl[p % 8 == 0, 0])) == min(8, len(pieces[p % 8 == 0]))

@@ -1,0 +1,160 @@
+"""The X^T product in XCD slices vs the CPU oracle and vs the unsliced plan.
+
+The sliced plan is chosen automatically when the FP64 sample-space vector exceeds 2 MiB
+(n > 262,144); FSDA_XT_SLICES=8 forces it and FSDA_XT_SLICES=1 turns it off, which is how
+these tests run both plans on the same inputs.  Split rows are summed in a different order
+than in the unsliced plan, so the two agree to rounding (1e-13 relative on products) but
+are not bit-identical; the oracle bars are those of the unsliced parity tests.
+
+The planted problem (300,000 samples, 24 features with fixed row lengths of X^T) covers
+every part of the sliced plan: a dense feature whose slices are longer than one chunk (two
+rounds of chunk items, the second ones short), the other chunk-summed rows (>= 8192
+nonzeros), each bin of split rows ([1024, 8192), [512, 1024), [256, 512), [64, 256)), and
+the short and empty rows that stay unsplit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+fsda = pytest.importorskip("paper_1709_04794_amd")
+
+pytestmark = pytest.mark.gpu
+
+PLANTED_COUNTS = [300000, 120000, 20000, 9000, 5000, 3000, 1500, 800, 600, 400, 300, 200, 100, 80, 64,
+                  63, 40, 20, 10, 5, 2, 1, 0, 0]
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def maxrel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def rhs_term_scale(pb, r):
+    """Per feature, the sum of the magnitudes of the terms of the Alg. 7 right-hand side
+    (X - 1 mu_l^T)^T v with v = [W 0; 0 0] X r (on a labeled sample, the mean of X r over
+    its class; 0 elsewhere): entries whose terms cancel (a feature present in every
+    sample has a zero centred column) are exact only to rounding of this size."""
+    t = np.zeros(pb.n)
+    rows = np.repeat(np.arange(pb.n), np.diff(pb.x_rowptr))
+    np.add.at(t, rows, r[pb.x_col])
+    v = np.zeros(pb.n)
+    for c in (1, -1):
+        m = pb.lab_y == c
+        v[pb.lab_idx[m]] = t[pb.lab_idx[m]].mean()
+    xtv = np.zeros(pb.d)
+    np.add.at(xtv, pb.x_col, np.abs(v)[rows])
+    lab = np.zeros(pb.n, bool)
+    lab[pb.lab_idx] = True
+    mu = np.bincount(pb.x_col[lab[rows]], minlength=pb.d) / pb.lab_idx.size
+    return xtv + mu * np.abs(v).sum()
+
+
+def build(pb, monkeypatch, slices, **kw):
+    monkeypatch.setenv("FSDA_XT_SLICES", str(slices))
+    return fsda.Operator.from_problem(pb, **kw)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return synth.workload("tiny")
+
+
+@pytest.fixture(scope="module")
+def planted():
+    return synth.planted_problem(300000, PLANTED_COUNTS, n_lab=3000, pos_frac=0.3, alpha=0.5,
+                                 betas=(0.05, 0.5, 5.0, 50.0), seed=4, rtol=1e-11)
+
+
+@pytest.mark.parametrize("which", ["tiny", "planted"])
+def test_sliced_products_match_oracle_and_unsliced(tiny, planted, monkeypatch, which):
+    pb = tiny if which == "tiny" else planted
+    op8 = build(pb, monkeypatch, 8)
+    op1 = build(pb, monkeypatch, 1)
+    p = synth.normal(pb.d, seed=2, stream=3)
+    for sigma in (0.0, 1e-2):
+        q8 = op8.apply(sigma, torch.from_numpy(p).cuda())
+        q1 = op1.apply(sigma, torch.from_numpy(p).cuda())
+        ref = oracle.apply(pb, sigma, p)
+        assert maxrel(q8.cpu().numpy(), ref) < 1e-12, sigma
+        assert maxrel(q8.cpu().numpy(), q1.cpu().numpy()) < 1e-13, sigma
+        if which == "planted":  # the two plans really differ (summation order of the split rows)
+            assert not torch.equal(q8, q1)
+    b8 = op8.rhs().cpu().numpy()
+    assert maxrel(b8, oracle.rhs(pb)) < 1e-13
+    r = synth.normal(pb.d, seed=3, stream=1)
+    br = op8.rhs(torch.from_numpy(r).cuda()).cpu().numpy()
+    ref = oracle.rhs(pb, r)
+    tol = 1e-11 * np.abs(ref).max() + 1e-13 * rhs_term_scale(pb, r)
+    assert (np.abs(br - ref) <= tol).all(), np.abs(br - ref) / tol
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.5, 0.0])
+def test_sliced_solve_matches_oracle_tiny(tiny, monkeypatch, alpha):
+    op = build(tiny, monkeypatch, 8, alpha=alpha)
+    W, iters, relres, st = op.solve(tiny.betas, rtol=tiny.rtol)
+    assert st == fsda.OK
+    Wr, *_ = oracle.solve(tiny, rtol=1e-13, maxit=20000, alpha=alpha)
+    W = W.cpu().numpy()
+    b = oracle.rhs(tiny)
+    for s, beta in enumerate(tiny.betas):
+        assert relerr(W[s], Wr[s]) < 1e-6, (s, relerr(W[s], Wr[s]))
+        assert relres[s] < 20 * tiny.rtol
+        ref = np.linalg.norm(b - oracle.apply(tiny, beta, W[s], alpha=alpha)) / np.linalg.norm(b)
+        assert abs(relres[s] - ref) <= 1e-3 * ref + 1e-15
+
+
+@pytest.mark.parametrize("chunk", [1, 3, 128])
+def test_sliced_solve_planted_matches_oracle(planted, monkeypatch, chunk):
+    """Fold interval 1 puts r_i and r_{i+1} in one ring slot (the split rows are read and
+    written by k_assemble); 3 and 128 end the solve inside a fold interval, after which no
+    kernel of the remaining iterations may write the ring."""
+    op = build(planted, monkeypatch, 8, max_chunk=128)
+    W, iters, relres, st = op.solve(planted.betas, rtol=planted.rtol, chunk=chunk)
+    assert st == fsda.OK
+    Wr, itr, *_ = oracle.solve(planted, rtol=1e-13, maxit=20000)
+    W = W.cpu().numpy()
+    for s in range(planted.betas.size):
+        assert relerr(W[s], Wr[s]) < 1e-6, (s, relerr(W[s], Wr[s]))
+        assert relres[s] < 20 * planted.rtol
+    W1, it1, *_ = build(planted, monkeypatch, 8, max_chunk=128).solve(planted.betas, rtol=planted.rtol, chunk=1)
+    assert np.array_equal(iters, it1)
+    assert maxrel(W, W1.cpu().numpy()) < 1e-12
+
+
+def test_sliced_solve_is_deterministic_and_graph_equals_direct(planted, monkeypatch):
+    """Replays of the captured fold interval give the same bits as direct launches."""
+    op_g = build(planted, monkeypatch, 8)
+    monkeypatch.setenv("FSDA_NO_GRAPH", "1")
+    op_d = build(planted, monkeypatch, 8)
+    monkeypatch.delenv("FSDA_NO_GRAPH")
+    for _ in range(3):  # replays with eager work in between
+        Wg, itg, rg, _ = op_g.solve(planted.betas, rtol=planted.rtol, chunk=16)
+        Wd, itd, rd, _ = op_d.solve(planted.betas, rtol=planted.rtol, chunk=16)
+        torch.cuda.synchronize()
+        assert torch.equal(Wg, Wd)
+        assert np.array_equal(itg, itd)
+        assert np.array_equal(rg, rd)
+
+
+def test_sliced_regression_and_mixed_tiny(tiny, monkeypatch):
+    z = synth.normal(tiny.n, seed=3, stream=8)
+    betas = np.logspace(-2, 2, 6)
+    op = build(tiny, monkeypatch, 8)
+    W, iters, relres, st = op.regression_solve(torch.from_numpy(z).cuda(), betas, rtol=1e-10)
+    assert st == fsda.OK
+    Wr, *_ = oracle.reg_solve(tiny, z, betas, rtol=1e-13, maxit=50000)
+    for s in range(betas.size):
+        assert relerr(W[s].cpu().numpy(), Wr[s]) < 1e-6, s
+    opm = build(tiny, monkeypatch, 8, precision=fsda.MIXED)
+    Wm, itm, rm, stm = opm.solve(tiny.betas, rtol=1e-8)
+    assert stm == fsda.OK
+    Wo, *_ = oracle.solve(tiny, rtol=1e-13, maxit=20000)
+    for s in range(tiny.betas.size):
+        assert relerr(Wm[s].cpu().numpy(), Wo[s]) < 1e-4, s
+        assert rm[s] <= 1e-8
