@@ -305,13 +305,25 @@ def gather_ceiling(args, fsda, torch):
                       "lines": stats, "rates": out}))
 
 
+# kernel classes of fsda_multishift_solve_batch (fsda_time_kernel)
+BATCH_KNAMES = {7: "bX", 8: "bLap", 9: "bXT", 10: "bresid", 11: "bpupdate", 12: "tfold"}
+
+
 def batched_targets(args, fsda, torch):
     """Many targets over one X and S (fsda_multishift_solve_batch): shifted solves per
     second at rel. residual 1e-8 for batches of 16, 32 and 64 labelings of the
-    workload (labeled fraction lognormal around 0.7 %, positive rate U(0.02, 0.3))."""
+    workload (labeled fraction lognormal around 0.7 %, positive rate U(0.02, 0.3)),
+    with the tile chosen by fsda_batch_autotune."""
     import synth
     pb = synth.workload(args.workload, seed=args.seed, cache_dir=args.cache)
     op = fsda.Operator.from_problem(pb)
+    # the tile (targets per pass over the indices) picked by the autotuner on the
+    # first 16 labelings, then used for every batch below
+    t0 = time.perf_counter()
+    tile, rates = op.autotune_batch(synth.target_labels(pb, 16, seed=1), pb.betas, trial_iters=32)
+    tune = {"tile": tile, "seconds": round(time.perf_counter() - t0, 2),
+            "shifted_target_iterations_per_s": {str(t): round(r, 1) for t, r in rates.items()}}
+    log("autotuned tile %d in %.1f s: %s" % (tile, tune["seconds"], tune["shifted_target_iterations_per_s"]))
     rows = []
     for k in (16, 32, 64):
         labs = synth.target_labels(pb, k, seed=1)
@@ -328,8 +340,25 @@ def batched_targets(args, fsda, torch):
         log("%d targets x %d shifts: %.3f s, %.1f shifted solves/s, worst relres %.2e"
             % (k, pb.betas.size, dt, solved / dt, rel.max()))
         del W
+    # per-kernel time of one 16-target solve: one solve per class, that class's
+    # launches bracketed by HIP events (direct launches while timing)
+    labs = synth.target_labels(pb, 16, seed=1)
+    per_class = {}
+    for k, name in BATCH_KNAMES.items():
+        op.time_kernel(k, True)
+        t0 = time.perf_counter()
+        op.solve_batch(labs, pb.betas, rtol=pb.rtol)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms, nl = op.kernel_time()
+        op.time_kernel(k, False)
+        per_class[name] = {"ms": round(ms, 1), "launches": nl, "us_per_launch": round(1e3 * ms / max(nl, 1), 1),
+                           "solve_s": round(dt, 2)}
+        log("  %-10s %8.1f ms %6d launches %9.1f us/launch (solve %.2f s)"
+            % (name, ms, nl, 1e3 * ms / max(nl, 1), dt))
     op.close()
-    print(json.dumps({"experiment": "batched-targets", "workload": pb.name, "rtol": pb.rtol, "rows": rows}))
+    print(json.dumps({"experiment": "batched-targets", "workload": pb.name, "rtol": pb.rtol, "autotune": tune,
+                      "rows": rows, "per_kernel_16_targets": per_class}))
 
 
 def shifted_table(args, fsda, torch):

@@ -228,8 +228,8 @@ int fsda_regression_solve(fsda_op *op, const double *z, const double *betas, int
  * labeled set), and is solved for every beta of one grid by its own shifted
  * CG (Alg. 3, seeded at min beta), in FP64.  X, S and alpha are the
  * handle's; its own labeled set is not used.  Targets go in tiles of up to
- * 16, one tile after the other; the sparse products of the targets of a tile
- * share one pass over the indices.
+ * 16 (fsda_set_batch_tile, fsda_batch_autotune), one tile after the other; the
+ * sparse products of the targets of a tile share one pass over the indices.
  *  ntarget       1..FSDA_MAX_TARGETS.
  *  lab_idx[], lab_y[] (device) the labeled sets of all targets, concatenated;
  *                target c owns entries lab_off[c] .. lab_off[c+1]-1 (same
@@ -253,6 +253,41 @@ int fsda_multishift_solve_batch(fsda_op *op, int ntarget, const int32_t *lab_idx
                                 const int64_t *lab_off, const double *betas, int nshift, double rtol, int maxit,
                                 int chunk, void *workspace, size_t ws_bytes, double *W, int *iters, double *relres,
                                 void *stream);
+
+/*
+ * Targets per tile of fsda_multishift_solve_batch (not part of the method: a
+ * launch shape).  A tile of T targets shares one pass over the indices per
+ * sparse product; a group of T lanes owns a row, so a wave holds 64 / T rows.
+ *  fsda_set_batch_tile: tile 4, 8 or 16, or 0 for the default (16).  Takes
+ *                effect at the next fsda_batch_workspace_size and batch solve
+ *                (the workspace size depends on it).  Errors: FSDA_E_ARG,
+ *                FSDA_E_RANGE.
+ *  fsda_get_batch_tile: *tile (host) receives the tile in use.
+ */
+int fsda_set_batch_tile(fsda_op *op, int tile);
+int fsda_get_batch_tile(const fsda_op *op, int *tile);
+
+/*
+ * Autotuner of the batch tile: for each tile T in {4, 8, 16} not larger than
+ * the tile that min(ntarget, 16) targets need, solves the first min(T, ntarget)
+ * targets (arguments as in fsda_multishift_solve_batch) once to warm up (graph
+ * capture), then for trial_iters and 2 trial_iters iterations (rtol 1e-300, so
+ * nothing stops early), and takes the time difference of the last two over
+ * their iteration difference: setup and the final residual checks cancel.  rates[3] (host) receive the shifted
+ * target-iterations per second of tiles 4, 8 and 16 (0 where not tried); the
+ * fastest tile is kept in the handle (as by fsda_set_batch_tile) and written to
+ * *tile.  Blocks until done.
+ *  trial_iters   1..4096 (32 to 64 suffice on the benchmark workloads).
+ *  workspace, ws_bytes  as for fsda_multishift_solve_batch with the default
+ *                tile (16) and the same ntarget, nshift and chunk 0.
+ *  W             device FP64, room for min(ntarget, 16) x nshift x d; its
+ *                contents afterwards are the unconverged trial iterates.
+ * Errors as fsda_multishift_solve_batch (the tile in use before the call is
+ * kept then), and FSDA_E_RANGE for trial_iters.
+ */
+int fsda_batch_autotune(fsda_op *op, int ntarget, const int32_t *lab_idx, const int8_t *lab_y,
+                        const int64_t *lab_off, const double *betas, int nshift, int trial_iters, void *workspace,
+                        size_t ws_bytes, double *W, void *stream, int *tile, double *rates);
 
 /*
  * Independent systems with different right-hand sides, solved together:
@@ -312,8 +347,9 @@ int fsda_project(fsda_op *op, const double *W, int nshift, double *S, void *stre
  * FSDA_E_RANGE.  Classes: 0 = X product, 1 = graph/centring product, 2 = X^T
  * product (fused with the residual update of every short row of X^T in the
  * feature-space solves), 4 = residual update (sample-space solves), 5 =
- * direction update (feature space: also the residual update of the long rows
- * of X^T), 6 = shift-state fold (3 is unused); the batched FP32 correction solves of FSDA_MIXED: 7 = X
+ * direction update (feature space with X^T unsliced: also the residual update
+ * of the rows of X^T longer than one chunk; with XCD slices those rows are
+ * finished between classes 2 and 5, in no class), 6 = shift-state fold (3 is unused); the batched FP32 correction solves of FSDA_MIXED: 7 = X
  * product, 8 = graph/centring product, 9 = X^T product, 10 = residual and
  * correction update, 11 = direction update; fsda_multishift_solve_batch: 7-9
  * its products, 10 = residual update, 11 = direction update, 12 = shift-state

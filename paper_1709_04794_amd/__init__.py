@@ -80,6 +80,10 @@ def lib():
         L.fsda_batch_workspace_size.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_size_t)]
         L.fsda_multishift_solve_batch.argtypes = [P, I, P, P, P, P, I, D, I, I, P, ctypes.c_size_t, P, P, P, P]
         L.fsda_gather_sum.argtypes = [P, P, ctypes.c_int64, P, I, P]
+        L.fsda_set_batch_tile.argtypes = [P, I]
+        L.fsda_get_batch_tile.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
+        L.fsda_batch_autotune.argtypes = [P, I, P, P, P, P, I, I, P, ctypes.c_size_t, P, P,
+                                          ctypes.POINTER(ctypes.c_int), P]
         L.fsda_destroy_operator.argtypes = [P]
         L.fsda_destroy_operator.restype = None
         L.fsda_last_error.argtypes = []
@@ -88,7 +92,7 @@ def lib():
                   L.fsda_project, L.fsda_time_kernel, L.fsda_kernel_time, L.fsda_batch_workspace_size,
                   L.fsda_multishift_solve_batch, L.fsda_sa_rhs, L.fsda_sa_solve, L.fsda_regression_solve,
                   L.fsda_columns_workspace_size, L.fsda_solve_columns, L.fsda_holdout, L.fsda_hypergradient,
-                  L.fsda_gather_sum):
+                  L.fsda_gather_sum, L.fsda_set_batch_tile, L.fsda_get_batch_tile, L.fsda_batch_autotune):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -316,32 +320,69 @@ class Operator:
         relres [ntarget, S] float64, status).
         """
         import torch
-        if not 1 <= len(labels) <= MAX_TARGETS:
-            raise ValueError("between 1 and %d targets per call" % MAX_TARGETS)
-        idx = [torch.as_tensor(np.asarray(i.cpu() if hasattr(i, "cpu") else i), dtype=torch.int32) for i, _ in labels]
-        ys = [torch.as_tensor(np.asarray(y.cpu() if hasattr(y, "cpu") else y), dtype=torch.int8) for _, y in labels]
-        off = np.zeros(len(labels) + 1, dtype=np.int64)
-        off[1:] = np.cumsum([i.numel() for i in idx])
-        lab_idx = torch.cat(idx).to(self.device)
-        lab_y = torch.cat(ys).to(self.device)
+        lab_idx, lab_y, off = self._labels(labels)
         betas = np.ascontiguousarray(betas, dtype=np.float64)
         S, K = betas.size, len(labels)
-        size = ctypes.c_size_t(0)
-        _check(lib().fsda_batch_workspace_size(self.handle, K, S, int(chunk), ctypes.byref(size)))
-        need = int(size.value) + 256
-        if getattr(self, "_bws", None) is None or self._bws.numel() < need:
-            self._bws = None
-            self._bws = torch.empty(need, dtype=torch.uint8, device=self.device)
-        ws = (self._bws.data_ptr() + 255) // 256 * 256
+        ws, size = self._batch_workspace(K, S, chunk)
         W = torch.empty((K, S, self.d), dtype=torch.float64, device=self.device)
         iters = np.zeros(K * S, dtype=np.int32)
         relres = np.zeros(K * S, dtype=np.float64)
         rc = _check(lib().fsda_multishift_solve_batch(
             self.handle, K, _ptr(lab_idx), _ptr(lab_y), off.ctypes.data_as(ctypes.c_void_p),
             betas.ctypes.data_as(ctypes.c_void_p), S, float(rtol), int(maxit), int(chunk), ctypes.c_void_p(ws),
-            ctypes.c_size_t(int(size.value)), _ptr(W), iters.ctypes.data_as(ctypes.c_void_p),
+            ctypes.c_size_t(size), _ptr(W), iters.ctypes.data_as(ctypes.c_void_p),
             relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
         return W, iters.reshape(K, S), relres.reshape(K, S), rc
+
+    def _labels(self, labels):
+        """(lab_idx, lab_y) pairs of several targets -> concatenated device arrays and host offsets."""
+        import torch
+        if not 1 <= len(labels) <= MAX_TARGETS:
+            raise ValueError("between 1 and %d targets per call" % MAX_TARGETS)
+        idx = [torch.as_tensor(np.asarray(i.cpu() if hasattr(i, "cpu") else i), dtype=torch.int32) for i, _ in labels]
+        ys = [torch.as_tensor(np.asarray(y.cpu() if hasattr(y, "cpu") else y), dtype=torch.int8) for _, y in labels]
+        off = np.zeros(len(labels) + 1, dtype=np.int64)
+        off[1:] = np.cumsum([i.numel() for i in idx])
+        return torch.cat(idx).to(self.device), torch.cat(ys).to(self.device), off
+
+    def _batch_workspace(self, K: int, S: int, chunk: int):
+        """Device address (256-byte aligned) and size of the batch workspace for the tile in use."""
+        import torch
+        size = ctypes.c_size_t(0)
+        _check(lib().fsda_batch_workspace_size(self.handle, K, S, int(chunk), ctypes.byref(size)))
+        need = int(size.value) + 256
+        if getattr(self, "_bws", None) is None or self._bws.numel() < need:
+            self._bws = None
+            self._bws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return (self._bws.data_ptr() + 255) // 256 * 256, int(size.value)
+
+    def set_batch_tile(self, tile: int) -> None:
+        """Targets per tile of solve_batch: 4, 8 or 16, or 0 for the default (fsda_set_batch_tile)."""
+        _check(lib().fsda_set_batch_tile(self.handle, int(tile)))
+
+    @property
+    def batch_tile(self) -> int:
+        t = ctypes.c_int(0)
+        _check(lib().fsda_get_batch_tile(self.handle, ctypes.byref(t)))
+        return int(t.value)
+
+    def autotune_batch(self, labels, betas: Sequence[float], trial_iters: int = 32, stream=None):
+        """Times tiles of 4, 8 and 16 targets on these targets (fsda_batch_autotune) and keeps
+        the fastest for solve_batch.  Returns (tile, {tile: shifted target-iterations per s})."""
+        import torch
+        lab_idx, lab_y, off = self._labels(labels)
+        betas = np.ascontiguousarray(betas, dtype=np.float64)
+        S, K = betas.size, len(labels)
+        self.set_batch_tile(0)  # the workspace of the largest tile tried
+        ws, size = self._batch_workspace(K, S, 0)
+        W = torch.empty((min(K, 16), S, self.d), dtype=torch.float64, device=self.device)
+        tile = ctypes.c_int(0)
+        rates = np.zeros(3, dtype=np.float64)
+        _check(lib().fsda_batch_autotune(self.handle, K, _ptr(lab_idx), _ptr(lab_y), off.ctypes.data_as(ctypes.c_void_p),
+                                         betas.ctypes.data_as(ctypes.c_void_p), S, int(trial_iters),
+                                         ctypes.c_void_p(ws), ctypes.c_size_t(size), _ptr(W), _stream(stream),
+                                         ctypes.byref(tile), rates.ctypes.data_as(ctypes.c_void_p)))
+        return int(tile.value), {t: float(r) for t, r in zip((4, 8, 16), rates) if r > 0}
 
     def project(self, W, stream=None):
         import torch

@@ -28,6 +28,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
@@ -84,6 +85,7 @@ int batch_tile(int ncol) { return std::max(4, pow2_at_least(ncol)); }
 // the indices stop paying beyond 16 at mid (16: 140 shifted solves/s, 32: 136,
 // 64: 92), since the per-target vectors dominate the traffic there.
 constexpr int TARGET_TILE = 16;
+int batch_tile_of(const fsda_op* op);
 
 struct Layout {
   size_t st, part, hist, fcoef, labw, ycen, zw, t, u, b, p, q, bu, new2old, old2new, xcol, xt_rowptr, xt_col;
@@ -306,7 +308,9 @@ struct fsda_op {
   // table of the batched product for tile btab_tile
   std::vector<int> xt_rp_med;
   int nmed, btab_tile, bnchunk;
-  // batched targets: one chunk of iterations + fold as a graph, and its key
+  // batched targets: targets per tile (0: TARGET_TILE; set by fsda_set_batch_tile
+  // or fsda_batch_autotune), one chunk of iterations + fold as a graph, and its key
+  int btile_sel;
   hipGraphExec_t tgexec;
   const void* tkey_ws;
   const double* tkey_W;
@@ -521,6 +525,8 @@ void fold(fsda_op* op, double* W, int nshift, int chunk, int mode, hipStream_t s
   });
   hipLaunchKernelGGL(k_fold_done, dim3(1), dim3(1), 0, s, op->st);
 }
+
+int batch_tile_of(const fsda_op* op) { return op->btile_sel ? op->btile_sel : TARGET_TILE; }
 
 void drop_graph(fsda_op* op) {
   if (op->gexec) (void)hipGraphExecDestroy(op->gexec);
@@ -2137,7 +2143,7 @@ int fsda_batch_workspace_size(const fsda_op* op, int ntarget, int nshift, int ch
   if (chunk < 0 || chunk > FSDA_MAX_BATCH_CHUNK) return fail(FSDA_E_RANGE, "chunk outside 0..FSDA_MAX_BATCH_CHUNK");
   if (chunk == 0) chunk = 64;
   TLayout L;
-  tlayout(op, batch_tile(std::min(ntarget, TARGET_TILE)), nshift, chunk, &L);
+  tlayout(op, batch_tile(std::min(ntarget, batch_tile_of(op))), nshift, chunk, &L);
   *bytes = L.total;
   return FSDA_OK;
 }
@@ -2164,12 +2170,13 @@ int fsda_multishift_solve_batch(fsda_op* op, int ntarget, const int32_t* lab_idx
   if (!workspace || ws_bytes < need)
     return fail(FSDA_E_WORKSPACE, "workspace NULL or smaller than fsda_batch_workspace_size()");
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(FSDA_E_WORKSPACE, "workspace not 256-byte aligned");
-  // tiles of at most TARGET_TILE targets, one after the other in the same workspace
+  // tiles of at most `tile` targets, one after the other in the same workspace
   // (each tile's solve completes before the next starts); the status is the
   // worst over the tiles
+  const int tile = batch_tile_of(op);
   int status = FSDA_OK;
-  for (int c0 = 0; c0 < ntarget; c0 += TARGET_TILE) {
-    const int nc = std::min(TARGET_TILE, ntarget - c0);
+  for (int c0 = 0; c0 < ntarget; c0 += tile) {
+    const int nc = std::min(tile, ntarget - c0);
     const int T = batch_tile(nc);
     TLayout L;
     tlayout(op, T, nshift, chunk, &L);
@@ -2180,6 +2187,68 @@ int fsda_multishift_solve_batch(fsda_op* op, int ntarget, const int32_t* lab_idx
     status = std::max(status, rc);
   }
   return status;
+}
+
+int fsda_set_batch_tile(fsda_op* op, int tile) {
+  if (!op) return fail(FSDA_E_ARG, "NULL handle");
+  if (tile != 0 && tile != 4 && tile != 8 && tile != 16) return fail(FSDA_E_RANGE, "tile must be 0, 4, 8 or 16");
+  op->btile_sel = tile;
+  return FSDA_OK;
+}
+
+int fsda_get_batch_tile(const fsda_op* op, int* tile) {
+  if (!op || !tile) return fail(FSDA_E_ARG, "NULL argument");
+  *tile = batch_tile_of(op);
+  return FSDA_OK;
+}
+
+int fsda_batch_autotune(fsda_op* op, int ntarget, const int32_t* lab_idx, const int8_t* lab_y, const int64_t* lab_off,
+                        const double* betas, int nshift, int trial_iters, void* workspace, size_t ws_bytes, double* W,
+                        void* stream, int* tile, double* rates) {
+  if (!op || !tile || !rates) return fail(FSDA_E_ARG, "NULL argument");
+  if (ntarget < 1 || ntarget > FSDA_MAX_TARGETS) return fail(FSDA_E_ARG, "ntarget outside 1..FSDA_MAX_TARGETS");
+  if (trial_iters < 1 || trial_iters > 4096) return fail(FSDA_E_RANGE, "trial_iters outside 1..4096");
+  const int keep = op->btile_sel;
+  const int cap = batch_tile(std::min(ntarget, TARGET_TILE));
+  const int cand[3] = {4, 8, 16};
+  std::vector<int> it((size_t)TARGET_TILE * FSDA_MAX_SHIFTS);
+  std::vector<double> rr((size_t)TARGET_TILE * FSDA_MAX_SHIFTS);
+  int best = 0;
+  double best_rate = -1.0;
+  for (int k = 0; k < 3; k++) {
+    rates[k] = 0.0;
+    const int T = cand[k];
+    if (T > cap) continue;
+    op->btile_sel = T;
+    const int nc = std::min(T, ntarget);
+    double sec[3];
+    int imax[3];
+    // a warm-up run (graph capture for this tile), then trial_iters and twice as
+    // many: the difference of the last two is iterations only
+    for (int rep = 0; rep < 3; rep++) {
+      const auto t0 = std::chrono::steady_clock::now();
+      const int rc = fsda_multishift_solve_batch(op, nc, lab_idx, lab_y, lab_off, betas, nshift, 1e-300,
+                                                 trial_iters * (rep == 2 ? 2 : 1), 0, workspace, ws_bytes, W,
+                                                 it.data(), rr.data(), stream);
+      const auto t1 = std::chrono::steady_clock::now();
+      if (rc < 0) {
+        op->btile_sel = keep;
+        return rc;
+      }
+      sec[rep] = std::chrono::duration<double>(t1 - t0).count();
+      imax[rep] = *std::max_element(it.begin(), it.begin() + (size_t)nc * nshift);
+    }
+    double per_iter = imax[2] > imax[1] ? (sec[2] - sec[1]) / (imax[2] - imax[1]) : 0.0;
+    if (!(per_iter > 0.0)) per_iter = sec[2] / std::max(imax[2], 1);  // timer noise on tiny problems
+    rates[k] = per_iter > 0.0 ? (double)nc * nshift / per_iter : 0.0;
+    if (rates[k] > best_rate) {
+      best_rate = rates[k];
+      best = T;
+    }
+  }
+  op->btile_sel = best;
+  *tile = best;
+  return FSDA_OK;
 }
 
 int fsda_time_kernel(fsda_op* op, int kernel, int enable) {

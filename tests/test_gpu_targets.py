@@ -140,3 +140,39 @@ def test_batch_error_names_target_in_a_later_tile(tiny):
     with pytest.raises(fsda.FsdaError) as e:
         op.solve_batch(labs, tiny.betas, rtol=1e-8)
     assert e.value.code == fsda.E_LABELS and "target 17" in str(e.value)
+
+
+@pytest.mark.parametrize("tile", [4, 8])
+def test_batch_set_tile_runs_smaller_tiles(tiny, tile):
+    """A batch of 11 targets in tiles of 4 (4 + 4 + 3) or 8 (8 + 3) matches the oracle."""
+    labs = synth.target_labels(tiny, 11, seed=21, frac_median=0.03, frac_hi=0.1)
+    betas = np.array([5e-2, 1.0, 9.0])
+    op = fsda.Operator.from_problem(tiny, alpha=0.5)
+    op.set_batch_tile(tile)
+    assert op.batch_tile == tile
+    W, iters, relres, st = op.solve_batch(labs, betas, rtol=1e-10, chunk=8)
+    assert st == fsda.OK
+    check_against_oracle(tiny, labs, W, relres, betas, 0.5, 1e-10)
+    with pytest.raises(fsda.FsdaError):
+        op.set_batch_tile(12)
+    assert op.batch_tile == tile
+    op.set_batch_tile(0)
+    assert op.batch_tile == 16
+
+
+def test_batch_autotune_picks_a_tile_and_the_batch_stays_exact(tiny):
+    """The tuner times tiles 4, 8 and 16 (9 targets allow all three), keeps the fastest,
+    and the batch solved with it matches the oracle."""
+    labs = synth.target_labels(tiny, 9, seed=8, frac_median=0.03, frac_hi=0.1)
+    op = fsda.Operator.from_problem(tiny, alpha=0.5)
+    tile, rates = op.autotune_batch(labs, tiny.betas, trial_iters=16)
+    assert tile in (4, 8, 16)
+    assert set(rates) == {4, 8, 16} and all(r > 0 for r in rates.values())
+    assert rates[tile] == max(rates.values())
+    assert op.batch_tile == tile
+    W, iters, relres, st = op.solve_batch(labs, tiny.betas, rtol=1e-10)
+    assert st == fsda.OK
+    check_against_oracle(tiny, labs, W, relres, tiny.betas, 0.5, 1e-10)
+    # two targets: only the tile of 4 fits them
+    tile2, rates2 = op.autotune_batch(labs[:2], tiny.betas, trial_iters=8)
+    assert tile2 == 4 and set(rates2) == {4}
