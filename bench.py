@@ -36,11 +36,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+LSLICE, MAXLSLICE, SPLIT_ROW = 8192, 32, 64  # the X^T plans of the library (LDS slices, split rows)
+
+
+def xt_plan(pb):
+    """The X^T plan the library picks for this problem (and FSDA_XT_SLICES): ("lds",
+    slices), ("xcd", 8) or ("none", 1), with the split rows' count and nonzeros."""
+    cnt = np.bincount(pb.x_col, minlength=pb.d)
+    nsplit, zsplit = int((cnt >= SPLIT_ROW).sum()), int(cnt[cnt >= SPLIT_ROW].sum())
+    nl = -(-pb.n // LSLICE)
+    env = os.environ.get("FSDA_XT_SLICES", "")
+    if env == "1":
+        return "none", 1, nsplit, zsplit
+    if env == "8" or nl > MAXLSLICE:
+        return ("xcd", 8, nsplit, zsplit) if env == "8" or 8 * pb.n > (2 << 20) else ("none", 1, nsplit, zsplit)
+    return "lds", nl, nsplit, zsplit
+
+
 def algorithmic_bytes(kernel: int, pb, nshift: int, chunk: int) -> float:
     """Bytes one launch must move (every array once; gathered vectors counted once)."""
     import paper_1709_04794_amd as fsda
     n, d, z, g = pb.n, pb.d, pb.x_nnz, pb.s_nnz
     lab = 8 * n if pb.alpha < 1.0 else 0
+    plan, nsl, nsplit, zsplit = xt_plan(pb) if kernel in (fsda.K_XT, fsda.K_XTL) else ("none", 1, 0, 0)
+    if kernel == fsda.K_XTL:    # split rows' indices and slice bounds, u (staged once per slice), parts written
+        return 4 * zsplit + 4 * (nsl + 1) * nsplit + 8 * n + 8 * nsl * nsplit if plan == "lds" else 0.0
+    if kernel == fsda.K_XT and plan == "lds":  # short rows' indices, u, p and r in, r out, parts read
+        return 4 * (d + 1) + 4 * (z - zsplit) + 8 * n + 24 * d + 8 * nsl * nsplit
     if kernel == fsda.K_X:      # rowptr, col, p (gathered), t written
         return 4 * (n + 1) + 4 * z + 8 * d + 8 * n + lab
     if kernel == fsda.K_S:      # rowptr, col, t (gathered), u written
@@ -56,7 +78,7 @@ def algorithmic_bytes(kernel: int, pb, nshift: int, chunk: int) -> float:
     return 0.0
 
 
-TRAFFIC_KEYS = {2: "k_xt", 0: "k_rows_x", 6: "k_fold"}
+TRAFFIC_KEYS = {2: "k_xt", 3: "k_xt_lds", 0: "k_rows_x", 6: "k_fold"}
 
 
 def kernel_source_key() -> str:
@@ -89,7 +111,8 @@ def measured_traffic(kernel: int, workload: str):
 
 
 KNAMES = {0: "k_rows<EpiX> (t = X p)", 1: "k_rows<EpiLap> (u = M' t)",
-          2: "k_xt<EpiXTR> (q = X^T u + s p, r -= a q)", 4: "k_resid (sample space)",
+          2: "k_xt<EpiXTR> (q = X^T u + s p, r -= a q)", 3: "k_xt_lds (X^T split rows from LDS slices)",
+          4: "k_resid (sample space)",
           5: "k_pupdate (long rows of X^T, p update, shift scalars)", 6: "k_fold"}
 
 
@@ -204,7 +227,9 @@ def gather_patterns(pb):
     xcol = new[pb.x_col]
     o = np.lexsort((xrow, xcol))
     cold = xcol >= HOT_FEATURES
+    short = cnt[pb.x_col[o]] < SPLIT_ROW  # rows of X^T left to L2 gathers by the LDS-slice plan
     return {"xt": (xcol[o], xrow[o], n), "x_cold": (xrow[cold], xcol[cold], d),
+            "xt_short": (xcol[o][short], xrow[o][short], n),
             "s": (np.repeat(np.arange(n), np.diff(pb.s_rowptr)), pb.s_col, n)}
 
 
@@ -426,8 +451,8 @@ def summarize_rocprof(d: str, kernel_substr: str, calib_mib: int) -> str:
     return "\n".join(lines)
 
 
-TRAFFIC_MATCH = {"k_xt": "k_xt<fsda::EpiXTR<double>", "k_rows_x": "k_rows<fsda::EpiX<double, false>",
-                 "k_fold": "k_fold_apply<double>"}
+TRAFFIC_MATCH = {"k_xt": "k_xt<fsda::EpiXTR<double>", "k_xt_lds": "k_xt_lds<double>",
+                 "k_rows_x": "k_rows<fsda::EpiX<double, false>", "k_fold": "k_fold_apply<double>"}
 
 
 def traffic_lines(dfetch: str, dwrite: str, calib_mib: int, workload: str) -> str:
@@ -611,7 +636,7 @@ def main():
     op_apply = None
     if per_class:
         us = 0.0
-        for k in (fsda.K_X, fsda.K_S, fsda.K_XT, fsda.K_RESID):
+        for k in (fsda.K_X, fsda.K_S, fsda.K_XT, fsda.K_XTL, fsda.K_RESID):
             ms, nl = per_class.get(k, (0.0, 0))
             if nl:
                 us += max(1e3 * ms / nl - pair_us, 0.0)
@@ -619,14 +644,14 @@ def main():
         op_apply = {"bytes": b_op, "us": round(us, 2), "GBps": round(b_op / (us * 1e-6) / 1e9, 1),
                     "frac": round(b_op / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                     "note": "X, graph and X^T passes of one iteration (the X^T pass also updates r, bytes not "
-                            "counted; its long rows are finished in the direction update); HIP-event times "
-                            "minus the event-pair overhead"}
+                            "counted; with LDS slices it is two kernels, both counted); HIP-event times minus "
+                            "the event-pair overhead"}
     bytes_launch = algorithmic_bytes(dom, pb, S, args.chunk)
     achieved = bytes_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
     # the products are bound by random 8-byte gathers: time a bare gather kernel
     # on the dominant product's own index stream
     gather = None
-    pname = {fsda.K_XT: "xt", fsda.K_X: "x_cold", fsda.K_S: "s"}.get(dom)
+    pname = {fsda.K_XT: "xt_short" if xt_plan(pb)[0] == "lds" else "xt", fsda.K_X: "x_cold", fsda.K_S: "s"}.get(dom)
     if pname is not None and not args.no_gather_ceiling:
         _, idx, size = gather_patterns(pb)[pname]
         g_us = time_gathers(fsda, torch, size, idx, pair_us=pair_us)

@@ -113,14 +113,17 @@ int fsda_workspace_size(const fsda_problem *pb, int max_shifts, int max_chunk, s
  * products, the labeled weights and the canonical right-hand side.  *out
  * (host) receives the handle.  Blocks until done.  The workspace belongs to the
  * handle until it is destroyed.
- * XCD slices: when the FP64 sample-space vector is larger than 2 MiB
- * (n > 262,144), the X^T product is planned so that each of the eight XCDs
- * gathers from one eighth of the sample range (its rows of >= 64 nonzeros are
- * cut at the sample boundaries x n / 8 and their parts added in a fixed order).
- * Results differ from the unsliced plan only in the summation order of those
- * rows.  The environment variable FSDA_XT_SLICES set to 1 (never) or 8
- * (always) overrides the choice; it is read by fsda_workspace_size and by this
- * call, which must see the same value (else FSDA_E_WORKSPACE may result).
+ * Plans of the X^T product (the rows of X^T of >= 64 nonzeros are cut at
+ * sample boundaries and their parts added in a fixed order):
+ *  n <= 262,144: LDS slices of 8192 samples; each work-group stages one slice
+ *    of the sample-space vector in LDS and sums the rows' segments there.
+ *  n > 262,144: XCD slices; each of the eight XCDs gathers from one eighth of
+ *    the sample range, which stays in its L2.
+ * Results differ between plans only in the summation order of those rows.
+ * The environment variable FSDA_XT_SLICES set to 1 (no slices), 8 (XCD slices)
+ * or lds (LDS slices, for n <= 262,144) overrides the choice; it is read by
+ * fsda_workspace_size and by this call, which must see the same value (else
+ * FSDA_E_WORKSPACE may result).
  * Errors: FSDA_E_ARG, FSDA_E_RANGE (alpha), FSDA_E_OVERFLOW, FSDA_E_WORKSPACE,
  * FSDA_E_CSR, FSDA_E_LABELS, FSDA_E_HIP.
  */
@@ -346,10 +349,11 @@ int fsda_project(fsda_op *op, const double *W, int nshift, double *S, void *stre
  * launch stream; enable = 0 switches timing off, a negative value is
  * FSDA_E_RANGE.  Classes: 0 = X product, 1 = graph/centring product, 2 = X^T
  * product (fused with the residual update of every short row of X^T in the
- * feature-space solves), 4 = residual update (sample-space solves), 5 =
+ * feature-space solves; with LDS slices it also finishes the split rows),
+ * 3 = the LDS-slice part of the X^T product (k_xt_lds), 4 = residual update (sample-space solves), 5 =
  * direction update (feature space with X^T unsliced: also the residual update
  * of the rows of X^T longer than one chunk; with XCD slices those rows are
- * finished between classes 2 and 5, in no class), 6 = shift-state fold (3 is unused); the batched FP32 correction solves of FSDA_MIXED: 7 = X
+ * finished between classes 2 and 5, in no class), 6 = shift-state fold; the batched FP32 correction solves of FSDA_MIXED: 7 = X
  * product, 8 = graph/centring product, 9 = X^T product, 10 = residual and
  * correction update, 11 = direction update; fsda_multishift_solve_batch: 7-9
  * its products, 10 = residual update, 11 = direction update, 12 = shift-state

@@ -29,7 +29,7 @@ E_ARG, E_CSR, E_LABELS, E_RANGE, E_BREAKDOWN, E_WORKSPACE, E_HIP, E_OVERFLOW = -
 FP64, MIXED = 0, 1
 MAX_SHIFTS, MAX_CHUNK, MAX_TARGETS, MAX_BATCH_CHUNK = 64, 256, 64, 128
 # kernel classes for fsda_time_kernel
-K_X, K_S, K_XT, K_RESID, K_PUPD, K_FOLD = 0, 1, 2, 4, 5, 6
+K_X, K_S, K_XT, K_XTL, K_RESID, K_PUPD, K_FOLD = 0, 1, 2, 3, 4, 5, 6
 # ... and of the batched FP32 correction solves of the mixed path
 K_BX, K_BS, K_BXT, K_BRESID, K_BPUPD = 7, 8, 9, 10, 11
 # ... and the shift-state fold of fsda_multishift_solve_batch

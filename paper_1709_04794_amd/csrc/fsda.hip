@@ -101,18 +101,30 @@ struct Layout {
   long long ldd;  // d padded: stride of the feature-space vectors of the refinement
   long long ldv;  // max(d, n) padded: stride of the ring and per-shift directions
   long long nchunk_max, nlong_max, npart_max, nsplit_max;
-  int nslice;  // X^T slices: 1, or NSLICE (one per XCD)
+  int nslice;  // X^T XCD slices: 1 (none), or NSLICE (one per XCD)
+  int lslice;  // X^T LDS slices (0: none)
+  size_t lparts, lxptr, lxcol;
 };
 
-// X^T is split into XCD slices when the FP64 sample-space vector it gathers from
-// is larger than this (an XCD's L2 is 4 MiB; at 1.6 MB the gathers already run
-// at the rate of L2-resident data).  The environment variable FSDA_XT_SLICES set
-// to 1 or 8 overrides the choice.
+// Plan of the X^T product.  Up to MAXLSLICE LDS slices of LSLICE samples (n <=
+// 262,144): the split rows are summed from u staged in LDS.  Beyond, the FP64
+// sample-space vector (> 2 MiB) outgrows an XCD's L2 share, and the split rows
+// are cut into XCD slices instead.  The environment variable FSDA_XT_SLICES set
+// to 1 (neither), 8 (XCD slices) or lds (LDS slices, where n allows) overrides
+// the choice.  Returns the XCD slice count (1 or NSLICE); *lslice receives the
+// LDS slice count (0: none).
 constexpr long long SLICE_BYTES = 2LL << 20;
-int xt_slices(const fsda_problem* pb) {
+int xt_slices(const fsda_problem* pb, int* lslice) {
+  const long long nl = (pb->n + LSLICE - 1) / LSLICE;
+  const bool lds_fits = nl <= MAXLSLICE;
   const char* e = std::getenv("FSDA_XT_SLICES");
+  *lslice = 0;
   if (e && std::strcmp(e, "1") == 0) return 1;
   if (e && std::strcmp(e, "8") == 0) return NSLICE;
+  if (lds_fits) {
+    *lslice = (int)nl;
+    return 1;
+  }
   return 8 * pb->n > SLICE_BYTES ? NSLICE : 1;
 }
 
@@ -127,7 +139,7 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->ldd = (d + 63) / 64 * 64;
   L->ldv = (std::max(d, n) + 63) / 64 * 64;
   const long long m = std::max(d, n);  // vectors serve both feature-space and sample-space solves
-  L->nslice = xt_slices(pb);
+  L->nslice = xt_slices(pb, &L->lslice);
   L->nlong_max = z / LONG_ROW + 1;
   L->nchunk_max = z / CH + L->nlong_max + 1;
   L->npart_max = L->nchunk_max;
@@ -140,6 +152,13 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
     L->nchunk_max = (long long)NSLICE * (z / CHUNK + z / SLICE_LONG + 1);
     L->npart_max = L->nchunk_max + (long long)NSLICE * L->nsplit_max;
     L->nlong_max = L->nsplit_max;
+  }
+  L->lparts = L->lxptr = L->lxcol = 0;
+  if (L->lslice > 0) {  // split rows: slice boundaries, slice-major indices, one part per (row, slice)
+    L->nsplit_max = z / SPLIT_ROW + 1;
+    L->lparts = 8 * (size_t)L->nsplit_max * (size_t)L->lslice;
+    L->lxptr = 4 * ((size_t)L->nsplit_max + 1) * (size_t)L->lslice;
+    L->lxcol = 2 * (size_t)z;
   }
   L->st = take(sizeof(State));
   L->part = take(sizeof(double) * NSITE * NPART);
@@ -167,7 +186,10 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->chunk_end = take(4 * (size_t)L->nchunk_max);
   L->lpart = take(8 * (size_t)L->npart_max);
   L->row_chunk0 = take(4 * ((size_t)L->nlong_max + 1));
-  L->segp = take(4 * (size_t)(NSLICE + 1) * (size_t)L->nsplit_max);
+  L->segp = take(4 * (size_t)(std::max(NSLICE, L->lslice) + 1) * (size_t)L->nsplit_max);
+  L->lparts = L->lslice > 0 ? take(L->lparts) : 0;
+  L->lxptr = L->lslice > 0 ? take(L->lxptr) : 0;
+  L->lxcol = L->lslice > 0 ? take(L->lxcol) : 0;
   L->bnchunk_max = z / 256 + z / BMED + 2;  // chunks of >= 256 nonzeros, plus one per row
   L->bcrow = L->bcbeg = L->brc0 = 0;
   if (pb->precision == FSDA_MIXED) {  // chunk tables of the batched X^T product (kept across solves)
@@ -252,6 +274,7 @@ enum Mode {
 
 struct XtPlan {  // X^T product: long rows in single-row chunks, the rest in length bins
   XtWork w;
+  XtLds lds;   // with LDS slices: the split rows' parts (k_xt_lds, before k_xt)
   int nlong;
   const int* row_chunk0;
   int grid;    // k_xt
@@ -354,6 +377,7 @@ enum {
   KC_X = 0,
   KC_S = 1,
   KC_XT = 2,
+  KC_XTL = 3,
   KC_RESID = 4,
   KC_PUPD = 5,
   KC_FOLD = 6,
@@ -401,6 +425,13 @@ void run_xt(fsda_op* op, const typename Epi::V* src, Epi epi, int solve, bool as
             double* part = nullptr) {
   const XtPlan& pl = op->pxt;
   if (!part) part = op->part + SITE_XT * NPART;
+  if (pl.lds.nslice > 0 && pl.lds.nsplit > 0) {
+    using V = typename Epi::V;
+    launch(op, KC_XTL, s, [&] {
+      hipLaunchKernelGGL(k_xt_lds<V>, dim3(pl.lds.nslice * pl.lds.bps), dim3(LTB), sizeof(V) * LSLICE, s, pl.lds, src,
+                         op->st, solve);
+    });
+  }
   launch(op, cls, s, [&] {
     hipLaunchKernelGGL(k_xt<Epi>, dim3(pl.grid), dim3(BS), 0, s, pl.w, src, epi, op->st, part, solve);
   });
@@ -612,7 +643,7 @@ int make_xt_slices(fsda_op* op, hipStream_t s) {
   if (nsplit == 0) return FSDA_OK;
   const long long nseg = (long long)(NSLICE + 1) * nsplit;
   hipLaunchKernelGGL(k_slice_bounds, dim3((unsigned)ceil_div(nseg, BS)), dim3(BS), 0, s, op->xt_rowptr, op->xt_col,
-                     nsplit, (long long)op->pb.n, const_cast<int*>(S.segp));
+                     nsplit, (long long)op->pb.n, NSLICE, 0, const_cast<int*>(S.segp));
   HIP_TRY(hipGetLastError());
   std::vector<int> sp(nseg);
   HIP_TRY(hipMemcpyAsync(sp.data(), S.segp, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
@@ -670,6 +701,81 @@ int make_xt_slices(fsda_op* op, hipStream_t s) {
   return FSDA_OK;
 }
 
+// LDS-sliced work of the X^T product (see XtLds): the rows of >= SPLIT_ROW
+// nonzeros [0, nsplit) get their slice boundaries on the device; k_xt_lds runs
+// bps blocks per slice over bins of those rows by expected segment length
+// (length / nslice: >= 256 -> 64 lanes per row, >= 64 -> 32, >= 16 -> 8, else 2),
+// and the X^T pass finishes them from their parts (assembly items).
+int make_xt_lds(fsda_op* op, hipStream_t s) {
+  XtPlan& pl = op->pxt;
+  XtLds& D = pl.lds;
+  const int nsplit = op->xt_bins[3];
+  const int nsl = op->L.lslice;
+  const std::vector<int>& rp = op->xt_rp_med;
+  if (nsplit > op->L.nsplit_max) return fail(FSDA_E_WORKSPACE, "split-row table larger than reserved");
+  std::memset(&D, 0, sizeof(D));
+  D.nslice = nsl;
+  D.n = (int)op->pb.n;
+  D.nsplit = nsplit;
+  int* segp = at<int>(op, op->L.segp);
+  D.xptr = at<int>(op, op->L.lxptr);
+  D.xcol = at<unsigned short>(op, op->L.lxcol);
+  D.parts = at<double>(op, op->L.lparts);
+  pl.w.nasm = nsplit;
+  pl.w.nslice_asm = nsl;
+  pl.w.parts = D.parts;
+  pl.nlong = 0;
+  if (nsplit == 0) return FSDA_OK;
+  const long long nseg = (long long)(nsl + 1) * nsplit;
+  hipLaunchKernelGGL(k_slice_bounds, dim3((unsigned)ceil_div(nseg, BS)), dim3(BS), 0, s, op->xt_rowptr, op->xt_col,
+                     nsplit, (long long)op->pb.n, nsl, LSLICE, segp);
+  HIP_TRY(hipGetLastError());
+  // slice-major index table: offsets per slice from the segment lengths
+  std::vector<int> sp(nseg), xp((size_t)nsl * (nsplit + 1));
+  HIP_TRY(hipMemcpyAsync(sp.data(), segp, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  long long tot = 0;
+  for (int x = 0; x < nsl; x++) {
+    int* px = xp.data() + (size_t)x * (nsplit + 1);
+    for (int j = 0; j < nsplit; j++) {
+      px[j] = (int)tot;
+      tot += sp[(size_t)(x + 1) * nsplit + j] - sp[(size_t)x * nsplit + j];
+    }
+    px[nsplit] = (int)tot;
+  }
+  if (tot > std::max<long long>(op->pb.x_nnz, 1))
+    return fail(FSDA_E_WORKSPACE, "slice-major index table larger than reserved");
+  HIP_TRY(hipMemcpyAsync(const_cast<int*>(D.xptr), xp.data(), sizeof(int) * xp.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_slice_copy, dim3((unsigned)ceil_div((long long)nsl * nsplit, BS)), dim3(BS), 0, s,
+                     op->xt_col, segp, D.xptr, nsplit, nsl, const_cast<unsigned short*>(D.xcol));
+  HIP_TRY(hipGetLastError());
+  const long long lo[4] = {256LL * nsl, 64LL * nsl, 16LL * nsl, 0};
+  const int lprs[4] = {64, 32, 8, 2};
+  int nb = 0, item = 0, j = 0;
+  for (int k = 0; k < 4; k++) {
+    const int r0 = j;
+    while (j < nsplit && rp[j + 1] - rp[j] >= lo[k]) j++;
+    if (j == r0) continue;
+    D.row0[nb] = r0;
+    D.row0[nb + 1] = j;
+    D.lpr[nb] = lprs[k];
+    D.item0[nb] = item;
+    item += (int)ceil_div(j - r0, LTB / lprs[k]);
+    D.item0[nb + 1] = item;
+    nb++;
+  }
+  if (j != nsplit) return fail(FSDA_E_CSR, "X^T rows not ordered by length");
+  D.nb = nb;
+  // about two blocks per CU over all slices, at most one per item
+  D.bps = std::max(1, std::min(item, (int)ceil_div(2 * 256, nsl)));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(k_xt_lds<double>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(double) * LSLICE)));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(k_xt_lds<float>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(float) * LSLICE)));
+  HIP_TRY(hipStreamSynchronize(s));
+  return FSDA_OK;
+}
+
 // Work of the X^T product: chunks of the long rows [0, nlong) (from their row
 // pointers, read back to the host once at build time), then length bins of the
 // other rows (lengths decreasing in the internal order).
@@ -693,8 +799,12 @@ int make_xt(fsda_op* op, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(op->xt_rp_med.data(), op->xt_rowptr, sizeof(int) * (ncopy + 1), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
   }
-  const bool sliced = op->L.nslice > 1;
-  if (sliced) {
+  std::memset(&pl.lds, 0, sizeof(pl.lds));
+  const bool sliced = op->L.nslice > 1 || op->L.lslice > 0;
+  if (op->L.lslice > 0) {
+    const int rc = make_xt_lds(op, s);
+    if (rc) return rc;
+  } else if (sliced) {
     const int rc = make_xt_slices(op, s);
     if (rc) return rc;
   } else if (nlong > 0) {
@@ -754,7 +864,8 @@ int make_xt(fsda_op* op, hipStream_t s) {
     R.lpr[0] = 0;
     R.item0[0] = R.item0[1] = 0;
   }
-  pl.grid = std::max(1, std::min(w.nchunk + NSLICE * w.sl.item0[w.sl.nb] + R.item0[R.nb], GRID_ROWS));
+  pl.grid = std::max(1, std::min((int)ceil_div(w.nasm, BS) + w.nchunk + NSLICE * w.sl.item0[w.sl.nb] + R.item0[R.nb],
+                                 GRID_ROWS));
   pl.gridL = sliced ? grid_for(std::max(pl.nlong, 1), 256) : grid_for(std::max(nlong, 1), 64);
   return FSDA_OK;
 }

@@ -690,9 +690,39 @@ struct XtSlices {
   int part0;                // lpart index of part 0 of row nlc; row j >= nlc has parts part0 + NSLICE (j - nlc) + x
 };
 
+// LDS slices.  When the sample range is cut into at most MAXLSLICE slices of
+// LSLICE samples, one slice of u fits a work-group's LDS, and the split rows'
+// segments of that slice are summed from there (k_xt_lds): gathers from LDS pay
+// no cache-line lookups, which bind the gathers from L2.  The split rows'
+// indices are copied slice-major (slice x: the segments of rows 0, 1, ... in
+// order, as 16-bit offsets in the slice), so a slice's index stream is
+// contiguous.  Part (row j, slice x) goes to parts[x * nsplit + j]; the X^T
+// pass adds a split row's parts in slice order and runs the epilogue (assembly
+// items, before its other items).
+constexpr int LSLICE = 8192;   // samples per LDS slice (64 KiB of FP64)
+constexpr int MAXLSLICE = 32;  // more slices: the XCD slices instead
+constexpr int LTB = 1024;      // threads per block of k_xt_lds
+
+struct XtLds {
+  int nslice;               // 0: not in use
+  int n;                    // samples
+  int nsplit;               // split rows [0, nsplit)
+  int bps;                  // blocks per slice
+  const int* xptr;          // [nslice * (nsplit + 1)]: slice x, row j: xcol[xptr[x (nsplit+1) + j] ..]
+  const unsigned short* xcol;  // slice-major offsets in the slice
+  double* parts;            // [nslice * nsplit]
+  int nb;                   // bins of split rows, lanes per row from the expected segment length
+  int row0[MAXBIN + 1];
+  int lpr[MAXBIN];
+  int item0[MAXBIN + 1];    // items (LTB / lpr rows) of one slice before bin b
+};
+
 struct XtWork {
   const int* rowptr;
   const int* col;
+  int nasm;                // with LDS slices: split rows [0, nasm) finished from their parts
+  int nslice_asm;          // their parts per row
+  const double* parts;     // [nslice_asm * nasm]
   int nchunk;              // chunks of the long rows, all processed before the bins
   int nchunk_multi;        // the first ones, of the rows of more than one part; a row of one
                            // chunk is finished where it is summed
@@ -734,8 +764,19 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __re
   if (Epi::kPublish && blockIdx.x == 0 && threadIdx.x == 0) epi.publish(st);
   const int tid = threadIdx.x;
   double acc = 0.0;
-  const int nitems = X.nchunk + NSLICE * X.sl.item0[X.sl.nb] + X.rows.item0[X.rows.nb];
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  const int nasm_items = (X.nasm + BS - 1) / BS;
+  const int nitems = nasm_items + X.nchunk + NSLICE * X.sl.item0[X.sl.nb] + X.rows.item0[X.rows.nb];
+  for (int it0 = blockIdx.x; it0 < nitems; it0 += gridDim.x) {
+    if (it0 < nasm_items) {  // split rows from their LDS-slice parts, in slice order
+      const int j = it0 * BS + tid;
+      if (j < X.nasm) {
+        double v = 0.0;
+        for (int x = 0; x < X.nslice_asm; x++) v += X.parts[(long long)x * X.nasm + j];
+        acc += epi.row(j, (V)v);
+      }
+      continue;
+    }
+    const int it = it0 - nasm_items;
     if (it < X.nchunk) {
       const int r = X.chunk_row[it];
       const int beg0 = X.chunk_beg[it];
@@ -801,15 +842,79 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __re
   if (Epi::kReduce) write_partial(part, blockIdx.x, acc);
 }
 
-// Slice boundaries of the split rows of X^T: segp[x * nsplit + j] is the first
-// nonzero k of row j with col[k] >= x n / NSLICE (the row's end if none), for
-// x = 0..NSLICE.  Sample indices increase along a row of X^T.
-__global__ __launch_bounds__(BS) void k_slice_bounds(const int* __restrict__ rowptr, const int* __restrict__ col,
-                                                     int nsplit, long long n, int* segp) {
+// Segments of the split rows in LDS slices: block (x, b) stages u over slice x
+// ([x LSLICE, (x+1) LSLICE) of the samples) in LDS, then takes the items b,
+// b + bps, ... of the slice; an item is LTB / lpr rows of one bin, lpr lanes per
+// row, each lane summing every (lpr XUNR)-th nonzero of the row's segment.
+template <typename V>
+__global__ __launch_bounds__(LTB) void k_xt_lds(XtLds L, const V* __restrict__ u, State* st, int solve) {
+  if (solve && st->stop) return;
+  extern __shared__ double lds_raw[];
+  V* lu = reinterpret_cast<V*>(lds_raw);
+  const int tid = threadIdx.x;
+  const int x = blockIdx.x / L.bps, b0 = blockIdx.x % L.bps;
+  const int x0 = x * LSLICE;
+  const int len = min(LSLICE, L.n - x0);
+  for (int k = tid; k < len; k += LTB) lu[k] = u[x0 + k];
+  __syncthreads();
+  const int* xp = L.xptr + (long long)x * (L.nsplit + 1);
+  const int nitems = L.item0[L.nb];
+  for (int it = b0; it < nitems; it += L.bps) {
+    int b = 0;
+    while (it >= L.item0[b + 1]) b++;
+    const int lpr = L.lpr[b];
+    const int j = L.row0[b] + (it - L.item0[b]) * (LTB / lpr) + tid / lpr;
+    const int lane = tid & (lpr - 1);
+    const bool live = j < L.row0[b + 1];
+    V v = (V)0;
+    if (live) {
+      const int end = xp[j + 1];
+      for (int k0 = xp[j] + lane; k0 < end; k0 += lpr * XUNR) {
+        int idx[XUNR];
+        V g[XUNR];
+#pragma unroll
+        for (int q = 0; q < XUNR; q++) {
+          const int k = k0 + q * lpr;
+          idx[q] = k < end ? (int)L.xcol[k] : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < XUNR; q++) g[q] = idx[q] >= 0 ? lu[idx[q]] : (V)0;
+#pragma unroll
+        for (int q = 0; q < XUNR; q++) v += g[q];
+      }
+    }
+    for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (live && lane == 0) L.parts[(long long)x * L.nsplit + j] = (double)v;
+  }
+}
+
+// Slice-major copy of the split rows' indices for the LDS slices: thread (x, j)
+// copies row j's segment of slice x ([segp[x nsplit + j], segp[(x+1) nsplit + j]))
+// to xcol[xptr[x (nsplit+1) + j] ..] as offsets from the slice's first sample.
+__global__ __launch_bounds__(BS) void k_slice_copy(const int* __restrict__ col, const int* __restrict__ segp,
+                                                   const int* __restrict__ xptr, int nsplit, int nslice,
+                                                   unsigned short* xcol) {
   const long long t = (long long)blockIdx.x * BS + threadIdx.x;
-  if (t >= (long long)(NSLICE + 1) * nsplit) return;
+  if (t >= (long long)nslice * nsplit) return;
   const int x = (int)(t / nsplit), j = (int)(t % nsplit);
-  const int key = (int)((long long)x * n / NSLICE);
+  const int b = segp[(long long)x * nsplit + j], e = segp[(long long)(x + 1) * nsplit + j];
+  const int o = xptr[(long long)x * (nsplit + 1) + j];
+  const int x0 = x * LSLICE;
+  for (int k = b; k < e; k++) xcol[o + (k - b)] = (unsigned short)(col[k] - x0);
+}
+
+// Slice boundaries of the split rows of X^T: segp[x * nsplit + j] is the first
+// nonzero k of row j with col[k] >= the first sample of slice x (the row's end
+// if none), for x = 0..nslice.  Slice x starts at x n / nslice (slice_len 0:
+// XCD slices) or at min(x slice_len, n) (LDS slices).  Sample indices increase
+// along a row of X^T.
+__global__ __launch_bounds__(BS) void k_slice_bounds(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                     int nsplit, long long n, int nslice, int slice_len, int* segp) {
+  const long long t = (long long)blockIdx.x * BS + threadIdx.x;
+  if (t >= (long long)(nslice + 1) * nsplit) return;
+  const int x = (int)(t / nsplit), j = (int)(t % nsplit);
+  const long long start = slice_len > 0 ? (long long)x * slice_len : (long long)x * n / nslice;
+  const int key = (int)(start < n ? start : n);
   int lo = rowptr[j], hi = rowptr[j + 1];
   while (lo < hi) {
     const int mid = lo + (hi - lo) / 2;

@@ -2,6 +2,7 @@
 gather patterns are the products' own index sets, and the byte model adds up.
 CPU only."""
 import numpy as np
+import pytest
 
 import bench
 import synth
@@ -29,14 +30,25 @@ def test_gather_patterns_are_the_products_index_sets():
     assert np.array_equal(sr, np.repeat(np.arange(pb.n), np.diff(pb.s_rowptr)))
 
 
-def test_operator_apply_bytes_are_the_sum_of_the_products():
-    pb = synth.small_problem(n=200, d=500, mean_nnz=7, k=3, seed=2)
+@pytest.mark.parametrize("plan", ["1", "lds"])
+def test_operator_apply_bytes_are_the_sum_of_the_products(monkeypatch, plan):
+    monkeypatch.setenv("FSDA_XT_SLICES", plan)
+    pb = synth.small_problem(n=200, d=500, mean_nnz=30, k=3, seed=2)
     import paper_1709_04794_amd as fsda
-    total = sum(bench.algorithmic_bytes(k, pb, 4, 32) for k in (fsda.K_X, fsda.K_S, fsda.K_XT))
+    total = sum(bench.algorithmic_bytes(k, pb, 4, 32) for k in (fsda.K_X, fsda.K_S, fsda.K_XT, fsda.K_XTL))
     n, d, z, g = pb.n, pb.d, pb.x_nnz, pb.s_nnz
     lab = 16 * n if pb.alpha < 1.0 else 0
     # products as launched (the X^T pass also reads and writes r: 8d + 8d beyond the bare apply)
-    assert total == 8 * z + 4 * g + 40 * n + 36 * d + 12 + lab
+    want = 8 * z + 4 * g + 40 * n + 36 * d + 12 + lab
+    kind, nsl, nsplit, zsplit = bench.xt_plan(pb)
+    if plan == "lds":
+        # two X^T kernels: u read by both, the split rows' slice bounds, parts written and read
+        cnt = np.bincount(pb.x_col, minlength=d)
+        assert (kind, nsl) == ("lds", 1) and nsplit == int((cnt >= 64).sum()) > 0
+        want += 8 * n + 4 * (nsl + 1) * nsplit + 16 * nsl * nsplit
+    else:
+        assert kind == "none"
+    assert total == want
 
 
 def test_xcd_sliced_stream_is_a_slice_aligned_permutation():

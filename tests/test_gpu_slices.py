@@ -1,16 +1,18 @@
-"""The X^T product in XCD slices vs the CPU oracle and vs the unsliced plan.
+"""The sliced plans of the X^T product vs the CPU oracle and vs the unsliced plan.
 
-The sliced plan is chosen automatically when the FP64 sample-space vector exceeds 2 MiB
-(n > 262,144); FSDA_XT_SLICES=8 forces it and FSDA_XT_SLICES=1 turns it off, which is how
-these tests run both plans on the same inputs.  Split rows are summed in a different order
-than in the unsliced plan, so the two agree to rounding (1e-13 relative on products) but
-are not bit-identical; the oracle bars are those of the unsliced parity tests.
+LDS slices (n <= 262,144) and XCD slices (larger n) are chosen automatically;
+FSDA_XT_SLICES=lds, 8 or 1 forces LDS slices, XCD slices or no slices, which is how these
+tests run the plans on the same inputs.  Split rows are summed in a different order than in
+the unsliced plan, so the plans agree to rounding (1e-13 relative on products) but are not
+bit-identical; the oracle bars are those of the unsliced parity tests.
 
-The planted problem (300,000 samples, 24 features with fixed row lengths of X^T) covers
-every part of the sliced plan: a dense feature whose slices are longer than one chunk (two
-rounds of chunk items, the second ones short), the other chunk-summed rows (>= 8192
-nonzeros), each bin of split rows ([1024, 8192), [512, 1024), [256, 512), [64, 256)), and
-the short and empty rows that stay unsplit.
+The planted problems (24 features with fixed row lengths of X^T) cover every part of each
+plan.  XCD slices, 300,000 samples: a dense feature whose slices are longer than one chunk
+(two rounds of chunk items, the second ones short), the other chunk-summed rows (>= 8192
+nonzeros), each bin of split rows ([1024, 8192), [512, 1024), [256, 512), [64, 256)).  LDS
+slices, 200,000 samples (25 slices of 8192): rows in each bin by expected segment length
+(>= 256, >= 64, >= 16 nonzeros per slice, and fewer), a dense feature.  Both: the short and
+empty rows that stay unsplit.
 """
 import numpy as np
 import pytest
@@ -25,6 +27,7 @@ pytestmark = pytest.mark.gpu
 
 PLANTED_COUNTS = [300000, 120000, 20000, 9000, 5000, 3000, 1500, 800, 600, 400, 300, 200, 100, 80, 64,
                   63, 40, 20, 10, 5, 2, 1, 0, 0]
+PLANS = ["8", "lds"]  # FSDA_XT_SLICES of the planted problem of each plan
 
 
 def relerr(a, b):
@@ -66,15 +69,19 @@ def tiny():
 
 
 @pytest.fixture(scope="module")
-def planted():
-    return synth.planted_problem(300000, PLANTED_COUNTS, n_lab=3000, pos_frac=0.3, alpha=0.5,
-                                 betas=(0.05, 0.5, 5.0, 50.0), seed=4, rtol=1e-11)
+def planted_by_plan():
+    """XCD slices: 300,000 samples; LDS slices: 200,000 (a dense feature of 200,000)."""
+    return {"8": synth.planted_problem(300000, PLANTED_COUNTS, n_lab=3000, pos_frac=0.3, alpha=0.5,
+                                       betas=(0.05, 0.5, 5.0, 50.0), seed=4, rtol=1e-11),
+            "lds": synth.planted_problem(200000, [200000] + PLANTED_COUNTS[1:], n_lab=2000, pos_frac=0.3,
+                                         alpha=0.5, betas=(0.05, 0.5, 5.0, 50.0), seed=6, rtol=1e-11)}
 
 
+@pytest.mark.parametrize("plan", PLANS)
 @pytest.mark.parametrize("which", ["tiny", "planted"])
-def test_sliced_products_match_oracle_and_unsliced(tiny, planted, monkeypatch, which):
-    pb = tiny if which == "tiny" else planted
-    op8 = build(pb, monkeypatch, 8)
+def test_sliced_products_match_oracle_and_unsliced(tiny, planted_by_plan, monkeypatch, which, plan):
+    pb = tiny if which == "tiny" else planted_by_plan[plan]
+    op8 = build(pb, monkeypatch, plan)
     op1 = build(pb, monkeypatch, 1)
     p = synth.normal(pb.d, seed=2, stream=3)
     for sigma in (0.0, 1e-2):
@@ -94,9 +101,10 @@ def test_sliced_products_match_oracle_and_unsliced(tiny, planted, monkeypatch, w
     assert (np.abs(br - ref) <= tol).all(), np.abs(br - ref) / tol
 
 
+@pytest.mark.parametrize("plan", PLANS)
 @pytest.mark.parametrize("alpha", [1.0, 0.5, 0.0])
-def test_sliced_solve_matches_oracle_tiny(tiny, monkeypatch, alpha):
-    op = build(tiny, monkeypatch, 8, alpha=alpha)
+def test_sliced_solve_matches_oracle_tiny(tiny, monkeypatch, alpha, plan):
+    op = build(tiny, monkeypatch, plan, alpha=alpha)
     W, iters, relres, st = op.solve(tiny.betas, rtol=tiny.rtol)
     assert st == fsda.OK
     Wr, *_ = oracle.solve(tiny, rtol=1e-13, maxit=20000, alpha=alpha)
@@ -109,12 +117,14 @@ def test_sliced_solve_matches_oracle_tiny(tiny, monkeypatch, alpha):
         assert abs(relres[s] - ref) <= 1e-3 * ref + 1e-15
 
 
+@pytest.mark.parametrize("plan", PLANS)
 @pytest.mark.parametrize("chunk", [1, 3, 128])
-def test_sliced_solve_planted_matches_oracle(planted, monkeypatch, chunk):
+def test_sliced_solve_planted_matches_oracle(planted_by_plan, monkeypatch, chunk, plan):
     """Fold interval 1 puts r_i and r_{i+1} in one ring slot (the split rows are read and
     written by k_assemble); 3 and 128 end the solve inside a fold interval, after which no
     kernel of the remaining iterations may write the ring."""
-    op = build(planted, monkeypatch, 8, max_chunk=128)
+    planted = planted_by_plan[plan]
+    op = build(planted, monkeypatch, plan, max_chunk=128)
     W, iters, relres, st = op.solve(planted.betas, rtol=planted.rtol, chunk=chunk)
     assert st == fsda.OK
     Wr, itr, *_ = oracle.solve(planted, rtol=1e-13, maxit=20000)
@@ -122,16 +132,18 @@ def test_sliced_solve_planted_matches_oracle(planted, monkeypatch, chunk):
     for s in range(planted.betas.size):
         assert relerr(W[s], Wr[s]) < 1e-6, (s, relerr(W[s], Wr[s]))
         assert relres[s] < 20 * planted.rtol
-    W1, it1, *_ = build(planted, monkeypatch, 8, max_chunk=128).solve(planted.betas, rtol=planted.rtol, chunk=1)
+    W1, it1, *_ = build(planted, monkeypatch, plan, max_chunk=128).solve(planted.betas, rtol=planted.rtol, chunk=1)
     assert np.array_equal(iters, it1)
     assert maxrel(W, W1.cpu().numpy()) < 1e-12
 
 
-def test_sliced_solve_is_deterministic_and_graph_equals_direct(planted, monkeypatch):
+@pytest.mark.parametrize("plan", PLANS)
+def test_sliced_solve_is_deterministic_and_graph_equals_direct(planted_by_plan, monkeypatch, plan):
     """Replays of the captured fold interval give the same bits as direct launches."""
-    op_g = build(planted, monkeypatch, 8)
+    planted = planted_by_plan[plan]
+    op_g = build(planted, monkeypatch, plan)
     monkeypatch.setenv("FSDA_NO_GRAPH", "1")
-    op_d = build(planted, monkeypatch, 8)
+    op_d = build(planted, monkeypatch, plan)
     monkeypatch.delenv("FSDA_NO_GRAPH")
     for _ in range(3):  # replays with eager work in between
         Wg, itg, rg, _ = op_g.solve(planted.betas, rtol=planted.rtol, chunk=16)
@@ -142,19 +154,40 @@ def test_sliced_solve_is_deterministic_and_graph_equals_direct(planted, monkeypa
         assert np.array_equal(rg, rd)
 
 
-def test_sliced_regression_and_mixed_tiny(tiny, monkeypatch):
+@pytest.mark.parametrize("plan", PLANS)
+def test_sliced_regression_and_mixed_tiny(tiny, monkeypatch, plan):
     z = synth.normal(tiny.n, seed=3, stream=8)
     betas = np.logspace(-2, 2, 6)
-    op = build(tiny, monkeypatch, 8)
+    op = build(tiny, monkeypatch, plan)
     W, iters, relres, st = op.regression_solve(torch.from_numpy(z).cuda(), betas, rtol=1e-10)
     assert st == fsda.OK
     Wr, *_ = oracle.reg_solve(tiny, z, betas, rtol=1e-13, maxit=50000)
     for s in range(betas.size):
         assert relerr(W[s].cpu().numpy(), Wr[s]) < 1e-6, s
-    opm = build(tiny, monkeypatch, 8, precision=fsda.MIXED)
+    opm = build(tiny, monkeypatch, plan, precision=fsda.MIXED)
     Wm, itm, rm, stm = opm.solve(tiny.betas, rtol=1e-8)
     assert stm == fsda.OK
     Wo, *_ = oracle.solve(tiny, rtol=1e-13, maxit=20000)
     for s in range(tiny.betas.size):
         assert relerr(Wm[s].cpu().numpy(), Wo[s]) < 1e-4, s
         assert rm[s] <= 1e-8
+
+
+@pytest.mark.parametrize("plan", PLANS)
+@pytest.mark.parametrize("n", [3, 7, 9, 70, 130])
+def test_sliced_tiny_sample_counts(monkeypatch, n, plan):
+    """Fewer samples than slices (empty slices), n not a multiple of 8, a dense feature and
+    features of 64 and more samples (split rows in every bin that fits), empty features."""
+    counts = [n, max(1, n // 2), min(n, 64), min(n, 65), 2, 1, 0]
+    pb = synth.planted_problem(n, counts, n_lab=max(2, n // 3), pos_frac=0.4, alpha=0.6,
+                               betas=(1e-2, 0.3, 4.0), seed=n, rtol=1e-11)
+    op = build(pb, monkeypatch, plan)
+    p = synth.normal(pb.d, seed=n, stream=2)
+    q = op.apply(1e-2, torch.from_numpy(p).cuda()).cpu().numpy()
+    ref = oracle.apply(pb, 1e-2, p)
+    assert maxrel(q, ref) < 1e-12
+    W, iters, relres, st = op.solve(pb.betas, rtol=pb.rtol)
+    assert st == fsda.OK
+    Wr, *_ = oracle.solve(pb, rtol=1e-13, maxit=50000)
+    for s in range(pb.betas.size):
+        assert relerr(W[s].cpu().numpy(), Wr[s]) < 1e-6, (n, s)
