@@ -290,8 +290,9 @@ def gather_ceiling(args, fsda, torch):
     workload's sizes: uniform indices, and the index patterns of the products
     themselves (X^T: the samples of every feature row; X: the features of every
     sample beyond the ones staged in shared memory; S: the neighbours of every
-    sample), and the X^T pattern cut into XCD slices (xcd_sliced_stream) with and
-    without the alignment of slices to XCDs.  Also counts the distinct 128-byte lines each row of a product
+    sample), the X^T rows that the LDS-slice plan leaves to L2 gathers (rows of
+    fewer than 64 nonzeros), and the X^T pattern cut into XCD slices
+    (xcd_sliced_stream) with and without the alignment of slices to XCDs.  Also counts the distinct 128-byte lines each row of a product
     touches (16 FP64 values per line), the number of cache-line lookups a
     product cannot avoid.  Features are ordered by decreasing frequency, as the
     operator orders them internally.
@@ -317,6 +318,7 @@ def gather_ceiling(args, fsda, torch):
         "X cold pattern over d (p)": (d, pat["x_cold"][1]),
         "S pattern over n (t)": (n, pat["s"][1]),
         "uniform over 4096 (L1-resident)": (4096, rng.integers(0, 4096, z)),
+        "X^T short rows (LDS plan: L2 part)": (n, pat["xt_short"][1]),
         "X^T pattern, XCD slices": (n, xcd_sliced_stream(pat["xt"][1], n)),
         "X^T pattern, slices not XCD-aligned": (n, xcd_sliced_stream(pat["xt"][1], n, aligned=False)),
     }
