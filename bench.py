@@ -367,6 +367,23 @@ def batched_targets(args, fsda, torch):
         log("%d targets x %d shifts: %.3f s, %.1f shifted solves/s, worst relres %.2e"
             % (k, pb.betas.size, dt, solved / dt, rel.max()))
         del W
+    many = None
+    if args.targets > 0:  # e.g. 1000 targets: calls of 64 (the most one call takes), one after the other
+        labs = synth.target_labels(pb, args.targets, seed=2)
+        t0 = time.perf_counter()
+        solved, worst, maxit = 0, 0.0, 0
+        for c0 in range(0, args.targets, 64):
+            W, it, rel, st = op.solve_batch(labs[c0:c0 + 64], pb.betas, rtol=pb.rtol)
+            torch.cuda.synchronize()
+            solved += int((rel <= TARGET_RELRES).sum())
+            worst, maxit = max(worst, float(rel.max())), max(maxit, int(it.max()))
+            del W
+            log("targets %d..%d done after %.1f s" % (c0, min(c0 + 64, args.targets) - 1, time.perf_counter() - t0))
+        dt = time.perf_counter() - t0
+        many = {"targets": args.targets, "shifts": int(pb.betas.size), "seconds": round(dt, 2),
+                "shifted_solves_per_s": round(solved / dt, 2), "solved": solved, "worst_relres": worst,
+                "max_iters": maxit, "calls": -(-args.targets // 64)}
+        log("%d targets x %d shifts: %.1f s, %.1f shifted solves/s" % (args.targets, pb.betas.size, dt, solved / dt))
     # per-kernel time of one 16-target solve: one solve per class, that class's
     # launches bracketed by HIP events (direct launches while timing)
     labs = synth.target_labels(pb, 16, seed=1)
@@ -385,7 +402,7 @@ def batched_targets(args, fsda, torch):
             % (name, ms, nl, 1e3 * ms / max(nl, 1), dt))
     op.close()
     print(json.dumps({"experiment": "batched-targets", "workload": pb.name, "rtol": pb.rtol, "autotune": tune,
-                      "rows": rows, "per_kernel_16_targets": per_class}))
+                      "rows": rows, "many_targets": many, "per_kernel_16_targets": per_class}))
 
 
 def shifted_table(args, fsda, torch):
@@ -524,6 +541,8 @@ def main():
     ap.add_argument("--no-paths", action="store_true", help="skip timing the further entry points (detail.paths)")
     ap.add_argument("--no-gather-ceiling", action="store_true",
                     help="skip timing the bare gathers of the dominant product's index stream")
+    ap.add_argument("--targets", type=int, default=0,
+                    help="batched-targets experiment: also solve this many targets, in calls of 64")
     ap.add_argument("--experiment", default="",
                     help="'shifted-table': the CG versus shifted CG table instead; 'gather-ceiling': the rate of "
                          "random gathers the sparse products are bound by; 'batched-targets': 16, 32 and 64 targets")
