@@ -92,3 +92,24 @@ def test_target_labels_are_valid_and_reproducible():
         assert set(np.unique(y1).tolist()) == {-1, 1}
         assert i1.size >= 4
     assert len({i.size for i, _ in a}) > 1  # the labeled fraction varies over targets
+
+
+def test_planted_problem_has_the_planted_counts_and_a_valid_graph():
+    """Feature f occurs in exactly counts[f] distinct samples (a count of n: every sample);
+    columns strictly increase in a row; the path graph is symmetric with degrees 1 and 2 and
+    no self loops; both classes are labeled."""
+    counts = [50, 20, 7, 1, 0, 3]
+    pb = synth.planted_problem(50, counts, n_lab=10, pos_frac=0.3, seed=3)
+    assert pb.d == len(counts) and pb.n == 50
+    assert np.array_equal(np.bincount(pb.x_col, minlength=pb.d), counts)
+    for i in range(pb.n):
+        row = pb.x_col[pb.x_rowptr[i]:pb.x_rowptr[i + 1]]
+        assert np.all(np.diff(row) > 0) and row[0] == 0  # feature 0 is in every sample
+    deg = np.diff(pb.s_rowptr)
+    assert deg[0] == deg[-1] == 1 and np.all(deg[1:-1] == 2)
+    src = np.repeat(np.arange(pb.n), deg)
+    edges = set(zip(src.tolist(), pb.s_col.tolist()))
+    assert all((j, i) in edges for i, j in edges) and all(i != j for i, j in edges)
+    assert all(abs(i - j) == 1 for i, j in edges)
+    assert pb.lab_idx.size == 10 and np.all(np.diff(pb.lab_idx) > 0)
+    assert set(np.unique(pb.lab_y).tolist()) == {-1, 1} and int((pb.lab_y == 1).sum()) == 3
