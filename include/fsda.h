@@ -337,6 +337,54 @@ int fsda_hypergradient(fsda_op *op, const double *W, const double *Lambda, const
                        double *dlogbeta, double *dalpha, void *stream);
 
 /*
+ * Many targets (as in fsda_multishift_solve_batch): the hold-out loss, the
+ * adjoint systems and the hypergradient of every (target, shift), for
+ * selecting beta and alpha per target over held-out labeled data (the ratings
+ * of Alg. 7 judged on labels the solve did not see).  Arrays over (target,
+ * shift) are ordered c * nshift + s; W, G, Lambda are [ntarget][nshift][d] in
+ * the caller's feature order.
+ *
+ * fsda_holdout_batch: loss[c * nshift + s] (host) = 1/2 ||X_ho,c w_cs -
+ *   y_ho,c||^2 / n_ho,c with target c's held-out rows ho_idx[ho_off[c] ..
+ *   ho_off[c+1]) (device int32, distinct within a target, in range) and targets
+ *   ho_y (device FP64, same positions); ho_off[ntarget+1] host, ho_off[0] = 0,
+ *   at least one held-out row per target.  G (device, or NULL) receives
+ *   X_ho,c^T (X_ho,c w_cs - y_ho,c) / n_ho,c, the right-hand sides of the
+ *   adjoint systems.  FSDA_E_ARG names the target of a bad held-out index.
+ *
+ * fsda_solve_columns_batch: solves A_c(beta_s) lambda_cs = B_cs for every
+ *   (target, shift), A_c the operator of target c's labeled set (lab_idx,
+ *   lab_y, lab_off as in fsda_multishift_solve_batch: the training part of
+ *   each target's labels) with the handle's X, S and alpha.  The right-hand
+ *   sides differ per (target, shift), so no shared basis: batched CG in FP64,
+ *   columns in tiles of 16 (each tile's products one pass over the indices),
+ *   taken shift by shift (the columns of one tile share a shift, so they need
+ *   similar iteration counts), tiles one after the other.  B, X [ntarget][nshift][d] device; betas
+ *   [nshift] host, each > 0; rtol, maxit per column as in fsda_solve_columns;
+ *   workspace device, 256-byte aligned, >= fsda_columns_batch_workspace_size()
+ *   (one tile; scratch); iters, relres [ntarget * nshift] host (relres the
+ *   true FP64 residual relative to ||B_cs||).  Status: the worst over the
+ *   columns (FSDA_NOT_CONVERGED if any column reached maxit).  Blocks until
+ *   done.
+ *
+ * fsda_hypergradient_batch: from W and Lambda (A_c symmetric, so Lambda solves
+ *   the transposed system too), dlogbeta[c * nshift + s] = -beta_s <lambda_cs,
+ *   w_cs> and dalpha[c * nshift + s] = -<X lambda_cs, [L - (P_lc - 1_lc 1_lc^T
+ *   / l_c)] X w_cs> (host outputs), with target c's training labeled set.
+ * 1 <= ntarget <= FSDA_MAX_TARGETS, 1 <= nshift <= FSDA_MAX_SHIFTS.
+ */
+int fsda_holdout_batch(fsda_op *op, int ntarget, const double *W, int nshift, const int32_t *ho_idx,
+                       const double *ho_y, const int64_t *ho_off, double *loss, double *G, void *stream);
+int fsda_columns_batch_workspace_size(const fsda_op *op, int ntarget, int nshift, size_t *bytes);
+int fsda_solve_columns_batch(fsda_op *op, int ntarget, const int32_t *lab_idx, const int8_t *lab_y,
+                             const int64_t *lab_off, const double *betas, int nshift, const double *B, double rtol,
+                             int maxit, void *workspace, size_t ws_bytes, double *X, int *iters, double *relres,
+                             void *stream);
+int fsda_hypergradient_batch(fsda_op *op, int ntarget, const int32_t *lab_idx, const int8_t *lab_y,
+                             const int64_t *lab_off, const double *W, const double *Lambda, const double *betas,
+                             int nshift, double *dlogbeta, double *dalpha, void *stream);
+
+/*
  * Ratings s = X w for each shift (Alg. 7, return value; uncentred):
  * W[nshift][d] device FP64 in, S[nshift][n] device FP64 out.
  */

@@ -79,6 +79,10 @@ def lib():
         L.fsda_hypergradient.argtypes = [P, P, P, P, I, P, P, P]
         L.fsda_batch_workspace_size.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_size_t)]
         L.fsda_multishift_solve_batch.argtypes = [P, I, P, P, P, P, I, D, I, I, P, ctypes.c_size_t, P, P, P, P]
+        L.fsda_holdout_batch.argtypes = [P, I, P, I, P, P, P, P, P, P]
+        L.fsda_columns_batch_workspace_size.argtypes = [P, I, I, ctypes.POINTER(ctypes.c_size_t)]
+        L.fsda_solve_columns_batch.argtypes = [P, I, P, P, P, P, I, P, D, I, P, ctypes.c_size_t, P, P, P, P]
+        L.fsda_hypergradient_batch.argtypes = [P, I, P, P, P, P, P, P, I, P, P, P]
         L.fsda_gather_sum.argtypes = [P, P, ctypes.c_int64, P, I, P]
         L.fsda_set_batch_tile.argtypes = [P, I]
         L.fsda_get_batch_tile.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
@@ -92,7 +96,9 @@ def lib():
                   L.fsda_project, L.fsda_time_kernel, L.fsda_kernel_time, L.fsda_batch_workspace_size,
                   L.fsda_multishift_solve_batch, L.fsda_sa_rhs, L.fsda_sa_solve, L.fsda_regression_solve,
                   L.fsda_columns_workspace_size, L.fsda_solve_columns, L.fsda_holdout, L.fsda_hypergradient,
-                  L.fsda_gather_sum, L.fsda_set_batch_tile, L.fsda_get_batch_tile, L.fsda_batch_autotune):
+                  L.fsda_gather_sum, L.fsda_set_batch_tile, L.fsda_get_batch_tile, L.fsda_batch_autotune,
+                  L.fsda_holdout_batch, L.fsda_columns_batch_workspace_size, L.fsda_solve_columns_batch,
+                  L.fsda_hypergradient_batch):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -333,6 +339,71 @@ class Operator:
             ctypes.c_size_t(size), _ptr(W), iters.ctypes.data_as(ctypes.c_void_p),
             relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
         return W, iters.reshape(K, S), relres.reshape(K, S), rc
+
+    def holdout_batch(self, W, heldout, gradient: bool = True, stream=None):
+        """Hold-out loss of every (target, shift) (fsda_holdout_batch).
+
+        W [ntarget, S, d] from solve_batch; ``heldout`` a list of (ho_idx, ho_y)
+        pairs, one per target (int32 rows, float64 targets).  Returns (loss
+        [ntarget, S] numpy, G [ntarget, S, d] tensor or None)."""
+        import torch
+        W = W.contiguous()
+        K, S = W.shape[0], W.shape[1]
+        if len(heldout) != K:
+            raise ValueError("one held-out set per target")
+        idx = [torch.as_tensor(np.asarray(i.cpu() if hasattr(i, "cpu") else i), dtype=torch.int32) for i, _ in heldout]
+        ys = [torch.as_tensor(np.asarray(y.cpu() if hasattr(y, "cpu") else y), dtype=torch.float64) for _, y in heldout]
+        off = np.zeros(K + 1, dtype=np.int64)
+        off[1:] = np.cumsum([i.numel() for i in idx])
+        hi, hy = torch.cat(idx).to(self.device), torch.cat(ys).to(self.device)
+        loss = np.zeros(K * S, dtype=np.float64)
+        G = torch.empty((K, S, self.d), dtype=torch.float64, device=self.device) if gradient else None
+        _check(lib().fsda_holdout_batch(self.handle, K, _ptr(W), S, _ptr(hi), _ptr(hy),
+                                        off.ctypes.data_as(ctypes.c_void_p), loss.ctypes.data_as(ctypes.c_void_p),
+                                        _ptr(G), _stream(stream)))
+        return loss.reshape(K, S), G
+
+    def solve_columns_batch(self, labels, betas: Sequence[float], B, rtol: float, maxit: int = 100000, stream=None):
+        """A_c(beta_s) x_cs = B_cs for every (target c, shift s) (fsda_solve_columns_batch):
+        ``labels`` as in solve_batch, B [ntarget, S, d].  Returns (X [ntarget, S, d],
+        iters [ntarget, S], relres [ntarget, S], status)."""
+        import torch
+        lab_idx, lab_y, off = self._labels(labels)
+        betas = np.ascontiguousarray(betas, dtype=np.float64)
+        S, K = betas.size, len(labels)
+        B = B.contiguous()
+        if tuple(B.shape) != (K, S, self.d):
+            raise ValueError("B must be [ntarget, nshift, d]")
+        size = ctypes.c_size_t(0)
+        _check(lib().fsda_columns_batch_workspace_size(self.handle, K, S, ctypes.byref(size)))
+        need = int(size.value) + 256
+        if getattr(self, "_cbws", None) is None or self._cbws.numel() < need:
+            self._cbws = None
+            self._cbws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        ws = (self._cbws.data_ptr() + 255) // 256 * 256
+        X = torch.empty((K, S, self.d), dtype=torch.float64, device=self.device)
+        iters = np.zeros(K * S, dtype=np.int32)
+        relres = np.zeros(K * S, dtype=np.float64)
+        rc = _check(lib().fsda_solve_columns_batch(
+            self.handle, K, _ptr(lab_idx), _ptr(lab_y), off.ctypes.data_as(ctypes.c_void_p),
+            betas.ctypes.data_as(ctypes.c_void_p), S, _ptr(B), float(rtol), int(maxit), ctypes.c_void_p(ws),
+            ctypes.c_size_t(int(size.value)), _ptr(X), iters.ctypes.data_as(ctypes.c_void_p),
+            relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return X, iters.reshape(K, S), relres.reshape(K, S), rc
+
+    def hypergradient_batch(self, labels, W, Lam, betas: Sequence[float], stream=None):
+        """(dH/dlog beta [ntarget, S], dH/dalpha [ntarget, S]) per target (fsda_hypergradient_batch)."""
+        lab_idx, lab_y, off = self._labels(labels)
+        betas = np.ascontiguousarray(betas, dtype=np.float64)
+        S, K = betas.size, len(labels)
+        dlb = np.zeros(K * S, dtype=np.float64)
+        da = np.zeros(K * S, dtype=np.float64)
+        _check(lib().fsda_hypergradient_batch(self.handle, K, _ptr(lab_idx), _ptr(lab_y),
+                                              off.ctypes.data_as(ctypes.c_void_p), _ptr(W.contiguous()),
+                                              _ptr(Lam.contiguous()), betas.ctypes.data_as(ctypes.c_void_p), S,
+                                              dlb.ctypes.data_as(ctypes.c_void_p), da.ctypes.data_as(ctypes.c_void_p),
+                                              _stream(stream)))
+        return dlb.reshape(K, S), da.reshape(K, S)
 
     def _labels(self, labels):
         """(lab_idx, lab_y) pairs of several targets -> concatenated device arrays and host offsets."""

@@ -519,4 +519,11 @@ __global__ void bk_unpack(const V* __restrict__ X, const int* __restrict__ old2n
   }
 }
 
+// out[jj] = X[old2new[jj] * T + c] for one column c (into its own row of the caller's array).
+template <int T, typename V>
+__global__ void bk_unpack_col(const V* __restrict__ X, const int* __restrict__ old2new, double* out, int c,
+                              long long d) {
+  FSDA_GRID_LOOP(jj, d) out[jj] = (double)X[(size_t)old2new[jj] * T + c];
+}
+
 }  // namespace fsda

@@ -85,6 +85,8 @@ int batch_tile(int ncol) { return std::max(4, pow2_at_least(ncol)); }
 // the indices stop paying beyond 16 at mid (16: 140 shifted solves/s, 32: 136,
 // 64: 92), since the per-target vectors dominate the traffic there.
 constexpr int TARGET_TILE = 16;
+// Columns per tile of fsda_solve_columns_batch (independent systems, FP64).
+constexpr int COLUMN_TILE = 16;
 int batch_tile_of(const fsda_op* op);
 
 struct Layout {
@@ -1038,6 +1040,10 @@ struct BBuf {
   double* part;  // BP_N sites of GRID_B x BT_MAX partials
   V *R, *P, *Q, *X, *t, *u, *lpart;
   BXtArgs xa;
+  // labeled weights of row r, column c: labw[r * lws + c * lcs] (the handle's
+  // labeled set for every column: lws = 1, lcs = 0; one set per column: T, 1)
+  const double* labw;
+  int lws, lcs;
   double* site(int k) const { return part + (size_t)k * GRID_B * BT_MAX; }
 };
 
@@ -1066,7 +1072,7 @@ void b_products(fsda_op* op, const BBuf<V>& b, const V* src, const V* P, const i
   launch(op, timed ? KC_BX : KC_OTHER, s, [&] {
     if (lab)
       hipLaunchKernelGGL((bk_rows<T, BEpiX<T, V, true>, true>), dim3(gx), dim3(BS), sm, s, xrp, xrc, (int)n, src,
-                         BEpiX<T, V, true>{b.t, op->labw, 1, 0}, stop, st->cm, b.site(BP_X), bm);
+                         BEpiX<T, V, true>{b.t, b.labw, b.lws, b.lcs}, stop, st->cm, b.site(BP_X), bm);
     else
       hipLaunchKernelGGL((bk_rows<T, BEpiX<T, V, false>, true>), dim3(gx), dim3(BS), sm, s, xrp, xrc, (int)n, src,
                          BEpiX<T, V, false>{b.t, nullptr, 1, 0}, stop, st->cm, b.site(BP_X), bm);
@@ -1075,7 +1081,8 @@ void b_products(fsda_op* op, const BBuf<V>& b, const V* src, const V* P, const i
   launch(op, timed ? KC_BS : KC_OTHER, s, [&] {
     if (lab)
       hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, V, true>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr, op->pb.s_col,
-                         (int)n, b.t, BEpiLap<T, V, true>{b.t, op->labw, 1, 0, op->pb.s_rowptr, b.u, op->pb.alpha, (V)0},
+                         (int)n, b.t,
+                         BEpiLap<T, V, true>{b.t, b.labw, b.lws, b.lcs, op->pb.s_rowptr, b.u, op->pb.alpha, (V)0},
                          stop, st->cm, b.site(BP_TU), BMask{nullptr, 0});
     else
       hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, V, false>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr,
@@ -1122,7 +1129,7 @@ void b_iteration(fsda_op* op, const BBuf<V>& b, hipStream_t s, int tag) {
 // *gexec and replayed.
 template <int T, typename V>
 int run_batched(fsda_op* op, const BBuf<V>& b, const double* B, long long ldb, int ncol, hipGraphExec_t* gexec,
-                const void** gkey, int* gtile, const void* key, hipStream_t s) {
+                const void** gkey, int* gtile, const void* key, hipStream_t s, bool graph_ok = true) {
   constexpr int G = BS / T;
   const long long d = op->pb.d;
   BState* h = b.hst;
@@ -1133,7 +1140,7 @@ int run_batched(fsda_op* op, const BBuf<V>& b, const double* B, long long ldb, i
   hipLaunchKernelGGL((bk_init<T, V>), dim3(gs), dim3(BS), 0, s, B, ldb, ncol, b.R, b.P, b.X, d, b.site(BP_PP));
   hipLaunchKernelGGL(bk_init_done<T>, dim3(1), dim3(BS), 0, s, b.st, b.site(BP_PP), gs);
   HIP_TRY(hipGetLastError());
-  bool graph = op->use_graph != 0 && !op->tk_on;
+  bool graph = graph_ok && op->use_graph != 0 && !op->tk_on;
   if (graph && (!*gexec || *gtile != T || *gkey != key)) {
     if (*gexec) (void)hipGraphExecDestroy(*gexec);
     *gexec = nullptr;
@@ -1202,6 +1209,9 @@ int refine_buffers(fsda_op* op, BBuf<float>* b, hipStream_t s) {
   b->lpart = at<float>(op, L.blpart);
   b->xa = BXtArgs{op->xt_rowptr, op->xt_col, (int)op->pb.d, op->nmed, op->bnchunk, at<int>(op, L.bcrow),
                   at<int>(op, L.bcbeg), at<int>(op, L.brc0)};
+  b->labw = op->labw;
+  b->lws = 1;
+  b->lcs = 0;
   return FSDA_OK;
 }
 
@@ -1253,14 +1263,26 @@ int refine(fsda_op* op, const double* rhs, const double* betas, int nshift, doub
   return FSDA_OK;
 }
 
-// ---- independent columns in FP64 (fsda_solve_columns) ----------------------
+// ---- independent columns in FP64 (fsda_solve_columns, fsda_solve_columns_batch)
+
+// Labeled sets per column (fsda_solve_columns_batch): column c of a tile belongs
+// to target tgt[c], whose labeled entries are lab_idx/lab_y[lab_off[t] ..
+// lab_off[t+1]) (lab_off on the host).  NULL: every column uses the handle's set.
+struct ColTargets {
+  const int* lab_idx;
+  const int8_t* lab_y;
+  const int64_t* lab_off;
+  const int* tgt;   // host [ncol]
+  const int* gcol;  // host [ncol]: the column's row of B, X, iters and relres
+};
 
 struct CLayout {
-  size_t st, part, b64, R, P, Q, X, t, u, lpart, crow, cbeg, rc0, total;
+  size_t st, part, R, P, Q, X, t, u, lpart, crow, cbeg, rc0, flags, labw, b64, total;
   long long ld;
 };
 
-void clayout(const fsda_op* op, int T, int ncol, CLayout* L) {
+// per_col: room for one labeled-weight column per batch column (n x T).
+void clayout(const fsda_op* op, int T, int ncol, bool per_col, CLayout* L) {
   const long long n = op->pb.n, z = std::max<long long>(op->pb.x_nnz, 1);
   const size_t ld = (size_t)op->L.ldd;
   size_t o = 0;
@@ -1272,7 +1294,6 @@ void clayout(const fsda_op* op, int T, int ncol, CLayout* L) {
   L->ld = op->L.ldd;
   L->st = take(sizeof(BState));
   L->part = take(sizeof(double) * BP_N * GRID_B * BT_MAX);
-  L->b64 = take(8 * ld * ncol);
   L->R = take(8 * ld * T);
   L->P = take(8 * ld * T);
   L->Q = take(8 * ld * T);
@@ -1283,12 +1304,54 @@ void clayout(const fsda_op* op, int T, int ncol, CLayout* L) {
   L->crow = take(4 * (size_t)op->L.bnchunk_max);
   L->cbeg = take(4 * (size_t)op->L.bnchunk_max);
   L->rc0 = take(4 * (size_t)(z / BMED + 2));
+  L->flags = take(sizeof(int) * 4 * BT_MAX);
+  L->labw = per_col ? take(8 * (size_t)n * T) : 0;
+  // last: every buffer the captured iterations touch sits at an offset that
+  // depends on (T, per_col) alone, so one graph per (workspace, T, per_col)
+  // serves any ncol
+  L->b64 = take(8 * ld * ncol);
   L->total = o;
+}
+
+// Per-column labeled weights of a tile (ct != NULL): checks every column's
+// labeled set (range, repeats, labels, both classes) and writes labw[i T + c]
+// = 1/l_c on its labeled rows, 0 elsewhere.  cnt and ycen are n x T scratch.
+template <int T>
+int column_labels(fsda_op* op, const ColTargets& ct, int ncol, double* labw, int* flags, int* cnt, double* ycen,
+                  hipStream_t s) {
+  const long long n = op->pb.n;
+  hipLaunchKernelGGL(k_fill_i, dim3(grid_for(n * T, 4096)), dim3(BS), 0, s, cnt, n * T, 0);
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(BS), 0, s, flags, (long long)(4 * BT_MAX), 0);
+  hipLaunchKernelGGL(k_fill_d, dim3(grid_for(n * T, 4096)), dim3(BS), 0, s, labw, n * T, 0.0);
+  for (int c = 0; c < ncol; c++) {
+    const long long k0 = ct.lab_off[ct.tgt[c]], k1 = ct.lab_off[ct.tgt[c] + 1];
+    if (k1 > k0)
+      hipLaunchKernelGGL(tk_label_check<T>, dim3(grid_for(k1 - k0, 1024)), dim3(BS), 0, s, ct.lab_idx, ct.lab_y, k0,
+                         k1, c, n, cnt, flags);
+  }
+  std::vector<int> fl(4 * BT_MAX);
+  HIP_TRY(hipMemcpyAsync(fl.data(), flags, sizeof(int) * fl.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int c = 0; c < ncol; c++) {
+    const std::string tg = "target " + std::to_string(ct.tgt[c]) + ": ";
+    if (fl[c * 4 + 2] & 1) return fail(FSDA_E_LABELS, tg + "labeled index out of range");
+    if (fl[c * 4 + 2] & 2) return fail(FSDA_E_LABELS, tg + "labeled index repeated");
+    if (fl[c * 4 + 2] & 4) return fail(FSDA_E_LABELS, tg + "labels must be +1 or -1");
+    if (fl[c * 4 + 0] == 0 || fl[c * 4 + 1] == 0) return fail(FSDA_E_LABELS, tg + "both classes must be labeled");
+  }
+  for (int c = 0; c < ncol; c++) {
+    const long long k0 = ct.lab_off[ct.tgt[c]], k1 = ct.lab_off[ct.tgt[c] + 1];
+    hipLaunchKernelGGL(tk_label_vectors<T>, dim3(grid_for(k1 - k0, 1024)), dim3(BS), 0, s, ct.lab_idx, ct.lab_y, k0,
+                       k1, c, 1.0 / (double)(k1 - k0), 0.0, labw, ycen);
+  }
+  HIP_TRY(hipGetLastError());
+  return FSDA_OK;
 }
 
 template <int T>
 int run_columns(fsda_op* op, char* ws, const CLayout& L, const double* B, const double* sigmas, int ncol, double rtol,
-                int maxit, double* Xout, int* iters, double* relres, hipStream_t s) {
+                int maxit, double* Xout, int* iters, double* relres, hipStream_t s, const ColTargets* ct = nullptr,
+                bool graph_ok = true) {
   const long long d = op->pb.d;
   BBuf<double> b;
   b.st = reinterpret_cast<BState*>(ws + L.st);
@@ -1301,6 +1364,9 @@ int run_columns(fsda_op* op, char* ws, const CLayout& L, const double* B, const 
   b.t = reinterpret_cast<double*>(ws + L.t);
   b.u = reinterpret_cast<double*>(ws + L.u);
   b.lpart = reinterpret_cast<double*>(ws + L.lpart);
+  b.labw = op->labw;
+  b.lws = 1;
+  b.lcs = 0;
   int* crow = reinterpret_cast<int*>(ws + L.crow);
   int* cbeg = reinterpret_cast<int*>(ws + L.cbeg);
   int* rc0 = reinterpret_cast<int*>(ws + L.rc0);
@@ -1308,17 +1374,31 @@ int run_columns(fsda_op* op, char* ws, const CLayout& L, const double* B, const 
   int rc = chunk_table<T>(op, crow, cbeg, rc0, &nchunk, s);
   if (rc) return rc;
   b.xa = BXtArgs{op->xt_rowptr, op->xt_col, (int)d, op->nmed, nchunk, crow, cbeg, rc0};
-  // right-hand sides in the internal feature order
+  if (ct) {  // one labeled set per column (t and u are scratch until the solve)
+    double* labw = reinterpret_cast<double*>(ws + L.labw);
+    if ((rc = column_labels<T>(op, *ct, ncol, labw, reinterpret_cast<int*>(ws + L.flags),
+                               reinterpret_cast<int*>(b.t), b.u, s)))
+      return rc;
+    b.labw = labw;
+    b.lws = T;
+    b.lcs = 1;
+  }
+  // right-hand sides in the internal feature order; tile column c is row col(c) of B and X
+  auto col = [&](int c) -> long long { return ct ? ct->gcol[c] : c; };
   double* B64 = reinterpret_cast<double*>(ws + L.b64);
   for (int c = 0; c < ncol; c++)
-    hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, B + (long long)c * d, op->new2old,
+    hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, B + col(c) * d, op->new2old,
                        B64 + (long long)c * L.ld, d);
   BState* h = b.hst;
   std::memset(h, 0, sizeof(BState));
   for (int c = 0; c < ncol; c++) h->sigma[c] = sigmas[c];
   h->trel = rtol;
   h->maxit = maxit;
-  if ((rc = run_batched<T, double>(op, b, B64, L.ld, ncol, &op->cgexec, &op->cg_key, &op->cg_tile, ws, s))) return rc;
+  // the captured buffers are fixed by (workspace, T, per-column labels); key 1 + per_col on the tile
+  const void* key = ws + (ct ? 1 : 0);
+  if ((rc = run_batched<T, double>(op, b, B64, L.ld, ncol, &op->cgexec, &op->cg_key, &op->cg_tile, key, s,
+                                   graph_ok)))
+    return rc;
   const int status = h->status;
   // true FP64 residuals ||b_c - A(sigma_c) x_c||
   constexpr int G = BS / T;
@@ -1328,8 +1408,14 @@ int run_columns(fsda_op* op, char* ws, const CLayout& L, const double* B, const 
   hipLaunchKernelGGL((bk_resnorm<T, double>), dim3(gs), dim3(BS), 0, s, b.st, B64, L.ld, ncol, b.Q, b.X, d,
                      b.site(BP_RR));
   hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, zero, b.site(BP_RR), gs, b.st->res2);
-  hipLaunchKernelGGL((bk_unpack<T, double>), dim3(grid_for((long long)ncol * d, 8192)), dim3(BS), 0, s, b.X,
-                     op->old2new, Xout, ncol, d);
+  if (ct) {
+    for (int c = 0; c < ncol; c++)
+      hipLaunchKernelGGL((bk_unpack_col<T, double>), dim3(grid_for(d, 2048)), dim3(BS), 0, s, b.X, op->old2new,
+                         Xout + col(c) * d, c, d);
+  } else {
+    hipLaunchKernelGGL((bk_unpack<T, double>), dim3(grid_for((long long)ncol * d, 8192)), dim3(BS), 0, s, b.X,
+                       op->old2new, Xout, ncol, d);
+  }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(h, b.st, sizeof(BState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1338,21 +1424,22 @@ int run_columns(fsda_op* op, char* ws, const CLayout& L, const double* B, const 
     if (trc) return trc;
   }
   for (int c = 0; c < ncol; c++) {
-    iters[c] = h->conv[c];
-    relres[c] = h->bnorm[c] > 0.0 ? std::sqrt(h->res2[c]) / h->bnorm[c] : 0.0;
+    iters[col(c)] = h->conv[c];
+    relres[col(c)] = h->bnorm[c] > 0.0 ? std::sqrt(h->res2[c]) / h->bnorm[c] : 0.0;
   }
   if (status == FSDA_E_BREAKDOWN) return fail(FSDA_E_BREAKDOWN, "CG breakdown: <p, A p> <= 0 or not finite");
   return status == FSDA_NOT_CONVERGED ? FSDA_NOT_CONVERGED : FSDA_OK;
 }
 
 int columns_any(int T, fsda_op* op, char* ws, const CLayout& L, const double* B, const double* sigmas, int ncol,
-                double rtol, int maxit, double* X, int* iters, double* relres, hipStream_t s) {
+                double rtol, int maxit, double* X, int* iters, double* relres, hipStream_t s,
+                const ColTargets* ct = nullptr, bool graph_ok = true) {
   switch (T) {
-    case 4: return run_columns<4>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s);
-    case 8: return run_columns<8>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s);
-    case 16: return run_columns<16>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s);
-    case 32: return run_columns<32>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s);
-    default: return run_columns<64>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s);
+    case 4: return run_columns<4>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s, ct, graph_ok);
+    case 8: return run_columns<8>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s, ct, graph_ok);
+    case 16: return run_columns<16>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s, ct, graph_ok);
+    case 32: return run_columns<32>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s, ct, graph_ok);
+    default: return run_columns<64>(op, ws, L, B, sigmas, ncol, rtol, maxit, X, iters, relres, s, ct, graph_ok);
   }
 }
 
@@ -1689,6 +1776,95 @@ int targets_any(int T, fsda_op* op, char* ws, const TLayout& L, int ncol, const 
     case 8: return run_targets<8>(op, ws, L, ncol, lab_idx, lab_y, lab_off, betas, nshift, rtol, maxit, chunk, W, iters, relres, s, cbase);
     default: return run_targets<16>(op, ws, L, ncol, lab_idx, lab_y, lab_off, betas, nshift, rtol, maxit, chunk, W, iters, relres, s, cbase);
   }
+}
+
+// Hold-out loss of the rows w_k of W (caller's order) on the held-out samples
+// ho_idx (checked: in range, distinct) with targets ho_y; G_k = X_ho^T e_k / n_ho.
+int holdout_rows(fsda_op* op, const double* W, int nshift, const int32_t* ho_idx, const double* ho_y, long long n_ho,
+                 double* loss, double* G, hipStream_t s) {
+  const long long n = op->pb.n, d = op->pb.d;
+  int* flag = reinterpret_cast<int*>(op->hist);
+  int* mark = reinterpret_cast<int*>(op->bu);  // n counters (bu holds max(n, d) doubles)
+  hipLaunchKernelGGL(k_fill_i, dim3(grid_for(n, 2048)), dim3(BS), 0, s, mark, n, 0);
+  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, flag, 1LL, 0);
+  hipLaunchKernelGGL(k_ho_check, dim3(grid_for(n_ho, 1024)), dim3(BS), 0, s, ho_idx, (long long)n_ho, n, mark, flag);
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hflag & 1) return fail(FSDA_E_ARG, "held-out index out of range");
+  if (hflag & 2) return fail(FSDA_E_ARG, "held-out index repeated");
+  double* v = op->u;             // sample-space adjoint load
+  double* sums = op->hist + 64;  // per shift: sum of squared errors
+  const int gh = grid_for(n_ho, GRID_STREAM);
+  for (int k = 0; k < nshift; k++) {
+    const double* w = W + (long long)k * d;
+    run_rows(op, op->px_user, w, EpiX<double, false>{op->t, nullptr}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
+    hipLaunchKernelGGL(k_fill_d, dim3(grid_for(n, 2048)), dim3(BS), 0, s, v, n, 0.0);
+    hipLaunchKernelGGL(k_ho_resid, dim3(gh), dim3(BS), 0, s, op->t, ho_idx, ho_y, (long long)n_ho, v,
+                       op->part + SITE_R * NPART);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, op->part + SITE_R * NPART, gh, sums + k);
+    if (G) {  // G_k = X^T v (internal order) -> caller's order
+      run_xt(op, v, EpiXT<double, false>{op->q, nullptr, 0.0, nullptr}, 0, true, s, KC_OTHER);
+      hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, op->q, op->old2new, G + (long long)k * d,
+                         d);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  std::vector<double> hs(nshift);
+  HIP_TRY(hipMemcpyAsync(hs.data(), sums, sizeof(double) * nshift, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int k = 0; k < nshift; k++) loss[k] = 0.5 * hs[k] / (double)n_ho;
+  return FSDA_OK;
+}
+
+// dH/dlog beta and dH/dalpha of one labeled set (labeled samples lab_idx[k0,
+// k1); k0 < 0: the handle's set through its labeled weights) for the rows w_k,
+// lambda_k of W and Lambda (caller's order):
+//   dH/dlog beta_k = -beta_k <lambda_k, w_k>,
+//   dH/dalpha_k    = -<X lambda_k, [L - (P_l - 1_l 1_l^T / l)] X w_k>.
+int hypergradient_rows(fsda_op* op, const double* W, const double* Lambda, const double* betas, int nshift,
+                       const int32_t* lab_idx, long long k0, long long k1, double* dlogbeta, double* dalpha,
+                       hipStream_t s) {
+  const long long n = op->pb.n, d = op->pb.d;
+  double* sums = op->hist + 64;  // per shift: <l, w>, <X l, L X w>, sum (X l)(X w), sum X l, sum X w over labeled
+  const int gd = grid_for(d, GRID_STREAM), gn = grid_for(n, GRID_STREAM);
+  const int gl = k0 >= 0 ? grid_for(std::max<long long>(k1 - k0, 1), GRID_STREAM) : gn;
+  double* pA = op->part + SITE_R * NPART;
+  double* pB = op->part + SITE_PP * NPART;
+  double* pC = op->part + SITE_TU * NPART;
+  double* pL = op->part + SITE_XT * NPART;
+  for (int k = 0; k < nshift; k++) {
+    const double* w = W + (long long)k * d;
+    const double* l = Lambda + (long long)k * d;
+    double* out = sums + 5 * k;
+    hipLaunchKernelGGL(k_dot, dim3(gd), dim3(BS), 0, s, l, w, d, pA);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pA, gd, out + 0);
+    run_rows(op, op->px_user, w, EpiX<double, false>{op->t, nullptr}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
+    run_rows(op, op->px_user, l, EpiX<double, false>{op->u, nullptr}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
+    run_rows(op, op->ps, op->t, EpiLapDot{op->t, op->u, op->pb.s_rowptr}, pL, 0, s, KC_OTHER);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pL, op->ps.grid, out + 1);
+    if (k0 >= 0)
+      hipLaunchKernelGGL(k_idxdots, dim3(gl), dim3(BS), 0, s, lab_idx, k0, k1, op->u, op->t, pA, pB, pC);
+    else
+      hipLaunchKernelGGL(k_labdots, dim3(gl), dim3(BS), 0, s, op->labw, op->u, op->t, n, pA, pB, pC);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pA, gl, out + 2);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pB, gl, out + 3);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pC, gl, out + 4);
+  }
+  HIP_TRY(hipGetLastError());
+  std::vector<double> hs(5 * nshift);
+  HIP_TRY(hipMemcpyAsync(hs.data(), sums, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double l = k0 >= 0 ? (double)(k1 - k0) : (double)op->pb.n_lab;
+  for (int k = 0; k < nshift; k++) {
+    const double* o = hs.data() + 5 * k;
+    dlogbeta[k] = -betas[k] * o[0];
+    // <X l, (P_l - 1_l 1_l^T / l) X w> = sum_lab a b - (sum_lab a)(sum_lab b) / l; the
+    // handle's weighted sums (weight 1/l) give l (sum w a b - (sum w a)(sum w b))
+    const double lab = k0 >= 0 ? o[2] - o[3] * o[4] / l : l * (o[2] - o[3] * o[4]);
+    dalpha[k] = -(o[1] - lab);
+  }
+  return FSDA_OK;
 }
 }  // namespace
 
@@ -2139,7 +2315,7 @@ int fsda_columns_workspace_size(const fsda_op* op, int ncol, size_t* bytes) {
   if (!op || !bytes) return fail(FSDA_E_ARG, "NULL argument");
   if (ncol < 1 || ncol > FSDA_MAX_TARGETS) return fail(FSDA_E_ARG, "ncol outside 1..FSDA_MAX_TARGETS");
   CLayout L;
-  clayout(op, batch_tile(ncol), ncol, &L);
+  clayout(op, batch_tile(ncol), ncol, false, &L);
   *bytes = L.total;
   return FSDA_OK;
 }
@@ -2159,7 +2335,7 @@ int fsda_solve_columns(fsda_op* op, const double* B, const double* sigmas, int n
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(FSDA_E_WORKSPACE, "workspace not 256-byte aligned");
   const int T = batch_tile(ncol);
   CLayout L;
-  clayout(op, T, ncol, &L);
+  clayout(op, T, ncol, false, &L);
   return columns_any(T, op, static_cast<char*>(workspace), L, B, sigmas, ncol, rtol, maxit, X, iters, relres,
                      static_cast<hipStream_t>(stream));
 }
@@ -2169,39 +2345,26 @@ int fsda_holdout(fsda_op* op, const double* W, int nshift, const int32_t* ho_idx
   if (!op || !W || !ho_idx || !ho_y || !loss) return fail(FSDA_E_ARG, "NULL argument");
   if (nshift < 1 || nshift > FSDA_MAX_SHIFTS) return fail(FSDA_E_ARG, "nshift outside 1..FSDA_MAX_SHIFTS");
   if (n_ho < 1 || n_ho > op->pb.n) return fail(FSDA_E_ARG, "need 1 <= n_ho <= n");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const long long n = op->pb.n, d = op->pb.d;
-  int* flag = reinterpret_cast<int*>(op->hist);
-  int* mark = reinterpret_cast<int*>(op->bu);  // n counters (bu holds max(n, d) doubles)
-  hipLaunchKernelGGL(k_fill_i, dim3(grid_for(n, 2048)), dim3(BS), 0, s, mark, n, 0);
-  hipLaunchKernelGGL(k_fill_i, dim3(1), dim3(64), 0, s, flag, 1LL, 0);
-  hipLaunchKernelGGL(k_ho_check, dim3(grid_for(n_ho, 1024)), dim3(BS), 0, s, ho_idx, (long long)n_ho, n, mark, flag);
-  int hflag = 0;
-  HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (hflag & 1) return fail(FSDA_E_ARG, "held-out index out of range");
-  if (hflag & 2) return fail(FSDA_E_ARG, "held-out index repeated");
-  double* v = op->u;                     // sample-space adjoint load
-  double* sums = op->hist + 64;          // per shift: sum of squared errors
-  const int gh = grid_for(n_ho, GRID_STREAM);
-  for (int k = 0; k < nshift; k++) {
-    const double* w = W + (long long)k * d;
-    run_rows(op, op->px_user, w, EpiX<double, false>{op->t, nullptr}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
-    hipLaunchKernelGGL(k_fill_d, dim3(grid_for(n, 2048)), dim3(BS), 0, s, v, n, 0.0);
-    hipLaunchKernelGGL(k_ho_resid, dim3(gh), dim3(BS), 0, s, op->t, ho_idx, ho_y, (long long)n_ho, v,
-                       op->part + SITE_R * NPART);
-    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, op->part + SITE_R * NPART, gh, sums + k);
-    if (G) {  // G_k = X^T v (internal order) -> caller's order
-      run_xt(op, v, EpiXT<double, false>{op->q, nullptr, 0.0, nullptr}, 0, true, s, KC_OTHER);
-      hipLaunchKernelGGL(k_gather_d, dim3(grid_for(d, 2048)), dim3(BS), 0, s, op->q, op->old2new, G + (long long)k * d,
-                         d);
-    }
+  return holdout_rows(op, W, nshift, ho_idx, ho_y, n_ho, loss, G, static_cast<hipStream_t>(stream));
+}
+
+int fsda_holdout_batch(fsda_op* op, int ntarget, const double* W, int nshift, const int32_t* ho_idx,
+                       const double* ho_y, const int64_t* ho_off, double* loss, double* G, void* stream) {
+  if (!op || !W || !ho_idx || !ho_y || !ho_off || !loss) return fail(FSDA_E_ARG, "NULL argument");
+  if (ntarget < 1 || ntarget > FSDA_MAX_TARGETS) return fail(FSDA_E_ARG, "ntarget outside 1..FSDA_MAX_TARGETS");
+  if (nshift < 1 || nshift > FSDA_MAX_SHIFTS) return fail(FSDA_E_ARG, "nshift outside 1..FSDA_MAX_SHIFTS");
+  if (ho_off[0] != 0) return fail(FSDA_E_ARG, "ho_off[0] must be 0");
+  for (int c = 0; c < ntarget; c++)
+    if (ho_off[c + 1] - ho_off[c] < 1 || ho_off[c + 1] - ho_off[c] > op->pb.n)
+      return fail(FSDA_E_ARG, "target " + std::to_string(c) + ": need 1 <= held-out count <= n");
+  const long long d = op->pb.d;
+  for (int c = 0; c < ntarget; c++) {
+    const size_t w0 = (size_t)c * nshift;
+    const int rc = holdout_rows(op, W + w0 * d, nshift, ho_idx + ho_off[c], ho_y + ho_off[c],
+                                ho_off[c + 1] - ho_off[c], loss + w0, G ? G + w0 * d : nullptr,
+                                static_cast<hipStream_t>(stream));
+    if (rc) return fail(rc, "target " + std::to_string(c) + ": " + g_err);
   }
-  HIP_TRY(hipGetLastError());
-  std::vector<double> hs(nshift);
-  HIP_TRY(hipMemcpyAsync(hs.data(), sums, sizeof(double) * nshift, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  for (int k = 0; k < nshift; k++) loss[k] = 0.5 * hs[k] / (double)n_ho;
   return FSDA_OK;
 }
 
@@ -2209,42 +2372,89 @@ int fsda_hypergradient(fsda_op* op, const double* W, const double* Lambda, const
                        double* dlogbeta, double* dalpha, void* stream) {
   if (!op || !W || !Lambda || !betas || !dlogbeta || !dalpha) return fail(FSDA_E_ARG, "NULL argument");
   if (nshift < 1 || nshift > FSDA_MAX_SHIFTS) return fail(FSDA_E_ARG, "nshift outside 1..FSDA_MAX_SHIFTS");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const long long n = op->pb.n, d = op->pb.d;
-  double* sums = op->hist + 64;  // per shift: <l, w>, <X l, L X w>, sum w (X l)(X w), sum w X l, sum w X w
-  const int gd = grid_for(d, GRID_STREAM), gn = grid_for(n, GRID_STREAM);
-  double* pA = op->part + SITE_R * NPART;
-  double* pB = op->part + SITE_PP * NPART;
-  double* pC = op->part + SITE_TU * NPART;
-  double* pL = op->part + SITE_XT * NPART;
-  for (int k = 0; k < nshift; k++) {
-    const double* w = W + (long long)k * d;
-    const double* l = Lambda + (long long)k * d;
-    double* out = sums + 5 * k;
-    hipLaunchKernelGGL(k_dot, dim3(gd), dim3(BS), 0, s, l, w, d, pA);
-    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pA, gd, out + 0);
-    run_rows(op, op->px_user, w, EpiX<double, false>{op->t, nullptr}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
-    run_rows(op, op->px_user, l, EpiX<double, false>{op->u, nullptr}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
-    run_rows(op, op->ps, op->t, EpiLapDot{op->t, op->u, op->pb.s_rowptr}, pL, 0, s, KC_OTHER);
-    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pL, op->ps.grid, out + 1);
-    hipLaunchKernelGGL(k_labdots, dim3(gn), dim3(BS), 0, s, op->labw, op->u, op->t, n, pA, pB, pC);
-    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pA, gn, out + 2);
-    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pB, gn, out + 3);
-    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, pC, gn, out + 4);
-  }
-  HIP_TRY(hipGetLastError());
-  std::vector<double> hs(5 * nshift);
-  HIP_TRY(hipMemcpyAsync(hs.data(), sums, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  const double l = (double)op->pb.n_lab;
-  for (int k = 0; k < nshift; k++) {
-    const double* o = hs.data() + 5 * k;
-    dlogbeta[k] = -betas[k] * o[0];
-    // <X l, (P_l - 1_l 1_l^T / l) X w> = l (sum w a b - (sum w a)(sum w b)) with w = 1/l on labeled rows
-    const double lab = l * (o[2] - o[3] * o[4]);
-    dalpha[k] = -(o[1] - lab);
+  return hypergradient_rows(op, W, Lambda, betas, nshift, nullptr, -1, -1, dlogbeta, dalpha,
+                            static_cast<hipStream_t>(stream));
+}
+
+int fsda_hypergradient_batch(fsda_op* op, int ntarget, const int32_t* lab_idx, const int8_t* lab_y,
+                             const int64_t* lab_off, const double* W, const double* Lambda, const double* betas,
+                             int nshift, double* dlogbeta, double* dalpha, void* stream) {
+  if (!op || !lab_idx || !lab_y || !lab_off || !W || !Lambda || !betas || !dlogbeta || !dalpha)
+    return fail(FSDA_E_ARG, "NULL argument");
+  if (ntarget < 1 || ntarget > FSDA_MAX_TARGETS) return fail(FSDA_E_ARG, "ntarget outside 1..FSDA_MAX_TARGETS");
+  if (nshift < 1 || nshift > FSDA_MAX_SHIFTS) return fail(FSDA_E_ARG, "nshift outside 1..FSDA_MAX_SHIFTS");
+  if (lab_off[0] != 0) return fail(FSDA_E_ARG, "lab_off[0] must be 0");
+  for (int c = 0; c < ntarget; c++)
+    if (lab_off[c + 1] - lab_off[c] < 2 || lab_off[c + 1] - lab_off[c] > op->pb.n)
+      return fail(FSDA_E_LABELS, "target " + std::to_string(c) + ": need 2 <= labeled count <= n");
+  const long long d = op->pb.d;
+  for (int c = 0; c < ntarget; c++) {
+    const size_t w0 = (size_t)c * nshift;
+    const int rc = hypergradient_rows(op, W + w0 * d, Lambda + w0 * d, betas, nshift, lab_idx, lab_off[c],
+                                      lab_off[c + 1], dlogbeta + w0, dalpha + w0, static_cast<hipStream_t>(stream));
+    if (rc) return rc;
   }
   return FSDA_OK;
+}
+
+int fsda_columns_batch_workspace_size(const fsda_op* op, int ntarget, int nshift, size_t* bytes) {
+  if (!op || !bytes) return fail(FSDA_E_ARG, "NULL argument");
+  if (ntarget < 1 || ntarget > FSDA_MAX_TARGETS) return fail(FSDA_E_ARG, "ntarget outside 1..FSDA_MAX_TARGETS");
+  if (nshift < 1 || nshift > FSDA_MAX_SHIFTS) return fail(FSDA_E_ARG, "nshift outside 1..FSDA_MAX_SHIFTS");
+  const int T = batch_tile(std::min(ntarget * nshift, COLUMN_TILE));
+  CLayout L;
+  clayout(op, T, T, true, &L);
+  *bytes = L.total;
+  return FSDA_OK;
+}
+
+int fsda_solve_columns_batch(fsda_op* op, int ntarget, const int32_t* lab_idx, const int8_t* lab_y,
+                             const int64_t* lab_off, const double* betas, int nshift, const double* B, double rtol,
+                             int maxit, void* workspace, size_t ws_bytes, double* X, int* iters, double* relres,
+                             void* stream) {
+  if (!op || !lab_idx || !lab_y || !lab_off || !betas || !B || !X || !iters || !relres)
+    return fail(FSDA_E_ARG, "NULL argument");
+  size_t need = 0;
+  int rc = fsda_columns_batch_workspace_size(op, ntarget, nshift, &need);
+  if (rc) return rc;
+  if (!(rtol > 0.0)) return fail(FSDA_E_RANGE, "rtol must be > 0");
+  if (maxit < 1) return fail(FSDA_E_RANGE, "maxit must be >= 1");
+  for (int k = 0; k < nshift; k++)
+    if (!(betas[k] > 0.0) || !std::isfinite(betas[k])) return fail(FSDA_E_RANGE, "every beta must be finite and > 0");
+  if (lab_off[0] != 0) return fail(FSDA_E_ARG, "lab_off[0] must be 0");
+  for (int c = 0; c < ntarget; c++)
+    if (lab_off[c + 1] - lab_off[c] < 2 || lab_off[c + 1] - lab_off[c] > op->pb.n)
+      return fail(FSDA_E_LABELS, "target " + std::to_string(c) + ": need 2 <= labeled count <= n");
+  if (!workspace || ws_bytes < need)
+    return fail(FSDA_E_WORKSPACE, "workspace NULL or smaller than fsda_columns_batch_workspace_size()");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(FSDA_E_WORKSPACE, "workspace not 256-byte aligned");
+  // columns (target c, shift s), row c * nshift + s of B and X, taken shift by
+  // shift (all targets of one shift, then the next) in tiles of T one after
+  // the other: a tile's columns then need similar iteration counts (small
+  // shifts need the most), and every tile stops when its slowest column does.
+  // The status is the worst over the tiles.
+  const int ncol = ntarget * nshift;
+  const int T = batch_tile(std::min(ncol, COLUMN_TILE));
+  CLayout L;
+  clayout(op, T, T, true, &L);
+  std::vector<int> tgt(T), gcol(T);
+  std::vector<double> sig(T);
+  int status = FSDA_OK;
+  for (int j0 = 0; j0 < ncol; j0 += T) {
+    const int nc = std::min(T, ncol - j0);
+    for (int c = 0; c < nc; c++) {
+      const int j = j0 + c, sh = j / ntarget, tg = j % ntarget;
+      tgt[c] = tg;
+      gcol[c] = tg * nshift + sh;
+      sig[c] = betas[sh];
+    }
+    const ColTargets ct{lab_idx, lab_y, lab_off, tgt.data(), gcol.data()};
+    rc = columns_any(T, op, static_cast<char*>(workspace), L, B, sig.data(), nc, rtol, maxit, X, iters, relres,
+                     static_cast<hipStream_t>(stream), &ct);
+    if (rc < 0) return rc;
+    status = std::max(status, rc);
+  }
+  return status;
 }
 
 int fsda_batch_workspace_size(const fsda_op* op, int ntarget, int nshift, int chunk, size_t* bytes) {

@@ -544,6 +544,23 @@ __global__ __launch_bounds__(BS) void k_labdots(const double* __restrict__ w, co
   write_partial(p2, blockIdx.x, s2);
 }
 
+// partials of sum a_i b_i, sum a_i, sum b_i over the samples i = idx[k],
+// k in [k0, k1) (one target's labeled set)
+__global__ __launch_bounds__(BS) void k_idxdots(const int* __restrict__ idx, long long k0, long long k1,
+                                                const double* __restrict__ a, const double* __restrict__ b,
+                                                double* p0, double* p1, double* p2) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (long long k = k0 + (long long)blockIdx.x * BS + threadIdx.x; k < k1; k += (long long)gridDim.x * BS) {
+    const int i = idx[k];
+    s0 += a[i] * b[i];
+    s1 += a[i];
+    s2 += b[i];
+  }
+  write_partial(p0, blockIdx.x, s0);
+  write_partial(p1, blockIdx.x, s1);
+  write_partial(p2, blockIdx.x, s2);
+}
+
 // Rows of S over src = t_w: reduction <t_l, L t_w>, (L t_w)_r = d_r t_w,r - (S t_w)_r.
 struct EpiLapDot {
   using V = double;

@@ -216,6 +216,30 @@ def target_labels(pb, ntarget: int, seed: int, frac_median: float = 0.007, frac_
     return out
 
 
+def holdout_splits(targets, seed: int, frac_ho: float = 0.2):
+    """Splits each target's labeled set (``target_labels`` output) into a
+    training part and a held-out part of round(frac_ho l) rows (at least one),
+    keeping both classes in the training part.  Returns (train, heldout): lists
+    of (lab_idx int32, lab_y int8) and (ho_idx int32 sorted, ho_y float64 +-1)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 77]))
+    train, held = [], []
+    for li, ly in targets:
+        li, ly = np.asarray(li), np.asarray(ly)
+        l = li.size
+        nho = min(max(1, int(round(frac_ho * l))), l - 2)
+        for _ in range(100):
+            perm = rng.permutation(l)
+            tr, ho = np.sort(perm[nho:]), np.sort(perm[:nho])
+            if (ly[tr] > 0).any() and (ly[tr] < 0).any():
+                break
+        else:  # pragma: no cover - a labeled set with one example of a class
+            raise ValueError("cannot keep both classes in the training part")
+        train.append((li[tr].astype(np.int32), ly[tr].astype(np.int8)))
+        o = np.argsort(li[ho], kind="stable")
+        held.append((li[ho][o].astype(np.int32), ly[ho][o].astype(np.float64)))
+    return train, held
+
+
 # ---------------------------------------------------------------------------
 # problems
 # ---------------------------------------------------------------------------
@@ -275,6 +299,11 @@ RECIPES = {
                   alpha=1.0, betas=tuple(np.logspace(-3, 2, 16)), rtol=1e-8),
     "large": Recipe(n=1_500_000, d=4_000_000, mean_nnz=70, zipf_s=1.2, lab_frac=0.01, pos_frac=0.05, k=10,
                     alpha=1.0, betas=tuple(np.logspace(-4, 2, 32)), rtol=1e-8),
+    # the differentiation workload: 64 targets (labeled sets drawn by
+    # target_labels, each split 80/20 by holdout_splits) over this X and graph;
+    # alpha inside (0, 1) so that the alpha-derivative has both sides
+    "diff": Recipe(n=500_000, d=2_000_000, mean_nnz=60, zipf_s=1.1, lab_frac=0.007, pos_frac=0.1, k=10,
+                   alpha=0.9, betas=tuple(np.logspace(-3, 2, 8)), rtol=1e-8),
     # the shape of the ChEMBL matrix of the shifted-CG timing table (regression
     # phase only, so no graph): 167,668 x 291,714 with about 12.2 million nonzeros
     "chembl": Recipe(n=167_668, d=291_714, mean_nnz=72.8, zipf_s=1.1, lab_frac=0.01, pos_frac=0.2, k=0,

@@ -108,4 +108,15 @@ def test_null_handle_calls_fail_cleanly():
                                          betas.ctypes.data, 1, 1e-8, 10, 0, ctypes.c_void_p(256), 1 << 20,
                                          ctypes.c_void_p(8), it.ctypes.data, rr.ctypes.data, None) == fsda.E_ARG
     assert b"NULL" in L.fsda_last_error()
+    assert L.fsda_columns_batch_workspace_size(None, 2, 2, ctypes.byref(size)) == fsda.E_ARG
+    assert L.fsda_solve_columns_batch(None, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), off.ctypes.data,
+                                      betas.ctypes.data, 1, ctypes.c_void_p(8), 1e-8, 10, ctypes.c_void_p(256),
+                                      1 << 20, ctypes.c_void_p(8), it.ctypes.data, rr.ctypes.data, None) == fsda.E_ARG
+    loss = np.zeros(1)
+    assert L.fsda_holdout_batch(None, 1, ctypes.c_void_p(8), 1, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                                off.ctypes.data, loss.ctypes.data, None, None) == fsda.E_ARG
+    g = np.zeros(1)
+    assert L.fsda_hypergradient_batch(None, 1, ctypes.c_void_p(8), ctypes.c_void_p(8), off.ctypes.data,
+                                      ctypes.c_void_p(8), ctypes.c_void_p(8), betas.ctypes.data, 1, g.ctypes.data,
+                                      g.ctypes.data, None) == fsda.E_ARG
     L.fsda_destroy_operator(None)
