@@ -311,6 +311,24 @@ int fsda_solve_columns(fsda_op *op, const double *B, const double *sigmas, int n
                        void *workspace, size_t ws_bytes, double *X, int *iters, double *relres, void *stream);
 
 /*
+ * fsda_solve_columns without a workspace argument, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * hosts that forbid allocation): the same solve and results, with its scratch
+ * in a static device array of FSDA_STATIC_SCRATCH_BYTES that the library holds
+ * on every GPU it is loaded on until the process ends.  The call allocates
+ * nothing (no device allocation, no graph instantiation: its kernels are
+ * launched directly).  Arguments and outputs as fsda_solve_columns.
+ * Scratch needed: fsda_columns_workspace_size(); a solve that needs more is
+ * rejected with FSDA_E_WORKSPACE before any HIP call.  All calls on one GPU
+ * share that GPU's scratch: calls that overlap in time on one GPU (two
+ * streams, two threads, two handles) race and give wrong results.  Blocks
+ * until done.
+ */
+#define FSDA_STATIC_SCRATCH_BYTES (64u << 20)
+int fsda_solve_columns_static(fsda_op *op, const double *B, const double *sigmas, int ncol, double rtol, int maxit,
+                              double *X, int *iters, double *relres, void *stream);
+
+/*
  * Hold-out loss of the ratings (Alg. 7, return value) for selecting beta and
  * alpha:  H_s = 1/2 ||X_ho w_s - y_ho||^2 / n_ho for every row w_s of W.
  *  W[nshift][d]  device, caller's feature order (e.g. from fsda_multishift_solve).

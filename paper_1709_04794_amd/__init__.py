@@ -28,6 +28,7 @@ OK, NOT_CONVERGED = 0, 1
 E_ARG, E_CSR, E_LABELS, E_RANGE, E_BREAKDOWN, E_WORKSPACE, E_HIP, E_OVERFLOW = -1, -2, -3, -4, -5, -6, -7, -8
 FP64, MIXED = 0, 1
 MAX_SHIFTS, MAX_CHUNK, MAX_TARGETS, MAX_BATCH_CHUNK = 64, 256, 64, 128
+STATIC_SCRATCH_BYTES = 64 << 20  # FSDA_STATIC_SCRATCH_BYTES
 # kernel classes for fsda_time_kernel
 K_X, K_S, K_XT, K_XTL, K_RESID, K_PUPD, K_FOLD = 0, 1, 2, 3, 4, 5, 6
 # ... and of the batched FP32 correction solves of the mixed path
@@ -79,6 +80,7 @@ def lib():
         L.fsda_hypergradient.argtypes = [P, P, P, P, I, P, P, P]
         L.fsda_batch_workspace_size.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_size_t)]
         L.fsda_multishift_solve_batch.argtypes = [P, I, P, P, P, P, I, D, I, I, P, ctypes.c_size_t, P, P, P, P]
+        L.fsda_solve_columns_static.argtypes = [P, P, P, I, D, I, P, P, P, P]
         L.fsda_holdout_batch.argtypes = [P, I, P, I, P, P, P, P, P, P]
         L.fsda_columns_batch_workspace_size.argtypes = [P, I, I, ctypes.POINTER(ctypes.c_size_t)]
         L.fsda_solve_columns_batch.argtypes = [P, I, P, P, P, P, I, P, D, I, P, ctypes.c_size_t, P, P, P, P]
@@ -98,7 +100,7 @@ def lib():
                   L.fsda_columns_workspace_size, L.fsda_solve_columns, L.fsda_holdout, L.fsda_hypergradient,
                   L.fsda_gather_sum, L.fsda_set_batch_tile, L.fsda_get_batch_tile, L.fsda_batch_autotune,
                   L.fsda_holdout_batch, L.fsda_columns_batch_workspace_size, L.fsda_solve_columns_batch,
-                  L.fsda_hypergradient_batch):
+                  L.fsda_hypergradient_batch, L.fsda_solve_columns_static):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -292,6 +294,22 @@ class Operator:
                                              int(maxit), ctypes.c_void_p(ws), ctypes.c_size_t(int(size.value)),
                                              _ptr(X), iters.ctypes.data_as(ctypes.c_void_p),
                                              relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return X, iters, relres, rc
+
+    def solve_columns_static(self, B, sigmas: Sequence[float], rtol: float, maxit: int = 100000, stream=None):
+        """solve_columns with the library's static scratch instead of a workspace
+        (fsda_solve_columns_static; allocates nothing but the outputs made here)."""
+        import torch
+        B = B.contiguous()
+        sig = np.ascontiguousarray(sigmas, dtype=np.float64)
+        K = sig.size
+        X = torch.empty((K, self.d), dtype=torch.float64, device=self.device)
+        iters = np.zeros(K, dtype=np.int32)
+        relres = np.zeros(K, dtype=np.float64)
+        rc = _check(lib().fsda_solve_columns_static(self.handle, _ptr(B), sig.ctypes.data_as(ctypes.c_void_p), K,
+                                                    float(rtol), int(maxit), _ptr(X),
+                                                    iters.ctypes.data_as(ctypes.c_void_p),
+                                                    relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
         return X, iters, relres, rc
 
     def holdout(self, W, ho_idx, ho_y, gradient: bool = True, stream=None):

@@ -34,6 +34,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -43,6 +44,13 @@
 #include "targets.h"
 
 using namespace fsda;
+
+// Scratch of fsda_solve_columns_static, for callers that cannot allocate: one
+// copy per GPU the library is loaded on, held until the process ends.  Host
+// code never passes this name to a kernel (on the host it is a stand-in, not a
+// device address): it takes the device address of each GPU's copy from
+// hipGetSymbolAddress (scratch_ptr below) and passes that.
+static __device__ __align__(256) unsigned char scratch[FSDA_STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -343,6 +351,7 @@ struct fsda_op {
   TState* htst;  // pinned host mirror
   BState* bst;
   BState* hbst;  // pinned host mirror
+  void* scratch_dev;  // device address of the static scratch on the handle's GPU
 };
 
 namespace {
@@ -1866,6 +1875,25 @@ int hypergradient_rows(fsda_op* op, const double* W, const double* Lambda, const
   }
   return FSDA_OK;
 }
+
+// Device address of the static scratch on the current GPU, looked up once per
+// GPU (each holds its own copy at its own address) and kept.
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;
+
+int scratch_ptr(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return FSDA_OK;
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1946,6 +1974,7 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
     op->htst = nullptr;
     return bail(fail(FSDA_E_HIP, "hipHostMalloc of the target-batch status mirror failed"));
   }
+  if ((rc = scratch_ptr(&op->scratch_dev))) return bail(rc);  // this GPU's copy of the static scratch
   const Layout& L = op->L;
   op->st = at<State>(op, L.st);
   op->bst = pb->precision == FSDA_MIXED ? at<BState>(op, L.bst) : nullptr;
@@ -2338,6 +2367,30 @@ int fsda_solve_columns(fsda_op* op, const double* B, const double* sigmas, int n
   clayout(op, T, ncol, false, &L);
   return columns_any(T, op, static_cast<char*>(workspace), L, B, sigmas, ncol, rtol, maxit, X, iters, relres,
                      static_cast<hipStream_t>(stream));
+}
+
+int fsda_solve_columns_static(fsda_op* op, const double* B, const double* sigmas, int ncol, double rtol, int maxit,
+                              double* X, int* iters, double* relres, void* stream) {
+  if (!op || !B || !sigmas || !X || !iters || !relres) return fail(FSDA_E_ARG, "NULL argument");
+  size_t need = 0;
+  int rc = fsda_columns_workspace_size(op, ncol, &need);
+  if (rc) return rc;
+  if (!(rtol > 0.0)) return fail(FSDA_E_RANGE, "rtol must be > 0");
+  if (maxit < 1) return fail(FSDA_E_RANGE, "maxit must be >= 1");
+  for (int c = 0; c < ncol; c++)
+    if (!(sigmas[c] > 0.0) || !std::isfinite(sigmas[c])) return fail(FSDA_E_RANGE, "every shift must be finite and > 0");
+  if (need > (size_t)FSDA_STATIC_SCRATCH_BYTES)
+    return fail(FSDA_E_WORKSPACE, "this solve needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                                      std::to_string((size_t)FSDA_STATIC_SCRATCH_BYTES) + " (use fsda_solve_columns)");
+  if (!op->scratch_dev) return fail(FSDA_E_HIP, "static scratch address unknown");
+  const int T = batch_tile(ncol);
+  CLayout L;
+  clayout(op, T, ncol, false, &L);
+  // the same kernels as fsda_solve_columns, launched directly (a graph would
+  // be instantiated, which allocates); every scratch buffer is written before
+  // it is read, so nothing needs clearing between calls
+  return columns_any(T, op, static_cast<char*>(op->scratch_dev), L, B, sigmas, ncol, rtol, maxit, X, iters, relres,
+                     static_cast<hipStream_t>(stream), nullptr, false);
 }
 
 int fsda_holdout(fsda_op* op, const double* W, int nshift, const int32_t* ho_idx, const double* ho_y, int64_t n_ho,
