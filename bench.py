@@ -1,17 +1,23 @@
 """Benchmark: shifted SDA solves per second on one MI355X.
 
-A step is one pass of the whole hot path over the workload: the right-hand
-side (Alg. 7, step 4), the multi-shift solve of every shift to relative
-residual 1e-8 with the FP64 true-residual check, and the ratings s = X w of
-every shift.  The operator build (X^T, tiles, labels) happens once before the
-timed region, as does input generation.  Prints one JSON line.
+Default run (the many-targets workload): a step is one call of
+fsda_multishift_solve_batch on 64 binary targets over the mid-scale X and kNN
+graph (200,000 x 1,000,000, 16 shifts each): per target its right-hand side,
+its shifted CG over all 16 shifts (FP64) and the FP64 true residual of every
+(target, shift).  Successive steps take the next 64 of 1000 targets (labeled
+fraction lognormal around 0.7 %, positive rate U(0.02, 0.3)).  The value is
+(target, shift) solves whose true relative residual is <= 1e-8, per second.
+Beside it: the plain per-target FP64 path on the same X (one labeled set, one
+multi-shift solve), and the roofline of the operator apply measured on the
+large workload (1.5e6 x 4e6, 1.05e8 nonzeros; its vectors outgrow the
+Infinity Cache), every launch of each apply kernel bracketed by HIP events.
+Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload mid] [--chunk 128]
+    python bench.py [--steps K] [--warmup W]
+    python bench.py --workload mid|large|tiny   # the single-target path of one workload
 
-The default run also times, once each and outside the headline, the other
-entry points on the same workload (detail.paths): the mixed-precision solve,
-a batch of 16 targets, and the sample-space solve.  A separate mode replays
-the paper's CG versus shifted CG table on a matrix of the ChEMBL shape:
+A separate mode replays the paper's CG versus shifted CG table on a matrix of
+the ChEMBL shape:
 
     python bench.py --experiment shifted-table
 """
@@ -36,39 +42,57 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-LSLICE, MAXLSLICE, SPLIT_ROW = 8192, 32, 64  # the X^T plans of the library (LDS slices, split rows)
+LSLICE, MAXLSLICE, SPLIT_ROW, LDS_HEAD = 8192, 32, 64, 2048  # the X^T plans of the library
 
 
 def xt_plan(pb):
-    """The X^T plan the library picks for this problem (and FSDA_XT_SLICES): ("lds",
-    slices), ("xcd", 8) or ("none", 1), with the split rows' count and nonzeros."""
+    """The X^T plan the library picks for this problem (and FSDA_XT_SLICES, FSDA_XT_HEAD):
+    a dict with the plan ("lds", "xcd", "hyb" or "none"), the LDS slice count, and the
+    rows of X^T in LDS slices and in XCD slices (counts and nonzeros)."""
     cnt = np.bincount(pb.x_col, minlength=pb.d)
-    nsplit, zsplit = int((cnt >= SPLIT_ROW).sum()), int(cnt[cnt >= SPLIT_ROW].sum())
     nl = -(-pb.n // LSLICE)
     env = os.environ.get("FSDA_XT_SLICES", "")
+    head = max(int(os.environ.get("FSDA_XT_HEAD", LDS_HEAD)), SPLIT_ROW)
     if env == "1":
-        return "none", 1, nsplit, zsplit
-    if env == "8" or nl > MAXLSLICE:
-        return ("xcd", 8, nsplit, zsplit) if env == "8" or 8 * pb.n > (2 << 20) else ("none", 1, nsplit, zsplit)
-    return "lds", nl, nsplit, zsplit
+        plan = "none"
+    elif env == "8":
+        plan = "xcd"
+    elif env == "hyb":
+        plan = "hyb"
+    elif nl <= MAXLSLICE:
+        plan = "lds"
+    else:
+        plan = "hyb" if 8 * pb.n > (2 << 20) else "none"
+    split = cnt >= SPLIT_ROW
+    lds = (cnt >= head) if plan == "hyb" else (split if plan == "lds" else np.zeros_like(split))
+    xcd = split & ~lds if plan in ("hyb", "xcd") else np.zeros_like(split)
+    lens = cnt[xcd]
+    xparts = int((8 * np.maximum(1, -(-(lens // 8) // 32768))).sum()) if lens.size else 0
+    return {"plan": plan, "nsl": nl if plan in ("lds", "hyb") else 0,
+            "n_lds": int(lds.sum()), "z_lds": int(cnt[lds].sum()), "n_xcd": int(xcd.sum()),
+            "z_xcd": int(cnt[xcd].sum()), "xcd_parts": xparts}
 
 
 def algorithmic_bytes(kernel: int, pb, nshift: int, chunk: int) -> float:
-    """Bytes one launch must move (every array once; gathered vectors counted once)."""
+    """Bytes one launch must move (every array once; gathered vectors counted once; int32 indices)."""
     import paper_1709_04794_amd as fsda
     n, d, z, g = pb.n, pb.d, pb.x_nnz, pb.s_nnz
     lab = 8 * n if pb.alpha < 1.0 else 0
-    plan, nsl, nsplit, zsplit = xt_plan(pb) if kernel in (fsda.K_XT, fsda.K_XTL) else ("none", 1, 0, 0)
-    if kernel == fsda.K_XTL:    # split rows' indices and slice bounds, u (staged once per slice), parts written
-        return 4 * zsplit + 4 * (nsl + 1) * nsplit + 8 * n + 8 * nsl * nsplit if plan == "lds" else 0.0
-    if kernel == fsda.K_XT and plan == "lds":  # short rows' indices, u, p and r in, r out, parts read
-        return 4 * (d + 1) + 4 * (z - zsplit) + 8 * n + 24 * d + 8 * nsl * nsplit
+    pl = xt_plan(pb) if kernel in (fsda.K_XT, fsda.K_XTL, fsda.K_ASM) else None
+    if kernel == fsda.K_XTL:    # LDS rows' indices and slice bounds, u (staged once per slice), parts written
+        nsl, nr = pl["nsl"], pl["n_lds"]
+        return float(4 * pl["z_lds"] + 4 * (nsl + 1) * nr + 8 * n + 8 * nsl * nr) if nr else 0.0
+    if kernel == fsda.K_XT:     # the other rows' indices, u; p and r in, r out but for the XCD-split rows;
+        # LDS parts read, XCD parts written
+        return float(4 * (d + 1) + 4 * (z - pl["z_lds"]) + 8 * n + 24 * (d - pl["n_xcd"])
+                     + 8 * pl["nsl"] * pl["n_lds"] + 8 * pl["xcd_parts"])
+    if kernel == fsda.K_ASM:    # XCD slices: the split rows' parts in, then p and r in, r out per row
+        nx = pl["n_xcd"]
+        return float(8 * pl["xcd_parts"] + 4 * (nx + 1) + 24 * nx) if nx else 0.0
     if kernel == fsda.K_X:      # rowptr, col, p (gathered), t written
         return 4 * (n + 1) + 4 * z + 8 * d + 8 * n + lab
     if kernel == fsda.K_S:      # rowptr, col, t (gathered), u written
         return 4 * (n + 1) + 4 * g + 8 * n + 8 * n + lab
-    if kernel == fsda.K_XT:     # rowptr, col, u (gathered), p and r read, r_{i+1} written
-        return 4 * (d + 1) + 4 * z + 8 * n + 24 * d
     if kernel == fsda.K_RESID:  # not launched by the feature-space solve
         return 0.0
     if kernel == fsda.K_PUPD:   # r_{i+1}, p in; p out (the long rows' chunk sums aside)
@@ -78,7 +102,7 @@ def algorithmic_bytes(kernel: int, pb, nshift: int, chunk: int) -> float:
     return 0.0
 
 
-TRAFFIC_KEYS = {2: "k_xt", 3: "k_xt_lds", 0: "k_rows_x", 6: "k_fold"}
+TRAFFIC_KEYS = {2: "k_xt", 3: "k_xt_lds", 0: "k_rows_x", 6: "k_fold", 1: "k_rows_s", 13: "k_assemble"}
 
 
 def kernel_source_key() -> str:
@@ -113,7 +137,26 @@ def measured_traffic(kernel: int, workload: str):
 KNAMES = {0: "k_rows<EpiX> (t = X p)", 1: "k_rows<EpiLap> (u = M' t)",
           2: "k_xt<EpiXTR> (q = X^T u + s p, r -= a q)", 3: "k_xt_lds (X^T split rows from LDS slices)",
           4: "k_resid (sample space)",
-          5: "k_pupdate (long rows of X^T, p update, shift scalars)", 6: "k_fold"}
+          5: "k_pupdate (long rows of X^T, p update, shift scalars)", 6: "k_fold",
+          13: "k_assemble<EpiXTR> (X^T split rows from their XCD-slice parts, r -= a q)"}
+APPLY_CLASSES = (0, 1, 2, 3, 13)  # the kernels of one operator apply (X, graph, X^T and its parts)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
 
 
 def cpu_baseline(pb, budget_s: float):
@@ -437,26 +480,42 @@ def shifted_table(args, fsda, torch):
                       "rows": rows}), flush=True)
 
 
-def summarize_rocprof(d: str, kernel_substr: str, calib_mib: int) -> str:
-    """Condenses rocprofv3 CSV output in directory d into a few lines of text.
-
-    kernel_stats.csv: the --stats table (durations).  counter_collection.csv:
-    per-dispatch counters, averaged per kernel (first 90 chars of the name);
-    for the calibration copy the dispatches whose FETCH/WRITE is at least half
-    of the largest are averaged (the plain copy of calib_mib MiB).
-    """
+def _rocpd_tables(d: str, pattern: str):
+    """(kernel stats, per-dispatch counters) as pandas frames from rocprofv3 output in directory d:
+    its SQLite database (*_results.db, the default format) or its CSV files."""
     import glob
+    import sqlite3
     import pandas as pd
-    lines = []
+    stats, counters = [], []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True)):
+        c = sqlite3.connect(f)
+        stats.append(pd.read_sql_query("select name as Name, total_calls as Calls, total_duration as TotalDurationNs, "
+                                       "average as AverageNs, percentage as Percentage from top_kernels", c))
+        counters.append(pd.read_sql_query("select kernel_name as Kernel_Name, counter_name as Counter_Name, "
+                                          "value as Counter_Value from counters_collection", c))
+        c.close()
     for f in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
-        df = pd.read_csv(f)
-        df["Name"] = df["Name"].str.slice(0, 90)
-        lines.append("kernel stats (%s):" % os.path.basename(f))
-        lines.append(df[["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"]].head(20).to_string())
+        stats.append(pd.read_csv(f))
     for f in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
-        df = pd.read_csv(f)
-        df["Kernel_Name"] = df["Kernel_Name"].str.slice(0, 90)
-        for cname, g in df.groupby("Counter_Name"):
+        counters.append(pd.read_csv(f))
+    cat = lambda fs: pd.concat(fs, ignore_index=True) if fs else None  # noqa: E731
+    return cat(stats), cat(counters)
+
+
+def summarize_rocprof(d: str, kernel_substr: str, calib_mib: int) -> str:
+    """Condenses rocprofv3 output in directory d into a few lines of text: the
+    kernel statistics (durations) and the per-dispatch counters averaged per kernel
+    (first 90 characters of the name); for the calibration copy the dispatches whose
+    count is at least half of the largest are averaged (the plain copy of calib_mib MiB)."""
+    lines = []
+    stats, counters = _rocpd_tables(d, "")
+    if stats is not None and len(stats):
+        stats["Name"] = stats["Name"].str.slice(0, 90)
+        lines.append("kernel statistics (durations in ns):")
+        lines.append(stats[["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"]].head(20).to_string())
+    if counters is not None and len(counters):
+        counters["Kernel_Name"] = counters["Kernel_Name"].str.slice(0, 90)
+        for cname, g in counters.groupby("Counter_Name"):
             agg = g.groupby("Kernel_Name")["Counter_Value"].agg(["count", "mean"]).sort_values("mean",
                                                                                            ascending=False)
             lines.append("counter %s (mean per dispatch):" % cname)
@@ -471,7 +530,8 @@ def summarize_rocprof(d: str, kernel_substr: str, calib_mib: int) -> str:
 
 
 TRAFFIC_MATCH = {"k_xt": "k_xt<fsda::EpiXTR<double>", "k_xt_lds": "k_xt_lds<double>",
-                 "k_rows_x": "k_rows<fsda::EpiX<double, false>", "k_fold": "k_fold_apply<double>"}
+                 "k_rows_x": "k_rows<fsda::EpiX<double, false>", "k_fold": "k_fold_apply<double>",
+                 "k_rows_s": "k_rows<fsda::EpiLap<double, false>", "k_assemble": "k_assemble<fsda::EpiXTR<double>"}
 
 
 def traffic_lines(dfetch: str, dwrite: str, calib_mib: int, workload: str) -> str:
@@ -479,13 +539,10 @@ def traffic_lines(dfetch: str, dwrite: str, calib_mib: int, workload: str) -> st
 
     Each counter is calibrated on the plain device copy of calib_mib MiB recorded in
     the same run (its per-dispatch value against the bytes it must read or write)."""
-    import glob
-    import pandas as pd
     sha = kernel_source_key()
     per = {}
     for d, cname in ((dfetch, "FETCH_SIZE"), (dwrite, "WRITE_SIZE")):
-        f = sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True))[0]
-        df = pd.read_csv(f)
+        _, df = _rocpd_tables(d, "")
         g = df[df["Counter_Name"] == cname]
         cp = g[g["Kernel_Name"].str.lower().str.contains("copy")]
         big = cp[cp["Counter_Value"] >= 0.5 * cp["Counter_Value"].max()]
@@ -520,9 +577,13 @@ def main():
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 8 batched, 10 single-target)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 1 batched, 2 single)")
+    ap.add_argument("--workload", default="batched",
+                    help="'batched' (default): many targets over the mid-scale X, roofline on large; or one "
+                         "workload's single-target path: mid, large, tiny, diff")
+    ap.add_argument("--roof-iters", type=int, default=128,
+                    help="iterations per timed solve of the large-workload roofline (one launch per class each)")
     ap.add_argument("--chunk", type=int, default=128)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -545,7 +606,8 @@ def main():
                     help="batched-targets experiment: also solve this many targets, in calls of 64")
     ap.add_argument("--experiment", default="",
                     help="'shifted-table': the CG versus shifted CG table instead; 'gather-ceiling': the rate of "
-                         "random gathers the sparse products are bound by; 'batched-targets': 16, 32 and 64 targets")
+                         "random gathers the sparse products are bound by; 'batched-targets': 16, 32 and 64 targets; "
+                         "'roofline-large': the operator-apply roofline on the large workload alone")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -555,6 +617,8 @@ def main():
     import synth
     import paper_1709_04794_amd as fsda
 
+    if args.experiment and args.workload == "batched":
+        args.workload = "mid"  # the experiments run on one workload's X
     if args.experiment == "shifted-table":
         shifted_table(args, fsda, torch)
         return
@@ -564,20 +628,46 @@ def main():
     if args.experiment == "batched-targets":
         batched_targets(args, fsda, torch)
         return
+    if args.experiment == "roofline-large":
+        if args.calib_copy_mb > 0:
+            calibration_copy(torch, args.calib_copy_mb)
+        roof, apply, gpu_iter, cpu_large = roofline_large(args, fsda, torch)
+        print(json.dumps({"experiment": "roofline-large", "roofline": roof, "operator_apply": apply,
+                          "large_iteration": gpu_iter, "cpu_large": cpu_large}), flush=True)
+        return
     if args.experiment:
         print("unknown experiment %r" % args.experiment, file=sys.stderr)
         sys.exit(2)
 
+    batched = args.workload == "batched"
+    if args.steps is None:
+        args.steps = 8 if batched else 10
+    if args.warmup is None:
+        args.warmup = 1 if batched else 2
+    if batched:
+        batched_bench(args, fsda, torch)
+        return
+    single_bench(args, fsda, torch)
+
+
+def calibration_copy(torch, mib: int):
+    """A plain device copy of `mib` MiB, three times (the reference of the profiler's byte counters)."""
+    nb = mib << 20
+    a = torch.empty(nb // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    log("calibration copy: %d MiB read + %d MiB written per launch, 3 launches" % (mib, mib))
+
+
+def single_bench(args, fsda, torch):
+    """The single-target path of one workload: a step is the right-hand side, the
+    multi-shift solve of every shift with the FP64 true-residual check, and the
+    ratings s = X w."""
+    import synth
     if args.calib_copy_mb > 0:
-        nb = args.calib_copy_mb << 20
-        a = torch.empty(nb // 8, dtype=torch.float64, device="cuda").fill_(1.0)
-        c = torch.empty_like(a)
-        for _ in range(3):
-            c.copy_(a)
-        torch.cuda.synchronize()
-        log("calibration copy: %d MiB read + %d MiB written per launch, 3 launches" % (args.calib_copy_mb,
-                                                                                     args.calib_copy_mb))
-        del a, c
+        calibration_copy(torch, args.calib_copy_mb)
 
     t0 = time.perf_counter()
     pb = synth.workload(args.workload, seed=args.seed, cache_dir=args.cache)
@@ -672,7 +762,8 @@ def main():
     # the products are bound by random 8-byte gathers: time a bare gather kernel
     # on the dominant product's own index stream
     gather = None
-    pname = {fsda.K_XT: "xt_short" if xt_plan(pb)[0] == "lds" else "xt", fsda.K_X: "x_cold", fsda.K_S: "s"}.get(dom)
+    pname = {fsda.K_XT: "xt_short" if xt_plan(pb)["plan"] == "lds" else "xt", fsda.K_X: "x_cold",
+             fsda.K_S: "s"}.get(dom)
     if pname is not None and not args.no_gather_ceiling:
         _, idx, size = gather_patterns(pb)[pname]
         g_us = time_gathers(fsda, torch, size, idx, pair_us=pair_us)
@@ -681,6 +772,7 @@ def main():
                   "note": "time of a bare gather-and-add kernel over the same index stream / the kernel's "
                           "time (python bench.py --experiment gather-ceiling covers all three products)"}
     value = solved / elapsed
+    ws_mb = (8 * pb.x_nnz + 4 * pb.s_nnz + 40 * pb.n + 28 * pb.d) / 1e6
     out = {
         "metric": "shifted SDA solves/sec at rel. residual 1e-8",
         "value": round(value, 3),
@@ -699,7 +791,10 @@ def main():
                                                                 pb.lab_idx.size, pb.alpha, S, pb.rtol),
                    "n": pb.n, "d": pb.d, "nnz_x": pb.x_nnz, "nnz_s": pb.s_nnz, "shifts": S, "chunk": args.chunk,
                    "precision": "fp64"},
-        "roofline": {"bound": "hbm", "kernel": KNAMES[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "workload": pb.name,
+                     "memory": ("working set of one iteration %.0f MB fits the 256 MB Infinity Cache: these are cache "
+                                "rates, not HBM rates" % (ws_mb,)) if ws_mb < 256 else "HBM (working set %.0f MB)" % ws_mb,
+                     "kernel": KNAMES[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(dom, args.workload),
                      "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_launch_s * 1e6, 2),

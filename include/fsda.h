@@ -419,11 +419,12 @@ int fsda_project(fsda_op *op, const double *W, int nshift, double *S, void *stre
  * 3 = the LDS-slice part of the X^T product (k_xt_lds), 4 = residual update (sample-space solves), 5 =
  * direction update (feature space with X^T unsliced: also the residual update
  * of the rows of X^T longer than one chunk; with XCD slices those rows are
- * finished between classes 2 and 5, in no class), 6 = shift-state fold; the batched FP32 correction solves of FSDA_MIXED: 7 = X
+ * finished between classes 2 and 5, in class 13), 6 = shift-state fold; the batched FP32 correction solves of FSDA_MIXED: 7 = X
  * product, 8 = graph/centring product, 9 = X^T product, 10 = residual and
  * correction update, 11 = direction update; fsda_multishift_solve_batch: 7-9
  * its products, 10 = residual update, 11 = direction update, 12 = shift-state
- * fold.  While timing is on, solves launch kernels
+ * fold; 13 = the assembly of the X^T rows cut into XCD slices (their parts
+ * summed, then the residual update of those rows).  While timing is on, solves launch kernels
  * directly instead of replaying a graph.  Launches made after the recurrence
  * stopped (which return at once) are not counted.  fsda_kernel_time() returns
  * (host) the summed milliseconds and count of the timed launches since the

@@ -71,7 +71,7 @@ def _load():
         lib.orc_m_apply.argtypes = [pp, P, P]
         lib.orc_xct.argtypes = [pp, P, P]
         lib.orc_rhs.argtypes = [pp, P, P]
-        lib.orc_solve.argtypes = [pp, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P, P, P]
+        lib.orc_solve.argtypes = [pp, P, ctypes.c_int, P, ctypes.c_double, ctypes.c_int, P, P, P, P]
         lib.orc_project.argtypes = [pp, P, ctypes.c_int, P]
         lib.orc_sa_rhs.argtypes = [pp, P, P]
         lib.orc_sa_apply.argtypes = [pp, ctypes.c_double, P, P]
@@ -179,9 +179,44 @@ def solve(pb, betas=None, rtol: float = 1e-12, maxit: int = 100000, b: np.ndarra
     iters = np.zeros(S, dtype=np.int32)
     relres = np.zeros(S)
     bb = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
-    rc = _load().orc_solve(bnd.ref, _p(bb), S, _p(betas), float(rtol), int(maxit), _p(W), _p(iters), _p(relres))
+    rc = _load().orc_solve(bnd.ref, _p(bb), S, _p(betas), float(rtol), int(maxit), _p(W), _p(iters), _p(relres),
+                           None)
     _check(rc, "solve")
     return W, iters, relres, rc
+
+
+def lanczos_condition(pb, betas=None, rtol: float = 1e-10, maxit: int = 20000, b: np.ndarray = None, alpha=None):
+    """kappa-hat per shift: the condition estimate of A(beta_s) from the CG run of
+    that shift (Sec. 3.2.1): CG's coefficients a_i, b_i define the Lanczos
+    tridiagonal T (diagonal 1/a_i + b_{i-1}/a_{i-1}, off-diagonal sqrt(b_i)/a_i),
+    whose extreme eigenvalues (Ritz values) approach those of A on the Krylov
+    space of b.  Returns (kappa [S], ritz_min [S], ritz_max [S], iters [S])."""
+    bnd = _Bound(pb, alpha)
+    betas = np.ascontiguousarray(pb.betas if betas is None else betas, dtype=np.float64)
+    S = betas.size
+    W = np.zeros((S, pb.d))
+    iters = np.zeros(S, dtype=np.int32)
+    relres = np.zeros(S)
+    rec = np.zeros((S, 2 * int(maxit)))
+    bb = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
+    rc = _load().orc_solve(bnd.ref, _p(bb), S, _p(betas), float(rtol), int(maxit), _p(W), _p(iters), _p(relres),
+                           _p(rec))
+    _check(rc, "solve")
+    kap, lo, hi = np.zeros(S), np.zeros(S), np.zeros(S)
+    for s in range(S):
+        k = int(iters[s])
+        a, bcoef = rec[s, 0:2 * k:2], rec[s, 1:2 * k:2]
+        if k == 0:
+            kap[s] = lo[s] = hi[s] = np.nan
+            continue
+        diag = 1.0 / a
+        diag[1:] += bcoef[:-1] / a[:-1]
+        off = np.sqrt(bcoef[:-1]) / a[:-1]
+        T = np.diag(diag) + np.diag(off, 1) + np.diag(off, -1)
+        ev = np.linalg.eigvalsh(T)
+        lo[s], hi[s] = ev[0], ev[-1]
+        kap[s] = ev[-1] / ev[0]
+    return kap, lo, hi, iters
 
 
 def project(pb, W: np.ndarray) -> np.ndarray:

@@ -300,7 +300,7 @@ typedef void (*apply_fn)(orc_ctx *, double, const double *, double *);
 /* Conjugate gradient (Alg. 2) on A(beta) w = b, w0 = 0, A = apply, vectors of length d.
  * Alg. 2 writes gamma = -<r,r>/<p,q>, w <- w - gamma p, r <- r + gamma q. */
 static int cg_ctx(orc_ctx *c, apply_fn apply, int64_t d, double beta, const double *b, double rtol, int maxit,
-                  double *w, double *r, double *p, double *q, int *iters_out, double *relres_out) {
+                  double *w, double *r, double *p, double *q, int *iters_out, double *relres_out, double *rec) {
   double bnorm = sqrt(dot(d, b, b));
   for (int64_t j = 0; j < d; j++) { w[j] = 0.0; r[j] = b[j]; p[j] = b[j]; }
   double rr = dot(d, r, r);
@@ -312,6 +312,7 @@ static int cg_ctx(orc_ctx *c, apply_fn apply, int64_t d, double beta, const doub
     double pq = dot(d, p, q);
     if (!(pq > 0.0) || !isfinite(pq)) { status = ORC_E_BREAKDOWN; break; }
     double gamma = -rr / pq;
+    if (rec) { rec[2 * it] = -gamma; rec[2 * it + 1] = 0.0; } /* step length of iteration it */
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < d; j++) {
       w[j] -= gamma * p[j];
@@ -321,6 +322,7 @@ static int cg_ctx(orc_ctx *c, apply_fn apply, int64_t d, double beta, const doub
     double rr_new = dot(d, r, r);
     if (sqrt(rr_new) <= tol) { status = ORC_OK; break; }
     double a = rr_new / rr;
+    if (rec) rec[2 * it - 1] = a; /* direction coefficient after iteration it - 1 */
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < d; j++) p[j] = r[j] + a * p[j];
     rr = rr_new;
@@ -334,9 +336,13 @@ static int cg_ctx(orc_ctx *c, apply_fn apply, int64_t d, double beta, const doub
 }
 
 /* Solve every shift independently.  b: [d] (NULL = canonical Xc^T y_c).
- * W: [nshift][d].  Returns the worst status (breakdown < 0 < not converged). */
+ * W: [nshift][d].  rec: NULL, or [nshift][2 maxit] receiving per iteration i the
+ * CG step length a_i = <r,r>/<p,A p> at 2i and the direction coefficient
+ * b_i = <r_{i+1},r_{i+1}>/<r_i,r_i> at 2i+1 (0 after the last iteration): the
+ * Lanczos coefficients of the run (Sec. 3.2.1).
+ * Returns the worst status (breakdown < 0 < not converged). */
 int orc_solve(const orc_problem *pb, const double *b, int nshift, const double *betas, double rtol, int maxit,
-              double *W, int *iters, double *relres) {
+              double *W, int *iters, double *relres, double *rec) {
   orc_ctx c;
   int rc = ctx_init(&c, pb);
   if (rc) return rc;
@@ -350,7 +356,8 @@ int orc_solve(const orc_problem *pb, const double *b, int nshift, const double *
   int worst = ORC_OK;
   for (int s = 0; s < nshift; s++) {
     if (!(betas[s] > 0.0)) { worst = ORC_E_ARG; break; }
-    int st = cg_ctx(&c, apply_ctx, d, betas[s], bb, rtol, maxit, W + (int64_t)s * d, r, p, q, iters + s, relres + s);
+    int st = cg_ctx(&c, apply_ctx, d, betas[s], bb, rtol, maxit, W + (int64_t)s * d, r, p, q, iters + s, relres + s,
+                    rec ? rec + (int64_t)s * 2 * maxit : NULL);
     if (st < 0) { worst = st; break; }
     if (st > worst) worst = st;
   }
@@ -426,7 +433,7 @@ int orc_sa_solve(const orc_problem *pb, const double *g, int nshift, const doubl
   for (int s = 0; s < nshift; s++) {
     if (!(betas[s] > 0.0)) { worst = ORC_E_ARG; break; }
     int st = cg_ctx(&c, sa_apply_ctx, n, betas[s], gg, rtol, maxit, Z + (int64_t)s * n, r, p, q, iters + s,
-                    relres + s);
+                    relres + s, NULL);
     if (st < 0) { worst = st; break; }
     if (st > worst) worst = st;
   }
@@ -462,7 +469,7 @@ int orc_reg_solve(const orc_problem *pb, const double *z, int nshift, const doub
   for (int s = 0; s < nshift; s++) {
     if (!(betas[s] > 0.0)) { worst = ORC_E_ARG; break; }
     int st = cg_ctx(&c, reg_apply_ctx, d, betas[s], b, rtol, maxit, W + (int64_t)s * d, r, p, q, iters + s,
-                    relres + s);
+                    relres + s, NULL);
     if (st < 0) { worst = st; break; }
     if (st > worst) worst = st;
   }

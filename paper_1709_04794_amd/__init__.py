@@ -35,6 +35,8 @@ K_X, K_S, K_XT, K_XTL, K_RESID, K_PUPD, K_FOLD = 0, 1, 2, 3, 4, 5, 6
 K_BX, K_BS, K_BXT, K_BRESID, K_BPUPD = 7, 8, 9, 10, 11
 # ... and the shift-state fold of fsda_multishift_solve_batch
 K_TFOLD = 12
+# ... and the assembly of the X^T rows cut into XCD slices (sample ranges per XCD)
+K_ASM = 13
 
 
 class FsdaError(RuntimeError):

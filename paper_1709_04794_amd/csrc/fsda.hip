@@ -398,6 +398,7 @@ enum {
   KC_BRESID = 10,
   KC_BPUPD = 11,
   KC_TFOLD = 12,
+  KC_ASM = 13,
   KC_OTHER = 99
 };
 
@@ -447,8 +448,10 @@ void run_xt(fsda_op* op, const typename Epi::V* src, Epi epi, int solve, bool as
     hipLaunchKernelGGL(k_xt<Epi>, dim3(pl.grid), dim3(BS), 0, s, pl.w, src, epi, op->st, part, solve);
   });
   if (assemble && pl.nlong > 0)
-    hipLaunchKernelGGL(k_assemble<Epi>, dim3(pl.gridL), dim3(BS), 0, s, pl.nlong, pl.row_chunk0, pl.w.lpart, epi,
-                       op->st, part, pl.grid, solve);
+    launch(op, cls == KC_XT ? KC_ASM : KC_OTHER, s, [&] {
+      hipLaunchKernelGGL(k_assemble<Epi>, dim3(pl.gridL), dim3(BS), 0, s, pl.nlong, pl.row_chunk0, pl.w.lpart, epi,
+                         op->st, part, pl.grid, solve);
+    });
 }
 
 int xt_npart(const fsda_op* op) { return op->pxt.grid + (op->pxt.nlong > 0 ? op->pxt.gridL : 0); }

@@ -182,12 +182,18 @@ def labels(n: int, x_rowptr: np.ndarray, x_col: np.ndarray, d: int, n_lab: int, 
     rng = np.random.default_rng(np.random.SeedSequence([seed, 77]))
     lab_idx = np.sort(rng.choice(n, size=n_lab, replace=False)).astype(np.int32)
     h = normal(d, seed, 11)
+    # scores of the labeled rows only: each row's values gathered contiguously,
+    # one reduction per row
     rp = x_rowptr.astype(np.int64)
-    score = np.zeros(n)
-    vals = h[x_col]
-    nz = rp[1:] > rp[:-1]
-    score[nz] = np.add.reduceat(vals, rp[:-1][nz]) if vals.size else 0.0
-    s_lab = score[lab_idx]
+    beg, lens = rp[lab_idx], rp[lab_idx + 1] - rp[lab_idx]
+    off = np.zeros(n_lab + 1, dtype=np.int64)
+    np.cumsum(lens, out=off[1:])
+    pos = np.repeat(beg - off[:-1], lens) + np.arange(off[-1])
+    vals = h[x_col[pos]]
+    s_lab = np.zeros(n_lab)
+    nz = lens > 0
+    if vals.size:
+        s_lab[nz] = np.add.reduceat(vals, off[:-1][nz])
     n_pos = int(round(pos_frac * n_lab))
     n_pos = min(max(n_pos, 1), n_lab - 1)
     order = np.argsort(-s_lab, kind="stable")

@@ -30,24 +30,34 @@ def test_gather_patterns_are_the_products_index_sets():
     assert np.array_equal(sr, np.repeat(np.arange(pb.n), np.diff(pb.s_rowptr)))
 
 
-@pytest.mark.parametrize("plan", ["1", "lds"])
+@pytest.mark.parametrize("plan", ["1", "lds", "8"])
 def test_operator_apply_bytes_are_the_sum_of_the_products(monkeypatch, plan):
     monkeypatch.setenv("FSDA_XT_SLICES", plan)
     pb = synth.small_problem(n=200, d=500, mean_nnz=30, k=3, seed=2)
     import paper_1709_04794_amd as fsda
-    total = sum(bench.algorithmic_bytes(k, pb, 4, 32) for k in (fsda.K_X, fsda.K_S, fsda.K_XT, fsda.K_XTL))
+    total = sum(bench.algorithmic_bytes(k, pb, 4, 32) for k in (fsda.K_X, fsda.K_S, fsda.K_XT, fsda.K_XTL,
+                                                                 fsda.K_ASM))
     n, d, z, g = pb.n, pb.d, pb.x_nnz, pb.s_nnz
     lab = 16 * n if pb.alpha < 1.0 else 0
     # products as launched (the X^T pass also reads and writes r: 8d + 8d beyond the bare apply)
     want = 8 * z + 4 * g + 40 * n + 36 * d + 12 + lab
-    kind, nsl, nsplit, zsplit = bench.xt_plan(pb)
+    pl = bench.xt_plan(pb)
+    cnt = np.bincount(pb.x_col, minlength=d)
+    split = cnt >= 64
     if plan == "lds":
         # two X^T kernels: u read by both, the split rows' slice bounds, parts written and read
-        cnt = np.bincount(pb.x_col, minlength=d)
-        assert (kind, nsl) == ("lds", 1) and nsplit == int((cnt >= 64).sum()) > 0
+        nsl, nsplit = pl["nsl"], pl["n_lds"]
+        assert (pl["plan"], nsl) == ("lds", 1) and nsplit == int(split.sum()) > 0
+        assert pl["z_lds"] == int(cnt[split].sum()) and pl["n_xcd"] == 0
         want += 8 * n + 4 * (nsl + 1) * nsplit + 16 * nsl * nsplit
+    elif plan == "8":
+        # the split rows' parts (8 per row, these rows are short) written by the X^T pass and read by
+        # the assembly, which also reads their part offsets (p and r in, r out move with their rows)
+        assert pl["plan"] == "xcd" and pl["n_xcd"] == int(split.sum()) > 0 and pl["n_lds"] == 0
+        assert pl["xcd_parts"] == 8 * pl["n_xcd"]
+        want += 16 * pl["xcd_parts"] + 4 * (pl["n_xcd"] + 1)
     else:
-        assert kind == "none"
+        assert pl["plan"] == "none"
     assert total == want
 
 

@@ -236,3 +236,26 @@ def test_shifted_cg_matches_per_shift_cg(alpha):
     # the printed index (alpha_i instead of alpha_{i+1}) breaks the collinearity
     Wp, *_ = shifted.shifted_cg(lambda p: oracle.apply(pb, s0, p), b, pb.betas - s0, tol, 5000, index="printed")
     assert max(relerr(Wp[s], W_ref[s]) for s in range(1, pb.betas.size)) > 1e-3
+
+
+def test_lanczos_condition_matches_dense_spectrum():
+    """kappa-hat from the CG coefficients (Sec. 3.2.1): run to convergence on a small
+    problem, the Lanczos tridiagonal's extreme eigenvalues are the extreme
+    eigenvalues of A(beta) over the eigenvectors b touches (dense eigh), for
+    every shift, and every Ritz value lies inside A's spectrum."""
+    pb = synth.small_problem(n=60, d=50, mean_nnz=6, k=3, alpha=0.5, seed=2)
+    betas = np.array([0.01, 1.0, 30.0])
+    kap, lo, hi, it = oracle.lanczos_condition(pb, betas=betas, rtol=1e-13, maxit=500)
+    b = dense.rhs(pb)
+    for s, beta in enumerate(betas):
+        ev, V = np.linalg.eigh(dense.operator(pb, beta))
+        touched = np.abs(V.T @ b) > 1e-10 * np.linalg.norm(b)
+        # every Ritz value lies in the hull of the spectrum b touches
+        assert ev[touched].min() * (1 - 1e-9) <= lo[s] and hi[s] <= ev[touched].max() * (1 + 1e-9), s
+        if it[s] >= touched.sum():  # the run exhausted the Krylov space: the extremes are exact
+            assert abs(hi[s] - ev[touched].max()) < 1e-8 * ev.max(), (s, hi[s], ev[touched].max())
+            assert abs(lo[s] - ev[touched].min()) < 1e-6 * ev[touched].min(), (s, lo[s], ev[touched].min())
+            assert abs(kap[s] - ev[touched].max() / ev[touched].min()) < 1e-5 * kap[s]
+    assert it[0] >= 50 and it[1] >= 50  # the two small shifts exhaust it
+    # shifting A shifts every Ritz value (the Krylov space does not depend on beta)
+    assert abs((lo[1] - betas[1]) - (lo[0] - betas[0])) < 1e-6 * (lo[0] - betas[0])
