@@ -566,6 +566,283 @@ def traffic_lines(dfetch: str, dwrite: str, calib_mib: int, workload: str) -> st
     return "\n".join(lines)
 
 
+STEP_TARGETS = 64     # targets per step (one fsda_multishift_solve_batch call)
+TOTAL_TARGETS = 1000  # the many-targets configuration; steps take the next 64, cyclically
+
+
+def roofline_large(args, fsda, torch):
+    """The operator apply on the large workload, whose vectors (p: 32 MB, t and u:
+    12 MB) and index arrays (0.9 GB) are far beyond the 256 MB Infinity Cache.
+
+    For each apply kernel class, one solve limited to `roof_iters` iterations
+    runs with HIP events around every launch of that class (on the launch
+    stream); average launch time = event time / launches (a pair costs a few
+    microseconds, under 2 % of these kernels; it is not subtracted).  The
+    dominant kernel's algorithmic bytes over its average time give `achieved`;
+    the operator apply is B_op = 8Z + 4G + 40N + 28D over the summed averages.
+    Also the time of one shared iteration over all 32 shifts (difference of
+    two solves of m and 2m iterations, graph replay) and the oracle's time per
+    per-shift CG iteration on the host, extrapolated."""
+    import synth
+    t0 = time.perf_counter()
+    pb = synth.workload("large", seed=args.seed, cache_dir=args.cache)
+    log("large workload in %.1fs: %s" % (time.perf_counter() - t0, pb.summary()))
+    op = fsda.Operator.from_problem(pb, max_chunk=128)
+    S = pb.betas.size
+    m = args.roof_iters
+    op.solve(pb.betas, rtol=pb.rtol, maxit=m, chunk=128)  # warm (graph capture)
+    torch.cuda.synchronize()
+    per = {}
+    for k in APPLY_CLASSES:
+        op.time_kernel(k, True, every=1)
+        op.solve(pb.betas, rtol=pb.rtol, maxit=m, chunk=128)
+        ms, nl = op.kernel_time()
+        op.time_kernel(k, False)
+        if nl:
+            per[k] = (ms, nl)
+            log("large: %-40s %8.1f us per launch over %d launches" % (KNAMES[k], 1e3 * ms / nl, nl))
+    # one shared iteration (all shifts), from solves of m and 2m iterations
+    sec = []
+    for mm in (m, 2 * m):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        W, it, rel, st = op.solve(pb.betas, rtol=pb.rtol, maxit=mm, chunk=128)
+        torch.cuda.synchronize()
+        sec.append(time.perf_counter() - t1)
+        del W
+    iter_s = (sec[1] - sec[0]) / m
+    pair_us = event_pair_us(torch)
+    op.close()
+    del op
+    dom = max(per, key=lambda k: per[k][0] / per[k][1])
+    ms, nl = per[dom]
+    avg_us = 1e3 * ms / nl
+    bytes_launch = algorithmic_bytes(dom, pb, S, 128)
+    achieved = bytes_launch / (avg_us * 1e-6) / 1e9
+    apply_us = sum(1e3 * v[0] / v[1] for v in per.values())
+    b_op = 8 * pb.x_nnz + 4 * pb.s_nnz + 40 * pb.n + 28 * pb.d
+    roof = {"bound": "hbm", "workload": "large: n=%d x d=%d, nnz_X=%d, nnz_S=%d" % (pb.n, pb.d, pb.x_nnz, pb.s_nnz),
+            "kernel": KNAMES[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, "large"),
+            "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_us, 2), "launches": nl,
+            "timed_every": 1, "event_pair_us": round(pair_us, 2), "xt_plan": xt_plan(pb)["plan"],
+            "note": "HIP events around every launch of the kernel on its launch stream, pair cost included"}
+    apply = {"workload": "large", "bytes": b_op, "us": round(apply_us, 2),
+             "GBps": round(b_op / (apply_us * 1e-6) / 1e9, 1),
+             "frac": round(b_op / (apply_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+             "kernels_us": {KNAMES[k]: round(1e3 * v[0] / v[1], 2) for k, v in per.items()},
+             "note": "X, graph and X^T kernels of one iteration (the X^T pass also updates r, bytes not counted)"}
+    gpu_iter = {"seconds_per_shared_iteration": round(iter_s, 6), "shifts": S,
+                "note": "one iteration of the shared recurrence for all %d shifts, fold included, graph replay" % S}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t1 = time.perf_counter()
+        oracle.solve(pb, betas=[pb.betas[-1]], rtol=pb.rtol, maxit=1)
+        one = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        oracle.solve(pb, betas=[pb.betas[-1]], rtol=pb.rtol, maxit=3)
+        three = time.perf_counter() - t1
+        cpu = {"seconds_per_iteration": round((three - one) / 2, 4), "cores": oracle.max_threads(),
+               "kind": "oracle", "note": "per-shift FP64 CG of the oracle on the large workload, one iteration of "
+                                         "one shift (difference of 3- and 1-iteration solves), extrapolated: a "
+                                         "per-shift CG needs one such iteration per shift per step of its own"}
+        log("large: oracle %.3f s per iteration on %d threads" % (cpu["seconds_per_iteration"], cpu["cores"]))
+    return roof, apply, gpu_iter, cpu
+
+
+def cpu_baseline_targets(pb, target, budget_s: float, rtol: float):
+    """The oracle (per-shift FP64 CG) on the host cores for one target of the
+    many-targets workload: its largest and smallest shift, then a 1-thread run of
+    a few iterations of the largest, extrapolated to the same iteration counts."""
+    import dataclasses
+    import oracle
+    pc = dataclasses.replace(pb, lab_idx=target[0], lab_y=target[1])
+    nt = oracle.max_threads()
+    solved, spent, sample, iters = 0, 0.0, [], 0
+    for s in (int(np.argmax(pb.betas)), int(np.argmin(pb.betas))):
+        if spent > budget_s:
+            break
+        t0 = time.perf_counter()
+        W, it, rel, rc = oracle.solve(pc, betas=[pb.betas[s]], rtol=rtol, maxit=20000)
+        dt = time.perf_counter() - t0
+        spent += dt
+        iters += int(it[0])
+        solved += bool(rel[0] <= TARGET_RELRES)
+        sample.append({"beta": float(pb.betas[s]), "iters": int(it[0]), "seconds": round(dt, 3),
+                       "relres": float(rel[0])})
+    one_core = None
+    try:
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.solve(pc, betas=[pb.betas[-1]], rtol=rtol, maxit=2)
+        t2 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.solve(pc, betas=[pb.betas[-1]], rtol=rtol, maxit=12)
+        t12 = time.perf_counter() - t0
+        per_it = (t12 - t2) / 10
+        one_core = {"value": round(solved / (per_it * iters), 5) if iters else 0.0, "unit": "solves/s", "cores": 1,
+                    "seconds_per_iteration": round(per_it, 4),
+                    "note": "extrapolated: 1-thread time per iteration x the iterations of the sample above"}
+    finally:
+        oracle.set_threads(nt)
+    return {"value": solved / spent if spent > 0 else 0.0, "unit": "solves/s", "cores": nt, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cores": host_cores(),
+            "sample": "per-shift FP64 CG of the oracle for target 0 of the first timed step (its own labeled set "
+                      "of %d rows) on the same mid-scale X and graph, for 2 of its %d shifts (largest and smallest "
+                      "beta) to rel. residual %.0e: %s" % (target[0].size, pb.betas.size, rtol, json.dumps(sample)),
+            "one_core": one_core}
+
+
+def batched_bench(args, fsda, torch):
+    """The default benchmark: shifted solves per second of many targets over one X."""
+    import synth
+    t0 = time.perf_counter()
+    pb = synth.workload("mid", seed=args.seed, cache_dir=args.cache)
+    log("mid workload in %.1fs: %s" % (time.perf_counter() - t0, pb.summary()))
+    t0 = time.perf_counter()
+    targets = synth.target_labels(pb, TOTAL_TARGETS, seed=2)
+    labeled = np.array([t[0].size for t in targets])
+    log("%d targets in %.1fs (labeled rows: median %d, min %d, max %d)"
+        % (len(targets), time.perf_counter() - t0, np.median(labeled), labeled.min(), labeled.max()))
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    op = fsda.Operator.from_problem(pb, max_chunk=128)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tile, rates = op.autotune_batch(targets[:16], pb.betas, trial_iters=32)
+    tune = {"tile": tile, "seconds": round(time.perf_counter() - t0, 2),
+            "shifted_target_iterations_per_s": {str(t): round(r, 1) for t, r in rates.items()}}
+    log("autotuned tile %d: %s" % (tile, tune["shifted_target_iterations_per_s"]))
+    S = pb.betas.size
+    group = [0]
+
+    def step():
+        k = group[0]
+        group[0] += 1
+        labs = [targets[(k * STEP_TARGETS + j) % TOTAL_TARGETS] for j in range(STEP_TARGETS)]
+        W, iters, relres, st = op.solve_batch(labs, pb.betas, rtol=pb.rtol)
+        del W
+        return iters, relres, st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    first_timed = group[0]
+    log("warmup done")
+    t0 = time.perf_counter()
+    solved, worst, maxit, statuses = 0, 0.0, 0, set()
+    for _ in range(args.steps):
+        iters, relres, st = step()
+        solved += int((relres <= TARGET_RELRES).sum())
+        worst = max(worst, float(relres.max()))
+        maxit = max(maxit, int(iters.max()))
+        statuses.add(int(st))
+        log("step done: %d of %d solved so far" % (solved, STEP_TARGETS * S * (group[0] - first_timed)))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = solved / elapsed
+    # the plain per-target FP64 path on the same X: the mid workload's own labeled set
+    op.solve(pb.betas, rtol=pb.rtol, chunk=128)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psolved = 0
+    for _ in range(3):
+        W, it1, rel1, st1 = op.solve(pb.betas, rtol=pb.rtol, chunk=128)
+        psolved += int((rel1 <= TARGET_RELRES).sum())
+        del W
+    torch.cuda.synchronize()
+    per_target = psolved / (time.perf_counter() - t0)
+    log("batched %.2f shifted solves/s; per-target FP64 path %.2f solves/s" % (value, per_target))
+    op.close()
+    del op
+    roof, apply, gpu_iter, cpu_large = roofline_large(args, fsda, torch)
+    out = {
+        "metric": "shifted SDA solves/sec at rel. residual 1e-8",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched targets: %d binary targets per step (of %d, labeled fraction lognormal "
+                               "around 0.7%% in [0.1%%, 5%%], positive rate U(2%%, 30%%)) x %d shifts logspace(-3, 2) "
+                               "over X n=%d x d=%d binary (nnz_X=%d, Zipf 1.1) and a 10-NN graph (nnz_S=%d), "
+                               "alpha=%g, rtol %g, FP64" % (STEP_TARGETS, TOTAL_TARGETS, S, pb.n, pb.d, pb.x_nnz,
+                                                          pb.s_nnz, pb.alpha, pb.rtol),
+                   "targets_per_step": STEP_TARGETS, "total_targets": TOTAL_TARGETS, "shifts": S, "n": pb.n,
+                   "d": pb.d, "nnz_x": pb.x_nnz, "nnz_s": pb.s_nnz, "tile": tile},
+        "roofline": roof,
+        "operator_apply": apply,
+        "detail": {"per_target_fp64_solves_per_s": round(per_target, 3),
+                   "speedup_vs_per_target_fp64": round(value / per_target, 3) if per_target > 0 else None,
+                   "per_target_fp64_iters": it1.tolist(), "worst_relres": worst, "max_iters": maxit,
+                   "statuses": sorted(statuses), "solved": solved, "solves_attempted": args.steps * STEP_TARGETS * S,
+                   "targets_timed": [first_timed * STEP_TARGETS % TOTAL_TARGETS, group[0] * STEP_TARGETS],
+                   "build_s": round(build_s, 3), "autotune": tune, "large_iteration": gpu_iter,
+                   "cpu_large": cpu_large},
+    }
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline_targets(pb, targets[(first_timed * STEP_TARGETS) % TOTAL_TARGETS],
+                                                   args.cpu_budget, pb.rtol)
+        log("cpu baseline took %.1fs" % (time.perf_counter() - t0))
+    print(json.dumps(out), flush=True)
+
+
+def diff_experiment(args, fsda, torch):
+    """The differentiation workload (500,000 x 2,000,000, about 60 nonzeros per row,
+    alpha 0.9, 8 shifts logspace(-3, 2)): 64 targets (labeled sets as in the
+    many-targets workload), each split 80/20 into training labels and held-out rows.
+    Times the phases of the hypergradient: the forward solves of every target
+    (fsda_multishift_solve_batch), the hold-out losses and adjoint right-hand sides
+    (fsda_holdout_batch), the 64 x 8 adjoint systems (fsda_solve_columns_batch) and
+    the gradient in (log beta, alpha) (fsda_hypergradient_batch); reports the
+    library's own true residuals.  (The oracle's recomputation of sampled residuals
+    and gradients at this size is tests/test_gpu_diff.py.)"""
+    import synth
+    t0 = time.perf_counter()
+    pb = synth.workload("diff", seed=args.seed, cache_dir=args.cache)
+    log("diff workload in %.1fs: %s" % (time.perf_counter() - t0, pb.summary()))
+    train, held = synth.holdout_splits(synth.target_labels(pb, 64, seed=5), seed=5)
+    op = fsda.Operator.from_problem(pb, max_chunk=128)
+    S = pb.betas.size
+    op.solve_batch(train[:16], pb.betas, rtol=pb.rtol)  # warm (graph capture, kernels)
+    phases = {}
+
+    def timed(name, fn):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        phases[name] = round(time.perf_counter() - t1, 3)
+        log("%s: %.2f s" % (name, phases[name]))
+        return r
+
+    W, it, rel, st = timed("forward_s", lambda: op.solve_batch(train, pb.betas, rtol=pb.rtol))
+    loss, G = timed("holdout_s", lambda: op.holdout_batch(W, held))
+    Lam, it2, rel2, st2 = timed("adjoint_s", lambda: op.solve_columns_batch(train, pb.betas, G, rtol=pb.rtol))
+    dlb, da = timed("gradient_s", lambda: op.hypergradient_batch(train, W, Lam, pb.betas))
+    total = sum(phases.values())
+    print(json.dumps({"experiment": "diff", "workload": "diff: n=%d x d=%d binary, nnz_X=%d, nnz_S=%d, alpha=%g, "
+                                                        "%d shifts, 64 targets (80/20 splits), rtol %g"
+                                                        % (pb.n, pb.d, pb.x_nnz, pb.s_nnz, pb.alpha, S, pb.rtol),
+                      "phases_s": phases, "total_s": round(total, 3),
+                      "hypergradients_per_s": round(64 * S / total, 2),
+                      "forward": {"status": st, "worst_relres": float(rel.max()), "max_iters": int(it.max()),
+                                  "solved": int((rel <= TARGET_RELRES).sum())},
+                      "adjoint": {"status": st2, "worst_relres": float(rel2.max()), "max_iters": int(it2.max()),
+                                  "solved": int((rel2 <= TARGET_RELRES).sum())},
+                      "finite": bool(np.isfinite(dlb).all() and np.isfinite(da).all()),
+                      "loss_range": [float(loss.min()), float(loss.max())]}), flush=True)
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-rocprof":
         # python bench.py --summarize-rocprof DIR KERNEL_SUBSTR CALIB_MIB
@@ -607,7 +884,8 @@ def main():
     ap.add_argument("--experiment", default="",
                     help="'shifted-table': the CG versus shifted CG table instead; 'gather-ceiling': the rate of "
                          "random gathers the sparse products are bound by; 'batched-targets': 16, 32 and 64 targets; "
-                         "'roofline-large': the operator-apply roofline on the large workload alone")
+                         "'roofline-large': the operator-apply roofline on the large workload alone; 'diff': the "
+                         "hypergradient of 64 targets on the differentiation workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -627,6 +905,9 @@ def main():
         return
     if args.experiment == "batched-targets":
         batched_targets(args, fsda, torch)
+        return
+    if args.experiment == "diff":
+        diff_experiment(args, fsda, torch)
         return
     if args.experiment == "roofline-large":
         if args.calib_copy_mb > 0:

@@ -80,3 +80,27 @@ def test_xcd_sliced_stream_is_a_slice_aligned_permutation():
         else:
             assert (sl[:, 0] == (p % 8 + p // 8) % 8).all()
             assert len(np.unique(sl[p % 8 == 0, 0])) == min(8, len(pieces[p % 8 == 0]))
+
+
+def test_every_function_bench_calls_is_defined():
+    """Every bare name bench.py calls is bound somewhere in it (a function, an
+    argument, an assignment) or is a builtin: a refactoring that drops a function
+    still called by the default run fails here, on the CPU."""
+    import ast
+    import builtins
+    tree = ast.parse(open(bench.__file__).read())
+    bound = set()
+    for node in ast.walk(tree):
+        if isinstance(node, (ast.FunctionDef, ast.ClassDef)):
+            bound.add(node.name)
+        elif isinstance(node, ast.arg):
+            bound.add(node.arg)
+        elif isinstance(node, ast.Name) and isinstance(node.ctx, ast.Store):
+            bound.add(node.id)
+        elif isinstance(node, (ast.Import, ast.ImportFrom)):
+            bound.update((a.asname or a.name).split(".")[0] for a in node.names)
+    called = {n.func.id for n in ast.walk(tree) if isinstance(n, ast.Call) and isinstance(n.func, ast.Name)}
+    missing = sorted(c for c in called if c not in bound and not hasattr(builtins, c))
+    assert not missing, missing
+    for name in ("batched_bench", "single_bench", "roofline_large", "diff_experiment", "cpu_baseline_targets"):
+        assert callable(getattr(bench, name)), name
