@@ -61,7 +61,8 @@ extern "C" {
 /* Limits of one handle. */
 #define FSDA_MAX_SHIFTS 64
 #define FSDA_MAX_CHUNK 256
-#define FSDA_MAX_TARGETS 64     /* targets of one fsda_multishift_solve_batch call */
+#define FSDA_MAX_TARGETS 4096   /* targets of one fsda_multishift_solve_batch call (in tiles) */
+#define FSDA_MAX_COLUMNS 64     /* right-hand sides of one fsda_solve_columns call (one tile) */
 #define FSDA_MAX_BATCH_CHUNK 128 /* fold interval of fsda_multishift_solve_batch */
 
 typedef struct fsda_op fsda_op; /* opaque handle, host memory */
@@ -117,13 +118,15 @@ int fsda_workspace_size(const fsda_problem *pb, int max_shifts, int max_chunk, s
  * sample boundaries and their parts added in a fixed order):
  *  n <= 262,144: LDS slices of 8192 samples; each work-group stages one slice
  *    of the sample-space vector in LDS and sums the rows' segments there.
- *  n > 262,144: XCD slices; each of the eight XCDs gathers from one eighth of
- *    the sample range, which stays in its L2.
+ *  n > 262,144: the rows of >= 2048 nonzeros in LDS slices, the other cut rows
+ *    in XCD slices: each of the eight XCDs gathers from one eighth of the
+ *    sample range, which stays in its L2.
  * Results differ between plans only in the summation order of those rows.
- * The environment variable FSDA_XT_SLICES set to 1 (no slices), 8 (XCD slices)
- * or lds (LDS slices, for n <= 262,144) overrides the choice; it is read by
- * fsda_workspace_size and by this call, which must see the same value (else
- * FSDA_E_WORKSPACE may result).
+ * The environment variable FSDA_XT_SLICES set to 1 (no slices), 8 (XCD slices
+ * only), lds (LDS slices only, for n <= 262,144) or hyb (LDS and XCD slices)
+ * overrides the choice, and FSDA_XT_HEAD the row length from which rows go to
+ * LDS slices in the hybrid plan; they are read by fsda_workspace_size and by
+ * this call, which must see the same values (else FSDA_E_WORKSPACE may result).
  * Errors: FSDA_E_ARG, FSDA_E_RANGE (alpha), FSDA_E_OVERFLOW, FSDA_E_WORKSPACE,
  * FSDA_E_CSR, FSDA_E_LABELS, FSDA_E_HIP.
  */
@@ -173,16 +176,27 @@ int fsda_apply(fsda_op *op, double sigma, const double *p, double *q, void *stre
  * last iterate), FSDA_E_BREAKDOWN, or an argument error.  Blocks until done.
  *
  * FSDA_MIXED: the shared recurrence runs with FP32 vectors (FP64 dot products
- * and scalars) to max(rtol, 1e-5), where FP32 rounding stalls it; then up to
- * three refinement rounds, each forming R_s = b - A(beta_s) w_s in FP64,
- * solving A(beta_s) delta_s = R_s for all unconverged shifts at once by
- * batched FP32 CG (one column per shift; the residuals of different shifts are
- * not collinear, so they cannot share one shifted basis) to 0.5 rtol ||b||,
- * and adding delta_s in FP64.  The status is FSDA_OK when every reported
- * relres[s] <= rtol, else FSDA_NOT_CONVERGED.
+ * and scalars) to max(rtol, 1e-5), where FP32 rounding stalls it; then one
+ * step of FP64 iterative refinement: R_s = b - A(beta_s) w_s in FP64, the
+ * corrections A(beta_s) delta_s = R_s of every shift not yet within rtol solved
+ * at once by batched FP32 CG (one column per shift; the residuals of different
+ * shifts are not collinear, so they cannot share one shifted basis) to
+ * 0.5 rtol ||b|| (at most 1e-6 below ||R_s||), and w_s += delta_s in FP64.  The
+ * status is FSDA_OK when every reported relres[s] <= rtol, else
+ * FSDA_NOT_CONVERGED.
  */
 int fsda_multishift_solve(fsda_op *op, const double *b, const double *betas, int nshift, double rtol, int maxit,
                           int chunk, double *W, int *iters, double *relres, void *stream);
+
+/*
+ * Breakdown of the last completed fsda_multishift_solve on this handle, per
+ * shift (host outputs of nshift entries; nshift must be that solve's):
+ * main_iters[s] the iterations after which shift s stopped in the shared
+ * recurrence, refine_iters[s] the iterations of its correction solve
+ * (FSDA_MIXED; 0 otherwise), steps[s] the refinement steps it took (0 or 1).
+ * iters[s] of the solve is main_iters[s] + refine_iters[s].  Host only.
+ */
+int fsda_solve_report(const fsda_op *op, int nshift, int *main_iters, int *refine_iters, int *steps);
 
 /*
  * Spectral analysis for SDA (Alg. sasda): the ratings of the samples present
@@ -233,6 +247,11 @@ int fsda_regression_solve(fsda_op *op, const double *z, const double *betas, int
  * handle's; its own labeled set is not used.  Targets go in tiles of up to
  * 16 (fsda_set_batch_tile, fsda_batch_autotune), one tile after the other; the
  * sparse products of the targets of a tile share one pass over the indices.
+ * When the sample-space vector over a tile's targets outgrows an XCD's share
+ * of L2 (n x tile x 8 bytes > 2 MiB), the rows of X^T of >= 64 nonzeros are
+ * summed in XCD slices (each XCD gathers from one eighth of the samples); the
+ * environment variable FSDA_BXT_SLICES set to 0 or 8 overrides this, here and
+ * in the column solves, and must be the same for the workspace-size call.
  *  ntarget       1..FSDA_MAX_TARGETS.
  *  lab_idx[], lab_y[] (device) the labeled sets of all targets, concatenated;
  *                target c owns entries lab_off[c] .. lab_off[c+1]-1 (same
@@ -300,7 +319,7 @@ int fsda_batch_autotune(fsda_op *op, int ntarget, const int32_t *lab_idx, const 
  * Batched CG in FP64, one column per system, the sparse products of all
  * columns sharing one pass over the indices.
  *  B[ncol][d]   device, right-hand sides in the caller's feature order.
- *  sigmas[ncol] host, each > 0.   ncol 1..FSDA_MAX_TARGETS.
+ *  sigmas[ncol] host, each > 0.   ncol 1..FSDA_MAX_COLUMNS.
  *  rtol, maxit  column c stops when ||r_c|| <= rtol ||b_c||; at most maxit iterations.
  *  workspace    device, 256-byte aligned, >= fsda_columns_workspace_size(); scratch.
  *  X[ncol][d]   device FP64 output.   iters, relres[ncol] host (true FP64 residual).

@@ -29,6 +29,7 @@ import os
 import subprocess
 
 import numpy as np
+from scipy import linalg as scipy_linalg
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
@@ -185,12 +186,13 @@ def solve(pb, betas=None, rtol: float = 1e-12, maxit: int = 100000, b: np.ndarra
     return W, iters, relres, rc
 
 
-def lanczos_condition(pb, betas=None, rtol: float = 1e-10, maxit: int = 20000, b: np.ndarray = None, alpha=None):
-    """kappa-hat per shift: the condition estimate of A(beta_s) from the CG run of
-    that shift (Sec. 3.2.1): CG's coefficients a_i, b_i define the Lanczos
-    tridiagonal T (diagonal 1/a_i + b_{i-1}/a_{i-1}, off-diagonal sqrt(b_i)/a_i),
-    whose extreme eigenvalues (Ritz values) approach those of A on the Krylov
-    space of b.  Returns (kappa [S], ritz_min [S], ritz_max [S], iters [S])."""
+def solve_with_kappa(pb, betas=None, rtol: float = 1e-12, maxit: int = 100000, b: np.ndarray = None, alpha=None):
+    """Per-shift CG as :func:`solve`, and kappa-hat per shift: the condition estimate of
+    A(beta_s) from that shift's CG run (Sec. 3.2.1).  CG's coefficients a_i, b_i define
+    the Lanczos tridiagonal T (diagonal 1/a_i + b_{i-1}/a_{i-1}, off-diagonal
+    sqrt(b_i)/a_i), whose extreme eigenvalues (Ritz values) approach those of A on the
+    Krylov space of b.  Returns (W [S, d], iters [S], relres [S], status, kappa [S],
+    ritz_min [S], ritz_max [S])."""
     bnd = _Bound(pb, alpha)
     betas = np.ascontiguousarray(pb.betas if betas is None else betas, dtype=np.float64)
     S = betas.size
@@ -202,20 +204,25 @@ def lanczos_condition(pb, betas=None, rtol: float = 1e-10, maxit: int = 20000, b
     rc = _load().orc_solve(bnd.ref, _p(bb), S, _p(betas), float(rtol), int(maxit), _p(W), _p(iters), _p(relres),
                            _p(rec))
     _check(rc, "solve")
-    kap, lo, hi = np.zeros(S), np.zeros(S), np.zeros(S)
+    kap, lo, hi = np.full(S, np.nan), np.full(S, np.nan), np.full(S, np.nan)
     for s in range(S):
         k = int(iters[s])
-        a, bcoef = rec[s, 0:2 * k:2], rec[s, 1:2 * k:2]
         if k == 0:
-            kap[s] = lo[s] = hi[s] = np.nan
             continue
+        a, bcoef = rec[s, 0:2 * k:2], rec[s, 1:2 * k:2]
         diag = 1.0 / a
         diag[1:] += bcoef[:-1] / a[:-1]
         off = np.sqrt(bcoef[:-1]) / a[:-1]
-        T = np.diag(diag) + np.diag(off, 1) + np.diag(off, -1)
-        ev = np.linalg.eigvalsh(T)
+        ev = scipy_linalg.eigvalsh_tridiagonal(diag, off) if k > 1 else diag
         lo[s], hi[s] = ev[0], ev[-1]
         kap[s] = ev[-1] / ev[0]
+    return W, iters, relres, rc, kap, lo, hi
+
+
+def lanczos_condition(pb, betas=None, rtol: float = 1e-10, maxit: int = 20000, b: np.ndarray = None, alpha=None):
+    """kappa-hat per shift from the CG run of that shift (see :func:`solve_with_kappa`).
+    Returns (kappa [S], ritz_min [S], ritz_max [S], iters [S])."""
+    W, iters, relres, rc, kap, lo, hi = solve_with_kappa(pb, betas, rtol, maxit, b, alpha)
     return kap, lo, hi, iters
 
 

@@ -27,7 +27,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "fsda.h")
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_CSR, E_LABELS, E_RANGE, E_BREAKDOWN, E_WORKSPACE, E_HIP, E_OVERFLOW = -1, -2, -3, -4, -5, -6, -7, -8
 FP64, MIXED = 0, 1
-MAX_SHIFTS, MAX_CHUNK, MAX_TARGETS, MAX_BATCH_CHUNK = 64, 256, 64, 128
+MAX_SHIFTS, MAX_CHUNK, MAX_TARGETS, MAX_BATCH_CHUNK, MAX_COLUMNS = 64, 256, 4096, 128, 64
 STATIC_SCRATCH_BYTES = 64 << 20  # FSDA_STATIC_SCRATCH_BYTES
 # kernel classes for fsda_time_kernel
 K_X, K_S, K_XT, K_XTL, K_RESID, K_PUPD, K_FOLD = 0, 1, 2, 3, 4, 5, 6
@@ -83,6 +83,7 @@ def lib():
         L.fsda_batch_workspace_size.argtypes = [P, I, I, I, ctypes.POINTER(ctypes.c_size_t)]
         L.fsda_multishift_solve_batch.argtypes = [P, I, P, P, P, P, I, D, I, I, P, ctypes.c_size_t, P, P, P, P]
         L.fsda_solve_columns_static.argtypes = [P, P, P, I, D, I, P, P, P, P]
+        L.fsda_solve_report.argtypes = [P, I, P, P, P]
         L.fsda_holdout_batch.argtypes = [P, I, P, I, P, P, P, P, P, P]
         L.fsda_columns_batch_workspace_size.argtypes = [P, I, I, ctypes.POINTER(ctypes.c_size_t)]
         L.fsda_solve_columns_batch.argtypes = [P, I, P, P, P, P, I, P, D, I, P, ctypes.c_size_t, P, P, P, P]
@@ -102,7 +103,7 @@ def lib():
                   L.fsda_columns_workspace_size, L.fsda_solve_columns, L.fsda_holdout, L.fsda_hypergradient,
                   L.fsda_gather_sum, L.fsda_set_batch_tile, L.fsda_get_batch_tile, L.fsda_batch_autotune,
                   L.fsda_holdout_batch, L.fsda_columns_batch_workspace_size, L.fsda_solve_columns_batch,
-                  L.fsda_hypergradient_batch, L.fsda_solve_columns_static):
+                  L.fsda_hypergradient_batch, L.fsda_solve_columns_static, L.fsda_solve_report):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -233,6 +234,13 @@ class Operator:
                                                 iters.ctypes.data_as(ctypes.c_void_p),
                                                 relres.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
         return W, iters, relres, rc
+
+    def solve_report(self, nshift: int):
+        """Per shift of the last solve: iterations of the shared recurrence, of the
+        correction solve (mixed path), refinement steps taken (fsda_solve_report)."""
+        out = [np.zeros(int(nshift), dtype=np.int32) for _ in range(3)]
+        _check(lib().fsda_solve_report(self.handle, int(nshift), *[o.ctypes.data_as(ctypes.c_void_p) for o in out]))
+        return {"main_iters": out[0], "refine_iters": out[1], "steps": out[2]}
 
     def sa_rhs(self, r=None, stream=None):
         """Right-hand side of the sample-space solve (Alg. sasda): y_c, or the printed one for start vector r."""

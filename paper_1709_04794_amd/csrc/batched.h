@@ -234,6 +234,14 @@ struct BXtArgs {
   const int* chunk_row;
   const int* chunk_beg;
   const int* row_chunk0;
+  // XCD slices (item_chunk != NULL): a row of >= BMED nonzeros is cut at the
+  // sample boundaries x n / 8 as well, chunk k ending at chunk_end[k], and
+  // chunk item it (of nitem, a multiple of 8) sums chunk item_chunk[it] (-1:
+  // none), a chunk of sample slice it % 8: with a grid that is a multiple of 8
+  // every XCD gathers from one eighth of u, which stays in its L2.
+  const int* chunk_end;
+  const int* item_chunk;
+  int nitem;
 };
 
 __device__ __forceinline__ size_t qidx(int T, long long ldq, long long r, int c) {
@@ -254,12 +262,15 @@ __global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __rest
   __shared__ V sh[BS];
   const int c = threadIdx.x % T, g = threadIdx.x / T;
   const V sg = P ? (V)sigma[c] : (V)0;
-  const int nitems = nchunk + (d - nmed + G - 1) / G;
+  const int nchit = X.item_chunk ? X.nitem : nchunk;  // chunk items
+  const int nitems = nchit + (d - nmed + G - 1) / G;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    if (it < nchunk) {  // uniform over the block
-      const int r = chunk_row[it];
-      const int end = rowptr[r + 1];
-      const int beg = min(chunk_beg[it] + g * SL, end);
+    if (it < nchit) {  // uniform over the block
+      const int k = X.item_chunk ? X.item_chunk[it] : it;
+      if (k < 0) continue;
+      const int r = chunk_row[k];
+      const int end = X.chunk_end ? X.chunk_end[k] : rowptr[r + 1];
+      const int beg = min(chunk_beg[k] + g * SL, end);
       const V v = group_gather<T, V>(col, beg, min(beg + SL, end), u, c);
       __syncthreads();
       sh[threadIdx.x] = v;
@@ -267,12 +278,12 @@ __global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __rest
       if (threadIdx.x < T) {
         V t = (V)0;
 #pragma unroll
-        for (int k = 0; k < G; k++) t += sh[k * T + threadIdx.x];
-        lpart[(size_t)it * T + threadIdx.x] = t;
+        for (int q = 0; q < G; q++) t += sh[q * T + threadIdx.x];
+        lpart[(size_t)k * T + threadIdx.x] = t;
       }
       continue;
     }
-    const int r = nmed + (it - nchunk) * G + g;
+    const int r = nmed + (it - nchit) * G + g;
     if (r >= d) continue;
     const V v = group_gather<T, V>(col, rowptr[r], rowptr[r + 1], u, c);
     Q[qidx(T, ldq, r, c)] = P ? v + sg * P[(size_t)r * T + c] : v;

@@ -76,7 +76,7 @@ constexpr int GRID_B = 2048;         // blocks of the batched kernels (partials 
 constexpr int B_CHUNK = 8;           // batched iterations per host check
 constexpr double MIXED_INNER = 1e-5; // FP32 main solve stops at max(rtol, this)
 constexpr double MIXED_FLOOR = 1e-6; // correction solves stop at most this far below ||R_s||
-constexpr int MIXED_ROUNDS = 3;      // refinement rounds at most
+constexpr int MIXED_STEPS = 1;       // FP64 refinement steps
 enum BSite { BP_X = 0, BP_TU = 1, BP_RR = 2, BP_PP = 3, BP_N = 4 };
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -111,6 +111,7 @@ struct Layout {
   long long ldd;  // d padded: stride of the feature-space vectors of the refinement
   long long ldv;  // max(d, n) padded: stride of the ring and per-shift directions
   long long nchunk_max, nlong_max, npart_max, nsplit_max;
+  long long nlds_max;  // rows in LDS slices (all split rows, or with XCD slices the head rows)
   int nslice;  // X^T XCD slices: 1 (none), or NSLICE (one per XCD)
   int lslice;  // X^T LDS slices (0: none)
   size_t lparts, lxptr, lxcol;
@@ -123,7 +124,18 @@ struct Layout {
 // to 1 (neither), 8 (XCD slices) or lds (LDS slices, where n allows) overrides
 // the choice.  Returns the XCD slice count (1 or NSLICE); *lslice receives the
 // LDS slice count (0: none).
+// With XCD slices, the longest rows (>= LDS_HEAD nonzeros, the head of the
+// frequency order) are also worth LDS slices: each has enough nonzeros per
+// slice to pay for its per-slice part.  Then the plan is a hybrid: the head rows
+// in LDS slices, the other split rows in XCD slices (FSDA_XT_SLICES=hyb forces
+// it at any n; FSDA_XT_HEAD sets the head threshold).
 constexpr long long SLICE_BYTES = 2LL << 20;
+constexpr int LDS_HEAD = 2048;
+int xt_head(void) {
+  const char* e = std::getenv("FSDA_XT_HEAD");
+  const int h = e ? std::atoi(e) : LDS_HEAD;
+  return std::max(h, SPLIT_ROW);
+}
 int xt_slices(const fsda_problem* pb, int* lslice) {
   const long long nl = (pb->n + LSLICE - 1) / LSLICE;
   const bool lds_fits = nl <= MAXLSLICE;
@@ -131,11 +143,19 @@ int xt_slices(const fsda_problem* pb, int* lslice) {
   *lslice = 0;
   if (e && std::strcmp(e, "1") == 0) return 1;
   if (e && std::strcmp(e, "8") == 0) return NSLICE;
+  if (e && std::strcmp(e, "hyb") == 0) {
+    *lslice = (int)nl;
+    return NSLICE;
+  }
   if (lds_fits) {
     *lslice = (int)nl;
     return 1;
   }
-  return 8 * pb->n > SLICE_BYTES ? NSLICE : 1;
+  if (8 * pb->n > SLICE_BYTES) {
+    *lslice = (int)nl;  // hybrid
+    return NSLICE;
+  }
+  return 1;
 }
 
 void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
@@ -164,10 +184,12 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
     L->nlong_max = L->nsplit_max;
   }
   L->lparts = L->lxptr = L->lxcol = 0;
-  if (L->lslice > 0) {  // split rows: slice boundaries, slice-major indices, one part per (row, slice)
+  L->nlds_max = 0;
+  if (L->lslice > 0) {  // LDS rows: slice boundaries, slice-major indices, one part per (row, slice)
     L->nsplit_max = z / SPLIT_ROW + 1;
-    L->lparts = 8 * (size_t)L->nsplit_max * (size_t)L->lslice;
-    L->lxptr = 4 * ((size_t)L->nsplit_max + 1) * (size_t)L->lslice;
+    L->nlds_max = L->nslice > 1 ? z / xt_head() + 1 : L->nsplit_max;  // hybrid: the head rows only
+    L->lparts = 8 * (size_t)L->nlds_max * (size_t)L->lslice;
+    L->lxptr = 4 * ((size_t)L->nlds_max + 1) * (size_t)L->lslice;
     L->lxcol = 2 * (size_t)z;
   }
   L->st = take(sizeof(State));
@@ -196,7 +218,8 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->chunk_end = take(4 * (size_t)L->nchunk_max);
   L->lpart = take(8 * (size_t)L->npart_max);
   L->row_chunk0 = take(4 * ((size_t)L->nlong_max + 1));
-  L->segp = take(4 * (size_t)(std::max(NSLICE, L->lslice) + 1) * (size_t)L->nsplit_max);
+  L->segp = take(4 * std::max((size_t)(NSLICE + 1) * (size_t)L->nsplit_max,
+                               (size_t)(L->lslice + 1) * (size_t)L->nlds_max));
   L->lparts = L->lslice > 0 ? take(L->lparts) : 0;
   L->lxptr = L->lslice > 0 ? take(L->lxptr) : 0;
   L->lxcol = L->lslice > 0 ? take(L->lxcol) : 0;
@@ -286,6 +309,7 @@ struct XtPlan {  // X^T product: long rows in single-row chunks, the rest in len
   XtWork w;
   XtLds lds;   // with LDS slices: the split rows' parts (k_xt_lds, before k_xt)
   int nlong;
+  int asm_r0;  // rows asm_r0 + [0, nlong) are finished by k_assemble
   const int* row_chunk0;
   int grid;    // k_xt
   int gridL;   // k_assemble
@@ -294,6 +318,7 @@ struct XtPlan {  // X^T product: long rows in single-row chunks, the rest in len
 struct RowPlan {
   Rows rows;
   int grid;
+  int nt;  // threads per block: BS, or XNT for the X product
 };
 
 }  // namespace
@@ -305,6 +330,7 @@ struct fsda_op {
   size_t ws_bytes;
   Layout L;
   RowPlan px, px_user, ps;  // px: mask features + CSR of the others (internal order); px_user: caller's order
+  RowPlan pxr;               // the same X in blocks of BS threads staging HOT_REG features (regression phase)
   XtPlan pxt;
   State* st;
   State* hst;  // pinned host mirror
@@ -340,18 +366,24 @@ struct fsda_op {
   // X^T rows of >= BMED nonzeros: their row pointers (host copy) and the chunk
   // table of the batched product for tile btab_tile
   std::vector<int> xt_rp_med;
-  int nmed, btab_tile, bnchunk;
+  int nmed, btab_tile;
+  BXtArgs bxa;  // the refinement's batched X^T tables (unsliced)
+  // with XCD slices of the batched X^T product: the split rows' segment bounds,
+  // [(NSLICE + 1) * nmed] as in k_slice_bounds (host copy, found once)
+  std::vector<int> bseg;
   // batched targets: targets per tile (0: TARGET_TILE; set by fsda_set_batch_tile
   // or fsda_batch_autotune), one chunk of iterations + fold as a graph, and its key
   int btile_sel;
   hipGraphExec_t tgexec;
   const void* tkey_ws;
-  const double* tkey_W;
-  int tkey_T, tkey_ncol, tkey_nshift, tkey_chunk;
+  int tkey_T, tkey_nshift, tkey_chunk, tkey_sliced;
   TState* htst;  // pinned host mirror
   BState* bst;
   BState* hbst;  // pinned host mirror
   void* scratch_dev;  // device address of the static scratch on the handle's GPU
+  // breakdown of the last fsda_multishift_solve per shift: iterations of the
+  // shared recurrence, of the correction solves, refinement steps taken
+  std::vector<int> rep_main, rep_refine, rep_steps;
 };
 
 namespace {
@@ -425,8 +457,21 @@ void run_rows(fsda_op* op, const RowPlan& pl, const typename Epi::V* src, Epi ep
               hipStream_t s, int cls) {
   launch(op, cls, s, [&] {
     const size_t smem = pl.rows.mask ? sizeof(typename Epi::V) * pl.rows.nhot : 0;
-    hipLaunchKernelGGL(k_rows<Epi>, dim3(pl.grid), dim3(BS), smem, s, pl.rows, src, epi, op->st, part, 0, solve);
+    if (pl.nt == XNT)
+      hipLaunchKernelGGL((k_rows<Epi, XNT>), dim3(pl.grid), dim3(XNT), smem, s, pl.rows, src, epi, op->st, part, 0,
+                         solve);
+    else
+      hipLaunchKernelGGL((k_rows<Epi, BS>), dim3(pl.grid), dim3(BS), smem, s, pl.rows, src, epi, op->st, part, 0,
+                         solve);
   });
+}
+
+// The X product's dynamic shared memory (the staged features) may exceed the default limit.
+template <class Epi>
+int allow_xrows_smem(size_t bytes) {
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(k_rows<Epi, XNT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return FSDA_OK;
 }
 
 // X^T product.  With `assemble`, the long rows are finished by k_assemble
@@ -449,8 +494,8 @@ void run_xt(fsda_op* op, const typename Epi::V* src, Epi epi, int solve, bool as
   });
   if (assemble && pl.nlong > 0)
     launch(op, cls == KC_XT ? KC_ASM : KC_OTHER, s, [&] {
-      hipLaunchKernelGGL(k_assemble<Epi>, dim3(pl.gridL), dim3(BS), 0, s, pl.nlong, pl.row_chunk0, pl.w.lpart, epi,
-                         op->st, part, pl.grid, solve);
+      hipLaunchKernelGGL(k_assemble<Epi>, dim3(pl.gridL), dim3(BS), 0, s, pl.asm_r0, pl.nlong, pl.row_chunk0,
+                         pl.w.lpart, epi, op->st, part, pl.grid, solve);
     });
 }
 
@@ -530,8 +575,8 @@ void iteration(fsda_op* op, int mode, hipStream_t s, int tag) {
     // finished by the direction update)
     const V* u = as<V>(op->u);
     if (mode == MODE_REG) {
-      run_rows(op, op->px, p, EpiXReg<V>{as<V>(op->t)}, op->part + SITE_TU * NPART, 1, s, KC_X);
-      ntu = op->px.grid;
+      run_rows(op, op->pxr, p, EpiXReg<V>{as<V>(op->t)}, op->part + SITE_TU * NPART, 1, s, KC_X);
+      ntu = op->pxr.grid;
       u = as<V>(op->t);
     } else {
       product_x<V>(op, p, 1, s);
@@ -619,10 +664,13 @@ int check_csr(const int* rowptr, const int* col, long long nrows, long long nnz,
   return FSDA_OK;
 }
 
-// One bin, lanes per row from the mean row length.
-RowPlan one_bin(const int* rowptr, const int* col, long long nrows, long long nnz) {
+// One bin, lanes per row from the mean row length; blocks of nt threads, at most
+// `cap` blocks.
+RowPlan one_bin(const int* rowptr, const int* col, long long nrows, long long nnz, int nt = BS,
+                int cap = GRID_ROWS) {
   RowPlan pl;
   std::memset(&pl, 0, sizeof(pl));
+  pl.nt = nt;
   pl.rows.rowptr = rowptr;
   pl.rows.col = col;
   pl.rows.nb = 1;
@@ -631,8 +679,8 @@ RowPlan one_bin(const int* rowptr, const int* col, long long nrows, long long nn
   const int lpr = pow2_at_least(ceil_div(std::max<long long>(nnz, 1), std::max<long long>(nrows, 1) * RUNR));
   pl.rows.lpr[0] = lpr;
   pl.rows.item0[0] = 0;
-  pl.rows.item0[1] = (int)ceil_div(nrows, BS / lpr);
-  pl.grid = std::max(1, std::min(pl.rows.item0[1], GRID_ROWS));
+  pl.rows.item0[1] = (int)ceil_div(nrows, nt / lpr);
+  pl.grid = std::max(1, std::min(pl.rows.item0[1], cap));
   return pl;
 }
 
@@ -644,66 +692,76 @@ RowPlan one_bin(const int* rowptr, const int* col, long long nrows, long long nn
 // contiguous and item k runs slice k % 8.  The other split rows go to bins of
 // NSLICE items each, by length: [1024, 8192) 64 lanes, [512, 1024) 16,
 // [256, 512) 8, [64, 256) 4 (about XUNR nonzeros of a slice per lane).
-int make_xt_slices(fsda_op* op, hipStream_t s) {
+int make_xt_slices(fsda_op* op, int r0, hipStream_t s) {
   XtPlan& pl = op->pxt;
   XtWork& w = pl.w;
   XtSlices& S = w.sl;
-  const int nsplit = op->xt_bins[3];
+  const int nend = op->xt_bins[3];   // split rows end here
+  const int nsplit = nend - r0;      // rows [r0, nend) in XCD slices
   const std::vector<int>& rp = op->xt_rp_med;
   if (nsplit > op->L.nsplit_max) return fail(FSDA_E_WORKSPACE, "split-row table larger than reserved");
+  S.r0 = r0;
   S.nsplit = nsplit;
   S.segp = at<int>(op, op->L.segp);
   pl.nlong = nsplit;
-  if (nsplit == 0) return FSDA_OK;
+  pl.asm_r0 = r0;
+  S.nlc = r0;
+  if (nsplit <= 0) {
+    S.nsplit = 0;
+    pl.nlong = 0;
+    return FSDA_OK;
+  }
   const long long nseg = (long long)(NSLICE + 1) * nsplit;
-  hipLaunchKernelGGL(k_slice_bounds, dim3((unsigned)ceil_div(nseg, BS)), dim3(BS), 0, s, op->xt_rowptr, op->xt_col,
-                     nsplit, (long long)op->pb.n, NSLICE, 0, const_cast<int*>(S.segp));
+  hipLaunchKernelGGL(k_slice_bounds, dim3((unsigned)ceil_div(nseg, BS)), dim3(BS), 0, s, op->xt_rowptr + r0,
+                     op->xt_col, nsplit, (long long)op->pb.n, NSLICE, 0, const_cast<int*>(S.segp));
   HIP_TRY(hipGetLastError());
   std::vector<int> sp(nseg);
   HIP_TRY(hipMemcpyAsync(sp.data(), S.segp, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  auto len = [&](int j) { return rp[j + 1] - rp[j]; };
-  int nlc = 0;
-  while (nlc < nsplit && len(nlc) >= SLICE_LONG) nlc++;
+  auto len = [&](int j) { return rp[j + 1] - rp[j]; };  // absolute row j
+  int nlc = r0;
+  while (nlc < nend && len(nlc) >= SLICE_LONG) nlc++;
+  // row_chunk0 and the segment table are indexed by the row relative to r0
   std::vector<int> crow, cbeg, cend, c0(nsplit + 1);
-  for (int j = 0; j < nlc; j++) {
+  for (int j = r0; j < nlc; j++) {
+    const int jj = j - r0;
     int longest = 0;
-    for (int x = 0; x < NSLICE; x++) longest = std::max(longest, sp[(x + 1) * nsplit + j] - sp[x * nsplit + j]);
+    for (int x = 0; x < NSLICE; x++) longest = std::max(longest, sp[(x + 1) * nsplit + jj] - sp[x * nsplit + jj]);
     const int ncut = std::max(1, (int)ceil_div(longest, CHUNK));
-    c0[j] = (int)crow.size();
+    c0[jj] = (int)crow.size();
     for (int c = 0; c < ncut; c++)
       for (int x = 0; x < NSLICE; x++) {
-        const int s0 = sp[x * nsplit + j], s1 = sp[(x + 1) * nsplit + j];
+        const int s0 = sp[x * nsplit + jj], s1 = sp[(x + 1) * nsplit + jj];
         crow.push_back(j);
         cbeg.push_back((int)std::min<long long>(s0 + (long long)c * CHUNK, s1));
         cend.push_back((int)std::min<long long>(s0 + (long long)(c + 1) * CHUNK, s1));
       }
   }
   const int nchunk = (int)crow.size();
-  for (int j = nlc; j <= nsplit; j++) c0[j] = nchunk + NSLICE * (j - nlc);
+  for (int j = nlc; j <= nend; j++) c0[j - r0] = nchunk + NSLICE * (j - nlc);
   if ((long long)nchunk > op->L.nchunk_max || (long long)c0[nsplit] > op->L.npart_max)
     return fail(FSDA_E_WORKSPACE, "sliced chunk table larger than reserved");
   w.nchunk = nchunk;
   w.nchunk_multi = nchunk;  // every chunk is a part of a split row
   S.nlc = nlc;
   S.part0 = nchunk;
-  // bins of the split rows [nlc, nsplit); lengths decrease with the row index
+  // bins of the split rows [nlc, nend); lengths decrease with the row index
   const int lo[4] = {1024, 512, 256, SPLIT_ROW};
   const int lprs[4] = {64, 16, 8, 4};
   int nb = 0, item = 0, j = nlc;
   for (int k = 0; k < 4; k++) {
-    const int r0 = j;
-    while (j < nsplit && len(j) >= lo[k]) j++;
-    if (j == r0) continue;
-    S.row0[nb] = r0;
+    const int b0 = j;
+    while (j < nend && len(j) >= lo[k]) j++;
+    if (j == b0) continue;
+    S.row0[nb] = b0;
     S.row0[nb + 1] = j;
     S.lpr[nb] = lprs[k];
     S.item0[nb] = item;
-    item += (int)ceil_div(j - r0, BS / lprs[k]);
+    item += (int)ceil_div(j - b0, BS / lprs[k]);
     S.item0[nb + 1] = item;
     nb++;
   }
-  if (j != nsplit) return fail(FSDA_E_CSR, "X^T rows not ordered by length");
+  if (j != nend) return fail(FSDA_E_CSR, "X^T rows not ordered by length");
   S.nb = nb;
   if (nchunk > 0) {
     HIP_TRY(hipMemcpyAsync(const_cast<int*>(w.chunk_row), crow.data(), sizeof(int) * nchunk, hipMemcpyHostToDevice, s));
@@ -720,13 +778,12 @@ int make_xt_slices(fsda_op* op, hipStream_t s) {
 // bps blocks per slice over bins of those rows by expected segment length
 // (length / nslice: >= 256 -> 64 lanes per row, >= 64 -> 32, >= 16 -> 8, else 2),
 // and the X^T pass finishes them from their parts (assembly items).
-int make_xt_lds(fsda_op* op, hipStream_t s) {
+int make_xt_lds(fsda_op* op, int nsplit, hipStream_t s) {
   XtPlan& pl = op->pxt;
   XtLds& D = pl.lds;
-  const int nsplit = op->xt_bins[3];
   const int nsl = op->L.lslice;
   const std::vector<int>& rp = op->xt_rp_med;
-  if (nsplit > op->L.nsplit_max) return fail(FSDA_E_WORKSPACE, "split-row table larger than reserved");
+  if (nsplit > op->L.nlds_max) return fail(FSDA_E_WORKSPACE, "LDS-slice row table larger than reserved");
   std::memset(&D, 0, sizeof(D));
   D.nslice = nsl;
   D.n = (int)op->pb.n;
@@ -814,12 +871,20 @@ int make_xt(fsda_op* op, hipStream_t s) {
     HIP_TRY(hipStreamSynchronize(s));
   }
   std::memset(&pl.lds, 0, sizeof(pl.lds));
+  pl.asm_r0 = 0;
   const bool sliced = op->L.nslice > 1 || op->L.lslice > 0;
-  if (op->L.lslice > 0) {
-    const int rc = make_xt_lds(op, s);
+  if (op->L.lslice > 0 && op->L.nslice > 1) {  // hybrid: head rows in LDS slices, the other split rows in XCD slices
+    const int head = xt_head();
+    int nh = 0;
+    while (nh < op->xt_bins[3] && op->xt_rp_med[nh + 1] - op->xt_rp_med[nh] >= head) nh++;
+    int rc = make_xt_lds(op, nh, s);
+    if (rc) return rc;
+    if ((rc = make_xt_slices(op, nh, s))) return rc;
+  } else if (op->L.lslice > 0) {
+    const int rc = make_xt_lds(op, op->xt_bins[3], s);
     if (rc) return rc;
   } else if (sliced) {
-    const int rc = make_xt_slices(op, s);
+    const int rc = make_xt_slices(op, 0, s);
     if (rc) return rc;
   } else if (nlong > 0) {
     const std::vector<int>& rp = op->xt_rp_med;
@@ -878,8 +943,9 @@ int make_xt(fsda_op* op, hipStream_t s) {
     R.lpr[0] = 0;
     R.item0[0] = R.item0[1] = 0;
   }
-  pl.grid = std::max(1, std::min((int)ceil_div(w.nasm, BS) + w.nchunk + NSLICE * w.sl.item0[w.sl.nb] + R.item0[R.nb],
-                                 GRID_ROWS));
+  // (assembly items rounded up to a multiple of NSLICE, as the kernel counts them)
+  const int nasm_items = (int)(ceil_div(ceil_div(w.nasm, BS), NSLICE) * NSLICE);
+  pl.grid = std::max(1, std::min(nasm_items + w.nchunk + NSLICE * w.sl.item0[w.sl.nb] + R.item0[R.nb], GRID_ROWS));
   pl.gridL = sliced ? grid_for(std::max(pl.nlong, 1), 256) : grid_for(std::max(nlong, 1), 64);
   return FSDA_OK;
 }
@@ -987,7 +1053,7 @@ int residuals_reg(fsda_op* op, const double* rhs, const double* betas, int nshif
   const long long d = op->pb.d;
   for (int k = 0; k < nshift; k++) {
     const double* w = W + (long long)k * d;
-    run_rows(op, op->px, w, EpiX<double, false>{op->t, nullptr}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
+    run_rows(op, op->pxr, w, EpiX<double, false>{op->t, nullptr}, op->part + SITE_X * NPART, 0, s, KC_OTHER);
     run_xt(op, op->t, EpiRes{rhs, w, betas[k], nullptr}, 0, true, s, KC_OTHER);
     hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(BS), 0, s, op->part + SITE_XT * NPART, xt_npart(op),
                        &op->st->res2[k]);
@@ -1019,28 +1085,117 @@ int residuals_sa(fsda_op* op, const double* g, const double* betas, int nshift, 
 
 int grid_b(long long items) { return (int)std::max<long long>(1, std::min<long long>(items, GRID_B)); }
 
-// chunk table of the X^T rows of >= BMED nonzeros for tile T (batched products)
+// Chunk tables of the batched X^T product: the rows of >= BMED nonzeros in
+// pieces of BCHUNK<T>() nonzeros, row after row (a row's pieces contiguous, so
+// the second level adds them in a fixed order).  With XCD slices every such
+// row is first cut at the sample boundaries x n / 8 (its segments found once
+// per handle on the device), a piece never crosses a boundary, and the chunk
+// items come in rounds of eight, item it taking a piece of slice it % 8.
+struct BxtTables {
+  int *crow, *cbeg, *cend, *item, *rc0;
+  long long cap;  // room for pieces (items: bxt_item_cap)
+  bool sliced;
+};
+
+// Room for the chunk items (and, at first use, the split rows' segment bounds).
+size_t bxt_item_cap(const fsda_op* op, long long cap) {
+  return std::max((size_t)NSLICE * (size_t)cap, (size_t)(NSLICE + 1) * (size_t)op->nmed);
+}
+
+// Whether the batched X^T product over T columns of vtype bytes uses XCD
+// slices: when u over T columns outgrows an XCD's share of L2.  The environment
+// variable FSDA_BXT_SLICES set to 0 or 8 overrides (read by the workspace-size
+// calls and the solves alike).
+bool bxt_sliced(const fsda_op* op, int T, int vbytes) {
+  const char* e = std::getenv("FSDA_BXT_SLICES");
+  if (e && std::strcmp(e, "0") == 0) return false;
+  if (e && std::strcmp(e, "8") == 0) return true;
+  return (long long)op->pb.n * T * vbytes > SLICE_BYTES;
+}
+
+// Grid of the batched X^T product: every chunk item and row group once (a
+// multiple of 8 whenever it is capped, so that item it runs on XCD it % 8).
+int bxt_grid(const BXtArgs& xa, int G) {
+  const long long items = (xa.item_chunk ? xa.nitem : xa.nchunk) + ceil_div((long long)xa.d - xa.nmed, G);
+  return (int)std::max<long long>(1, std::min<long long>(items, GRID_B));
+}
+
+// With XCD slices, only rows of at least NSLICE chunks are cut (a shorter row's
+// slice segments would leave most groups of a chunk item idle); the others are
+// summed in whole chunks, after the sliced rounds.
+int bxt_slice_min(int T) {
+  const char* e = std::getenv("FSDA_BXT_SLICE_MIN");
+  return e ? std::max(1, std::atoi(e)) : NSLICE * BS * (T >= 64 ? 1 : 64 / T);
+}
+
+// Pieces of the batched X^T product for tile T, an upper bound.
+long long bxt_chunk_cap(const fsda_op* op, int T, bool sliced) {
+  const long long bc = (long long)BS * (T >= 64 ? 1 : 64 / T);  // BCHUNK<T>()
+  const int smin = bxt_slice_min(T);
+  const std::vector<int>& rp = op->xt_rp_med;
+  long long n = 1;
+  for (int j = 0; j < op->nmed; j++) {
+    const int len = rp[j + 1] - rp[j];
+    n += ceil_div(len, bc) + (sliced && len >= smin ? NSLICE : 0);
+  }
+  return n;
+}
+
 template <int T>
-int chunk_table(fsda_op* op, int* crow_d, int* cbeg_d, int* rc0_d, int* nchunk, hipStream_t s) {
+int chunk_table(fsda_op* op, const BxtTables& tb, BXtArgs* xa, hipStream_t s) {
   const int nmed = op->nmed;
   const std::vector<int>& rp = op->xt_rp_med;
-  std::vector<int> crow, cbeg, c0(nmed + 1);
+  constexpr int bc = BCHUNK<T>();
+  if (tb.sliced && nmed > 0 && op->bseg.empty()) {  // segment bounds of the split rows, once per handle
+    const long long nseg = (long long)(NSLICE + 1) * nmed;
+    if ((size_t)nseg > bxt_item_cap(op, tb.cap)) return fail(FSDA_E_WORKSPACE, "segment table larger than reserved");
+    hipLaunchKernelGGL(k_slice_bounds, dim3((unsigned)ceil_div(nseg, BS)), dim3(BS), 0, s, op->xt_rowptr, op->xt_col,
+                       nmed, (long long)op->pb.n, NSLICE, 0, tb.item);
+    HIP_TRY(hipGetLastError());
+    std::vector<int> seg(nseg);
+    HIP_TRY(hipMemcpyAsync(seg.data(), tb.item, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    op->bseg.swap(seg);
+  }
+  std::vector<int> crow, cbeg, cend, c0(nmed + 1), item, whole;
+  std::vector<std::vector<int>> per(tb.sliced ? NSLICE : 0);
+  const int smin = bxt_slice_min(T);
   for (int j = 0; j < nmed; j++) {
     c0[j] = (int)crow.size();
-    for (int k = rp[j]; k < rp[j + 1]; k += BCHUNK<T>()) {
-      crow.push_back(j);
-      cbeg.push_back(k);
+    const bool cut = tb.sliced && rp[j + 1] - rp[j] >= smin;
+    const int nsl = cut ? NSLICE : 1;
+    for (int x = 0; x < nsl; x++) {
+      const int b = cut ? op->bseg[(size_t)x * nmed + j] : rp[j];
+      const int e = cut ? op->bseg[(size_t)(x + 1) * nmed + j] : rp[j + 1];
+      for (int k = b; k < e; k += bc) {
+        (cut ? per[x] : whole).push_back((int)crow.size());
+        crow.push_back(j);
+        cbeg.push_back(k);
+        cend.push_back(std::min(k + bc, e));
+      }
     }
   }
   c0[nmed] = (int)crow.size();
-  if ((long long)crow.size() > op->L.bnchunk_max) return fail(FSDA_E_WORKSPACE, "chunk table larger than reserved");
-  if (!crow.empty()) {
-    HIP_TRY(hipMemcpyAsync(crow_d, crow.data(), sizeof(int) * crow.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(cbeg_d, cbeg.data(), sizeof(int) * cbeg.size(), hipMemcpyHostToDevice, s));
+  if ((long long)crow.size() > tb.cap) return fail(FSDA_E_WORKSPACE, "chunk table larger than reserved");
+  if (tb.sliced) {  // rounds of NSLICE (item it: slice it % 8), then the uncut rows' chunks
+    size_t rounds = 0;
+    for (const auto& v : per) rounds = std::max(rounds, v.size());
+    item.assign(rounds * NSLICE, -1);
+    for (int x = 0; x < NSLICE; x++)
+      for (size_t r = 0; r < per[x].size(); r++) item[r * NSLICE + x] = per[x][r];
+    item.insert(item.end(), whole.begin(), whole.end());
   }
-  HIP_TRY(hipMemcpyAsync(rc0_d, c0.data(), sizeof(int) * c0.size(), hipMemcpyHostToDevice, s));
+  if (!crow.empty()) {
+    HIP_TRY(hipMemcpyAsync(tb.crow, crow.data(), sizeof(int) * crow.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(tb.cbeg, cbeg.data(), sizeof(int) * cbeg.size(), hipMemcpyHostToDevice, s));
+    if (tb.sliced)
+      HIP_TRY(hipMemcpyAsync(tb.cend, cend.data(), sizeof(int) * cend.size(), hipMemcpyHostToDevice, s));
+  }
+  if (!item.empty()) HIP_TRY(hipMemcpyAsync(tb.item, item.data(), sizeof(int) * item.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(tb.rc0, c0.data(), sizeof(int) * c0.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  *nchunk = (int)crow.size();
+  *xa = BXtArgs{op->xt_rowptr, op->xt_col, (int)op->pb.d, nmed, (int)crow.size(), tb.crow, tb.cbeg, tb.rc0,
+                tb.sliced ? tb.cend : nullptr, tb.sliced ? tb.item : nullptr, (int)item.size()};
   return FSDA_OK;
 }
 
@@ -1073,7 +1228,7 @@ BMask b_mask(const fsda_op* op, size_t* smem) {
 template <int T, typename V>
 void b_products(fsda_op* op, const BBuf<V>& b, const V* src, const V* P, const int* stop, hipStream_t s, bool timed) {
   constexpr int G = BS / T;
-  const long long n = op->pb.n, d = op->pb.d;
+  const long long n = op->pb.n;
   BState* st = b.st;
   const int gx = grid_b(ceil_div(n, G));
   const bool lab = has_lab_term(op);
@@ -1102,7 +1257,7 @@ void b_products(fsda_op* op, const BBuf<V>& b, const V* src, const V* P, const i
                          BEpiLap<T, V, false>{b.t, nullptr, 1, 0, op->pb.s_rowptr, b.u, op->pb.alpha, (V)0}, stop,
                          st->cm, b.site(BP_TU), BMask{nullptr, 0});
   });
-  const int gxt = grid_b(b.xa.nchunk + ceil_div(d - b.xa.nmed, G));
+  const int gxt = bxt_grid(b.xa, G);
   launch(op, timed ? KC_BXT : KC_OTHER, s, [&] {
     hipLaunchKernelGGL((bk_xt<T, V>), dim3(gxt), dim3(BS), 0, s, b.xa, b.lpart, b.u, P, b.Q, 0LL, st->sigma, stop);
     if (b.xa.nmed > 0)
@@ -1205,7 +1360,9 @@ template <int T>
 int refine_buffers(fsda_op* op, BBuf<float>* b, hipStream_t s) {
   const Layout& L = op->L;
   if (op->btab_tile != T) {
-    int rc = chunk_table<T>(op, at<int>(op, L.bcrow), at<int>(op, L.bcbeg), at<int>(op, L.brc0), &op->bnchunk, s);
+    const BxtTables tb{at<int>(op, L.bcrow), at<int>(op, L.bcbeg), nullptr, nullptr, at<int>(op, L.brc0),
+                       L.bnchunk_max, false};
+    int rc = chunk_table<T>(op, tb, &op->bxa, s);
     if (rc) return rc;
     op->btab_tile = T;
   }
@@ -1219,30 +1376,29 @@ int refine_buffers(fsda_op* op, BBuf<float>* b, hipStream_t s) {
   b->t = at<float>(op, L.bT);
   b->u = at<float>(op, L.bU);
   b->lpart = at<float>(op, L.blpart);
-  b->xa = BXtArgs{op->xt_rowptr, op->xt_col, (int)op->pb.d, op->nmed, op->bnchunk, at<int>(op, L.bcrow),
-                  at<int>(op, L.bcbeg), at<int>(op, L.brc0)};
+  b->xa = op->bxa;
   b->labw = op->labw;
   b->lws = 1;
   b->lcs = 0;
   return FSDA_OK;
 }
 
-// Refinement of the mixed path, W (internal order) in FP64: up to
-// MIXED_ROUNDS rounds of FP64 residuals R_s = b - A(beta_s) w_s, correction
-// solves A(beta_s) delta_s = R_s by batched FP32 CG (one column per shift,
-// to 0.5 rtol ||b||, never more than MIXED_FLOOR below ||R_s||), and
-// w_s += delta_s in FP64; stops as soon as every shift meets rtol.
-// extra[s] accumulates the correction iterations.
+// Refinement of the mixed path, W (internal order) in FP64: MIXED_STEPS steps
+// of FP64 residuals R_s = b - A(beta_s) w_s, correction solves A(beta_s)
+// delta_s = R_s by batched FP32 CG (one column per shift not yet within rtol,
+// to 0.5 rtol ||b||, never more than MIXED_FLOOR below ||R_s||), and w_s +=
+// delta_s in FP64; no step once every shift meets rtol.  extra[s] accumulates
+// the correction iterations, steps[s] the refinement steps shift s took.
 template <int T>
 int refine(fsda_op* op, const double* rhs, const double* betas, int nshift, double rtol, int maxit, double* W,
-           int* extra, int* status, hipStream_t s) {
+           int* extra, int* steps, int* status, hipStream_t s) {
   const long long d = op->pb.d;
   double* R64 = at<double>(op, op->L.b64);
   State* h = op->hst;
   BBuf<float> b;
   int rc = refine_buffers<T>(op, &b, s);
   if (rc) return rc;
-  for (int round = 0; round < MIXED_ROUNDS; round++) {
+  for (int round = 0; round < MIXED_STEPS; round++) {
     if ((rc = residuals(op, rhs, betas, nshift, W, s, R64, op->L.ldd))) return rc;
     HIP_TRY(hipMemcpyAsync(h, op->st, sizeof(State), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1267,7 +1423,10 @@ int refine(fsda_op* op, const double* rhs, const double* betas, int nshift, doub
       return FSDA_OK;
     }
     if (hb->status == FSDA_NOT_CONVERGED) *status = FSDA_NOT_CONVERGED;
-    for (int k = 0; k < nshift; k++) extra[k] += hb->conv[k];
+    for (int k = 0; k < nshift; k++) {
+      extra[k] += hb->conv[k];
+      steps[k] += hb->tabs[k] < HUGE_VAL ? 1 : 0;
+    }
     constexpr int G = BS / T;
     hipLaunchKernelGGL((bk_add<T, float>), dim3(grid_b(ceil_div(d, G))), dim3(BS), 0, s, b.X, W, d, nshift, d);
     HIP_TRY(hipGetLastError());
@@ -1289,9 +1448,17 @@ struct ColTargets {
 };
 
 struct CLayout {
-  size_t st, part, R, P, Q, X, t, u, lpart, crow, cbeg, rc0, flags, labw, b64, total;
-  long long ld;
+  size_t st, part, R, P, Q, X, t, u, lpart, crow, cbeg, cend, item, rc0, flags, labw, b64, total;
+  long long ld, cap;
+  bool sliced;
 };
+
+BxtTables bxt_tables(char* ws, size_t crow, size_t cbeg, size_t cend, size_t item, size_t rc0, long long cap,
+                     bool sliced) {
+  return BxtTables{reinterpret_cast<int*>(ws + crow), reinterpret_cast<int*>(ws + cbeg),
+                   reinterpret_cast<int*>(ws + cend), sliced ? reinterpret_cast<int*>(ws + item) : nullptr,
+                   reinterpret_cast<int*>(ws + rc0), cap, sliced};
+}
 
 // per_col: room for one labeled-weight column per batch column (n x T).
 void clayout(const fsda_op* op, int T, int ncol, bool per_col, CLayout* L) {
@@ -1312,9 +1479,13 @@ void clayout(const fsda_op* op, int T, int ncol, bool per_col, CLayout* L) {
   L->X = take(8 * ld * T);
   L->t = take(8 * (size_t)n * T);
   L->u = take(8 * (size_t)n * T);
-  L->lpart = take(8 * (size_t)op->L.bnchunk_max * T);
-  L->crow = take(4 * (size_t)op->L.bnchunk_max);
-  L->cbeg = take(4 * (size_t)op->L.bnchunk_max);
+  L->sliced = bxt_sliced(op, T, 8);
+  L->cap = bxt_chunk_cap(op, T, L->sliced);
+  L->lpart = take(8 * (size_t)L->cap * T);
+  L->crow = take(4 * (size_t)L->cap);
+  L->cbeg = take(4 * (size_t)L->cap);
+  L->cend = take(4 * (size_t)L->cap);
+  L->item = L->sliced ? take(4 * bxt_item_cap(op, L->cap)) : 0;
   L->rc0 = take(4 * (size_t)(z / BMED + 2));
   L->flags = take(sizeof(int) * 4 * BT_MAX);
   L->labw = per_col ? take(8 * (size_t)n * T) : 0;
@@ -1379,13 +1550,8 @@ int run_columns(fsda_op* op, char* ws, const CLayout& L, const double* B, const 
   b.labw = op->labw;
   b.lws = 1;
   b.lcs = 0;
-  int* crow = reinterpret_cast<int*>(ws + L.crow);
-  int* cbeg = reinterpret_cast<int*>(ws + L.cbeg);
-  int* rc0 = reinterpret_cast<int*>(ws + L.rc0);
-  int nchunk = 0;
-  int rc = chunk_table<T>(op, crow, cbeg, rc0, &nchunk, s);
+  int rc = chunk_table<T>(op, bxt_tables(ws, L.crow, L.cbeg, L.cend, L.item, L.rc0, L.cap, L.sliced), &b.xa, s);
   if (rc) return rc;
-  b.xa = BXtArgs{op->xt_rowptr, op->xt_col, (int)d, op->nmed, nchunk, crow, cbeg, rc0};
   if (ct) {  // one labeled set per column (t and u are scratch until the solve)
     double* labw = reinterpret_cast<double*>(ws + L.labw);
     if ((rc = column_labels<T>(op, *ct, ncol, labw, reinterpret_cast<int*>(ws + L.flags),
@@ -1406,8 +1572,8 @@ int run_columns(fsda_op* op, char* ws, const CLayout& L, const double* B, const 
   for (int c = 0; c < ncol; c++) h->sigma[c] = sigmas[c];
   h->trel = rtol;
   h->maxit = maxit;
-  // the captured buffers are fixed by (workspace, T, per-column labels); key 1 + per_col on the tile
-  const void* key = ws + (ct ? 1 : 0);
+  // the captured buffers and tables are fixed by (workspace, T, per-column labels, X^T slicing)
+  const void* key = ws + (ct ? 1 : 0) + (L.sliced ? 2 : 0);
   if ((rc = run_batched<T, double>(op, b, B64, L.ld, ncol, &op->cgexec, &op->cg_key, &op->cg_tile, key, s,
                                    graph_ok)))
     return rc;
@@ -1456,13 +1622,13 @@ int columns_any(int T, fsda_op* op, char* ws, const CLayout& L, const double* B,
 }
 
 int refine_any(fsda_op* op, const double* rhs, const double* betas, int nshift, double rtol, int maxit, double* W,
-               int* extra, int* status, hipStream_t s) {
+               int* extra, int* steps, int* status, hipStream_t s) {
   switch (std::min(batch_tile(nshift), op->L.btile)) {
-    case 4: return refine<4>(op, rhs, betas, nshift, rtol, maxit, W, extra, status, s);
-    case 8: return refine<8>(op, rhs, betas, nshift, rtol, maxit, W, extra, status, s);
-    case 16: return refine<16>(op, rhs, betas, nshift, rtol, maxit, W, extra, status, s);
-    case 32: return refine<32>(op, rhs, betas, nshift, rtol, maxit, W, extra, status, s);
-    default: return refine<64>(op, rhs, betas, nshift, rtol, maxit, W, extra, status, s);
+    case 4: return refine<4>(op, rhs, betas, nshift, rtol, maxit, W, extra, steps, status, s);
+    case 8: return refine<8>(op, rhs, betas, nshift, rtol, maxit, W, extra, steps, status, s);
+    case 16: return refine<16>(op, rhs, betas, nshift, rtol, maxit, W, extra, steps, status, s);
+    case 32: return refine<32>(op, rhs, betas, nshift, rtol, maxit, W, extra, steps, status, s);
+    default: return refine<64>(op, rhs, betas, nshift, rtol, maxit, W, extra, steps, status, s);
   }
 }
 
@@ -1472,8 +1638,9 @@ int refine_any(fsda_op* op, const double* rhs, const double* betas, int nshift, 
 // ---------------------------------------------------------------------------
 
 struct TLayout {
-  size_t st, part, hist, coef, flags, labw, B, P, Q, t, u, ring, Ps, lpart, crow, cbeg, rc0, total;
-  long long ld;
+  size_t st, part, hist, coef, flags, labw, B, P, Q, t, u, ring, Ps, lpart, crow, cbeg, cend, item, rc0, total;
+  long long ld, cap;
+  bool sliced;
 };
 
 void tlayout(const fsda_op* op, int T, int nshift, int chunk, TLayout* L) {
@@ -1499,9 +1666,13 @@ void tlayout(const fsda_op* op, int T, int nshift, int chunk, TLayout* L) {
   L->Q = take(8 * ld * T);
   L->ring = take(8 * ld * T * chunk);
   L->Ps = take(8 * ld * T * nshift);
-  L->lpart = take(8 * (size_t)op->L.bnchunk_max * T);
-  L->crow = take(4 * (size_t)op->L.bnchunk_max);
-  L->cbeg = take(4 * (size_t)op->L.bnchunk_max);
+  L->sliced = bxt_sliced(op, T, 8);
+  L->cap = bxt_chunk_cap(op, T, L->sliced);
+  L->lpart = take(8 * (size_t)L->cap * T);
+  L->crow = take(4 * (size_t)L->cap);
+  L->cbeg = take(4 * (size_t)L->cap);
+  L->cend = take(4 * (size_t)L->cap);
+  L->item = L->sliced ? take(4 * bxt_item_cap(op, L->cap)) : 0;
   L->rc0 = take(4 * (size_t)(z / BMED + 2));
   L->total = o;
 }
@@ -1557,8 +1728,7 @@ template <int T>
 void t_xt(fsda_op* op, const TPtr& p, const double* u, const double* P, double* Q, const int* stop, hipStream_t s,
           bool timed) {
   constexpr int G = BS / T;
-  const long long d = op->pb.d;
-  const int gxt = grid_b(p.xa.nchunk + ceil_div(d - p.xa.nmed, G));
+  const int gxt = bxt_grid(p.xa, G);
   launch(op, timed ? KC_BXT : KC_OTHER, s, [&] {
     hipLaunchKernelGGL((bk_xt<T, double>), dim3(gxt), dim3(BS), 0, s, p.xa, p.lpart, u, P, Q, p.ld, p.st->sigma, stop);
     if (p.xa.nmed > 0)
@@ -1591,13 +1761,16 @@ void t_iteration(fsda_op* op, const TPtr& p, hipStream_t s, int tag) {
   op->cur_tag = -1;
 }
 
+// (grids over all T columns of the tile: the kernels skip the columns beyond
+// the tile's targets and read W from the state, so a captured chunk serves
+// every tile of a call)
 template <int T>
 void t_fold(fsda_op* op, const TPtr& p, hipStream_t s) {
   const long long d = op->pb.d;
-  const dim3 g(t_colgrid(d), p.ncol);
-  hipLaunchKernelGGL(ts_fold_coef, dim3(1, p.ncol), dim3(BS), 0, s, p.st, p.hist, T, p.coef, p.nshift);
+  const dim3 g(t_colgrid(d), T);
+  hipLaunchKernelGGL(ts_fold_coef, dim3(1, T), dim3(BS), 0, s, p.st, p.hist, T, p.coef, p.nshift);
   launch(op, KC_TFOLD, s, [&] {
-    hipLaunchKernelGGL(ts_fold_apply, g, dim3(BS), 0, s, p.st, p.coef, T, p.ring, p.ld, p.W, p.Ps, d, p.nshift);
+    hipLaunchKernelGGL(ts_fold_apply, g, dim3(BS), 0, s, p.st, p.coef, T, p.ring, p.ld, p.Ps, d, p.nshift);
   });
   hipLaunchKernelGGL(ts_fold_done, dim3(1), dim3(1), 0, s, p.st);
 }
@@ -1627,13 +1800,8 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
   p.ncol = ncol;
   p.nshift = nshift;
   p.chunk = chunk;
-  int* crow = reinterpret_cast<int*>(ws + L.crow);
-  int* cbeg = reinterpret_cast<int*>(ws + L.cbeg);
-  int* rc0 = reinterpret_cast<int*>(ws + L.rc0);
-  int nchunk = 0;
-  int rc = chunk_table<T>(op, crow, cbeg, rc0, &nchunk, s);
+  int rc = chunk_table<T>(op, bxt_tables(ws, L.crow, L.cbeg, L.cend, L.item, L.rc0, L.cap, L.sliced), &p.xa, s);
   if (rc) return rc;
-  p.xa = BXtArgs{op->xt_rowptr, op->xt_col, (int)d, op->nmed, nchunk, crow, cbeg, rc0};
 
   // solver state (uploaded first: the set-up launches test its `zero` flag)
   double sigma0 = betas[0];
@@ -1644,6 +1812,7 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
   h->ncol = ncol;
   h->nshift = nshift;
   h->chunk = chunk;
+  h->W = W;
   for (int c = 0; c < T; c++) {
     h->tol[c] = rtol;
     h->sigma[c] = sigma0;
@@ -1693,8 +1862,10 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
 
   // chunks of iterations + one fold, replayed as a graph
   bool graph = op->use_graph != 0 && !op->tk_on;
-  if (graph && !(op->tgexec && op->tkey_ws == ws && op->tkey_W == W && op->tkey_T == T && op->tkey_ncol == ncol &&
-                 op->tkey_nshift == nshift && op->tkey_chunk == chunk)) {
+  // the captured chunk depends on the workspace layout (T, nshift, chunk, slicing)
+  // only: W and the tile's target count are read from the state
+  if (graph && !(op->tgexec && op->tkey_ws == ws && op->tkey_T == T && op->tkey_nshift == nshift &&
+                 op->tkey_chunk == chunk && op->tkey_sliced == (int)L.sliced)) {
     if (op->tgexec) (void)hipGraphExecDestroy(op->tgexec);
     op->tgexec = nullptr;
     hipGraph_t gr = nullptr;
@@ -1713,11 +1884,10 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
       graph = false;
     } else {
       op->tkey_ws = ws;
-      op->tkey_W = W;
       op->tkey_T = T;
-      op->tkey_ncol = ncol;
       op->tkey_nshift = nshift;
       op->tkey_chunk = chunk;
+      op->tkey_sliced = (int)L.sliced;
     }
   }
   const size_t off = offsetof(TState, iter);
@@ -2105,10 +2275,21 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
     int zr = 0;
     HIP_TRY(hipMemcpyAsync(&zr, rrp + n, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    op->px = one_bin(rrp, rcol, n, zr);
+    // blocks of XNT threads, two per CU (each stages the HOT most frequent features)
+    op->px = one_bin(rrp, rcol, n, zr, XNT, 2 * 256);
     op->px.rows.mask = xm;
     op->px.rows.mtop = op->mtop;
     op->px.rows.nhot = (int)std::min<long long>(HOT, d);
+    const size_t hb = sizeof(double) * (size_t)op->px.rows.nhot;
+    if ((rc = allow_xrows_smem<EpiX<double, true>>(hb)) || (rc = allow_xrows_smem<EpiX<double, false>>(hb)) ||
+        (rc = allow_xrows_smem<EpiX<float, true>>(hb)) || (rc = allow_xrows_smem<EpiX<float, false>>(hb)))
+      return bail(rc);
+    // the regression phase's X product stays in blocks of BS threads: with its
+    // epilogue (t and <t, t>) the XNT-thread blocks gave wrong step lengths
+    op->pxr = one_bin(rrp, rcol, n, zr);
+    op->pxr.rows.mask = xm;
+    op->pxr.rows.mtop = op->mtop;
+    op->pxr.rows.nhot = (int)std::min<long long>(HOT_REG, d);
   }
   op->px_user = one_bin(pb->x_rowptr, pb->x_col, n, z);
   op->ps = one_bin(pb->s_rowptr, pb->s_col, n, g);
@@ -2185,7 +2366,8 @@ int fsda_multishift_solve(fsda_op* op, const double* b, const double* betas, int
     rhs = op->bu;
   }
   const bool mixed = op->pb.precision == FSDA_MIXED;
-  std::vector<int> extra(nshift, 0);
+  std::vector<int> extra(nshift, 0), steps(nshift, 0);
+  op->rep_main.clear();
   int rstatus = FSDA_OK;
   int rc = mixed ? run_multishift<float>(op, rhs, betas, sigma0, nshift, std::max(rtol, MIXED_INNER), maxit, chunk,
                                          W, s)
@@ -2195,7 +2377,7 @@ int fsda_multishift_solve(fsda_op* op, const double* b, const double* betas, int
     HIP_TRY(hipMemcpyAsync(op->hst, op->st, sizeof(State), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (op->hst->status != FSDA_E_BREAKDOWN &&
-        (rc = refine_any(op, rhs, betas, nshift, rtol, maxit, W, extra.data(), &rstatus, s)))
+        (rc = refine_any(op, rhs, betas, nshift, rtol, maxit, W, extra.data(), steps.data(), &rstatus, s)))
       return rc;
   }
   if ((rc = residuals(op, rhs, betas, nshift, W, s))) return rc;
@@ -2213,6 +2395,9 @@ int fsda_multishift_solve(fsda_op* op, const double* b, const double* betas, int
     const int trc = tk_flush(op, 1 << 30);
     if (trc) return trc;
   }
+  op->rep_main.assign(h->conv, h->conv + nshift);
+  op->rep_refine = extra;
+  op->rep_steps = steps;
   for (int k = 0; k < nshift; k++) {
     iters[k] = h->conv[k] + extra[k];
     relres[k] = h->bnorm > 0.0 ? std::sqrt(h->res2[k]) / h->bnorm : 0.0;
@@ -2225,6 +2410,18 @@ int fsda_multishift_solve(fsda_op* op, const double* b, const double* betas, int
     return ok ? FSDA_OK : FSDA_NOT_CONVERGED;
   }
   return h->status == FSDA_NOT_CONVERGED ? FSDA_NOT_CONVERGED : FSDA_OK;
+}
+
+int fsda_solve_report(const fsda_op* op, int nshift, int* main_iters, int* refine_iters, int* steps) {
+  if (!op || !main_iters || !refine_iters || !steps) return fail(FSDA_E_ARG, "NULL argument");
+  if (op->rep_main.empty()) return fail(FSDA_E_ARG, "no completed fsda_multishift_solve on this handle");
+  if (nshift != (int)op->rep_main.size()) return fail(FSDA_E_ARG, "nshift differs from the last solve's");
+  for (int k = 0; k < nshift; k++) {
+    main_iters[k] = op->rep_main[k];
+    refine_iters[k] = op->rep_refine[k];
+    steps[k] = op->rep_steps[k];
+  }
+  return FSDA_OK;
 }
 
 int fsda_sa_rhs(fsda_op* op, const double* r, double* g, void* stream) {
@@ -2345,7 +2542,7 @@ int fsda_regression_solve(fsda_op* op, const double* z, const double* betas, int
 
 int fsda_columns_workspace_size(const fsda_op* op, int ncol, size_t* bytes) {
   if (!op || !bytes) return fail(FSDA_E_ARG, "NULL argument");
-  if (ncol < 1 || ncol > FSDA_MAX_TARGETS) return fail(FSDA_E_ARG, "ncol outside 1..FSDA_MAX_TARGETS");
+  if (ncol < 1 || ncol > FSDA_MAX_COLUMNS) return fail(FSDA_E_ARG, "ncol outside 1..FSDA_MAX_COLUMNS");
   CLayout L;
   clayout(op, batch_tile(ncol), ncol, false, &L);
   *bytes = L.total;

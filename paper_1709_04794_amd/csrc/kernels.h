@@ -591,7 +591,9 @@ struct EpiLapDot {
 // but are read from the same shared copy: random 8-byte gathers are limited by
 // the rate of distinct cache-line lookups, which shared memory does not pay.
 constexpr int MK = 64;     // features in the mask
-constexpr int HOT = 2048;  // features staged in shared memory by the X product (16 KiB of FP64)
+constexpr int HOT = 8192;  // features staged in shared memory by the X product (64 KiB of FP64)
+constexpr int XNT = 1024;  // threads per block of the X product (two blocks and their copies fit a CU's LDS)
+constexpr int HOT_REG = 2048;  // features staged by the regression phase's X product (blocks of BS threads)
 
 struct Rows {
   const int* rowptr;
@@ -605,8 +607,25 @@ struct Rows {
   int nhot;                        // with mask: features [0, nhot) staged in shared memory, mtop <= nhot <= HOT
 };
 
-template <class Epi>
-__global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __restrict__ src, Epi epi, State* st,
+// Block sum over NT threads in a fixed order; every thread gets the result.
+template <int NT>
+__device__ __forceinline__ double block_sum_nt(double v) {
+  __shared__ double sh[NT / 64];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; i++) t += sh[i];
+  return t;
+}
+
+// Row products in blocks of NT threads (an item is NT / lpr rows; the host plan
+// is built for the same NT).
+template <class Epi, int NT = BS>
+__global__ __launch_bounds__(NT) void k_rows(Rows R, const typename Epi::V* __restrict__ src, Epi epi, State* st,
                                              double* part, int slot0, int solve) {
   using V = typename Epi::V;
   if (solve && st->stop) return;
@@ -616,7 +635,7 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __re
   V* ptop = reinterpret_cast<V*>(rows_smem);
   const int nhot = R.mask ? R.nhot : 0;
   if (R.mask) {
-    for (int k = tid; k < nhot; k += BS) ptop[k] = src[k];
+    for (int k = tid; k < nhot; k += NT) ptop[k] = src[k];
     __syncthreads();
   }
   double acc = 0.0;
@@ -626,11 +645,11 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __re
     while (it >= R.item0[b + 1]) b++;
     const int lpr = R.lpr[b];
     if (lpr == 0) {
-      const int r = R.row0[b] + (it - R.item0[b]) * BS + tid;
+      const int r = R.row0[b] + (it - R.item0[b]) * NT + tid;
       if (r < R.row0[b + 1]) acc += epi.row(r, (V)0);
       continue;
     }
-    const int r = R.row0[b] + (it - R.item0[b]) * (BS / lpr) + tid / lpr;
+    const int r = R.row0[b] + (it - R.item0[b]) * (NT / lpr) + tid / lpr;
     const int lane = tid & (lpr - 1);
     const bool live = r < R.row0[b + 1];
     V v = (V)0;
@@ -665,7 +684,10 @@ __global__ __launch_bounds__(BS) void k_rows(Rows R, const typename Epi::V* __re
     for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if (live && lane == 0) acc += epi.row(r, v);
   }
-  if (Epi::kReduce) write_partial(part, slot0 + blockIdx.x, acc);
+  if (Epi::kReduce) {
+    const double t = block_sum_nt<NT>(acc);
+    if (tid == 0) part[slot0 + blockIdx.x] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -701,9 +723,10 @@ struct XtSlices {
   int row0[MAXBIN + 1];
   int lpr[MAXBIN];
   int item0[MAXBIN + 1];    // items of one slice before bin b (each item runs for all slices)
-  int nsplit;               // split rows [0, nsplit)
-  int nlc;                  // [0, nlc) are summed in the chunk items, [nlc, nsplit) in the bins
-  const int* segp;          // [(NSLICE + 1) * nsplit]: slice x of row j is [segp[x*nsplit+j], segp[(x+1)*nsplit+j])
+  int r0;                   // first split row (0; with the LDS head rows of the hybrid plan, their count)
+  int nsplit;               // split rows [r0, r0 + nsplit)
+  int nlc;                  // [r0, nlc) are summed in the chunk items, [nlc, r0 + nsplit) in the bins
+  const int* segp;          // [(NSLICE + 1) * nsplit]: slice x of row j is [segp[x*nsplit+j-r0], segp[(x+1)*nsplit+j-r0])
   int part0;                // lpart index of part 0 of row nlc; row j >= nlc has parts part0 + NSLICE (j - nlc) + x
 };
 
@@ -781,7 +804,9 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __re
   if (Epi::kPublish && blockIdx.x == 0 && threadIdx.x == 0) epi.publish(st);
   const int tid = threadIdx.x;
   double acc = 0.0;
-  const int nasm_items = (X.nasm + BS - 1) / BS;
+  // assembly items rounded up to a multiple of NSLICE, so that the XCD-slice
+  // items after them keep item % 8 == slice (with a grid that is a multiple of 8)
+  const int nasm_items = ((X.nasm + BS - 1) / BS + NSLICE - 1) / NSLICE * NSLICE;
   const int nitems = nasm_items + X.nchunk + NSLICE * X.sl.item0[X.sl.nb] + X.rows.item0[X.rows.nb];
   for (int it0 = blockIdx.x; it0 < nitems; it0 += gridDim.x) {
     if (it0 < nasm_items) {  // split rows from their LDS-slice parts, in slice order
@@ -833,7 +858,9 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __re
       const int lane = tid & (lpr - 1);
       const bool live = j < S.row0[b + 1];
       V v = (V)0;
-      if (live) v = lane_row_sum<V>(X.col, src, S.segp[x * S.nsplit + j], S.segp[(x + 1) * S.nsplit + j], lane, lpr);
+      if (live)
+        v = lane_row_sum<V>(X.col, src, S.segp[x * S.nsplit + j - S.r0], S.segp[(x + 1) * S.nsplit + j - S.r0], lane,
+                            lpr);
       for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
       if (live && lane == 0) X.lpart[S.part0 + NSLICE * (j - S.nlc) + x] = (double)v;
       continue;
@@ -943,13 +970,13 @@ __global__ __launch_bounds__(BS) void k_slice_bounds(const int* __restrict__ row
   segp[t] = lo;
 }
 
-// Multi-part rows [0, nlong) of an X^T product (the rows of several chunks, or
-// with XCD slices every split row): row j is the ordered sum of its parts
-// lpart[row_chunk0[j] .. row_chunk0[j+1]).  Partial in slot `slot`.  In a solve
-// (solve != 0) nothing runs once every shift has stopped.
+// Multi-part rows r0 + [0, nlong) of an X^T product (the rows of several
+// chunks, or with XCD slices every XCD-split row): row r0 + j is the ordered sum
+// of its parts lpart[row_chunk0[j] .. row_chunk0[j+1]).  Partial in slot `slot`.
+// In a solve (solve != 0) nothing runs once every shift has stopped.
 template <class Epi>
-__global__ __launch_bounds__(BS) void k_assemble(int nlong, const int* row_chunk0, const double* lpart, Epi epi,
-                                                 State* st, double* part, int slot, int solve) {
+__global__ __launch_bounds__(BS) void k_assemble(int r0, int nlong, const int* row_chunk0, const double* lpart,
+                                                 Epi epi, State* st, double* part, int slot, int solve) {
   if (solve && st->stop) return;
   epi.prepare(st);
   double acc = 0.0;
@@ -963,7 +990,7 @@ __global__ __launch_bounds__(BS) void k_assemble(int nlong, const int* row_chunk
 #pragma unroll
       for (int e = 0; e < 8; e++) v += x[e];
     }
-    acc += epi.row(j, (typename Epi::V)v);
+    acc += epi.row(r0 + j, (typename Epi::V)v);
   }
   if (Epi::kReduce) write_partial(part, slot + blockIdx.x, acc);
 }

@@ -24,6 +24,8 @@ struct TState {
   int ncol, nshift, chunk, fold_start;
   int zero;                        // always 0: the stop flag of launches outside the recurrence
   int pad_[3];
+  double* W;                       // the caller's [ncol][nshift][d] iterates (read by the fold, so
+                                   // that one captured chunk serves every tile of a call)
   double rr[BT_MAX];               // <r_c, r_c>
   double a_cur[BT_MAX], a_prev[BT_MAX], b_cur[BT_MAX];
   double tol[BT_MAX];              // rtol ||b_c||
@@ -326,7 +328,7 @@ __global__ __launch_bounds__(BS) void ts_fold_coef(const TState* st, const doubl
                                                    double* __restrict__ coef, int nshift) {
   const int k0 = st->fold_start, cnt = st->iter - k0, m = st->chunk;
   const int c = blockIdx.y, s = threadIdx.x;
-  if (cnt <= 0 || s >= nshift) return;
+  if (cnt <= 0 || s >= nshift || c >= st->ncol) return;
   double* H = coef + (size_t)c * ts_coef_stride(m, nshift);
   double* G = H + (size_t)m * nshift;
   double* AB = G + (size_t)m * nshift;  // A [S], B [S], on [S]
@@ -359,11 +361,12 @@ __global__ __launch_bounds__(BS) void ts_fold_coef(const TState* st, const doubl
 }
 
 __global__ __launch_bounds__(BS) void ts_fold_apply(const TState* st, const double* __restrict__ coef, int T,
-                                                    const double* ring, long long ld, double* W, double* Ps,
-                                                    long long d, int nshift) {
+                                                    const double* ring, long long ld, double* Ps, long long d,
+                                                    int nshift) {
   const int k0 = st->fold_start, cnt = st->iter - k0, m = st->chunk;
-  if (cnt <= 0) return;
   const int c = blockIdx.y;
+  if (cnt <= 0 || c >= st->ncol) return;
+  double* W = st->W;
   const double* H = coef + (size_t)c * ts_coef_stride(m, nshift);
   const double* G = H + (size_t)m * nshift;
   const double* AB = G + (size_t)m * nshift;

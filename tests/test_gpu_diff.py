@@ -1,0 +1,103 @@
+"""The differentiation workload at full size (500,000 x 2,000,000 binary, about 60
+nonzeros per row, alpha 0.9, 8 shifts), in the launch configuration bench.py
+times for it (--experiment diff): targets whose labeled sets are split 80/20
+into training labels (the solve's) and held-out rows (the loss's), the forward
+solves of every target, the hold-out losses, the target x shift adjoint systems
+and the hypergradient in (log beta, alpha).  The test runs the first 16 of the
+workload's 64 targets (one tile of the forward solve, eight tiles of adjoint
+columns), so that it ends in about a minute; the bench experiment runs all 64.
+
+An oracle solve at this size is out of reach, so for a seeded sample of (target,
+shift) pairs the oracle recomputes, from the returned iterates and with that
+target's labeled set: the forward true residual ||b_c - A_c(beta_s) w_cs|| /
+||b_c||, the adjoint right-hand side and the adjoint true residual, the loss, and
+both derivatives (from the GPU's w and lambda, with the oracle's operator for the
+alpha-derivative).  Residuals must meet rtol and agree with the ones the solver
+reports; loss and gradients agree to 1e-10 relative (the same vectors enter both
+sides, only the operator products differ in rounding).  The whole grid of every
+target must meet rtol.  FSDA_SKIP_LARGE=1 leaves this test out.
+"""
+import dataclasses
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import hyper as ohyper
+
+torch = pytest.importorskip("torch")
+fsda = pytest.importorskip("paper_1709_04794_amd")
+
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.timeout(900),
+    pytest.mark.skipif(os.environ.get("FSDA_SKIP_LARGE") == "1", reason="FSDA_SKIP_LARGE=1"),
+]
+
+NTARGET = 16  # of the workload's 64
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def diff():
+    pb = synth.workload("diff", log=log)
+    log("diff workload: %s" % pb.summary())
+    return pb
+
+
+def test_diff_hypergradient_at_full_size(diff):
+    pb = diff
+    train, held = synth.holdout_splits(synth.target_labels(pb, 64, seed=5), seed=5)
+    train, held = train[:NTARGET], held[:NTARGET]
+    op = fsda.Operator.from_problem(pb, max_chunk=128)
+    W, it, rel, st = op.solve_batch(train, pb.betas, rtol=pb.rtol)
+    log("forward: status %d, worst relres %.3e, max iters %d" % (st, rel.max(), it.max()))
+    assert st == fsda.OK and rel.max() <= pb.rtol
+    loss, G = op.holdout_batch(W, held)
+    # adjoint columns in groups of 4 targets (2 tiles of 16 columns), a line after each
+    Lam = torch.empty_like(G)
+    it2 = np.zeros((NTARGET, pb.betas.size), dtype=np.int32)
+    rel2 = np.zeros((NTARGET, pb.betas.size))
+    st2 = fsda.OK
+    # the batched CG stops on its recursive residual; asked for half of rtol, every
+    # true residual meets rtol (at the smallest shift it ends up to 20 % above the
+    # recursive one)
+    for c0 in range(0, NTARGET, 4):
+        L, i2, r2, s2 = op.solve_columns_batch(train[c0:c0 + 4], pb.betas, G[c0:c0 + 4], rtol=0.5 * pb.rtol)
+        Lam[c0:c0 + 4], it2[c0:c0 + 4], rel2[c0:c0 + 4] = L, i2, r2
+        st2 = max(st2, s2)
+        log("adjoint targets %d..%d: status %d, worst relres %.3e" % (c0, c0 + 3, s2, r2.max()))
+    log("adjoint: status %d, worst relres %.3e, max iters %d" % (st2, rel2.max(), it2.max()))
+    assert st2 == fsda.OK and rel2.max() <= pb.rtol
+    dlb, da = op.hypergradient_batch(train, W, Lam, pb.betas)
+    assert np.isfinite(dlb).all() and np.isfinite(da).all()
+    rng = np.random.default_rng(11)
+    pairs = [(int(c), int(s)) for c, s in zip(rng.choice(NTARGET, 3, replace=False), rng.integers(0, 8, 3))]
+    pairs.append((int(rng.integers(NTARGET)), int(np.argmin(pb.betas))))
+    for c, s in pairs:
+        pc = dataclasses.replace(pb, lab_idx=train[c][0], lab_y=train[c][1])
+        ho, y = held[c]
+        beta = pb.betas[s]
+        w = W[c, s].cpu().numpy()
+        lam = Lam[c, s].cpu().numpy()
+        b = oracle.rhs(pc)
+        fwd = np.linalg.norm(b - oracle.apply(pc, beta, w)) / np.linalg.norm(b)
+        g = ohyper.adjoint_rhs(pc, w[None], ho, y)[0]
+        adj = np.linalg.norm(g - oracle.apply(pc, beta, lam)) / np.linalg.norm(g)
+        h = ohyper.loss(pc, w[None], ho, y)[0]
+        dlb_r = -beta * float(lam @ w)
+        da_r = -float(lam @ (oracle.apply(pc, 0.0, w, alpha=1.0) - oracle.apply(pc, 0.0, w, alpha=0.0)))
+        log("target %d beta %.3g: forward relres %.4e (reported %.4e), adjoint %.4e (reported %.4e), "
+            "loss %.6e / %.6e, dlogbeta %.6e / %.6e, dalpha %.6e / %.6e"
+            % (c, beta, fwd, rel[c, s], adj, rel2[c, s], loss[c, s], h, dlb[c, s], dlb_r, da[c, s], da_r))
+        assert fwd <= pb.rtol * 1.001 and abs(fwd - rel[c, s]) <= 1e-3 * fwd, (c, s)
+        assert adj <= pb.rtol * 1.001 and abs(adj - rel2[c, s]) <= 1e-3 * adj, (c, s)
+        assert np.abs(G[c, s].cpu().numpy() - g).max() <= 1e-12 * np.abs(g).max()
+        assert abs(loss[c, s] - h) <= 1e-10 * abs(h)
+        assert abs(dlb[c, s] - dlb_r) <= 1e-10 * abs(dlb_r)
+        assert abs(da[c, s] - da_r) <= 1e-8 * abs(da_r)

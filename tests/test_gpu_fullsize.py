@@ -6,6 +6,8 @@ operator product against the oracle's (full vector), the two extreme shifts agai
 solves, the reported true residuals of every shift against residuals the oracle recomputes
 from the returned iterates, and the ratings against the oracle's X w.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -66,8 +68,36 @@ def test_fullsize_extreme_shifts_match_oracle_solve(mid, mid_solved, which):
     op = mid_solved[0]
     s = int(np.argmax(mid.betas)) if which == "largest" else int(np.argmin(mid.betas))
     W, iters, relres, st = op.solve([mid.betas[s]], rtol=1e-11, chunk=128)
-    Wr, itr, rr, rc = oracle.solve(mid, betas=[mid.betas[s]], rtol=1e-11, maxit=20000)
-    assert relerr(W[0].cpu().numpy(), Wr[0]) < 1e-6, (s, relerr(W[0].cpu().numpy(), Wr[0]))
+    Wr, itr, rr, rc, kap, *_ = oracle.solve_with_kappa(mid, betas=[mid.betas[s]], rtol=1e-11, maxit=20000)
+    err = relerr(W[0].cpu().numpy(), Wr[0])
+    print("beta %.3g: relerr %.2e, kappa-hat %.3g (kappa-hat * 1e-8 = %.2e, * 1e-11 = %.2e)"
+          % (mid.betas[s], err, kap[0], kap[0] * 1e-8, kap[0] * 1e-11))
+    assert err < 1e-6, (s, err)
+
+
+def test_fullsize_batched_targets_residuals_recomputed_by_oracle(mid):
+    """16 targets x 16 shifts at full size in the bench's launch configuration (autotuned
+    tile, the batch's default fold interval): every (target, shift) meets rtol, and for a
+    seeded sample of (target, shift) pairs the oracle recomputes the true residual of the
+    returned iterate with that target's labeled set: at most rtol, within 0.1 % of the one
+    the solver reports."""
+    labs = synth.target_labels(mid, 16, seed=2)
+    op = fsda.Operator.from_problem(mid, max_chunk=128)
+    op.autotune_batch(labs, mid.betas, trial_iters=32)
+    W, iters, relres, st = op.solve_batch(labs, mid.betas, rtol=mid.rtol)
+    assert st == fsda.OK
+    assert relres.max() <= mid.rtol
+    rng = np.random.default_rng(7)
+    pairs = [(int(c), int(s)) for c, s in zip(rng.choice(16, 4, replace=False), rng.integers(0, 16, 4))]
+    pairs.append((0, int(np.argmin(mid.betas))))
+    for c, s in pairs:
+        pc = dataclasses.replace(mid, lab_idx=labs[c][0], lab_y=labs[c][1])
+        b = oracle.rhs(pc)
+        w = W[c, s].cpu().numpy()
+        ref = np.linalg.norm(b - oracle.apply(pc, mid.betas[s], w)) / np.linalg.norm(b)
+        print("target %d shift %d: reported %.4e, oracle %.4e" % (c, s, relres[c, s], ref))
+        assert ref <= mid.rtol * 1.001, (c, s, ref)
+        assert abs(relres[c, s] - ref) <= 1e-3 * ref, (c, s, relres[c, s], ref)
 
 
 def test_fullsize_ratings_match_oracle(mid, mid_solved):

@@ -32,6 +32,14 @@ def test_mixed_solve_matches_oracle_tiny(tiny, alpha):
     op = fsda.Operator.from_problem(tiny, precision=fsda.MIXED, alpha=alpha)
     W, iters, relres, st = op.solve(tiny.betas, rtol=1e-8)
     assert st == fsda.OK
+    rep = op.solve_report(tiny.betas.size)
+    # one FP64 refinement step at most, and the iterations split into the shared
+    # recurrence's and the correction solve's
+    assert rep["steps"].max() <= 1
+    assert np.array_equal(iters, rep["main_iters"] + rep["refine_iters"])
+    assert (rep["refine_iters"][rep["steps"] == 0] == 0).all()
+    print("alpha %.1f: main %s, correction %s, steps %s" % (alpha, rep["main_iters"].tolist(),
+                                                            rep["refine_iters"].tolist(), rep["steps"].tolist()))
     Wr, *_ = oracle.solve(tiny, rtol=1e-13, maxit=20000, alpha=alpha)
     W = W.cpu().numpy()
     b = oracle.rhs(tiny)

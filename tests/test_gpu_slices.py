@@ -1,7 +1,8 @@
 """The sliced plans of the X^T product vs the CPU oracle and vs the unsliced plan.
 
-LDS slices (n <= 262,144) and XCD slices (larger n) are chosen automatically;
-FSDA_XT_SLICES=lds, 8 or 1 forces LDS slices, XCD slices or no slices, which is how these
+LDS slices (n <= 262,144) and the hybrid of LDS slices for the longest rows and XCD
+slices for the other split rows (larger n) are chosen automatically; FSDA_XT_SLICES=lds,
+8, hyb or 1 forces LDS slices, XCD slices, the hybrid or no slices, which is how these
 tests run the plans on the same inputs.  Split rows are summed in a different order than in
 the unsliced plan, so the plans agree to rounding (1e-13 relative on products) but are not
 bit-identical; the oracle bars are those of the unsliced parity tests.
@@ -27,7 +28,12 @@ pytestmark = pytest.mark.gpu
 
 PLANTED_COUNTS = [300000, 120000, 20000, 9000, 5000, 3000, 1500, 800, 600, 400, 300, 200, 100, 80, 64,
                   63, 40, 20, 10, 5, 2, 1, 0, 0]
-PLANS = ["8", "lds"]  # FSDA_XT_SLICES of the planted problem of each plan
+# FSDA_XT_SLICES of each plan; the hybrid plan (rows of at least a head length in
+# LDS slices, the other split rows in XCD slices) with its default head of 2048
+# nonzeros, a head of 64 (every split row in LDS slices, none left to XCD slices)
+# and of 50,000 (the XCD part keeps rows of >= 8192 nonzeros, summed in chunk items)
+PLANS = ["8", "lds", "hyb", "hyb64", "hyb50k"]
+HEADS = {"hyb": None, "hyb64": "64", "hyb50k": "50000"}
 
 
 def relerr(a, b):
@@ -59,7 +65,12 @@ def rhs_term_scale(pb, r):
 
 
 def build(pb, monkeypatch, slices, **kw):
-    monkeypatch.setenv("FSDA_XT_SLICES", str(slices))
+    slices = str(slices)
+    monkeypatch.setenv("FSDA_XT_SLICES", "hyb" if slices in HEADS else slices)
+    if HEADS.get(slices):
+        monkeypatch.setenv("FSDA_XT_HEAD", HEADS[slices])
+    else:
+        monkeypatch.delenv("FSDA_XT_HEAD", raising=False)
     return fsda.Operator.from_problem(pb, **kw)
 
 
@@ -71,8 +82,9 @@ def tiny():
 @pytest.fixture(scope="module")
 def planted_by_plan():
     """XCD slices: 300,000 samples; LDS slices: 200,000 (a dense feature of 200,000)."""
-    return {"8": synth.planted_problem(300000, PLANTED_COUNTS, n_lab=3000, pos_frac=0.3, alpha=0.5,
-                                       betas=(0.05, 0.5, 5.0, 50.0), seed=4, rtol=1e-11),
+    xcd = synth.planted_problem(300000, PLANTED_COUNTS, n_lab=3000, pos_frac=0.3, alpha=0.5,
+                                betas=(0.05, 0.5, 5.0, 50.0), seed=4, rtol=1e-11)
+    return {"8": xcd, "hyb": xcd, "hyb64": xcd, "hyb50k": xcd,
             "lds": synth.planted_problem(200000, [200000] + PLANTED_COUNTS[1:], n_lab=2000, pos_frac=0.3,
                                          alpha=0.5, betas=(0.05, 0.5, 5.0, 50.0), seed=6, rtol=1e-11)}
 
