@@ -142,6 +142,17 @@ KNAMES = {0: "k_rows<EpiX> (t = X p)", 1: "k_rows<EpiLap> (u = M' t)",
 APPLY_CLASSES = (0, 1, 2, 3, 13)  # the kernels of one operator apply (X, graph, X^T and its parts)
 
 
+def graph_stats(pb) -> dict:
+    """How the workload's kNN graph was made and its degrees (the graph is an input of the solve)."""
+    import synth
+    deg = np.diff(pb.s_rowptr)
+    exact = pb.n <= synth.EXACT_KNN_MAX
+    return {"method": "exact Tanimoto kNN, ties included" if exact else
+            "MinHash-LSH candidates re-ranked by exact Tanimoto, ties included (an approximation of the exact graph)",
+            "neighbours_kept_per_sample_before_symmetrising": "at most max(4k, 64)",
+            "mean_degree": round(float(deg.mean()), 2), "max_degree": int(deg.max()), "nnz": int(pb.s_nnz)}
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -390,10 +401,11 @@ def batched_targets(args, fsda, torch):
     # the tile (targets per pass over the indices) picked by the autotuner on the
     # first 16 labelings, then used for every batch below
     t0 = time.perf_counter()
-    tile, rates = op.autotune_batch(synth.target_labels(pb, 16, seed=1), pb.betas, trial_iters=32)
-    tune = {"tile": tile, "seconds": round(time.perf_counter() - t0, 2),
-            "shifted_target_iterations_per_s": {str(t): round(r, 1) for t, r in rates.items()}}
-    log("autotuned tile %d in %.1f s: %s" % (tile, tune["seconds"], tune["shifted_target_iterations_per_s"]))
+    tile, groups, rates = op.autotune_batch(synth.target_labels(pb, 16, seed=1), pb.betas, trial_iters=32)
+    tune = {"tile": tile, "groups_per_row": groups, "seconds": round(time.perf_counter() - t0, 2),
+            "shifted_target_iterations_per_s": {"%dx%d" % sh: round(r, 1) for sh, r in rates.items()}}
+    log("autotuned tile %d, %d groups per row, in %.1f s: %s" % (tile, groups, tune["seconds"],
+                                                                tune["shifted_target_iterations_per_s"]))
     rows = []
     for k in (16, 32, 64):
         labs = synth.target_labels(pb, k, seed=1)
@@ -711,10 +723,10 @@ def batched_bench(args, fsda, torch):
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    tile, rates = op.autotune_batch(targets[:16], pb.betas, trial_iters=32)
-    tune = {"tile": tile, "seconds": round(time.perf_counter() - t0, 2),
-            "shifted_target_iterations_per_s": {str(t): round(r, 1) for t, r in rates.items()}}
-    log("autotuned tile %d: %s" % (tile, tune["shifted_target_iterations_per_s"]))
+    tile, groups, rates = op.autotune_batch(targets[:16], pb.betas, trial_iters=32)
+    tune = {"tile": tile, "groups_per_row": groups, "seconds": round(time.perf_counter() - t0, 2),
+            "shifted_target_iterations_per_s": {"%dx%d" % sh: round(r, 1) for sh, r in rates.items()}}
+    log("autotuned tile %d, %d groups per row: %s" % (tile, groups, tune["shifted_target_iterations_per_s"]))
     S = pb.betas.size
     group = [0]
 
@@ -776,8 +788,9 @@ def batched_bench(args, fsda, torch):
                                "over X n=%d x d=%d binary (nnz_X=%d, Zipf 1.1) and a 10-NN graph (nnz_S=%d), "
                                "alpha=%g, rtol %g, FP64" % (STEP_TARGETS, TOTAL_TARGETS, S, pb.n, pb.d, pb.x_nnz,
                                                           pb.s_nnz, pb.alpha, pb.rtol),
+                   "graph": graph_stats(pb),
                    "targets_per_step": STEP_TARGETS, "total_targets": TOTAL_TARGETS, "shifts": S, "n": pb.n,
-                   "d": pb.d, "nnz_x": pb.x_nnz, "nnz_s": pb.s_nnz, "tile": tile},
+                   "d": pb.d, "nnz_x": pb.x_nnz, "nnz_s": pb.s_nnz, "tile": tile, "groups_per_row": groups},
         "roofline": roof,
         "operator_apply": apply,
         "detail": {"per_target_fp64_solves_per_s": round(per_target, 3),
@@ -857,6 +870,44 @@ def diff_experiment(args, fsda, torch):
                       "loss_range": [float(loss.min()), float(loss.max())]}), flush=True)
 
 
+def mixed_large(args, fsda, torch):
+    """The whole shift grid of the large workload solved in FP64 and by the mixed
+    path (FP32 shared recurrence, one FP64 refinement step), each timed once from
+    the right-hand side to the reported true residuals, with the mixed path's
+    iterations per shift."""
+    import synth
+    os.environ.setdefault("FSDA_PROGRESS", "20")  # the solve loops print their iteration count
+    pb = synth.workload("large", seed=args.seed, cache_dir=args.cache, log=log)
+    torch.cuda.set_device(0)
+    S = pb.betas.size
+    out = {}
+    for name, prec in (("fp64", fsda.FP64), ("mixed", fsda.MIXED)):
+        op = fsda.Operator.from_problem(pb, precision=prec, max_chunk=128)
+        W = torch.empty((S, pb.d), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        log("%s: solving %d shifts" % (name, S))
+        t0 = time.perf_counter()
+        b = op.rhs()
+        _, iters, relres, st = op.solve(pb.betas, rtol=pb.rtol, chunk=128, b=b, out=W)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        rep = op.solve_report(S)
+        ok = int((relres <= pb.rtol).sum())
+        out[name] = {"seconds": round(sec, 2), "status": int(st), "shifts_within_rtol": ok,
+                     "worst_relres": float(relres.max()), "relres": [float("%.3e" % r) for r in relres],
+                     "iters": [int(i) for i in iters], "main_iters": [int(i) for i in rep["main_iters"]],
+                     "refine_iters": [int(i) for i in rep["refine_iters"]],
+                     "refine_steps": [int(i) for i in rep["steps"]]}
+        log("%s: %.2f s, status %d, %d of %d shifts within rtol, worst relres %.3e, max main iterations %d, "
+            "max correction iterations %d" % (name, sec, st, ok, S, relres.max(), rep["main_iters"].max(),
+                                               rep["refine_iters"].max()))
+        op.close()
+        del W
+    print(json.dumps({"experiment": "mixed-large", "workload": "large: n=%d x d=%d, nnz_X=%d, nnz_S=%d, %d shifts "
+                      "%.0e..%.0e, rtol %.0e" % (pb.n, pb.d, pb.x_nnz, pb.s_nnz, S, pb.betas.min(), pb.betas.max(),
+                                                  pb.rtol), **out}), flush=True)
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-rocprof":
         # python bench.py --summarize-rocprof DIR KERNEL_SUBSTR CALIB_MIB
@@ -899,7 +950,8 @@ def main():
                     help="'shifted-table': the CG versus shifted CG table instead; 'gather-ceiling': the rate of "
                          "random gathers the sparse products are bound by; 'batched-targets': 16, 32 and 64 targets; "
                          "'roofline-large': the operator-apply roofline on the large workload alone; 'diff': the "
-                         "hypergradient of 64 targets on the differentiation workload")
+                         "hypergradient of 64 targets on the differentiation workload; 'mixed-large': the large "
+                         "workload's whole shift grid in FP64 and by the mixed path")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -922,6 +974,9 @@ def main():
         return
     if args.experiment == "diff":
         diff_experiment(args, fsda, torch)
+        return
+    if args.experiment == "mixed-large":
+        mixed_large(args, fsda, torch)
         return
     if args.experiment == "roofline-large":
         if args.calib_copy_mb > 0:

@@ -277,39 +277,47 @@ int fsda_multishift_solve_batch(fsda_op *op, int ntarget, const int32_t *lab_idx
                                 void *stream);
 
 /*
- * Targets per tile of fsda_multishift_solve_batch (not part of the method: a
- * launch shape).  A tile of T targets shares one pass over the indices per
- * sparse product; a group of T lanes owns a row, so a wave holds 64 / T rows.
+ * Launch shape of fsda_multishift_solve_batch (not part of the method): the
+ * targets per tile T (a tile of T targets shares one pass over the indices per
+ * sparse product; its vectors over samples are interleaved, T values per row)
+ * and the groups of T lanes that share one row of the row products (the X and
+ * graph products and the short rows of X^T), so a wave holds 64 / (T groups)
+ * rows.
  *  fsda_set_batch_tile: tile 4, 8 or 16, or 0 for the default (16).  Takes
  *                effect at the next fsda_batch_workspace_size and batch solve
- *                (the workspace size depends on it).  Errors: FSDA_E_ARG,
- *                FSDA_E_RANGE.
- *  fsda_get_batch_tile: *tile (host) receives the tile in use.
+ *                (the workspace size depends on it).
+ *  fsda_set_batch_groups: groups 1, 2 or 4, or 0 for the default (1).
+ *  Errors: FSDA_E_ARG, FSDA_E_RANGE.  The getters write the shape in use to
+ *  *tile, *groups (host).
  */
 int fsda_set_batch_tile(fsda_op *op, int tile);
 int fsda_get_batch_tile(const fsda_op *op, int *tile);
+int fsda_set_batch_groups(fsda_op *op, int groups);
+int fsda_get_batch_groups(const fsda_op *op, int *groups);
 
 /*
- * Autotuner of the batch tile: for each tile T in {4, 8, 16} not larger than
- * the tile that min(ntarget, 16) targets need, solves the first min(T, ntarget)
- * targets (arguments as in fsda_multishift_solve_batch) once to warm up (graph
- * capture), then for trial_iters and 2 trial_iters iterations (rtol 1e-300, so
- * nothing stops early), and takes the time difference of the last two over
- * their iteration difference: setup and the final residual checks cancel.  rates[3] (host) receive the shifted
- * target-iterations per second of tiles 4, 8 and 16 (0 where not tried); the
- * fastest tile is kept in the handle (as by fsda_set_batch_tile) and written to
- * *tile.  Blocks until done.
+ * Autotuner of the launch shape: for each tile T in {4, 8, 16} not larger than
+ * the tile that min(ntarget, 16) targets need, and each group count in {1, 2,
+ * 4}, solves the first min(T, ntarget) targets (arguments as in
+ * fsda_multishift_solve_batch) once to warm up (graph capture), then for
+ * trial_iters and 2 trial_iters iterations (rtol 1e-300, so nothing stops
+ * early), and takes the time difference of the last two over their iteration
+ * difference: setup and the final residual checks cancel.  rates[9] (host)
+ * receive the shifted target-iterations per second of (tile, groups) = (4, 1),
+ * (4, 2), (4, 4), (8, 1), ..., (16, 4) (0 where not tried); the fastest shape
+ * is kept in the handle (as by fsda_set_batch_tile and fsda_set_batch_groups)
+ * and written to *tile, *groups.  Blocks until done.
  *  trial_iters   1..4096 (32 to 64 suffice on the benchmark workloads).
  *  workspace, ws_bytes  as for fsda_multishift_solve_batch with the default
  *                tile (16) and the same ntarget, nshift and chunk 0.
  *  W             device FP64, room for min(ntarget, 16) x nshift x d; its
  *                contents afterwards are the unconverged trial iterates.
- * Errors as fsda_multishift_solve_batch (the tile in use before the call is
+ * Errors as fsda_multishift_solve_batch (the shape in use before the call is
  * kept then), and FSDA_E_RANGE for trial_iters.
  */
 int fsda_batch_autotune(fsda_op *op, int ntarget, const int32_t *lab_idx, const int8_t *lab_y,
                         const int64_t *lab_off, const double *betas, int nshift, int trial_iters, void *workspace,
-                        size_t ws_bytes, double *W, void *stream, int *tile, double *rates);
+                        size_t ws_bytes, double *W, void *stream, int *tile, int *groups, double *rates);
 
 /*
  * Independent systems with different right-hand sides, solved together:

@@ -92,7 +92,9 @@ def lib():
         L.fsda_set_batch_tile.argtypes = [P, I]
         L.fsda_get_batch_tile.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
         L.fsda_batch_autotune.argtypes = [P, I, P, P, P, P, I, I, P, ctypes.c_size_t, P, P,
-                                          ctypes.POINTER(ctypes.c_int), P]
+                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), P]
+        L.fsda_set_batch_groups.argtypes = [P, I]
+        L.fsda_get_batch_groups.argtypes = [P, ctypes.POINTER(ctypes.c_int)]
         L.fsda_destroy_operator.argtypes = [P]
         L.fsda_destroy_operator.restype = None
         L.fsda_last_error.argtypes = []
@@ -103,7 +105,8 @@ def lib():
                   L.fsda_columns_workspace_size, L.fsda_solve_columns, L.fsda_holdout, L.fsda_hypergradient,
                   L.fsda_gather_sum, L.fsda_set_batch_tile, L.fsda_get_batch_tile, L.fsda_batch_autotune,
                   L.fsda_holdout_batch, L.fsda_columns_batch_workspace_size, L.fsda_solve_columns_batch,
-                  L.fsda_hypergradient_batch, L.fsda_solve_columns_static, L.fsda_solve_report):
+                  L.fsda_hypergradient_batch, L.fsda_solve_columns_static, L.fsda_solve_report,
+                  L.fsda_set_batch_groups, L.fsda_get_batch_groups):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -465,9 +468,21 @@ class Operator:
         _check(lib().fsda_get_batch_tile(self.handle, ctypes.byref(t)))
         return int(t.value)
 
+    def set_batch_groups(self, groups: int) -> None:
+        """Groups of tile lanes per row of solve_batch's row products: 1, 2 or 4, or 0 for
+        the default (fsda_set_batch_groups)."""
+        _check(lib().fsda_set_batch_groups(self.handle, int(groups)))
+
+    @property
+    def batch_groups(self) -> int:
+        g = ctypes.c_int(0)
+        _check(lib().fsda_get_batch_groups(self.handle, ctypes.byref(g)))
+        return int(g.value)
+
     def autotune_batch(self, labels, betas: Sequence[float], trial_iters: int = 32, stream=None):
-        """Times tiles of 4, 8 and 16 targets on these targets (fsda_batch_autotune) and keeps
-        the fastest for solve_batch.  Returns (tile, {tile: shifted target-iterations per s})."""
+        """Times tiles of 4, 8 and 16 targets with 1, 2 and 4 groups of lanes per row on these
+        targets (fsda_batch_autotune) and keeps the fastest shape for solve_batch.  Returns
+        (tile, groups, {(tile, groups): shifted target-iterations per s})."""
         import torch
         lab_idx, lab_y, off = self._labels(labels)
         betas = np.ascontiguousarray(betas, dtype=np.float64)
@@ -475,13 +490,15 @@ class Operator:
         self.set_batch_tile(0)  # the workspace of the largest tile tried
         ws, size = self._batch_workspace(K, S, 0)
         W = torch.empty((min(K, 16), S, self.d), dtype=torch.float64, device=self.device)
-        tile = ctypes.c_int(0)
-        rates = np.zeros(3, dtype=np.float64)
+        tile, groups = ctypes.c_int(0), ctypes.c_int(0)
+        rates = np.zeros(9, dtype=np.float64)
         _check(lib().fsda_batch_autotune(self.handle, K, _ptr(lab_idx), _ptr(lab_y), off.ctypes.data_as(ctypes.c_void_p),
                                          betas.ctypes.data_as(ctypes.c_void_p), S, int(trial_iters),
                                          ctypes.c_void_p(ws), ctypes.c_size_t(size), _ptr(W), _stream(stream),
-                                         ctypes.byref(tile), rates.ctypes.data_as(ctypes.c_void_p)))
-        return int(tile.value), {t: float(r) for t, r in zip((4, 8, 16), rates) if r > 0}
+                                         ctypes.byref(tile), ctypes.byref(groups),
+                                         rates.ctypes.data_as(ctypes.c_void_p)))
+        shapes = [(t, g) for t in (4, 8, 16) for g in (1, 2, 4)]
+        return int(tile.value), int(groups.value), {sh: float(r) for sh, r in zip(shapes, rates) if r > 0}
 
     def project(self, W, stream=None):
         import torch

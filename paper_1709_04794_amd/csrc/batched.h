@@ -152,12 +152,14 @@ constexpr int BMED = 64;  // X^T rows at least this long are cut into chunks in 
 // index then comes from its lane by a shuffle inside the group (all lanes of a
 // group share the trip count, so every source lane is active), and the gathers
 // of a pass are independent of each other.
-template <int T, typename V>
+// With GPR groups per row, group `sub` of a row takes the passes sub, sub +
+// GPR, ... (the caller adds the GPR groups' sums).
+template <int T, typename V, int GPR = 1>
 __device__ __forceinline__ V group_gather(const int* __restrict__ col, int beg, int end, const V* __restrict__ src,
-                                          int c) {
+                                          int c, int sub = 0) {
   constexpr int M = BM<T>();
   V v = (V)0;
-  for (int base = beg; base < end; base += T * M) {
+  for (int base = beg + sub * T * M; base < end; base += GPR * T * M) {
     int id[M];
 #pragma unroll
     for (int m = 0; m < M; m++) {
@@ -185,18 +187,28 @@ struct BMask {
   int nmask;
 };
 
-// Rows of one CSR over T columns; `stop` (the solver's stop flag) ends the
-// launch at once when set, cm holds the per-column labeled means.  With MASK,
-// bm gives the masks and the launch has nmask * T values of V of dynamic
-// shared memory.
-template <int T, class Epi, bool MASK = false>
+// The GPR groups of one row (lanes g0 T .. (g0 + GPR) T - 1, g0 a multiple of
+// GPR) add their sums: every lane c of them gets the row's column c.
+template <int T, int GPR, typename V>
+__device__ __forceinline__ V groups_sum(V v) {
+#pragma unroll
+  for (int o = T; o < T * GPR; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Rows of one CSR over T columns, GPR groups of T lanes per row (64 / (T GPR)
+// rows per wave); `stop` (the solver's stop flag) ends the launch at once when
+// set, cm holds the per-column labeled means.  With MASK, bm gives the masks
+// and the launch has nmask * T values of V of dynamic shared memory.
+template <int T, class Epi, bool MASK = false, int GPR = 1>
 __global__ __launch_bounds__(BS) void bk_rows(const int* __restrict__ rowptr, const int* __restrict__ col, int nrows,
                                               const typename Epi::VT* __restrict__ src, Epi epi, const int* stop,
                                               const double* cm, double* part, BMask bm) {
   using V = typename Epi::VT;
   if (*stop) return;
   constexpr int G = BS / T;
-  const int c = threadIdx.x % T, g = threadIdx.x / T;
+  constexpr int RB = G / GPR;  // rows per block and pass
+  const int c = threadIdx.x % T, g = threadIdx.x / T, q = g % GPR;
   extern __shared__ double bk_smem[];
   V* hot = reinterpret_cast<V*>(bk_smem);
   if (MASK) {
@@ -205,18 +217,19 @@ __global__ __launch_bounds__(BS) void bk_rows(const int* __restrict__ rowptr, co
   }
   epi.prepare(cm, c);
   double acc = 0.0;
-  for (int r0 = blockIdx.x * G; r0 < nrows; r0 += gridDim.x * G) {
-    const int r = r0 + g;
+  for (int r0 = blockIdx.x * RB; r0 < nrows; r0 += gridDim.x * RB) {
+    const int r = r0 + g / GPR;  // the same for the GPR groups of a row
     if (r >= nrows) continue;
-    V v = group_gather<T, V>(col, rowptr[r], rowptr[r + 1], src, c);
-    if (MASK) {
+    V v = group_gather<T, V, GPR>(col, rowptr[r], rowptr[r + 1], src, c, q);
+    if (MASK && q == 0) {
       unsigned long long mb = bm.mask[r];
       while (mb) {
         v += hot[(__ffsll((long long)mb) - 1) * T + c];
         mb &= mb - 1;
       }
     }
-    acc += epi.row(r, c, v);
+    v = groups_sum<T, GPR>(v);
+    if (q == 0) acc += epi.row(r, c, v);
   }
   if (Epi::kReduce) write_partials_cols<T>(part, acc);
 }
@@ -248,7 +261,7 @@ __device__ __forceinline__ size_t qidx(int T, long long ldq, long long r, int c)
   return ldq ? (size_t)c * ldq + r : (size_t)r * T + c;
 }
 
-template <int T, typename V>
+template <int T, typename V, int GPR = 1>
 __global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __restrict__ u, const V* __restrict__ P,
                                             V* Q, long long ldq, const double* sigma, const int* stop) {
   if (*stop) return;
@@ -262,8 +275,10 @@ __global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __rest
   __shared__ V sh[BS];
   const int c = threadIdx.x % T, g = threadIdx.x / T;
   const V sg = P ? (V)sigma[c] : (V)0;
+  constexpr int RB = G / GPR;  // short rows per item
+  const int q = g % GPR;
   const int nchit = X.item_chunk ? X.nitem : nchunk;  // chunk items
-  const int nitems = nchit + (d - nmed + G - 1) / G;
+  const int nitems = nchit + (d - nmed + RB - 1) / RB;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     if (it < nchit) {  // uniform over the block
       const int k = X.item_chunk ? X.item_chunk[it] : it;
@@ -283,10 +298,10 @@ __global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __rest
       }
       continue;
     }
-    const int r = nmed + (it - nchit) * G + g;
+    const int r = nmed + (it - nchit) * RB + g / GPR;
     if (r >= d) continue;
-    const V v = group_gather<T, V>(col, rowptr[r], rowptr[r + 1], u, c);
-    Q[qidx(T, ldq, r, c)] = P ? v + sg * P[(size_t)r * T + c] : v;
+    const V v = groups_sum<T, GPR>(group_gather<T, V, GPR>(col, rowptr[r], rowptr[r + 1], u, c, q));
+    if (q == 0) Q[qidx(T, ldq, r, c)] = P ? v + sg * P[(size_t)r * T + c] : v;
   }
 }
 

@@ -25,7 +25,8 @@
 // ones form a prefix cut into single-row chunks and the rest fall into a few
 // length bins with a fixed number of lanes per row.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include <algorithm>
 #include <chrono>
@@ -96,6 +97,7 @@ constexpr int TARGET_TILE = 16;
 // Columns per tile of fsda_solve_columns_batch (independent systems, FP64).
 constexpr int COLUMN_TILE = 16;
 int batch_tile_of(const fsda_op* op);
+int batch_gpr_of(const fsda_op* op);  // groups of T lanes per row in the target batch's row products
 
 struct Layout {
   size_t st, part, hist, fcoef, labw, ycen, zw, t, u, b, p, q, bu, new2old, old2new, xcol, xt_rowptr, xt_col;
@@ -115,6 +117,7 @@ struct Layout {
   int nslice;  // X^T XCD slices: 1 (none), or NSLICE (one per XCD)
   int lslice;  // X^T LDS slices (0: none)
   size_t lparts, lxptr, lxcol;
+  size_t lxcol_bytes;  // reserved for the slice-major index table
 };
 
 // Plan of the X^T product.  Up to MAXLSLICE LDS slices of LSLICE samples (n <=
@@ -190,8 +193,10 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
     L->nlds_max = L->nslice > 1 ? z / xt_head() + 1 : L->nsplit_max;  // hybrid: the head rows only
     L->lparts = 8 * (size_t)L->nlds_max * (size_t)L->lslice;
     L->lxptr = 4 * ((size_t)L->nlds_max + 1) * (size_t)L->lslice;
-    L->lxcol = 2 * (size_t)z;
+    // every nonempty segment padded to a multiple of LVEC entries
+    L->lxcol = 2 * ((size_t)z + (LVEC - 1) * (size_t)std::min<long long>((long long)L->nlds_max * L->lslice, z));
   }
+  L->lxcol_bytes = L->lxcol;
   L->st = take(sizeof(State));
   L->part = take(sizeof(double) * NSITE * NPART);
   L->hist = take(sizeof(double) * MAXCHUNK * MAXS * 4);
@@ -356,6 +361,8 @@ struct fsda_op {
   hipGraphExec_t gexec;
   GraphKey gkey;
   int use_graph;
+  double progress_s;  // FSDA_PROGRESS: seconds between progress lines of the solve loops (0: none)
+  std::chrono::steady_clock::time_point progress_t;
   // batched refinement solve: one chunk of iterations as a graph, per tile
   hipGraphExec_t bgexec;
   const void* bg_key;
@@ -374,9 +381,10 @@ struct fsda_op {
   // batched targets: targets per tile (0: TARGET_TILE; set by fsda_set_batch_tile
   // or fsda_batch_autotune), one chunk of iterations + fold as a graph, and its key
   int btile_sel;
+  int bgpr_sel;  // groups of T lanes per row (0: 1), set by fsda_set_batch_groups or fsda_batch_autotune
   hipGraphExec_t tgexec;
   const void* tkey_ws;
-  int tkey_T, tkey_nshift, tkey_chunk, tkey_sliced;
+  int tkey_T, tkey_gpr, tkey_nshift, tkey_chunk, tkey_sliced;
   TState* htst;  // pinned host mirror
   BState* bst;
   BState* hbst;  // pinned host mirror
@@ -452,6 +460,18 @@ void launch(fsda_op* op, int cls, hipStream_t s, F f) {
   }
 }
 
+// With FSDA_PROGRESS=<seconds> in the environment, the host loops of the solves
+// print their iteration count to stderr at most that often, so that a long solve
+// shows that it advances.
+void progress(fsda_op* op, const char* what, int iter) {
+  if (!(op->progress_s > 0.0)) return;
+  const auto now = std::chrono::steady_clock::now();
+  if (std::chrono::duration<double>(now - op->progress_t).count() < op->progress_s) return;
+  op->progress_t = now;
+  std::fprintf(stderr, "[fsda] %s: iteration %d\n", what, iter);
+  std::fflush(stderr);
+}
+
 template <class Epi>
 void run_rows(fsda_op* op, const RowPlan& pl, const typename Epi::V* src, Epi epi, double* part, int solve,
               hipStream_t s, int cls) {
@@ -485,7 +505,7 @@ void run_xt(fsda_op* op, const typename Epi::V* src, Epi epi, int solve, bool as
   if (pl.lds.nslice > 0 && pl.lds.nsplit > 0) {
     using V = typename Epi::V;
     launch(op, KC_XTL, s, [&] {
-      hipLaunchKernelGGL(k_xt_lds<V>, dim3(pl.lds.nslice * pl.lds.bps), dim3(LTB), sizeof(V) * LSLICE, s, pl.lds, src,
+      hipLaunchKernelGGL(k_xt_lds<V>, dim3(pl.lds.nblk), dim3(LTB), sizeof(V) * (LSLICE + 1), s, pl.lds, src,
                          op->st, solve);
     });
   }
@@ -617,6 +637,7 @@ void fold(fsda_op* op, double* W, int nshift, int chunk, int mode, hipStream_t s
 }
 
 int batch_tile_of(const fsda_op* op) { return op->btile_sel ? op->btile_sel : TARGET_TILE; }
+int batch_gpr_of(const fsda_op* op) { return op->bgpr_sel ? op->bgpr_sel : 1; }
 
 void drop_graph(fsda_op* op) {
   if (op->gexec) (void)hipGraphExecDestroy(op->gexec);
@@ -775,9 +796,9 @@ int make_xt_slices(fsda_op* op, int r0, hipStream_t s) {
 
 // LDS-sliced work of the X^T product (see XtLds): the rows of >= SPLIT_ROW
 // nonzeros [0, nsplit) get their slice boundaries on the device; k_xt_lds runs
-// bps blocks per slice over bins of those rows by expected segment length
-// (length / nslice: >= 256 -> 64 lanes per row, >= 64 -> 32, >= 16 -> 8, else 2),
-// and the X^T pass finishes them from their parts (assembly items).
+// one resident wave of blocks over bins of those rows by expected segment length
+// (length / nslice: >= 1024 -> 64 lanes per row, >= 256 -> 16, >= 64 -> 4, else
+// 1), and the X^T pass finishes them from their parts (assembly items).
 int make_xt_lds(fsda_op* op, int nsplit, hipStream_t s) {
   XtPlan& pl = op->pxt;
   XtLds& D = pl.lds;
@@ -810,18 +831,22 @@ int make_xt_lds(fsda_op* op, int nsplit, hipStream_t s) {
     int* px = xp.data() + (size_t)x * (nsplit + 1);
     for (int j = 0; j < nsplit; j++) {
       px[j] = (int)tot;
-      tot += sp[(size_t)(x + 1) * nsplit + j] - sp[(size_t)x * nsplit + j];
+      const long long len = sp[(size_t)(x + 1) * nsplit + j] - sp[(size_t)x * nsplit + j];
+      tot += (len + LVEC - 1) / LVEC * LVEC;  // padded to whole index loads
     }
     px[nsplit] = (int)tot;
   }
-  if (tot > std::max<long long>(op->pb.x_nnz, 1))
+  if (2 * tot > (long long)op->L.lxcol_bytes)
     return fail(FSDA_E_WORKSPACE, "slice-major index table larger than reserved");
   HIP_TRY(hipMemcpyAsync(const_cast<int*>(D.xptr), xp.data(), sizeof(int) * xp.size(), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_slice_copy, dim3((unsigned)ceil_div((long long)nsl * nsplit, BS)), dim3(BS), 0, s,
                      op->xt_col, segp, D.xptr, nsplit, nsl, const_cast<unsigned short*>(D.xcol));
   HIP_TRY(hipGetLastError());
-  const long long lo[4] = {256LL * nsl, 64LL * nsl, 16LL * nsl, 0};
-  const int lprs[4] = {64, 32, 8, 2};
+  // lanes per row from the expected segment (row length / slices): about LXV index
+  // loads of LVEC offsets per lane
+  const long long lo[4] = {(long long)64 * LXV * LVEC * nsl, (long long)16 * LXV * LVEC * nsl,
+                           (long long)4 * LXV * LVEC * nsl, 0};
+  const int lprs[4] = {64, 16, 4, 1};
   int nb = 0, item = 0, j = 0;
   for (int k = 0; k < 4; k++) {
     const int r0 = j;
@@ -837,12 +862,13 @@ int make_xt_lds(fsda_op* op, int nsplit, hipStream_t s) {
   }
   if (j != nsplit) return fail(FSDA_E_CSR, "X^T rows not ordered by length");
   D.nb = nb;
-  // about two blocks per CU over all slices, at most one per item
-  D.bps = std::max(1, std::min(item, (int)ceil_div(2 * 256, nsl)));
+  D.nitem = item;
+  // one resident wave of blocks (two per CU: the LDS holds two slices), at most one per item
+  D.nblk = (int)std::max<long long>(1, std::min<long long>((long long)item * nsl, 2 * 256));
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(k_xt_lds<double>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(double) * LSLICE)));
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(double) * (LSLICE + 1))));
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(k_xt_lds<float>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(float) * LSLICE)));
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(sizeof(float) * (LSLICE + 1))));
   HIP_TRY(hipStreamSynchronize(s));
   return FSDA_OK;
 }
@@ -1026,6 +1052,7 @@ int run_multishift(fsda_op* op, const double* rhs, const double* betas, double s
       if (trc) return trc;
     }
     done_iters = h->iter;
+    progress(op, "multi-shift solve", h->iter);
     if (h->stop) break;
   }
   return FSDA_OK;
@@ -1113,10 +1140,10 @@ bool bxt_sliced(const fsda_op* op, int T, int vbytes) {
   return (long long)op->pb.n * T * vbytes > SLICE_BYTES;
 }
 
-// Grid of the batched X^T product: every chunk item and row group once (a
-// multiple of 8 whenever it is capped, so that item it runs on XCD it % 8).
-int bxt_grid(const BXtArgs& xa, int G) {
-  const long long items = (xa.item_chunk ? xa.nitem : xa.nchunk) + ceil_div((long long)xa.d - xa.nmed, G);
+// Grid of the batched X^T product: every chunk item and item of rb short rows
+// once (a multiple of 8 whenever it is capped, so that item it runs on XCD it % 8).
+int bxt_grid(const BXtArgs& xa, int rb) {
+  const long long items = (xa.item_chunk ? xa.nitem : xa.nchunk) + ceil_div((long long)xa.d - xa.nmed, rb);
   return (int)std::max<long long>(1, std::min<long long>(items, GRID_B));
 }
 
@@ -1257,7 +1284,7 @@ void b_products(fsda_op* op, const BBuf<V>& b, const V* src, const V* P, const i
                          BEpiLap<T, V, false>{b.t, nullptr, 1, 0, op->pb.s_rowptr, b.u, op->pb.alpha, (V)0}, stop,
                          st->cm, b.site(BP_TU), BMask{nullptr, 0});
   });
-  const int gxt = bxt_grid(b.xa, G);
+  const int gxt = bxt_grid(b.xa, G);  // one group of T lanes per short row
   launch(op, timed ? KC_BXT : KC_OTHER, s, [&] {
     hipLaunchKernelGGL((bk_xt<T, V>), dim3(gxt), dim3(BS), 0, s, b.xa, b.lpart, b.u, P, b.Q, 0LL, st->sigma, stop);
     if (b.xa.nmed > 0)
@@ -1347,6 +1374,7 @@ int run_batched(fsda_op* op, const BBuf<V>& b, const double* B, long long ldb, i
       if (trc) return trc;
     }
     done_iters = h->iter;
+    progress(op, "batched columns", h->iter);
     if (h->stop) break;
   }
   HIP_TRY(hipMemcpyAsync(h, b.st, sizeof(BState), hipMemcpyDeviceToHost, s));
@@ -1690,11 +1718,16 @@ double* tpart(const TPtr& p, int site) { return p.part + (size_t)site * GRID_B *
 
 // Q (column-major) = X^T M'_c X src for the T columns of src (interleaved), with
 // the products' partials; stop is the flag the launches test.
-template <int T>
+// Blocks of the batched row products: G / GPR rows per block and pass.
+template <int T, int GPR>
+int t_rowgrid(long long n) {
+  return grid_b(ceil_div(n, BS / T / GPR));
+}
+
+template <int T, int GPR>
 void t_products(fsda_op* op, const TPtr& p, const double* src, const int* stop, hipStream_t s, bool timed) {
-  constexpr int G = BS / T;
   const long long n = op->pb.n;
-  const int gx = grid_b(ceil_div(n, G));
+  const int gx = t_rowgrid<T, GPR>(n);
   const bool lab = has_lab_term(op);
   TState* st = p.st;
   size_t sm = 0;
@@ -1703,34 +1736,34 @@ void t_products(fsda_op* op, const TPtr& p, const double* src, const int* stop, 
   const int* xrc = op->px.rows.col;
   launch(op, timed ? KC_BX : KC_OTHER, s, [&] {
     if (lab)
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, true>, true>), dim3(gx), dim3(BS), sm, s, xrp, xrc, (int)n, src,
-                         BEpiX<T, double, true>{p.t, p.labw, T, 1}, stop, st->cm, tpart(p, BP_X), bm);
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, true>, true, GPR>), dim3(gx), dim3(BS), sm, s, xrp, xrc, (int)n,
+                         src, BEpiX<T, double, true>{p.t, p.labw, T, 1}, stop, st->cm, tpart(p, BP_X), bm);
     else
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, false>, true>), dim3(gx), dim3(BS), sm, s, xrp, xrc, (int)n, src,
-                         BEpiX<T, double, false>{p.t, nullptr, T, 1}, stop, st->cm, tpart(p, BP_X), bm);
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, false>, true, GPR>), dim3(gx), dim3(BS), sm, s, xrp, xrc,
+                         (int)n, src, BEpiX<T, double, false>{p.t, nullptr, T, 1}, stop, st->cm, tpart(p, BP_X), bm);
   });
   if (lab) hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, stop, tpart(p, BP_X), gx, st->cm);
   launch(op, timed ? KC_BS : KC_OTHER, s, [&] {
     if (lab)
-      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, double, true>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr,
-                         op->pb.s_col, (int)n, p.t,
+      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, double, true>, false, GPR>), dim3(gx), dim3(BS), 0, s,
+                         op->pb.s_rowptr, op->pb.s_col, (int)n, p.t,
                          BEpiLap<T, double, true>{p.t, p.labw, T, 1, op->pb.s_rowptr, p.u, op->pb.alpha, 0.0}, stop,
                          st->cm, tpart(p, BP_TU), BMask{nullptr, 0});
     else
-      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, double, false>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr,
-                         op->pb.s_col, (int)n, p.t,
+      hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, double, false>, false, GPR>), dim3(gx), dim3(BS), 0, s,
+                         op->pb.s_rowptr, op->pb.s_col, (int)n, p.t,
                          BEpiLap<T, double, false>{p.t, nullptr, T, 1, op->pb.s_rowptr, p.u, op->pb.alpha, 0.0},
                          stop, st->cm, tpart(p, BP_TU), BMask{nullptr, 0});
   });
 }
 
-template <int T>
+template <int T, int GPR>
 void t_xt(fsda_op* op, const TPtr& p, const double* u, const double* P, double* Q, const int* stop, hipStream_t s,
           bool timed) {
-  constexpr int G = BS / T;
-  const int gxt = bxt_grid(p.xa, G);
+  const int gxt = bxt_grid(p.xa, BS / T / GPR);
   launch(op, timed ? KC_BXT : KC_OTHER, s, [&] {
-    hipLaunchKernelGGL((bk_xt<T, double>), dim3(gxt), dim3(BS), 0, s, p.xa, p.lpart, u, P, Q, p.ld, p.st->sigma, stop);
+    hipLaunchKernelGGL((bk_xt<T, double, GPR>), dim3(gxt), dim3(BS), 0, s, p.xa, p.lpart, u, P, Q, p.ld, p.st->sigma,
+                       stop);
     if (p.xa.nmed > 0)
       hipLaunchKernelGGL((bk_xt_rows<T, double>), dim3(grid_b(p.xa.nmed)), dim3(BS), 0, s, p.xa, p.lpart, P, Q, p.ld,
                          p.st->sigma, stop);
@@ -1739,18 +1772,18 @@ void t_xt(fsda_op* op, const TPtr& p, const double* u, const double* P, double* 
 
 int t_colgrid(long long d) { return grid_b(ceil_div(d, BS)); }
 
-template <int T>
+template <int T, int GPR>
 void t_iteration(fsda_op* op, const TPtr& p, hipStream_t s, int tag) {
   op->cur_tag = tag;
   constexpr int G = BS / T;
   const long long n = op->pb.n, d = op->pb.d;
   TState* st = p.st;
-  const int gx = grid_b(ceil_div(n, G));
+  const int gx = t_rowgrid<T, GPR>(n);
   const int gsb = grid_b(ceil_div(d, G));
   const int gc = t_colgrid(d);
-  t_products<T>(op, p, p.P, &st->stop, s, true);
+  t_products<T, GPR>(op, p, p.P, &st->stop, s, true);
   hipLaunchKernelGGL(ts_step_a<T>, dim3(1), dim3(BS), 0, s, st, tpart(p, BP_TU), gx, tpart(p, BP_PP), gsb);
-  t_xt<T>(op, p, p.u, p.P, p.Q, &st->stop, s, true);
+  t_xt<T, GPR>(op, p, p.u, p.P, p.Q, &st->stop, s, true);
   launch(op, KC_BRESID, s, [&] {
     hipLaunchKernelGGL(ts_resid<T>, dim3(gc, T), dim3(BS), 0, s, st, p.Q, p.ring, p.ld, d, tpart(p, BP_RR));
   });
@@ -1775,7 +1808,7 @@ void t_fold(fsda_op* op, const TPtr& p, hipStream_t s) {
   hipLaunchKernelGGL(ts_fold_done, dim3(1), dim3(1), 0, s, p.st);
 }
 
-template <int T>
+template <int T, int GPR>
 int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* lab_idx, const int8_t* lab_y,
                 const int64_t* lab_off, const double* betas, int nshift, double rtol, int maxit, int chunk, double* W,
                 int* iters, double* relres, hipStream_t s, int cbase) {
@@ -1851,7 +1884,7 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
                        1.0 / l, ybar, p.labw, ycen);
   }
   // right-hand sides B_c = X^T y_c (column-major)
-  t_xt<T>(op, p, ycen, nullptr, p.B, &p.st->zero, s, false);
+  t_xt<T, GPR>(op, p, ycen, nullptr, p.B, &p.st->zero, s, false);
 
   // initial state
   const int gc = t_colgrid(d);
@@ -1864,13 +1897,13 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
   bool graph = op->use_graph != 0 && !op->tk_on;
   // the captured chunk depends on the workspace layout (T, nshift, chunk, slicing)
   // only: W and the tile's target count are read from the state
-  if (graph && !(op->tgexec && op->tkey_ws == ws && op->tkey_T == T && op->tkey_nshift == nshift &&
-                 op->tkey_chunk == chunk && op->tkey_sliced == (int)L.sliced)) {
+  if (graph && !(op->tgexec && op->tkey_ws == ws && op->tkey_T == T && op->tkey_gpr == GPR &&
+                 op->tkey_nshift == nshift && op->tkey_chunk == chunk && op->tkey_sliced == (int)L.sliced)) {
     if (op->tgexec) (void)hipGraphExecDestroy(op->tgexec);
     op->tgexec = nullptr;
     hipGraph_t gr = nullptr;
     HIP_TRY(hipStreamBeginCapture(op->cap, hipStreamCaptureModeThreadLocal));
-    for (int j = 0; j < chunk; j++) t_iteration<T>(op, p, op->cap, j);
+    for (int j = 0; j < chunk; j++) t_iteration<T, GPR>(op, p, op->cap, j);
     t_fold<T>(op, p, op->cap);
     const hipError_t ce = hipStreamEndCapture(op->cap, &gr);
     hipError_t ie = hipErrorUnknown;
@@ -1885,6 +1918,7 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
     } else {
       op->tkey_ws = ws;
       op->tkey_T = T;
+      op->tkey_gpr = GPR;
       op->tkey_nshift = nshift;
       op->tkey_chunk = chunk;
       op->tkey_sliced = (int)L.sliced;
@@ -1897,7 +1931,7 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
     if (graph) {
       HIP_TRY(hipGraphLaunch(op->tgexec, s));
     } else {
-      for (int j = 0; j < chunk; j++) t_iteration<T>(op, p, s, j);
+      for (int j = 0; j < chunk; j++) t_iteration<T, GPR>(op, p, s, j);
       t_fold<T>(op, p, s);
     }
     HIP_TRY(hipGetLastError());
@@ -1909,6 +1943,7 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
       if (trc) return trc;
     }
     done_iters = h->iter;
+    progress(op, "target batch", h->iter);
     if (h->stop) break;
   }
 
@@ -1916,8 +1951,8 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
   for (int k = 0; k < nshift; k++) {
     constexpr int G = BS / T;
     hipLaunchKernelGGL(ts_pack<T>, dim3(grid_b(ceil_div(d, G))), dim3(BS), 0, s, W, k, nshift, ncol, p.P, d);
-    t_products<T>(op, p, p.P, &p.st->zero, s, false);
-    t_xt<T>(op, p, p.u, nullptr, p.Q, &p.st->zero, s, false);
+    t_products<T, GPR>(op, p, p.P, &p.st->zero, s, false);
+    t_xt<T, GPR>(op, p, p.u, nullptr, p.Q, &p.st->zero, s, false);
     hipLaunchKernelGGL(ts_resnorm<T>, dim3(gc, ncol), dim3(BS), 0, s, p.B, p.Q, p.ld, W, k, nshift, betas[k], d,
                        tpart(p, BP_RR));
     hipLaunchKernelGGL(ts_res_done<T>, dim3(1), dim3(BS), 0, s, p.st, tpart(p, BP_RR), gc, k, ncol);
@@ -1950,14 +1985,24 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
   return h->status == FSDA_NOT_CONVERGED ? FSDA_NOT_CONVERGED : FSDA_OK;
 }
 
-int targets_any(int T, fsda_op* op, char* ws, const TLayout& L, int ncol, const int* lab_idx, const int8_t* lab_y,
-                const int64_t* lab_off, const double* betas, int nshift, double rtol, int maxit, int chunk, double* W,
-                int* iters, double* relres, hipStream_t s, int cbase) {
-  switch (T) {
-    case 4: return run_targets<4>(op, ws, L, ncol, lab_idx, lab_y, lab_off, betas, nshift, rtol, maxit, chunk, W, iters, relres, s, cbase);
-    case 8: return run_targets<8>(op, ws, L, ncol, lab_idx, lab_y, lab_off, betas, nshift, rtol, maxit, chunk, W, iters, relres, s, cbase);
-    default: return run_targets<16>(op, ws, L, ncol, lab_idx, lab_y, lab_off, betas, nshift, rtol, maxit, chunk, W, iters, relres, s, cbase);
+int targets_any(int T, int gpr, fsda_op* op, char* ws, const TLayout& L, int ncol, const int* lab_idx,
+                const int8_t* lab_y, const int64_t* lab_off, const double* betas, int nshift, double rtol, int maxit,
+                int chunk, double* W, int* iters, double* relres, hipStream_t s, int cbase) {
+#define FSDA_TARGETS(TT, GG)                                                                                    \
+  return run_targets<TT, GG>(op, ws, L, ncol, lab_idx, lab_y, lab_off, betas, nshift, rtol, maxit, chunk, W, iters, \
+                             relres, s, cbase)
+  switch (T * 8 + gpr) {
+    case 4 * 8 + 1: FSDA_TARGETS(4, 1);
+    case 4 * 8 + 2: FSDA_TARGETS(4, 2);
+    case 4 * 8 + 4: FSDA_TARGETS(4, 4);
+    case 8 * 8 + 1: FSDA_TARGETS(8, 1);
+    case 8 * 8 + 2: FSDA_TARGETS(8, 2);
+    case 8 * 8 + 4: FSDA_TARGETS(8, 4);
+    case 16 * 8 + 2: FSDA_TARGETS(16, 2);
+    case 16 * 8 + 4: FSDA_TARGETS(16, 4);
+    default: FSDA_TARGETS(16, 1);
   }
+#undef FSDA_TARGETS
 }
 
 // Hold-out loss of the rows w_k of W (caller's order) on the held-out samples
@@ -2126,6 +2171,9 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
   {
     const char* e = getenv("FSDA_NO_GRAPH");
     if (e && e[0] == '1') op->use_graph = 0;
+    const char* pr = getenv("FSDA_PROGRESS");
+    op->progress_s = pr ? std::atof(pr) : 0.0;
+    op->progress_t = std::chrono::steady_clock::now();
   }
   auto bail = [&](int code) {
     fsda_destroy_operator(op);
@@ -2217,12 +2265,12 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
     int end_bit = 1;
     while (end_bit < 31 && (1LL << end_bit) <= n) end_bit++;  // counts are <= n
     size_t tb = 0;
-    HIP_TRY(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, tb, cnt, cnt_sorted, iota, op->new2old, (int)d, 0,
-                                                         end_bit, s));
+    HIP_TRY(rocprim::radix_sort_pairs_desc(nullptr, tb, cnt, cnt_sorted, iota, op->new2old, (unsigned int)d, 0u,
+                                           (unsigned int)end_bit, s));
     if (tb > L.sort_bytes)
       return bail(fail(FSDA_E_WORKSPACE, "feature sort needs " + std::to_string(tb) + " bytes of temporary storage"));
-    HIP_TRY(hipcub::DeviceRadixSort::SortPairsDescending(tmp, tb, cnt, cnt_sorted, iota, op->new2old, (int)d, 0,
-                                                         end_bit, s));
+    HIP_TRY(rocprim::radix_sort_pairs_desc(tmp, tb, cnt, cnt_sorted, iota, op->new2old, (unsigned int)d, 0u,
+                                           (unsigned int)end_bit, s));
     hipLaunchKernelGGL(k_invert, dim3(grid_for(d, 2048)), dim3(BS), 0, s, op->new2old, op->old2new, d);
     if (z > 0) {
       hipLaunchKernelGGL(k_gather_i, dim3(grid_for(z, 4096)), dim3(BS), 0, s, pb->x_col, op->old2new, op->xcol, z);
@@ -2231,12 +2279,14 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
       int kb = 1;
       while (kb < 31 && (1LL << kb) < d) kb++;
       tb = 0;
-      HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, op->xcol, keys, rowid, op->xt_col, (int)z, 0, kb, s));
+      HIP_TRY(rocprim::radix_sort_pairs(nullptr, tb, op->xcol, keys, rowid, op->xt_col, (unsigned int)z, 0u,
+                                        (unsigned int)kb, s));
       if (tb > L.sort_bytes)
         return bail(
             fail(FSDA_E_WORKSPACE, "transpose sort needs " + std::to_string(tb) + " bytes of temporary storage"));
       hipLaunchKernelGGL(k_expand_rows, dim3(grid_for(n, 2048)), dim3(BS), 0, s, pb->x_rowptr, n, rowid);
-      HIP_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tb, op->xcol, keys, rowid, op->xt_col, (int)z, 0, kb, s));
+      HIP_TRY(rocprim::radix_sort_pairs(tmp, tb, op->xcol, keys, rowid, op->xt_col, (unsigned int)z, 0u,
+                                        (unsigned int)kb, s));
       hipLaunchKernelGGL(k_keys_to_rowptr, dim3(grid_for(d + 1, 2048)), dim3(BS), 0, s, keys, z, (int)d,
                          op->xt_rowptr);
     } else {
@@ -2267,9 +2317,9 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
     hipLaunchKernelGGL(k_mask_split, dim3(grid_for(n, 2048)), dim3(BS), 0, s, pb->x_rowptr, op->xcol, n, op->mtop, xm,
                        mcnt);
     size_t tb = 0;
-    HIP_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, mcnt, rrp, (int)(n + 1), s));
+    HIP_TRY(rocprim::exclusive_scan(nullptr, tb, mcnt, rrp, 0, (size_t)(n + 1), rocprim::plus<int>(), s));
     if (tb > L.sort_bytes) return bail(fail(FSDA_E_WORKSPACE, "scan needs " + std::to_string(tb) + " bytes"));
-    HIP_TRY(hipcub::DeviceScan::ExclusiveSum(op->ws + L.sort_tmp, tb, mcnt, rrp, (int)(n + 1), s));
+    HIP_TRY(rocprim::exclusive_scan(op->ws + L.sort_tmp, tb, mcnt, rrp, 0, (size_t)(n + 1), rocprim::plus<int>(), s));
     hipLaunchKernelGGL(k_mask_fill, dim3(grid_for(n, 2048)), dim3(BS), 0, s, pb->x_rowptr, op->xcol, n, op->mtop, rrp,
                        rcol);
     int zr = 0;
@@ -2754,9 +2804,9 @@ int fsda_multishift_solve_batch(fsda_op* op, int ntarget, const int32_t* lab_idx
     const int T = batch_tile(nc);
     TLayout L;
     tlayout(op, T, nshift, chunk, &L);
-    rc = targets_any(T, op, static_cast<char*>(workspace), L, nc, lab_idx, lab_y, lab_off + c0, betas, nshift, rtol,
-                     maxit, chunk, W + (size_t)c0 * nshift * op->pb.d, iters + (size_t)c0 * nshift,
-                     relres + (size_t)c0 * nshift, static_cast<hipStream_t>(stream), c0);
+    rc = targets_any(T, batch_gpr_of(op), op, static_cast<char*>(workspace), L, nc, lab_idx, lab_y, lab_off + c0,
+                     betas, nshift, rtol, maxit, chunk, W + (size_t)c0 * nshift * op->pb.d,
+                     iters + (size_t)c0 * nshift, relres + (size_t)c0 * nshift, static_cast<hipStream_t>(stream), c0);
     if (rc < 0) return rc;
     status = std::max(status, rc);
   }
@@ -2776,28 +2826,42 @@ int fsda_get_batch_tile(const fsda_op* op, int* tile) {
   return FSDA_OK;
 }
 
+int fsda_set_batch_groups(fsda_op* op, int groups) {
+  if (!op) return fail(FSDA_E_ARG, "NULL handle");
+  if (groups != 0 && groups != 1 && groups != 2 && groups != 4) return fail(FSDA_E_RANGE, "groups must be 0, 1, 2 or 4");
+  op->bgpr_sel = groups;
+  return FSDA_OK;
+}
+
+int fsda_get_batch_groups(const fsda_op* op, int* groups) {
+  if (!op || !groups) return fail(FSDA_E_ARG, "NULL argument");
+  *groups = batch_gpr_of(op);
+  return FSDA_OK;
+}
+
 int fsda_batch_autotune(fsda_op* op, int ntarget, const int32_t* lab_idx, const int8_t* lab_y, const int64_t* lab_off,
                         const double* betas, int nshift, int trial_iters, void* workspace, size_t ws_bytes, double* W,
-                        void* stream, int* tile, double* rates) {
-  if (!op || !tile || !rates) return fail(FSDA_E_ARG, "NULL argument");
+                        void* stream, int* tile, int* groups, double* rates) {
+  if (!op || !tile || !groups || !rates) return fail(FSDA_E_ARG, "NULL argument");
   if (ntarget < 1 || ntarget > FSDA_MAX_TARGETS) return fail(FSDA_E_ARG, "ntarget outside 1..FSDA_MAX_TARGETS");
   if (trial_iters < 1 || trial_iters > 4096) return fail(FSDA_E_RANGE, "trial_iters outside 1..4096");
-  const int keep = op->btile_sel;
+  const int keep_t = op->btile_sel, keep_g = op->bgpr_sel;
   const int cap = batch_tile(std::min(ntarget, TARGET_TILE));
-  const int cand[3] = {4, 8, 16};
+  const int tiles[3] = {4, 8, 16}, grps[3] = {1, 2, 4};
   std::vector<int> it((size_t)TARGET_TILE * FSDA_MAX_SHIFTS);
   std::vector<double> rr((size_t)TARGET_TILE * FSDA_MAX_SHIFTS);
-  int best = 0;
+  int best_t = 0, best_g = 1;
   double best_rate = -1.0;
-  for (int k = 0; k < 3; k++) {
+  for (int k = 0; k < 9; k++) {
     rates[k] = 0.0;
-    const int T = cand[k];
+    const int T = tiles[k / 3], gp = grps[k % 3];
     if (T > cap) continue;
     op->btile_sel = T;
+    op->bgpr_sel = gp;
     const int nc = std::min(T, ntarget);
     double sec[3];
     int imax[3];
-    // a warm-up run (graph capture for this tile), then trial_iters and twice as
+    // a warm-up run (graph capture for this shape), then trial_iters and twice as
     // many: the difference of the last two is iterations only
     for (int rep = 0; rep < 3; rep++) {
       const auto t0 = std::chrono::steady_clock::now();
@@ -2806,7 +2870,8 @@ int fsda_batch_autotune(fsda_op* op, int ntarget, const int32_t* lab_idx, const 
                                                  it.data(), rr.data(), stream);
       const auto t1 = std::chrono::steady_clock::now();
       if (rc < 0) {
-        op->btile_sel = keep;
+        op->btile_sel = keep_t;
+        op->bgpr_sel = keep_g;
         return rc;
       }
       sec[rep] = std::chrono::duration<double>(t1 - t0).count();
@@ -2817,11 +2882,14 @@ int fsda_batch_autotune(fsda_op* op, int ntarget, const int32_t* lab_idx, const 
     rates[k] = per_iter > 0.0 ? (double)nc * nshift / per_iter : 0.0;
     if (rates[k] > best_rate) {
       best_rate = rates[k];
-      best = T;
+      best_t = T;
+      best_g = gp;
     }
   }
-  op->btile_sel = best;
-  *tile = best;
+  op->btile_sel = best_t;
+  op->bgpr_sel = best_g;
+  *tile = best_t;
+  *groups = best_g;
   return FSDA_OK;
 }
 

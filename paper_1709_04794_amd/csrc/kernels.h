@@ -736,20 +736,25 @@ struct XtSlices {
 // no cache-line lookups, which bind the gathers from L2.  The split rows'
 // indices are copied slice-major (slice x: the segments of rows 0, 1, ... in
 // order, as 16-bit offsets in the slice), so a slice's index stream is
-// contiguous.  Part (row j, slice x) goes to parts[x * nsplit + j]; the X^T
-// pass adds a split row's parts in slice order and runs the epilogue (assembly
-// items, before its other items).
+// contiguous; every segment starts at a multiple of LVEC entries and is padded
+// to one with the offset LSLICE, a slot of LDS that holds zero, so that a lane
+// loads LVEC offsets with one 16-byte load.  Part (row j, slice x) goes to
+// parts[x * nsplit + j]; the X^T pass adds a split row's parts in slice order and
+// runs the epilogue (assembly items, before its other items).
 constexpr int LSLICE = 8192;   // samples per LDS slice (64 KiB of FP64)
 constexpr int MAXLSLICE = 32;  // more slices: the XCD slices instead
 constexpr int LTB = 1024;      // threads per block of k_xt_lds
+constexpr int LVEC = 8;        // 16-bit offsets per index load (16 bytes)
+constexpr int LXV = 2;         // index loads per lane per pass
 
 struct XtLds {
   int nslice;               // 0: not in use
   int n;                    // samples
   int nsplit;               // split rows [0, nsplit)
-  int bps;                  // blocks per slice
-  const int* xptr;          // [nslice * (nsplit + 1)]: slice x, row j: xcol[xptr[x (nsplit+1) + j] ..]
-  const unsigned short* xcol;  // slice-major offsets in the slice
+  int nblk;                 // blocks; block k takes work items [k W / nblk, (k+1) W / nblk), W = nslice * nitem
+  int nitem;                // items of one slice (item0[nb])
+  const int* xptr;          // [nslice * (nsplit + 1)]: slice x, row j: xcol[xptr[x (nsplit+1) + j] ..], multiples of LVEC
+  const unsigned short* xcol;  // slice-major offsets in the slice, segments padded with LSLICE
   double* parts;            // [nslice * nsplit]
   int nb;                   // bins of split rows, lanes per row from the expected segment length
   int row0[MAXBIN + 1];
@@ -886,55 +891,70 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __re
   if (Epi::kReduce) write_partial(part, blockIdx.x, acc);
 }
 
-// Segments of the split rows in LDS slices: block (x, b) stages u over slice x
-// ([x LSLICE, (x+1) LSLICE) of the samples) in LDS, then takes the items b,
-// b + bps, ... of the slice; an item is LTB / lpr rows of one bin, lpr lanes per
-// row, each lane summing every (lpr XUNR)-th nonzero of the row's segment.
+// Segments of the split rows in LDS slices.  The work items, slice-major (item
+// i of slice x is work item x nitem + i), are dealt to the blocks in contiguous
+// ranges of equal size, so that every block of the one resident wave of blocks
+// gets the same share; a block stages u over each slice its range touches
+// ([x LSLICE, (x+1) LSLICE) of the samples, at most a few) in LDS and takes that
+// slice's items.  An item is LTB / lpr rows of one bin, lpr lanes per row; a
+// lane loads LVEC offsets at a time (LXV loads in flight) and adds the LDS
+// values they name.
 template <typename V>
 __global__ __launch_bounds__(LTB) void k_xt_lds(XtLds L, const V* __restrict__ u, State* st, int solve) {
   if (solve && st->stop) return;
   extern __shared__ double lds_raw[];
-  V* lu = reinterpret_cast<V*>(lds_raw);
+  V* lu = reinterpret_cast<V*>(lds_raw);  // LSLICE + 1 values: the slice, then the zero slot
   const int tid = threadIdx.x;
-  const int x = blockIdx.x / L.bps, b0 = blockIdx.x % L.bps;
-  const int x0 = x * LSLICE;
-  const int len = min(LSLICE, L.n - x0);
-  for (int k = tid; k < len; k += LTB) lu[k] = u[x0 + k];
-  __syncthreads();
-  const int* xp = L.xptr + (long long)x * (L.nsplit + 1);
-  const int nitems = L.item0[L.nb];
-  for (int it = b0; it < nitems; it += L.bps) {
-    int b = 0;
-    while (it >= L.item0[b + 1]) b++;
-    const int lpr = L.lpr[b];
-    const int j = L.row0[b] + (it - L.item0[b]) * (LTB / lpr) + tid / lpr;
-    const int lane = tid & (lpr - 1);
-    const bool live = j < L.row0[b + 1];
-    V v = (V)0;
-    if (live) {
-      const int end = xp[j + 1];
-      for (int k0 = xp[j] + lane; k0 < end; k0 += lpr * XUNR) {
-        int idx[XUNR];
-        V g[XUNR];
+  const long long total = (long long)L.nslice * L.nitem;
+  const int w0 = (int)(total * blockIdx.x / L.nblk), w1 = (int)(total * (blockIdx.x + 1) / L.nblk);
+  const uint4* xv = reinterpret_cast<const uint4*>(L.xcol);
+  constexpr unsigned PAD2 = (unsigned)LSLICE | ((unsigned)LSLICE << 16);  // two padding offsets
+  for (int w = w0; w < w1;) {
+    const int x = w / L.nitem;
+    const int wend = min(w1, (x + 1) * L.nitem);
+    __syncthreads();  // every wave is done with the previous slice
+    const int x0 = x * LSLICE;
+    const int len = min(LSLICE, L.n - x0);
+    for (int k = tid; k < len; k += LTB) lu[k] = u[x0 + k];
+    if (tid == 0) lu[LSLICE] = (V)0;
+    __syncthreads();
+    const int* xp = L.xptr + (long long)x * (L.nsplit + 1);
+    for (int it = w - x * L.nitem; it < wend - x * L.nitem; it++) {
+      int b = 0;
+      while (it >= L.item0[b + 1]) b++;
+      const int lpr = L.lpr[b];
+      const int j = L.row0[b] + (it - L.item0[b]) * (LTB / lpr) + tid / lpr;
+      const int lane = tid & (lpr - 1);
+      const bool live = j < L.row0[b + 1];
+      V v = (V)0;
+      if (live) {
+        const int ve = xp[j + 1] / LVEC;
+        for (int k0 = xp[j] / LVEC + lane; k0 < ve; k0 += lpr * LXV) {
+          uint4 q[LXV];
 #pragma unroll
-        for (int q = 0; q < XUNR; q++) {
-          const int k = k0 + q * lpr;
-          idx[q] = k < end ? (int)L.xcol[k] : -1;
+          for (int e = 0; e < LXV; e++) {
+            const int k = k0 + e * lpr;
+            q[e] = k < ve ? xv[k] : make_uint4(PAD2, PAD2, PAD2, PAD2);
+          }
+#pragma unroll
+          for (int e = 0; e < LXV; e++) {
+            const unsigned wd[4] = {q[e].x, q[e].y, q[e].z, q[e].w};
+#pragma unroll
+            for (int h = 0; h < 4; h++) v += lu[wd[h] & 0xffffu] + lu[wd[h] >> 16];
+          }
         }
-#pragma unroll
-        for (int q = 0; q < XUNR; q++) g[q] = idx[q] >= 0 ? lu[idx[q]] : (V)0;
-#pragma unroll
-        for (int q = 0; q < XUNR; q++) v += g[q];
       }
+      for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (live && lane == 0) L.parts[(long long)x * L.nsplit + j] = (double)v;
     }
-    for (int o = lpr >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (live && lane == 0) L.parts[(long long)x * L.nsplit + j] = (double)v;
+    w = wend;
   }
 }
 
 // Slice-major copy of the split rows' indices for the LDS slices: thread (x, j)
 // copies row j's segment of slice x ([segp[x nsplit + j], segp[(x+1) nsplit + j]))
-// to xcol[xptr[x (nsplit+1) + j] ..] as offsets from the slice's first sample.
+// to xcol[xptr[x (nsplit+1) + j] ..] as offsets from the slice's first sample,
+// then fills the rest of its entries (up to the next segment's start) with LSLICE.
 __global__ __launch_bounds__(BS) void k_slice_copy(const int* __restrict__ col, const int* __restrict__ segp,
                                                    const int* __restrict__ xptr, int nsplit, int nslice,
                                                    unsigned short* xcol) {
@@ -942,9 +962,10 @@ __global__ __launch_bounds__(BS) void k_slice_copy(const int* __restrict__ col, 
   if (t >= (long long)nslice * nsplit) return;
   const int x = (int)(t / nsplit), j = (int)(t % nsplit);
   const int b = segp[(long long)x * nsplit + j], e = segp[(long long)(x + 1) * nsplit + j];
-  const int o = xptr[(long long)x * (nsplit + 1) + j];
+  const int o = xptr[(long long)x * (nsplit + 1) + j], o1 = xptr[(long long)x * (nsplit + 1) + j + 1];
   const int x0 = x * LSLICE;
   for (int k = b; k < e; k++) xcol[o + (k - b)] = (unsigned short)(col[k] - x0);
+  for (int k = o + (e - b); k < o1; k++) xcol[k] = (unsigned short)LSLICE;
 }
 
 // Slice boundaries of the split rows of X^T: segp[x * nsplit + j] is the first

@@ -125,6 +125,9 @@ def _symmetrize(n: int, nbr: np.ndarray, cnt: np.ndarray):
     return rowptr.astype(np.int32), c.astype(np.int32)
 
 
+EXACT_KNN_MAX = 20000  # "auto" builds the exact graph up to this many samples, MinHash LSH beyond
+
+
 def knn_graph(n: int, x_rowptr: np.ndarray, x_col: np.ndarray, k: int, ties: bool = True,
               method: str = "auto", seed: int = 0, cap: Optional[int] = None):
     """Binary symmetric k-NN graph under Tanimoto similarity (Sec. 2.4).
@@ -141,7 +144,7 @@ def knn_graph(n: int, x_rowptr: np.ndarray, x_col: np.ndarray, k: int, ties: boo
     rp = np.ascontiguousarray(x_rowptr, dtype=np.int64)
     col = np.ascontiguousarray(x_col, dtype=np.int32)
     if method == "auto":
-        method = "exact" if n <= 20000 else "lsh"
+        method = "exact" if n <= EXACT_KNN_MAX else "lsh"
     if cap is None:
         cap = max(4 * k, 64)
     nbr = np.zeros((n, cap), dtype=np.int32)

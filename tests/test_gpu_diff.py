@@ -16,6 +16,17 @@ alpha-derivative).  Residuals must meet rtol and agree with the ones the solver
 reports; loss and gradients agree to 1e-10 relative (the same vectors enter both
 sides, only the operator products differ in rounding).  The whole grid of every
 target must meet rtol.  FSDA_SKIP_LARGE=1 leaves this test out.
+
+At the smallest shift (beta = 1e-3, a condition number near 1e9) an FP64
+evaluation of b - A w is itself uncertain at the 1e-9 level: |A| |w| is that many
+times ||b||, and rounding adds a vector of about eps |A| |w| to the residual.  The
+test measures that noise instead of assuming it: the oracle evaluates the residual
+a second time with w split into its FP32 rounding and the remainder (the same
+exact value, every rounding different), and the difference of the two residual
+vectors sizes the noise of one evaluation.  The reported residual must agree with
+the oracle's within 1e-3 relative plus three times that noise; the alpha-derivative
+<lambda, (A(alpha=1) - A(alpha=0)) w> within 1e-10 relative plus three times
+|lambda| times the difference of two such evaluations of its operator product.
 """
 import dataclasses
 import os
@@ -41,6 +52,17 @@ NTARGET = 16  # of the workload's 64
 
 def log(msg):
     print(msg, flush=True)
+
+
+def true_residual(pc, beta, x, rhs):
+    """||rhs - A(beta) x|| / ||rhs|| by the oracle, and the size of one evaluation's
+    rounding noise: the norm of the difference from a second evaluation with x split
+    into fl32(x) + (x - fl32(x)), relative to ||rhs||."""
+    x32 = x.astype(np.float32).astype(np.float64)
+    r1 = rhs - oracle.apply(pc, beta, x)
+    r2 = rhs - (oracle.apply(pc, beta, x32) + oracle.apply(pc, beta, x - x32))
+    nb = np.linalg.norm(rhs)
+    return np.linalg.norm(r1) / nb, np.linalg.norm(r1 - r2) / nb
 
 
 @pytest.fixture(scope="module")
@@ -86,18 +108,26 @@ def test_diff_hypergradient_at_full_size(diff):
         w = W[c, s].cpu().numpy()
         lam = Lam[c, s].cpu().numpy()
         b = oracle.rhs(pc)
-        fwd = np.linalg.norm(b - oracle.apply(pc, beta, w)) / np.linalg.norm(b)
+        fwd, fwd_noise = true_residual(pc, beta, w, b)
         g = ohyper.adjoint_rhs(pc, w[None], ho, y)[0]
-        adj = np.linalg.norm(g - oracle.apply(pc, beta, lam)) / np.linalg.norm(g)
+        adj, adj_noise = true_residual(pc, beta, lam, g)
         h = ohyper.loss(pc, w[None], ho, y)[0]
         dlb_r = -beta * float(lam @ w)
-        da_r = -float(lam @ (oracle.apply(pc, 0.0, w, alpha=1.0) - oracle.apply(pc, 0.0, w, alpha=0.0)))
-        log("target %d beta %.3g: forward relres %.4e (reported %.4e), adjoint %.4e (reported %.4e), "
-            "loss %.6e / %.6e, dlogbeta %.6e / %.6e, dalpha %.6e / %.6e"
-            % (c, beta, fwd, rel[c, s], adj, rel2[c, s], loss[c, s], h, dlb[c, s], dlb_r, da[c, s], da_r))
-        assert fwd <= pb.rtol * 1.001 and abs(fwd - rel[c, s]) <= 1e-3 * fwd, (c, s)
-        assert adj <= pb.rtol * 1.001 and abs(adj - rel2[c, s]) <= 1e-3 * adj, (c, s)
+        dA = oracle.apply(pc, 0.0, w, alpha=1.0) - oracle.apply(pc, 0.0, w, alpha=0.0)
+        da_r = -float(lam @ dA)
+        # rounding noise of <lambda, dA w>: |lambda| times the difference of two evaluations of dA w
+        w32 = w.astype(np.float32).astype(np.float64)
+        dA2 = (oracle.apply(pc, 0.0, w32, alpha=1.0) - oracle.apply(pc, 0.0, w32, alpha=0.0)
+               + oracle.apply(pc, 0.0, w - w32, alpha=1.0) - oracle.apply(pc, 0.0, w - w32, alpha=0.0))
+        da_noise = float(np.linalg.norm(lam) * np.linalg.norm(dA - dA2))
+        log("target %d beta %.3g: forward relres %.4e (reported %.4e, evaluation noise %.1e), adjoint %.4e "
+            "(reported %.4e, evaluation noise %.1e), loss %.6e / %.6e, dlogbeta %.6e / %.6e, dalpha %.6e / %.6e "
+            "(evaluation noise %.1e)"
+            % (c, beta, fwd, rel[c, s], fwd_noise, adj, rel2[c, s], adj_noise, loss[c, s], h, dlb[c, s], dlb_r,
+               da[c, s], da_r, da_noise))
+        assert fwd <= pb.rtol * 1.001 and abs(fwd - rel[c, s]) <= 1e-3 * fwd + 3 * fwd_noise, (c, s)
+        assert adj <= pb.rtol * 1.001 and abs(adj - rel2[c, s]) <= 1e-3 * adj + 3 * adj_noise, (c, s)
         assert np.abs(G[c, s].cpu().numpy() - g).max() <= 1e-12 * np.abs(g).max()
         assert abs(loss[c, s] - h) <= 1e-10 * abs(h)
         assert abs(dlb[c, s] - dlb_r) <= 1e-10 * abs(dlb_r)
-        assert abs(da[c, s] - da_r) <= 1e-8 * abs(da_r)
+        assert abs(da[c, s] - da_r) <= 1e-10 * abs(da_r) + 3 * da_noise

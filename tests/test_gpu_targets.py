@@ -160,19 +160,37 @@ def test_batch_set_tile_runs_smaller_tiles(tiny, tile):
     assert op.batch_tile == 16
 
 
-def test_batch_autotune_picks_a_tile_and_the_batch_stays_exact(tiny):
-    """The tuner times tiles 4, 8 and 16 (9 targets allow all three), keeps the fastest,
-    and the batch solved with it matches the oracle."""
+def test_batch_autotune_picks_a_shape_and_the_batch_stays_exact(tiny):
+    """The tuner times tiles 4, 8 and 16 (9 targets allow all three) with 1, 2 and 4 groups
+    of lanes per row, keeps the fastest shape, and the batch solved with it matches the oracle."""
     labs = synth.target_labels(tiny, 9, seed=8, frac_median=0.03, frac_hi=0.1)
     op = fsda.Operator.from_problem(tiny, alpha=0.5)
-    tile, rates = op.autotune_batch(labs, tiny.betas, trial_iters=16)
-    assert tile in (4, 8, 16)
-    assert set(rates) == {4, 8, 16} and all(r > 0 for r in rates.values())
-    assert rates[tile] == max(rates.values())
-    assert op.batch_tile == tile
+    tile, groups, rates = op.autotune_batch(labs, tiny.betas, trial_iters=16)
+    assert (tile, groups) in rates
+    assert set(rates) == {(t, g) for t in (4, 8, 16) for g in (1, 2, 4)} and all(r > 0 for r in rates.values())
+    assert rates[(tile, groups)] == max(rates.values())
+    assert (op.batch_tile, op.batch_groups) == (tile, groups)
     W, iters, relres, st = op.solve_batch(labs, tiny.betas, rtol=1e-10)
     assert st == fsda.OK
     check_against_oracle(tiny, labs, W, relres, tiny.betas, 0.5, 1e-10)
     # two targets: only the tile of 4 fits them
-    tile2, rates2 = op.autotune_batch(labs[:2], tiny.betas, trial_iters=8)
-    assert tile2 == 4 and set(rates2) == {4}
+    tile2, groups2, rates2 = op.autotune_batch(labs[:2], tiny.betas, trial_iters=8)
+    assert tile2 == 4 and {t for t, _ in rates2} == {4}
+
+
+@pytest.mark.parametrize("tile,groups", [(4, 4), (8, 2), (16, 2), (16, 4)])
+def test_batch_groups_per_row_match_oracle(tiny, tile, groups):
+    """Rows of the row products shared by 2 or 4 groups of tile lanes (the X product with
+    its mask features, the graph product, the short rows of X^T), ragged tiles included."""
+    labs = synth.target_labels(tiny, 11, seed=tile + groups, frac_median=0.03, frac_hi=0.1)
+    betas = np.array([3e-2, 0.4, 7.0])
+    op = fsda.Operator.from_problem(tiny, alpha=0.5)
+    op.set_batch_tile(tile)
+    op.set_batch_groups(groups)
+    W, iters, relres, st = op.solve_batch(labs, betas, rtol=1e-10, chunk=8)
+    assert st == fsda.OK
+    check_against_oracle(tiny, labs, W, relres, betas, 0.5, 1e-10)
+    with pytest.raises(fsda.FsdaError):
+        op.set_batch_groups(3)
+    op.set_batch_groups(0)
+    assert op.batch_groups == 1
