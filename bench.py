@@ -706,6 +706,40 @@ def cpu_baseline_targets(pb, target, budget_s: float, rtol: float):
             "one_core": one_core}
 
 
+def cpu_baseline_diff(pb, target, iters_total: int, nhyper: int):
+    """The oracle on the host cores for the differentiation workload, extrapolated:
+    the time of one per-shift FP64 CG iteration with one target's training labels
+    (difference of a 12- and a 2-iteration solve), all threads and one thread, times
+    the iterations the GPU needed for every forward and adjoint system (a per-shift
+    CG needs about as many for its shift as the shared recurrence took to meet it)."""
+    import dataclasses
+    import oracle
+    pc = dataclasses.replace(pb, lab_idx=target[0], lab_y=target[1])
+    nt = oracle.max_threads()
+
+    def per_iteration():
+        t0 = time.perf_counter()
+        oracle.solve(pc, betas=[pb.betas[-1]], rtol=pb.rtol, maxit=2)
+        t2 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.solve(pc, betas=[pb.betas[-1]], rtol=pb.rtol, maxit=12)
+        return (time.perf_counter() - t0 - t2) / 10
+
+    per_it = per_iteration()
+    try:
+        oracle.set_threads(1)
+        per_it1 = per_iteration()
+    finally:
+        oracle.set_threads(nt)
+    return {"value": round(nhyper / (per_it * iters_total), 5), "unit": "hypergradients/s", "cores": nt,
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cores": host_cores(),
+            "sample": "extrapolated: %.4f s per per-shift FP64 CG iteration of the oracle (target 0's training "
+                      "labels, difference of 12- and 2-iteration solves) x %d iterations (the GPU's iteration "
+                      "counts of all 64 x %d forward and adjoint systems)" % (per_it, iters_total, pb.betas.size),
+            "one_core": {"value": round(nhyper / (per_it1 * iters_total), 6), "unit": "hypergradients/s",
+                         "cores": 1, "seconds_per_iteration": round(per_it1, 4)}}
+
+
 def batched_bench(args, fsda, torch):
     """The default benchmark: shifted solves per second of many targets over one X."""
     import synth
@@ -857,6 +891,10 @@ def diff_experiment(args, fsda, torch):
     Lam, it2, rel2, st2 = timed("adjoint_s", adjoint)
     dlb, da = timed("gradient_s", lambda: op.hypergradient_batch(train, W, Lam, pb.betas))
     total = sum(phases.values())
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_diff(pb, train[0], int(it.sum()) + int(it2.sum()), 64 * S)
+        log("cpu baseline: %s" % json.dumps(cpu))
     print(json.dumps({"experiment": "diff", "workload": "diff: n=%d x d=%d binary, nnz_X=%d, nnz_S=%d, alpha=%g, "
                                                         "%d shifts, 64 targets (80/20 splits), rtol %g"
                                                         % (pb.n, pb.d, pb.x_nnz, pb.s_nnz, pb.alpha, S, pb.rtol),
@@ -867,7 +905,7 @@ def diff_experiment(args, fsda, torch):
                       "adjoint": {"status": st2, "worst_relres": float(rel2.max()), "max_iters": int(it2.max()),
                                   "solved": int((rel2 <= TARGET_RELRES).sum())},
                       "finite": bool(np.isfinite(dlb).all() and np.isfinite(da).all()),
-                      "loss_range": [float(loss.min()), float(loss.max())]}), flush=True)
+                      "loss_range": [float(loss.min()), float(loss.max())], "cpu_baseline": cpu}), flush=True)
 
 
 def mixed_large(args, fsda, torch):
