@@ -423,21 +423,22 @@ def batched_targets(args, fsda, torch):
             % (k, pb.betas.size, dt, solved / dt, rel.max()))
         del W
     many = None
-    if args.targets > 0:  # e.g. 1000 targets: calls of 64 (the most one call takes), one after the other
+    if args.targets > 0:  # e.g. 1000 targets in calls of 256 (the W of a call: 256 x 16 x d doubles)
         labs = synth.target_labels(pb, args.targets, seed=2)
+        CALL = 256
         t0 = time.perf_counter()
         solved, worst, maxit = 0, 0.0, 0
-        for c0 in range(0, args.targets, 64):
-            W, it, rel, st = op.solve_batch(labs[c0:c0 + 64], pb.betas, rtol=pb.rtol)
+        for c0 in range(0, args.targets, CALL):
+            W, it, rel, st = op.solve_batch(labs[c0:c0 + CALL], pb.betas, rtol=pb.rtol)
             torch.cuda.synchronize()
             solved += int((rel <= TARGET_RELRES).sum())
             worst, maxit = max(worst, float(rel.max())), max(maxit, int(it.max()))
             del W
-            log("targets %d..%d done after %.1f s" % (c0, min(c0 + 64, args.targets) - 1, time.perf_counter() - t0))
+            log("targets %d..%d done after %.1f s" % (c0, min(c0 + CALL, args.targets) - 1, time.perf_counter() - t0))
         dt = time.perf_counter() - t0
         many = {"targets": args.targets, "shifts": int(pb.betas.size), "seconds": round(dt, 2),
                 "shifted_solves_per_s": round(solved / dt, 2), "solved": solved, "worst_relres": worst,
-                "max_iters": maxit, "calls": -(-args.targets // 64)}
+                "max_iters": maxit, "calls": -(-args.targets // CALL), "targets_per_call": CALL}
         log("%d targets x %d shifts: %.1f s, %.1f shifted solves/s" % (args.targets, pb.betas.size, dt, solved / dt))
     # per-kernel time of one 16-target solve: one solve per class, that class's
     # launches bracketed by HIP events (direct launches while timing)
@@ -542,7 +543,7 @@ def summarize_rocprof(d: str, kernel_substr: str, calib_mib: int) -> str:
 
 
 TRAFFIC_MATCH = {"k_xt": "k_xt<fsda::EpiXTR<double>", "k_xt_lds": "k_xt_lds<double>",
-                 "k_rows_x": "k_rows<fsda::EpiX<double, false>", "k_fold": "k_fold_apply<double>",
+                 "k_rows_x": "k_rows<fsda::EpiX<double, false>, 1024>", "k_fold": "k_fold_apply<double>",
                  "k_rows_s": "k_rows<fsda::EpiLap<double, false>", "k_assemble": "k_assemble<fsda::EpiXTR<double>"}
 
 
@@ -638,7 +639,10 @@ def roofline_large(args, fsda, torch):
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, "large"),
             "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_us, 2), "launches": nl,
             "timed_every": 1, "event_pair_us": round(pair_us, 2), "xt_plan": xt_plan(pb)["plan"],
-            "note": "HIP events around every launch of the kernel on its launch stream, pair cost included"}
+            "note": "HIP events around every launch of the kernel on its launch stream, pair cost included",
+            "traffic_note": "rocprofv3 FETCH_SIZE + WRITE_SIZE (beyond L2: Infinity Cache or HBM) per launch, "
+                            "calibrated on a 1 GiB device copy in the same run; a lower bound (the counters "
+                            "read 0.29 of the fold's 12.3 GB pure stream), see profiles/large_apply_traffic.txt"}
     apply = {"workload": "large", "bytes": b_op, "us": round(apply_us, 2),
              "GBps": round(b_op / (apply_us * 1e-6) / 1e9, 1),
              "frac": round(b_op / (apply_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),

@@ -255,6 +255,29 @@ struct BXtArgs {
   const int* chunk_end;
   const int* item_chunk;
   int nitem;
+  // chunk k's sum goes to lpart[(part0 + k) T + c]; the first part0 pieces are
+  // the LDS-slice parts of the longest rows (BXtLds), rows [0, part0 / nslice)
+  int part0;
+};
+
+// LDS slices of the batched X^T product.  The longest rows of X^T [0, nrow) (at
+// least BL_SEG nonzeros per slice on average) are summed per slice of slen
+// samples from u over those samples and the T columns, staged in LDS
+// (slen T values, 128 KiB in FP64): gathers from LDS pay no cache-line lookups
+// and move no L2 bytes.  Part (row j, slice x) goes to lpart[(j nslice + x) T
+// + c], which bk_xt_rows adds in slice order.  The rows' indices are copied
+// slice-major as 16-bit offsets in the slice, each segment at a multiple of
+// LVEC entries and padded to one with the offset slen (a zero row of LDS).
+constexpr int BLT = 1024;                  // threads per block of bk_xt_lds
+constexpr int BL_LDS_BYTES = 128 * 1024;   // staged slice of u (one block per CU)
+constexpr int BL_SEG = 16;                 // shortest average segment of a row taken
+constexpr int BLX = 4;                     // index loads per group and pass
+
+struct BXtLds {
+  int nslice, slen, n, nrow;  // slices of slen samples; rows [0, nrow) of X^T
+  int nitem, nblk;            // items per slice (BLT / T rows each); blocks
+  const int* xptr;            // [nslice][nrow + 1]: segment starts (multiples of LVEC)
+  const unsigned short* xcol; // slice-major offsets, padded with slen
 };
 
 __device__ __forceinline__ size_t qidx(int T, long long ldq, long long r, int c) {
@@ -294,7 +317,7 @@ __global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __rest
         V t = (V)0;
 #pragma unroll
         for (int q = 0; q < G; q++) t += sh[q * T + threadIdx.x];
-        lpart[(size_t)k * T + threadIdx.x] = t;
+        lpart[(size_t)(X.part0 + k) * T + threadIdx.x] = t;
       }
       continue;
     }
@@ -303,6 +326,73 @@ __global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __rest
     const V v = groups_sum<T, GPR>(group_gather<T, V, GPR>(col, rowptr[r], rowptr[r + 1], u, c, q));
     if (q == 0) Q[qidx(T, ldq, r, c)] = P ? v + sg * P[(size_t)r * T + c] : v;
   }
+}
+
+// The LDS-slice parts (see BXtLds).  The (slice, item) work items, slice-major,
+// are dealt to the blocks in contiguous ranges of equal size; a block stages u
+// over each slice its range touches and takes that slice's items.  Group g (T
+// lanes, lane c for column c) of an item sums row j's segment: the group's
+// lanes load the same LVEC offsets (one 16-byte load, BLX in flight) and lane c
+// adds lu[offset T + c] (T consecutive values: one LDS line per offset).
+template <int T, typename V>
+__global__ __launch_bounds__(BLT) void bk_xt_lds(BXtLds L, const V* __restrict__ u, V* lpart, const int* stop) {
+  if (*stop) return;
+  extern __shared__ double bl_raw[];
+  V* lu = reinterpret_cast<V*>(bl_raw);  // (slen + 1) T values: the slice, then a zero row
+  constexpr int G = BLT / T;
+  const int c = threadIdx.x % T, g = threadIdx.x / T;
+  const long long total = (long long)L.nslice * L.nitem;
+  const int w0 = (int)(total * blockIdx.x / L.nblk), w1 = (int)(total * (blockIdx.x + 1) / L.nblk);
+  const uint4* xv = reinterpret_cast<const uint4*>(L.xcol);
+  const unsigned pad2 = (unsigned)L.slen | ((unsigned)L.slen << 16);
+  for (int w = w0; w < w1;) {
+    const int x = w / L.nitem;
+    const int wend = min(w1, (x + 1) * L.nitem);
+    __syncthreads();  // every group is done with the previous slice
+    const long long s0 = (long long)x * L.slen;
+    const int len = (int)min((long long)L.slen, (long long)L.n - s0) * T;
+    for (int k = threadIdx.x; k < len; k += BLT) lu[k] = u[(size_t)s0 * T + k];
+    if (threadIdx.x < T) lu[(size_t)L.slen * T + threadIdx.x] = (V)0;
+    __syncthreads();
+    const int* xp = L.xptr + (long long)x * (L.nrow + 1);
+    for (int it = w - x * L.nitem; it < wend - x * L.nitem; it++) {
+      const int j = it * G + g;
+      if (j >= L.nrow) continue;
+      V v = (V)0;
+      const int ve = xp[j + 1] / LVEC;
+      for (int k0 = xp[j] / LVEC; k0 < ve; k0 += BLX) {
+        uint4 q[BLX];
+#pragma unroll
+        for (int e = 0; e < BLX; e++) q[e] = k0 + e < ve ? xv[k0 + e] : make_uint4(pad2, pad2, pad2, pad2);
+#pragma unroll
+        for (int e = 0; e < BLX; e++) {
+          const unsigned wd[4] = {q[e].x, q[e].y, q[e].z, q[e].w};
+#pragma unroll
+          for (int h = 0; h < 4; h++)
+            v += lu[(size_t)(wd[h] & 0xffffu) * T + c] + lu[(size_t)(wd[h] >> 16) * T + c];
+        }
+      }
+      lpart[((size_t)j * L.nslice + x) * T + c] = v;
+    }
+    w = wend;
+  }
+}
+
+// Slice-major copy of the LDS-slice rows' indices: thread (x, j) copies row j's
+// segment of slice x ([segp[x nrow + j], segp[(x+1) nrow + j])) to
+// xcol[xptr[x (nrow+1) + j] ..] as offsets from the slice's first sample, then
+// fills the rest of its entries (up to the next segment's start) with slen.
+__global__ __launch_bounds__(BS) void bk_slice_copy(const int* __restrict__ col, const int* __restrict__ segp,
+                                                    const int* __restrict__ xptr, int nrow, int nslice, int slen,
+                                                    unsigned short* xcol) {
+  const long long t = (long long)blockIdx.x * BS + threadIdx.x;
+  if (t >= (long long)nslice * nrow) return;
+  const int x = (int)(t / nrow), j = (int)(t % nrow);
+  const int b = segp[(long long)x * nrow + j], e = segp[(long long)(x + 1) * nrow + j];
+  const int o = xptr[(long long)x * (nrow + 1) + j], o1 = xptr[(long long)x * (nrow + 1) + j + 1];
+  const long long x0 = (long long)x * slen;
+  for (int k = b; k < e; k++) xcol[o + (k - b)] = (unsigned short)(col[k] - x0);
+  for (int k = o + (e - b); k < o1; k++) xcol[k] = (unsigned short)slen;
 }
 
 // X^T product, second level: row j < nmed is the fixed-order sum of its chunk

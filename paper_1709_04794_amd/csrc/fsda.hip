@@ -37,6 +37,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fsda.h"
@@ -1122,7 +1123,41 @@ struct BxtTables {
   int *crow, *cbeg, *cend, *item, *rc0;
   long long cap;  // room for pieces (items: bxt_item_cap)
   bool sliced;
+  // LDS slices of the longest rows (NULL: none): segment bounds, segment starts,
+  // the slice-major offsets and the bytes reserved for them
+  int *bl_segp, *bl_xptr;
+  unsigned short* bl_xcol;
+  size_t bl_cap;
 };
+
+// LDS slices of the batched X^T product over T FP64 columns (see BXtLds): slices
+// of BL_LDS_BYTES / (8 T) samples, and the rows of X^T with at least BL_SEG
+// nonzeros per slice on average (the environment variable FSDA_BXT_LDS_SEG sets
+// that threshold; 0 turns the LDS slices off).  entries bounds the padded
+// offset table.
+struct BlPlan {
+  int slen, nsl, nrow;
+  long long nnz, entries;
+};
+BlPlan bxt_lds_plan(const fsda_op* op, int T) {
+  BlPlan b{0, 0, 0, 0, 0};
+  const char* e = std::getenv("FSDA_BXT_LDS_SEG");
+  const int seg = e ? std::atoi(e) : BL_SEG;
+  if (seg <= 0 || op->nmed == 0) return b;
+  b.slen = BL_LDS_BYTES / (8 * T);
+  b.nsl = (int)ceil_div(op->pb.n, b.slen);
+  const std::vector<int>& rp = op->xt_rp_med;  // rows by decreasing length
+  while (b.nrow < op->nmed && (long long)(rp[b.nrow + 1] - rp[b.nrow]) >= (long long)seg * b.nsl) b.nrow++;
+  if (b.nrow == 0) return BlPlan{0, 0, 0, 0, 0};
+  b.nnz = (long long)rp[b.nrow] - rp[0];
+  b.entries = b.nnz + (long long)(LVEC - 1) * std::min<long long>((long long)b.nrow * b.nsl, b.nnz);
+  return b;
+}
+
+template <int T>
+size_t bl_smem(const BXtLds& bl) {
+  return sizeof(double) * (size_t)(bl.slen + 1) * T;
+}
 
 // Room for the chunk items (and, at first use, the split rows' segment bounds).
 size_t bxt_item_cap(const fsda_op* op, long long cap) {
@@ -1160,8 +1195,9 @@ long long bxt_chunk_cap(const fsda_op* op, int T, bool sliced) {
   const long long bc = (long long)BS * (T >= 64 ? 1 : 64 / T);  // BCHUNK<T>()
   const int smin = bxt_slice_min(T);
   const std::vector<int>& rp = op->xt_rp_med;
-  long long n = 1;
-  for (int j = 0; j < op->nmed; j++) {
+  const BlPlan bp = bxt_lds_plan(op, T);
+  long long n = 1 + (long long)bp.nrow * bp.nsl;
+  for (int j = bp.nrow; j < op->nmed; j++) {
     const int len = rp[j + 1] - rp[j];
     n += ceil_div(len, bc) + (sliced && len >= smin ? NSLICE : 0);
   }
@@ -1169,8 +1205,11 @@ long long bxt_chunk_cap(const fsda_op* op, int T, bool sliced) {
 }
 
 template <int T>
-int chunk_table(fsda_op* op, const BxtTables& tb, BXtArgs* xa, hipStream_t s) {
+int chunk_table(fsda_op* op, const BxtTables& tb, BXtArgs* xa, hipStream_t s, BXtLds* bl = nullptr) {
   const int nmed = op->nmed;
+  const BlPlan bp = tb.bl_xptr && bl ? bxt_lds_plan(op, T) : BlPlan{0, 0, 0, 0, 0};
+  const int part0 = bp.nrow * bp.nsl;  // the LDS-slice parts come first
+  if (bl) *bl = BXtLds{0, 0, 0, 0, 0, 0, nullptr, nullptr};
   const std::vector<int>& rp = op->xt_rp_med;
   constexpr int bc = BCHUNK<T>();
   if (tb.sliced && nmed > 0 && op->bseg.empty()) {  // segment bounds of the split rows, once per handle
@@ -1187,8 +1226,9 @@ int chunk_table(fsda_op* op, const BxtTables& tb, BXtArgs* xa, hipStream_t s) {
   std::vector<int> crow, cbeg, cend, c0(nmed + 1), item, whole;
   std::vector<std::vector<int>> per(tb.sliced ? NSLICE : 0);
   const int smin = bxt_slice_min(T);
-  for (int j = 0; j < nmed; j++) {
-    c0[j] = (int)crow.size();
+  for (int j = 0; j < bp.nrow; j++) c0[j] = j * bp.nsl;
+  for (int j = bp.nrow; j < nmed; j++) {
+    c0[j] = part0 + (int)crow.size();
     const bool cut = tb.sliced && rp[j + 1] - rp[j] >= smin;
     const int nsl = cut ? NSLICE : 1;
     for (int x = 0; x < nsl; x++) {
@@ -1202,8 +1242,8 @@ int chunk_table(fsda_op* op, const BxtTables& tb, BXtArgs* xa, hipStream_t s) {
       }
     }
   }
-  c0[nmed] = (int)crow.size();
-  if ((long long)crow.size() > tb.cap) return fail(FSDA_E_WORKSPACE, "chunk table larger than reserved");
+  c0[nmed] = part0 + (int)crow.size();
+  if (part0 + (long long)crow.size() > tb.cap) return fail(FSDA_E_WORKSPACE, "chunk table larger than reserved");
   if (tb.sliced) {  // rounds of NSLICE (item it: slice it % 8), then the uncut rows' chunks
     size_t rounds = 0;
     for (const auto& v : per) rounds = std::max(rounds, v.size());
@@ -1222,7 +1262,43 @@ int chunk_table(fsda_op* op, const BxtTables& tb, BXtArgs* xa, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(tb.rc0, c0.data(), sizeof(int) * c0.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   *xa = BXtArgs{op->xt_rowptr, op->xt_col, (int)op->pb.d, nmed, (int)crow.size(), tb.crow, tb.cbeg, tb.rc0,
-                tb.sliced ? tb.cend : nullptr, tb.sliced ? tb.item : nullptr, (int)item.size()};
+                tb.sliced ? tb.cend : nullptr, tb.sliced ? tb.item : nullptr, (int)item.size(), part0};
+  if (bp.nrow == 0) return FSDA_OK;
+  // LDS slices of rows [0, bp.nrow): segment bounds on the device, padded
+  // segment starts on the host, then the slice-major offsets
+  const long long nseg = (long long)(bp.nsl + 1) * bp.nrow;
+  hipLaunchKernelGGL(k_slice_bounds, dim3((unsigned)ceil_div(nseg, BS)), dim3(BS), 0, s, op->xt_rowptr, op->xt_col,
+                     bp.nrow, (long long)op->pb.n, bp.nsl, bp.slen, tb.bl_segp);
+  HIP_TRY(hipGetLastError());
+  std::vector<int> sp(nseg), xp((size_t)bp.nsl * (bp.nrow + 1));
+  HIP_TRY(hipMemcpyAsync(sp.data(), tb.bl_segp, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  long long tot = 0;
+  for (int x = 0; x < bp.nsl; x++) {
+    int* px = xp.data() + (size_t)x * (bp.nrow + 1);
+    for (int j = 0; j < bp.nrow; j++) {
+      px[j] = (int)tot;
+      const long long len = sp[(size_t)(x + 1) * bp.nrow + j] - sp[(size_t)x * bp.nrow + j];
+      tot += (len + LVEC - 1) / LVEC * LVEC;
+    }
+    px[bp.nrow] = (int)tot;
+  }
+  if (2 * (size_t)tot > tb.bl_cap) return fail(FSDA_E_WORKSPACE, "LDS-slice offset table larger than reserved");
+  HIP_TRY(hipMemcpyAsync(tb.bl_xptr, xp.data(), sizeof(int) * xp.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(bk_slice_copy, dim3((unsigned)ceil_div((long long)bp.nsl * bp.nrow, BS)), dim3(BS), 0, s,
+                     op->xt_col, tb.bl_segp, tb.bl_xptr, bp.nrow, bp.nsl, bp.slen, tb.bl_xcol);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));  // xp is read by the copy above
+  bl->nslice = bp.nsl;
+  bl->slen = bp.slen;
+  bl->n = (int)op->pb.n;
+  bl->nrow = bp.nrow;
+  bl->nitem = (int)ceil_div(bp.nrow, BLT / T);
+  bl->nblk = (int)std::min<long long>((long long)bp.nsl * bl->nitem, 256);  // one block per CU (128 KiB of LDS)
+  bl->xptr = tb.bl_xptr;
+  bl->xcol = tb.bl_xcol;
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(bk_xt_lds<T, double>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bl_smem<T>(*bl)));
   return FSDA_OK;
 }
 
@@ -1234,6 +1310,7 @@ struct BBuf {
   double* part;  // BP_N sites of GRID_B x BT_MAX partials
   V *R, *P, *Q, *X, *t, *u, *lpart;
   BXtArgs xa;
+  BXtLds bl;  // LDS slices of the X^T product (FP64 only; nrow 0: none)
   // labeled weights of row r, column c: labw[r * lws + c * lcs] (the handle's
   // labeled set for every column: lws = 1, lcs = 0; one set per column: T, 1)
   const double* labw;
@@ -1286,6 +1363,11 @@ void b_products(fsda_op* op, const BBuf<V>& b, const V* src, const V* P, const i
   });
   const int gxt = bxt_grid(b.xa, G);  // one group of T lanes per short row
   launch(op, timed ? KC_BXT : KC_OTHER, s, [&] {
+    if constexpr (std::is_same<V, double>::value) {
+      if (b.bl.nrow > 0)
+        hipLaunchKernelGGL((bk_xt_lds<T, double>), dim3(b.bl.nblk), dim3(BLT), bl_smem<T>(b.bl), s, b.bl, b.u,
+                           b.lpart, stop);
+    }
     hipLaunchKernelGGL((bk_xt<T, V>), dim3(gxt), dim3(BS), 0, s, b.xa, b.lpart, b.u, P, b.Q, 0LL, st->sigma, stop);
     if (b.xa.nmed > 0)
       hipLaunchKernelGGL((bk_xt_rows<T, V>), dim3(grid_b(b.xa.nmed)), dim3(BS), 0, s, b.xa, b.lpart, P, b.Q, 0LL,
@@ -1396,6 +1478,7 @@ int refine_buffers(fsda_op* op, BBuf<float>* b, hipStream_t s) {
   }
   b->st = op->bst;
   b->hst = op->hbst;
+  b->bl = BXtLds{0, 0, 0, 0, 0, 0, nullptr, nullptr};  // FP32: no LDS slices
   b->part = at<double>(op, L.bpart);
   b->R = at<float>(op, L.bR);
   b->P = at<float>(op, L.bP);
@@ -1476,16 +1559,20 @@ struct ColTargets {
 };
 
 struct CLayout {
-  size_t st, part, R, P, Q, X, t, u, lpart, crow, cbeg, cend, item, rc0, flags, labw, b64, total;
+  size_t st, part, R, P, Q, X, t, u, lpart, crow, cbeg, cend, item, rc0, bl_segp, bl_xptr, bl_xcol, flags, labw, b64,
+      total;
+  size_t bl_cap;
   long long ld, cap;
   bool sliced;
 };
 
-BxtTables bxt_tables(char* ws, size_t crow, size_t cbeg, size_t cend, size_t item, size_t rc0, long long cap,
-                     bool sliced) {
-  return BxtTables{reinterpret_cast<int*>(ws + crow), reinterpret_cast<int*>(ws + cbeg),
-                   reinterpret_cast<int*>(ws + cend), sliced ? reinterpret_cast<int*>(ws + item) : nullptr,
-                   reinterpret_cast<int*>(ws + rc0), cap, sliced};
+template <class Lay>
+BxtTables bxt_tables(char* ws, const Lay& L) {
+  return BxtTables{reinterpret_cast<int*>(ws + L.crow), reinterpret_cast<int*>(ws + L.cbeg),
+                   reinterpret_cast<int*>(ws + L.cend), L.sliced ? reinterpret_cast<int*>(ws + L.item) : nullptr,
+                   reinterpret_cast<int*>(ws + L.rc0), L.cap, L.sliced,
+                   reinterpret_cast<int*>(ws + L.bl_segp), reinterpret_cast<int*>(ws + L.bl_xptr),
+                   reinterpret_cast<unsigned short*>(ws + L.bl_xcol), L.bl_cap};
 }
 
 // per_col: room for one labeled-weight column per batch column (n x T).
@@ -1515,6 +1602,13 @@ void clayout(const fsda_op* op, int T, int ncol, bool per_col, CLayout* L) {
   L->cend = take(4 * (size_t)L->cap);
   L->item = L->sliced ? take(4 * bxt_item_cap(op, L->cap)) : 0;
   L->rc0 = take(4 * (size_t)(z / BMED + 2));
+  {
+    const BlPlan bp = bxt_lds_plan(op, T);
+    L->bl_segp = take(4 * (size_t)(bp.nsl + 1) * bp.nrow);
+    L->bl_xptr = take(4 * (size_t)bp.nsl * (bp.nrow + 1));
+    L->bl_cap = 2 * (size_t)bp.entries;
+    L->bl_xcol = take(L->bl_cap);
+  }
   L->flags = take(sizeof(int) * 4 * BT_MAX);
   L->labw = per_col ? take(8 * (size_t)n * T) : 0;
   // last: every buffer the captured iterations touch sits at an offset that
@@ -1578,7 +1672,7 @@ int run_columns(fsda_op* op, char* ws, const CLayout& L, const double* B, const 
   b.labw = op->labw;
   b.lws = 1;
   b.lcs = 0;
-  int rc = chunk_table<T>(op, bxt_tables(ws, L.crow, L.cbeg, L.cend, L.item, L.rc0, L.cap, L.sliced), &b.xa, s);
+  int rc = chunk_table<T>(op, bxt_tables(ws, L), &b.xa, s, &b.bl);
   if (rc) return rc;
   if (ct) {  // one labeled set per column (t and u are scratch until the solve)
     double* labw = reinterpret_cast<double*>(ws + L.labw);
@@ -1666,7 +1760,9 @@ int refine_any(fsda_op* op, const double* rhs, const double* betas, int nshift, 
 // ---------------------------------------------------------------------------
 
 struct TLayout {
-  size_t st, part, hist, coef, flags, labw, B, P, Q, t, u, ring, Ps, lpart, crow, cbeg, cend, item, rc0, total;
+  size_t st, part, hist, coef, flags, labw, B, P, Q, t, u, ring, Ps, lpart, crow, cbeg, cend, item, rc0, bl_segp,
+      bl_xptr, bl_xcol, total;
+  size_t bl_cap;
   long long ld, cap;
   bool sliced;
 };
@@ -1702,6 +1798,13 @@ void tlayout(const fsda_op* op, int T, int nshift, int chunk, TLayout* L) {
   L->cend = take(4 * (size_t)L->cap);
   L->item = L->sliced ? take(4 * bxt_item_cap(op, L->cap)) : 0;
   L->rc0 = take(4 * (size_t)(z / BMED + 2));
+  {
+    const BlPlan bp = bxt_lds_plan(op, T);
+    L->bl_segp = take(4 * (size_t)(bp.nsl + 1) * bp.nrow);
+    L->bl_xptr = take(4 * (size_t)bp.nsl * (bp.nrow + 1));
+    L->bl_cap = 2 * (size_t)bp.entries;
+    L->bl_xcol = take(L->bl_cap);
+  }
   L->total = o;
 }
 
@@ -1710,6 +1813,7 @@ struct TPtr {
   double *part, *hist, *coef, *labw, *B, *P, *Q, *t, *u, *ring, *Ps, *lpart, *W;
   int* flags;
   BXtArgs xa;
+  BXtLds bl;
   long long ld;
   int ncol, nshift, chunk;
 };
@@ -1762,6 +1866,9 @@ void t_xt(fsda_op* op, const TPtr& p, const double* u, const double* P, double* 
           bool timed) {
   const int gxt = bxt_grid(p.xa, BS / T / GPR);
   launch(op, timed ? KC_BXT : KC_OTHER, s, [&] {
+    if (p.bl.nrow > 0)
+      hipLaunchKernelGGL((bk_xt_lds<T, double>), dim3(p.bl.nblk), dim3(BLT), bl_smem<T>(p.bl), s, p.bl, u, p.lpart,
+                         stop);
     hipLaunchKernelGGL((bk_xt<T, double, GPR>), dim3(gxt), dim3(BS), 0, s, p.xa, p.lpart, u, P, Q, p.ld, p.st->sigma,
                        stop);
     if (p.xa.nmed > 0)
@@ -1833,7 +1940,7 @@ int run_targets(fsda_op* op, char* ws, const TLayout& L, int ncol, const int* la
   p.ncol = ncol;
   p.nshift = nshift;
   p.chunk = chunk;
-  int rc = chunk_table<T>(op, bxt_tables(ws, L.crow, L.cbeg, L.cend, L.item, L.rc0, L.cap, L.sliced), &p.xa, s);
+  int rc = chunk_table<T>(op, bxt_tables(ws, L), &p.xa, s, &p.bl);
   if (rc) return rc;
 
   // solver state (uploaded first: the set-up launches test its `zero` flag)

@@ -34,7 +34,10 @@ def relerr(a, b):
 
 
 def build(pb, monkeypatch, slices, slice_min=None, **kw):
-    """slices "8" or "0"; slice_min: the shortest row cut into slices (default: eight chunks)."""
+    """slices "8" or "0"; slice_min: the shortest row cut into slices (default: eight chunks).
+    The LDS slices of the longest rows are off here (they would take every chunked row of
+    the tiny workload; tests/test_gpu_bxt_lds.py covers them)."""
+    monkeypatch.setenv("FSDA_BXT_LDS_SEG", "0")
     monkeypatch.setenv("FSDA_BXT_SLICES", str(slices))
     if slice_min is None:
         monkeypatch.delenv("FSDA_BXT_SLICE_MIN", raising=False)
