@@ -58,6 +58,23 @@ __device__ __forceinline__ void write_partials_cols(double* part, double acc) {
   }
 }
 
+// The same into slot `slot` (part[slot * T + c]).
+template <int T>
+__device__ __forceinline__ void write_partials_cols_at(double* part, int slot, double acc) {
+  __shared__ double sh[BS];
+  constexpr int G = BS / T;
+  const int tid = threadIdx.x;
+  __syncthreads();
+  sh[tid] = acc;
+  __syncthreads();
+  if (tid < T) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < G; k++) t += sh[k * T + tid];
+    part[(size_t)slot * T + tid] = t;
+  }
+}
+
 // out[c] (shared memory, c < T) = sum over blocks of part[blk * T + c], in a
 // fixed order.  All threads of the block must call it.
 template <int T>
@@ -284,10 +301,34 @@ __device__ __forceinline__ size_t qidx(int T, long long ldq, long long r, int c)
   return ldq ? (size_t)c * ldq + r : (size_t)r * T + c;
 }
 
+// The residual update fused into the X^T product of the target batch (ring !=
+// NULL): instead of storing q, the product's epilogue writes r_{i+1} = r_i -
+// a_c q to ring slot (i + 1) mod m (r_i in slot i mod m, i = *iter; the ring is
+// column-major like Q, [slot][c][row] with row stride ld) and adds r_{i+1}^2 to
+// the block's per-column partials, stored in slot slot0 + block of part.
+struct BResid {
+  const int* iter;
+  int m;
+  double* ring;
+  long long ld;
+  const double* a;
+  double* part;
+  int slot0;
+};
+
 template <int T, typename V, int GPR = 1>
 __global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __restrict__ u, const V* __restrict__ P,
-                                            V* Q, long long ldq, const double* sigma, const int* stop) {
+                                            V* Q, long long ldq, const double* sigma, const int* stop,
+                                            BResid R = BResid{nullptr, 0, nullptr, 0, nullptr, nullptr, 0}) {
   if (*stop) return;
+  double acc = 0.0;  // fused residual update: this block's <r_{i+1}, r_{i+1}> for the lane's column
+  const double* rin = nullptr;
+  double* rout = nullptr;
+  if (R.ring) {
+    const int i = *R.iter;
+    rin = R.ring + (size_t)(i % R.m) * T * R.ld;
+    rout = R.ring + (size_t)((i + 1) % R.m) * T * R.ld;
+  }
   const int* __restrict__ rowptr = X.rowptr;
   const int* __restrict__ col = X.col;
   const int d = X.d, nmed = X.nmed, nchunk = X.nchunk;
@@ -324,8 +365,19 @@ __global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __rest
     const int r = nmed + (it - nchit) * RB + g / GPR;
     if (r >= d) continue;
     const V v = groups_sum<T, GPR>(group_gather<T, V, GPR>(col, rowptr[r], rowptr[r + 1], u, c, q));
-    if (q == 0) Q[qidx(T, ldq, r, c)] = P ? v + sg * P[(size_t)r * T + c] : v;
+    if (q == 0) {
+      const V qv = P ? v + sg * P[(size_t)r * T + c] : v;
+      if (rout) {
+        const size_t e = (size_t)c * R.ld + r;
+        const double x = rin[e] - R.a[c] * (double)qv;
+        rout[e] = x;
+        acc += x * x;
+      } else {
+        Q[qidx(T, ldq, r, c)] = qv;
+      }
+    }
   }
+  if (R.ring) write_partials_cols_at<T>(R.part, R.slot0 + blockIdx.x, acc);
 }
 
 // The LDS-slice parts (see BXtLds).  The (slice, item) work items, slice-major,
@@ -400,8 +452,17 @@ __global__ __launch_bounds__(BS) void bk_slice_copy(const int* __restrict__ col,
 // every G-th chunk, then add up in order), plus sigma_c P.
 template <int T, typename V>
 __global__ __launch_bounds__(BS) void bk_xt_rows(BXtArgs X, const V* __restrict__ lpart, const V* __restrict__ P, V* Q,
-                                                 long long ldq, const double* sigma, const int* stop) {
+                                                 long long ldq, const double* sigma, const int* stop,
+                                                 BResid R = BResid{nullptr, 0, nullptr, 0, nullptr, nullptr, 0}) {
   if (*stop) return;
+  double acc = 0.0;
+  const double* rin = nullptr;
+  double* rout = nullptr;
+  if (R.ring) {
+    const int i = *R.iter;
+    rin = R.ring + (size_t)(i % R.m) * T * R.ld;
+    rout = R.ring + (size_t)((i + 1) % R.m) * T * R.ld;
+  }
   const int nmed = X.nmed;
   const int* __restrict__ row_chunk0 = X.row_chunk0;
   constexpr int G = BS / T;
@@ -425,9 +486,18 @@ __global__ __launch_bounds__(BS) void bk_xt_rows(BXtArgs X, const V* __restrict_
       V t = (V)0;
 #pragma unroll
       for (int k = 0; k < G; k++) t += sh[k * T + cc];
-      Q[qidx(T, ldq, j, cc)] = P ? t + (V)sigma[cc] * P[(size_t)j * T + cc] : t;
+      const V qv = P ? t + (V)sigma[cc] * P[(size_t)j * T + cc] : t;
+      if (rout) {
+        const size_t e = (size_t)cc * R.ld + j;
+        const double x = rin[e] - R.a[cc] * (double)qv;
+        rout[e] = x;
+        acc += x * x;
+      } else {
+        Q[qidx(T, ldq, j, cc)] = qv;
+      }
     }
   }
+  if (R.ring) write_partials_cols_at<T>(R.part, R.slot0 + blockIdx.x, acc);
 }
 
 // ---------------------------------------------------------------------------

@@ -1863,18 +1863,32 @@ void t_products(fsda_op* op, const TPtr& p, const double* src, const int* stop, 
 
 template <int T, int GPR>
 void t_xt(fsda_op* op, const TPtr& p, const double* u, const double* P, double* Q, const int* stop, hipStream_t s,
-          bool timed) {
+          bool timed, const BResid& R = BResid{nullptr, 0, nullptr, 0, nullptr, nullptr, 0}) {
   const int gxt = bxt_grid(p.xa, BS / T / GPR);
   launch(op, timed ? KC_BXT : KC_OTHER, s, [&] {
     if (p.bl.nrow > 0)
       hipLaunchKernelGGL((bk_xt_lds<T, double>), dim3(p.bl.nblk), dim3(BLT), bl_smem<T>(p.bl), s, p.bl, u, p.lpart,
                          stop);
     hipLaunchKernelGGL((bk_xt<T, double, GPR>), dim3(gxt), dim3(BS), 0, s, p.xa, p.lpart, u, P, Q, p.ld, p.st->sigma,
-                       stop);
-    if (p.xa.nmed > 0)
+                       stop, R);
+    if (p.xa.nmed > 0) {
+      BResid R2 = R;
+      R2.slot0 = R.slot0 + gxt;  // the rows' partials after the first level's
       hipLaunchKernelGGL((bk_xt_rows<T, double>), dim3(grid_b(p.xa.nmed)), dim3(BS), 0, s, p.xa, p.lpart, P, Q, p.ld,
-                         p.st->sigma, stop);
+                         p.st->sigma, stop, R2);
+    }
   });
+}
+
+// Partials of the X^T product with the residual update fused (blocks of both
+// levels), or 0 when they do not fit a partial site.  FSDA_BXT_FUSE=0 keeps
+// the separate residual kernel.
+template <int T, int GPR>
+int t_fused_parts(const TPtr& p) {
+  const char* e = std::getenv("FSDA_BXT_FUSE");
+  if (e && e[0] == '0') return 0;
+  const int n = bxt_grid(p.xa, BS / T / GPR) + (p.xa.nmed > 0 ? grid_b(p.xa.nmed) : 0);
+  return (long long)n * T <= (long long)GRID_B * BT_MAX ? n : 0;
 }
 
 int t_colgrid(long long d) { return grid_b(ceil_div(d, BS)); }
@@ -1890,11 +1904,17 @@ void t_iteration(fsda_op* op, const TPtr& p, hipStream_t s, int tag) {
   const int gc = t_colgrid(d);
   t_products<T, GPR>(op, p, p.P, &st->stop, s, true);
   hipLaunchKernelGGL(ts_step_a<T>, dim3(1), dim3(BS), 0, s, st, tpart(p, BP_TU), gx, tpart(p, BP_PP), gsb);
-  t_xt<T, GPR>(op, p, p.u, p.P, p.Q, &st->stop, s, true);
-  launch(op, KC_BRESID, s, [&] {
-    hipLaunchKernelGGL(ts_resid<T>, dim3(gc, T), dim3(BS), 0, s, st, p.Q, p.ring, p.ld, d, tpart(p, BP_RR));
-  });
-  hipLaunchKernelGGL(ts_step_b<T>, dim3(1), dim3(BS), 0, s, st, tpart(p, BP_RR), gc, p.hist);
+  const int nfused = t_fused_parts<T, GPR>(p);
+  if (nfused > 0) {  // r_{i+1} = r_i - a q written by the X^T product itself
+    t_xt<T, GPR>(op, p, p.u, p.P, p.Q, &st->stop, s, true,
+                 BResid{&st->iter, p.chunk, p.ring, p.ld, st->a_cur, tpart(p, BP_RR), 0});
+  } else {
+    t_xt<T, GPR>(op, p, p.u, p.P, p.Q, &st->stop, s, true);
+    launch(op, KC_BRESID, s, [&] {
+      hipLaunchKernelGGL(ts_resid<T>, dim3(gc, T), dim3(BS), 0, s, st, p.Q, p.ring, p.ld, d, tpart(p, BP_RR));
+    });
+  }
+  hipLaunchKernelGGL(ts_step_b<T>, dim3(1), dim3(BS), 0, s, st, tpart(p, BP_RR), nfused > 0 ? nfused : gc, p.hist);
   launch(op, KC_BPUPD, s, [&] {
     hipLaunchKernelGGL(ts_pupdate<T>, dim3(gsb), dim3(BS), 0, s, st, p.ring, p.ld, p.P, d, tpart(p, BP_PP));
   });
