@@ -81,7 +81,7 @@ template <int T>
 __device__ void col_sums(const double* part, int nblk, double* out) {
   __shared__ double sh[BS];
   constexpr int G = BS / T;
-  constexpr int U = 8;
+  constexpr int U = 32;  // loads in flight per thread: a few thousand partials take a few round trips
   const int c = threadIdx.x % T, g = threadIdx.x / T;
   double v = 0.0;
   for (int b0 = g; b0 < nblk; b0 += G * U) {
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(BS) void bk_rows(const int* __restrict__ rowptr, co
   extern __shared__ double bk_smem[];
   V* hot = reinterpret_cast<V*>(bk_smem);
   if (MASK) {
-    for (int e = threadIdx.x; e < bm.nmask * T; e += BS) hot[e] = src[e];
+    stage_lds<BS, 4>(hot, src, bm.nmask * T);
     __syncthreads();
   }
   epi.prepare(cm, c);
@@ -288,7 +288,7 @@ struct BXtArgs {
 constexpr int BLT = 1024;                  // threads per block of bk_xt_lds
 constexpr int BL_LDS_BYTES = 128 * 1024;   // staged slice of u (one block per CU)
 constexpr int BL_SEG = 16;                 // shortest average segment of a row taken
-constexpr int BLX = 4;                     // index loads per group and pass
+constexpr int BLX = 8;                     // index loads per group and pass
 
 struct BXtLds {
   int nslice, slen, n, nrow;  // slices of slen samples; rows [0, nrow) of X^T
@@ -403,7 +403,7 @@ __global__ __launch_bounds__(BLT) void bk_xt_lds(BXtLds L, const V* __restrict__
     __syncthreads();  // every group is done with the previous slice
     const long long s0 = (long long)x * L.slen;
     const int len = (int)min((long long)L.slen, (long long)L.n - s0) * T;
-    for (int k = threadIdx.x; k < len; k += BLT) lu[k] = u[(size_t)s0 * T + k];
+    stage_lds<BLT, 16>(lu, u + (size_t)s0 * T, len);
     if (threadIdx.x < T) lu[(size_t)L.slen * T + threadIdx.x] = (V)0;
     __syncthreads();
     const int* xp = L.xptr + (long long)x * (L.nrow + 1);

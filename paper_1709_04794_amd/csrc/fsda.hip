@@ -2452,11 +2452,17 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
     int zr = 0;
     HIP_TRY(hipMemcpyAsync(&zr, rrp + n, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    // blocks of XNT threads, two per CU (each stages the HOT most frequent features)
-    op->px = one_bin(rrp, rcol, n, zr, XNT, 2 * 256);
+    // blocks of XNT threads, two per CU (each stages the HOT most frequent
+    // features; FSDA_X_HOT sets another count, up to 20000 (the LDS holds 160 KiB), with as
+    // many blocks per CU as the LDS holds)
+    long long hot = HOT;
+    if (const char* e = std::getenv("FSDA_X_HOT")) hot = std::max(64, std::min(20000, std::atoi(e)));
+    hot = std::min<long long>(hot, d);
+    const int per_cu = (int)std::max<long long>(1, std::min<long long>(2, (160LL << 10) / std::max<long long>(8 * hot, 1)));
+    op->px = one_bin(rrp, rcol, n, zr, XNT, per_cu * 256);
     op->px.rows.mask = xm;
     op->px.rows.mtop = op->mtop;
-    op->px.rows.nhot = (int)std::min<long long>(HOT, d);
+    op->px.rows.nhot = (int)hot;
     const size_t hb = sizeof(double) * (size_t)op->px.rows.nhot;
     if ((rc = allow_xrows_smem<EpiX<double, true>>(hb)) || (rc = allow_xrows_smem<EpiX<double, false>>(hb)) ||
         (rc = allow_xrows_smem<EpiX<float, true>>(hb)) || (rc = allow_xrows_smem<EpiX<float, false>>(hb)))

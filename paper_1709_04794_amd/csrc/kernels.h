@@ -622,6 +622,26 @@ __device__ __forceinline__ double block_sum_nt(double v) {
   return t;
 }
 
+// dst[k] = src[k] for k < len by the NT threads of a block, SU loads per thread
+// in flight before their values are stored (a plain loop waits for each load
+// before its store: one memory round trip per element a thread copies).
+template <int NT, int SU, typename V>
+__device__ __forceinline__ void stage_lds(V* dst, const V* __restrict__ src, int len) {
+  for (int k0 = threadIdx.x; k0 < len; k0 += NT * SU) {
+    V v[SU];
+#pragma unroll
+    for (int e = 0; e < SU; e++) {
+      const int k = k0 + e * NT;
+      v[e] = k < len ? src[k] : (V)0;
+    }
+#pragma unroll
+    for (int e = 0; e < SU; e++) {
+      const int k = k0 + e * NT;
+      if (k < len) dst[k] = v[e];
+    }
+  }
+}
+
 // Row products in blocks of NT threads (an item is NT / lpr rows; the host plan
 // is built for the same NT).
 template <class Epi, int NT = BS>
@@ -635,7 +655,7 @@ __global__ __launch_bounds__(NT) void k_rows(Rows R, const typename Epi::V* __re
   V* ptop = reinterpret_cast<V*>(rows_smem);
   const int nhot = R.mask ? R.nhot : 0;
   if (R.mask) {
-    for (int k = tid; k < nhot; k += NT) ptop[k] = src[k];
+    stage_lds<NT, 8>(ptop, src, nhot);
     __syncthreads();
   }
   double acc = 0.0;
@@ -915,7 +935,7 @@ __global__ __launch_bounds__(LTB) void k_xt_lds(XtLds L, const V* __restrict__ u
     __syncthreads();  // every wave is done with the previous slice
     const int x0 = x * LSLICE;
     const int len = min(LSLICE, L.n - x0);
-    for (int k = tid; k < len; k += LTB) lu[k] = u[x0 + k];
+    stage_lds<LTB, 8>(lu, u + x0, len);
     if (tid == 0) lu[LSLICE] = (V)0;
     __syncthreads();
     const int* xp = L.xptr + (long long)x * (L.nsplit + 1);

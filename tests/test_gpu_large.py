@@ -6,8 +6,9 @@ The inputs take from ten seconds to a few minutes to generate, depending on the 
 so an oracle solve at this size is out of reach.  The checks are the operator product and right-hand side against the oracle's (full vectors), the
 ratings against the oracle's X w, and, for the four largest shifts of the grid (a few thousand
 iterations), the FP64 true residual of every returned iterate recomputed by the oracle: it
-must meet rtol and agree with the residual the solver reports.  The full grid (45,923
-iterations at the smallest shift) is what bench.py times.
+must meet rtol and agree with the residual the solver reports; and the whole FP64 grid
+(about 45,600 iterations at the smallest shift, 35 s), every shift's iterate checked the
+same way by the oracle.
 """
 import os
 
@@ -85,3 +86,33 @@ def test_large_top_shifts_meet_rtol_by_oracle_residual(large, precision):
         # the recurrence's iteration counts fall with the shift (Alg. 3 stops each shift
         # when its own residual is met)
         assert all(iters[s] >= iters[s + 1] for s in range(TOP - 1))
+
+
+def test_large_full_grid_fp64_every_shift_by_oracle_residual(large):
+    """The whole grid (32 shifts down to beta = 1e-4, about 45,600 iterations) in FP64, as
+    bench.py --experiment mixed-large times it: the oracle recomputes the true residual of
+    every returned iterate (one oracle product per shift); each must meet rtol and agree
+    with the reported one within 1e-3 relative, or, where it does not, within that plus three
+    times the rounding noise of one FP64 evaluation (measured by a second evaluation with w
+    split into fl32(w) + the rest)."""
+    op = fsda.Operator.from_problem(large, max_chunk=128)
+    try:
+        W, iters, relres, st = op.solve(large.betas, rtol=large.rtol, chunk=128)
+        W = W.cpu().numpy()
+    finally:
+        op.close()
+    assert st == fsda.OK and relres.max() <= large.rtol
+    b = oracle.rhs(large)
+    nb = np.linalg.norm(b)
+    for s, beta in enumerate(large.betas):
+        w = W[s]
+        r1 = b - oracle.apply(large, beta, w)
+        ref, noise = np.linalg.norm(r1) / nb, 0.0
+        if abs(relres[s] - ref) > 1e-3 * ref:  # size the rounding noise only where it is needed
+            w32 = w.astype(np.float32).astype(np.float64)
+            r2 = b - (oracle.apply(large, beta, w32) + oracle.apply(large, beta, w - w32))
+            noise = np.linalg.norm(r1 - r2) / nb
+        log("beta %.3e: %d iterations, oracle relres %.4e, reported %.4e, evaluation noise %.1e"
+            % (beta, iters[s], ref, relres[s], noise))
+        assert ref <= 1.001 * large.rtol, (s, beta, ref)
+        assert abs(relres[s] - ref) <= 1e-3 * ref + 3 * noise, (s, relres[s], ref, noise)
