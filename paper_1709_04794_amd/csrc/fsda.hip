@@ -1154,6 +1154,20 @@ BlPlan bxt_lds_plan(const fsda_op* op, int T) {
   return b;
 }
 
+// Rows [0, nmed) of X^T are summed in pieces (chunks, slice segments, LDS
+// parts) by the batched X^T product and finished by its second level; the
+// shorter rows get one group of T lanes each.  The boundary is BMED nonzeros
+// (FSDA_BXT_MED sets another, for measurements), and never below the LDS-slice
+// rows.
+int bxt_nmed(const fsda_op* op, const BlPlan& bp) {
+  const char* e = std::getenv("FSDA_BXT_MED");
+  const int thr = std::max(BMED, e ? std::atoi(e) : BMED);
+  const std::vector<int>& rp = op->xt_rp_med;
+  int n = 0;
+  while (n < op->nmed && rp[n + 1] - rp[n] >= thr) n++;
+  return std::max(n, bp.nrow);
+}
+
 template <int T>
 size_t bl_smem(const BXtLds& bl) {
   return sizeof(double) * (size_t)(bl.slen + 1) * T;
@@ -1197,7 +1211,8 @@ long long bxt_chunk_cap(const fsda_op* op, int T, bool sliced) {
   const std::vector<int>& rp = op->xt_rp_med;
   const BlPlan bp = bxt_lds_plan(op, T);
   long long n = 1 + (long long)bp.nrow * bp.nsl;
-  for (int j = bp.nrow; j < op->nmed; j++) {
+  const int nmed = bxt_nmed(op, bp);
+  for (int j = bp.nrow; j < nmed; j++) {
     const int len = rp[j + 1] - rp[j];
     n += ceil_div(len, bc) + (sliced && len >= smin ? NSLICE : 0);
   }
@@ -1206,17 +1221,18 @@ long long bxt_chunk_cap(const fsda_op* op, int T, bool sliced) {
 
 template <int T>
 int chunk_table(fsda_op* op, const BxtTables& tb, BXtArgs* xa, hipStream_t s, BXtLds* bl = nullptr) {
-  const int nmed = op->nmed;
+  const int nm0 = op->nmed;  // rows with slice bounds (the stride of op->bseg)
   const BlPlan bp = tb.bl_xptr && bl ? bxt_lds_plan(op, T) : BlPlan{0, 0, 0, 0, 0};
+  const int nmed = bxt_nmed(op, bp);
   const int part0 = bp.nrow * bp.nsl;  // the LDS-slice parts come first
   if (bl) *bl = BXtLds{0, 0, 0, 0, 0, 0, nullptr, nullptr};
   const std::vector<int>& rp = op->xt_rp_med;
   constexpr int bc = BCHUNK<T>();
-  if (tb.sliced && nmed > 0 && op->bseg.empty()) {  // segment bounds of the split rows, once per handle
-    const long long nseg = (long long)(NSLICE + 1) * nmed;
+  if (tb.sliced && nm0 > 0 && op->bseg.empty()) {  // segment bounds of the split rows, once per handle
+    const long long nseg = (long long)(NSLICE + 1) * nm0;
     if ((size_t)nseg > bxt_item_cap(op, tb.cap)) return fail(FSDA_E_WORKSPACE, "segment table larger than reserved");
     hipLaunchKernelGGL(k_slice_bounds, dim3((unsigned)ceil_div(nseg, BS)), dim3(BS), 0, s, op->xt_rowptr, op->xt_col,
-                       nmed, (long long)op->pb.n, NSLICE, 0, tb.item);
+                       nm0, (long long)op->pb.n, NSLICE, 0, tb.item);
     HIP_TRY(hipGetLastError());
     std::vector<int> seg(nseg);
     HIP_TRY(hipMemcpyAsync(seg.data(), tb.item, sizeof(int) * nseg, hipMemcpyDeviceToHost, s));
@@ -1232,8 +1248,8 @@ int chunk_table(fsda_op* op, const BxtTables& tb, BXtArgs* xa, hipStream_t s, BX
     const bool cut = tb.sliced && rp[j + 1] - rp[j] >= smin;
     const int nsl = cut ? NSLICE : 1;
     for (int x = 0; x < nsl; x++) {
-      const int b = cut ? op->bseg[(size_t)x * nmed + j] : rp[j];
-      const int e = cut ? op->bseg[(size_t)(x + 1) * nmed + j] : rp[j + 1];
+      const int b = cut ? op->bseg[(size_t)x * nm0 + j] : rp[j];
+      const int e = cut ? op->bseg[(size_t)(x + 1) * nm0 + j] : rp[j + 1];
       for (int k = b; k < e; k += bc) {
         (cut ? per[x] : whole).push_back((int)crow.size());
         crow.push_back(j);

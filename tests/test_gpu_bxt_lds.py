@@ -9,7 +9,8 @@ The tiny workload (2,000 samples: two slices at T = 16, every chunked row taken)
 and a planted problem (300,000 samples, 293 slices at T = 16: the five features
 of >= 4,688 nonzeros taken, the others chunked and cut into XCD slices) run
 with and without them; a threshold of 1 takes every chunked row, down to
-segments of a single nonzero (mostly padding).  The plans differ only in the
+segments of a single nonzero (mostly padding).  The multi-column solves run
+tiles of 4, 16 and 64 columns (slices of 4096, 1024 and 256 samples).  The plans differ only in the
 order of additions, so they agree to rounding; the oracle bars are the FP64 ones.
 """
 import dataclasses
@@ -107,7 +108,7 @@ def test_lds_columns_batch_planted(planted, monkeypatch):
             assert relerr(X[c, s], ref) < 1e-6, (c, s, relerr(X[c, s], ref))
 
 
-@pytest.mark.parametrize("ncol", [3, 16])
+@pytest.mark.parametrize("ncol", [3, 16, 40])
 def test_lds_columns_tiny_match_oracle_and_plain(tiny, monkeypatch, ncol):
     B = np.stack([oracle.rhs(tiny) * (1 + c) + synth.normal(tiny.d, seed=70 + c, stream=4) for c in range(ncol)])
     sig = np.logspace(-2, 1, ncol)
