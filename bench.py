@@ -409,10 +409,10 @@ def batched_targets(args, fsda, torch):
     rows = []
     for k in (16, 32, 64):
         labs = synth.target_labels(pb, k, seed=1)
-        op.solve_batch(labs[:4], pb.betas, rtol=pb.rtol)  # warm the kernels
+        op.solve_batch(labs[:4], pb.betas, rtol=pb.rtol, chunk=args.batch_chunk)  # warm the kernels
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        W, it, rel, st = op.solve_batch(labs, pb.betas, rtol=pb.rtol)
+        W, it, rel, st = op.solve_batch(labs, pb.betas, rtol=pb.rtol, chunk=args.batch_chunk)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         solved = int((rel <= TARGET_RELRES).sum())
@@ -429,7 +429,7 @@ def batched_targets(args, fsda, torch):
         t0 = time.perf_counter()
         solved, worst, maxit = 0, 0.0, 0
         for c0 in range(0, args.targets, CALL):
-            W, it, rel, st = op.solve_batch(labs[c0:c0 + CALL], pb.betas, rtol=pb.rtol)
+            W, it, rel, st = op.solve_batch(labs[c0:c0 + CALL], pb.betas, rtol=pb.rtol, chunk=args.batch_chunk)
             torch.cuda.synchronize()
             solved += int((rel <= TARGET_RELRES).sum())
             worst, maxit = max(worst, float(rel.max())), max(maxit, int(it.max()))
@@ -447,7 +447,7 @@ def batched_targets(args, fsda, torch):
     for k, name in BATCH_KNAMES.items():
         op.time_kernel(k, True)
         t0 = time.perf_counter()
-        op.solve_batch(labs, pb.betas, rtol=pb.rtol)
+        op.solve_batch(labs, pb.betas, rtol=pb.rtol, chunk=args.batch_chunk)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ms, nl = op.kernel_time()
@@ -627,6 +627,7 @@ def roofline_large(args, fsda, torch):
     pair_us = event_pair_us(torch)
     op.close()
     del op
+    copy_gbs = copy_ceiling(torch)
     dom = max(per, key=lambda k: per[k][0] / per[k][1])
     ms, nl = per[dom]
     avg_us = 1e3 * ms / nl
@@ -640,12 +641,14 @@ def roofline_large(args, fsda, torch):
             "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_us, 2), "launches": nl,
             "timed_every": 1, "event_pair_us": round(pair_us, 2), "xt_plan": xt_plan(pb)["plan"],
             "note": "HIP events around every launch of the kernel on its launch stream, pair cost included",
+            "copy_ceiling_GBps": round(copy_gbs, 1), "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
             "traffic_note": "rocprofv3 FETCH_SIZE + WRITE_SIZE (beyond L2: Infinity Cache or HBM) per launch, "
                             "calibrated on a 1 GiB device copy in the same run; a lower bound (the counters "
                             "read 0.29 of the fold's 12.3 GB pure stream), see profiles/large_apply_traffic.txt"}
     apply = {"workload": "large", "bytes": b_op, "us": round(apply_us, 2),
              "GBps": round(b_op / (apply_us * 1e-6) / 1e9, 1),
              "frac": round(b_op / (apply_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+             "frac_of_copy_ceiling": round(b_op / (apply_us * 1e-6) / 1e9 / copy_gbs, 4),
              "kernels_us": {KNAMES[k]: round(1e3 * v[0] / v[1], 2) for k, v in per.items()},
              "note": "X, graph and X^T kernels of one iteration (the X^T pass also updates r, bytes not counted)"}
     gpu_iter = {"seconds_per_shared_iteration": round(iter_s, 6), "shifts": S,
@@ -772,7 +775,7 @@ def batched_bench(args, fsda, torch):
         k = group[0]
         group[0] += 1
         labs = [targets[(k * STEP_TARGETS + j) % TOTAL_TARGETS] for j in range(STEP_TARGETS)]
-        W, iters, relres, st = op.solve_batch(labs, pb.betas, rtol=pb.rtol)
+        W, iters, relres, st = op.solve_batch(labs, pb.betas, rtol=pb.rtol, chunk=args.batch_chunk)
         del W
         return iters, relres, st
 
@@ -969,6 +972,8 @@ def main():
     ap.add_argument("--roof-iters", type=int, default=128,
                     help="iterations per timed solve of the large-workload roofline (one launch per class each)")
     ap.add_argument("--chunk", type=int, default=128)
+    ap.add_argument("--batch-chunk", type=int, default=0,
+                    help="fold interval of the target batches (0: the library's default)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
@@ -1040,6 +1045,25 @@ def main():
         batched_bench(args, fsda, torch)
         return
     single_bench(args, fsda, torch)
+
+
+def copy_ceiling(torch, mib: int = 2048, reps: int = 5) -> float:
+    """A measured stream ceiling of this GPU: GB/s of a plain device copy of `mib`
+    MiB (read + write counted), the median of `reps` copies timed with events."""
+    a = torch.empty((mib << 20) // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    c = torch.empty_like(a)
+    c.copy_(a)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        c.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del a, c
+    torch.cuda.empty_cache()
+    return 2 * (mib << 20) / float(np.median(ts)) / 1e9
 
 
 def calibration_copy(torch, mib: int):
