@@ -162,7 +162,7 @@ template <int T>
 constexpr int BCHUNK() {
   return (BS / T) * T * BM<T>();
 }
-constexpr int BMED = 64;  // X^T rows at least this long are cut into chunks in the batched product
+constexpr int BMED = 64;  // X^T rows shorter than this always get one group per row in the batched product
 
 // Sum over the nonzeros [beg, end) of a row of src[col[k] * T + c] for the
 // group's column c.  Lane c of the group loads the indices beg + m*T + c; each

@@ -625,14 +625,13 @@ void iteration(fsda_op* op, int mode, hipStream_t s, int tag) {
 
 template <typename V>
 void fold(fsda_op* op, double* W, int nshift, int chunk, int mode, hipStream_t s) {
-  (void)chunk;
   const long long d = mode == MODE_SA ? op->pb.n : op->pb.d;
   const int g = grid_for(d, GRID_FOLD);
   FoldCoef* cf = at<FoldCoef>(op, op->L.fcoef);
   hipLaunchKernelGGL(k_fold_coef, dim3(1), dim3(BS), 0, s, op->st, op->hist, cf, nshift);
   launch(op, KC_FOLD, s, [&] {
-    hipLaunchKernelGGL(k_fold_apply<V>, dim3(g), dim3(BS), 0, s, op->st, cf, as<V>(op->ring), op->L.ldv, W, d,
-                       as<V>(op->P), op->L.ldv, nshift);
+    hipLaunchKernelGGL(k_fold_apply<V>, dim3(g), dim3(BS), fold_lds_bytes(chunk), s, op->st, cf, as<V>(op->ring),
+                       op->L.ldv, W, d, as<V>(op->P), op->L.ldv, nshift);
   });
   hipLaunchKernelGGL(k_fold_done, dim3(1), dim3(1), 0, s, op->st);
 }
@@ -1156,12 +1155,14 @@ BlPlan bxt_lds_plan(const fsda_op* op, int T) {
 
 // Rows [0, nmed) of X^T are summed in pieces (chunks, slice segments, LDS
 // parts) by the batched X^T product and finished by its second level; the
-// shorter rows get one group of T lanes each.  The boundary is BMED nonzeros
-// (FSDA_BXT_MED sets another, for measurements), and never below the LDS-slice
-// rows.
+// shorter rows get one group of T lanes each, which loops over the row.  The
+// boundary is BXT_MED nonzeros (at mid, 16 targets x 16 shifts: 64 -> 168.7
+// shifted solves/s, 128 -> 176.2, 256 -> 175.9, 512 -> 178.5, 1024 -> 167.4;
+// FSDA_BXT_MED sets another, at least BMED), and never below the LDS-slice rows.
+constexpr int BXT_MED = 512;
 int bxt_nmed(const fsda_op* op, const BlPlan& bp) {
   const char* e = std::getenv("FSDA_BXT_MED");
-  const int thr = std::max(BMED, e ? std::atoi(e) : BMED);
+  const int thr = std::max(BMED, e ? std::atoi(e) : BXT_MED);
   const std::vector<int>& rp = op->xt_rp_med;
   int n = 0;
   while (n < op->nmed && rp[n + 1] - rp[n] >= thr) n++;
@@ -1946,7 +1947,8 @@ void t_fold(fsda_op* op, const TPtr& p, hipStream_t s) {
   const dim3 g(t_colgrid(d), T);
   hipLaunchKernelGGL(ts_fold_coef, dim3(1, T), dim3(BS), 0, s, p.st, p.hist, T, p.coef, p.nshift);
   launch(op, KC_TFOLD, s, [&] {
-    hipLaunchKernelGGL(ts_fold_apply, g, dim3(BS), 0, s, p.st, p.coef, T, p.ring, p.ld, p.Ps, d, p.nshift);
+    hipLaunchKernelGGL(ts_fold_apply, g, dim3(BS), ts_fold_lds_bytes(p.chunk), s, p.st, p.coef, T, p.ring, p.ld, p.Ps,
+                       d, p.nshift);
   });
   hipLaunchKernelGGL(ts_fold_done, dim3(1), dim3(1), 0, s, p.st);
 }

@@ -372,8 +372,21 @@ __global__ __launch_bounds__(BS) void ts_fold_apply(const TState* st, const doub
   const double* AB = G + (size_t)m * nshift;
   const int first = (k0 + 1) % m;
   constexpr int KU = 8;  // buffered residuals in flight
-  for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
-    for (int s0 = 0; s0 < nshift; s0 += TFG) {
+  // the group's coefficients staged once per block and read as broadcasts (as
+  // scalar operands the KU x TFG x 2 coefficients of an unrolled step outgrow
+  // the SGPRs); the launch's LDS holds m rows of TFG
+  extern __shared__ double tfold_lds[];
+  double* lh = tfold_lds;
+  double* lg = tfold_lds + (size_t)m * TFG;
+  for (int s0 = 0; s0 < nshift; s0 += TFG) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt * TFG; e += BS) {
+      const int k = e / TFG, s = s0 + e % TFG;
+      lh[e] = s < nshift ? H[(size_t)k * nshift + s] : 0.0;
+      lg[e] = s < nshift ? G[(size_t)k * nshift + s] : 0.0;
+    }
+    __syncthreads();
+    for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
       double ah[TFG], ag[TFG];
 #pragma unroll
       for (int g = 0; g < TFG; g++) ah[g] = ag[g] = 0.0;
@@ -387,14 +400,12 @@ __global__ __launch_bounds__(BS) void ts_fold_apply(const TState* st, const doub
 #pragma unroll
         for (int u = 0; u < KU; u++) {
           if (k + u < cnt) {
-            const double* hk = H + (size_t)(k + u) * nshift + s0;
-            const double* gk = G + (size_t)(k + u) * nshift + s0;
+            const double* hk = lh + (size_t)(k + u) * TFG;
+            const double* gk = lg + (size_t)(k + u) * TFG;
 #pragma unroll
             for (int g = 0; g < TFG; g++) {
-              if (s0 + g < nshift) {
-                ah[g] += hk[g] * rv[u];
-                ag[g] += gk[g] * rv[u];
-              }
+              ah[g] += hk[g] * rv[u];
+              ag[g] += gk[g] * rv[u];
             }
           }
         }
@@ -412,6 +423,9 @@ __global__ __launch_bounds__(BS) void ts_fold_apply(const TState* st, const doub
     }
   }
 }
+
+// LDS of ts_fold_apply for a fold interval of m iterations.
+inline size_t ts_fold_lds_bytes(int m) { return 2 * sizeof(double) * (size_t)m * TFG; }
 
 __global__ void ts_fold_done(TState* st) { st->fold_start = st->iter; }
 
