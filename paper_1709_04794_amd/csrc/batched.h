@@ -42,10 +42,10 @@ struct BState {
 
 // Per-column block sum of acc (thread tid holds column tid % T) into
 // part[blockIdx.x * T + c], summed over the groups in a fixed order.
-template <int T>
+template <int T, int NT = BS>
 __device__ __forceinline__ void write_partials_cols(double* part, double acc) {
-  __shared__ double sh[BS];
-  constexpr int G = BS / T;
+  __shared__ double sh[NT];
+  constexpr int G = NT / T;
   const int tid = threadIdx.x;
   __syncthreads();
   sh[tid] = acc;
@@ -217,19 +217,19 @@ __device__ __forceinline__ V groups_sum(V v) {
 // rows per wave); `stop` (the solver's stop flag) ends the launch at once when
 // set, cm holds the per-column labeled means.  With MASK, bm gives the masks
 // and the launch has nmask * T values of V of dynamic shared memory.
-template <int T, class Epi, bool MASK = false, int GPR = 1>
-__global__ __launch_bounds__(BS) void bk_rows(const int* __restrict__ rowptr, const int* __restrict__ col, int nrows,
+template <int T, class Epi, bool MASK = false, int GPR = 1, int NT = BS>
+__global__ __launch_bounds__(NT) void bk_rows(const int* __restrict__ rowptr, const int* __restrict__ col, int nrows,
                                               const typename Epi::VT* __restrict__ src, Epi epi, const int* stop,
                                               const double* cm, double* part, BMask bm) {
   using V = typename Epi::VT;
   if (*stop) return;
-  constexpr int G = BS / T;
+  constexpr int G = NT / T;
   constexpr int RB = G / GPR;  // rows per block and pass
   const int c = threadIdx.x % T, g = threadIdx.x / T, q = g % GPR;
   extern __shared__ double bk_smem[];
   V* hot = reinterpret_cast<V*>(bk_smem);
   if (MASK) {
-    stage_lds<BS, 4>(hot, src, bm.nmask * T);
+    stage_lds<NT, 4>(hot, src, bm.nmask * T);
     __syncthreads();
   }
   epi.prepare(cm, c);
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(BS) void bk_rows(const int* __restrict__ rowptr, co
     v = groups_sum<T, GPR>(v);
     if (q == 0) acc += epi.row(r, c, v);
   }
-  if (Epi::kReduce) write_partials_cols<T>(part, acc);
+  if (Epi::kReduce) write_partials_cols<T, NT>(part, acc);
 }
 
 // X^T product, first level.  Block items: the chunks of BCHUNK<T>() nonzeros

@@ -625,13 +625,14 @@ void iteration(fsda_op* op, int mode, hipStream_t s, int tag) {
 
 template <typename V>
 void fold(fsda_op* op, double* W, int nshift, int chunk, int mode, hipStream_t s) {
+  (void)chunk;
   const long long d = mode == MODE_SA ? op->pb.n : op->pb.d;
   const int g = grid_for(d, GRID_FOLD);
   FoldCoef* cf = at<FoldCoef>(op, op->L.fcoef);
   hipLaunchKernelGGL(k_fold_coef, dim3(1), dim3(BS), 0, s, op->st, op->hist, cf, nshift);
   launch(op, KC_FOLD, s, [&] {
-    hipLaunchKernelGGL(k_fold_apply<V>, dim3(g), dim3(BS), fold_lds_bytes(chunk), s, op->st, cf, as<V>(op->ring),
-                       op->L.ldv, W, d, as<V>(op->P), op->L.ldv, nshift);
+    hipLaunchKernelGGL(k_fold_apply<V>, dim3(g), dim3(BS), 0, s, op->st, cf, as<V>(op->ring), op->L.ldv, W, d,
+                       as<V>(op->P), op->L.ldv, nshift);
   });
   hipLaunchKernelGGL(k_fold_done, dim3(1), dim3(1), 0, s, op->st);
 }
@@ -1337,13 +1338,26 @@ struct BBuf {
 
 // t = X src, u = M' t (with the labeled-mean and <t, u> partials), and
 // Q = X^T u + sigma_c P (P NULL: Q = X^T u), all over T columns.
-// The batched X product reads the mask features from a shared copy per block
-// (64 x T values; a copy of more features, up to 32 KiB, lowered the resident
-// waves and made the product slower).
+// The batched X product runs in blocks of BS threads with a copy of the 64
+// mask features' T columns in LDS.  Measured and not kept (16 targets at mid,
+// X product per launch): a copy of more features (up to 32 KiB) in those
+// blocks, 121 -> 211 us; blocks of 1024 threads (one per CU at their register
+// count) with the mask features, 118 -> 127 us, and with 512 features in 64 KiB,
+// 226 us.  bk_rows keeps the block size as a parameter.
+template <int T>
+constexpr int xb_nt() {
+  return BS;
+}
 template <int T, typename V>
 BMask b_mask(const fsda_op* op, size_t* smem) {
   *smem = sizeof(V) * (size_t)op->mtop * T;
   return BMask{op->px.rows.mask, op->mtop};
+}
+
+// Blocks of the batched X product: one pass of xb_nt / T / GPR rows per block.
+template <int T, int GPR>
+int xb_grid(long long n) {
+  return grid_b(ceil_div(n, xb_nt<T>() / T / GPR));
 }
 
 template <int T, typename V>
@@ -1357,15 +1371,17 @@ void b_products(fsda_op* op, const BBuf<V>& b, const V* src, const V* P, const i
   const BMask bm = b_mask<T, V>(op, &sm);
   const int* xrp = op->px.rows.rowptr;
   const int* xrc = op->px.rows.col;
+  constexpr int XN = xb_nt<T>();
+  const int gxx = xb_grid<T, 1>(n);
   launch(op, timed ? KC_BX : KC_OTHER, s, [&] {
     if (lab)
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, V, true>, true>), dim3(gx), dim3(BS), sm, s, xrp, xrc, (int)n, src,
-                         BEpiX<T, V, true>{b.t, b.labw, b.lws, b.lcs}, stop, st->cm, b.site(BP_X), bm);
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, V, true>, true, 1, XN>), dim3(gxx), dim3(XN), sm, s, xrp, xrc, (int)n,
+                         src, BEpiX<T, V, true>{b.t, b.labw, b.lws, b.lcs}, stop, st->cm, b.site(BP_X), bm);
     else
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, V, false>, true>), dim3(gx), dim3(BS), sm, s, xrp, xrc, (int)n, src,
-                         BEpiX<T, V, false>{b.t, nullptr, 1, 0}, stop, st->cm, b.site(BP_X), bm);
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, V, false>, true, 1, XN>), dim3(gxx), dim3(XN), sm, s, xrp, xrc, (int)n,
+                         src, BEpiX<T, V, false>{b.t, nullptr, 1, 0}, stop, st->cm, b.site(BP_X), bm);
   });
-  if (lab) hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, stop, b.site(BP_X), gx, st->cm);
+  if (lab) hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, stop, b.site(BP_X), gxx, st->cm);
   launch(op, timed ? KC_BS : KC_OTHER, s, [&] {
     if (lab)
       hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, V, true>>), dim3(gx), dim3(BS), 0, s, op->pb.s_rowptr, op->pb.s_col,
@@ -1855,15 +1871,17 @@ void t_products(fsda_op* op, const TPtr& p, const double* src, const int* stop, 
   const BMask bm = b_mask<T, double>(op, &sm);
   const int* xrp = op->px.rows.rowptr;
   const int* xrc = op->px.rows.col;
+  constexpr int XN = xb_nt<T>();
+  const int gxx = xb_grid<T, GPR>(n);
   launch(op, timed ? KC_BX : KC_OTHER, s, [&] {
     if (lab)
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, true>, true, GPR>), dim3(gx), dim3(BS), sm, s, xrp, xrc, (int)n,
-                         src, BEpiX<T, double, true>{p.t, p.labw, T, 1}, stop, st->cm, tpart(p, BP_X), bm);
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, true>, true, GPR, XN>), dim3(gxx), dim3(XN), sm, s, xrp, xrc,
+                         (int)n, src, BEpiX<T, double, true>{p.t, p.labw, T, 1}, stop, st->cm, tpart(p, BP_X), bm);
     else
-      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, false>, true, GPR>), dim3(gx), dim3(BS), sm, s, xrp, xrc,
+      hipLaunchKernelGGL((bk_rows<T, BEpiX<T, double, false>, true, GPR, XN>), dim3(gxx), dim3(XN), sm, s, xrp, xrc,
                          (int)n, src, BEpiX<T, double, false>{p.t, nullptr, T, 1}, stop, st->cm, tpart(p, BP_X), bm);
   });
-  if (lab) hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, stop, tpart(p, BP_X), gx, st->cm);
+  if (lab) hipLaunchKernelGGL(bk_colsum<T>, dim3(1), dim3(BS), 0, s, stop, tpart(p, BP_X), gxx, st->cm);
   launch(op, timed ? KC_BS : KC_OTHER, s, [&] {
     if (lab)
       hipLaunchKernelGGL((bk_rows<T, BEpiLap<T, double, true>, false, GPR>), dim3(gx), dim3(BS), 0, s,

@@ -1359,21 +1359,8 @@ __global__ __launch_bounds__(BS) void k_fold_apply(const State* st, const FoldCo
   if (cnt <= 0) return;
   const int first = (k0 + 1) % m;
   constexpr int KU = 8;  // buffered residuals in flight
-  // the group's coefficients H_k,s and G_k,s (k < cnt <= m, the launch's LDS
-  // holds m rows of FG) staged once per block and read as broadcasts: as scalar
-  // operands the KU x FG x 2 coefficients of an unrolled step outgrow the SGPRs
-  extern __shared__ double fold_lds[];
-  double* lh = fold_lds;
-  double* lg = fold_lds + (size_t)m * FG;
-  for (int s0 = 0; s0 < nshift; s0 += FG) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < cnt * FG; e += BS) {
-      const int k = e / FG, s = s0 + e % FG;
-      lh[e] = s < nshift ? cf->h[k][s] : 0.0;
-      lg[e] = s < nshift ? cf->g[k][s] : 0.0;
-    }
-    __syncthreads();
-    for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
+  for (long long j = (long long)blockIdx.x * BS + threadIdx.x; j < d; j += (long long)gridDim.x * BS) {
+    for (int s0 = 0; s0 < nshift; s0 += FG) {
       double ah[FG], ag[FG];
 #pragma unroll
       for (int g = 0; g < FG; g++) ah[g] = ag[g] = 0.0;
@@ -1387,8 +1374,8 @@ __global__ __launch_bounds__(BS) void k_fold_apply(const State* st, const FoldCo
 #pragma unroll
         for (int u = 0; u < KU; u++) {
           if (k + u < cnt) {
-            const double* hk = lh + (size_t)(k + u) * FG;
-            const double* gk = lg + (size_t)(k + u) * FG;
+            const double* hk = cf->h[k + u] + s0;
+            const double* gk = cf->g[k + u] + s0;
 #pragma unroll
             for (int g = 0; g < FG; g++) {
               ah[g] += hk[g] * rv[u];
@@ -1409,9 +1396,6 @@ __global__ __launch_bounds__(BS) void k_fold_apply(const State* st, const FoldCo
     }
   }
 }
-
-// LDS of k_fold_apply for a fold interval of m iterations.
-inline size_t fold_lds_bytes(int m) { return 2 * sizeof(double) * (size_t)m * FG; }
 
 __global__ void k_fold_done(State* st) { st->fold_start = st->iter; }
 
