@@ -290,23 +290,42 @@ __global__ __launch_bounds__(BS) void ts_step_b(TState* st, const double* rr_par
 // P = r_{i+1} + b_c P (interleaved; the ring is column-major) for the targets
 // still active; partials of <p, p> per target.
 template <int T>
+// r_{i+1} is column-major in the ring and P interleaved: a block takes RT rows
+// at a time, reads their T columns of r whole (RT consecutive values per
+// column) into LDS, then updates P row by row from there.
 __global__ __launch_bounds__(BS) void ts_pupdate(const TState* st, const double* __restrict__ ring, long long ld,
                                                  double* P, long long d, double* part) {
   if (st->stop) return;
   constexpr int G = BS / T;
+  constexpr int RT = 4 * G;  // rows per pass: T RT = 4 BS values of r
+  __shared__ double tile[T][RT + 1];
   const int c = threadIdx.x % T, g = threadIdx.x / T;
   const double b = st->b_cur[c];
   const bool on = st->col_active[c] != 0;
-  const double* r = ring + ((size_t)((st->iter) % st->chunk) * T + c) * ld;  // iter was advanced by ts_step_b
+  const double* r0 = ring + (size_t)((st->iter) % st->chunk) * T * ld;  // iter was advanced by ts_step_b
   double acc = 0.0;
-  for (long long j = (long long)blockIdx.x * G + g; j < d; j += (long long)gridDim.x * G) {
-    const size_t e = (size_t)j * T + c;
-    double p = P[e];
-    if (on) {
-      p = r[j] + b * p;
-      P[e] = p;
+  for (long long j0 = (long long)blockIdx.x * RT; j0 < d; j0 += (long long)gridDim.x * RT) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int e = threadIdx.x + k * BS, cc = e / RT, jj = e % RT;
+      tile[cc][jj] = j0 + jj < d ? r0[(size_t)cc * ld + j0 + jj] : 0.0;
     }
-    acc += p * p;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+      const int jj = g + m * G;
+      const long long j = j0 + jj;
+      if (j < d) {
+        const size_t e = (size_t)j * T + c;
+        double p = P[e];
+        if (on) {
+          p = tile[c][jj] + b * p;
+          P[e] = p;
+        }
+        acc += p * p;
+      }
+    }
+    __syncthreads();
   }
   write_partials_cols<T>(part, acc);
 }
