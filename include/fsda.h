@@ -247,11 +247,18 @@ int fsda_regression_solve(fsda_op *op, const double *z, const double *betas, int
  * handle's; its own labeled set is not used.  Targets go in tiles of up to
  * 16 (fsda_set_batch_tile, fsda_batch_autotune), one tile after the other; the
  * sparse products of the targets of a tile share one pass over the indices.
- * When the sample-space vector over a tile's targets outgrows an XCD's share
- * of L2 (n x tile x 8 bytes > 2 MiB), the rows of X^T of >= 64 nonzeros are
- * summed in XCD slices (each XCD gathers from one eighth of the samples); the
- * environment variable FSDA_BXT_SLICES set to 0 or 8 overrides this, here and
- * in the column solves, and must be the same for the workspace-size call.
+ * The rows of X^T of >= 512 nonzeros are summed in pieces and the shorter
+ * ones one group of lanes each (FSDA_BXT_MED sets the boundary); the longest
+ * rows (>= 16 nonzeros per slice on average) are summed from slices of the
+ * sample-space vector staged in LDS (FSDA_BXT_LDS_SEG sets that threshold, 0
+ * turns it off); when the sample-space vector over a tile's targets outgrows
+ * an XCD's share of L2 (n x tile x 8 bytes > 2 MiB), the other pieces of rows
+ * of >= 8 chunks are summed in XCD slices (each XCD gathers from one eighth of
+ * the samples; FSDA_BXT_SLICES set to 0 or 8 overrides this).  These
+ * environment variables apply here and in the column solves, and must be the
+ * same for the workspace-size call.  With FSDA_PROGRESS=<seconds> the host
+ * loops of every solve print their iteration count to stderr at most that
+ * often (read when a handle is built).
  *  ntarget       1..FSDA_MAX_TARGETS.
  *  lab_idx[], lab_y[] (device) the labeled sets of all targets, concatenated;
  *                target c owns entries lab_off[c] .. lab_off[c+1]-1 (same

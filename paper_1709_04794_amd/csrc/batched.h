@@ -75,6 +75,23 @@ __device__ __forceinline__ void write_partials_cols_at(double* part, int slot, d
   }
 }
 
+// The same into slot `slot` for partials held column by column in runs of RB
+// threads (thread t < RB T holds column t / RB; the others hold nothing).
+template <int T, int RB>
+__device__ __forceinline__ void write_partials_rows(double* part, int slot, double acc) {
+  __shared__ double sh[BS];
+  const int tid = threadIdx.x;
+  __syncthreads();
+  sh[tid] = acc;
+  __syncthreads();
+  if (tid < T) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < RB; k++) t += sh[tid * RB + k];
+    part[(size_t)slot * T + tid] = t;
+  }
+}
+
 // out[c] (shared memory, c < T) = sum over blocks of part[blk * T + c], in a
 // fixed order.  All threads of the block must call it.
 template <int T>
@@ -337,9 +354,10 @@ __global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __rest
   constexpr int G = BS / T;
   constexpr int SL = T * BM<T>();  // nonzeros of a group's slice
   __shared__ V sh[BS];
+  constexpr int RB = G / GPR;  // short rows per item
+  __shared__ double tq[T * (RB + 1)];
   const int c = threadIdx.x % T, g = threadIdx.x / T;
   const V sg = P ? (V)sigma[c] : (V)0;
-  constexpr int RB = G / GPR;  // short rows per item
   const int q = g % GPR;
   const int nchit = X.item_chunk ? X.nitem : nchunk;  // chunk items
   const int nitems = nchit + (d - nmed + RB - 1) / RB;
@@ -362,22 +380,34 @@ __global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __rest
       }
       continue;
     }
-    const int r = nmed + (it - nchit) * RB + g / GPR;
-    if (r >= d) continue;
-    const V v = groups_sum<T, GPR>(group_gather<T, V, GPR>(col, rowptr[r], rowptr[r + 1], u, c, q));
-    if (q == 0) {
-      const V qv = P ? v + sg * P[(size_t)r * T + c] : v;
-      if (rout) {
-        const size_t e = (size_t)c * R.ld + r;
-        const double x = rin[e] - R.a[c] * (double)qv;
-        rout[e] = x;
-        acc += x * x;
-      } else {
-        Q[qidx(T, ldq, r, c)] = qv;
+    const int r0 = nmed + (it - nchit) * RB;
+    const int r = r0 + g / GPR;
+    const bool live = r < d;
+    V qv = (V)0;
+    if (live) {
+      const V v = groups_sum<T, GPR>(group_gather<T, V, GPR>(col, rowptr[r], rowptr[r + 1], u, c, q));
+      qv = P ? v + sg * P[(size_t)r * T + c] : v;
+    }
+    if (rout) {
+      // the item's RB x T results through LDS, so that the column-major ring is
+      // read and written RB consecutive rows per column at a time
+      if (live && q == 0) tq[c * (RB + 1) + g / GPR] = (double)qv;
+      __syncthreads();
+      if (threadIdx.x < RB * T) {
+        const int cc = threadIdx.x / RB, jj = threadIdx.x % RB;
+        if (r0 + jj < d) {
+          const size_t e = (size_t)cc * R.ld + r0 + jj;
+          const double x = rin[e] - R.a[cc] * tq[cc * (RB + 1) + jj];
+          rout[e] = x;
+          acc += x * x;  // column threadIdx.x / RB
+        }
       }
+      __syncthreads();
+    } else if (live && q == 0) {
+      Q[qidx(T, ldq, r, c)] = qv;
     }
   }
-  if (R.ring) write_partials_cols_at<T>(R.part, R.slot0 + blockIdx.x, acc);
+  if (R.ring) write_partials_rows<T, RB>(R.part, R.slot0 + blockIdx.x, acc);
 }
 
 // The LDS-slice parts (see BXtLds).  The (slice, item) work items, slice-major,
