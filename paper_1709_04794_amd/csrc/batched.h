@@ -94,10 +94,10 @@ __device__ __forceinline__ void write_partials_rows(double* part, int slot, doub
 
 // out[c] (shared memory, c < T) = sum over blocks of part[blk * T + c], in a
 // fixed order.  All threads of the block must call it.
-template <int T>
+template <int T, int NT = BS>
 __device__ void col_sums(const double* part, int nblk, double* out) {
-  __shared__ double sh[BS];
-  constexpr int G = BS / T;
+  __shared__ double sh[NT];
+  constexpr int G = NT / T;
   constexpr int U = 32;  // loads in flight per thread: a few thousand partials take a few round trips
   const int c = threadIdx.x % T, g = threadIdx.x / T;
   double v = 0.0;

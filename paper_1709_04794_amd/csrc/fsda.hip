@@ -1938,7 +1938,7 @@ void t_iteration(fsda_op* op, const TPtr& p, hipStream_t s, int tag) {
   const int gsb = grid_b(ceil_div(d, G));
   const int gc = t_colgrid(d);
   t_products<T, GPR>(op, p, p.P, &st->stop, s, true);
-  hipLaunchKernelGGL(ts_step_a<T>, dim3(1), dim3(BS), 0, s, st, tpart(p, BP_TU), gx, tpart(p, BP_PP), gsb);
+  hipLaunchKernelGGL(ts_step_a<T>, dim3(1), dim3(SBS), 0, s, st, tpart(p, BP_TU), gx, tpart(p, BP_PP), gsb);
   const int nfused = t_fused_parts<T, GPR>(p);
   if (nfused > 0) {  // r_{i+1} = r_i - a q written by the X^T product itself
     t_xt<T, GPR>(op, p, p.u, p.P, p.Q, &st->stop, s, true,
@@ -1949,7 +1949,7 @@ void t_iteration(fsda_op* op, const TPtr& p, hipStream_t s, int tag) {
       hipLaunchKernelGGL(ts_resid<T>, dim3(gc, T), dim3(BS), 0, s, st, p.Q, p.ring, p.ld, d, tpart(p, BP_RR));
     });
   }
-  hipLaunchKernelGGL(ts_step_b<T>, dim3(1), dim3(BS), 0, s, st, tpart(p, BP_RR), nfused > 0 ? nfused : gc, p.hist);
+  hipLaunchKernelGGL(ts_step_b<T>, dim3(1), dim3(SBS), 0, s, st, tpart(p, BP_RR), nfused > 0 ? nfused : gc, p.hist);
   launch(op, KC_BPUPD, s, [&] {
     hipLaunchKernelGGL(ts_pupdate<T>, dim3(gsb), dim3(BS), 0, s, st, p.ring, p.ld, p.P, d, tpart(p, BP_PP));
   });

@@ -18,6 +18,7 @@
 namespace fsda {
 
 constexpr int TS_MAX = 64;  // shifts per target
+constexpr int SBS = 1024;   // threads of the one-block scalar steps (they sum thousands of partials per column)
 
 struct TState {
   int iter, stop, status, maxit;
@@ -155,13 +156,13 @@ __global__ __launch_bounds__(BS) void ts_init_done(TState* st, const double* par
 // first iteration); the zeta step of every active (target, shift):
 // zeta_{i+1} and a_s = a zeta_{i+1} / zeta_i.  One block.
 template <int T>
-__global__ __launch_bounds__(BS) void ts_step_a(TState* st, const double* tu_part, int ntu, const double* pp_part,
+__global__ __launch_bounds__(SBS) void ts_step_a(TState* st, const double* tu_part, int ntu, const double* pp_part,
                                                 int npp) {
   if (st->stop) return;
   __shared__ double tu[T], pp[T], av[T];
   __shared__ int bad;
-  col_sums<T>(tu_part, ntu, tu);
-  col_sums<T>(pp_part, npp, pp);
+  col_sums<T, SBS>(tu_part, ntu, tu);
+  col_sums<T, SBS>(pp_part, npp, pp);
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   if (threadIdx.x < T) {
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(BS) void ts_step_a(TState* st, const double* tu_par
     return;
   }
   const int S = st->nshift;
-  for (int e = threadIdx.x; e < T * S; e += BS) {
+  for (int e = threadIdx.x; e < T * S; e += SBS) {
     const int c = e / S, s = e % S, k = c * TS_MAX + s;
     if (!st->active[k]) continue;
     const double a = av[c], ap = st->a_prev[c], b = st->b_cur[c];
@@ -226,12 +227,12 @@ __global__ __launch_bounds__(BS) void ts_resid(const TState* st, const double* _
 // into hist[((i % m) * T + c) * S + s]; the stop test |zeta_{i+1}| ||r_{i+1}||
 // <= rtol ||b_c||; target and global stop; iteration count.  One block.
 template <int T>
-__global__ __launch_bounds__(BS) void ts_step_b(TState* st, const double* rr_part, int nrr, double* hist) {
+__global__ __launch_bounds__(SBS) void ts_step_b(TState* st, const double* rr_part, int nrr, double* hist) {
   if (st->stop) return;
   __shared__ double rrn[T], bv[T];
   __shared__ int still[T];
   __shared__ int any;
-  col_sums<T>(rr_part, nrr, rrn);
+  col_sums<T, SBS>(rr_part, nrr, rrn);
   if (threadIdx.x < T) {
     const int c = threadIdx.x;
     bv[c] = st->col_active[c] ? rrn[c] / st->rr[c] : 0.0;
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(BS) void ts_step_b(TState* st, const double* rr_par
   if (threadIdx.x == 0) any = 0;
   __syncthreads();
   const int i = st->iter, S = st->nshift, slot = i % st->chunk;
-  for (int e = threadIdx.x; e < T * S; e += BS) {
+  for (int e = threadIdx.x; e < T * S; e += SBS) {
     const int c = e / S, s = e % S, k = c * TS_MAX + s;
     double* h = hist + (((size_t)slot * T + c) * S + s) * 4;
     if (st->active[k]) {
