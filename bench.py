@@ -42,7 +42,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-LSLICE, MAXLSLICE, SPLIT_ROW, LDS_HEAD = 8192, 32, 64, 2048  # the X^T plans of the library
+LSLICE, MAXLSLICE, SPLIT_ROW, LDS_HEAD = 8192, 32, 64, 512  # the X^T plans of the library
 
 
 def xt_plan(pb):
@@ -644,7 +644,7 @@ def roofline_large(args, fsda, torch):
             "copy_ceiling_GBps": round(copy_gbs, 1), "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
             "traffic_note": "rocprofv3 FETCH_SIZE + WRITE_SIZE (beyond L2: Infinity Cache or HBM) per launch, "
                             "calibrated on a 1 GiB device copy in the same run; a lower bound (the counters "
-                            "read 0.29 of the fold's 12.3 GB pure stream), see profiles/large_apply_traffic.txt"}
+                            "read 0.26 to 0.43 of the fold's 12.3 GB pure stream), see profiles/large_apply_traffic.txt"}
     apply = {"workload": "large", "bytes": b_op, "us": round(apply_us, 2),
              "GBps": round(b_op / (apply_us * 1e-6) / 1e9, 1),
              "frac": round(b_op / (apply_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),

@@ -118,7 +118,7 @@ int fsda_workspace_size(const fsda_problem *pb, int max_shifts, int max_chunk, s
  * sample boundaries and their parts added in a fixed order):
  *  n <= 262,144: LDS slices of 8192 samples; each work-group stages one slice
  *    of the sample-space vector in LDS and sums the rows' segments there.
- *  n > 262,144: the rows of >= 2048 nonzeros in LDS slices, the other cut rows
+ *  n > 262,144: the rows of >= 512 nonzeros in LDS slices, the other cut rows
  *    in XCD slices: each of the eight XCDs gathers from one eighth of the
  *    sample range, which stays in its L2.
  * Results differ between plans only in the summation order of those rows.

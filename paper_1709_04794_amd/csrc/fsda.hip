@@ -134,7 +134,9 @@ struct Layout {
 // in LDS slices, the other split rows in XCD slices (FSDA_XT_SLICES=hyb forces
 // it at any n; FSDA_XT_HEAD sets the head threshold).
 constexpr long long SLICE_BYTES = 2LL << 20;
-constexpr int LDS_HEAD = 2048;
+// The head threshold measured at large (operator apply per iteration): 64 ->
+// 732.8 us, 256 -> 715.7, 512 -> 713.9, 1024 -> 714.4, 2048 -> 731, 8192 -> 750.2.
+constexpr int LDS_HEAD = 512;
 int xt_head(void) {
   const char* e = std::getenv("FSDA_XT_HEAD");
   const int h = e ? std::atoi(e) : LDS_HEAD;

@@ -29,7 +29,7 @@ pytestmark = pytest.mark.gpu
 PLANTED_COUNTS = [300000, 120000, 20000, 9000, 5000, 3000, 1500, 800, 600, 400, 300, 200, 100, 80, 64,
                   63, 40, 20, 10, 5, 2, 1, 0, 0]
 # FSDA_XT_SLICES of each plan; the hybrid plan (rows of at least a head length in
-# LDS slices, the other split rows in XCD slices) with its default head of 2048
+# LDS slices, the other split rows in XCD slices) with its default head of 512
 # nonzeros, a head of 64 (every split row in LDS slices, none left to XCD slices)
 # and of 50,000 (the XCD part keeps rows of >= 8192 nonzeros, summed in chunk items)
 PLANS = ["8", "lds", "hyb", "hyb64", "hyb50k"]
