@@ -333,10 +333,24 @@ struct BResid {
   int slot0;
 };
 
-template <int T, typename V, int GPR = 1>
+// The same for the batched column solves (kernels instantiated with CU), whose
+// vectors are all interleaved: the product's epilogue does r = R - a_c q, R = r, X += a_c P
+// (P the product's direction) instead of storing q, with the per-column
+// partials of <r, r> in slot slot0 + block of part.
+template <typename V>
+struct BColResid {
+  V* R;
+  V* X;
+  const double* a;
+  double* part;
+  int slot0;
+};
+
+template <int T, typename V, int GPR = 1, bool CU = false>
 __global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __restrict__ u, const V* __restrict__ P,
                                             V* Q, long long ldq, const double* sigma, const int* stop,
-                                            BResid R = BResid{nullptr, 0, nullptr, 0, nullptr, nullptr, 0}) {
+                                            BResid R = BResid{nullptr, 0, nullptr, 0, nullptr, nullptr, 0},
+                                            BColResid<V> CR = BColResid<V>{nullptr, nullptr, nullptr, nullptr, 0}) {
   if (*stop) return;
   double acc = 0.0;  // fused residual update: this block's <r_{i+1}, r_{i+1}> for the lane's column
   const double* rin = nullptr;
@@ -403,11 +417,21 @@ __global__ __launch_bounds__(BS) void bk_xt(BXtArgs X, V* lpart, const V* __rest
         }
       }
       __syncthreads();
+    } else if (CU) {
+      if (live && q == 0) {
+        const size_t e = (size_t)r * T + c;
+        const double a = CR.a[c];
+        const V x = (V)((double)CR.R[e] - a * (double)qv);
+        CR.R[e] = x;
+        CR.X[e] = (V)((double)CR.X[e] + a * (double)P[e]);
+        acc += (double)x * (double)x;
+      }
     } else if (live && q == 0) {
       Q[qidx(T, ldq, r, c)] = qv;
     }
   }
   if (R.ring) write_partials_rows<T, RB>(R.part, R.slot0 + blockIdx.x, acc);
+  if (CU) write_partials_cols_at<T>(CR.part, CR.slot0 + blockIdx.x, acc);
 }
 
 // The LDS-slice parts (see BXtLds).  The (slice, item) work items, slice-major,
@@ -480,10 +504,11 @@ __global__ __launch_bounds__(BS) void bk_slice_copy(const int* __restrict__ col,
 // X^T product, second level: row j < nmed is the fixed-order sum of its chunk
 // sums lpart[row_chunk0[j] .. row_chunk0[j+1]) (the groups of a block take
 // every G-th chunk, then add up in order), plus sigma_c P.
-template <int T, typename V>
+template <int T, typename V, bool CU = false>
 __global__ __launch_bounds__(BS) void bk_xt_rows(BXtArgs X, const V* __restrict__ lpart, const V* __restrict__ P, V* Q,
                                                  long long ldq, const double* sigma, const int* stop,
-                                                 BResid R = BResid{nullptr, 0, nullptr, 0, nullptr, nullptr, 0}) {
+                                                 BResid R = BResid{nullptr, 0, nullptr, 0, nullptr, nullptr, 0},
+                                                 BColResid<V> CR = BColResid<V>{nullptr, nullptr, nullptr, nullptr, 0}) {
   if (*stop) return;
   double acc = 0.0;
   const double* rin = nullptr;
@@ -522,12 +547,20 @@ __global__ __launch_bounds__(BS) void bk_xt_rows(BXtArgs X, const V* __restrict_
         const double x = rin[e] - R.a[cc] * (double)qv;
         rout[e] = x;
         acc += x * x;
+      } else if (CU) {
+        const size_t e = (size_t)j * T + cc;
+        const double a = CR.a[cc];
+        const V x = (V)((double)CR.R[e] - a * (double)qv);
+        CR.R[e] = x;
+        CR.X[e] = (V)((double)CR.X[e] + a * (double)P[e]);
+        acc += (double)x * (double)x;
       } else {
         Q[qidx(T, ldq, j, cc)] = qv;
       }
     }
   }
   if (R.ring) write_partials_cols_at<T>(R.part, R.slot0 + blockIdx.x, acc);
+  if (CU) write_partials_cols_at<T>(CR.part, CR.slot0 + blockIdx.x, acc);
 }
 
 // ---------------------------------------------------------------------------

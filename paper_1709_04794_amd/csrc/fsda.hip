@@ -1362,8 +1362,9 @@ int xb_grid(long long n) {
   return grid_b(ceil_div(n, xb_nt<T>() / T / GPR));
 }
 
+// t = X src and u = M' t (first half of b_products).
 template <int T, typename V>
-void b_products(fsda_op* op, const BBuf<V>& b, const V* src, const V* P, const int* stop, hipStream_t s, bool timed) {
+void b_xl(fsda_op* op, const BBuf<V>& b, const V* src, const int* stop, hipStream_t s, bool timed) {
   constexpr int G = BS / T;
   const long long n = op->pb.n;
   BState* st = b.st;
@@ -1396,22 +1397,63 @@ void b_products(fsda_op* op, const BBuf<V>& b, const V* src, const V* P, const i
                          BEpiLap<T, V, false>{b.t, nullptr, 1, 0, op->pb.s_rowptr, b.u, op->pb.alpha, (V)0}, stop,
                          st->cm, b.site(BP_TU), BMask{nullptr, 0});
   });
+}
+
+// Q = X^T u + sigma_c P (P NULL: Q = X^T u; second half of b_products); with
+// cr.R set, the residual and iterate update r = R - a_c q, R = r, X += a_c P
+// in place of the store of Q (see BColResid), its partials in the blocks of
+// both levels (b_fused_parts of them).
+template <int T, typename V>
+void b_xtp(fsda_op* op, const BBuf<V>& b, const V* P, const int* stop, hipStream_t s, bool timed,
+           BColResid<V> cr = BColResid<V>{nullptr, nullptr, nullptr, nullptr, 0}) {
+  constexpr int G = BS / T;
+  BState* st = b.st;
   const int gxt = bxt_grid(b.xa, G);  // one group of T lanes per short row
+  const BResid nr{nullptr, 0, nullptr, 0, nullptr, nullptr, 0};
   launch(op, timed ? KC_BXT : KC_OTHER, s, [&] {
     if constexpr (std::is_same<V, double>::value) {
       if (b.bl.nrow > 0)
         hipLaunchKernelGGL((bk_xt_lds<T, double>), dim3(b.bl.nblk), dim3(BLT), bl_smem<T>(b.bl), s, b.bl, b.u,
                            b.lpart, stop);
     }
-    hipLaunchKernelGGL((bk_xt<T, V>), dim3(gxt), dim3(BS), 0, s, b.xa, b.lpart, b.u, P, b.Q, 0LL, st->sigma, stop);
-    if (b.xa.nmed > 0)
-      hipLaunchKernelGGL((bk_xt_rows<T, V>), dim3(grid_b(b.xa.nmed)), dim3(BS), 0, s, b.xa, b.lpart, P, b.Q, 0LL,
-                         st->sigma, stop);
+    if (cr.R)
+      hipLaunchKernelGGL((bk_xt<T, V, 1, true>), dim3(gxt), dim3(BS), 0, s, b.xa, b.lpart, b.u, P, b.Q, 0LL,
+                         st->sigma, stop, nr, cr);
+    else
+      hipLaunchKernelGGL((bk_xt<T, V>), dim3(gxt), dim3(BS), 0, s, b.xa, b.lpart, b.u, P, b.Q, 0LL, st->sigma, stop);
+    if (b.xa.nmed > 0) {
+      BColResid<V> cr2 = cr;
+      cr2.slot0 = cr.slot0 + gxt;
+      if (cr.R)
+        hipLaunchKernelGGL((bk_xt_rows<T, V, true>), dim3(grid_b(b.xa.nmed)), dim3(BS), 0, s, b.xa, b.lpart, P, b.Q,
+                           0LL, st->sigma, stop, nr, cr2);
+      else
+        hipLaunchKernelGGL((bk_xt_rows<T, V>), dim3(grid_b(b.xa.nmed)), dim3(BS), 0, s, b.xa, b.lpart, P, b.Q, 0LL,
+                           st->sigma, stop);
+    }
   });
 }
 
-// One iteration over T columns: the products, a, R -= a Q and X += a P, b and
-// the stop tests, P = R + b P.
+template <int T, typename V>
+void b_products(fsda_op* op, const BBuf<V>& b, const V* src, const V* P, const int* stop, hipStream_t s, bool timed) {
+  b_xl<T, V>(op, b, src, stop, s, timed);
+  b_xtp<T, V>(op, b, P, stop, s, timed);
+}
+
+// Partials of the X^T product with the residual update fused (blocks of both
+// levels), or 0 when they do not fit a partial site.  FSDA_BXT_FUSE=0 keeps
+// the separate residual kernel.
+template <int T, typename V>
+int b_fused_parts(const BBuf<V>& b) {
+  const char* e = std::getenv("FSDA_BXT_FUSE");
+  if (e && e[0] == '0') return 0;
+  const int n = bxt_grid(b.xa, BS / T) + (b.xa.nmed > 0 ? grid_b(b.xa.nmed) : 0);
+  return (long long)n * T <= (long long)GRID_B * BT_MAX ? n : 0;
+}
+
+// One iteration over T columns: the products, a, R -= a Q and X += a P (in
+// the X^T product's epilogue where its partials fit a site), b and the stop
+// tests, P = R + b P.
 template <int T, typename V>
 void b_iteration(fsda_op* op, const BBuf<V>& b, hipStream_t s, int tag) {
   op->cur_tag = tag;
@@ -1420,13 +1462,19 @@ void b_iteration(fsda_op* op, const BBuf<V>& b, hipStream_t s, int tag) {
   BState* st = b.st;
   const int gx = grid_b(ceil_div(n, G));
   const int gs = grid_b(ceil_div(d, G));
-  b_products<T, V>(op, b, b.P, b.P, &st->stop, s, true);
+  b_xl<T, V>(op, b, b.P, &st->stop, s, true);
   // (the products' TU partials and the previous direction update's PP partials)
   hipLaunchKernelGGL(bk_step_a<T>, dim3(1), dim3(BS), 0, s, st, b.site(BP_TU), gx, b.site(BP_PP), gs);
-  launch(op, KC_BRESID, s, [&] {
-    hipLaunchKernelGGL((bk_resid<T, V>), dim3(gs), dim3(BS), 0, s, st, b.Q, b.P, b.R, b.X, d, b.site(BP_RR));
-  });
-  hipLaunchKernelGGL(bk_step_b<T>, dim3(1), dim3(BS), 0, s, st, b.site(BP_RR), gs);
+  const int nfused = b_fused_parts<T, V>(b);
+  if (nfused > 0) {
+    b_xtp<T, V>(op, b, b.P, &st->stop, s, true, BColResid<V>{b.R, b.X, st->a, b.site(BP_RR), 0});
+  } else {
+    b_xtp<T, V>(op, b, b.P, &st->stop, s, true);
+    launch(op, KC_BRESID, s, [&] {
+      hipLaunchKernelGGL((bk_resid<T, V>), dim3(gs), dim3(BS), 0, s, st, b.Q, b.P, b.R, b.X, d, b.site(BP_RR));
+    });
+  }
+  hipLaunchKernelGGL(bk_step_b<T>, dim3(1), dim3(BS), 0, s, st, b.site(BP_RR), nfused > 0 ? nfused : gs);
   launch(op, KC_BPUPD, s, [&] {
     hipLaunchKernelGGL((bk_pupdate<T, V>), dim3(gs), dim3(BS), 0, s, st, b.R, b.P, d, b.site(BP_PP));
   });
