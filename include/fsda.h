@@ -254,7 +254,9 @@ int fsda_regression_solve(fsda_op *op, const double *z, const double *betas, int
  * turns it off); when the sample-space vector over a tile's targets outgrows
  * an XCD's share of L2 (n x tile x 8 bytes > 2 MiB), the other pieces of rows
  * of >= 8 chunks are summed in XCD slices (each XCD gathers from one eighth of
- * the samples; FSDA_BXT_SLICES set to 0 or 8 overrides this).  These
+ * the samples; FSDA_BXT_SLICES set to 0 or 8 overrides this).  The X^T
+ * product also does the residual update (r -= a q and its partial sums; in the
+ * column solves the iterate update as well) unless FSDA_BXT_FUSE=0.  These
  * environment variables apply here and in the column solves, and must be the
  * same for the workspace-size call.  With FSDA_PROGRESS=<seconds> the host
  * loops of every solve print their iteration count to stderr at most that
@@ -455,9 +457,10 @@ int fsda_project(fsda_op *op, const double *W, int nshift, double *S, void *stre
  * of the rows of X^T longer than one chunk; with XCD slices those rows are
  * finished between classes 2 and 5, in class 13), 6 = shift-state fold; the batched FP32 correction solves of FSDA_MIXED: 7 = X
  * product, 8 = graph/centring product, 9 = X^T product, 10 = residual and
- * correction update, 11 = direction update; fsda_multishift_solve_batch: 7-9
- * its products, 10 = residual update, 11 = direction update, 12 = shift-state
- * fold; 13 = the assembly of the X^T rows cut into XCD slices (their parts
+ * correction update (no launches where the X^T product does it), 11 =
+ * direction update; fsda_multishift_solve_batch: 7-9
+ * its products, 10 = residual update (no launches where the X^T product does
+ * it), 11 = direction update, 12 = shift-state fold; 13 = the assembly of the X^T rows cut into XCD slices (their parts
  * summed, then the residual update of those rows).  While timing is on, solves launch kernels
  * directly instead of replaying a graph.  Launches made after the recurrence
  * stopped (which return at once) are not counted.  fsda_kernel_time() returns
