@@ -36,6 +36,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 TARGET_RELRES = 1e-8
+# The solvers stop on their recursive residual; they are asked for 1 % below the
+# counted threshold, so that rounding drift between it and the true FP64 residual
+# (a relative 1e-6 of the threshold has been seen) does not fail a solve.  This
+# costs about one iteration per solve.
+SOLVE_RTOL = 0.99 * TARGET_RELRES
 
 
 def log(*a):
@@ -209,7 +214,7 @@ def time_paths(pb, fsda, torch, chunk: int):
         return (time.perf_counter() - t0) / reps, r
 
     op_m = fsda.Operator.from_problem(pb, precision=fsda.MIXED, max_chunk=chunk)
-    dt, (W, it, rel, st) = timed(lambda: op_m.solve(pb.betas, rtol=pb.rtol, chunk=chunk))
+    dt, (W, it, rel, st) = timed(lambda: op_m.solve(pb.betas, rtol=SOLVE_RTOL, chunk=chunk))
     out["mixed"] = {"seconds": round(dt, 4), "solves_per_s": round(int((rel <= TARGET_RELRES).sum()) / dt, 3),
                     "worst_relres": float(rel.max()), "iters": it.tolist(), "status": st,
                     "what": "FP32 shared recurrence to 1e-5, then FP64 residuals and batched FP32 correction "
@@ -218,14 +223,14 @@ def time_paths(pb, fsda, torch, chunk: int):
     del op_m
     op = fsda.Operator.from_problem(pb, max_chunk=chunk)
     labs = synth.target_labels(pb, 16, seed=1)
-    dt, (W, it, rel, st) = timed(lambda: op.solve_batch(labs, pb.betas, rtol=pb.rtol))  # its default fold interval
+    dt, (W, it, rel, st) = timed(lambda: op.solve_batch(labs, pb.betas, rtol=SOLVE_RTOL))  # its default fold interval
     out["batched_targets"] = {"targets": len(labs), "seconds": round(dt, 4),
                               "shifted_solves_per_s": round(int((rel <= TARGET_RELRES).sum()) / dt, 3),
                               "worst_relres": float(rel.max()), "max_iters": int(it.max()), "status": st,
                               "what": "16 labelings (labeled fraction lognormal around 0.7%%, positive rate "
                                       "U(0.02, 0.3)) x %d shifts, FP64, to rel. residual %.0e" % (S, pb.rtol)}
     del W
-    dt, (Z, it, rel, st) = timed(lambda: op.sa_solve(pb.betas, rtol=pb.rtol, chunk=chunk), reps=3)
+    dt, (Z, it, rel, st) = timed(lambda: op.sa_solve(pb.betas, rtol=SOLVE_RTOL, chunk=chunk), reps=3)
     out["sample_space"] = {"seconds": round(dt, 5), "solves_per_s": round(int((rel <= TARGET_RELRES).sum()) / dt, 3),
                            "worst_relres": float(rel.max()), "max_iters": int(it.max()), "status": st,
                            "what": "Alg. sasda ratings for every shift, FP64, to rel. residual %.0e" % pb.rtol}
@@ -409,10 +414,10 @@ def batched_targets(args, fsda, torch):
     rows = []
     for k in (16, 32, 64):
         labs = synth.target_labels(pb, k, seed=1)
-        op.solve_batch(labs[:4], pb.betas, rtol=pb.rtol, chunk=args.batch_chunk)  # warm the kernels
+        op.solve_batch(labs[:4], pb.betas, rtol=SOLVE_RTOL, chunk=args.batch_chunk)  # warm the kernels
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        W, it, rel, st = op.solve_batch(labs, pb.betas, rtol=pb.rtol, chunk=args.batch_chunk)
+        W, it, rel, st = op.solve_batch(labs, pb.betas, rtol=SOLVE_RTOL, chunk=args.batch_chunk)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         solved = int((rel <= TARGET_RELRES).sum())
@@ -429,7 +434,7 @@ def batched_targets(args, fsda, torch):
         t0 = time.perf_counter()
         solved, worst, maxit = 0, 0.0, 0
         for c0 in range(0, args.targets, CALL):
-            W, it, rel, st = op.solve_batch(labs[c0:c0 + CALL], pb.betas, rtol=pb.rtol, chunk=args.batch_chunk)
+            W, it, rel, st = op.solve_batch(labs[c0:c0 + CALL], pb.betas, rtol=SOLVE_RTOL, chunk=args.batch_chunk)
             torch.cuda.synchronize()
             solved += int((rel <= TARGET_RELRES).sum())
             worst, maxit = max(worst, float(rel.max())), max(maxit, int(it.max()))
@@ -447,7 +452,7 @@ def batched_targets(args, fsda, torch):
     for k, name in BATCH_KNAMES.items():
         op.time_kernel(k, True)
         t0 = time.perf_counter()
-        op.solve_batch(labs, pb.betas, rtol=pb.rtol, chunk=args.batch_chunk)
+        op.solve_batch(labs, pb.betas, rtol=SOLVE_RTOL, chunk=args.batch_chunk)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ms, nl = op.kernel_time()
@@ -775,7 +780,7 @@ def batched_bench(args, fsda, torch):
         k = group[0]
         group[0] += 1
         labs = [targets[(k * STEP_TARGETS + j) % TOTAL_TARGETS] for j in range(STEP_TARGETS)]
-        W, iters, relres, st = op.solve_batch(labs, pb.betas, rtol=pb.rtol, chunk=args.batch_chunk)
+        W, iters, relres, st = op.solve_batch(labs, pb.betas, rtol=SOLVE_RTOL, chunk=args.batch_chunk)
         del W
         return iters, relres, st
 
@@ -797,12 +802,12 @@ def batched_bench(args, fsda, torch):
     elapsed = time.perf_counter() - t0
     value = solved / elapsed
     # the plain per-target FP64 path on the same X: the mid workload's own labeled set
-    op.solve(pb.betas, rtol=pb.rtol, chunk=128)
+    op.solve(pb.betas, rtol=SOLVE_RTOL, chunk=128)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     psolved = 0
     for _ in range(3):
-        W, it1, rel1, st1 = op.solve(pb.betas, rtol=pb.rtol, chunk=128)
+        W, it1, rel1, st1 = op.solve(pb.betas, rtol=SOLVE_RTOL, chunk=128)
         psolved += int((rel1 <= TARGET_RELRES).sum())
         del W
     torch.cuda.synchronize()
@@ -837,7 +842,7 @@ def batched_bench(args, fsda, torch):
         "detail": {"per_target_fp64_solves_per_s": round(per_target, 3),
                    "speedup_vs_per_target_fp64": round(value / per_target, 3) if per_target > 0 else None,
                    "per_target_fp64_iters": it1.tolist(), "worst_relres": worst, "max_iters": maxit,
-                   "statuses": sorted(statuses), "solved": solved, "solves_attempted": args.steps * STEP_TARGETS * S,
+                   "solver_rtol": SOLVE_RTOL, "counted_at": TARGET_RELRES, "statuses": sorted(statuses), "solved": solved, "solves_attempted": args.steps * STEP_TARGETS * S,
                    "targets_timed": [first_timed * STEP_TARGETS % TOTAL_TARGETS, group[0] * STEP_TARGETS],
                    "build_s": round(build_s, 3), "autotune": tune, "large_iteration": gpu_iter,
                    "cpu_large": cpu_large},
