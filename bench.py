@@ -47,7 +47,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-LSLICE, MAXLSLICE, SPLIT_ROW, LDS_HEAD = 8192, 32, 64, 512  # the X^T plans of the library
+LSLICE, MAXLSLICE, SPLIT_ROW, XCD_SPLIT_ROW, LDS_HEAD = 8192, 32, 64, 16, 512  # the X^T plans of the library
 
 
 def xt_plan(pb):
@@ -70,7 +70,7 @@ def xt_plan(pb):
         plan = "hyb" if 8 * pb.n > (2 << 20) else "none"
     split = cnt >= SPLIT_ROW
     lds = (cnt >= head) if plan == "hyb" else (split if plan == "lds" else np.zeros_like(split))
-    xcd = split & ~lds if plan in ("hyb", "xcd") else np.zeros_like(split)
+    xcd = (cnt >= XCD_SPLIT_ROW) & ~lds if plan in ("hyb", "xcd") else np.zeros_like(split)
     lens = cnt[xcd]
     xparts = int((8 * np.maximum(1, -(-(lens // 8) // 32768))).sum()) if lens.size else 0
     return {"plan": plan, "nsl": nl if plan in ("lds", "hyb") else 0,

@@ -114,13 +114,14 @@ int fsda_workspace_size(const fsda_problem *pb, int max_shifts, int max_chunk, s
  * products, the labeled weights and the canonical right-hand side.  *out
  * (host) receives the handle.  Blocks until done.  The workspace belongs to the
  * handle until it is destroyed.
- * Plans of the X^T product (the rows of X^T of >= 64 nonzeros are cut at
- * sample boundaries and their parts added in a fixed order):
- *  n <= 262,144: LDS slices of 8192 samples; each work-group stages one slice
- *    of the sample-space vector in LDS and sums the rows' segments there.
- *  n > 262,144: the rows of >= 512 nonzeros in LDS slices, the other cut rows
- *    in XCD slices: each of the eight XCDs gathers from one eighth of the
- *    sample range, which stays in its L2.
+ * Plans of the X^T product (the longer rows of X^T are cut at sample
+ * boundaries and their parts added in a fixed order):
+ *  n <= 262,144: the rows of >= 64 nonzeros in LDS slices of 8192 samples;
+ *    each work-group stages one slice of the sample-space vector in LDS and
+ *    sums the rows' segments there.
+ *  n > 262,144: the rows of >= 512 nonzeros in LDS slices, the rows of 16 to
+ *    511 nonzeros in XCD slices: each of the eight XCDs gathers from one eighth
+ *    of the sample range, which stays in its L2.
  * Results differ between plans only in the summation order of those rows.
  * The environment variable FSDA_XT_SLICES set to 1 (no slices), 8 (XCD slices
  * only), lds (LDS slices only, for n <= 262,144) or hyb (LDS and XCD slices)

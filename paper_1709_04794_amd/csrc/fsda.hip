@@ -137,6 +137,8 @@ constexpr long long SLICE_BYTES = 2LL << 20;
 // The head threshold measured at large (operator apply per iteration): 64 ->
 // 732.8 us, 256 -> 715.7, 512 -> 713.9, 1024 -> 714.4, 2048 -> 731, 8192 -> 750.2.
 constexpr int LDS_HEAD = 512;
+// indices of the row-length classes of X^T (fsda_op::xt_bins) at SPLIT_ROW and XCD_SPLIT_ROW
+constexpr int XT_BIN_LDS = 3, XT_BIN_XCD = 4;
 int xt_head(void) {
   const char* e = std::getenv("FSDA_XT_HEAD");
   const int h = e ? std::atoi(e) : LDS_HEAD;
@@ -181,10 +183,10 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->npart_max = L->nchunk_max;
   L->nsplit_max = 0;
   if (L->nslice > 1) {
-    // split rows (>= SPLIT_ROW nonzeros); chunk items of the rows of >= SLICE_LONG:
+    // split rows (>= XCD_SPLIT_ROW nonzeros); chunk items of the rows of >= SLICE_LONG:
     // per row NSLICE x ceil(longest slice / CHUNK) <= NSLICE (len / CHUNK + 1);
     // parts: those chunks plus NSLICE per binned split row
-    L->nsplit_max = z / SPLIT_ROW + 1;
+    L->nsplit_max = z / XCD_SPLIT_ROW + 1;
     L->nchunk_max = (long long)NSLICE * (z / CHUNK + z / SLICE_LONG + 1);
     L->npart_max = L->nchunk_max + (long long)NSLICE * L->nsplit_max;
     L->nlong_max = L->nsplit_max;
@@ -192,8 +194,8 @@ void layout(const fsda_problem* pb, int max_shifts, int max_chunk, Layout* L) {
   L->lparts = L->lxptr = L->lxcol = 0;
   L->nlds_max = 0;
   if (L->lslice > 0) {  // LDS rows: slice boundaries, slice-major indices, one part per (row, slice)
-    L->nsplit_max = z / SPLIT_ROW + 1;
-    L->nlds_max = L->nslice > 1 ? z / xt_head() + 1 : L->nsplit_max;  // hybrid: the head rows only
+    L->nsplit_max = std::max<long long>(L->nsplit_max, z / SPLIT_ROW + 1);
+    L->nlds_max = L->nslice > 1 ? z / xt_head() + 1 : z / SPLIT_ROW + 1;  // hybrid: the head rows only
     L->lparts = 8 * (size_t)L->nlds_max * (size_t)L->lslice;
     L->lxptr = 4 * ((size_t)L->nlds_max + 1) * (size_t)L->lslice;
     // every nonempty segment padded to a multiple of LVEC entries
@@ -347,6 +349,7 @@ struct fsda_op {
   int npos, nneg;
   int mtop;  // features held as per-sample masks (the first mtop of the internal order)
   int xt_bins[8];  // rows of X^T with length >= 1024, 512, 256, 64, 16, 4, 1 (sorted order), and d
+                   // (index XT_BIN_LDS: SPLIT_ROW, index XT_BIN_XCD: XCD_SPLIT_ROW)
   // kernel timing: event pairs around the launches of one kernel class; a
   // pair's tag is the iteration index inside its chunk (or -1), so launches
   // after the recurrence stopped (which return at once) are left out
@@ -708,19 +711,19 @@ RowPlan one_bin(const int* rowptr, const int* col, long long nrows, long long nn
   return pl;
 }
 
-// XCD-sliced work of the X^T product (see XtSlices): the rows of >= SPLIT_ROW
+// XCD-sliced work of the X^T product (see XtSlices): the rows of >= XCD_SPLIT_ROW
 // nonzeros [0, nsplit) are cut at the slice boundaries (found on the device, read
 // back once).  Rows of >= SLICE_LONG: per row ncut = ceil(longest slice / CHUNK)
 // rounds of NSLICE chunk items, item (round c, slice x) taking nonzeros
 // [c CHUNK, (c+1) CHUNK) of slice x (possibly empty), so that a row's parts are
 // contiguous and item k runs slice k % 8.  The other split rows go to bins of
 // NSLICE items each, by length: [1024, 8192) 64 lanes, [512, 1024) 16,
-// [256, 512) 8, [64, 256) 4 (about XUNR nonzeros of a slice per lane).
+// [256, 512) 8, [64, 256) 4, [16, 64) 1 (about XUNR nonzeros of a slice per lane).
 int make_xt_slices(fsda_op* op, int r0, hipStream_t s) {
   XtPlan& pl = op->pxt;
   XtWork& w = pl.w;
   XtSlices& S = w.sl;
-  const int nend = op->xt_bins[3];   // split rows end here
+  const int nend = op->xt_bins[XT_BIN_XCD];  // split rows end here
   const int nsplit = nend - r0;      // rows [r0, nend) in XCD slices
   const std::vector<int>& rp = op->xt_rp_med;
   if (nsplit > op->L.nsplit_max) return fail(FSDA_E_WORKSPACE, "split-row table larger than reserved");
@@ -770,10 +773,10 @@ int make_xt_slices(fsda_op* op, int r0, hipStream_t s) {
   S.nlc = nlc;
   S.part0 = nchunk;
   // bins of the split rows [nlc, nend); lengths decrease with the row index
-  const int lo[4] = {1024, 512, 256, SPLIT_ROW};
-  const int lprs[4] = {64, 16, 8, 4};
+  const int lo[5] = {1024, 512, 256, 64, XCD_SPLIT_ROW};
+  const int lprs[5] = {64, 16, 8, 4, 1};
   int nb = 0, item = 0, j = nlc;
-  for (int k = 0; k < 4; k++) {
+  for (int k = 0; k < 5; k++) {
     const int b0 = j;
     while (j < nend && len(j) >= lo[k]) j++;
     if (j == b0) continue;
@@ -892,8 +895,9 @@ int make_xt(fsda_op* op, hipStream_t s) {
   const int nlong = op->xt_bins[0];
   pl.nlong = nlong;
   pl.row_chunk0 = at<int>(op, op->L.row_chunk0);
-  op->nmed = op->xt_bins[3];  // rows of >= 64 nonzeros
-  const int ncopy = std::max(op->nmed, nlong);
+  op->nmed = op->xt_bins[XT_BIN_LDS];  // rows of >= SPLIT_ROW nonzeros
+  // (host copy of the row pointers of every row that a plan splits)
+  const int ncopy = std::max(op->L.nslice > 1 ? op->xt_bins[XT_BIN_XCD] : op->nmed, nlong);
   op->xt_rp_med.assign(ncopy + 1, 0);
   if (ncopy > 0) {
     HIP_TRY(hipMemcpyAsync(op->xt_rp_med.data(), op->xt_rowptr, sizeof(int) * (ncopy + 1), hipMemcpyDeviceToHost, s));
@@ -905,12 +909,12 @@ int make_xt(fsda_op* op, hipStream_t s) {
   if (op->L.lslice > 0 && op->L.nslice > 1) {  // hybrid: head rows in LDS slices, the other split rows in XCD slices
     const int head = xt_head();
     int nh = 0;
-    while (nh < op->xt_bins[3] && op->xt_rp_med[nh + 1] - op->xt_rp_med[nh] >= head) nh++;
+    while (nh < op->xt_bins[XT_BIN_LDS] && op->xt_rp_med[nh + 1] - op->xt_rp_med[nh] >= head) nh++;
     int rc = make_xt_lds(op, nh, s);
     if (rc) return rc;
     if ((rc = make_xt_slices(op, nh, s))) return rc;
   } else if (op->L.lslice > 0) {
-    const int rc = make_xt_lds(op, op->xt_bins[3], s);
+    const int rc = make_xt_lds(op, op->xt_bins[XT_BIN_LDS], s);
     if (rc) return rc;
   } else if (sliced) {
     const int rc = make_xt_slices(op, 0, s);
@@ -951,10 +955,11 @@ int make_xt(fsda_op* op, hipStream_t s) {
   // xt_bins: counts of rows with length >= 1024, 512, 256, 64, 16, 4, 1; then d.
   // lanes per row so that one pass of XUNR nonzeros per lane covers the bin
   // (two passes for [512, 1024))
-  // (with XCD slices the rows of >= 64 nonzeros are the split rows, done above)
+  // (the split rows, done above: with XCD slices those of >= XCD_SPLIT_ROW
+  // nonzeros, with LDS slices alone those of >= SPLIT_ROW)
   const int lprs[7] = {64, 64, 32, 8, 2, 1, 0};
   int nb = 0, item = 0;
-  for (int k = sliced ? 3 : 0; k < 7; k++) {
+  for (int k = op->L.nslice > 1 ? XT_BIN_XCD : sliced ? XT_BIN_LDS : 0; k < 7; k++) {
     const int r0 = op->xt_bins[k], r1 = op->xt_bins[k + 1];
     if (r1 <= r0) continue;
     R.row0[nb] = r0;
@@ -973,7 +978,7 @@ int make_xt(fsda_op* op, hipStream_t s) {
     R.item0[0] = R.item0[1] = 0;
   }
   // (assembly items rounded up to a multiple of NSLICE, as the kernel counts them)
-  const int nasm_items = (int)(ceil_div(ceil_div(w.nasm, BS), NSLICE) * NSLICE);
+  const int nasm_items = xt_asm_items(w.nasm);
   pl.grid = std::max(1, std::min(nasm_items + w.nchunk + NSLICE * w.sl.item0[w.sl.nb] + R.item0[R.nb], GRID_ROWS));
   pl.gridL = sliced ? grid_for(std::max(pl.nlong, 1), 256) : grid_for(std::max(nlong, 1), 64);
   return FSDA_OK;
@@ -2508,7 +2513,7 @@ int fsda_build_operator(const fsda_problem* pb, int max_shifts, int max_chunk, v
     // row-length classes of X^T (lengths are decreasing in the new order)
     int* thr = flag_dev;
     int* cnts = flag_dev + 8;
-    const int th[7] = {LONG_ROW, 512, 256, 64, 16, 4, 1};
+    const int th[7] = {LONG_ROW, 512, 256, SPLIT_ROW, XCD_SPLIT_ROW, 4, 1};  // (XT_BIN_LDS, XT_BIN_XCD)
     HIP_TRY(hipMemcpyAsync(thr, th, sizeof(th), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_count_at_least, dim3(1), dim3(64), 0, s, cnt_sorted, d, thr, 7, cnts);
     HIP_TRY(hipMemcpyAsync(flag_host, cnts, 7 * sizeof(int), hipMemcpyDeviceToHost, s));

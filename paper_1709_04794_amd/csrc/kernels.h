@@ -730,12 +730,17 @@ constexpr int CHUNK = NCP * CH; // nonzeros of a long-row chunk
 // XCD slices.  Work-groups are dispatched to the eight XCDs round robin, so with a
 // grid that is a multiple of eight (or one item per block) item `it` runs on XCD
 // it % 8.  When the sample-space vector is larger than an XCD's L2, the rows of at
-// least SPLIT_ROW nonzeros are cut at the sample boundaries x n / 8 and segment x of
+// least XCD_SPLIT_ROW nonzeros (not in LDS slices) are cut at the sample boundaries
+// x n / 8 and segment x of
 // every such row is given to items with it % 8 == x: each XCD then gathers from one
 // eighth of the vector, which stays in its L2.  A split row's sum is the ordered sum
 // of its parts (k_assemble).
 constexpr int NSLICE = 8;        // XCDs of the chip
-constexpr int SPLIT_ROW = 64;    // rows at least this long are split into slices
+constexpr int SPLIT_ROW = 64;    // rows at least this long are split into LDS slices
+// Rows at least this long are split into XCD slices (the large workload's X^T
+// pass: 16 -> 229.1 us per launch against 240.2 with 64, its assembly 13.2
+// against 9.3; a row of 16 nonzeros still leaves about two per slice).
+constexpr int XCD_SPLIT_ROW = 16;
 constexpr int SLICE_LONG = 8192; // split rows at least this long are summed in block chunks
 
 struct XtSlices {
@@ -781,6 +786,16 @@ struct XtLds {
   int lpr[MAXBIN];
   int item0[MAXBIN + 1];    // items (LTB / lpr rows) of one slice before bin b
 };
+
+// Rows per assembly item of the X^T pass: a split row's LDS-slice parts (up to
+// MAXLSLICE, or one per LDS slice in the hybrid plan: 184 at large) are added by
+// BS / ASM_ROWS groups of lanes, so that a lane has a few loads in flight rather
+// than a serial walk over the slices (the large workload's X^T pass: 240.2 ->
+// 221.1 us per launch against one row per thread).
+constexpr int ASM_ROWS = 16;
+__host__ __device__ inline int xt_asm_items(int nasm) {
+  return ((nasm + ASM_ROWS - 1) / ASM_ROWS + NSLICE - 1) / NSLICE * NSLICE;
+}
 
 struct XtWork {
   const int* rowptr;
@@ -829,17 +844,29 @@ __global__ __launch_bounds__(BS) void k_xt(XtWork X, const typename Epi::V* __re
   if (Epi::kPublish && blockIdx.x == 0 && threadIdx.x == 0) epi.publish(st);
   const int tid = threadIdx.x;
   double acc = 0.0;
-  // assembly items rounded up to a multiple of NSLICE, so that the XCD-slice
-  // items after them keep item % 8 == slice (with a grid that is a multiple of 8)
-  const int nasm_items = ((X.nasm + BS - 1) / BS + NSLICE - 1) / NSLICE * NSLICE;
+  __shared__ double ash[BS];
+  // assembly items (ASM_ROWS rows each) rounded up to a multiple of NSLICE, so
+  // that the XCD-slice items after them keep item % 8 == slice (with a grid that
+  // is a multiple of 8)
+  const int nasm_items = xt_asm_items(X.nasm);
   const int nitems = nasm_items + X.nchunk + NSLICE * X.sl.item0[X.sl.nb] + X.rows.item0[X.rows.nb];
   for (int it0 = blockIdx.x; it0 < nitems; it0 += gridDim.x) {
-    if (it0 < nasm_items) {  // split rows from their LDS-slice parts, in slice order
-      const int j = it0 * BS + tid;
-      if (j < X.nasm) {
-        double v = 0.0;
-        for (int x = 0; x < X.nslice_asm; x++) v += X.parts[(long long)x * X.nasm + j];
-        acc += epi.row(j, (V)v);
+    if (it0 < nasm_items) {
+      // split rows from their LDS-slice parts: ASM_ROWS rows per item, group g of
+      // the block's BS / ASM_ROWS groups adds the parts of slices g, g + BS /
+      // ASM_ROWS, ... (consecutive rows in consecutive lanes), then the groups'
+      // sums are added in group order
+      const int j = it0 * ASM_ROWS + tid % ASM_ROWS, g = tid / ASM_ROWS;
+      double v = 0.0;
+      if (j < X.nasm)
+        for (int x = g; x < X.nslice_asm; x += BS / ASM_ROWS) v += X.parts[(long long)x * X.nasm + j];
+      __syncthreads();
+      ash[tid] = v;
+      __syncthreads();
+      if (tid < ASM_ROWS && j < X.nasm) {
+        double t = 0.0;
+        for (int k = 0; k < BS / ASM_ROWS; k++) t += ash[k * ASM_ROWS + tid];
+        acc += epi.row(j, (V)t);
       }
       continue;
     }

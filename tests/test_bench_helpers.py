@@ -53,7 +53,9 @@ def test_operator_apply_bytes_are_the_sum_of_the_products(monkeypatch, plan):
     elif plan == "8":
         # the split rows' parts (8 per row, these rows are short) written by the X^T pass and read by
         # the assembly, which also reads their part offsets (p and r in, r out move with their rows)
-        assert pl["plan"] == "xcd" and pl["n_xcd"] == int(split.sum()) > 0 and pl["n_lds"] == 0
+        # (XCD slices take the rows of >= 16 nonzeros)
+        assert pl["plan"] == "xcd" and pl["n_xcd"] == int((cnt >= 16).sum()) > int(split.sum()) > 0
+        assert pl["n_lds"] == 0
         assert pl["xcd_parts"] == 8 * pl["n_xcd"]
         want += 16 * pl["xcd_parts"] + 4 * (pl["n_xcd"] + 1)
     else:
