@@ -739,7 +739,8 @@ constexpr int NSLICE = 8;        // XCDs of the chip
 constexpr int SPLIT_ROW = 64;    // rows at least this long are split into LDS slices
 // Rows at least this long are split into XCD slices (the large workload's X^T
 // pass: 16 -> 229.1 us per launch against 240.2 with 64, its assembly 13.2
-// against 9.3; a row of 16 nonzeros still leaves about two per slice).
+// against 9.3; with 4, 258.4 and 28.8: below about two nonzeros per slice a
+// part per slice costs more than the L2 saves).
 constexpr int XCD_SPLIT_ROW = 16;
 constexpr int SLICE_LONG = 8192; // split rows at least this long are summed in block chunks
 
