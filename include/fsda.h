@@ -254,7 +254,7 @@ int fsda_regression_solve(fsda_op *op, const double *z, const double *betas, int
  * sample-space vector staged in LDS (FSDA_BXT_LDS_SEG sets that threshold, 0
  * turns it off); when the sample-space vector over a tile's targets outgrows
  * an XCD's share of L2 (n x tile x 8 bytes > 2 MiB), the other pieces of rows
- * of >= 8 chunks are summed in XCD slices (each XCD gathers from one eighth of
+ * of >= 2 chunks are summed in XCD slices (each XCD gathers from one eighth of
  * the samples; FSDA_BXT_SLICES set to 0 or 8 overrides this).  The X^T
  * product also does the residual update (r -= a q and its partial sums; in the
  * column solves the iterate update as well) unless FSDA_BXT_FUSE=0.  These

@@ -1205,12 +1205,16 @@ int bxt_grid(const BXtArgs& xa, int rb) {
   return (int)std::max<long long>(1, std::min<long long>(items, GRID_B));
 }
 
-// With XCD slices, only rows of at least NSLICE chunks are cut (a shorter row's
-// slice segments would leave most groups of a chunk item idle); the others are
-// summed in whole chunks, after the sliced rounds.
+// With XCD slices, only rows of at least BXT_SLICE_CHUNKS chunks are cut (a
+// shorter row's slice segments leave most groups of a chunk item idle); the
+// others are summed in whole chunks, after the sliced rounds.  Measured at mid
+// (64 targets x 16 shifts per call, tiles of 16: chunks of 1024 nonzeros):
+// rows of >= 8 chunks cut 183.0-183.3 shifted solves/s, >= 4 183.1, >= 2 185.5,
+// >= 1 173.8, >= 1/2 167.8.  FSDA_BXT_SLICE_MIN sets the row length instead.
+constexpr int BXT_SLICE_CHUNKS = 2;
 int bxt_slice_min(int T) {
   const char* e = std::getenv("FSDA_BXT_SLICE_MIN");
-  return e ? std::max(1, std::atoi(e)) : NSLICE * BS * (T >= 64 ? 1 : 64 / T);
+  return e ? std::max(1, std::atoi(e)) : BXT_SLICE_CHUNKS * BS * (T >= 64 ? 1 : 64 / T);
 }
 
 // Pieces of the batched X^T product for tile T, an upper bound.

@@ -6,7 +6,7 @@ and summed in pieces that never cross one, so that each XCD gathers from one
 eighth of the sample-space vector for them.  They are chosen when that
 vector over the tile's columns outgrows an XCD's L2 share; FSDA_BXT_SLICES=8
 or 0 forces them on or off, which is how these tests run both plans on the same
-inputs.  Only rows of at least eight chunks are cut by default
+inputs.  Only rows of at least two chunks are cut by default
 (FSDA_BXT_SLICE_MIN sets the shortest row cut; the tiny workload's rows are cut
 from 64 nonzeros here, so that every row of the chunked part is cut).  The two
 plans differ only in the order in which a long row's pieces are added, so they
