@@ -765,8 +765,8 @@ struct XtSlices {
 // contiguous; every segment starts at a multiple of LVEC entries and is padded
 // to one with the offset LSLICE, a slot of LDS that holds zero, so that a lane
 // loads LVEC offsets with one 16-byte load.  Part (row j, slice x) goes to
-// parts[x * nsplit + j]; the X^T pass adds a split row's parts in slice order and
-// runs the epilogue (assembly items, before its other items).
+// parts[x * nsplit + j]; the X^T pass adds a split row's parts in a fixed order
+// (see ASM_ROWS) and runs the epilogue (assembly items, before its other items).
 constexpr int LSLICE = 8192;   // samples per LDS slice (64 KiB of FP64)
 constexpr int MAXLSLICE = 32;  // more slices: the XCD slices instead
 constexpr int LTB = 1024;      // threads per block of k_xt_lds
