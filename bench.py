@@ -888,16 +888,22 @@ def diff_experiment(args, fsda, torch):
     W, it, rel, st = timed("forward_s", lambda: op.solve_batch(train, pb.betas, rtol=pb.rtol))
     loss, G = timed("holdout_s", lambda: op.holdout_batch(W, held))
 
-    def adjoint():  # in groups of 8 targets (64 columns), a line after each
+    # in groups of ADJ targets, a line after each: the library takes a call's columns
+    # shift by shift in tiles of 16, so with 16 targets per call every tile holds one
+    # shift (similar iteration counts), where 8 per call pair neighbouring shifts
+    ADJ = 16
+
+    def adjoint():
         Lam = torch.empty_like(G)
         its = np.zeros((64, S), dtype=np.int32)
         rels = np.zeros((64, S))
         worst = fsda.OK
-        for c0 in range(0, 64, 8):
-            L, i2, r2, s2 = op.solve_columns_batch(train[c0:c0 + 8], pb.betas, G[c0:c0 + 8], rtol=0.5 * pb.rtol)
-            Lam[c0:c0 + 8], its[c0:c0 + 8], rels[c0:c0 + 8] = L, i2, r2
+        for c0 in range(0, 64, ADJ):
+            L, i2, r2, s2 = op.solve_columns_batch(train[c0:c0 + ADJ], pb.betas, G[c0:c0 + ADJ],
+                                                   rtol=0.5 * pb.rtol)
+            Lam[c0:c0 + ADJ], its[c0:c0 + ADJ], rels[c0:c0 + ADJ] = L, i2, r2
             worst = max(worst, s2)
-            log("adjoint targets %d..%d done" % (c0, c0 + 7))
+            log("adjoint targets %d..%d done" % (c0, c0 + ADJ - 1))
         return Lam, its, rels, worst
 
     Lam, it2, rel2, st2 = timed("adjoint_s", adjoint)
@@ -915,7 +921,8 @@ def diff_experiment(args, fsda, torch):
                       "forward": {"status": st, "worst_relres": float(rel.max()), "max_iters": int(it.max()),
                                   "solved": int((rel <= TARGET_RELRES).sum())},
                       "adjoint": {"status": st2, "worst_relres": float(rel2.max()), "max_iters": int(it2.max()),
-                                  "solved": int((rel2 <= TARGET_RELRES).sum())},
+                                  "solved": int((rel2 <= TARGET_RELRES).sum()), "iters_sum": int(it2.sum()),
+                                  "targets_per_call": ADJ},
                       "finite": bool(np.isfinite(dlb).all() and np.isfinite(da).all()),
                       "loss_range": [float(loss.min()), float(loss.max())], "cpu_baseline": cpu}), flush=True)
 
