@@ -270,7 +270,7 @@ int fsda_regression_solve(fsda_op *op, const double *z, const double *betas, int
  *  lab_off[ntarget+1] host offsets, lab_off[0] = 0.
  *  betas, nshift, rtol, maxit, chunk: as in fsda_multishift_solve (1 <= nshift
  *                <= FSDA_MAX_SHIFTS; the handle's max_shifts does not apply;
- *                0 <= chunk <= FSDA_MAX_BATCH_CHUNK, 0 = default 64; as there,
+ *                0 <= chunk <= FSDA_MAX_BATCH_CHUNK, 0 = default 96; as there,
  *                chunk changes W only through the order of its rounding).
  *  workspace     device, 256-byte aligned, ws_bytes >= fsda_batch_workspace_size()
  *                for the same ntarget, nshift and chunk; scratch for this call only.

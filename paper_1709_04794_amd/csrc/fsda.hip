@@ -95,6 +95,11 @@ int batch_tile(int ncol) { return std::max(4, pow2_at_least(ncol)); }
 // the indices stop paying beyond 16 at mid (16: 140 shifted solves/s, 32: 136,
 // 64: 92), since the per-target vectors dominate the traffic there.
 constexpr int TARGET_TILE = 16;
+// Fold interval of the target batch when the caller passes 0.  With the fold on
+// the matrix cores, at mid (64 targets x 16 shifts per call): 48 -> 185.1
+// shifted solves/s (vector-ALU fold), 64 -> 188.8, 96 -> 191.0, 128 -> 191.2;
+// 96 keeps most of the gain at three quarters of the residual ring of 128.
+constexpr int BATCH_CHUNK_DEFAULT = 96;
 // Columns per tile of fsda_solve_columns_batch (independent systems, FP64).
 constexpr int COLUMN_TILE = 16;
 int batch_tile_of(const fsda_op* op);
@@ -2018,14 +2023,25 @@ void t_iteration(fsda_op* op, const TPtr& p, hipStream_t s, int tag) {
 // (grids over all T columns of the tile: the kernels skip the columns beyond
 // the tile's targets and read W from the state, so a captured chunk serves
 // every tile of a call)
+// The fold's sums over the buffered residuals run on the matrix cores
+// (ts_fold_apply_mfma) unless FSDA_FOLD_MFMA=0 (the vector-ALU kernel).
+bool fold_mfma() {
+  const char* e = std::getenv("FSDA_FOLD_MFMA");
+  return !(e && e[0] == '0');
+}
+
 template <int T>
 void t_fold(fsda_op* op, const TPtr& p, hipStream_t s) {
   const long long d = op->pb.d;
   const dim3 g(t_colgrid(d), T);
   hipLaunchKernelGGL(ts_fold_coef, dim3(1, T), dim3(BS), 0, s, p.st, p.hist, T, p.coef, p.nshift);
   launch(op, KC_TFOLD, s, [&] {
-    hipLaunchKernelGGL(ts_fold_apply, g, dim3(BS), ts_fold_lds_bytes(p.chunk), s, p.st, p.coef, T, p.ring, p.ld, p.Ps,
-                       d, p.nshift);
+    if (fold_mfma())
+      hipLaunchKernelGGL(ts_fold_apply_mfma, g, dim3(BS), ts_fold_lds_bytes(p.chunk), s, p.st, p.coef, T, p.ring,
+                         p.ld, p.Ps, d, p.nshift);
+    else
+      hipLaunchKernelGGL(ts_fold_apply, g, dim3(BS), ts_fold_lds_bytes(p.chunk), s, p.st, p.coef, T, p.ring, p.ld,
+                         p.Ps, d, p.nshift);
   });
   hipLaunchKernelGGL(ts_fold_done, dim3(1), dim3(1), 0, s, p.st);
 }
@@ -2993,7 +3009,7 @@ int fsda_batch_workspace_size(const fsda_op* op, int ntarget, int nshift, int ch
   if (ntarget < 1 || ntarget > FSDA_MAX_TARGETS) return fail(FSDA_E_ARG, "ntarget outside 1..FSDA_MAX_TARGETS");
   if (nshift < 1 || nshift > FSDA_MAX_SHIFTS) return fail(FSDA_E_ARG, "nshift outside 1..FSDA_MAX_SHIFTS");
   if (chunk < 0 || chunk > FSDA_MAX_BATCH_CHUNK) return fail(FSDA_E_RANGE, "chunk outside 0..FSDA_MAX_BATCH_CHUNK");
-  if (chunk == 0) chunk = 64;
+  if (chunk == 0) chunk = BATCH_CHUNK_DEFAULT;
   TLayout L;
   tlayout(op, batch_tile(std::min(ntarget, batch_tile_of(op))), nshift, chunk, &L);
   *bytes = L.total;
@@ -3009,7 +3025,7 @@ int fsda_multishift_solve_batch(fsda_op* op, int ntarget, const int32_t* lab_idx
   size_t need = 0;
   int rc = fsda_batch_workspace_size(op, ntarget, nshift, chunk, &need);
   if (rc) return rc;
-  if (chunk == 0) chunk = 64;
+  if (chunk == 0) chunk = BATCH_CHUNK_DEFAULT;
   if (!(rtol > 0.0)) return fail(FSDA_E_RANGE, "rtol must be > 0");
   if (maxit < 1) return fail(FSDA_E_RANGE, "maxit must be >= 1");
   for (int k = 0; k < nshift; k++)

@@ -3,7 +3,8 @@
 // Everything on this path is bound by memory bandwidth or latency: the sparse
 // products are gather-sums over int32 column indices of binary matrices (no
 // multiplies), the rest are streaming vector updates and FP64 dot products.
-// No kernel here is a dense contraction, so none uses the matrix cores.
+// The one dense contraction of the method, the target batch's fold of buffered
+// residuals into the per-shift state, runs on the matrix cores (targets.h).
 //
 // Reductions never synchronise blocks inside a kernel.  A producing kernel
 // writes one partial per block; every block of the consuming kernel sums the

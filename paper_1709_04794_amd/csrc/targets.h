@@ -444,8 +444,87 @@ __global__ __launch_bounds__(BS) void ts_fold_apply(const TState* st, const doub
   }
 }
 
-// LDS of ts_fold_apply for a fold interval of m iterations.
-inline size_t ts_fold_lds_bytes(int m) { return 2 * sizeof(double) * (size_t)m * TFG; }
+// LDS of ts_fold_apply for a fold interval of m iterations (rows rounded up to
+// a multiple of 4 for ts_fold_apply_mfma).
+inline size_t ts_fold_lds_bytes(int m) { return 2 * sizeof(double) * (size_t)((m + 3) / 4 * 4) * TFG; }
+
+// The same fold on the matrix cores.  For a target c and a group of 16 shifts
+// the chunk's sums over the buffered residuals are a small dense product,
+//   [sum_k H_k,s r_k(j)]_{s,j} = H^T (16 x cnt) R (cnt x columns),
+// and likewise with G: each wave takes 16 columns j at a time and accumulates
+// them with the FP64 16x16x4 instruction, 4 buffered residuals per step.  Lane
+// layout of that instruction (checked on gfx950): lane l supplies A[l % 16][l /
+// 16] and B[l / 16][l % 16], and holds D[l / 16 + 4 v][l % 16] in element v.
+// Here A[i][kk] = H[k][s0 + i] (from LDS, zero beyond cnt and nshift), B[kk][jj]
+// = r_k(j0 + jj) (zero beyond cnt and d), k = 4 kb + kk; lane l then finishes
+// shifts s0 + l / 16 + 4 v of column j0 + l % 16.  Every instruction runs with
+// all 64 lanes (the loops are uniform over the wave; only loads and stores are
+// predicated).
+typedef double tf_d4 __attribute__((ext_vector_type(4)));
+constexpr int TFK = 4;  // steps of 4 buffered residuals whose loads are in flight together
+__global__ __launch_bounds__(BS) void ts_fold_apply_mfma(const TState* st, const double* __restrict__ coef, int T,
+                                                         const double* ring, long long ld, double* Ps, long long d,
+                                                         int nshift) {
+  const int k0 = st->fold_start, cnt = st->iter - k0, m = st->chunk;
+  const int c = blockIdx.y;
+  if (cnt <= 0 || c >= st->ncol) return;
+  double* W = st->W;
+  const double* H = coef + (size_t)c * ts_coef_stride(m, nshift);
+  const double* G = H + (size_t)m * nshift;
+  const double* AB = G + (size_t)m * nshift;
+  const int first = (k0 + 1) % m;
+  const int nkb = (cnt + 3) / 4;
+  extern __shared__ double tfold_lds[];
+  double* lh = tfold_lds;  // [4 nkb][16]
+  double* lg = tfold_lds + (size_t)(m + 3) / 4 * 4 * TFG;
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  constexpr int WPB = BS / 64;  // waves per block
+  const long long jstep = (long long)gridDim.x * WPB * 16;
+  for (int s0 = 0; s0 < nshift; s0 += TFG) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < nkb * 4 * TFG; e += BS) {
+      const int k = e / TFG, s = s0 + e % TFG;
+      const bool ok = k < cnt && s < nshift;
+      lh[e] = ok ? H[(size_t)k * nshift + s] : 0.0;
+      lg[e] = ok ? G[(size_t)k * nshift + s] : 0.0;
+    }
+    __syncthreads();
+    for (long long j0 = ((long long)blockIdx.x * WPB + (threadIdx.x >> 6)) * 16; j0 < d; j0 += jstep) {
+      const long long j = j0 + li;
+      const bool jin = j < d;
+      tf_d4 dh = {0.0, 0.0, 0.0, 0.0}, dg = {0.0, 0.0, 0.0, 0.0};
+      for (int kb0 = 0; kb0 < nkb; kb0 += TFK) {
+        double rv[TFK];
+#pragma unroll
+        for (int u = 0; u < TFK; u++) {  // slot (k0 + k + 1) mod m: the chunk wraps the ring at most once
+          const int k = (kb0 + u) * 4 + lk;
+          const int sl = first + k;
+          rv[u] = k < cnt && jin ? ring[((size_t)(sl < m ? sl : sl - m) * T + c) * ld + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < TFK; u++) {
+          if (kb0 + u < nkb) {  // uniform over the wave
+            const int e = ((kb0 + u) * 4 + lk) * TFG + li;
+            dh = __builtin_amdgcn_mfma_f64_16x16x4f64(lh[e], rv[u], dh, 0, 0, 0);
+            dg = __builtin_amdgcn_mfma_f64_16x16x4f64(lg[e], rv[u], dg, 0, 0, 0);
+          }
+        }
+      }
+      if (jin) {
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int s = s0 + lk + 4 * v;
+          if (s < nshift && AB[2 * nshift + s] != 0.0) {
+            const size_t e = (size_t)c * nshift + s;
+            const double pv = Ps[e * ld + j];
+            W[e * d + j] += AB[s] * pv + dh[v];
+            Ps[e * ld + j] = AB[nshift + s] * pv + dg[v];
+          }
+        }
+      }
+    }
+  }
+}
 
 __global__ void ts_fold_done(TState* st) { st->fold_start = st->iter; }
 
